@@ -1,0 +1,590 @@
+/*
+ * sorlayout oracle: a plain IEEE-double reference of the SOR-accelerated
+ * stress-majorization graph layout of Wang & Wang, "A Fast Successive
+ * Over-Relaxation Algorithm for Force-Directed Network Graph Drawing",
+ * Sci. China Inf. Sci. 55:677 (2012), arXiv:1711.01228.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the benchmark's
+ * CPU-baseline leg call it; the product library neither links nor calls it,
+ * and the two share no code, headers or tables.
+ *
+ * It is slow and direct on purpose.  Each function writes out one definition
+ * of the paper in the paper's notation: the stress (eq. 1), the Laplacians
+ * L^W and L^Y and the majorant g (Prop. 2.1, eq. 2), the linear system of the
+ * majorization step (Prop. 2.3, eq. 5), Algorithms 1 and 2 with the
+ * extrapolation of eq. 10/11.  There is no blocking, fusion or reordering.
+ * OpenMP only hands independent rows or sources to threads; every sum that
+ * crosses rows is taken serially in index order, so results do not depend on
+ * the thread count.
+ *
+ * Conventions
+ *   vertices     0 .. n-1 (the paper numbers them 1 .. n)
+ *   X            row-major n x dim, dim >= 1
+ *   D            row-major n x n ideal distances, D[i][i] = 0, +INFINITY for
+ *                a pair in different components
+ *   w_ij         d_ij^-2 for 0 < d_ij < inf, else 0 (Sec. 5.1 takes w = d^-2;
+ *                a pair with no path contributes nothing, the limit d -> inf)
+ *   CSR graph    symmetric, row_ptr[n+1] (int64), col_idx[nnz] (int32),
+ *                optional positive edge lengths len[nnz]
+ *
+ * Compiled with -O2 -ffp-contract=off and no fast-math: IEEE sqrt and divide.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define SLO_OK 0
+#define SLO_EINVAL (-1)
+#define SLO_ENOMEM (-2)
+#define SLO_ENUMERIC (-5)
+
+enum { SLO_JACOBI = 0, SLO_EXACT = 1, SLO_GAUSS_SEIDEL = 2 };
+
+/* ---------------------------------------------------------------------- */
+/* Weights w_ij = d_ij^-2 (Sec. 5.1), the products that appear in L^Y      */
+/* (w_ij d_ij) and in the constant C of eq. 2 (w_ij d_ij^2).              */
+/* ---------------------------------------------------------------------- */
+static double w_of(double d) { return (d > 0.0 && isfinite(d)) ? 1.0 / (d * d) : 0.0; }
+static double wd_of(double d) { return (d > 0.0 && isfinite(d)) ? 1.0 / d : 0.0; }
+static double wdd_of(double d) { return (d > 0.0 && isfinite(d)) ? 1.0 : 0.0; }
+
+static double dist(int dim, const double* a, const double* b) {
+  double s = 0.0;
+  for (int c = 0; c < dim; ++c) {
+    double t = a[c] - b[c];
+    s += t * t;
+  }
+  return sqrt(s);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Ideal distances d_ij: graph-theoretic shortest paths.  Hop counts when  */
+/* len == NULL (breadth-first search); sums of edge lengths otherwise      */
+/* (Dijkstra with a binary heap), as for the weighted railway net of Sec. 5.4. */
+/* ---------------------------------------------------------------------- */
+typedef struct { double key; int32_t v; } heap_item;
+
+static void heap_push(heap_item* h, int64_t* size, double key, int32_t v) {
+  int64_t i = (*size)++;
+  h[i].key = key;
+  h[i].v = v;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h[p].key <= h[i].key) break;
+    heap_item t = h[p]; h[p] = h[i]; h[i] = t;
+    i = p;
+  }
+}
+
+static heap_item heap_pop(heap_item* h, int64_t* size) {
+  heap_item top = h[0];
+  h[0] = h[--(*size)];
+  int64_t i = 0;
+  for (;;) {
+    int64_t l = 2 * i + 1, r = l + 1, m = i;
+    if (l < *size && h[l].key < h[m].key) m = l;
+    if (r < *size && h[r].key < h[m].key) m = r;
+    if (m == i) break;
+    heap_item t = h[m]; h[m] = h[i]; h[i] = t;
+    i = m;
+  }
+  return top;
+}
+
+int slo_sssp(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* len,
+             int32_t src, double* drow) {
+  if (n < 0 || src < 0 || src >= n) return SLO_EINVAL;
+  for (int32_t v = 0; v < n; ++v) drow[v] = INFINITY;
+  drow[src] = 0.0;
+  if (len == NULL) {
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!queue) return SLO_ENOMEM;
+    int32_t head = 0, tail = 0;
+    queue[tail++] = src;
+    while (head < tail) {
+      int32_t u = queue[head++];
+      for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+        int32_t v = col_idx[e];
+        if (isinf(drow[v])) {
+          drow[v] = drow[u] + 1.0;
+          queue[tail++] = v;
+        }
+      }
+    }
+    free(queue);
+    return SLO_OK;
+  }
+  int64_t nnz = row_ptr[n];
+  heap_item* heap = (heap_item*)malloc(sizeof(heap_item) * (size_t)(nnz + 1));
+  char* done = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!heap || !done) { free(heap); free(done); return SLO_ENOMEM; }
+  int64_t size = 0;
+  heap_push(heap, &size, 0.0, src);
+  while (size > 0) {
+    heap_item it = heap_pop(heap, &size);
+    int32_t u = it.v;
+    if (done[u]) continue;
+    done[u] = 1;
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      int32_t v = col_idx[e];
+      double nd = drow[u] + len[e];
+      if (nd < drow[v]) {
+        drow[v] = nd;
+        heap_push(heap, &size, nd, v);
+      }
+    }
+  }
+  free(heap);
+  free(done);
+  return SLO_OK;
+}
+
+int slo_apsp(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* len, double* D) {
+  int status = SLO_OK;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t s = 0; s < n; ++s) {
+    int r = slo_sssp(n, row_ptr, col_idx, len, s, D + (size_t)s * n);
+    if (r != SLO_OK) {
+#pragma omp critical
+      status = r;
+    }
+  }
+  return status;
+}
+
+/* Distances from a list of sources: rows[k] -> Drows[k][0..n). */
+int slo_sssp_rows(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* len,
+                  const int32_t* rows, int32_t nrows, double* Drows) {
+  int status = SLO_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t k = 0; k < nrows; ++k) {
+    int r = slo_sssp(n, row_ptr, col_idx, len, rows[k], Drows + (size_t)k * n);
+    if (r != SLO_OK) {
+#pragma omp critical
+      status = r;
+    }
+  }
+  return status;
+}
+
+/* W_i = sum_{j != i} w_ij: the diagonal of L^W (Prop. 2.1). */
+void slo_weight_sums(int32_t n, const double* D, double* W) {
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int32_t j = 0; j < n; ++j)
+      if (j != i) s += w_of(D[(size_t)i * n + j]);
+    W[i] = s;
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Stress, eq. 1: f(X) = sum_{i<j} w_ij (||x_i - x_j|| - d_ij)^2.          */
+/* ---------------------------------------------------------------------- */
+double slo_stress(int32_t n, int32_t dim, const double* D, const double* X) {
+  double* part = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!part) return NAN;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int32_t j = i + 1; j < n; ++j) {
+      double d = D[(size_t)i * n + j];
+      double w = w_of(d);
+      if (w == 0.0) continue;
+      double e = dist(dim, X + (size_t)i * dim, X + (size_t)j * dim) - d;
+      s += w * e * e;
+    }
+    part[i] = s;
+  }
+  double f = 0.0;
+  for (int32_t i = 0; i < n; ++i) f += part[i];
+  free(part);
+  return f;
+}
+
+/* f(XA) - f(XB), summed pair by pair as sum_{i<j} [w(rA-d)^2 - w(rB-d)^2],
+ * plus the scale sum_{i<j} |w(rA-d)^2 - w(rB-d)^2| of that sum: the
+ * comparison of Algorithm 2 (line 6) and the size of the terms it rests on. */
+void slo_stress_delta(int32_t n, int32_t dim, const double* D, const double* XA, const double* XB,
+                      double* delta, double* scale) {
+  double* pd = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* ps = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!pd || !ps) { free(pd); free(ps); *delta = NAN; *scale = NAN; return; }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < n; ++i) {
+    double sd = 0.0, ss = 0.0;
+    for (int32_t j = i + 1; j < n; ++j) {
+      double d = D[(size_t)i * n + j];
+      double w = w_of(d);
+      if (w == 0.0) continue;
+      double ea = dist(dim, XA + (size_t)i * dim, XA + (size_t)j * dim) - d;
+      double eb = dist(dim, XB + (size_t)i * dim, XB + (size_t)j * dim) - d;
+      double t = w * ea * ea - w * eb * eb;
+      sd += t;
+      ss += fabs(t);
+    }
+    pd[i] = sd;
+    ps[i] = ss;
+  }
+  double a = 0.0, b = 0.0;
+  for (int32_t i = 0; i < n; ++i) { a += pd[i]; b += ps[i]; }
+  *delta = a;
+  *scale = b;
+  free(pd);
+  free(ps);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Laplacians of Prop. 2.1, applied to a placement.                       */
+/*   l^W_ij = -w_ij (i != j),  l^W_ii = -sum_{k != i} l^W_ik              */
+/*   l^Y_ij = 0 if y_i = y_j, else -w_ij d_ij / ||y_i - y_j|| (i != j),   */
+/*   l^Y_ii = -sum_{k != i} l^Y_ik                                        */
+/* ---------------------------------------------------------------------- */
+static double lw_entry(int32_t n, const double* D, int32_t i, int32_t j) {
+  if (i != j) return -w_of(D[(size_t)i * n + j]);
+  double s = 0.0;
+  for (int32_t k = 0; k < n; ++k)
+    if (k != i) s += w_of(D[(size_t)i * n + k]);
+  return s;
+}
+
+static double ly_offdiag(int32_t n, int32_t dim, const double* D, const double* Y, int32_t i, int32_t j) {
+  double r = dist(dim, Y + (size_t)i * dim, Y + (size_t)j * dim);
+  if (r == 0.0) return 0.0;
+  return -wd_of(D[(size_t)i * n + j]) / r;
+}
+
+/* out = L^W X (n x dim) */
+void slo_apply_LW(int32_t n, int32_t dim, const double* D, const double* X, double* out) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t c = 0; c < dim; ++c) {
+      double s = 0.0;
+      for (int32_t j = 0; j < n; ++j) s += lw_entry(n, D, i, j) * X[(size_t)j * dim + c];
+      out[(size_t)i * dim + c] = s;
+    }
+  }
+}
+
+/* out = L^Y Y (n x dim) */
+void slo_apply_LY(int32_t n, int32_t dim, const double* D, const double* Y, double* out) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < n; ++i) {
+    double diag = 0.0;
+    for (int32_t k = 0; k < n; ++k)
+      if (k != i) diag -= ly_offdiag(n, dim, D, Y, i, k);
+    for (int32_t c = 0; c < dim; ++c) {
+      double s = diag * Y[(size_t)i * dim + c];
+      for (int32_t j = 0; j < n; ++j)
+        if (j != i) s += ly_offdiag(n, dim, D, Y, i, j) * Y[(size_t)j * dim + c];
+      out[(size_t)i * dim + c] = s;
+    }
+  }
+}
+
+/* g(X, Y) = tr(X^T L^W X) - 2 tr(X^T L^Y Y) + C, C = sum_{i<j} w_ij d_ij^2 (eq. 2). */
+double slo_majorant(int32_t n, int32_t dim, const double* D, const double* X, const double* Y) {
+  size_t nd = (size_t)n * dim;
+  double* LX = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  double* LYY = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  if (!LX || !LYY) { free(LX); free(LYY); return NAN; }
+  slo_apply_LW(n, dim, D, X, LX);
+  slo_apply_LY(n, dim, D, Y, LYY);
+  double t1 = 0.0, t2 = 0.0, C = 0.0;
+  for (size_t k = 0; k < nd; ++k) {
+    t1 += X[k] * LX[k];
+    t2 += X[k] * LYY[k];
+  }
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t j = i + 1; j < n; ++j) C += wdd_of(D[(size_t)i * n + j]);
+  free(LX);
+  free(LYY);
+  return t1 - 2.0 * t2 + C;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The majorization step H (Algorithm 1/2, line 4): X^H solves             */
+/*   L^W X^H = L^X X          (eq. 5 with Y = X, one column per dimension) */
+/* ---------------------------------------------------------------------- */
+
+/* One Jacobi update of row i of eq. 5 from the iterate X:
+ *   l^W_ii x_i^H = (L^X X)_i - sum_{j != i} l^W_ij x_j
+ *   x_i^H = [ (L^X X)_i + sum_{j != i} w_ij x_j ] / W_i,
+ * with (L^X X)_i = sum_{j != i, x_j != x_i} w_ij d_ij (x_i - x_j) / ||x_i - x_j||.
+ * A vertex with W_i = 0 (no path to any other vertex) keeps its position. */
+void slo_h_jacobi_row(int32_t n, int32_t dim, const double* drow, int32_t i, const double* X,
+                      double* xh) {
+  const double* xi = X + (size_t)i * dim;
+  double Wi = 0.0;
+  for (int32_t j = 0; j < n; ++j)
+    if (j != i) Wi += w_of(drow[j]);
+  if (Wi == 0.0) {
+    for (int32_t c = 0; c < dim; ++c) xh[c] = xi[c];
+    return;
+  }
+  for (int32_t c = 0; c < dim; ++c) {
+    double lyx = 0.0, wx = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double* xj = X + (size_t)j * dim;
+      double w = w_of(drow[j]);
+      if (w == 0.0) continue;
+      double r = dist(dim, xi, xj);
+      if (r != 0.0) lyx += wd_of(drow[j]) / r * (xi[c] - xj[c]);
+      wx += w * xj[c];
+    }
+    xh[c] = (lyx + wx) / Wi;
+  }
+}
+
+void slo_h_jacobi(int32_t n, int32_t dim, const double* D, const double* X, double* XH) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < n; ++i) slo_h_jacobi_row(n, dim, D + (size_t)i * n, i, X, XH + (size_t)i * dim);
+}
+
+/* Jacobi rows for a sample of vertices whose distance rows are given:
+ * Drows[k] is the distance row of vertex rows[k]; XH_rows[k] receives x^H of it. */
+void slo_h_jacobi_rows(int32_t n, int32_t dim, const double* Drows, const int32_t* rows, int32_t nrows,
+                       const double* X, double* XH_rows) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t k = 0; k < nrows; ++k)
+    slo_h_jacobi_row(n, dim, Drows + (size_t)k * n, rows[k], X, XH_rows + (size_t)k * dim);
+}
+
+/* Sequential (Gauss-Seidel) sweep of the same row update: rows are updated
+ * in place for i = 0 .. n-1, each one seeing the newest positions of the rows
+ * before it (the "one-by-one" vertex update of Kamada-Kawai style methods). */
+void slo_h_gauss_seidel(int32_t n, int32_t dim, const double* D, const double* X, double* XH) {
+  memcpy(XH, X, sizeof(double) * (size_t)n * dim);
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)(dim > 0 ? dim : 1));
+  if (!tmp) return;
+  for (int32_t i = 0; i < n; ++i) {
+    slo_h_jacobi_row(n, dim, D + (size_t)i * n, i, XH, tmp);
+    for (int32_t c = 0; c < dim; ++c) XH[(size_t)i * dim + c] = tmp[c];
+  }
+  free(tmp);
+}
+
+/* Exact solve of eq. 5, as the paper reduces it: within each connected
+ * component the lowest-numbered vertex p is held fixed, its row and column
+ * are dropped, and the remaining symmetric positive definite system is
+ * solved by a Cholesky factorization computed once.  The paper fixes
+ * x_1 = 0; holding x_p at its current position instead only translates the
+ * component. */
+typedef struct {
+  int32_t n;
+  int32_t ncomp;
+  int32_t* comp_start;  /* ncomp + 1 offsets into verts */
+  int32_t* verts;       /* vertices grouped by component, ascending; first = pinned */
+  double** chol;        /* per component: lower factor of size (m x m), m = size - 1 */
+} slo_exact_ctx;
+
+void slo_exact_free(slo_exact_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->chol)
+    for (int32_t c = 0; c < ctx->ncomp; ++c) free(ctx->chol[c]);
+  free(ctx->chol);
+  free(ctx->comp_start);
+  free(ctx->verts);
+  free(ctx);
+}
+
+slo_exact_ctx* slo_exact_prepare(int32_t n, const double* D) {
+  slo_exact_ctx* ctx = (slo_exact_ctx*)calloc(1, sizeof(slo_exact_ctx));
+  if (!ctx) return NULL;
+  ctx->n = n;
+  int32_t* label = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  ctx->verts = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  ctx->comp_start = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  if (!label || !ctx->verts || !ctx->comp_start) { free(label); slo_exact_free(ctx); return NULL; }
+  for (int32_t i = 0; i < n; ++i) label[i] = -1;
+  int32_t ncomp = 0, pos = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (label[i] >= 0) continue;
+    ctx->comp_start[ncomp] = pos;
+    for (int32_t j = i; j < n; ++j)
+      if (label[j] < 0 && isfinite(D[(size_t)i * n + j])) {
+        label[j] = ncomp;
+        ctx->verts[pos++] = j;
+      }
+    ++ncomp;
+  }
+  ctx->comp_start[ncomp] = pos;
+  ctx->ncomp = ncomp;
+  free(label);
+  ctx->chol = (double**)calloc((size_t)(ncomp > 0 ? ncomp : 1), sizeof(double*));
+  if (!ctx->chol) { slo_exact_free(ctx); return NULL; }
+  for (int32_t c = 0; c < ncomp; ++c) {
+    int32_t s = ctx->comp_start[c], m = ctx->comp_start[c + 1] - s - 1;
+    if (m <= 0) continue;
+    const int32_t* v = ctx->verts + s + 1;
+    double* L = (double*)calloc((size_t)m * m, sizeof(double));
+    if (!L) { slo_exact_free(ctx); return NULL; }
+    for (int32_t a = 0; a < m; ++a)
+      for (int32_t b = 0; b < m; ++b) L[(size_t)a * m + b] = lw_entry(n, D, v[a], v[b]);
+    /* in-place Cholesky, lower triangle: A = L L^T */
+    for (int32_t j = 0; j < m; ++j) {
+      double s2 = L[(size_t)j * m + j];
+      for (int32_t k = 0; k < j; ++k) s2 -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+      if (!(s2 > 0.0)) { free(L); slo_exact_free(ctx); return NULL; }
+      double ljj = sqrt(s2);
+      L[(size_t)j * m + j] = ljj;
+#pragma omp parallel for schedule(static)
+      for (int32_t i = j + 1; i < m; ++i) {
+        double t = L[(size_t)i * m + j];
+        for (int32_t k = 0; k < j; ++k) t -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+        L[(size_t)i * m + j] = t / ljj;
+      }
+    }
+    ctx->chol[c] = L;
+  }
+  return ctx;
+}
+
+int slo_h_exact(const slo_exact_ctx* ctx, int32_t dim, const double* D, const double* X, double* XH) {
+  int32_t n = ctx->n;
+  size_t nd = (size_t)n * dim;
+  double* LYX = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  if (!LYX) return SLO_ENOMEM;
+  slo_apply_LY(n, dim, D, X, LYX);
+  memcpy(XH, X, sizeof(double) * nd);
+  for (int32_t c = 0; c < ctx->ncomp; ++c) {
+    int32_t s = ctx->comp_start[c], m = ctx->comp_start[c + 1] - s - 1;
+    if (m <= 0) continue;
+    int32_t p = ctx->verts[s];
+    const int32_t* v = ctx->verts + s + 1;
+    const double* L = ctx->chol[c];
+    double* y = (double*)malloc(sizeof(double) * (size_t)m);
+    if (!y) { free(LYX); return SLO_ENOMEM; }
+    for (int32_t col = 0; col < dim; ++col) {
+      /* right-hand side: (L^X X)_i - l^W_ip x_p for the kept rows */
+      for (int32_t a = 0; a < m; ++a)
+        y[a] = LYX[(size_t)v[a] * dim + col] - lw_entry(n, D, v[a], p) * X[(size_t)p * dim + col];
+      for (int32_t a = 0; a < m; ++a) { /* forward: L z = b */
+        double t = y[a];
+        for (int32_t k = 0; k < a; ++k) t -= L[(size_t)a * m + k] * y[k];
+        y[a] = t / L[(size_t)a * m + a];
+      }
+      for (int32_t a = m - 1; a >= 0; --a) { /* backward: L^T x = z */
+        double t = y[a];
+        for (int32_t k = a + 1; k < m; ++k) t -= L[(size_t)k * m + a] * y[k];
+        y[a] = t / L[(size_t)a * m + a];
+      }
+      for (int32_t a = 0; a < m; ++a) XH[(size_t)v[a] * dim + col] = y[a];
+    }
+    free(y);
+  }
+  free(LYX);
+  return SLO_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Termination measure: the relative size of the step H(X) - X,            */
+/*   res = ||X^H - X||_F / ||X^H - mean(X^H)||_F   (0 when both are 0).     */
+/* ---------------------------------------------------------------------- */
+double slo_residual(int32_t n, int32_t dim, const double* X, const double* XH) {
+  double num = 0.0, den = 0.0;
+  for (int32_t c = 0; c < dim; ++c) {
+    double mean = 0.0;
+    for (int32_t i = 0; i < n; ++i) mean += XH[(size_t)i * dim + c];
+    mean /= (n > 0 ? n : 1);
+    for (int32_t i = 0; i < n; ++i) {
+      double a = XH[(size_t)i * dim + c] - X[(size_t)i * dim + c];
+      double b = XH[(size_t)i * dim + c] - mean;
+      num += a * a;
+      den += b * b;
+    }
+  }
+  if (num == 0.0) return 0.0;
+  return sqrt(num) / sqrt(den);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Algorithm 2 (Algorithm 1 when omega = 1).                               */
+/* omega is the classical relaxation factor: the paper's factor is          */
+/* omega - 1, so the extrapolation of eq. 11 reads                          */
+/*   X~ = X^H + (omega - 1)(X^H - X).                                       */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t iterations;
+  int32_t converged;
+  int32_t rejected;
+  int32_t status;
+  double residual;  /* residual of the last step taken */
+} slo_result;
+
+/* trace (optional): max_iter rows of SLO_TRACE_COLS doubles:
+ *   [0] res_k   [1] accepted (1/0; -1 when no extrapolation is formed)
+ *   [2] f(X~) - f(X^H)   [3] scale of that sum   [4] f(X^k) (NAN unless trace_stress)
+ * xtrace (optional): max_iter placements X^{k+1}, n*dim each. */
+#define SLO_TRACE_COLS 5
+
+int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega, double tol,
+               int32_t max_iter, int32_t ordering, int32_t safeguard, int32_t trace_stress,
+               double* trace, double* xtrace, slo_result* out) {
+  memset(out, 0, sizeof(*out));
+  if (n < 0 || dim < 1 || !(omega > 0.0) || !(tol >= 0.0) || max_iter < 0) return SLO_EINVAL;
+  if (ordering != SLO_JACOBI && ordering != SLO_EXACT && ordering != SLO_GAUSS_SEIDEL) return SLO_EINVAL;
+  const double omega_p = omega - 1.0;
+  size_t nd = (size_t)n * dim;
+  double* XH = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  double* XT = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  slo_exact_ctx* ctx = NULL;
+  if (!XH || !XT) { free(XH); free(XT); return SLO_ENOMEM; }
+  if (ordering == SLO_EXACT && n > 0) {
+    ctx = slo_exact_prepare(n, D);
+    if (!ctx) { free(XH); free(XT); return SLO_ENOMEM; }
+  }
+  int status = SLO_OK;
+  /* a single vertex (or none) is already laid out: no step is taken */
+  for (int32_t k = 0; k < max_iter && n > 1; ++k) {
+    double f_k = trace_stress ? slo_stress(n, dim, D, X) : NAN;
+    /* line 4: X^{k+1} <- H(X^k) */
+    if (ordering == SLO_JACOBI) slo_h_jacobi(n, dim, D, X, XH);
+    else if (ordering == SLO_GAUSS_SEIDEL) slo_h_gauss_seidel(n, dim, D, X, XH);
+    else status = slo_h_exact(ctx, dim, D, X, XH);
+    if (status != SLO_OK) break;
+    for (size_t q = 0; q < nd; ++q)
+      if (!isfinite(XH[q])) status = SLO_ENUMERIC;
+    if (status != SLO_OK) break;
+    double res = slo_residual(n, dim, X, XH);
+    double accepted = -1.0, df = 0.0, scale = 0.0;
+    if (omega_p == 0.0) {
+      memcpy(X, XH, sizeof(double) * nd);
+    } else {
+      /* line 5 (eq. 11): X~ = X^H + omega_p (X^H - X^k) */
+      for (size_t q = 0; q < nd; ++q) XT[q] = XH[q] + omega_p * (XH[q] - X[q]);
+      int take = 1;
+      if (safeguard) {
+        /* line 6: keep X~ only if f(X~) <= f(X^H) */
+        slo_stress_delta(n, dim, D, XT, XH, &df, &scale);
+        take = (df <= 0.0);
+      }
+      accepted = take ? 1.0 : 0.0;
+      if (!take) out->rejected += 1;
+      memcpy(X, take ? XT : XH, sizeof(double) * nd);
+    }
+    out->iterations = k + 1;
+    out->residual = res;
+    if (trace) {
+      double* row = trace + (size_t)k * SLO_TRACE_COLS;
+      row[0] = res;
+      row[1] = accepted;
+      row[2] = df;
+      row[3] = scale;
+      row[4] = f_k;
+    }
+    if (xtrace) memcpy(xtrace + (size_t)k * nd, X, sizeof(double) * nd);
+    if (res <= tol) {
+      out->converged = 1;
+      break;
+    }
+  }
+  if (n <= 1 && status == SLO_OK) out->converged = 1;
+  slo_exact_free(ctx);
+  free(XH);
+  free(XT);
+  out->status = status;
+  return status;
+}

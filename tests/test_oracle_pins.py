@@ -1,0 +1,436 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+None of these tests retypes the oracle's formula.  Each checks the oracle
+against an independent fact: a hand-computed step (tests/golden/hand_cases.txt),
+a closed form, an identity between two different definitions in the paper
+(pair sums of eq. 1 vs the Laplacian form of eq. 2; the row form of eq. 5 vs
+the gradient of f), an invariant (Newton's third law, rigid-motion and
+symmetry equivariance), a library routine (scipy shortest paths) or the
+convergence theory of Sec. 3.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path
+
+import oracle
+from fixtures import hand_cases, ppi_fig4a
+from paper_1711_01228_amd import inputs
+
+CASES = hand_cases()
+
+
+def dmat(g):
+    return oracle.apsp(g.row_ptr, g.col_idx, g.edge_len)
+
+
+# ---------------------------------------------------------------------------
+# hand-computed steps
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_hand_case_steps(name):
+    c = CASES[name]
+    g = inputs.to_csr(c["n"], c["edges"])
+    D = dmat(g)
+    X0 = c["x0"]
+    np.testing.assert_allclose(oracle.weight_sums(D), c["W"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(oracle.stress(D, X0), c["stress_x0"], rtol=1e-14, atol=0)
+    XJ = oracle.h_jacobi(D, X0)
+    np.testing.assert_allclose(XJ, c["jacobi"], rtol=0, atol=1e-14)
+    if "stress_jacobi" in c:
+        np.testing.assert_allclose(oracle.stress(D, XJ), c["stress_jacobi"], rtol=1e-13, atol=0)
+    if "gauss_seidel" in c:
+        np.testing.assert_allclose(oracle.h_gauss_seidel(D, X0), c["gauss_seidel"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(oracle.h_exact(D, X0), c["exact"], rtol=0, atol=1e-14)
+
+
+def test_two_vertex_jacobi_oscillates_and_sor_driver_reports_it():
+    # r_01 alternates 0.5 -> 1.5 -> 0.5: the residual never drops
+    c = CASES["n2_edge"]
+    D = dmat(inputs.to_csr(2, c["edges"]))
+    X, info = oracle.layout(D, c["x0"], omega=1.0, tol=1e-6, max_iter=9)
+    assert info["iterations"] == 9 and not info["converged"]
+    r = np.linalg.norm(X[0] - X[1])
+    assert abs(r - 1.5) < 1e-14  # odd number of steps
+    # residual of X=(0,0),(0.5,0) -> X^H=(-0.5,0),(1,0): ||dX|| = sqrt(0.5), spread sqrt(2*0.75^2)
+    np.testing.assert_allclose(info["trace"][0, 0], 2.0 / 3.0, rtol=1e-14)
+
+
+def test_residual_closed_form():
+    X = np.array([[0.0, 0.0], [0.5, 0.0]])
+    XH = np.array([[-0.5, 0.0], [1.0, 0.0]])
+    assert oracle.residual(X, XH) == pytest.approx(2.0 / 3.0, rel=1e-15)
+    assert oracle.residual(X, X) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# distances and weights
+# ---------------------------------------------------------------------------
+def test_grid_distances_closed_form():
+    R, C = 5, 7
+    g = inputs.grid_graph(R, C)
+    D = dmat(g)
+    r, c = np.divmod(np.arange(R * C), C)
+    expect = np.abs(r[:, None] - r[None, :]) + np.abs(c[:, None] - c[None, :])
+    np.testing.assert_array_equal(D, expect)
+    with np.errstate(divide="ignore"):
+        w = np.where(expect > 0, 1.0 / expect.astype(float) ** 2, 0.0)
+    np.testing.assert_allclose(oracle.weight_sums(D), w.sum(1), rtol=1e-14)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_distances_match_scipy(weighted):
+    g = inputs.erdos_renyi(300, 280, seed=7)  # sparse: many components, isolated vertices
+    lengths = None
+    if weighted:
+        rng = np.random.default_rng(3)
+        e = g.edges()
+        lengths = rng.uniform(0.5, 2.0, size=len(e))
+        g = inputs.to_csr(g.n, e, lengths)
+        lengths = g.edge_len.astype(np.float64)
+    D = oracle.apsp(g.row_ptr, g.col_idx, lengths)
+    data = np.ones(g.nnz) if lengths is None else lengths
+    A = sp.csr_matrix((data, g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    ref = shortest_path(A, method="D", directed=False, unweighted=lengths is None)
+    np.testing.assert_allclose(D, ref, rtol=1e-12)
+    assert np.isinf(D).any()
+    rows = np.array([0, 17, 299, 5])
+    np.testing.assert_array_equal(oracle.sssp_rows(g.row_ptr, g.col_idx, rows, lengths), D[rows])
+
+
+# ---------------------------------------------------------------------------
+# stress, eq. 1, and the majorant, eq. 2
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("s", [1.0, 0.5, 2.5])
+def test_stress_of_scaled_path_closed_form(s):
+    # P_n drawn on a line with spacing s: r_ij = s d_ij, w d^2 = 1 -> f = (s-1)^2 n(n-1)/2
+    n = 11
+    g = inputs.path_graph(n)
+    X = np.stack([s * np.arange(n), np.zeros(n)], axis=1)
+    assert oracle.stress(dmat(g), X) == pytest.approx((s - 1) ** 2 * n * (n - 1) / 2, rel=1e-13, abs=1e-24)
+
+
+def test_stress_rigid_motion_invariant():
+    g = inputs.erdos_renyi(60, 90, seed=1)
+    D = dmat(g)
+    X = inputs.uniform_positions(60, 3, seed=2)
+    q, _ = np.linalg.qr(np.random.default_rng(0).normal(size=(3, 3)))
+    f0 = oracle.stress(D, X)
+    assert oracle.stress(D, X @ q.T + np.array([3.0, -1.0, 7.0])) == pytest.approx(f0, rel=1e-12)
+
+
+def test_majorant_dominates_stress():
+    # Prop. 2.1: f(X) <= g(X, Y) for all X, Y, with equality at X = Y
+    g = inputs.erdos_renyi(40, 70, seed=11)
+    D = dmat(g)
+    rng = np.random.default_rng(5)
+    for t in range(6):
+        X = rng.normal(size=(40, 2))
+        Y = rng.normal(size=(40, 2))
+        Y[3] = Y[8]  # coincident pair: l^Y_38 = 0 (Prop. 2.1)
+        f = oracle.stress(D, X)
+        assert f <= oracle.majorant(D, X, Y) + 1e-12 * abs(f)
+        assert oracle.majorant(D, X, X) == pytest.approx(f, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the majorization step H, eq. 5
+# ---------------------------------------------------------------------------
+def _er_case(n=50, m=90, seed=3, dim=2):
+    g = inputs.erdos_renyi(n, m, seed)
+    return dmat(g), inputs.uniform_positions(n, dim, seed + 1)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_exact_step_solves_eq5_and_minimizes_majorant(dim):
+    D, X = _er_case(dim=dim)
+    XH = oracle.h_exact(D, X)
+    lhs, rhs = oracle.apply_LW(D, XH), oracle.apply_LY(D, X)
+    assert np.abs(lhs - rhs).max() <= 1e-10 * np.abs(rhs).max()
+    # X^H = argmin_X g(X, X^k) (eq. 4): any perturbation raises g
+    g0 = oracle.majorant(D, XH, X)
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        V = rng.normal(size=X.shape)
+        assert oracle.majorant(D, XH + 1e-3 * V, X) >= g0 - 1e-12 * abs(g0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_jacobi_step_is_row_solve_of_eq5(dim):
+    # row i of eq. 5 solved for x_i with every other x_j held at X:
+    # W_i x_i^H + sum_{j != i} l^W_ij x_j = (L^X X)_i  <=>  diag(W)(X^H - X) + L^W X = L^X X
+    D, X = _er_case(dim=dim)
+    XH = oracle.h_jacobi(D, X)
+    W = oracle.weight_sums(D)
+    lhs = W[:, None] * (XH - X) + oracle.apply_LW(D, X)
+    rhs = oracle.apply_LY(D, X)
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+def test_jacobi_step_is_preconditioned_gradient_step():
+    # x_i^H = x_i - grad_i f / (2 W_i): gradient by central differences of eq. 1
+    D, X = _er_case(n=30, m=50, seed=9)
+    XH = oracle.h_jacobi(D, X)
+    W = oracle.weight_sums(D)
+    h = 1e-6
+    grad = np.zeros_like(X)
+    for i in range(X.shape[0]):
+        for c in range(X.shape[1]):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, c] += h
+            Xm[i, c] -= h
+            grad[i, c] = (oracle.stress(D, Xp) - oracle.stress(D, Xm)) / (2 * h)
+    moving = W > 0
+    expect = X.copy()
+    expect[moving] = X[moving] - grad[moving] / (2 * W[moving, None])
+    np.testing.assert_allclose(XH, expect, rtol=0, atol=1e-7)
+    np.testing.assert_array_equal(XH[~moving], X[~moving])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_newton_third_law(dim):
+    # pair forces are equal and opposite and central: sum_i W_i (x_i^H - x_i) = 0 and zero torque
+    D, X = _er_case(n=80, m=200, seed=4, dim=dim)
+    X = X * 10 + 3.0
+    XH = oracle.h_jacobi(D, X)
+    F = oracle.weight_sums(D)[:, None] * (XH - X)
+    scale = np.abs(F).sum()
+    assert np.abs(F.sum(0)).max() <= 1e-13 * scale
+    if dim == 2:
+        torque = np.sum(X[:, 0] * F[:, 1] - X[:, 1] * F[:, 0])
+    else:
+        torque = np.cross(X, F).sum(0)
+    assert np.abs(torque).max() <= 1e-13 * scale * np.abs(X).max()
+
+
+def test_isolated_and_coincident_vertices():
+    g = inputs.to_csr(5, [(0, 1), (1, 2)])  # 3 and 4 isolated
+    D = dmat(g)
+    X = np.array([[0.0, 0.0], [0.0, 0.0], [1.0, 0.0], [5.0, 5.0], [7.0, 1.0]])  # 0 and 1 coincide
+    XH = oracle.h_jacobi(D, X)
+    assert np.isfinite(XH).all()
+    np.testing.assert_array_equal(XH[3:], X[3:])
+    # vertex 0: pair (0,1) is coincident (l^X_01 = 0, Prop. 2.1), pair (0,2): d = 2, r = 1
+    # x_0^H = [w01 x_1 + w02 x_2 + (w02 d02 / r02)(x_0 - x_2)] / W_0 = [0 + 0.25 (1,0) - 0.5 (1,0)] / 1.25
+    np.testing.assert_allclose(XH[0], [-0.2, 0.0], atol=1e-15)
+
+
+def test_monotone_descent_exact_and_gauss_seidel():
+    # Prop. 2.2: f(X^{k+1}) <= f(X^k) for the majorization sequence (exact H);
+    # the in-place sweep minimizes the same majorant one coordinate block at a time
+    g = inputs.erdos_renyi(70, 140, seed=21)
+    D = dmat(g)
+    for ordering in ("exact", "gauss_seidel"):
+        X, info = oracle.layout(D, inputs.uniform_positions(70, 2, 22), omega=1.0, tol=0,
+                                max_iter=25, ordering=ordering, trace_stress=True)
+        f = info["trace"][:, 4]
+        assert np.all(np.diff(f) <= 1e-12 * f[0]), ordering
+
+
+def test_symmetric_start_stays_symmetric():
+    # 4x4 grid, start invariant under the quarter turn sigma(r, c) = (c, 3 - r) about (1.5, 1.5)
+    k = 4
+    g = inputs.grid_graph(k, k)
+    D = dmat(g)
+    sig = np.array([c * k + (k - 1 - r) for r in range(k) for c in range(k)])
+    A = np.array([[0.0, -1.0], [1.0, 0.0]])  # quarter turn: (c, r) -> (3 - r, c) about the centre
+    ctr = np.array([1.5, 1.5])
+    rng = np.random.default_rng(8)
+    X = np.full((k * k, 2), np.nan)
+    for i in range(k * k):
+        if np.isnan(X[i, 0]):
+            X[i] = rng.uniform(0, 3, size=2)
+            j = i
+            for _ in range(3):
+                X[sig[j]] = A @ (X[j] - ctr) + ctr
+                j = sig[j]
+    grid_pos = np.stack(np.divmod(np.arange(k * k), k), 1)[:, ::-1].astype(float)  # (c, r)
+    np.testing.assert_allclose(grid_pos[sig], (A @ (grid_pos - ctr).T).T + ctr)  # A realizes sigma
+    for ordering in ("jacobi", "exact"):
+        Y, _ = oracle.layout(D, X, omega=1.0, tol=0, max_iter=6, ordering=ordering)
+        Yc = Y - Y.mean(0)
+        np.testing.assert_allclose(Yc[sig], Yc @ A.T, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 driver
+# ---------------------------------------------------------------------------
+def test_omega_one_is_algorithm1_bit_exact():
+    D, X0 = _er_case(n=60, m=120, seed=31)
+    X, info = oracle.layout(D, X0, omega=1.0, tol=0, max_iter=7)
+    Y = X0.copy()
+    for _ in range(7):
+        Y = oracle.h_jacobi(D, Y)
+    np.testing.assert_array_equal(X, Y)
+    assert np.all(info["trace"][:, 1] == -1)
+
+
+def test_extrapolation_is_eq10():
+    # without the safeguard the step is (1 + w) X^{k+1} - w X^k (eq. 10), w = omega - 1
+    D, X0 = _er_case(n=60, m=120, seed=32)
+    w = 0.7
+    X, info = oracle.layout(D, X0, omega=1 + w, tol=0, max_iter=1, safeguard=False)
+    XH = oracle.h_jacobi(D, X0)
+    np.testing.assert_allclose(X, (1 + w) * XH - w * X0, rtol=1e-14, atol=1e-14)
+    assert info["rejected"] == 0
+
+
+@pytest.mark.parametrize("omega", [1.5, 3.0])
+def test_safeguard_keeps_the_better_placement(omega):
+    # Algorithm 2, lines 6-8: X~ replaces X^{k+1} only if f(X~) <= f(X^{k+1})
+    D, X0 = _er_case(n=80, m=160, seed=33)
+    X = X0.copy()
+    decisions = []
+    for k in range(6):
+        XH = oracle.h_jacobi(D, X)
+        XT = XH + (omega - 1) * (XH - X)
+        X1, info = oracle.layout(D, X, omega=omega, tol=0, max_iter=1)
+        take = oracle.stress(D, XT) <= oracle.stress(D, XH)
+        decisions.append(take)
+        np.testing.assert_array_equal(X1, XT if take else XH)
+        assert oracle.stress(D, X1) <= oracle.stress(D, XH) * (1 + 1e-14)
+        df, scale = info["trace"][0, 2], info["trace"][0, 3]
+        assert df == pytest.approx(oracle.stress(D, XT) - oracle.stress(D, XH), abs=1e-10 * scale)
+        X = X1
+    if omega == 3.0:
+        assert not all(decisions)  # a stride this long is rejected at least once
+
+
+def test_degenerate_sizes():
+    X, info = oracle.layout(np.zeros((1, 1)), np.array([[0.3, 0.4]]), omega=1.5, max_iter=10)
+    assert info["iterations"] == 0 and info["converged"]
+    D, X0 = _er_case()
+    X, info = oracle.layout(D, X0, omega=1.5, max_iter=0)
+    np.testing.assert_array_equal(X, X0)
+    assert info["iterations"] == 0 and not info["converged"]
+    g = inputs.to_csr(6, [])
+    X, info = oracle.layout(dmat(g), inputs.uniform_positions(6, 2, 1), max_iter=5)
+    assert info["iterations"] == 1 and info["converged"]
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3: convergence rate (Thm. 3.2) and the admissible relaxation factors
+# ---------------------------------------------------------------------------
+def _hessian(D, X):
+    """d^2 f / dX^2 of eq. 1 written from the pair term: for a pair (i, j) the
+    block is 2w[(d/r) u u^T + (1 - d/r) I] on (i,i), (j,j) and its negative on (i,j)."""
+    n, dim = X.shape
+    H = np.zeros((n * dim, n * dim))
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = D[i, j]
+            if not (0 < d < np.inf):
+                continue
+            w = d ** -2.0
+            v = X[i] - X[j]
+            r = np.linalg.norm(v)
+            u = v / r
+            B = 2 * w * ((d / r) * np.outer(u, u) + (1 - d / r) * np.eye(dim))
+            si, sj = slice(i * dim, i * dim + dim), slice(j * dim, j * dim + dim)
+            H[si, si] += B
+            H[sj, sj] += B
+            H[si, sj] -= B
+            H[sj, si] -= B
+    return H
+
+
+def _gen_eigs(H, P, dim, n):
+    """Generalized eigenvalues of H z = lambda P z on the complement of translations,
+    with the rigid rotation modes (lambda ~ 0) dropped."""
+    T = np.zeros((n * dim, dim))
+    for c in range(dim):
+        T[c::dim, c] = 1.0
+    Q, _ = np.linalg.qr(np.concatenate([T, np.random.default_rng(0).normal(size=(n * dim, n * dim - dim))], 1))
+    Q = Q[:, dim:]
+    Hr, Pr = Q.T @ H @ Q, Q.T @ P @ Q
+    Lc = np.linalg.cholesky(Pr)
+    Li = np.linalg.inv(Lc)
+    lam = np.linalg.eigvalsh(Li @ Hr @ Li.T)
+    return lam[lam > 1e-8]
+
+
+def _grid3_optimum():
+    g = inputs.grid_graph(3, 3)
+    D = dmat(g)
+    X0 = np.stack(np.divmod(np.arange(9), 3), 1).astype(float) + 0.05 * np.random.default_rng(2).normal(size=(9, 2))
+    Xs, info = oracle.layout(D, X0, omega=1.0, tol=1e-14, max_iter=2000, ordering="exact")
+    assert info["converged"]
+    return D, Xs
+
+
+def _observed_rate(D, Xs, omega, ordering, iters=40, tail=20):
+    # start 1e-4 away: small enough for the linearization, far enough that the
+    # residual stays well above rounding (~1e-16) over the whole run
+    X0 = Xs + 1e-4 * np.random.default_rng(4).normal(size=Xs.shape)
+    _, info = oracle.layout(D, X0, omega=omega, tol=0, max_iter=iters, ordering=ordering, safeguard=False)
+    res = info["trace"][:, 0]
+    return (res[-1] / res[-1 - tail]) ** (1.0 / tail)
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.5])
+def test_exact_rate_matches_theorem_3_2(omega):
+    D, Xs = _grid3_optimum()
+    H = _hessian(D, Xs)
+    LW = oracle.apply_LW(D, np.eye(9))  # columns of L^W
+    P = 2 * np.kron(LW, np.eye(2))  # D_11 g = 2 L^W
+    lam = _gen_eigs(H, P, 2, 9)
+    assert lam.max() == pytest.approx(1.0, abs=1e-9)  # uniform scaling: r.(d^2 f) r = 2 r.L^W r
+    predicted = max(abs(1 - omega * lam.min()), abs(1 - omega * lam.max()))
+    assert _observed_rate(D, Xs, omega, "exact") == pytest.approx(predicted, abs=5e-3)
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.5])
+def test_jacobi_rate_matches_linearization(omega):
+    D, Xs = _grid3_optimum()
+    H = _hessian(D, Xs)
+    P = 2 * np.kron(np.diag(oracle.weight_sums(D)), np.eye(2))  # the Jacobi step's curvature model
+    lam = _gen_eigs(H, P, 2, 9)
+    predicted = max(abs(1 - omega * lam.min()), abs(1 - omega * lam.max()))
+    assert _observed_rate(D, Xs, omega, "jacobi", iters=50, tail=25) == pytest.approx(predicted, abs=1e-2)
+
+
+def test_exact_converges_below_omega_two_and_diverges_above():
+    # linearized SOR map I - omega [D_11 g]^-1 D^2 f has the eigenvalue 1 - omega (scaling mode)
+    D, Xs = _grid3_optimum()
+    X0 = Xs * (1 + 1e-9)
+    _, a = oracle.layout(D, X0, omega=1.8, tol=0, max_iter=40, ordering="exact", safeguard=False)
+    _, b = oracle.layout(D, X0, omega=2.2, tol=0, max_iter=40, ordering="exact", safeguard=False)
+    assert a["trace"][-1, 0] < 1e-3 * a["trace"][0, 0]
+    assert b["trace"][-1, 0] > 100 * b["trace"][0, 0]
+
+
+# ---------------------------------------------------------------------------
+# the paper's own data: Fig. 4(a) and the iteration savings of Table 1
+# ---------------------------------------------------------------------------
+def test_printed_ppi_layout_is_near_a_stress_minimum():
+    # Fig. 4(a) shows a converged SOR layout.  Scaled to the stress-optimal size
+    # s = sum w d r / sum w r^2, polishing it with the exact step barely lowers f.
+    n, edges, P = ppi_fig4a()
+    g = inputs.to_csr(n, edges)
+    D = dmat(g)
+    assert np.isfinite(D).all() and D.max() == 20
+    iu = np.triu_indices(n, 1)
+    r = np.linalg.norm(P[:, None, :] - P[None, :, :], axis=2)[iu]
+    d = D[iu]
+    s = np.sum(r / d) / np.sum(r * r / (d * d))
+    f0 = oracle.stress(D, s * P)
+    X, _ = oracle.layout(D, s * P, omega=1.0, tol=1e-9, max_iter=400, ordering="exact")
+    f1 = oracle.stress(D, X)
+    assert f1 <= f0 and f1 >= 0.97 * f0
+    Xr, _ = oracle.layout(D, inputs.uniform_positions(n, 2, 5), omega=1.0, tol=1e-9, max_iter=400,
+                          ordering="exact")
+    assert oracle.stress(D, Xr) >= 0.97 * f1  # random starts do not beat the printed basin by much
+
+
+def test_sor_saves_iterations_like_table_1():
+    # Table 1: at the paper's factor 0.5 (omega = 1.5) SOR needs ~67% of the plain
+    # iterations.  Weak behavioural check on the 16 x 16 grid, mean over seeds.
+    ratios = []
+    for run in range(3):
+        g, X0 = inputs.grid16(run)
+        D = dmat(g)
+        _, a = oracle.layout(D, X0, omega=1.0, tol=1e-4, max_iter=3000)
+        _, b = oracle.layout(D, X0, omega=1.5, tol=1e-4, max_iter=3000)
+        assert a["converged"] and b["converged"]
+        ratios.append(b["iterations"] / a["iterations"])
+    assert 0.5 < np.mean(ratios) < 0.85
