@@ -1,0 +1,182 @@
+"""Benchmark: SOR stress-majorization layout of a Barabasi-Albert graph,
+n = 65,536, m = 3, 2-D, FP32, on one MI355X.
+
+A step is one iteration of Algorithm 2 at omega = 1.5 with the safeguard on:
+the all-pairs force pass, the Jacobi update and extrapolation, the safeguard
+pass f(X~) - f(X^H) and the select/termination kernel.  The plan (distances
+and weights) is built before the timed region, so inputs are resident in HBM.
+
+value = n (n - 1) * steps / seconds   (pair interactions of the force pass)
+
+Also reported: time-to-converge (res <= 1e-3) for omega = 1 and omega = 1.5
+from the same start, the roofline of the force kernel (HIP-event time), and
+the FP64 oracle's pair rate on a sample of rows on the host cores.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dim 2] [--quick]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-interactions/s + time-to-converge (SOR-ω vs ω=1) at n=65,536, 1 MI355X"
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed-FMA issue)
+FLOPS_PER_PAIR = {2: 12, 3: 17}  # algorithmic flops of one ordered pair of the force pass
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_ba65536_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1711_01228_amd", "csrc", "sl_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(dim):
+    """HBM bytes per force-pass launch from committed rocprofv3 counters, if they
+    were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha") != kernel_hash() or rec.get("dim") != dim:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(g, X0, target_s=12.0):
+    """The FP64 oracle's Jacobi step on a sample of rows of the same graph."""
+    import numpy as np
+
+    import oracle
+
+    n = g.n
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(n, 128, replace=False))
+    Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
+    t = time.perf_counter()
+    oracle.h_jacobi_rows(Drows, rows, X0)
+    t1 = time.perf_counter() - t
+    R = int(min(n, max(128, 128 * target_s / max(t1, 1e-3))))
+    rows = np.sort(rng.choice(n, R, replace=False))
+    Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
+    t = time.perf_counter()
+    oracle.h_jacobi_rows(Drows, rows, X0)
+    dt = time.perf_counter() - t
+    del Drows
+    pairs = R * (n - 1)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 Jacobi step (eq. 5 row solves) for %d random rows x all %d columns of the same "
+                      "BA graph and start, %.1f s; distance rows (BFS) not timed" % (R, n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3))
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--omega", type=float, default=1.5)
+    ap.add_argument("--quick", action="store_true", help="skip time-to-converge and the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1711_01228_amd import binding, build_lib, inputs
+
+    assert os.path.exists(build_lib.LIB), "libsorlayout.so is not built"
+    torch.cuda.set_device(0)
+    n, dim = args.n, args.dim
+    t0 = time.perf_counter()
+    g, X0 = inputs.ba65536(dim=dim, n=n)
+    log("graph: BA n=%d m=3, %d edges, max degree %d (%.1f s)" % (g.n, g.num_edges, np.diff(g.row_ptr).max(),
+                                                               time.perf_counter() - t0))
+    Xdev0 = torch.tensor(X0.astype(np.float32), device="cuda")
+    plan = binding.Plan(g, dim)
+    X = Xdev0.clone()
+    info = plan.run(X, omega=args.omega, tol=0.0, max_iter=max(args.warmup, 1))  # warmup (+ graph capture)
+    plan_ms = info["plan_ms"]
+    log("plan %.1f ms; warmup %d steps %.1f ms" % (plan_ms, info["iterations"], info["run_ms"]))
+
+    # ---- timed region: K steps
+    X = Xdev0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    info = plan.run(X, omega=args.omega, tol=0.0, max_iter=args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    assert info["iterations"] == args.steps, info
+    pairs = float(n) * (n - 1)
+    value = pairs * args.steps / wall
+    log("timed: %d steps %.3f s wall (%.3f s device), %.4g pair-interactions/s" % (args.steps, wall,
+                                                                                   info["run_ms"] / 1e3, value))
+
+    # ---- force-kernel roofline (HIP events on the kernels' stream)
+    ms = plan.profile(Xdev0, omega=args.omega, reps=5)
+    t_force = ms["force"] * 1e-3
+    flops = FLOPS_PER_PAIR[dim] * pairs
+    achieved = flops / t_force / 1e12
+    traffic = measured_traffic(dim)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "kernel": "k_force", "kernel_ms": round(ms["force"], 4),
+                "pairs_per_launch": pairs, "flops_per_pair": FLOPS_PER_PAIR[dim],
+                "algorithmic_bytes_per_launch": float(n) * n,
+                "hbm_GBps_algorithmic": round(float(n) * n / t_force / 1e9, 1),
+                "step_kernel_ms": {k: round(v, 4) for k, v in ms.items()}}
+    log("kernels (ms):", ms)
+
+    out = {"metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Barabasi-Albert n=%d m=3 (%d edges), %d-D, start U[0,1]^%d, omega=%.2f "
+                                  "with safeguard, Jacobi ordering" % (n, g.num_edges, dim, dim, args.omega),
+                      "n": n, "dim": dim, "omega": args.omega, "step": "one iteration of Algorithm 2"},
+           "plan_ms": plan_ms, "roofline": roofline}
+
+    # ---- time to converge: SOR-omega vs omega = 1 at equal final residual
+    if not args.quick:
+        ttc = {}
+        for om in (1.0, args.omega):
+            X = Xdev0.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = plan.run(X, omega=om, tol=1e-3, max_iter=3000)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t
+            ttc["omega=%g" % om] = {"seconds": round(w, 4), "device_s": round(r["run_ms"] / 1e3, 4),
+                                    "iterations": r["iterations"], "converged": bool(r["converged"]),
+                                    "rejected": r["rejected"], "final_residual": r["residual"],
+                                    "final_stress": r["stress"]}
+            log("time-to-converge omega=%g: %s" % (om, ttc["omega=%g" % om]))
+        a, b = ttc["omega=1"], ttc["omega=%g" % args.omega]
+        ttc["speedup"] = round(a["seconds"] / b["seconds"], 3)
+        ttc["tol"] = 1e-3
+        out["time_to_converge"] = ttc
+    plan.close()
+
+    if not args.quick and not args.no_cpu:
+        cb = cpu_baseline(g, X0)
+        out["cpu_baseline"] = cb
+        log("cpu baseline:", cb)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * sorlayout.h: C ABI of the MI355X (gfx950) library for SOR-accelerated
+ * stress-majorization graph layout.
+ *
+ * Method: Wang & Wang, "A Fast Successive Over-Relaxation Algorithm for
+ * Force-Directed Network Graph Drawing", Sci. China Inf. Sci. 55:677 (2012).
+ *
+ *   problem (Sec. 1, Sec. 2)  undirected G = (V, E), straight-line drawing,
+ *                             placement X in R^{n x dim}
+ *   stress (eq. 1)            f(X) = sum_{i<j} w_ij (||x_i - x_j|| - d_ij)^2,
+ *                             d_ij = graph distance, w_ij = d_ij^-2 (Sec. 5.1)
+ *   step H (Prop. 2.3, eq. 5) L^W X^H = L^X X; this library applies one Jacobi
+ *                             sweep of eq. 5 per iteration:
+ *                             x_i^H = x_i + (1/W_i) sum_j w_ij (d_ij - r_ij) u_ij
+ *   SOR (Alg. 2, eq. 11)      X~ = X^H + (omega - 1)(X^H - X); keep X~ only if
+ *                             f(X~) <= f(X^H) (Alg. 2, lines 6-8)
+ *   termination               res_k = ||X^H - X^k||_F / ||X^H - mean(X^H)||_F
+ *                             <= tol (the paper leaves the test open: Alg. 1/2)
+ *
+ * omega is the classical relaxation factor: the paper's factor is omega - 1,
+ * so omega = 1 is Algorithm 1 and the paper's 0.5, 1.0, 1.5 are omega = 1.5,
+ * 2.0, 2.5.
+ *
+ * Conventions for every call
+ *   - Every call returns sl_status (SL_OK = 0).  On failure sl_last_error()
+ *     returns a message for the calling thread; it stays valid until the
+ *     thread's next call into the library.
+ *   - The caller owns every buffer it passes.  The library keeps no caller
+ *     pointer after a call returns.  A plan owns its device memory (distances,
+ *     weights, iterates, workspaces) until sl_plan_destroy.
+ *   - Device work is queued on `stream` (a hipStream_t; NULL = the null
+ *     stream) of the current HIP device.  Calls that return results to the
+ *     host synchronize that stream before returning.
+ *   - Validation errors (SL_EINVAL) are reported before any device work.
+ */
+#ifndef SORLAYOUT_H
+#define SORLAYOUT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SL_OK = 0,
+  SL_EINVAL = -1,    /* malformed graph or option                               */
+  SL_ENOMEM = -2,    /* device or host allocation failed                       */
+  SL_EDEVICE = -3,   /* a HIP call failed                                      */
+  SL_ERANGE = -4,    /* a finite graph distance exceeds 255 hops               */
+  SL_ENUMERIC = -5,  /* a non-finite coordinate appeared during the iteration  */
+  SL_ENOTSUP = -6    /* valid input this build does not handle                 */
+} sl_status;
+
+/* Columns of one trace row (one row per iteration, doubles). */
+#define SL_TRACE_COLS 5
+/*   [0] res_k                      relative step ||X^H - X^k|| / ||X^H - mean||
+ *   [1] accepted                   1 / 0 for the safeguard decision, -1 when no
+ *                                  extrapolation is formed (omega == 1)
+ *   [2] f(X~) - f(X^H)             summed pair by pair (0 when not evaluated)
+ *   [3] reserved                   0
+ *   [4] f(X^k)                     stress at the iterate the step starts from
+ *                                  (NaN unless SL_FLAG_TRACE_STRESS)                */
+
+#define SL_FLAG_TRACE_STRESS 1u  /* evaluate f(X^k) every iteration into trace[4]  */
+#define SL_FLAG_NO_GRAPH 2u      /* launch kernels one by one instead of replaying a
+                                    captured HIP graph of `check_every` iterations */
+
+/* The graph G = (V, E) of the problem statement (Sec. 1), host memory, CSR.
+ * Symmetric: (u, v) present iff (v, u) present.  Vertex ids 0 .. n-1.  No self
+ * loops, no duplicate entries; neighbours of each row in any order. */
+typedef struct {
+  int32_t n;                /* |V| >= 0                                            */
+  int64_t nnz;              /* 2|E| = row_ptr[n]                                   */
+  const int64_t* row_ptr;   /* n + 1 offsets, row_ptr[0] = 0, non-decreasing        */
+  const int32_t* col_idx;   /* nnz neighbour ids in [0, n)                         */
+  const float* edge_len;    /* NULL: unit edges (hop distances).  Edge lengths are
+                               not handled by this build: non-NULL -> SL_ENOTSUP  */
+} sl_graph;
+
+typedef struct {
+  int32_t dim;              /* 2 or 3                                              */
+  int32_t max_iter;         /* >= 0; 0 returns X unchanged                         */
+  double omega;             /* relaxation factor, finite, in (0, 16]                */
+  double tol;               /* >= 0, on res_k                                     */
+  int32_t safeguard;        /* 1: Alg. 2 lines 6-8; 0: always keep X~             */
+  int32_t check_every;      /* iterations between host polls of the stop flag;
+                               <= 0 selects a default from the graph size          */
+  uint32_t flags;           /* SL_FLAG_*                                           */
+  int32_t reserved;
+  double* trace;            /* NULL or device buffer of max_iter * SL_TRACE_COLS
+                               doubles, row k written by iteration k               */
+  float* xtrace;            /* NULL or device buffer of max_iter * n * dim floats:
+                               the placement after every iteration                  */
+} sl_options;
+
+typedef struct {
+  int32_t iterations;       /* steps taken                                         */
+  int32_t converged;        /* 1 if res <= tol was reached (or n <= 1)             */
+  int32_t rejected;         /* extrapolations refused by the safeguard            */
+  int32_t reserved;
+  double residual;          /* res of the last step                               */
+  double stress;            /* f of the returned placement                        */
+  double plan_ms;           /* time of sl_plan_create (sl_layout: distances+weights) */
+  double run_ms;            /* device time of the iteration loop                  */
+} sl_result;
+
+typedef struct sl_plan sl_plan;
+
+/* Fill `opt` with defaults: dim 2, omega 1, tol 1e-3, max_iter 1000, safeguard 1. */
+void sl_default_options(sl_options* opt);
+
+/* Check a graph and options on the host, with no HIP call.  `opt` may be NULL
+ * (graph only).  Returns SL_OK, SL_EINVAL or SL_ENOTSUP. */
+sl_status sl_validate(const sl_graph* g, const sl_options* opt);
+
+/* Build the per-graph state the iteration reads (Sec. 2): ideal distances d_ij
+ * as hop counts by a multi-source breadth-first search on the device, stored
+ * as bytes (0 = same vertex or no path), and the weight sums W_i = sum_j d_ij^-2
+ * (the diagonal of L^W, Prop. 2.1).  `dim` (2 or 3) sizes the iterate buffers.
+ * Errors: SL_EINVAL, SL_ENOTSUP, SL_ERANGE (a distance above 255), SL_ENOMEM,
+ * SL_EDEVICE.  On success *out owns about n_pad^2 bytes + O(n) device memory,
+ * n_pad = n rounded up to 64. */
+sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan** out);
+
+/* Run Algorithm 2 from the placement in X (device, n * dim floats, row-major)
+ * and write the final placement back to X.  Each iteration:
+ *   1. F_i = sum_j w_ij (d_ij - r_ij) u_ij at X^k (eq. 5 residual, all pairs)
+ *   2. X^H = X^k + F / W (W_i = 0: the vertex keeps its place), res_k
+ *   3. X~ = X^H + (omega - 1)(X^H - X^k)          (eq. 11)
+ *   4. keep X~ iff f(X~) - f(X^H) <= 0              (Alg. 2, lines 6-8)
+ *   5. stop when res_k <= tol or after max_iter steps
+ * `out` may be NULL.  Not converging within max_iter is not an error.
+ * Errors: SL_EINVAL (opt, or opt->dim differs from the plan's), SL_ENUMERIC
+ * (X is then the last finite iterate), SL_EDEVICE. */
+sl_status sl_plan_run(sl_plan* plan, float* X, const sl_options* opt, void* stream, sl_result* out);
+
+/* f(X) of eq. 1 for a device placement X (n * dim floats), into *f (host). */
+sl_status sl_plan_stress(sl_plan* plan, const float* X, int32_t dim, void* stream, double* f);
+
+/* Copy distance rows out of a plan: out[k * n + j] = d(rows[k], j) as stored
+ * (0 for j = rows[k] or no path).  `rows` and `out` are host memory. */
+sl_status sl_plan_distance_rows(sl_plan* plan, const int32_t* rows, int32_t nrows, void* stream,
+                                uint8_t* out);
+
+/* Copy the weight sums W_i (n doubles) to host memory. */
+sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
+
+/* Measurement: device time of each kernel of one iteration, in ms, averaged
+ * over `reps` back-to-back launches and timed with HIP events on the stream
+ * the kernels run on (the plan's own stream, ordered after `stream`).  The
+ * iteration starts from the device placement X (n * dim floats, not
+ * modified) with relaxation factor `omega`:
+ *   ms[0] all-pairs force pass   ms[1] Jacobi update + extrapolation
+ *   ms[2] safeguard pass         ms[3] select + termination test
+ * For profilers and benchmarks; the iterate buffers of the plan are left in an
+ * unspecified state (a later sl_plan_run starts from its own X). */
+sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,
+                          double* ms);
+
+/* Release a plan and all its device memory.  NULL is accepted. */
+sl_status sl_plan_destroy(sl_plan* plan);
+
+/* layout(G, X0, omega, tol, max_iter) -> X: sl_plan_create + sl_plan_run +
+ * sl_plan_destroy. */
+sl_status sl_layout(const sl_graph* g, float* X, const sl_options* opt, void* stream, sl_result* out);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* sl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SORLAYOUT_H */

@@ -1,0 +1,273 @@
+"""ctypes binding of libsorlayout (include/sorlayout.h).
+
+Argument marshalling only: every step of the layout runs in the HIP library.
+Device buffers and streams come from PyTorch (``tensor.data_ptr()``,
+``torch.cuda.current_stream().cuda_stream``); torch does no arithmetic here.
+Importing this module fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsorlayout.so")
+
+SL_OK, SL_EINVAL, SL_ENOMEM, SL_EDEVICE, SL_ERANGE, SL_ENUMERIC, SL_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "SL_OK", -1: "SL_EINVAL", -2: "SL_ENOMEM", -3: "SL_EDEVICE", -4: "SL_ERANGE",
+                -5: "SL_ENUMERIC", -6: "SL_ENOTSUP"}
+SL_TRACE_COLS = 5
+SL_FLAG_TRACE_STRESS = 1
+SL_FLAG_NO_GRAPH = 2
+
+EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run", "sl_plan_stress",
+            "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
+            "sl_last_error")
+
+
+class SlError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class sl_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("edge_len", ctypes.c_void_p)]
+
+
+class sl_options(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("tol", ctypes.c_double), ("safeguard", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("xtrace", ctypes.c_void_p)]
+
+
+class sl_result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("rejected", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("residual", ctypes.c_double), ("stress", ctypes.c_double),
+                ("plan_ms", ctypes.c_double), ("run_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsorlayout.so is not built (%s); run __graft_entry__.build() or "
+                          "python -m paper_1711_01228_amd.build_lib" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+    sigs = {
+        "sl_default_options": (None, [ctypes.POINTER(sl_options)]),
+        "sl_validate": (st, [ctypes.POINTER(sl_graph), ctypes.POINTER(sl_options)]),
+        "sl_plan_create": (st, [ctypes.POINTER(sl_graph), i32, P, ctypes.POINTER(P)]),
+        "sl_plan_run": (st, [P, P, ctypes.POINTER(sl_options), P, ctypes.POINTER(sl_result)]),
+        "sl_plan_stress": (st, [P, P, i32, P, ctypes.POINTER(ctypes.c_double)]),
+        "sl_plan_distance_rows": (st, [P, P, i32, P, P]),
+        "sl_plan_weights": (st, [P, P, P]),
+        "sl_plan_profile": (st, [P, P, i32, ctypes.c_double, i32, P, P]),
+        "sl_plan_destroy": (st, [P]),
+        "sl_layout": (st, [ctypes.POINTER(sl_graph), P, ctypes.POINTER(sl_options), P, ctypes.POINTER(sl_result)]),
+        "sl_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def last_error() -> str:
+    return LIB.sl_last_error().decode()
+
+
+def _check(status):
+    if status != SL_OK:
+        raise SlError(status, last_error())
+
+
+class _GraphArgs:
+    """Keeps the CSR arrays alive for the duration of a call."""
+
+    def __init__(self, n, row_ptr, col_idx, edge_len=None):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        self.edge_len = None if edge_len is None else np.ascontiguousarray(edge_len, dtype=np.float32)
+        self.s = sl_graph(int(n), int(self.row_ptr[-1]) if len(self.row_ptr) else 0,
+                          self.row_ptr.ctypes.data if len(self.row_ptr) else None,
+                          self.col_idx.ctypes.data if len(self.col_idx) else None,
+                          None if self.edge_len is None else self.edge_len.ctypes.data)
+
+
+def graph_args(g) -> _GraphArgs:
+    """From an object with n, row_ptr, col_idx (and optional edge_len)."""
+    return _GraphArgs(g.n, g.row_ptr, g.col_idx, getattr(g, "edge_len", None))
+
+
+def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0,
+                 trace_stress=False, use_graph=True, trace=None, xtrace=None) -> sl_options:
+    o = sl_options()
+    LIB.sl_default_options(ctypes.byref(o))
+    o.dim, o.omega, o.tol, o.max_iter = int(dim), float(omega), float(tol), int(max_iter)
+    o.safeguard, o.check_every = int(bool(safeguard)), int(check_every)
+    o.flags = (SL_FLAG_TRACE_STRESS if trace_stress else 0) | (0 if use_graph else SL_FLAG_NO_GRAPH)
+    o.trace = None if trace is None else int(trace)
+    o.xtrace = None if xtrace is None else int(xtrace)
+    return o
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+# --------------------------------------------------------------------------
+# C-ABI entry points, same names
+# --------------------------------------------------------------------------
+def sl_validate(g, opt: sl_options | None = None) -> None:
+    ga = graph_args(g)
+    _check(LIB.sl_validate(ctypes.byref(ga.s), None if opt is None else ctypes.byref(opt)))
+
+
+def sl_validate_status(g, opt: sl_options | None = None) -> int:
+    ga = graph_args(g)
+    return LIB.sl_validate(ctypes.byref(ga.s), None if opt is None else ctypes.byref(opt))
+
+
+def sl_plan_create(g, dim: int, stream=None) -> int:
+    ga = graph_args(g)
+    h = ctypes.c_void_p()
+    _check(LIB.sl_plan_create(ctypes.byref(ga.s), int(dim), _stream_handle(stream), ctypes.byref(h)))
+    return h.value
+
+
+def sl_plan_run(plan: int, X_ptr: int, opt: sl_options, stream=None) -> dict:
+    res = sl_result()
+    _check(LIB.sl_plan_run(plan, X_ptr, ctypes.byref(opt), _stream_handle(stream), ctypes.byref(res)))
+    return res.as_dict()
+
+
+def sl_plan_stress(plan: int, X_ptr: int, dim: int, stream=None) -> float:
+    f = ctypes.c_double()
+    _check(LIB.sl_plan_stress(plan, X_ptr, int(dim), _stream_handle(stream), ctypes.byref(f)))
+    return f.value
+
+
+def sl_plan_distance_rows(plan: int, rows, n: int, stream=None) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((len(rows), n), dtype=np.uint8)
+    _check(LIB.sl_plan_distance_rows(plan, rows.ctypes.data, len(rows), _stream_handle(stream), out.ctypes.data))
+    return out
+
+
+def sl_plan_weights(plan: int, n: int, stream=None) -> np.ndarray:
+    W = np.zeros(n, dtype=np.float64)
+    _check(LIB.sl_plan_weights(plan, _stream_handle(stream), W.ctypes.data))
+    return W
+
+
+def sl_plan_profile(plan: int, X_ptr: int, dim: int, omega: float, reps: int, stream=None) -> np.ndarray:
+    ms = np.zeros(4, dtype=np.float64)
+    _check(LIB.sl_plan_profile(plan, X_ptr, int(dim), float(omega), int(reps), _stream_handle(stream),
+                               ms.ctypes.data))
+    return ms
+
+
+def sl_plan_destroy(plan: int) -> None:
+    _check(LIB.sl_plan_destroy(plan))
+
+
+def sl_layout(g, X_ptr: int, opt: sl_options, stream=None) -> dict:
+    ga = graph_args(g)
+    res = sl_result()
+    _check(LIB.sl_layout(ctypes.byref(ga.s), X_ptr, ctypes.byref(opt), _stream_handle(stream), ctypes.byref(res)))
+    return res.as_dict()
+
+
+# --------------------------------------------------------------------------
+# Convenience wrapper over torch tensors
+# --------------------------------------------------------------------------
+class Plan:
+    """A plan on the current device: distances and weights of one graph."""
+
+    def __init__(self, g, dim=2, stream=None):
+        self.n, self.dim = int(g.n), int(dim)
+        self.handle = sl_plan_create(g, dim, stream)
+
+    def run(self, X, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0, trace=False,
+            trace_stress=False, trace_positions=False, use_graph=True, stream=None):
+        """Run Algorithm 2 in place on the device tensor X (n x dim, float32).
+
+        Returns the sl_result fields; with ``trace`` also a ``trace`` array
+        (iterations x 5) and with ``trace_positions`` the ``positions``
+        (iterations x n x dim) on the host."""
+        import torch
+
+        if X.dtype != torch.float32 or not X.is_cuda or not X.is_contiguous() or tuple(X.shape) != (self.n, self.dim):
+            raise ValueError("X must be a contiguous cuda float32 tensor of shape (%d, %d)" % (self.n, self.dim))
+        tr = xt = None
+        if trace or trace_stress:
+            tr = torch.full((max(max_iter, 1), SL_TRACE_COLS), float("nan"), dtype=torch.float64, device=X.device)
+        if trace_positions:
+            xt = torch.zeros((max(max_iter, 1), self.n, self.dim), dtype=torch.float32, device=X.device)
+        opt = make_options(self.dim, omega, tol, max_iter, safeguard, check_every, trace_stress, use_graph,
+                           None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr())
+        info = sl_plan_run(self.handle, X.data_ptr(), opt, stream)
+        k = info["iterations"]
+        if tr is not None:
+            info["trace"] = tr[:k].cpu().numpy()
+        if xt is not None:
+            info["positions"] = xt[:k].cpu().numpy()
+        return info
+
+    def stress(self, X, stream=None) -> float:
+        return sl_plan_stress(self.handle, X.data_ptr(), self.dim, stream)
+
+    def distance_rows(self, rows, stream=None) -> np.ndarray:
+        return sl_plan_distance_rows(self.handle, rows, self.n, stream)
+
+    def weights(self, stream=None) -> np.ndarray:
+        return sl_plan_weights(self.handle, self.n, stream)
+
+    def profile(self, X, omega=1.5, reps=5, stream=None) -> dict:
+        """Average device ms of each kernel of one iteration (HIP events)."""
+        ms = sl_plan_profile(self.handle, X.data_ptr(), self.dim, omega, reps, stream)
+        return dict(zip(("force", "update", "safeguard", "select"), ms.tolist()))
+
+    def close(self):
+        if self.handle:
+            sl_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def layout(g, X0, omega=1.0, tol=1e-3, max_iter=1000, **kw):
+    """layout(G, X0, omega, tol, max_iter) -> (X, info) on the GPU.  X0 is a
+    host array or a device tensor (n x dim); X is a new cuda float32 tensor."""
+    import torch
+
+    X = torch.as_tensor(np.asarray(X0, dtype=np.float32) if not torch.is_tensor(X0) else X0)
+    X = X.to(device="cuda", dtype=torch.float32).contiguous().clone()
+    with Plan(g, X.shape[1]) as plan:
+        info = plan.run(X, omega=omega, tol=tol, max_iter=max_iter, **kw)
+    return X, info

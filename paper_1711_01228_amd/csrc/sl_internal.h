@@ -1,0 +1,95 @@
+// Internal declarations shared by the kernels (sl_kernels.hip) and the host
+// runtime (sl_api.hip) of libsorlayout.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace sl {
+
+// ---------------------------------------------------------------------------
+// Device data layout
+//
+//   n_pad  = n rounded up to 64; rows and columns past n are padding.
+//   d      one byte per ordered pair (i, j): the hop distance d_ij, 0 for i = j
+//          or no path.  Tile-major: a tile is 64 rows x 16 columns stored as
+//          64 lane-chunks of 16 bytes, so a wave whose lane l owns row
+//          64*rb + l reads one tile as one contiguous 1 KiB load:
+//            offset(i, j) = ((i/64) * NG + j/16) * 1024 + (i%64) * 16 + j%16,
+//          NG = n_pad / 16 column groups per row block.
+//   X      iterates as float2 (dim 2) or float4 with w = 0 (dim 3), n_pad
+//          entries each, padding at the origin.  Three buffers rotate: the
+//          current iterate, X^H and X~; DevState::cur names the current one.
+// ---------------------------------------------------------------------------
+constexpr int kRowBlock = 64;   // rows per wave (one per lane)
+constexpr int kColGroup = 16;   // columns per 16-byte lane chunk
+constexpr int kTileBytes = kRowBlock * kColGroup;
+
+__host__ __device__ inline size_t tile_offset(int64_t i, int64_t j, int64_t ng) {
+  return (size_t)(((i / kRowBlock) * ng + j / kColGroup) * kTileBytes + (i % kRowBlock) * kColGroup + j % kColGroup);
+}
+
+// Iteration state kept in device memory so that a captured graph of several
+// iterations can be replayed: every kernel reads `done` and returns at once
+// when it is set, and reads `cur` to find the current iterate.
+struct DevState {
+  int32_t cur;        // buffer index of X^k (0..2)
+  int32_t iter;       // iterations completed
+  int32_t done;       // 1: converged, max_iter reached or numeric failure
+  int32_t converged;
+  int32_t rejected;
+  int32_t status;     // 0 or SL_ENUMERIC
+  int32_t max_iter;
+  int32_t pad;
+  double residual;
+  double last_df;
+  double stress;      // f of the last evaluated placement (stress passes)
+};
+
+// Scalars every kernel of the loop needs, passed by value.
+struct LoopParams {
+  int32_t n, n_pad, ng, nrb, slices, groups_per_slice;
+  double omega_p;     // paper's relaxation factor = omega - 1
+  double tol;
+  int32_t safeguard;  // evaluate f(X~) - f(X^H) and select
+  int32_t stress;     // accumulate f(X^k) in the force pass
+};
+
+// Work split of the all-pairs passes for a graph of n_pad vertices.
+struct Split {
+  int nrb;              // row blocks (waves per column slice)
+  int ng;               // column groups
+  int slices;           // column slices S
+  int groups_per_slice; // column groups per slice
+  int blocks_x;         // workgroups along rows (4 waves each)
+};
+Split make_split(int n_pad);
+
+// ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
+hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);
+hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, int n, int base, hipStream_t s);
+hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col_idx, const uint64_t* frontier,
+                            uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base, int level,
+                            int write, int32_t* flag, hipStream_t s);
+hipError_t launch_weights(const uint8_t* d, double* W, const Split& sp, int n, hipStream_t s);
+hipError_t launch_pack_in(const float* X, float* Xb, int n, int n_pad, int dim, hipStream_t s);
+hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, float* X, int n, int dim,
+                           hipStream_t s);
+hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* Xb, size_t stride,
+                        const DevState* st, double* fpart, double* spart, const Split& sp, int n_pad,
+                        hipStream_t s);
+hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, const double* spart,
+                         const double* W, float* Xb, size_t stride, const DevState* st, double* red,
+                         hipStream_t s);
+hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const DevState* st,
+                          double* sgpart, const Split& sp, int n_pad, hipStream_t s);
+hipError_t launch_select(int dim, const LoopParams& p, const double* red, int nred, const double* sgpart,
+                         int nsg, DevState* st, double* trace, hipStream_t s);
+hipError_t launch_record(const float* Xb, size_t stride, const DevState* st, float* xtrace, int n, int dim,
+                         hipStream_t s);
+hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevState* st, hipStream_t s);
+hipError_t launch_gather_rows(const uint8_t* d, const int32_t* rows, int nrows, int n, int ng, uint8_t* out,
+                              hipStream_t s);
+
+}  // namespace sl

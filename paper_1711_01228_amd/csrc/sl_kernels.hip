@@ -1,0 +1,599 @@
+// HIP kernels of libsorlayout for gfx950 (CDNA4, wave64).
+//
+// Per iteration of Algorithm 2 (Wang & Wang 2012) the loop runs
+//   k_force    all-pairs pass at X^k: F_i = sum_j w_ij (d_ij - r_ij) u_ij, the
+//              residual of eq. 5 (Prop. 2.1: L^X X - L^W X), optionally with the
+//              stress terms of eq. 1
+//   k_update   Jacobi sweep of eq. 5, X^H = X^k + F / W, and the extrapolation
+//              X~ = X^H + (omega - 1)(X^H - X^k) of eq. 11, plus block sums for
+//              the termination test
+//   k_sgdelta  f(X~) - f(X^H) over unordered pairs (Alg. 2, line 6)
+//   k_select   the decision of Alg. 2 lines 6-8, the termination test and the
+//              iteration counter, in one workgroup
+// and once per graph
+//   k_bfs_*    breadth-first search from 256 sources at a time (bit-parallel
+//              frontiers) writing hop distances d_ij as bytes
+//   k_weights  W_i = sum_j d_ij^-2, the diagonal of L^W
+//
+// Every cross-thread sum is taken in a fixed order (per-lane sequences, fixed
+// trees, fixed slice order), so results are bitwise repeatable run to run.
+#include "sl_internal.h"
+
+#include <cmath>
+
+namespace sl {
+
+namespace {
+
+template <int DIM> struct VecT;
+template <> struct VecT<2> { using T = float2; };
+template <> struct VecT<3> { using T = float4; };
+
+// Added to r^2 so that rsq never sees 0: for coincident vertices (or i = j)
+// the pair term is c * (x_i - x_j) = c * 0 = 0 with c finite.
+constexpr float kTiny = 1e-30f;
+
+__device__ __forceinline__ float byte_as_float(uint32_t word, int b) {
+  return (float)((word >> (8 * b)) & 0xffu);
+}
+
+__device__ __forceinline__ uint32_t chunk_word(const uint4& q, int k) {
+  return (k < 4) ? q.x : (k < 8) ? q.y : (k < 12) ? q.z : q.w;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic tree sum of K doubles over a 256-thread block.  Thread 0 gets
+// the totals in v.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double (*sh)[256]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) sh[k][t] = v[k];
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) sh[k][t] += sh[k][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = sh[k][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// All-pairs force pass.  One wave per (row block, column slice): lane l owns
+// row i = 64 rb + l, streams its 16-byte distance chunks tile by tile, and
+// reads the positions x_j of the slice through the scalar cache (j is uniform
+// across the wave).  Per pair (w = d^-2, c = w d / r - w):
+//   F_i += c (x_i - x_j)          [= w (d - r) u_ij]
+//   s_i += (r / d - 1)^2          [= w (r - d)^2]            (STRESS only)
+// Sixteen pairs are summed in float, then folded into double accumulators.
+// Pairs with d = 0 (i = j, no path, padding) give c = 0.
+// ---------------------------------------------------------------------------
+template <int DIM, bool STRESS>
+__global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
+                                               size_t stride, const DevState* __restrict__ st,
+                                               double* __restrict__ fpart, double* __restrict__ spart, int nrb,
+                                               int ng, int gps, int n_pad) {
+  using V = typename VecT<DIM>::T;
+  if (st->done) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb = blockIdx.x * 4 + wave;
+  if (rb >= nrb) return;
+  const int slice = blockIdx.y;
+  const int g0 = slice * gps;
+  const int g1 = min(g0 + gps, ng);
+  const V* __restrict__ X = reinterpret_cast<const V*>(Xb + (size_t)st->cur * stride);
+  const int i = rb * kRowBlock + lane;
+  const V xi = X[i];
+  const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
+  double F0 = 0.0, F1 = 0.0, F2 = 0.0, Sd = 0.0;
+  if (g0 < g1) {
+    uint4 q = tile[(size_t)g0 * 64];
+    for (int g = g0; g < g1; ++g) {
+      uint4 qn = make_uint4(0u, 0u, 0u, 0u);
+      if (g + 1 < g1) qn = tile[(size_t)(g + 1) * 64];
+      const V* __restrict__ xj = X + (size_t)g * kColGroup;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
+#pragma unroll
+      for (int k = 0; k < kColGroup; ++k) {
+        const float dd = byte_as_float(chunk_word(q, k), k & 3);
+        const V p = xj[k];
+        const float dx = xi.x - p.x, dy = xi.y - p.y;
+        float r2 = fmaf(dx, dx, kTiny);
+        r2 = fmaf(dy, dy, r2);
+        float dz = 0.f;
+        if constexpr (DIM == 3) {
+          dz = xi.z - p.z;
+          r2 = fmaf(dz, dz, r2);
+        }
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const bool nz = dd > 0.f;
+        const float inv = nz ? __builtin_amdgcn_rcpf(dd) : 0.f;
+        const float c = fmaf(inv, rinv, -(inv * inv));
+        a0 = fmaf(c, dx, a0);
+        a1 = fmaf(c, dy, a1);
+        if constexpr (DIM == 3) a2 = fmaf(c, dz, a2);
+        if constexpr (STRESS) {
+          const float r = r2 * rinv;
+          const float t = fmaf(r, inv, nz ? -1.f : 0.f);
+          as = fmaf(t, t, as);
+        }
+      }
+      F0 += (double)a0;
+      F1 += (double)a1;
+      if constexpr (DIM == 3) F2 += (double)a2;
+      if constexpr (STRESS) Sd += (double)as;
+      q = qn;
+    }
+  }
+  double* fp = fpart + (size_t)slice * DIM * n_pad + i;
+  fp[0] = F0;
+  fp[n_pad] = F1;
+  if constexpr (DIM == 3) fp[2 * (size_t)n_pad] = F2;
+  if constexpr (STRESS) spart[(size_t)slice * n_pad + i] = Sd;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi update and extrapolation, one thread per vertex.
+//   x^H = x + F / W   (W = 0: the vertex has no partner and stays)
+//   x~  = x^H + omega_p (x^H - x)                                  (eq. 11)
+// Block sums (double): ||x^H - x||^2, ||x^H||^2, sum x^H per axis, stress
+// terms, count of non-finite values.
+// ---------------------------------------------------------------------------
+template <int DIM, bool STRESS>
+__global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __restrict__ fpart,
+                                                const double* __restrict__ spart, const double* __restrict__ W,
+                                                float* __restrict__ Xb, size_t stride,
+                                                const DevState* __restrict__ st, double* __restrict__ red) {
+  using V = typename VecT<DIM>::T;
+  __shared__ double sh[7][256];
+  if (st->done) return;
+  const int cur = st->cur, h = (cur + 1) % 3, t = (cur + 2) % 3;
+  const V* __restrict__ X = reinterpret_cast<const V*>(Xb + (size_t)cur * stride);
+  V* __restrict__ XH = reinterpret_cast<V*>(Xb + (size_t)h * stride);
+  V* __restrict__ XT = reinterpret_cast<V*>(Xb + (size_t)t * stride);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (i < p.n) {
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < p.slices; ++s) {
+      const double* fp = fpart + (size_t)s * DIM * p.n_pad + i;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) F[c] += fp[(size_t)c * p.n_pad];
+    }
+    const V x = X[i];
+    const double Wi = W[i];
+    float xv[3] = {x.x, x.y, 0.f};
+    if constexpr (DIM == 3) xv[2] = x.z;
+    float xh[3] = {0.f, 0.f, 0.f}, xt[3] = {0.f, 0.f, 0.f};
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      xh[c] = (Wi > 0.0) ? (float)((double)xv[c] + F[c] / Wi) : xv[c];
+      const double dl = (double)xh[c] - (double)xv[c];
+      xt[c] = (float)((double)xh[c] + p.omega_p * dl);
+      v[0] += dl * dl;
+      v[1] += (double)xh[c] * (double)xh[c];
+      v[2 + c] = (double)xh[c];
+      bad = bad || !isfinite(xh[c]) || !isfinite(xt[c]);
+    }
+    if constexpr (DIM == 2) {
+      XH[i] = make_float2(xh[0], xh[1]);
+      if (p.omega_p != 0.0) XT[i] = make_float2(xt[0], xt[1]);
+    } else {
+      XH[i] = make_float4(xh[0], xh[1], xh[2], 0.f);
+      if (p.omega_p != 0.0) XT[i] = make_float4(xt[0], xt[1], xt[2], 0.f);
+    }
+    if constexpr (STRESS) {
+      for (int s = 0; s < p.slices; ++s) v[5] += spart[(size_t)s * p.n_pad + i];
+    }
+    v[6] = bad ? 1.0 : 0.0;
+  }
+  block_sum<7>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) red[(size_t)blockIdx.x * 8 + k] = v[k];
+    red[(size_t)blockIdx.x * 8 + 7] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Safeguard: f(X~) - f(X^H) = sum_{i<j} w (r~ - r^H)(r~ + r^H - 2 d), taken
+// over the upper triangle only (column groups left of the diagonal block are
+// skipped; inside it pairs with j <= i are masked).  One double per wave.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
+                                                 size_t stride, const DevState* __restrict__ st,
+                                                 double* __restrict__ sgpart, int nrb, int ng, int gps) {
+  using V = typename VecT<DIM>::T;
+  if (st->done) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb = blockIdx.x * 4 + wave;
+  const size_t slot = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wave;
+  double acc = 0.0;
+  if (rb < nrb) {
+    const int cur = st->cur, h = (cur + 1) % 3, t = (cur + 2) % 3;
+    const V* __restrict__ XH = reinterpret_cast<const V*>(Xb + (size_t)h * stride);
+    const V* __restrict__ XT = reinterpret_cast<const V*>(Xb + (size_t)t * stride);
+    const int slice = blockIdx.y;
+    const int gdiag = rb * (kRowBlock / kColGroup);
+    const int g0 = max(slice * gps, gdiag);
+    const int g1 = min(slice * gps + gps, ng);
+    const int i = rb * kRowBlock + lane;
+    const V hi = XH[i], ti = XT[i];
+    const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
+    for (int g = g0; g < g1; ++g) {
+      const uint4 q = tile[(size_t)g * 64];
+      const bool diag = g < gdiag + kRowBlock / kColGroup;
+      const V* __restrict__ hj = XH + (size_t)g * kColGroup;
+      const V* __restrict__ tj = XT + (size_t)g * kColGroup;
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < kColGroup; ++k) {
+        const float dd = byte_as_float(chunk_word(q, k), k & 3);
+        const V ph = hj[k], pt = tj[k];
+        float hx = hi.x - ph.x, hy = hi.y - ph.y;
+        float tx = ti.x - pt.x, ty = ti.y - pt.y;
+        float rh2 = fmaf(hx, hx, kTiny), rt2 = fmaf(tx, tx, kTiny);
+        rh2 = fmaf(hy, hy, rh2);
+        rt2 = fmaf(ty, ty, rt2);
+        if constexpr (DIM == 3) {
+          const float hz = hi.z - ph.z, tz = ti.z - pt.z;
+          rh2 = fmaf(hz, hz, rh2);
+          rt2 = fmaf(tz, tz, rt2);
+        }
+        const float rh = rh2 * __builtin_amdgcn_rsqf(rh2);
+        const float rt = rt2 * __builtin_amdgcn_rsqf(rt2);
+        const float inv = dd > 0.f ? __builtin_amdgcn_rcpf(dd) : 0.f;
+        float term = (inv * inv) * (rt - rh) * fmaf(-2.f, dd, rt + rh);
+        if (diag && g * kColGroup + k <= i) term = 0.f;
+        a += term;
+      }
+      acc += (double)a;
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) sgpart[slot] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 2 lines 6-9 and the termination test, one workgroup.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __restrict__ red, int nred,
+                                                const double* __restrict__ sgpart, int nsg,
+                                                DevState* __restrict__ st, double* __restrict__ trace, int dim) {
+  __shared__ double sh[8][256];
+  if (st->done) return;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nred; b += 256) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] += red[(size_t)b * 8 + k];
+  }
+  const bool sg = p.safeguard && p.omega_p != 0.0;
+  if (sg)
+    for (int b = threadIdx.x; b < nsg; b += 256) v[7] += sgpart[b];
+  block_sum<8>(v, sh);
+  if (threadIdx.x != 0) return;
+  const int k = st->iter;
+  if (v[6] > 0.0) {  // a non-finite coordinate: keep the last finite iterate
+    st->status = -5;
+    st->done = 1;
+    return;
+  }
+  const double dsq = v[0], hsq = v[1];
+  const double mean2 = (v[2] * v[2] + v[3] * v[3] + (dim == 3 ? v[4] * v[4] : 0.0)) / (double)p.n;
+  const double den2 = hsq - mean2;
+  const double res = dsq > 0.0 ? sqrt(dsq) / sqrt(den2 > 0.0 ? den2 : 0.0) : 0.0;
+  const int cur = st->cur, h = (cur + 1) % 3, t = (cur + 2) % 3;
+  double accepted;
+  const double df = sg ? v[7] : 0.0;
+  if (p.omega_p == 0.0) {
+    st->cur = h;
+    accepted = -1.0;
+  } else if (p.safeguard) {
+    const bool take = df <= 0.0;
+    st->cur = take ? t : h;
+    accepted = take ? 1.0 : 0.0;
+    if (!take) st->rejected += 1;
+  } else {
+    st->cur = t;
+    accepted = 1.0;
+  }
+  st->iter = k + 1;
+  st->residual = res;
+  st->last_df = df;
+  if (trace) {
+    double* row = trace + (size_t)k * 5;
+    row[0] = res;
+    row[1] = accepted;
+    row[2] = df;
+    row[3] = 0.0;
+    row[4] = p.stress ? 0.5 * v[5] : __builtin_nan("");
+  }
+  if (res <= p.tol) {
+    st->converged = 1;
+    st->done = 1;
+  }
+  if (k + 1 >= st->max_iter) st->done = 1;
+}
+
+// Copy the placement after the latest iteration into xtrace[iter - 1].
+__global__ __launch_bounds__(256) void k_record(const float* __restrict__ Xb, size_t stride,
+                                                const DevState* __restrict__ st, float* __restrict__ xtrace, int n,
+                                                int dim) {
+  const int it = st->iter;
+  if (it <= 0) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int vec = dim == 2 ? 2 : 4;
+  const float* src = Xb + (size_t)st->cur * stride + (size_t)i * vec;
+  float* dst = xtrace + ((size_t)(it - 1) * n + i) * dim;
+  for (int c = 0; c < dim; ++c) dst[c] = src[c];
+}
+
+// f = (1/2) sum_i s_i over the stress partials of one force pass.
+__global__ __launch_bounds__(256) void k_stress_sum(const double* __restrict__ spart, int slices, int n_pad,
+                                                    DevState* __restrict__ st) {
+  __shared__ double sh[1][256];
+  double v[1] = {0.0};
+  const size_t total = (size_t)slices * n_pad;
+  for (size_t q = threadIdx.x; q < total; q += 256) v[0] += spart[q];
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) st->stress = 0.5 * v[0];
+}
+
+// Caller placement (n x dim, row-major) -> iterate buffer (float2/float4, padded
+// with zeros up to n_pad).
+__global__ __launch_bounds__(256) void k_pack_in(const float* __restrict__ X, float* __restrict__ Xb, int n,
+                                                 int n_pad, int dim) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_pad) return;
+  const int vec = dim == 2 ? 2 : 4;
+  for (int c = 0; c < vec; ++c) Xb[(size_t)i * vec + c] = (i < n && c < dim) ? X[(size_t)i * dim + c] : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_pack_out(const float* __restrict__ Xb, const DevState* __restrict__ st,
+                                                  size_t stride, float* __restrict__ X, int n, int dim) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int vec = dim == 2 ? 2 : 4;
+  const float* src = Xb + (size_t)st->cur * stride + (size_t)i * vec;
+  for (int c = 0; c < dim; ++c) X[(size_t)i * dim + c] = src[c];
+}
+
+// ---------------------------------------------------------------------------
+// Breadth-first search from the 256 sources base .. base+255 at once.  Word k
+// of a vertex holds one bit per source base + 64k + b.  A level pulls the
+// frontier bits of all neighbours (a segmented OR over the CSR row), keeps
+// those not yet visited, and writes the level into d(v, s) for each new bit.
+// Distances are symmetric, so the row of v is written: its 16 sources per
+// chunk share one 16-byte lane chunk of the tile layout, read-modify-written by
+// the only thread that owns row v.
+// ---------------------------------------------------------------------------
+constexpr int kBfsWords = 4;
+
+__global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ frontier, uint64_t* __restrict__ visited,
+                                                  int n, int base) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+#pragma unroll
+  for (int k = 0; k < kBfsWords; ++k) {
+    const int s0 = base + 64 * k;
+    const uint64_t w = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
+    frontier[(size_t)v * kBfsWords + k] = w;
+    visited[(size_t)v * kBfsWords + k] = w;
+  }
+}
+
+__device__ __forceinline__ uint32_t byte_mask4(uint32_t nib) {
+  return ((nib & 1u) ? 0x000000ffu : 0u) | ((nib & 2u) ? 0x0000ff00u : 0u) | ((nib & 4u) ? 0x00ff0000u : 0u) |
+         ((nib & 8u) ? 0xff000000u : 0u);
+}
+
+__global__ __launch_bounds__(256) void k_bfs_level(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx,
+                                                   const uint64_t* __restrict__ frontier,
+                                                   uint64_t* __restrict__ visited, uint64_t* __restrict__ next,
+                                                   uint8_t* __restrict__ d, int n, int ng, int base, int level,
+                                                   int write, int32_t* __restrict__ flag) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  uint64_t acc[kBfsWords] = {0, 0, 0, 0};
+  const int64_t e1 = row_ptr[v + 1];
+  for (int64_t e = row_ptr[v]; e < e1; ++e) {
+    const ulonglong2* f = reinterpret_cast<const ulonglong2*>(frontier + (size_t)col_idx[e] * kBfsWords);
+    const ulonglong2 a = f[0], b = f[1];
+    acc[0] |= a.x;
+    acc[1] |= a.y;
+    acc[2] |= b.x;
+    acc[3] |= b.y;
+  }
+  bool any = false;
+  const uint32_t lv = (uint32_t)level * 0x01010101u;
+#pragma unroll
+  for (int k = 0; k < kBfsWords; ++k) {
+    const uint64_t vis = visited[(size_t)v * kBfsWords + k];
+    const uint64_t nw = acc[k] & ~vis;
+    next[(size_t)v * kBfsWords + k] = nw;
+    if (nw == 0) continue;
+    any = true;
+    if (!write) continue;
+    visited[(size_t)v * kBfsWords + k] = vis | nw;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t bits = (uint32_t)(nw >> (16 * q)) & 0xffffu;
+      if (bits == 0) continue;
+      const int s0 = base + 64 * k + 16 * q;
+      uint4* chunk = reinterpret_cast<uint4*>(d + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
+                                              (size_t)(v % kRowBlock) * kColGroup);
+      uint4 c = *chunk;
+      c.x |= lv & byte_mask4(bits & 0xfu);
+      c.y |= lv & byte_mask4((bits >> 4) & 0xfu);
+      c.z |= lv & byte_mask4((bits >> 8) & 0xfu);
+      c.w |= lv & byte_mask4((bits >> 12) & 0xfu);
+      *chunk = c;
+    }
+  }
+  if (any) *flag = 1;
+}
+
+// W_i = sum_j d_ij^-2 in double, columns in ascending order (one wave per row
+// block, lane = row, the same tile stream as the force pass).
+__global__ __launch_bounds__(256) void k_weights(const uint8_t* __restrict__ d, double* __restrict__ W, int nrb,
+                                                 int ng, int n) {
+  __shared__ double lut[256];
+  lut[threadIdx.x] = threadIdx.x ? 1.0 / ((double)threadIdx.x * (double)threadIdx.x) : 0.0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb = blockIdx.x * 4 + wave;
+  if (rb >= nrb) return;
+  const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
+  double s = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    const uint4 q = tile[(size_t)g * 64];
+#pragma unroll
+    for (int k = 0; k < kColGroup; ++k) s += lut[(chunk_word(q, k) >> (8 * (k & 3))) & 0xffu];
+  }
+  const int i = rb * kRowBlock + lane;
+  W[i] = (i < n) ? s : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(const uint8_t* __restrict__ d, const int32_t* __restrict__ rows,
+                                                     int nrows, int n, int ng, uint8_t* __restrict__ out) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)nrows * n) return;
+  const int k = (int)(q / n), j = (int)(q % n);
+  out[q] = d[tile_offset(rows[k], j, ng)];
+}
+
+inline unsigned blocks_for(size_t items) { return (unsigned)((items + 255) / 256); }
+
+}  // namespace
+
+Split make_split(int n_pad) {
+  Split sp;
+  sp.nrb = n_pad / kRowBlock;
+  sp.ng = n_pad / kColGroup;
+  // About 8 waves per SIMD over the chip (256 CUs x 4 SIMDs), with at least
+  // 8 column groups (128 columns) per wave.
+  const int max_slices = std::max(1, sp.ng / 8);
+  const int want = std::max(1, 8192 / std::max(1, sp.nrb));
+  int slices = std::min(max_slices, want);
+  sp.groups_per_slice = (sp.ng + slices - 1) / slices;
+  sp.slices = (sp.ng + sp.groups_per_slice - 1) / sp.groups_per_slice;
+  sp.blocks_x = (sp.nrb + 3) / 4;
+  return sp;
+}
+
+hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s) { return hipMemsetAsync(p, 0, bytes, s); }
+
+hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, int n, int base, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_bfs_init<<<blocks_for(n), 256, 0, s>>>(frontier, visited, n, base);
+  return hipGetLastError();
+}
+
+hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col_idx, const uint64_t* frontier,
+                            uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base, int level,
+                            int write, int32_t* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_bfs_level<<<blocks_for(n), 256, 0, s>>>(row_ptr, col_idx, frontier, visited, next, d, n, ng, base, level,
+                                            write, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const uint8_t* d, double* W, const Split& sp, int n, hipStream_t s) {
+  k_weights<<<sp.blocks_x, 256, 0, s>>>(d, W, sp.nrb, sp.ng, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_in(const float* X, float* Xb, int n, int n_pad, int dim, hipStream_t s) {
+  k_pack_in<<<blocks_for(n_pad), 256, 0, s>>>(X, Xb, n, n_pad, dim);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, float* X, int n, int dim,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_pack_out<<<blocks_for(n), 256, 0, s>>>(Xb, st, stride, X, n, dim);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* Xb, size_t stride,
+                        const DevState* st, double* fpart, double* spart, const Split& sp, int n_pad,
+                        hipStream_t s) {
+  const dim3 grid(sp.blocks_x, sp.slices);
+  if (dim == 2) {
+    if (stress)
+      k_force<2, true><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+    else
+      k_force<2, false><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+  } else {
+    if (stress)
+      k_force<3, true><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+    else
+      k_force<3, false><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, const double* spart,
+                         const double* W, float* Xb, size_t stride, const DevState* st, double* red,
+                         hipStream_t s) {
+  const unsigned nb = blocks_for(p.n_pad);
+  if (dim == 2) {
+    if (p.stress) k_update<2, true><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
+    else k_update<2, false><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
+  } else {
+    if (p.stress) k_update<3, true><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
+    else k_update<3, false><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const DevState* st,
+                          double* sgpart, const Split& sp, int n_pad, hipStream_t s) {
+  (void)n_pad;
+  const dim3 grid(sp.blocks_x, sp.slices);
+  if (dim == 2) k_sgdelta<2><<<grid, 256, 0, s>>>(d, Xb, stride, st, sgpart, sp.nrb, sp.ng, sp.groups_per_slice);
+  else k_sgdelta<3><<<grid, 256, 0, s>>>(d, Xb, stride, st, sgpart, sp.nrb, sp.ng, sp.groups_per_slice);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(int dim, const LoopParams& p, const double* red, int nred, const double* sgpart,
+                         int nsg, DevState* st, double* trace, hipStream_t s) {
+  k_select<<<1, 256, 0, s>>>(p, red, nred, sgpart, nsg, st, trace, dim);
+  return hipGetLastError();
+}
+
+hipError_t launch_record(const float* Xb, size_t stride, const DevState* st, float* xtrace, int n, int dim,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_record<<<blocks_for(n), 256, 0, s>>>(Xb, stride, st, xtrace, n, dim);
+  return hipGetLastError();
+}
+
+hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevState* st, hipStream_t s) {
+  k_stress_sum<<<1, 256, 0, s>>>(spart, slices, n_pad, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const uint8_t* d, const int32_t* rows, int nrows, int n, int ng, uint8_t* out,
+                              hipStream_t s) {
+  const size_t items = (size_t)nrows * n;
+  if (items == 0) return hipSuccess;
+  k_gather_rows<<<blocks_for(items), 256, 0, s>>>(d, rows, nrows, n, ng, out);
+  return hipGetLastError();
+}
+
+}  // namespace sl

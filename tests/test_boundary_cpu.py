@@ -1,0 +1,159 @@
+"""Host-side checks of the C-ABI library and the input generators (no GPU).
+
+The library loads without a GPU; validation runs before any HIP call, so
+every malformed-input path is exercised here.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1711_01228_amd import binding as b
+from paper_1711_01228_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sorlayout.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sl_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(b.LIB, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", b.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    exported = set(re.findall(r"\sT\s+(\S+)", out))
+    assert set(names) <= exported
+    assert set(b.EXPORTED) == set(names)
+
+
+def test_default_options():
+    o = b.sl_options()
+    b.LIB.sl_default_options(ctypes.byref(o))
+    assert (o.dim, o.max_iter, o.omega, o.tol, o.safeguard, o.flags) == (2, 1000, 1.0, 1e-3, 1, 0)
+    assert b.LIB.sl_validate(None, ctypes.byref(o)) == b.SL_EINVAL  # graph is required
+
+
+class G:
+    def __init__(self, n, row_ptr, col_idx, edge_len=None):
+        self.n, self.row_ptr, self.col_idx, self.edge_len = n, np.asarray(row_ptr), np.asarray(col_idx), edge_len
+
+
+def _tri():
+    g = inputs.grid_graph(2, 2)
+    return G(g.n, g.row_ptr.copy(), g.col_idx.copy())
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda g: setattr(g, "n", -1), "negative"),
+    (lambda g: g.row_ptr.__setitem__(0, 1), "row_ptr[0]"),
+    (lambda g: g.row_ptr.__setitem__(2, 1), "decreases"),
+    (lambda g: g.col_idx.__setitem__(0, 7), "outside"),
+    (lambda g: g.col_idx.__setitem__(0, 0), "self loop"),
+    (lambda g: g.col_idx.__setitem__(1, g.col_idx[0]), "duplicate"),
+])
+def test_validation_rejects_malformed_graphs(mutate, msg):
+    g = _tri()
+    mutate(g)
+    if g.n < 0:
+        ga = b._GraphArgs(0, g.row_ptr, g.col_idx)
+        ga.s.n = -1
+        st = b.LIB.sl_validate(ctypes.byref(ga.s), None)
+    else:
+        st = b.sl_validate_status(g)
+    assert st == b.SL_EINVAL
+    assert msg in b.last_error()
+
+
+def test_validation_rejects_asymmetric_and_nnz_mismatch():
+    # 0 -> 1 without 1 -> 0
+    g = G(2, [0, 1, 1], [1])
+    assert b.sl_validate_status(g) == b.SL_EINVAL and "symmetric" in b.last_error()
+    ga = b.graph_args(_tri())
+    ga.s.nnz = ga.s.nnz + 1
+    assert b.LIB.sl_validate(ctypes.byref(ga.s), None) == b.SL_EINVAL and "nnz" in b.last_error()
+
+
+def test_edge_lengths_are_refused_as_unsupported():
+    g = _tri()
+    g.edge_len = np.ones(len(g.col_idx), dtype=np.float32)
+    assert b.sl_validate_status(g) == b.SL_ENOTSUP
+    g.edge_len[2] = -1.0
+    assert b.sl_validate_status(g) == b.SL_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 1), ("dim", 4), ("omega", 0.0), ("omega", float("nan")), ("omega", float("inf")),
+    ("omega", 17.0), ("tol", -1e-3), ("tol", float("nan")), ("max_iter", -1), ("safeguard", 2), ("flags", 64),
+])
+def test_validation_rejects_bad_options(field, value):
+    o = b.make_options()
+    setattr(o, field, value)
+    assert b.sl_validate_status(_tri(), o) == b.SL_EINVAL
+    assert b.last_error()
+
+
+def test_valid_inputs_and_empty_graph():
+    b.sl_validate(_tri(), b.make_options(dim=3, omega=2.5, tol=0.0, max_iter=0, safeguard=False))
+    b.sl_validate(G(0, [0], []))
+    b.sl_validate(G(3, [0, 0, 0, 0], []))  # isolated vertices only
+
+
+def test_plan_create_rejects_before_device_work():
+    # validation fails before any HIP call, so this runs without a GPU
+    g = _tri()
+    g.col_idx[0] = 0
+    with pytest.raises(b.SlError) as e:
+        b.sl_plan_create(g, 2, stream=0)
+    assert e.value.status == b.SL_EINVAL
+    with pytest.raises(b.SlError) as e:
+        b.sl_plan_create(_tri(), 5, stream=0)
+    assert e.value.status == b.SL_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# input generators
+# ---------------------------------------------------------------------------
+def _is_connected(g):
+    seen = np.zeros(g.n, bool)
+    stack = [0]
+    seen[0] = True
+    while stack:
+        u = stack.pop()
+        for v in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+            if not seen[v]:
+                seen[v] = True
+                stack.append(v)
+    return seen.all()
+
+
+def test_generators_shapes_and_validity():
+    g = inputs.grid_graph(16, 16)
+    assert (g.n, g.num_edges) == (256, 480)
+    er = inputs.erdos_renyi(4096, 12288, seed=2000)
+    assert (er.n, er.num_edges) == (4096, 12288)
+    ba = inputs.barabasi_albert(2000, 3, seed=3000)
+    assert ba.num_edges == 6 + 3 * (2000 - 4) and _is_connected(ba)
+    t = inputs.random_tree(500, seed=1)
+    assert t.num_edges == 499 and _is_connected(t)
+    for gg in (g, er, ba, t):
+        b.sl_validate(gg)
+    # deterministic in the seed
+    np.testing.assert_array_equal(inputs.erdos_renyi(300, 500, 9).col_idx, inputs.erdos_renyi(300, 500, 9).col_idx)
+    X = inputs.uniform_positions(1000, 3, seed=4, lo=0.0, hi=64.0)
+    assert X.min() >= 0 and X.max() < 64
+    np.testing.assert_array_equal(X, X.astype(np.float32).astype(np.float64))
+
+
+def test_ba_degree_is_heavy_tailed():
+    ba = inputs.barabasi_albert(20000, 3, seed=5)
+    deg = np.diff(ba.row_ptr)
+    assert deg.min() >= 3 and deg.max() > 100
