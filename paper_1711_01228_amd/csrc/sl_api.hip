@@ -118,12 +118,14 @@ struct sl_plan {
   uint8_t* d = nullptr;         // n_pad^2 bytes, tile-major
   double* W = nullptr;          // n_pad
   float* Xb = nullptr;          // 3 iterate buffers
+  float* Eb = nullptr;          // x~ - x^H, same format as one iterate buffer
   size_t stride = 0;            // floats per iterate buffer
   double* fpart = nullptr;      // slices x 3 x n_pad
   double* spart = nullptr;      // slices x n_pad
   double* red = nullptr;        // nred x 8
   int nred = 0;
-  double* sgpart = nullptr;     // nsg
+  double* sgpart = nullptr;     // one double per safeguard work item
+  int4* items = nullptr;        // safeguard work items
   int nsg = 0;
   DevState* st = nullptr;       // loop state
   DevState* st_eval = nullptr;  // state for stand-alone stress passes
@@ -140,6 +142,8 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->d);
   (void)hipFree(p->W);
   (void)hipFree(p->Xb);
+  (void)hipFree(p->Eb);
+  (void)hipFree(p->items);
   (void)hipFree(p->fpart);
   (void)hipFree(p->spart);
   (void)hipFree(p->red);
@@ -234,10 +238,11 @@ sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* 
   HIP_TRY(launch_force(p->dim, lp.stress != 0, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                        p->ps),
           "force kernel");
-  HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->st, p->red, p->ps),
+  HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
           "update kernel");
   if (lp.safeguard && lp.omega_p != 0.0)
-    HIP_TRY(launch_sgdelta(p->dim, p->d, p->Xb, p->stride, p->st, p->sgpart, p->sp, p->n_pad, p->ps),
+    HIP_TRY(launch_sgdelta(p->dim, p->d, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart, p->sp,
+                           p->ps),
             "safeguard kernel");
   HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsg, p->st, o->trace, p->ps), "select kernel");
   if (o->xtrace) HIP_TRY(launch_record(p->Xb, p->stride, p->st, o->xtrace, p->n, p->dim, p->ps), "record kernel");
@@ -299,7 +304,8 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   p->sp = make_split(p->n_pad);
   p->stride = (size_t)p->n_pad * p->vec;
   p->nred = (p->n_pad + 255) / 256;
-  p->nsg = p->sp.blocks_x * 4 * p->sp.slices;
+  const std::vector<int4> items = triangle_items(p->sp);
+  p->nsg = (int)items.size();
   hipStream_t user = (hipStream_t)stream;
   auto bail = [&](sl_status st) {
     free_plan_memory(p);
@@ -313,6 +319,8 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess) e = hipMalloc(&p->d, (size_t)p->n_pad * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->W, sizeof(double) * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->Xb, sizeof(float) * 3 * p->stride);
+  if (e == hipSuccess) e = hipMalloc(&p->Eb, sizeof(float) * p->stride);
+  if (e == hipSuccess) e = hipMalloc(&p->items, sizeof(int4) * items.size());
   if (e == hipSuccess) e = hipMalloc(&p->fpart, sizeof(double) * p->sp.slices * 3 * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->spart, sizeof(double) * p->sp.slices * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(double) * 8 * p->nred);
@@ -322,7 +330,10 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
   if (e != hipSuccess) return bail(hip_fail(e, "plan allocation"));
   e = hipMemsetAsync(p->Xb, 0, sizeof(float) * 3 * p->stride, p->ps);
-  if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
+  if (e == hipSuccess) e = hipMemsetAsync(p->Eb, 0, sizeof(float) * p->stride, p->ps);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->ps);
+  if (e != hipSuccess) return bail(hip_fail(e, "plan initialization"));
   if ((s = join_from(p, user)) != SL_OK) return bail(s);
   if ((e = hipEventRecord(p->ev_a, p->ps)) != hipSuccess) return bail(hip_fail(e, "hipEventRecord"));
   if ((s = build_distances(p, g)) != SL_OK) return bail(s);
@@ -493,11 +504,13 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                                p->ps), "force kernel");
           break;
         case 1:
-          HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->st, p->red, p->ps),
+          HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red,
+                                p->ps),
                   "update kernel");
           break;
         case 2:
-          HIP_TRY(launch_sgdelta(p->dim, p->d, p->Xb, p->stride, p->st, p->sgpart, p->sp, p->n_pad, p->ps),
+          HIP_TRY(launch_sgdelta(p->dim, p->d, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart,
+                                 p->sp, p->ps),
                   "safeguard kernel");
           break;
         default:

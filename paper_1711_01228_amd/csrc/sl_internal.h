@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace sl {
 
@@ -21,6 +22,8 @@ namespace sl {
 //   X      iterates as float2 (dim 2) or float4 with w = 0 (dim 3), n_pad
 //          entries each, padding at the origin.  Three buffers rotate: the
 //          current iterate, X^H and X~; DevState::cur names the current one.
+//   E      the extrapolation step e_i = x~_i - x^H_i as stored (same format),
+//          read by the safeguard pass.
 // ---------------------------------------------------------------------------
 constexpr int kRowBlock = 64;   // rows per wave (one per lane)
 constexpr int kColGroup = 16;   // columns per 16-byte lane chunk
@@ -80,10 +83,14 @@ hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* Xb,
                         const DevState* st, double* fpart, double* spart, const Split& sp, int n_pad,
                         hipStream_t s);
 hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, const double* spart,
-                         const double* W, float* Xb, size_t stride, const DevState* st, double* red,
+                         const double* W, float* Xb, size_t stride, float* Eb, const DevState* st, double* red,
                          hipStream_t s);
-hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const DevState* st,
-                          double* sgpart, const Split& sp, int n_pad, hipStream_t s);
+// Work items (row block, first column group, end group, 0) of the safeguard
+// pass: the upper triangle in equal runs of column groups.
+std::vector<int4> triangle_items(const Split& sp);
+hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
+                          const int4* items, int nitems, const DevState* st, double* sgpart, const Split& sp,
+                          hipStream_t s);
 hipError_t launch_select(int dim, const LoopParams& p, const double* red, int nred, const double* sgpart,
                          int nsg, DevState* st, double* trace, hipStream_t s);
 hipError_t launch_record(const float* Xb, size_t stride, const DevState* st, float* xtrace, int n, int dim,

@@ -19,7 +19,9 @@
 // trees, fixed slice order), so results are bitwise repeatable run to run.
 #include "sl_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace sl {
 
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, co
 template <int DIM, bool STRESS>
 __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __restrict__ fpart,
                                                 const double* __restrict__ spart, const double* __restrict__ W,
-                                                float* __restrict__ Xb, size_t stride,
+                                                float* __restrict__ Xb, size_t stride, float* __restrict__ Eb,
                                                 const DevState* __restrict__ st, double* __restrict__ red) {
   using V = typename VecT<DIM>::T;
   __shared__ double sh[7][256];
@@ -186,12 +188,19 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
       v[2 + c] = (double)xh[c];
       bad = bad || !isfinite(xh[c]) || !isfinite(xt[c]);
     }
+    V* __restrict__ E = reinterpret_cast<V*>(Eb);
     if constexpr (DIM == 2) {
       XH[i] = make_float2(xh[0], xh[1]);
-      if (p.omega_p != 0.0) XT[i] = make_float2(xt[0], xt[1]);
+      if (p.omega_p != 0.0) {
+        XT[i] = make_float2(xt[0], xt[1]);
+        E[i] = make_float2(xt[0] - xh[0], xt[1] - xh[1]);
+      }
     } else {
       XH[i] = make_float4(xh[0], xh[1], xh[2], 0.f);
-      if (p.omega_p != 0.0) XT[i] = make_float4(xt[0], xt[1], xt[2], 0.f);
+      if (p.omega_p != 0.0) {
+        XT[i] = make_float4(xt[0], xt[1], xt[2], 0.f);
+        E[i] = make_float4(xt[0] - xh[0], xt[1] - xh[1], xt[2] - xh[2], 0.f);
+      }
     }
     if constexpr (STRESS) {
       for (int s = 0; s < p.slices; ++s) v[5] += spart[(size_t)s * p.n_pad + i];
@@ -207,63 +216,71 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// Safeguard: f(X~) - f(X^H) = sum_{i<j} w (r~ - r^H)(r~ + r^H - 2 d), taken
-// over the upper triangle only (column groups left of the diagonal block are
-// skipped; inside it pairs with j <= i are masked).  One double per wave.
+// Safeguard: f(X~) - f(X^H) = sum_{i<j} w (r~ - r^H)(r~ + r^H - 2 d).
+// Near convergence r~ and r^H agree to many digits, so r~ - r^H is not formed
+// as a difference: with the stored step e_i = x~_i - x^H_i, h = x^H_i - x^H_j,
+// t = x~_i - x~_j = h + (e_i - e_j) and s = h + t,
+//   r~^2 - r^H^2 = (e_i - e_j) . s,   r~ - r^H = (e_i - e_j) . s / (r~ + r^H),
+// and the pair term is w (r~ - r^H)(r~ + r^H - 2d)
+//                   = ((e_i - e_j) . s) (1/d) (1/d - 2 / (r~ + r^H)).
+// Work items cover the upper triangle in equal runs of column groups: item =
+// (row block, first group, end group); inside the diagonal block pairs with
+// j <= i are masked.  One double per wave, summed later in item order.
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
-                                                 size_t stride, const DevState* __restrict__ st,
-                                                 double* __restrict__ sgpart, int nrb, int ng, int gps) {
+                                                 size_t stride, const float* __restrict__ Eb,
+                                                 const int4* __restrict__ items, int nitems,
+                                                 const DevState* __restrict__ st, double* __restrict__ sgpart,
+                                                 int ng) {
   using V = typename VecT<DIM>::T;
   if (st->done) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rb = blockIdx.x * 4 + wave;
-  const size_t slot = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + wave;
+  const int item = blockIdx.x * 4 + wave;
+  if (item >= nitems) return;
+  const int4 it = items[item];
+  const int rb = it.x, g0 = it.y, g1 = it.z;
+  const int h = (st->cur + 1) % 3;
+  const V* __restrict__ XH = reinterpret_cast<const V*>(Xb + (size_t)h * stride);
+  const V* __restrict__ E = reinterpret_cast<const V*>(Eb);
+  const int gdiag = rb * (kRowBlock / kColGroup);
+  const int i = rb * kRowBlock + lane;
+  const V hi = XH[i], ei = E[i];
+  const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
   double acc = 0.0;
-  if (rb < nrb) {
-    const int cur = st->cur, h = (cur + 1) % 3, t = (cur + 2) % 3;
-    const V* __restrict__ XH = reinterpret_cast<const V*>(Xb + (size_t)h * stride);
-    const V* __restrict__ XT = reinterpret_cast<const V*>(Xb + (size_t)t * stride);
-    const int slice = blockIdx.y;
-    const int gdiag = rb * (kRowBlock / kColGroup);
-    const int g0 = max(slice * gps, gdiag);
-    const int g1 = min(slice * gps + gps, ng);
-    const int i = rb * kRowBlock + lane;
-    const V hi = XH[i], ti = XT[i];
-    const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
-    for (int g = g0; g < g1; ++g) {
-      const uint4 q = tile[(size_t)g * 64];
-      const bool diag = g < gdiag + kRowBlock / kColGroup;
-      const V* __restrict__ hj = XH + (size_t)g * kColGroup;
-      const V* __restrict__ tj = XT + (size_t)g * kColGroup;
-      float a = 0.f;
+  for (int g = g0; g < g1; ++g) {
+    const uint4 q = tile[(size_t)g * 64];
+    const bool diag = g < gdiag + kRowBlock / kColGroup;
+    const V* __restrict__ hj = XH + (size_t)g * kColGroup;
+    const V* __restrict__ ej = E + (size_t)g * kColGroup;
+    float a = 0.f;
 #pragma unroll
-      for (int k = 0; k < kColGroup; ++k) {
-        const float dd = byte_as_float(chunk_word(q, k), k & 3);
-        const V ph = hj[k], pt = tj[k];
-        float hx = hi.x - ph.x, hy = hi.y - ph.y;
-        float tx = ti.x - pt.x, ty = ti.y - pt.y;
-        float rh2 = fmaf(hx, hx, kTiny), rt2 = fmaf(tx, tx, kTiny);
-        rh2 = fmaf(hy, hy, rh2);
-        rt2 = fmaf(ty, ty, rt2);
-        if constexpr (DIM == 3) {
-          const float hz = hi.z - ph.z, tz = ti.z - pt.z;
-          rh2 = fmaf(hz, hz, rh2);
-          rt2 = fmaf(tz, tz, rt2);
-        }
-        const float rh = rh2 * __builtin_amdgcn_rsqf(rh2);
-        const float rt = rt2 * __builtin_amdgcn_rsqf(rt2);
-        const float inv = dd > 0.f ? __builtin_amdgcn_rcpf(dd) : 0.f;
-        float term = (inv * inv) * (rt - rh) * fmaf(-2.f, dd, rt + rh);
-        if (diag && g * kColGroup + k <= i) term = 0.f;
-        a += term;
+    for (int k = 0; k < kColGroup; ++k) {
+      const float dd = byte_as_float(chunk_word(q, k), k & 3);
+      const V ph = hj[k], pe = ej[k];
+      const float hx = hi.x - ph.x, hy = hi.y - ph.y;
+      const float ex = ei.x - pe.x, ey = ei.y - pe.y;
+      const float tx = hx + ex, ty = hy + ey;
+      float rh2 = fmaf(hx, hx, kTiny), rt2 = fmaf(tx, tx, kTiny);
+      rh2 = fmaf(hy, hy, rh2);
+      rt2 = fmaf(ty, ty, rt2);
+      float num = fmaf(ey, hy + ty, ex * (hx + tx));
+      if constexpr (DIM == 3) {
+        const float hz = hi.z - ph.z, ez = ei.z - pe.z, tz = hz + ez;
+        rh2 = fmaf(hz, hz, rh2);
+        rt2 = fmaf(tz, tz, rt2);
+        num = fmaf(ez, hz + tz, num);
       }
-      acc += (double)a;
+      const float sum = fmaf(rh2, __builtin_amdgcn_rsqf(rh2), rt2 * __builtin_amdgcn_rsqf(rt2));
+      const float inv = dd > 0.f ? __builtin_amdgcn_rcpf(dd) : 0.f;
+      float term = (num * inv) * fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv);
+      if (diag && g * kColGroup + k <= i) term = 0.f;
+      a += term;
     }
+    acc += (double)a;
   }
   acc = wave_sum(acc);
-  if (lane == 0) sgpart[slot] = acc;
+  if (lane == 0) sgpart[item] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -548,25 +565,37 @@ hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* Xb,
 }
 
 hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, const double* spart,
-                         const double* W, float* Xb, size_t stride, const DevState* st, double* red,
+                         const double* W, float* Xb, size_t stride, float* Eb, const DevState* st, double* red,
                          hipStream_t s) {
   const unsigned nb = blocks_for(p.n_pad);
   if (dim == 2) {
-    if (p.stress) k_update<2, true><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
-    else k_update<2, false><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
+    if (p.stress) k_update<2, true><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, Eb, st, red);
+    else k_update<2, false><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, Eb, st, red);
   } else {
-    if (p.stress) k_update<3, true><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
-    else k_update<3, false><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, st, red);
+    if (p.stress) k_update<3, true><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, Eb, st, red);
+    else k_update<3, false><<<nb, 256, 0, s>>>(p, fpart, spart, W, Xb, stride, Eb, st, red);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const DevState* st,
-                          double* sgpart, const Split& sp, int n_pad, hipStream_t s) {
-  (void)n_pad;
-  const dim3 grid(sp.blocks_x, sp.slices);
-  if (dim == 2) k_sgdelta<2><<<grid, 256, 0, s>>>(d, Xb, stride, st, sgpart, sp.nrb, sp.ng, sp.groups_per_slice);
-  else k_sgdelta<3><<<grid, 256, 0, s>>>(d, Xb, stride, st, sgpart, sp.nrb, sp.ng, sp.groups_per_slice);
+std::vector<int4> triangle_items(const Split& sp) {
+  // equal runs of column groups over the upper triangle (block granularity)
+  int64_t total = 0;
+  for (int rb = 0; rb < sp.nrb; ++rb) total += sp.ng - rb * (kRowBlock / kColGroup);
+  const int run = (int)std::max<int64_t>(8, (total + 8191) / 8192);
+  std::vector<int4> items;
+  for (int rb = 0; rb < sp.nrb; ++rb)
+    for (int g0 = rb * (kRowBlock / kColGroup); g0 < sp.ng; g0 += run)
+      items.push_back(make_int4(rb, g0, std::min(g0 + run, sp.ng), 0));
+  return items;
+}
+
+hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
+                          const int4* items, int nitems, const DevState* st, double* sgpart, const Split& sp,
+                          hipStream_t s) {
+  const unsigned nb = (unsigned)((nitems + 3) / 4);
+  if (dim == 2) k_sgdelta<2><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+  else k_sgdelta<3><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
   return hipGetLastError();
 }
 

@@ -252,7 +252,8 @@ def test_degenerate_graphs(sl):
     with sl.Plan(g2, 2) as plan:
         info = plan.run(X, omega=1.0, tol=1e-6, max_iter=3)
     assert info["iterations"] == 3 and info["converged"] == 0
-    np.testing.assert_array_equal(X.cpu().numpy(), [[-0.5, 0.0], [1.0, 0.0]])
+    # hand value (tests/golden/hand_cases.txt); rsq/rcp round to ~1 ulp
+    np.testing.assert_allclose(X.cpu().numpy(), [[-0.5, 0.0], [1.0, 0.0]], rtol=0, atol=1e-6)
     # isolated vertices keep their place; max_iter = 0 leaves X alone
     g = inputs.to_csr(6, [(0, 1), (1, 2)])
     X0 = inputs.uniform_positions(6, 2, 3)
