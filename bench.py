@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--omega", type=float, default=1.5)
     ap.add_argument("--quick", action="store_true", help="skip time-to-converge and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1).", file=sys.stderr)
@@ -170,6 +172,13 @@ def main():
         ttc["tol"] = 1e-3
         out["time_to_converge"] = ttc
     plan.close()
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = src.numel() * 4
+        del src, dst
 
     if not args.quick and not args.no_cpu:
         cb = cpu_baseline(g, X0)

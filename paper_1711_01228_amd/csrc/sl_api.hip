@@ -172,55 +172,61 @@ sl_status join_to(sl_plan* p, hipStream_t user) {
   return SL_OK;
 }
 
-// Multi-source BFS, 256 sources per sweep, then W.  Distances above 255 hops
-// are refused (SL_ERANGE).
+// Multi-source BFS, bfs_sources_per_sweep() sources per sweep, then W.
+// Distances above 255 hops are refused (SL_ERANGE).
 sl_status build_distances(sl_plan* p, const sl_graph* g) {
   const int n = p->n;
   HIP_TRY(hipMemsetAsync(p->d, 0, (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
   if (n > 1 && g->nnz > 0) {
-    int64_t* rp = nullptr;
-    int32_t* ci = nullptr;
-    uint64_t *fr = nullptr, *vis = nullptr, *nx = nullptr;
+    // source row of every CSR entry, for the edge-parallel gather
+    std::vector<int32_t> erow((size_t)g->nnz);
+    for (int v = 0; v < n; ++v)
+      for (int64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e) erow[(size_t)e] = v;
+    int32_t *er = nullptr, *ci = nullptr;
+    uint64_t *fr = nullptr, *vis = nullptr, *nx = nullptr, *acc = nullptr;
     int32_t* flag = nullptr;
     int32_t* hflag = nullptr;
     sl_status status = SL_OK;
     auto cleanup = [&]() {
       (void)hipStreamSynchronize(p->ps);
-      (void)hipFree(rp);
+      (void)hipFree(er);
       (void)hipFree(ci);
       (void)hipFree(fr);
       (void)hipFree(vis);
       (void)hipFree(nx);
+      (void)hipFree(acc);
       (void)hipFree(flag);
       if (hflag) (void)hipHostFree(hflag);
     };
     hipError_t e = hipSuccess;
-    const size_t words = (size_t)n * 4;
-    if (e == hipSuccess) e = hipMalloc(&rp, sizeof(int64_t) * (n + 1));
-    if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * std::max<int64_t>(g->nnz, 1));
+    const size_t words = (size_t)n * bfs_words();
+    if (e == hipSuccess) e = hipMalloc(&er, sizeof(int32_t) * g->nnz);
+    if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * g->nnz);
     if (e == hipSuccess) e = hipMalloc(&fr, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&vis, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&nx, sizeof(uint64_t) * words);
+    if (e == hipSuccess) e = hipMalloc(&acc, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t));
     if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMemcpyAsync(rp, g->row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess) e = hipMemcpyAsync(er, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e != hipSuccess) {
       cleanup();
       return hip_fail(e, "distance buffers");
     }
-    for (int base = 0; base < n && status == SL_OK; base += 256) {
-      e = launch_bfs_init(fr, vis, n, base, p->ps);
+    const int sweep = bfs_sources_per_sweep();
+    for (int base = 0; base < n && status == SL_OK && e == hipSuccess; base += sweep) {
+      e = launch_bfs_init(fr, vis, acc, n, base, p->ps);
       for (int level = 1; e == hipSuccess; ++level) {
         const int write = level <= 255;
         e = hipMemsetAsync(flag, 0, sizeof(int32_t), p->ps);
         if (e == hipSuccess)
-          e = launch_bfs_level(rp, ci, fr, vis, nx, p->d, n, p->sp.ng, base, level, write, flag, p->ps);
+          e = launch_bfs_level(er, ci, g->nnz, fr, acc, vis, nx, p->d, n, p->sp.ng, base, level, write, flag, p->ps);
         if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, p->ps);
         if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
         if (e != hipSuccess || *hflag == 0) break;
         if (!write) {
-          status = fail(SL_ERANGE, "a graph distance exceeds 255 hops (sources %d..%d)", base, base + 255);
+          status = fail(SL_ERANGE, "a graph distance exceeds 255 hops (sources %d..%d)", base, base + sweep - 1);
           break;
         }
         std::swap(fr, nx);

@@ -71,10 +71,12 @@ Split make_split(int n_pad);
 
 // ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);
-hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, int n, int base, hipStream_t s);
-hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col_idx, const uint64_t* frontier,
-                            uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base, int level,
-                            int write, int32_t* flag, hipStream_t s);
+int bfs_sources_per_sweep();  // sources searched together (bits per vertex)
+int bfs_words();              // 64-bit words per vertex in the BFS buffers
+hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s);
+hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* frontier,
+                            uint64_t* acc, uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base,
+                            int level, int write, int32_t* flag, hipStream_t s);
 hipError_t launch_weights(const uint8_t* d, double* W, const Split& sp, int n, hipStream_t s);
 hipError_t launch_pack_in(const float* X, float* Xb, int n, int n_pad, int dim, hipStream_t s);
 hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, float* X, int n, int dim,

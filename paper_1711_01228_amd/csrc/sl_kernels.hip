@@ -35,10 +35,6 @@ template <> struct VecT<3> { using T = float4; };
 // the pair term is c * (x_i - x_j) = c * 0 = 0 with c finite.
 constexpr float kTiny = 1e-30f;
 
-__device__ __forceinline__ float byte_as_float(uint32_t word, int b) {
-  return (float)((word >> (8 * b)) & 0xffu);
-}
-
 __device__ __forceinline__ uint32_t chunk_word(const uint4& q, int k) {
   return (k < 4) ? q.x : (k < 8) ? q.y : (k < 12) ? q.z : q.w;
 }
@@ -70,11 +66,30 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (*sh)[256]) {
   }
 }
 
+// Per-block table of the weights a distance byte stands for, built in LDS at
+// kernel start: entry b holds 1/b and 1/b^2 (correctly rounded), and 1 in .z
+// for the stress terms; entry 0 (same vertex, no path, padding) is all zero.
+template <bool STRESS> struct WeightEntry { using T = float2; };
+template <> struct WeightEntry<true> { using T = float4; };
+
+template <bool STRESS>
+__device__ __forceinline__ void fill_weight_table(typename WeightEntry<STRESS>::T* lut) {
+  const int b = threadIdx.x;  // blockDim.x == 256 == number of entries
+  const float fb = (float)b;
+  const float inv = b ? 1.0f / fb : 0.f;
+  const float w = b ? 1.0f / (fb * fb) : 0.f;
+  if constexpr (STRESS) lut[b] = make_float4(inv, w, b ? 1.f : 0.f, 0.f);
+  else lut[b] = make_float2(inv, w);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t word, int b) { return (word >> (8 * b)) & 0xffu; }
+
 // ---------------------------------------------------------------------------
 // All-pairs force pass.  One wave per (row block, column slice): lane l owns
 // row i = 64 rb + l, streams its 16-byte distance chunks tile by tile, and
 // reads the positions x_j of the slice through the scalar cache (j is uniform
-// across the wave).  Per pair (w = d^-2, c = w d / r - w):
+// across the wave).  Per pair, with (1/d, w = 1/d^2) from the LDS table:
+//   c    = w d / r - w = (1/d)(1/r) - w
 //   F_i += c (x_i - x_j)          [= w (d - r) u_ij]
 //   s_i += (r / d - 1)^2          [= w (r - d)^2]            (STRESS only)
 // Sixteen pairs are summed in float, then folded into double accumulators.
@@ -86,7 +101,11 @@ __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, co
                                                double* __restrict__ fpart, double* __restrict__ spart, int nrb,
                                                int ng, int gps, int n_pad) {
   using V = typename VecT<DIM>::T;
+  using E = typename WeightEntry<STRESS>::T;
+  __shared__ E lut[256];
   if (st->done) return;
+  fill_weight_table<STRESS>(lut);
+  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rb = blockIdx.x * 4 + wave;
   if (rb >= nrb) return;
@@ -107,7 +126,7 @@ __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, co
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
 #pragma unroll
       for (int k = 0; k < kColGroup; ++k) {
-        const float dd = byte_as_float(chunk_word(q, k), k & 3);
+        const E wt = lut[byte_of(chunk_word(q, k), k & 3)];
         const V p = xj[k];
         const float dx = xi.x - p.x, dy = xi.y - p.y;
         float r2 = fmaf(dx, dx, kTiny);
@@ -118,15 +137,12 @@ __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, co
           r2 = fmaf(dz, dz, r2);
         }
         const float rinv = __builtin_amdgcn_rsqf(r2);
-        const bool nz = dd > 0.f;
-        const float inv = nz ? __builtin_amdgcn_rcpf(dd) : 0.f;
-        const float c = fmaf(inv, rinv, -(inv * inv));
+        const float c = fmaf(wt.x, rinv, -wt.y);
         a0 = fmaf(c, dx, a0);
         a1 = fmaf(c, dy, a1);
         if constexpr (DIM == 3) a2 = fmaf(c, dz, a2);
         if constexpr (STRESS) {
-          const float r = r2 * rinv;
-          const float t = fmaf(r, inv, nz ? -1.f : 0.f);
+          const float t = fmaf(r2 * rinv, wt.x, -wt.z);
           as = fmaf(t, t, as);
         }
       }
@@ -217,16 +233,49 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
 
 // ---------------------------------------------------------------------------
 // Safeguard: f(X~) - f(X^H) = sum_{i<j} w (r~ - r^H)(r~ + r^H - 2 d).
-// Near convergence r~ and r^H agree to many digits, so r~ - r^H is not formed
-// as a difference: with the stored step e_i = x~_i - x^H_i, h = x^H_i - x^H_j,
-// t = x~_i - x~_j = h + (e_i - e_j) and s = h + t,
-//   r~^2 - r^H^2 = (e_i - e_j) . s,   r~ - r^H = (e_i - e_j) . s / (r~ + r^H),
-// and the pair term is w (r~ - r^H)(r~ + r^H - 2d)
-//                   = ((e_i - e_j) . s) (1/d) (1/d - 2 / (r~ + r^H)).
+// Near convergence r~ and r^H agree to many digits, so neither r~ - r^H nor
+// r~^2 - r^H^2 is formed as a difference.  With the stored step
+// e_i = x~_i - x^H_i, h = x^H_i - x^H_j and e = e_i - e_j:
+//   r~^2 - r^H^2 = e . (2h + e) =: m,     r~^2 = r^H^2 + m,
+//   r~ - r^H = m / (r~ + r^H),
+// and the pair term is w (r~ - r^H)(r~ + r^H - 2d) = m (1/d)(1/d - 2/(r~ + r^H)).
 // Work items cover the upper triangle in equal runs of column groups: item =
-// (row block, first group, end group); inside the diagonal block pairs with
+// (row block, first group, end group); in the diagonal block pairs with
 // j <= i are masked.  One double per wave, summed later in item order.
 // ---------------------------------------------------------------------------
+template <int DIM, bool MASK>
+__device__ __forceinline__ float safeguard_group(const uint4& q, const float* lut, typename VecT<DIM>::T hi,
+                                                 typename VecT<DIM>::T ei,
+                                                 const typename VecT<DIM>::T* __restrict__ hj,
+                                                 const typename VecT<DIM>::T* __restrict__ ej, int jrel) {
+  using V = typename VecT<DIM>::T;
+  float a = 0.f;
+#pragma unroll
+  for (int k = 0; k < kColGroup; ++k) {
+    const float inv = lut[byte_of(chunk_word(q, k), k & 3)];
+    const V ph = hj[k], pe = ej[k];
+    const float hx = hi.x - ph.x, hy = hi.y - ph.y;
+    const float ex = ei.x - pe.x, ey = ei.y - pe.y;
+    float rh2 = fmaf(hx, hx, kTiny);
+    rh2 = fmaf(hy, hy, rh2);
+    float m = ex * fmaf(2.f, hx, ex);
+    m = fmaf(ey, fmaf(2.f, hy, ey), m);
+    if constexpr (DIM == 3) {
+      const float hz = hi.z - ph.z, ez = ei.z - pe.z;
+      rh2 = fmaf(hz, hz, rh2);
+      m = fmaf(ez, fmaf(2.f, hz, ez), m);
+    }
+    const float rt2 = fmaxf(rh2 + m, kTiny);
+    const float sum = fmaf(rh2, __builtin_amdgcn_rsqf(rh2), rt2 * __builtin_amdgcn_rsqf(rt2));
+    float term = (m * inv) * fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv);
+    if constexpr (MASK) {
+      if (k <= jrel) term = 0.f;  // column j = i - jrel + k is not right of the diagonal
+    }
+    a += term;
+  }
+  return a;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
                                                  size_t stride, const float* __restrict__ Eb,
@@ -234,7 +283,10 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
                                                  const DevState* __restrict__ st, double* __restrict__ sgpart,
                                                  int ng) {
   using V = typename VecT<DIM>::T;
+  __shared__ float lut[256];
   if (st->done) return;
+  lut[threadIdx.x] = threadIdx.x ? 1.0f / (float)threadIdx.x : 0.f;
+  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int item = blockIdx.x * 4 + wave;
   if (item >= nitems) return;
@@ -244,40 +296,22 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
   const V* __restrict__ XH = reinterpret_cast<const V*>(Xb + (size_t)h * stride);
   const V* __restrict__ E = reinterpret_cast<const V*>(Eb);
   const int gdiag = rb * (kRowBlock / kColGroup);
+  const int gfree = gdiag + kRowBlock / kColGroup;  // first group right of the diagonal block
   const int i = rb * kRowBlock + lane;
   const V hi = XH[i], ei = E[i];
   const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
   double acc = 0.0;
-  for (int g = g0; g < g1; ++g) {
+  int g = g0;
+  for (; g < g1 && g < gfree; ++g) {
     const uint4 q = tile[(size_t)g * 64];
-    const bool diag = g < gdiag + kRowBlock / kColGroup;
-    const V* __restrict__ hj = XH + (size_t)g * kColGroup;
-    const V* __restrict__ ej = E + (size_t)g * kColGroup;
-    float a = 0.f;
-#pragma unroll
-    for (int k = 0; k < kColGroup; ++k) {
-      const float dd = byte_as_float(chunk_word(q, k), k & 3);
-      const V ph = hj[k], pe = ej[k];
-      const float hx = hi.x - ph.x, hy = hi.y - ph.y;
-      const float ex = ei.x - pe.x, ey = ei.y - pe.y;
-      const float tx = hx + ex, ty = hy + ey;
-      float rh2 = fmaf(hx, hx, kTiny), rt2 = fmaf(tx, tx, kTiny);
-      rh2 = fmaf(hy, hy, rh2);
-      rt2 = fmaf(ty, ty, rt2);
-      float num = fmaf(ey, hy + ty, ex * (hx + tx));
-      if constexpr (DIM == 3) {
-        const float hz = hi.z - ph.z, ez = ei.z - pe.z, tz = hz + ez;
-        rh2 = fmaf(hz, hz, rh2);
-        rt2 = fmaf(tz, tz, rt2);
-        num = fmaf(ez, hz + tz, num);
-      }
-      const float sum = fmaf(rh2, __builtin_amdgcn_rsqf(rh2), rt2 * __builtin_amdgcn_rsqf(rt2));
-      const float inv = dd > 0.f ? __builtin_amdgcn_rcpf(dd) : 0.f;
-      float term = (num * inv) * fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv);
-      if (diag && g * kColGroup + k <= i) term = 0.f;
-      a += term;
-    }
-    acc += (double)a;
+    // pair (i, j) with j = 16 g + k is kept iff j > i, i.e. k > i - 16 g
+    acc += (double)safeguard_group<DIM, true>(q, lut, hi, ei, XH + (size_t)g * kColGroup,
+                                              E + (size_t)g * kColGroup, i - g * kColGroup);
+  }
+  for (; g < g1; ++g) {
+    const uint4 q = tile[(size_t)g * 64];
+    acc += (double)safeguard_group<DIM, false>(q, lut, hi, ei, XH + (size_t)g * kColGroup,
+                                               E + (size_t)g * kColGroup, 0);
   }
   acc = wave_sum(acc);
   if (lane == 0) sgpart[item] = acc;
@@ -389,18 +423,25 @@ __global__ __launch_bounds__(256) void k_pack_out(const float* __restrict__ Xb, 
 }
 
 // ---------------------------------------------------------------------------
-// Breadth-first search from the 256 sources base .. base+255 at once.  Word k
-// of a vertex holds one bit per source base + 64k + b.  A level pulls the
-// frontier bits of all neighbours (a segmented OR over the CSR row), keeps
-// those not yet visited, and writes the level into d(v, s) for each new bit.
-// Distances are symmetric, so the row of v is written: its 16 sources per
-// chunk share one 16-byte lane chunk of the tile layout, read-modify-written by
-// the only thread that owns row v.
+// Breadth-first search from kBfsSources sources at once.  Word k of a vertex
+// holds one bit per source base + 64k + b (bit-parallel frontiers).  A level
+// is two kernels:
+//   k_bfs_gather  one thread per CSR entry (v, u): the frontier bits of u,
+//                 OR-reduced over each run of equal v inside the wave (a
+//                 segmented OR over the CSR row; rows are contiguous) and
+//                 folded into acc[v] by one atomic OR per run and word
+//   k_bfs_update  one thread per vertex: the new bits acc[v] & ~visited[v]
+//                 become the next frontier, and the level is written into
+//                 d(v, s) for every new source s.  Distances are symmetric, so
+//                 row v is written: 16 sources share one 16-byte lane chunk of
+//                 the tile layout, read-modify-written by the only thread that
+//                 owns row v.
 // ---------------------------------------------------------------------------
-constexpr int kBfsWords = 4;
+constexpr int kBfsWords = 8;
+constexpr int kBfsSources = 64 * kBfsWords;
 
 __global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ frontier, uint64_t* __restrict__ visited,
-                                                  int n, int base) {
+                                                  uint64_t* __restrict__ acc, int n, int base) {
   const int v = blockIdx.x * 256 + threadIdx.x;
   if (v >= n) return;
 #pragma unroll
@@ -409,6 +450,37 @@ __global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ frontie
     const uint64_t w = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
     frontier[(size_t)v * kBfsWords + k] = w;
     visited[(size_t)v * kBfsWords + k] = w;
+    acc[(size_t)v * kBfsWords + k] = 0ull;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ erow,
+                                                    const int32_t* __restrict__ col_idx, int64_t nnz,
+                                                    const uint64_t* __restrict__ frontier,
+                                                    unsigned long long* __restrict__ acc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = e < nnz;
+  const int v = valid ? erow[e] : -1 - lane;  // padding lanes never join a run
+  const int u = valid ? col_idx[e] : 0;
+  bool same[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int off = 1 << s;
+    const int ov = __shfl_down(v, off, 64);
+    same[s] = (lane + off < 64) && ov == v;
+  }
+  const int pv = __shfl_up(v, 1, 64);
+  const bool head = valid && (lane == 0 || pv != v);
+#pragma unroll
+  for (int k = 0; k < kBfsWords; ++k) {
+    unsigned long long f = valid ? frontier[(size_t)u * kBfsWords + k] : 0ull;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const unsigned long long o = __shfl_down(f, 1 << s, 64);
+      if (same[s]) f |= o;
+    }
+    if (head && f) atomicOr(&acc[(size_t)v * kBfsWords + k], f);
   }
 }
 
@@ -417,48 +489,39 @@ __device__ __forceinline__ uint32_t byte_mask4(uint32_t nib) {
          ((nib & 8u) ? 0xff000000u : 0u);
 }
 
-__global__ __launch_bounds__(256) void k_bfs_level(const int64_t* __restrict__ row_ptr,
-                                                   const int32_t* __restrict__ col_idx,
-                                                   const uint64_t* __restrict__ frontier,
-                                                   uint64_t* __restrict__ visited, uint64_t* __restrict__ next,
-                                                   uint8_t* __restrict__ d, int n, int ng, int base, int level,
-                                                   int write, int32_t* __restrict__ flag) {
+__global__ __launch_bounds__(256) void k_bfs_update(uint64_t* __restrict__ acc, uint64_t* __restrict__ visited,
+                                                    uint64_t* __restrict__ next, uint8_t* __restrict__ d, int n,
+                                                    int ng, int base, int level, int write,
+                                                    int32_t* __restrict__ flag) {
   const int v = blockIdx.x * 256 + threadIdx.x;
   if (v >= n) return;
-  uint64_t acc[kBfsWords] = {0, 0, 0, 0};
-  const int64_t e1 = row_ptr[v + 1];
-  for (int64_t e = row_ptr[v]; e < e1; ++e) {
-    const ulonglong2* f = reinterpret_cast<const ulonglong2*>(frontier + (size_t)col_idx[e] * kBfsWords);
-    const ulonglong2 a = f[0], b = f[1];
-    acc[0] |= a.x;
-    acc[1] |= a.y;
-    acc[2] |= b.x;
-    acc[3] |= b.y;
-  }
   bool any = false;
   const uint32_t lv = (uint32_t)level * 0x01010101u;
 #pragma unroll
   for (int k = 0; k < kBfsWords; ++k) {
-    const uint64_t vis = visited[(size_t)v * kBfsWords + k];
-    const uint64_t nw = acc[k] & ~vis;
-    next[(size_t)v * kBfsWords + k] = nw;
+    const size_t q = (size_t)v * kBfsWords + k;
+    const uint64_t a = acc[q];
+    const uint64_t vis = visited[q];
+    const uint64_t nw = a & ~vis;
+    next[q] = nw;
+    if (a) acc[q] = 0ull;
     if (nw == 0) continue;
     any = true;
     if (!write) continue;
-    visited[(size_t)v * kBfsWords + k] = vis | nw;
+    visited[q] = vis | nw;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t bits = (uint32_t)(nw >> (16 * q)) & 0xffffu;
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t bits = (uint32_t)(nw >> (16 * c)) & 0xffffu;
       if (bits == 0) continue;
-      const int s0 = base + 64 * k + 16 * q;
+      const int s0 = base + 64 * k + 16 * c;
       uint4* chunk = reinterpret_cast<uint4*>(d + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
                                               (size_t)(v % kRowBlock) * kColGroup);
-      uint4 c = *chunk;
-      c.x |= lv & byte_mask4(bits & 0xfu);
-      c.y |= lv & byte_mask4((bits >> 4) & 0xfu);
-      c.z |= lv & byte_mask4((bits >> 8) & 0xfu);
-      c.w |= lv & byte_mask4((bits >> 12) & 0xfu);
-      *chunk = c;
+      uint4 w = *chunk;
+      w.x |= lv & byte_mask4(bits & 0xfu);
+      w.y |= lv & byte_mask4((bits >> 4) & 0xfu);
+      w.z |= lv & byte_mask4((bits >> 8) & 0xfu);
+      w.w |= lv & byte_mask4((bits >> 12) & 0xfu);
+      *chunk = w;
     }
   }
   if (any) *flag = 1;
@@ -514,18 +577,25 @@ Split make_split(int n_pad) {
 
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s) { return hipMemsetAsync(p, 0, bytes, s); }
 
-hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, int n, int base, hipStream_t s) {
+int bfs_sources_per_sweep() { return kBfsSources; }
+int bfs_words() { return kBfsWords; }
+
+hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_bfs_init<<<blocks_for(n), 256, 0, s>>>(frontier, visited, n, base);
+  k_bfs_init<<<blocks_for(n), 256, 0, s>>>(frontier, visited, acc, n, base);
   return hipGetLastError();
 }
 
-hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col_idx, const uint64_t* frontier,
-                            uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base, int level,
-                            int write, int32_t* flag, hipStream_t s) {
+hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* frontier,
+                            uint64_t* acc, uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base,
+                            int level, int write, int32_t* flag, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_bfs_level<<<blocks_for(n), 256, 0, s>>>(row_ptr, col_idx, frontier, visited, next, d, n, ng, base, level,
-                                            write, flag);
+  if (nnz > 0)
+    k_bfs_gather<<<blocks_for((size_t)nnz), 256, 0, s>>>(erow, col_idx, nnz, frontier,
+                                                         reinterpret_cast<unsigned long long*>(acc));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_bfs_update<<<blocks_for(n), 256, 0, s>>>(acc, visited, next, d, n, ng, base, level, write, flag);
   return hipGetLastError();
 }
 
