@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, co
   if (st->done) return;
   fill_weight_table<STRESS>(lut);
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int rb = blockIdx.x * 4 + wave;
   if (rb >= nrb) return;
   const int slice = blockIdx.y;
@@ -265,13 +265,14 @@ __device__ __forceinline__ float safeguard_group(const uint4& q, const float* lu
       rh2 = fmaf(hz, hz, rh2);
       m = fmaf(ez, fmaf(2.f, hz, ez), m);
     }
-    const float rt2 = fmaxf(rh2 + m, kTiny);
+    // |.|: rounding may leave rh2 + m a hair below zero when x~_i and x~_j coincide
+    const float rt2 = fabsf(rh2 + m);
     const float sum = fmaf(rh2, __builtin_amdgcn_rsqf(rh2), rt2 * __builtin_amdgcn_rsqf(rt2));
-    float term = (m * inv) * fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv);
+    float mi = m * inv;
     if constexpr (MASK) {
-      if (k <= jrel) term = 0.f;  // column j = i - jrel + k is not right of the diagonal
+      if (k <= jrel) mi = 0.f;  // column j = i - jrel + k is not right of the diagonal
     }
-    a += term;
+    a = fmaf(mi, fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv), a);
   }
   return a;
 }
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
   if (st->done) return;
   lut[threadIdx.x] = threadIdx.x ? 1.0f / (float)threadIdx.x : 0.f;
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int item = blockIdx.x * 4 + wave;
   if (item >= nitems) return;
   const int4 it = items[item];
