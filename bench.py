@@ -80,6 +80,40 @@ def cpu_baseline(g, X0, target_s=12.0):
                       "BA graph and start, %.1f s; distance rows (BFS) not timed" % (R, n, dt)}
 
 
+def bench_batch(omega, count=2048):
+    """2,048 graphs (n ~ U[16, 1024]: grids, random trees, Erdos-Renyi giant
+    components of mean degree 4), omega = 1.5 with the safeguard, each graph to
+    res <= 1e-3, in one persistent captured launch with autotuned tile shapes."""
+    import numpy as np
+    import torch
+
+    from paper_1711_01228_amd import binding, inputs
+
+    gs, xs = inputs.batch_of_graphs(count)
+    X0 = torch.tensor(np.concatenate(xs).astype(np.float32), device="cuda")
+    t = time.perf_counter()
+    plan = binding.BatchPlan(gs, 2)
+    plan_s = time.perf_counter() - t
+    cfg = plan.tune(X0, omega=omega)
+    X = X0.clone()
+    plan.run(X, omega=omega, tol=1e-3, max_iter=3000)  # warm (graph capture)
+    X = X0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tot, per = plan.run(X, omega=omega, tol=1e-3, max_iter=3000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    plan.close()
+    its = np.array([p["iterations"] for p in per])
+    ns = np.array([g.n for g in gs], dtype=np.float64)
+    pairs = float(np.sum(ns * (ns - 1) * its))
+    return {"graphs": count, "vertices": int(ns.sum()), "pairs_per_pass": float(np.sum(ns * (ns - 1))),
+            "seconds": round(wall, 4), "device_ms": round(tot["run_ms"], 3), "plan_s": round(plan_s, 3),
+            "pair_interactions_per_s": pairs / wall, "iterations_mean": float(its.mean()),
+            "iterations_max": int(its.max()), "all_converged": bool(tot["converged"]),
+            "rejected_total": int(tot["rejected"]), "tuned_config": cfg.tolist()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +124,8 @@ def main():
     ap.add_argument("--omega", type=float, default=1.5)
     ap.add_argument("--quick", action="store_true", help="skip time-to-converge and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D run of the same workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched small-graph run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -172,6 +208,43 @@ def main():
         ttc["tol"] = 1e-3
         out["time_to_converge"] = ttc
     plan.close()
+    del plan
+
+    # ---- the same workload in 3-D (float4 iterates, 17 flops per pair)
+    if not args.quick and not args.no_3d and dim == 2:
+        g3, X03 = inputs.ba65536(dim=3, n=n)
+        X3dev0 = torch.tensor(X03.astype(np.float32), device="cuda")
+        plan3 = binding.Plan(g3, 3)
+        X = X3dev0.clone()
+        plan3.run(X, omega=args.omega, tol=0.0, max_iter=max(args.warmup, 1))
+        X = X3dev0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = plan3.run(X, omega=args.omega, tol=0.0, max_iter=args.steps)
+        torch.cuda.synchronize()
+        w3 = time.perf_counter() - t
+        ms3 = plan3.profile(X3dev0, omega=args.omega, reps=5)
+        ttc3 = {}
+        for om in (1.0, args.omega):
+            X = X3dev0.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rr = plan3.run(X, omega=om, tol=1e-3, max_iter=3000)
+            torch.cuda.synchronize()
+            ttc3["omega=%g" % om] = {"seconds": round(time.perf_counter() - t, 4), "iterations": rr["iterations"],
+                                     "converged": bool(rr["converged"]), "rejected": rr["rejected"],
+                                     "final_residual": rr["residual"]}
+        plan3.close()
+        a3 = FLOPS_PER_PAIR[3] * pairs / (ms3["force"] * 1e-3) / 1e12
+        out["dim3"] = {"value": pairs * args.steps / w3, "ms_per_step": w3 * 1e3 / args.steps,
+                       "force_kernel_ms": round(ms3["force"], 4), "force_TFLOPs": round(a3, 3),
+                       "force_frac": round(a3 / PEAK_FP32_TFLOPS, 4),
+                       "step_kernel_ms": {k: round(v, 4) for k, v in ms3.items()}, "time_to_converge": ttc3}
+        log("3-D:", out["dim3"])
+    # ---- batched: 2,048 small graphs, one persistent launch, each to its own tol
+    if not args.quick and not args.no_batch:
+        out["batched"] = bench_batch(args.omega)
+        log("batched:", out["batched"])
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

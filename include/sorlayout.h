@@ -161,6 +161,53 @@ sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double ome
 /* Release a plan and all its device memory.  NULL is accepted. */
 sl_status sl_plan_destroy(sl_plan* plan);
 
+/* ---------------------------------------------------------------------------
+ * Batched layouts: many independent graphs of at most SL_BATCH_MAX_N vertices,
+ * each laid out by Algorithm 2 exactly as above (same step, extrapolation,
+ * safeguard and termination test, each graph stopping on its own), scheduled
+ * together: one persistent launch in which each workgroup takes the next graph
+ * from a queue ordered largest first and keeps its iterates in LDS.
+ * ------------------------------------------------------------------------- */
+#define SL_BATCH_MAX_N 1024
+#define SL_BATCH_CLASSES 16   /* size classes n_pad = 64, 128, ..., 1024 */
+
+typedef struct {
+  int32_t num_graphs;        /* >= 0                                                   */
+  const int64_t* graph_ptr;  /* host, num_graphs + 1 vertex offsets, graph_ptr[0] = 0: graph g
+                                owns vertices graph_ptr[g] .. graph_ptr[g+1]-1 of the
+                                concatenated graph; each graph has <= SL_BATCH_MAX_N vertices */
+  int64_t nnz;               /* entries of the concatenated CSR                         */
+  const int64_t* row_ptr;    /* host, graph_ptr[num_graphs] + 1 offsets                  */
+  const int32_t* col_idx;    /* host, nnz global neighbour ids; symmetric, no self loops or
+                                duplicates, and every edge stays inside its graph          */
+} sl_batch;
+
+typedef struct sl_batch_plan sl_batch_plan;
+
+/* Distances (breadth-first search) and weight sums of every graph, on the
+ * device, one workgroup per graph.  Errors: SL_EINVAL, SL_ERANGE (a distance
+ * above 255 hops), SL_ENOMEM, SL_EDEVICE. */
+sl_status sl_batch_plan_create(const sl_batch* b, int32_t dim, void* stream, sl_batch_plan** out);
+
+/* Autotuner: times short runs (tol 0, min(opt->max_iter, 8) iterations) from
+ * the device placement X (not modified) for workgroup sizes 256/512/1024 and,
+ * per size class, the number of column slices of the all-pairs passes, and
+ * keeps the fastest in the plan.  config (host, may be NULL) receives
+ * 1 + SL_BATCH_CLASSES ints: the workgroup size, then the slices per class
+ * (0 for classes with no graph). */
+sl_status sl_batch_plan_tune(sl_batch_plan* plan, const float* X, const sl_options* opt, void* stream,
+                             int32_t* config);
+
+/* Lay out every graph from the concatenated device placement X
+ * (graph_ptr[num_graphs] x dim floats, row-major) in place.  opt->trace and
+ * opt->xtrace must be NULL.  per_graph (host, num_graphs entries) and total may
+ * be NULL; total holds the largest iteration count and residual, converged = 1
+ * iff every graph converged, the sum of rejections, and run_ms. */
+sl_status sl_batch_plan_run(sl_batch_plan* plan, float* X, const sl_options* opt, void* stream, sl_result* per_graph,
+                            sl_result* total);
+
+sl_status sl_batch_plan_destroy(sl_batch_plan* plan);
+
 /* layout(G, X0, omega, tol, max_iter) -> X: sl_plan_create + sl_plan_run +
  * sl_plan_destroy. */
 sl_status sl_layout(const sl_graph* g, float* X, const sl_options* opt, void* stream, sl_result* out);

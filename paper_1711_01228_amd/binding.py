@@ -24,7 +24,10 @@ SL_FLAG_NO_GRAPH = 2
 
 EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run", "sl_plan_stress",
             "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
-            "sl_last_error")
+            "sl_last_error", "sl_batch_plan_create", "sl_batch_plan_tune", "sl_batch_plan_run",
+            "sl_batch_plan_destroy")
+SL_BATCH_MAX_N = 1024
+SL_BATCH_CLASSES = 16
 
 
 class SlError(RuntimeError):
@@ -43,6 +46,11 @@ class sl_options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("safeguard", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("trace", ctypes.c_void_p),
                 ("xtrace", ctypes.c_void_p)]
+
+
+class sl_batch(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_int32), ("graph_ptr", ctypes.c_void_p), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
 
 
 class sl_result(ctypes.Structure):
@@ -72,6 +80,10 @@ def _load():
         "sl_plan_destroy": (st, [P]),
         "sl_layout": (st, [ctypes.POINTER(sl_graph), P, ctypes.POINTER(sl_options), P, ctypes.POINTER(sl_result)]),
         "sl_last_error": (ctypes.c_char_p, []),
+        "sl_batch_plan_create": (st, [ctypes.POINTER(sl_batch), i32, P, ctypes.POINTER(P)]),
+        "sl_batch_plan_tune": (st, [P, P, ctypes.POINTER(sl_options), P, P]),
+        "sl_batch_plan_run": (st, [P, P, ctypes.POINTER(sl_options), P, P, ctypes.POINTER(sl_result)]),
+        "sl_batch_plan_destroy": (st, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -271,3 +283,95 @@ def layout(g, X0, omega=1.0, tol=1e-3, max_iter=1000, **kw):
     with Plan(g, X.shape[1]) as plan:
         info = plan.run(X, omega=omega, tol=tol, max_iter=max_iter, **kw)
     return X, info
+
+
+# --------------------------------------------------------------------------
+# Batched layouts
+# --------------------------------------------------------------------------
+class BatchArgs:
+    """Concatenation of many graphs into one block-diagonal CSR (global ids)."""
+
+    def __init__(self, graphs):
+        ns = [int(g.n) for g in graphs]
+        self.graph_ptr = np.zeros(len(graphs) + 1, dtype=np.int64)
+        self.graph_ptr[1:] = np.cumsum(ns)
+        rps, cis = [np.zeros(1, dtype=np.int64)], []
+        off_e = 0
+        for g, v0 in zip(graphs, self.graph_ptr[:-1]):
+            rps.append(np.asarray(g.row_ptr[1:], dtype=np.int64) + off_e)
+            cis.append(np.asarray(g.col_idx, dtype=np.int64) + v0)
+            off_e += int(g.row_ptr[-1])
+        self.row_ptr = np.ascontiguousarray(np.concatenate(rps))
+        self.col_idx = np.ascontiguousarray(np.concatenate(cis).astype(np.int32) if cis else np.zeros(0, np.int32))
+        self.n_total = int(self.graph_ptr[-1])
+        self.s = sl_batch(len(graphs), self.graph_ptr.ctypes.data, int(self.row_ptr[-1]), self.row_ptr.ctypes.data,
+                          self.col_idx.ctypes.data if len(self.col_idx) else None)
+
+
+def sl_batch_plan_create(batch: BatchArgs, dim: int, stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(LIB.sl_batch_plan_create(ctypes.byref(batch.s), int(dim), _stream_handle(stream), ctypes.byref(h)))
+    return h.value
+
+
+def sl_batch_plan_tune(plan: int, X_ptr: int, opt: sl_options, stream=None) -> np.ndarray:
+    cfg = np.zeros(1 + SL_BATCH_CLASSES, dtype=np.int32)
+    _check(LIB.sl_batch_plan_tune(plan, X_ptr, ctypes.byref(opt), _stream_handle(stream), cfg.ctypes.data))
+    return cfg
+
+
+def sl_batch_plan_run(plan: int, X_ptr: int, opt: sl_options, num_graphs: int, stream=None):
+    per = (sl_result * max(num_graphs, 1))()
+    tot = sl_result()
+    _check(LIB.sl_batch_plan_run(plan, X_ptr, ctypes.byref(opt), _stream_handle(stream), per, ctypes.byref(tot)))
+    return tot.as_dict(), [per[k].as_dict() for k in range(num_graphs)]
+
+
+def sl_batch_plan_destroy(plan: int) -> None:
+    _check(LIB.sl_batch_plan_destroy(plan))
+
+
+class BatchPlan:
+    """Distances and weights of many small graphs (each n <= 1024) on the device."""
+
+    def __init__(self, graphs, dim=2, stream=None):
+        self.args = BatchArgs(graphs)
+        self.num_graphs, self.dim = len(graphs), int(dim)
+        self.graph_ptr = self.args.graph_ptr
+        self.handle = sl_batch_plan_create(self.args, dim, stream)
+
+    def _check_x(self, X):
+        import torch
+
+        if X.dtype != torch.float32 or not X.is_cuda or not X.is_contiguous() or \
+                tuple(X.shape) != (self.args.n_total, self.dim):
+            raise ValueError("X must be a contiguous cuda float32 tensor of shape (%d, %d)" % (self.args.n_total,
+                                                                                          self.dim))
+
+    def tune(self, X, omega=1.5, max_iter=8, safeguard=True, stream=None) -> np.ndarray:
+        self._check_x(X)
+        opt = make_options(self.dim, omega, 0.0, max_iter, safeguard)
+        return sl_batch_plan_tune(self.handle, X.data_ptr(), opt, stream)
+
+    def run(self, X, omega=1.5, tol=1e-3, max_iter=1000, safeguard=True, stream=None):
+        """Lay out every graph in place; returns (total, per-graph list)."""
+        self._check_x(X)
+        opt = make_options(self.dim, omega, tol, max_iter, safeguard)
+        return sl_batch_plan_run(self.handle, X.data_ptr(), opt, self.num_graphs, stream)
+
+    def close(self):
+        if self.handle:
+            sl_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -159,6 +159,24 @@ sl_status free_plan_memory(sl_plan* p) {
   return SL_OK;
 }
 
+sl_status join_from_stream(hipStream_t ps, hipEvent_t ev, hipStream_t user) {
+  HIP_TRY(hipEventRecord(ev, user), "hipEventRecord");
+  HIP_TRY(hipStreamWaitEvent(ps, ev, 0), "hipStreamWaitEvent");
+  return SL_OK;
+}
+
+sl_status join_to_stream(hipStream_t ps, hipEvent_t ev, hipStream_t user) {
+  HIP_TRY(hipEventRecord(ev, ps), "hipEventRecord");
+  HIP_TRY(hipStreamWaitEvent(user, ev, 0), "hipStreamWaitEvent");
+  return SL_OK;
+}
+
+sl_status hip_try_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return SL_OK;
+}
+
 // Order the plan stream after the caller's stream.
 sl_status join_from(sl_plan* p, hipStream_t user) {
   HIP_TRY(hipEventRecord(p->ev_sync, user), "hipEventRecord");
@@ -581,6 +599,403 @@ sl_status sl_layout(const sl_graph* g, float* X, const sl_options* o, void* stre
   sl_plan_destroy(p);
   g_err = keep;
   return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched plans
+// ---------------------------------------------------------------------------
+struct sl_batch_plan {
+  int ngraphs = 0, dim = 2, cus = 0, threads = 512;
+  int64_t n_total = 0;
+  hipStream_t ps = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_sync = nullptr;
+  std::vector<BatchGraph> hgraphs;
+  std::vector<int32_t> horder;  // largest first
+  BatchGraph* graphs = nullptr;
+  int32_t* order = nullptr;
+  int32_t* queue = nullptr;
+  int32_t* status = nullptr;
+  uint8_t* d = nullptr;
+  double* W = nullptr;
+  BatchResult* res = nullptr;
+  std::vector<BatchResult> hres;
+  double plan_ms = 0.0;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<double> gkey;
+};
+
+namespace {
+
+sl_status check_batch(const sl_batch* b) {
+  if (!b) return fail(SL_EINVAL, "batch is NULL");
+  if (b->num_graphs < 0) return fail(SL_EINVAL, "num_graphs is negative");
+  if (b->num_graphs > 0 && !b->graph_ptr) return fail(SL_EINVAL, "graph_ptr is NULL");
+  int64_t n_total = 0;
+  if (b->num_graphs > 0) {
+    if (b->graph_ptr[0] != 0) return fail(SL_EINVAL, "graph_ptr[0] must be 0");
+    for (int g = 0; g < b->num_graphs; ++g) {
+      const int64_t n = b->graph_ptr[g + 1] - b->graph_ptr[g];
+      if (n < 0) return fail(SL_EINVAL, "graph_ptr decreases at graph %d", g);
+      if (n > SL_BATCH_MAX_N) return fail(SL_EINVAL, "graph %d has %lld vertices, more than %d", g, (long long)n,
+                                          SL_BATCH_MAX_N);
+    }
+    n_total = b->graph_ptr[b->num_graphs];
+  }
+  if (n_total > INT32_MAX) return fail(SL_EINVAL, "too many vertices in the batch");
+  sl_graph g{};
+  g.n = (int32_t)n_total;
+  g.nnz = b->nnz;
+  g.row_ptr = b->row_ptr;
+  g.col_idx = b->col_idx;
+  g.edge_len = nullptr;
+  if (n_total == 0 && b->nnz != 0) return fail(SL_EINVAL, "empty batch with edges");
+  sl_status s = check_graph(&g);
+  if (s != SL_OK) return s;
+  for (int gi = 0; gi < b->num_graphs; ++gi)
+    for (int64_t v = b->graph_ptr[gi]; v < b->graph_ptr[gi + 1]; ++v)
+      for (int64_t e = b->row_ptr[v]; e < b->row_ptr[v + 1]; ++e)
+        if (b->col_idx[e] < b->graph_ptr[gi] || b->col_idx[e] >= b->graph_ptr[gi + 1])
+          return fail(SL_EINVAL, "edge (%lld, %d) leaves graph %d", (long long)v, b->col_idx[e], gi);
+  return SL_OK;
+}
+
+void free_batch(sl_batch_plan* p) {
+  (void)hipFree(p->graphs);
+  (void)hipFree(p->order);
+  (void)hipFree(p->queue);
+  (void)hipFree(p->status);
+  (void)hipFree(p->d);
+  (void)hipFree(p->W);
+  (void)hipFree(p->res);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->ev_a) (void)hipEventDestroy(p->ev_a);
+  if (p->ev_b) (void)hipEventDestroy(p->ev_b);
+  if (p->ev_sync) (void)hipEventDestroy(p->ev_sync);
+  if (p->ps) (void)hipStreamDestroy(p->ps);
+}
+
+// Column slices that give every wave of a `threads` workgroup a unit, within
+// the LDS budget of the force partials.
+int default_slices(int n_pad, int threads) {
+  const int nrb = n_pad / kRowBlock, ng = n_pad / kColGroup, nw = threads / 64;
+  int s = std::max(1, nw / nrb);
+  s = std::min(s, ng);
+  s = std::min(s, kBatchMaxPartial / n_pad);
+  return std::max(1, s);
+}
+
+bool slices_ok(int n_pad, int s) { return s >= 1 && s <= n_pad / kColGroup && s * n_pad <= kBatchMaxPartial; }
+
+int batch_blocks(const sl_batch_plan* p, int count) {
+  const int per_cu = p->dim == 2 ? 2 : 1;  // LDS: ~78 KiB (2-D) or ~127 KiB (3-D) per workgroup
+  return std::max(1, std::min(count, p->cus * per_cu));
+}
+
+sl_status batch_upload_graphs(sl_batch_plan* p) {
+  HIP_TRY(hipMemcpyAsync(p->graphs, p->hgraphs.data(), sizeof(BatchGraph) * p->hgraphs.size(),
+                         hipMemcpyHostToDevice, p->ps),
+          "batch descriptors");
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  return SL_OK;
+}
+
+sl_status batch_params(const sl_batch_plan* p, const sl_options* o, BatchParams* bp) {
+  sl_status s = check_options(o);
+  if (s != SL_OK) return s;
+  if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
+  if (o->trace || o->xtrace) return fail(SL_EINVAL, "traces are not available for batched layouts");
+  bp->omega_p = o->omega - 1.0;
+  bp->tol = o->tol;
+  bp->max_iter = o->max_iter;
+  bp->safeguard = o->safeguard;
+  return SL_OK;
+}
+
+// Time one launch over the graphs listed in `order` (device), in ms.
+sl_status batch_time(sl_batch_plan* p, float* X, const int32_t* order, int count, const BatchParams& bp, float* ms) {
+  HIP_TRY(launch_batch_reset(p->queue, p->ps), "reset kernel");
+  HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+  HIP_TRY(launch_batch_layout(p->dim, p->threads, batch_blocks(p, count), p->graphs, order, count, p->queue, p->d,
+                              p->W, X, p->res, bp, p->ps),
+          "batch layout kernel");
+  HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+  HIP_TRY(hipEventSynchronize(p->ev_b), "hipEventSynchronize");
+  HIP_TRY(hipEventElapsedTime(ms, p->ev_a, p->ev_b), "hipEventElapsedTime");
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sl_status sl_batch_plan_create(const sl_batch* b, int32_t dim, void* stream, sl_batch_plan** out) {
+  g_err.clear();
+  if (!out) return fail(SL_EINVAL, "out is NULL");
+  *out = nullptr;
+  sl_status s = check_batch(b);
+  if (s != SL_OK) return s;
+  if (dim != 2 && dim != 3) return fail(SL_EINVAL, "dim = %d, expected 2 or 3", dim);
+  sl_batch_plan* p = new (std::nothrow) sl_batch_plan();
+  if (!p) return fail(SL_ENOMEM, "host allocation failed");
+  auto bail = [&](sl_status st) {
+    free_batch(p);
+    delete p;
+    return st;
+  };
+  p->ngraphs = b->num_graphs;
+  p->dim = dim;
+  p->n_total = b->num_graphs > 0 ? b->graph_ptr[b->num_graphs] : 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->ps, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_a);
+  if (e == hipSuccess) e = hipEventCreate(&p->ev_b);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_sync, hipEventDisableTiming);
+  if (e != hipSuccess) return bail(hip_fail(e, "batch plan setup"));
+  int64_t d_bytes = 0, w_total = 0;
+  p->hgraphs.resize(p->ngraphs);
+  for (int g = 0; g < p->ngraphs; ++g) {
+    BatchGraph& G = p->hgraphs[g];
+    G.n = (int32_t)(b->graph_ptr[g + 1] - b->graph_ptr[g]);
+    G.n_pad = std::max(kRowBlock, round_up(G.n, kRowBlock));
+    G.slices = default_slices(G.n_pad, p->threads);
+    G.pad = 0;
+    G.d_off = d_bytes;
+    G.v_off = b->graph_ptr[g];
+    G.w_off = w_total;
+    d_bytes += (int64_t)G.n_pad * G.n_pad;
+    w_total += G.n_pad;
+  }
+  p->horder.resize(p->ngraphs);
+  for (int g = 0; g < p->ngraphs; ++g) p->horder[g] = g;
+  std::stable_sort(p->horder.begin(), p->horder.end(),
+                   [&](int a, int c) { return p->hgraphs[a].n_pad > p->hgraphs[c].n_pad; });
+  p->hres.resize(p->ngraphs);
+  const size_t ng1 = std::max(1, p->ngraphs);
+  e = hipMalloc(&p->graphs, sizeof(BatchGraph) * ng1);
+  if (e == hipSuccess) e = hipMalloc(&p->order, sizeof(int32_t) * ng1);
+  if (e == hipSuccess) e = hipMalloc(&p->queue, sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&p->status, sizeof(int32_t) * ng1);
+  if (e == hipSuccess) e = hipMalloc(&p->d, std::max<int64_t>(d_bytes, 1));
+  if (e == hipSuccess) e = hipMalloc(&p->W, sizeof(double) * std::max<int64_t>(w_total, 1));
+  if (e == hipSuccess) e = hipMalloc(&p->res, sizeof(BatchResult) * ng1);
+  if (e != hipSuccess) return bail(hip_fail(e, "batch plan allocation"));
+  if (p->ngraphs == 0) {
+    *out = p;
+    return SL_OK;
+  }
+  int64_t* rp = nullptr;
+  int32_t* ci = nullptr;
+  e = hipMalloc(&rp, sizeof(int64_t) * (p->n_total + 1));
+  if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * std::max<int64_t>(b->nnz, 1));
+  if (e == hipSuccess) e = hipEventRecord(p->ev_sync, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->ps, p->ev_sync, 0);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_a, p->ps);
+  if (e == hipSuccess) e = hipMemsetAsync(p->d, 0, d_bytes, p->ps);
+  if (e == hipSuccess) e = hipMemsetAsync(p->status, 0, sizeof(int32_t) * p->ngraphs, p->ps);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(rp, b->row_ptr, sizeof(int64_t) * (p->n_total + 1), hipMemcpyHostToDevice, p->ps);
+  if (e == hipSuccess && b->nnz > 0)
+    e = hipMemcpyAsync(ci, b->col_idx, sizeof(int32_t) * b->nnz, hipMemcpyHostToDevice, p->ps);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->order, p->horder.data(), sizeof(int32_t) * p->ngraphs, hipMemcpyHostToDevice, p->ps);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->graphs, p->hgraphs.data(), sizeof(BatchGraph) * p->ngraphs, hipMemcpyHostToDevice, p->ps);
+  if (e == hipSuccess) e = launch_batch_reset(p->queue, p->ps);
+  if (e == hipSuccess)
+    e = launch_batch_distances(512, std::max(1, std::min(p->ngraphs, p->cus)), p->graphs, p->order, p->ngraphs,
+                               p->queue, rp, ci, p->d, p->W, p->status, p->ps);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_b, p->ps);
+  std::vector<int32_t> hstatus(p->ngraphs, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hstatus.data(), p->status, sizeof(int32_t) * p->ngraphs, hipMemcpyDeviceToHost, p->ps);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
+  (void)hipFree(rp);
+  (void)hipFree(ci);
+  if (e != hipSuccess) return bail(hip_fail(e, "batch distances"));
+  for (int g = 0; g < p->ngraphs; ++g)
+    if (hstatus[g] != 0) return bail(fail(SL_ERANGE, "graph %d has a distance above 255 hops", g));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+  p->plan_ms = ms;
+  *out = p;
+  return SL_OK;
+}
+
+sl_status sl_batch_plan_destroy(sl_batch_plan* p) {
+  g_err.clear();
+  if (!p) return SL_OK;
+  (void)hipStreamSynchronize(p->ps);
+  free_batch(p);
+  delete p;
+  return SL_OK;
+}
+
+sl_status sl_batch_plan_tune(sl_batch_plan* p, const float* X, const sl_options* o, void* stream, int32_t* config) {
+  g_err.clear();
+  if (!p) return fail(SL_EINVAL, "plan is NULL");
+  BatchParams bp{};
+  sl_status s = batch_params(p, o, &bp);
+  if (s != SL_OK) return s;
+  if (p->ngraphs == 0 || p->n_total == 0) return SL_OK;
+  if (!X) return fail(SL_EINVAL, "X is NULL");
+  bp.tol = 0.0;
+  bp.max_iter = std::max(1, std::min(o->max_iter, 8));
+  const size_t xbytes = sizeof(float) * (size_t)p->n_total * p->dim;
+  float* tmp = nullptr;
+  int32_t* sub = nullptr;
+  HIP_TRY(hipMalloc(&tmp, xbytes), "tuning buffer");
+  if (hipMalloc(&sub, sizeof(int32_t) * p->ngraphs) != hipSuccess) {
+    (void)hipFree(tmp);
+    return fail(SL_ENOMEM, "tuning buffer");
+  }
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(p->ps);
+    (void)hipFree(tmp);
+    (void)hipFree(sub);
+  };
+  auto timed = [&](const int32_t* order, int count, float* ms) -> sl_status {
+    HIP_TRY(hipMemcpyAsync(tmp, X, xbytes, hipMemcpyDeviceToDevice, p->ps), "tuning copy");
+    return batch_time(p, tmp, order, count, bp, ms);
+  };
+  if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) {
+    cleanup();
+    return s;
+  }
+  // 1. workgroup size, with the default slices for each
+  int best_t = p->threads;
+  float best_ms = 1e30f;
+  for (int t : {256, 512, 1024}) {
+    p->threads = t;
+    for (auto& G : p->hgraphs) G.slices = default_slices(G.n_pad, t);
+    if ((s = batch_upload_graphs(p)) != SL_OK) break;
+    float ms = 0.f;
+    if ((s = timed(p->order, p->ngraphs, &ms)) != SL_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_t = t;
+    }
+  }
+  if (s != SL_OK) {
+    cleanup();
+    return s;
+  }
+  p->threads = best_t;
+  for (auto& G : p->hgraphs) G.slices = default_slices(G.n_pad, best_t);
+  // 2. column slices per size class, timed on that class alone
+  int chosen[kBatchClasses] = {0};
+  for (int c = 0; c < kBatchClasses && s == SL_OK; ++c) {
+    const int n_pad = (c + 1) * kRowBlock;
+    std::vector<int32_t> members;
+    for (int g : p->horder)
+      if (p->hgraphs[g].n_pad == n_pad) members.push_back(g);
+    if (members.empty()) continue;
+    if ((s = hip_try_copy(sub, members.data(), sizeof(int32_t) * members.size(), p->ps)) != SL_OK) break;
+    int best_s = default_slices(n_pad, best_t);
+    float best = 1e30f;
+    for (int cand : {1, 2, 4, 8, 16}) {
+      if (!slices_ok(n_pad, cand)) continue;
+      for (int g : members) p->hgraphs[g].slices = cand;
+      if ((s = batch_upload_graphs(p)) != SL_OK) break;
+      float ms = 0.f;
+      if ((s = timed(sub, (int)members.size(), &ms)) != SL_OK) break;
+      if (ms < best) {
+        best = ms;
+        best_s = cand;
+      }
+    }
+    for (int g : members) p->hgraphs[g].slices = best_s;
+    chosen[c] = best_s;
+  }
+  if (s == SL_OK) s = batch_upload_graphs(p);
+  cleanup();
+  if (s != SL_OK) return s;
+  if (config) {
+    config[0] = p->threads;
+    for (int c = 0; c < kBatchClasses; ++c) config[1 + c] = chosen[c];
+  }
+  return join_to_stream(p->ps, p->ev_sync, (hipStream_t)stream);
+}
+
+sl_status sl_batch_plan_run(sl_batch_plan* p, float* X, const sl_options* o, void* stream, sl_result* per_graph,
+                            sl_result* total) {
+  g_err.clear();
+  if (!p) return fail(SL_EINVAL, "plan is NULL");
+  BatchParams bp{};
+  sl_status s = batch_params(p, o, &bp);
+  if (s != SL_OK) return s;
+  sl_result tot{};
+  tot.plan_ms = p->plan_ms;
+  tot.converged = 1;
+  if (p->ngraphs > 0 && p->n_total > 0) {
+    if (!X) return fail(SL_EINVAL, "X is NULL");
+    if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) return s;
+    std::vector<double> key = {(double)p->threads, bp.omega_p, bp.tol, (double)bp.max_iter, (double)bp.safeguard,
+                               (double)(uintptr_t)X};
+    if (!p->gexec || key != p->gkey) {
+      if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+      }
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      hipError_t le = launch_batch_reset(p->queue, p->ps);
+      if (le == hipSuccess)
+        le = launch_batch_layout(p->dim, p->threads, batch_blocks(p, p->ngraphs), p->graphs, p->order, p->ngraphs,
+                                 p->queue, p->d, p->W, X, p->res, bp, p->ps);
+      hipError_t ce = hipStreamEndCapture(p->ps, &graph);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le != hipSuccess ? le : ce, "batch graph capture");
+      }
+      hipError_t ie = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        p->gexec = nullptr;
+        return hip_fail(ie, "hipGraphInstantiate");
+      }
+      p->gkey = key;
+    }
+    HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+    HIP_TRY(hipGraphLaunch(p->gexec, p->ps), "hipGraphLaunch");
+    HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+    HIP_TRY(hipMemcpyAsync(p->hres.data(), p->res, sizeof(BatchResult) * p->ngraphs, hipMemcpyDeviceToHost, p->ps),
+            "batch results");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+    tot.run_ms = ms;
+    if ((s = join_to_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) return s;
+  }
+  int bad = -1;
+  for (int g = 0; g < p->ngraphs; ++g) {
+    const BatchResult& r = p->hres[g];
+    if (per_graph) {
+      sl_result& o2 = per_graph[g];
+      o2 = sl_result{};
+      o2.iterations = r.iterations;
+      o2.converged = r.converged;
+      o2.rejected = r.rejected;
+      o2.residual = r.residual;
+      o2.stress = r.stress;
+      o2.plan_ms = p->plan_ms;
+      o2.run_ms = tot.run_ms;
+    }
+    tot.iterations = std::max(tot.iterations, r.iterations);
+    tot.converged = tot.converged && r.converged;
+    tot.rejected += r.rejected;
+    tot.residual = std::max(tot.residual, r.residual);
+    if (r.status != 0 && bad < 0) bad = g;
+  }
+  if (total) *total = tot;
+  if (bad >= 0) return fail(SL_ENUMERIC, "graph %d: non-finite coordinate; its X holds the last finite iterate", bad);
+  return SL_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,389 @@
+// Batched layouts for gfx950: thousands of small graphs (n <= 1024) laid out
+// by one persistent launch.  Each workgroup takes the next graph from a queue
+// ordered largest first, keeps its iterates, weights and force partials in
+// LDS, and runs Algorithm 2 for that graph to its own termination test: the
+// same arithmetic as the single-graph kernels (force pass, Jacobi update and
+// extrapolation of eq. 11, safeguard of Alg. 2 lines 6-8, residual test), with
+// workgroup barriers in place of kernel boundaries.  Distances come from a
+// per-graph breadth-first search run the same way.
+#include "sl_device.h"
+
+namespace sl {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Distances and weights, one graph per workgroup.  256 sources per sweep, one
+// bit each in 4 words per vertex, frontiers in LDS; a thread per vertex pulls
+// its neighbours' frontier words (the batch graphs have small degrees) and
+// writes new levels into its own row of the tile-major distance block.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restrict__ graphs,
+                                                       const int32_t* __restrict__ order, int count,
+                                                       int32_t* __restrict__ queue, const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col_idx, uint8_t* __restrict__ d,
+                                                       double* __restrict__ Wg, int32_t* __restrict__ status) {
+  constexpr int kWords = 4;
+  __shared__ uint64_t fa[kBatchMaxN * kWords], fb[kBatchMaxN * kWords], vis[kBatchMaxN * kWords];
+  __shared__ double wl[256];
+  __shared__ int sh_q, sh_any;
+  const int tid = threadIdx.x;
+  for (int b = tid; b < 256; b += T) wl[b] = b ? 1.0 / ((double)b * (double)b) : 0.0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) sh_q = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = sh_q;
+    if (q >= count) break;
+    const int gid = order[q];
+    const BatchGraph G = graphs[gid];
+    const int n = G.n, ng = G.n_pad / kColGroup;
+    uint8_t* __restrict__ dg = d + G.d_off;
+    int err = 0;
+    for (int base = 0; base < n && !err; base += 64 * kWords) {
+      for (int v = tid; v < n; v += T) {
+#pragma unroll
+        for (int k = 0; k < kWords; ++k) {
+          const int s0 = base + 64 * k;
+          const uint64_t w = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
+          fa[v * kWords + k] = w;
+          vis[v * kWords + k] = w;
+        }
+      }
+      uint64_t* F = fa;
+      uint64_t* N = fb;
+      __syncthreads();
+      for (int level = 1;; ++level) {
+        if (tid == 0) sh_any = 0;
+        __syncthreads();
+        bool any = false;
+        const uint32_t lv = (uint32_t)level * 0x01010101u;
+        for (int v = tid; v < n; v += T) {
+          uint64_t acc[kWords] = {0, 0, 0, 0};
+          const int64_t e1 = row_ptr[G.v_off + v + 1];
+          for (int64_t e = row_ptr[G.v_off + v]; e < e1; ++e) {
+            const int u = (int)(col_idx[e] - G.v_off);
+#pragma unroll
+            for (int k = 0; k < kWords; ++k) acc[k] |= F[u * kWords + k];
+          }
+#pragma unroll
+          for (int k = 0; k < kWords; ++k) {
+            const uint64_t old = vis[v * kWords + k];
+            const uint64_t nw = acc[k] & ~old;
+            N[v * kWords + k] = nw;
+            if (nw == 0) continue;
+            any = true;
+            if (level > 255) continue;
+            vis[v * kWords + k] = old | nw;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const uint32_t bits = (uint32_t)(nw >> (16 * c)) & 0xffffu;
+              if (bits == 0) continue;
+              const int s0 = base + 64 * k + 16 * c;
+              uint4* chunk = reinterpret_cast<uint4*>(dg + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
+                                                      (size_t)(v % kRowBlock) * kColGroup);
+              uint4 w = *chunk;
+              w.x |= lv & byte_mask4(bits & 0xfu);
+              w.y |= lv & byte_mask4((bits >> 4) & 0xfu);
+              w.z |= lv & byte_mask4((bits >> 8) & 0xfu);
+              w.w |= lv & byte_mask4((bits >> 12) & 0xfu);
+              *chunk = w;
+            }
+          }
+        }
+        if (any) sh_any = 1;
+        __syncthreads();
+        const int a = sh_any;
+        if (!a) break;
+        if (level > 255) {
+          err = 1;
+          break;
+        }
+        uint64_t* tmp = F;
+        F = N;
+        N = tmp;
+      }
+      __syncthreads();
+    }
+    if (err && tid == 0) status[gid] = -4;
+    __syncthreads();
+    // W_i = sum_j d_ij^-2, columns in ascending order
+    for (int i = tid; i < G.n_pad; i += T) {
+      const uint4* row = reinterpret_cast<const uint4*>(dg + (size_t)(i / kRowBlock) * ng * kTileBytes) + (i % kRowBlock);
+      double s = 0.0;
+      for (int g = 0; g < ng; ++g) {
+        const uint4 qd = row[(size_t)g * 64];
+#pragma unroll
+        for (int k = 0; k < kColGroup; ++k) s += wl[byte_of(chunk_word(qd, k), k & 3)];
+      }
+      Wg[G.w_off + i] = (i < n) ? s : 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Layout, one graph per workgroup.  Work units of the all-pairs passes are
+// (row block rb, column slice s): wave w takes units w, w + NW, ...; lane l of
+// a unit owns row i = 64 rb + l and reads x_j as an LDS broadcast.
+// ---------------------------------------------------------------------------
+template <int DIM, int T>
+__global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict__ graphs,
+                                                    const int32_t* __restrict__ order, int count,
+                                                    int32_t* __restrict__ queue, const uint8_t* __restrict__ d,
+                                                    const double* __restrict__ Wg, float* __restrict__ X,
+                                                    BatchResult* __restrict__ res, BatchParams p) {
+  using V = typename VecT<DIM>::T;
+  constexpr int NW = T / 64;
+  __shared__ V xs[3][kBatchMaxN];
+  __shared__ V es[kBatchMaxN];
+  __shared__ double Ws[kBatchMaxN];
+  __shared__ double Fp[kBatchMaxPartial * DIM];
+  __shared__ float2 lut[256];
+  __shared__ double red[8][NW];
+  __shared__ double red_tot[8];
+  __shared__ float lut1[256];
+  __shared__ int sh_q;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  fill_weight_table<false>(lut);
+  for (int b = tid; b < 256; b += T) lut1[b] = b ? 1.0f / (float)b : 0.f;
+  const bool sg = p.safeguard && p.omega_p != 0.0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) sh_q = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = sh_q;
+    if (q >= count) break;
+    const int gid = order[q];
+    const BatchGraph G = graphs[gid];
+    const int n = G.n, n_pad = G.n_pad, nrb = n_pad / kRowBlock, ng = n_pad / kColGroup;
+    const int S = G.slices, gps = (ng + S - 1) / S, units = nrb * S;
+    const uint8_t* __restrict__ dg = d + G.d_off;
+    for (int i = tid; i < n_pad; i += T) {
+      V x;
+      if constexpr (DIM == 2) {
+        x = make_float2(0.f, 0.f);
+        if (i < n) x = make_float2(X[(G.v_off + i) * 2], X[(G.v_off + i) * 2 + 1]);
+      } else {
+        x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < n) x = make_float4(X[(G.v_off + i) * 3], X[(G.v_off + i) * 3 + 1], X[(G.v_off + i) * 3 + 2], 0.f);
+      }
+      xs[0][i] = x;
+      xs[1][i] = x;
+      xs[2][i] = x;
+      es[i] = V{};
+      Ws[i] = (i < n) ? Wg[G.w_off + i] : 0.0;
+    }
+    __syncthreads();
+    int cur = 0, it = 0, rejected = 0, converged = n <= 1 ? 1 : 0, status = 0;
+    double resid = 0.0;
+    while (it < p.max_iter && !converged && n > 1) {
+      // ---- force pass at X^k: F_i = sum_j w (d - r) u_ij
+      for (int u = wave; u < units; u += NW) {
+        const int rb = u % nrb, s = u / nrb;
+        const int g0 = s * gps, g1 = min(g0 + gps, ng);
+        const int i = rb * kRowBlock + lane;
+        const V xi = xs[cur][i];
+        const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(dg + (size_t)rb * ng * kTileBytes) + lane;
+        double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+        for (int g = g0; g < g1; ++g) {
+          const uint4 qd = tile[(size_t)g * 64];
+          float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+          for (int k = 0; k < kColGroup; ++k) {
+            const float2 wt = lut[byte_of(chunk_word(qd, k), k & 3)];
+            const V pj = xs[cur][g * kColGroup + k];
+            const float dx = xi.x - pj.x, dy = xi.y - pj.y;
+            float r2 = fmaf(dx, dx, kTiny);
+            r2 = fmaf(dy, dy, r2);
+            float dz = 0.f;
+            if constexpr (DIM == 3) {
+              dz = xi.z - pj.z;
+              r2 = fmaf(dz, dz, r2);
+            }
+            const float c = fmaf(wt.x, __builtin_amdgcn_rsqf(r2), -wt.y);
+            a0 = fmaf(c, dx, a0);
+            a1 = fmaf(c, dy, a1);
+            if constexpr (DIM == 3) a2 = fmaf(c, dz, a2);
+            // keep the scheduler from hoisting all 16 LDS reads (VGPR pressure)
+            if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+          F0 += (double)a0;
+          F1 += (double)a1;
+          if constexpr (DIM == 3) F2 += (double)a2;
+        }
+        double* fp = Fp + ((size_t)s * n_pad + i) * DIM;
+        fp[0] = F0;
+        fp[1] = F1;
+        if constexpr (DIM == 3) fp[2] = F2;
+      }
+      __syncthreads();
+      // ---- Jacobi update x^H = x + F / W and extrapolation (eq. 11)
+      const int h = (cur + 1) % 3, t = (cur + 2) % 3;
+      double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int i = tid; i < n; i += T) {
+        double F[3] = {0.0, 0.0, 0.0};
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) F[c] += Fp[((size_t)s * n_pad + i) * DIM + c];
+        const V x = xs[cur][i];
+        const double Wi = Ws[i];
+        float xv[3] = {x.x, x.y, 0.f};
+        if constexpr (DIM == 3) xv[2] = x.z;
+        float xh[3] = {0.f, 0.f, 0.f}, xt[3] = {0.f, 0.f, 0.f};
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          xh[c] = (Wi > 0.0) ? (float)((double)xv[c] + F[c] / Wi) : xv[c];
+          const double dl = (double)xh[c] - (double)xv[c];
+          xt[c] = (float)((double)xh[c] + p.omega_p * dl);
+          v[0] += dl * dl;
+          v[1] += (double)xh[c] * (double)xh[c];
+          v[2 + c] += (double)xh[c];
+          bad = bad || !isfinite(xh[c]) || !isfinite(xt[c]);
+        }
+        if constexpr (DIM == 2) {
+          xs[h][i] = make_float2(xh[0], xh[1]);
+          xs[t][i] = make_float2(xt[0], xt[1]);
+          es[i] = make_float2(xt[0] - xh[0], xt[1] - xh[1]);
+        } else {
+          xs[h][i] = make_float4(xh[0], xh[1], xh[2], 0.f);
+          xs[t][i] = make_float4(xt[0], xt[1], xt[2], 0.f);
+          es[i] = make_float4(xt[0] - xh[0], xt[1] - xh[1], xt[2] - xh[2], 0.f);
+        }
+        if (bad) v[6] += 1.0;
+      }
+      block_sum_waves<8, NW>(v, red, red_tot);
+      // ---- safeguard: f(X~) - f(X^H) over the upper triangle
+      double df = 0.0;
+      if (sg) {
+        double acc = 0.0;
+        for (int u = wave; u < units; u += NW) {
+          const int rb = u % nrb, s = u / nrb;
+          const int gdiag = rb * (kRowBlock / kColGroup), gfree = gdiag + kRowBlock / kColGroup;
+          const int g0 = max(s * gps, gdiag), g1 = min(s * gps + gps, ng);
+          const int i = rb * kRowBlock + lane;
+          const V hi = xs[h][i], ei = es[i];
+          const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(dg + (size_t)rb * ng * kTileBytes) + lane;
+          for (int g = g0; g < g1; ++g) {
+            const uint4 qd = tile[(size_t)g * 64];
+            const int jrel = (g < gfree) ? i - g * kColGroup : -1;  // mask k <= jrel in the diagonal block
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < kColGroup; ++k) {
+              const float inv = lut1[byte_of(chunk_word(qd, k), k & 3)];
+              const V ph = xs[h][g * kColGroup + k], pe = es[g * kColGroup + k];
+              const float hx = hi.x - ph.x, hy = hi.y - ph.y;
+              const float ex = ei.x - pe.x, ey = ei.y - pe.y;
+              float rh2 = fmaf(hx, hx, kTiny);
+              rh2 = fmaf(hy, hy, rh2);
+              float m = ex * fmaf(2.f, hx, ex);
+              m = fmaf(ey, fmaf(2.f, hy, ey), m);
+              if constexpr (DIM == 3) {
+                const float hz = hi.z - ph.z, ez = ei.z - pe.z;
+                rh2 = fmaf(hz, hz, rh2);
+                m = fmaf(ez, fmaf(2.f, hz, ez), m);
+              }
+              const float rt2 = fabsf(rh2 + m);
+              const float sum = fmaf(rh2, __builtin_amdgcn_rsqf(rh2), rt2 * __builtin_amdgcn_rsqf(rt2));
+              float mi = m * inv;
+              if (k <= jrel) mi = 0.f;
+              a = fmaf(mi, fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv), a);
+              if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            acc += (double)a;
+          }
+        }
+        double vv[1] = {acc};
+        block_sum_waves<1, NW>(vv, red, red_tot);
+        df = vv[0];
+      }
+      // ---- decision and termination test (every thread holds the same sums)
+      if (__builtin_amdgcn_readfirstlane(v[6] > 0.0 ? 1 : 0)) {
+        status = -5;
+        break;
+      }
+      const double mean2 = (v[2] * v[2] + v[3] * v[3] + (DIM == 3 ? v[4] * v[4] : 0.0)) / (double)n;
+      const double den2 = v[1] - mean2;
+      const double r = v[0] > 0.0 ? sqrt(v[0]) / sqrt(den2 > 0.0 ? den2 : 0.0) : 0.0;
+      if (p.omega_p == 0.0) {
+        cur = h;
+      } else if (p.safeguard) {
+        const bool take = df <= 0.0;
+        cur = take ? t : h;
+        if (!take) ++rejected;
+      } else {
+        cur = t;
+      }
+      ++it;
+      resid = r;
+      if (r <= p.tol) converged = 1;
+      // every thread computed the same decision from the same block sums
+      cur = __builtin_amdgcn_readfirstlane(cur);
+      converged = __builtin_amdgcn_readfirstlane(converged);
+      rejected = __builtin_amdgcn_readfirstlane(rejected);
+    }
+    for (int i = tid; i < n; i += T) {
+      const V x = xs[cur][i];
+      X[(G.v_off + i) * DIM] = x.x;
+      X[(G.v_off + i) * DIM + 1] = x.y;
+      if constexpr (DIM == 3) X[(G.v_off + i) * DIM + 2] = x.z;
+    }
+    if (tid == 0) {
+      BatchResult br;
+      br.iterations = it;
+      br.converged = converged;
+      br.rejected = rejected;
+      br.status = status;
+      br.residual = resid;
+      br.stress = 0.0;
+      res[gid] = br;
+    }
+  }
+}
+
+__global__ void k_batch_reset(int32_t* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+}
+
+}  // namespace
+
+bool batch_threads_supported(int threads) { return threads == 256 || threads == 512 || threads == 1024; }
+
+hipError_t launch_batch_reset(int32_t* queue, hipStream_t s) {
+  k_batch_reset<<<1, 64, 0, s>>>(queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_distances(int threads, int blocks, const BatchGraph* graphs, const int32_t* order, int count,
+                                  int32_t* queue, const int64_t* row_ptr, const int32_t* col_idx, uint8_t* d,
+                                  double* W, int32_t* status, hipStream_t s) {
+  if (threads == 1024)
+    k_batch_distances<1024><<<blocks, 1024, 0, s>>>(graphs, order, count, queue, row_ptr, col_idx, d, W, status);
+  else if (threads == 512)
+    k_batch_distances<512><<<blocks, 512, 0, s>>>(graphs, order, count, queue, row_ptr, col_idx, d, W, status);
+  else
+    k_batch_distances<256><<<blocks, 256, 0, s>>>(graphs, order, count, queue, row_ptr, col_idx, d, W, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_layout(int dim, int threads, int blocks, const BatchGraph* graphs, const int32_t* order,
+                               int count, int32_t* queue, const uint8_t* d, const double* W, float* X,
+                               BatchResult* res, const BatchParams& p, hipStream_t s) {
+#define SL_BATCH_LAUNCH(DD, TT) \
+  k_batch_layout<DD, TT><<<blocks, TT, 0, s>>>(graphs, order, count, queue, d, W, X, res, p)
+  if (dim == 2) {
+    if (threads == 1024) SL_BATCH_LAUNCH(2, 1024);
+    else if (threads == 512) SL_BATCH_LAUNCH(2, 512);
+    else SL_BATCH_LAUNCH(2, 256);
+  } else {
+    if (threads == 1024) SL_BATCH_LAUNCH(3, 1024);
+    else if (threads == 512) SL_BATCH_LAUNCH(3, 512);
+    else SL_BATCH_LAUNCH(3, 256);
+  }
+#undef SL_BATCH_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace sl

@@ -101,4 +101,41 @@ hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevStat
 hipError_t launch_gather_rows(const uint8_t* d, const int32_t* rows, int nrows, int n, int ng, uint8_t* out,
                               hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Batched layouts: many independent graphs of at most kBatchMaxN vertices.
+// One persistent kernel: each workgroup takes the next graph from a queue
+// (largest first) and runs its whole layout with the iterates in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kBatchMaxN = 1024;
+constexpr int kBatchMaxPartial = 2048;  // bound on slices * n_pad of one graph
+constexpr int kBatchClasses = kBatchMaxN / kRowBlock;  // size classes n_pad = 64, 128, ..., 1024
+
+struct BatchGraph {
+  int32_t n, n_pad;
+  int32_t slices;   // column slices of the all-pairs passes (tuned per size class)
+  int32_t pad;
+  int64_t d_off;    // byte offset of the graph's tile-major distance block
+  int64_t v_off;    // first vertex of the graph in the concatenated arrays
+  int64_t w_off;    // first entry of its n_pad weight sums
+};
+
+struct BatchResult {
+  int32_t iterations, converged, rejected, status;
+  double residual, stress;
+};
+
+struct BatchParams {
+  double omega_p, tol;
+  int32_t max_iter, safeguard;
+};
+
+hipError_t launch_batch_reset(int32_t* queue, hipStream_t s);
+hipError_t launch_batch_distances(int threads, int blocks, const BatchGraph* graphs, const int32_t* order, int count,
+                                  int32_t* queue, const int64_t* row_ptr, const int32_t* col_idx, uint8_t* d,
+                                  double* W, int32_t* status, hipStream_t s);
+hipError_t launch_batch_layout(int dim, int threads, int blocks, const BatchGraph* graphs, const int32_t* order,
+                               int count, int32_t* queue, const uint8_t* d, const double* W, float* X,
+                               BatchResult* res, const BatchParams& p, hipStream_t s);
+bool batch_threads_supported(int threads);
+
 }  // namespace sl

@@ -17,7 +17,7 @@
 //
 // Every cross-thread sum is taken in a fixed order (per-lane sequences, fixed
 // trees, fixed slice order), so results are bitwise repeatable run to run.
-#include "sl_internal.h"
+#include "sl_device.h"
 
 #include <algorithm>
 #include <cmath>
@@ -26,63 +26,6 @@
 namespace sl {
 
 namespace {
-
-template <int DIM> struct VecT;
-template <> struct VecT<2> { using T = float2; };
-template <> struct VecT<3> { using T = float4; };
-
-// Added to r^2 so that rsq never sees 0: for coincident vertices (or i = j)
-// the pair term is c * (x_i - x_j) = c * 0 = 0 with c finite.
-constexpr float kTiny = 1e-30f;
-
-__device__ __forceinline__ uint32_t chunk_word(const uint4& q, int k) {
-  return (k < 4) ? q.x : (k < 8) ? q.y : (k < 12) ? q.z : q.w;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Deterministic tree sum of K doubles over a 256-thread block.  Thread 0 gets
-// the totals in v.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double (*sh)[256]) {
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < K; ++k) sh[k][t] = v[k];
-  __syncthreads();
-  for (int s = 128; s >= 1; s >>= 1) {
-    if (t < s) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) sh[k][t] += sh[k][t + s];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = sh[k][0];
-  }
-}
-
-// Per-block table of the weights a distance byte stands for, built in LDS at
-// kernel start: entry b holds 1/b and 1/b^2 (correctly rounded), and 1 in .z
-// for the stress terms; entry 0 (same vertex, no path, padding) is all zero.
-template <bool STRESS> struct WeightEntry { using T = float2; };
-template <> struct WeightEntry<true> { using T = float4; };
-
-template <bool STRESS>
-__device__ __forceinline__ void fill_weight_table(typename WeightEntry<STRESS>::T* lut) {
-  const int b = threadIdx.x;  // blockDim.x == 256 == number of entries
-  const float fb = (float)b;
-  const float inv = b ? 1.0f / fb : 0.f;
-  const float w = b ? 1.0f / (fb * fb) : 0.f;
-  if constexpr (STRESS) lut[b] = make_float4(inv, w, b ? 1.f : 0.f, 0.f);
-  else lut[b] = make_float2(inv, w);
-}
-
-__device__ __forceinline__ uint32_t byte_of(uint32_t word, int b) { return (word >> (8 * b)) & 0xffu; }
 
 // ---------------------------------------------------------------------------
 // All-pairs force pass.  One wave per (row block, column slice): lane l owns
@@ -483,11 +426,6 @@ __global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ 
     }
     if (head && f) atomicOr(&acc[(size_t)v * kBfsWords + k], f);
   }
-}
-
-__device__ __forceinline__ uint32_t byte_mask4(uint32_t nib) {
-  return ((nib & 1u) ? 0x000000ffu : 0u) | ((nib & 2u) ? 0x0000ff00u : 0u) | ((nib & 4u) ? 0x00ff0000u : 0u) |
-         ((nib & 8u) ? 0xff000000u : 0u);
 }
 
 __global__ __launch_bounds__(256) void k_bfs_update(uint64_t* __restrict__ acc, uint64_t* __restrict__ visited,

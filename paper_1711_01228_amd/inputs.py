@@ -217,3 +217,58 @@ def ba65536(dim: int = 2, run: int = 0, n: int = 65536):
     s = workload_seed(3, run)
     g = barabasi_albert(n, 3, s)
     return g, uniform_positions(g.n, dim, s + 500 + dim)
+
+
+def near_square_grid(n: int) -> Graph:
+    """The rows x cols lattice with rows = floor(sqrt(n)), cols = n // rows."""
+    rows = max(1, int(np.floor(np.sqrt(n))))
+    return grid_graph(rows, max(1, n // rows))
+
+
+def largest_component(g: Graph) -> Graph:
+    """The largest connected component of g, vertices renumbered in order."""
+    label = -np.ones(g.n, dtype=np.int64)
+    best, best_size = -1, 0
+    for s in range(g.n):
+        if label[s] >= 0:
+            continue
+        stack, label[s], size = [s], s, 0
+        while stack:
+            u = stack.pop()
+            size += 1
+            for v in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+                if label[v] < 0:
+                    label[v] = s
+                    stack.append(int(v))
+        if size > best_size:
+            best, best_size = s, size
+    keep = np.flatnonzero(label == best)
+    new_id = -np.ones(g.n, dtype=np.int64)
+    new_id[keep] = np.arange(len(keep))
+    e = g.edges()
+    e = e[(new_id[e[:, 0]] >= 0) & (new_id[e[:, 1]] >= 0)]
+    return to_csr(len(keep), new_id[e], name=g.name + "-lcc")
+
+
+def batch_of_graphs(count: int = 2048, n_lo: int = 16, n_hi: int = 1024, seed: int = 4000, dim: int = 2):
+    """Many small graphs: n uniform in [n_lo, n_hi], family cycling through
+    near-square grids, uniform random trees and the largest component of
+    G(n, 2n) (mean degree 4), each with its own start uniform on [0,1]^dim.
+    Returns (graphs, X0 list).  (A two-vertex component would make the
+    one-sweep Jacobi step oscillate, r -> 2d - r, for ever.)"""
+    rng = rng_for(seed)
+    ns = rng.integers(n_lo, n_hi + 1, size=count)
+    fam = rng.integers(0, 3, size=count)
+    graphs, starts = [], []
+    for k in range(count):
+        n = int(ns[k])
+        s = seed * 10 + k
+        if fam[k] == 0:
+            g = near_square_grid(n)
+        elif fam[k] == 1:
+            g = random_tree(n, s)
+        else:
+            g = largest_component(erdos_renyi(n, min(2 * n, n * (n - 1) // 2), s))
+        graphs.append(g)
+        starts.append(uniform_positions(g.n, dim, s + 7))
+    return graphs, starts
