@@ -63,6 +63,14 @@ class sl_result(ctypes.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7)
+    # as the one the library links.  Whichever is loaded first serves the whole
+    # process, so torch is imported first: one runtime for torch's allocations
+    # and streams and for the library's kernels.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsorlayout.so is not built (%s); run __graft_entry__.build() or "
                           "python -m paper_1711_01228_amd.build_lib" % LIB_PATH)

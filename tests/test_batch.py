@@ -78,10 +78,13 @@ def _split(X, plan):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("omega,safeguard", [(1.0, True), (1.5, True), (3.0, True), (1.3, False)])
+@pytest.mark.parametrize("omega,safeguard", [(1.0, True), (1.5, True), (2.5, True), (3.0, True), (1.3, False)])
 def test_batch_fixed_iterations_match_oracle(omega, safeguard):
     gs, xs = small_batch()
-    iters = 30
+    # long strides (omega >= 2) make the trajectory sensitive to rounding (the
+    # oracle itself drifts by ~1e-4 diam within 30 steps from a 1-ulp change of
+    # its start), so those runs are compared over their first 10 steps
+    iters = 30 if omega < 2.0 else 10
     X = _dev(xs)
     with b.BatchPlan(gs, 2) as plan:
         tot, per = plan.run(X, omega=omega, tol=0.0, max_iter=iters, safeguard=safeguard)
@@ -96,15 +99,23 @@ def test_batch_fixed_iterations_match_oracle(omega, safeguard):
             continue
         assert per[k]["iterations"] == io["iterations"]
         tr = io["trace"]
-        ambiguous = np.any((tr[:, 1] >= 0) & (np.abs(tr[:, 2]) <= AMBIG * tr[:, 3]))
+        ambiguous = safeguard and np.any((tr[:, 1] >= 0) & (np.abs(tr[:, 2]) <= AMBIG * tr[:, 3]))
         if ambiguous:
             continue
         assert per[k]["rejected"] == io["rejected"], k
         diam = float(np.linalg.norm(Xo.max(0) - Xo.min(0)))
         if g.n == 2 and omega == 1.0:
             diam = 1.0  # the two-vertex Jacobi step oscillates; compare absolutely
+        tol = 1e-4 * max(diam, 1e-12)
+        # unstable runs (long strides; a two-vertex component without the
+        # safeguard: r -> 2.6 - 1.6 r at omega = 1.3) amplify rounding: allow 4x
+        # the drift the oracle itself shows from a start perturbed by one ulp
+        xp = x0 * (1.0 + 2.0 ** -24 * np.random.default_rng(k).standard_normal(x0.shape))
+        Xp, ip = oracle.layout(D, xp, omega=omega, tol=0.0, max_iter=iters, safeguard=safeguard)
+        if np.array_equal(ip["trace"][:, 1], tr[:, 1]):
+            tol = max(tol, 4.0 * np.abs(Xp - Xo).max())
         err = np.abs(out[k] - Xo).max()
-        assert err <= 1e-4 * max(diam, 1e-12), (k, err, diam)
+        assert err <= tol, (k, err, diam, tol)
         checked += 1
     assert checked >= 8
 
