@@ -58,9 +58,19 @@ typedef enum {
  *   [1] accepted                   1 / 0 for the safeguard decision, -1 when no
  *                                  extrapolation is formed (omega == 1)
  *   [2] f(X~) - f(X^H)             summed pair by pair (0 when not evaluated)
- *   [3] reserved                   0
+ *   [3] paper's factor used        omega - 1 of this iteration (NaN with per-vertex
+ *                                  factors)
  *   [4] f(X^k)                     stress at the iterate the step starts from
  *                                  (NaN unless SL_FLAG_TRACE_STRESS)                */
+
+/* Relaxation strategies (Sec. 5.2; per-vertex factors: Sec. 6, item 1). */
+#define SL_OMEGA_FIXED 0     /* `omega` every iteration                                  */
+#define SL_OMEGA_SCHEDULE 1  /* omega_schedule[k] at iteration k (the probabilistic
+                                strategy draws this sequence by roulette; the draws are
+                                the caller's input)                                       */
+#define SL_OMEGA_ENUM 2      /* the paper's factor c = omega - 1 chosen each iteration as
+                                the argmin of f(X^H + c (X^H - X^k)) over
+                                c in {0, 0.5, ..., 9}; c = 0 keeps X^H (counted rejected) */
 
 #define SL_FLAG_TRACE_STRESS 1u  /* evaluate f(X^k) every iteration into trace[4]  */
 #define SL_FLAG_NO_GRAPH 2u      /* launch kernels one by one instead of replaying a
@@ -92,6 +102,13 @@ typedef struct {
                                doubles, row k written by iteration k               */
   float* xtrace;            /* NULL or device buffer of max_iter * n * dim floats:
                                the placement after every iteration                  */
+  int32_t strategy;         /* SL_OMEGA_FIXED (default), SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM */
+  int32_t reserved2;
+  const double* omega_schedule; /* host, max_iter classical factors in (0, 16]
+                                   (SL_OMEGA_SCHEDULE), else NULL                  */
+  const float* omega_vertex;    /* NULL, or device, n classical factors in (0, 16]: vertex i
+                                   extrapolates by omega_vertex[i] - 1 (SL_OMEGA_FIXED only;
+                                   `omega` is then unused)                           */
 } sl_options;
 
 typedef struct {
@@ -199,8 +216,8 @@ sl_status sl_batch_plan_tune(sl_batch_plan* plan, const float* X, const sl_optio
                              int32_t* config);
 
 /* Lay out every graph from the concatenated device placement X
- * (graph_ptr[num_graphs] x dim floats, row-major) in place.  opt->trace and
- * opt->xtrace must be NULL.  per_graph (host, num_graphs entries) and total may
+ * (graph_ptr[num_graphs] x dim floats, row-major) in place.  opt->trace,
+ * opt->xtrace and opt->omega_vertex must be NULL and the strategy fixed.  per_graph (host, num_graphs entries) and total may
  * be NULL; total holds the largest iteration count and residual, converged = 1
  * iff every graph converged, the sum of rejections, and run_ms. */
 sl_status sl_batch_plan_run(sl_batch_plan* plan, float* X, const sl_options* opt, void* stream, sl_result* per_graph,

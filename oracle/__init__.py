@@ -35,7 +35,7 @@ _lib = None
 
 JACOBI, EXACT, GAUSS_SEIDEL = 0, 1, 2
 _ORDERINGS = {"jacobi": JACOBI, "exact": EXACT, "gauss_seidel": GAUSS_SEIDEL, "gs": GAUSS_SEIDEL}
-TRACE_COLS = 5
+TRACE_COLS = 8
 
 
 def build(force: bool = False) -> str:
@@ -80,7 +80,7 @@ def _load():
                 "slo_exact_free": (None, [P]),
                 "slo_h_exact": (ctypes.c_int, [P, i32, P, P, P]),
                 "slo_residual": (f64, [i32, i32, P, P]),
-                "slo_layout": (ctypes.c_int, [i32, i32, P, P, f64, f64, i32, i32, i32, i32, P, P,
+                "slo_layout": (ctypes.c_int, [i32, i32, P, P, f64, f64, i32, i32, i32, i32, P, P, i32, P, P,
                                               ctypes.POINTER(_Result)]),
             }
             for name, (res, args) in sig.items():
@@ -238,13 +238,20 @@ def residual(X, XH) -> float:
 # Algorithm 2 driver
 # --------------------------------------------------------------------------
 def layout(D, X0, omega=1.0, tol=1e-3, max_iter=200, ordering="jacobi", safeguard=True,
-           trace_stress=False, trace_positions=False):
+           trace_stress=False, trace_positions=False, omega_schedule=None, omega_vertex=None,
+           enumerate=False):
     """Run Algorithm 2 (Algorithm 1 at omega = 1) from X0.
+
+    Relaxation strategies (Sec. 5.2): a fixed ``omega``; ``omega_schedule``
+    (one classical factor per iteration, e.g. drawn by the roulette of the
+    probabilistic strategy); ``enumerate`` (argmin over the paper's candidates
+    0, 0.5, ..., 9); ``omega_vertex`` (one classical factor per vertex).
 
     Returns ``(X, info)``; ``info`` holds iterations, converged, rejected,
     residual, the per-iteration ``trace`` (columns: residual, accepted,
-    f(X~) - f(X^H), its term scale, f(X^k)) and, when asked, ``positions``
-    (placement after every iteration).
+    f(X~) - f(X^H), its term scale, f(X^k), paper's factor used, enumerating
+    gap and its scale) and, when asked, ``positions`` (placement after every
+    iteration).
     """
     lib = _load()
     D = _f64(D)
@@ -254,9 +261,15 @@ def layout(D, X0, omega=1.0, tol=1e-3, max_iter=200, ordering="jacobi", safeguar
     trace = np.full((max(max_iter, 1), TRACE_COLS), np.nan)
     xtrace = np.empty((max(max_iter, 1), n, dim)) if trace_positions else None
     res = _Result()
+    sched = None if omega_schedule is None else _f64(omega_schedule)
+    if sched is not None and len(sched) < max_iter:
+        raise ValueError("omega_schedule needs max_iter entries")
+    vert = None if omega_vertex is None else _f64(omega_vertex)
+    if vert is not None and len(vert) != n:
+        raise ValueError("omega_vertex needs n entries")
     st = lib.slo_layout(n, dim, _p(D), _p(X), float(omega), float(tol), int(max_iter), order,
-                        int(bool(safeguard)), int(bool(trace_stress)), _p(trace), _p(xtrace),
-                        ctypes.byref(res))
+                        int(bool(safeguard)), int(bool(trace_stress)), _p(sched), _p(vert), int(bool(enumerate)),
+                        _p(trace), _p(xtrace), ctypes.byref(res))
     _check(st, "layout")
     k = res.iterations
     info = {"iterations": k, "converged": bool(res.converged), "rejected": res.rejected,
@@ -264,3 +277,10 @@ def layout(D, X0, omega=1.0, tol=1e-3, max_iter=200, ordering="jacobi", safeguar
     if trace_positions:
         info["positions"] = xtrace[:k].copy()
     return X, info
+
+
+# Probabilistic strategy (Sec. 5.2): roulette over the paper's factors
+# 0.5, 1.0, 1.5, 2.0 with probabilities 0.3, 0.3, 0.2, 0.2.
+AUTO_FACTORS = (0.5, 1.0, 1.5, 2.0)
+AUTO_PROBS = (0.3, 0.3, 0.2, 0.2)
+ENUM_FACTORS = tuple(0.5 * c for c in range(19))

@@ -505,6 +505,14 @@ double slo_residual(int32_t n, int32_t dim, const double* X, const double* XH) {
 /* omega is the classical relaxation factor: the paper's factor is          */
 /* omega - 1, so the extrapolation of eq. 11 reads                          */
 /*   X~ = X^H + (omega - 1)(X^H - X).                                       */
+/* Relaxation strategies of Sec. 5.2:                                        */
+/*   fixed           one omega for every iteration                          */
+/*   schedule        omega_schedule[k] at iteration k (the probabilistic     */
+/*                   strategy draws this sequence by roulette; the draws are */
+/*                   an input here)                                          */
+/*   enumerating     the paper's factor chosen each iteration as the argmin  */
+/*                   of f(X^H + c (X^H - X)) over c in {0, 0.5, ..., 9}       */
+/*   per vertex      x~_i = x^H_i + (omega_i - 1)(x^H_i - x_i) (Sec. 6, (1)) */
 /* ---------------------------------------------------------------------- */
 typedef struct {
   int32_t iterations;
@@ -516,17 +524,22 @@ typedef struct {
 
 /* trace (optional): max_iter rows of SLO_TRACE_COLS doubles:
  *   [0] res_k   [1] accepted (1/0; -1 when no extrapolation is formed)
- *   [2] f(X~) - f(X^H)   [3] scale of that sum   [4] f(X^k) (NAN unless trace_stress)
+ *   [2] f(X~) - f(X^H) of the placement considered   [3] scale of that sum
+ *   [4] f(X^k) (NAN unless trace_stress)
+ *   [5] the paper's relaxation factor used (omega - 1; NAN for per-vertex)
+ *   [6] enumerating: smallest |f-difference| between the best candidate and
+ *       any other one   [7] enumerating: the larger term scale of that pair
  * xtrace (optional): max_iter placements X^{k+1}, n*dim each. */
-#define SLO_TRACE_COLS 5
+#define SLO_TRACE_COLS 8
+#define SLO_ENUM_CANDIDATES 19
 
 int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega, double tol,
                int32_t max_iter, int32_t ordering, int32_t safeguard, int32_t trace_stress,
+               const double* omega_schedule, const double* omega_vertex, int32_t enumerate,
                double* trace, double* xtrace, slo_result* out) {
   memset(out, 0, sizeof(*out));
   if (n < 0 || dim < 1 || !(omega > 0.0) || !(tol >= 0.0) || max_iter < 0) return SLO_EINVAL;
   if (ordering != SLO_JACOBI && ordering != SLO_EXACT && ordering != SLO_GAUSS_SEIDEL) return SLO_EINVAL;
-  const double omega_p = omega - 1.0;
   size_t nd = (size_t)n * dim;
   double* XH = (double*)malloc(sizeof(double) * (nd ? nd : 1));
   double* XT = (double*)malloc(sizeof(double) * (nd ? nd : 1));
@@ -549,21 +562,68 @@ int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega,
       if (!isfinite(XH[q])) status = SLO_ENUMERIC;
     if (status != SLO_OK) break;
     double res = slo_residual(n, dim, X, XH);
-    double accepted = -1.0, df = 0.0, scale = 0.0;
-    if (omega_p == 0.0) {
-      memcpy(X, XH, sizeof(double) * nd);
-    } else {
-      /* line 5 (eq. 11): X~ = X^H + omega_p (X^H - X^k) */
-      for (size_t q = 0; q < nd; ++q) XT[q] = XH[q] + omega_p * (XH[q] - X[q]);
-      int take = 1;
-      if (safeguard) {
-        /* line 6: keep X~ only if f(X~) <= f(X^H) */
-        slo_stress_delta(n, dim, D, XT, XH, &df, &scale);
-        take = (df <= 0.0);
+    double accepted = -1.0, df = 0.0, scale = 0.0, used = NAN, gap = NAN, gscale = NAN;
+    if (enumerate) {
+      /* Sec. 5.2, enumerating strategy: c = 0 is X^H itself (difference 0) */
+      double best_df = 0.0, best_scale = 0.0, best_c = 0.0;
+      double dfs[SLO_ENUM_CANDIDATES], scs[SLO_ENUM_CANDIDATES];
+      dfs[0] = 0.0;
+      scs[0] = 0.0;
+      for (int c = 1; c < SLO_ENUM_CANDIDATES; ++c) {
+        const double wc = 0.5 * c;
+        for (size_t q = 0; q < nd; ++q) XT[q] = XH[q] + wc * (XH[q] - X[q]);
+        slo_stress_delta(n, dim, D, XT, XH, &dfs[c], &scs[c]);
+        if (dfs[c] < best_df) {
+          best_df = dfs[c];
+          best_scale = scs[c];
+          best_c = wc;
+        }
       }
-      accepted = take ? 1.0 : 0.0;
-      if (!take) out->rejected += 1;
-      memcpy(X, take ? XT : XH, sizeof(double) * nd);
+      gap = INFINITY;
+      gscale = 0.0;
+      for (int c = 0; c < SLO_ENUM_CANDIDATES; ++c) {
+        if (0.5 * c == best_c) continue;
+        const double gp = fabs(dfs[c] - best_df);
+        if (gp < gap) {
+          gap = gp;
+          gscale = fmax(scs[c], best_scale);
+        }
+      }
+      df = best_df;
+      scale = best_scale;
+      used = best_c;
+      accepted = best_c > 0.0 ? 1.0 : 0.0;
+      if (best_c == 0.0) {
+        out->rejected += 1;
+        memcpy(X, XH, sizeof(double) * nd);
+      } else {
+        for (size_t q = 0; q < nd; ++q) X[q] = XH[q] + best_c * (XH[q] - X[q]);
+      }
+    } else {
+      const double omega_k = omega_schedule ? omega_schedule[k] : omega;
+      const double omega_p = omega_k - 1.0;
+      used = omega_vertex ? NAN : omega_p;
+      if (omega_p == 0.0 && !omega_vertex) {
+        memcpy(X, XH, sizeof(double) * nd);
+      } else {
+        /* line 5 (eq. 11): X~ = X^H + omega_p (X^H - X^k), per vertex if given */
+        for (int32_t i = 0; i < n; ++i) {
+          const double wp = omega_vertex ? omega_vertex[i] - 1.0 : omega_p;
+          for (int32_t c = 0; c < dim; ++c) {
+            const size_t q = (size_t)i * dim + c;
+            XT[q] = XH[q] + wp * (XH[q] - X[q]);
+          }
+        }
+        int take = 1;
+        if (safeguard) {
+          /* line 6: keep X~ only if f(X~) <= f(X^H) */
+          slo_stress_delta(n, dim, D, XT, XH, &df, &scale);
+          take = (df <= 0.0);
+        }
+        accepted = take ? 1.0 : 0.0;
+        if (!take) out->rejected += 1;
+        memcpy(X, take ? XT : XH, sizeof(double) * nd);
+      }
     }
     out->iterations = k + 1;
     out->residual = res;
@@ -574,6 +634,9 @@ int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega,
       row[2] = df;
       row[3] = scale;
       row[4] = f_k;
+      row[5] = used;
+      row[6] = gap;
+      row[7] = gscale;
     }
     if (xtrace) memcpy(xtrace + (size_t)k * nd, X, sizeof(double) * nd);
     if (res <= tol) {

@@ -21,6 +21,17 @@ STATUS_NAMES = {0: "SL_OK", -1: "SL_EINVAL", -2: "SL_ENOMEM", -3: "SL_EDEVICE", 
 SL_TRACE_COLS = 5
 SL_FLAG_TRACE_STRESS = 1
 SL_FLAG_NO_GRAPH = 2
+SL_OMEGA_FIXED, SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM = 0, 1, 2
+# probabilistic strategy (Sec. 5.2): roulette over the paper's factors
+AUTO_FACTORS = (0.5, 1.0, 1.5, 2.0)
+AUTO_PROBS = (0.3, 0.3, 0.2, 0.2)
+
+
+def auto_schedule(max_iter: int, seed: int) -> np.ndarray:
+    """Classical factors 1 + c for max_iter iterations, c drawn by the paper's
+    roulette P(0.5) = P(1.0) = 0.3, P(1.5) = P(2.0) = 0.2 (seeded)."""
+    rng = np.random.Generator(np.random.PCG64(int(seed)))
+    return 1.0 + rng.choice(np.array(AUTO_FACTORS), size=int(max_iter), p=np.array(AUTO_PROBS))
 
 EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run", "sl_plan_stress",
             "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
@@ -45,7 +56,8 @@ class sl_options(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("tol", ctypes.c_double), ("safeguard", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("trace", ctypes.c_void_p),
-                ("xtrace", ctypes.c_void_p)]
+                ("xtrace", ctypes.c_void_p), ("strategy", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("omega_schedule", ctypes.c_void_p), ("omega_vertex", ctypes.c_void_p)]
 
 
 class sl_batch(ctypes.Structure):
@@ -131,7 +143,10 @@ def graph_args(g) -> _GraphArgs:
 
 
 def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0,
-                 trace_stress=False, use_graph=True, trace=None, xtrace=None) -> sl_options:
+                 trace_stress=False, use_graph=True, trace=None, xtrace=None, strategy=SL_OMEGA_FIXED,
+                 omega_schedule=None, omega_vertex=None) -> sl_options:
+    """omega_schedule: host float64 array (kept alive by the caller);
+    omega_vertex: device pointer (int) or None."""
     o = sl_options()
     LIB.sl_default_options(ctypes.byref(o))
     o.dim, o.omega, o.tol, o.max_iter = int(dim), float(omega), float(tol), int(max_iter)
@@ -139,6 +154,9 @@ def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, chec
     o.flags = (SL_FLAG_TRACE_STRESS if trace_stress else 0) | (0 if use_graph else SL_FLAG_NO_GRAPH)
     o.trace = None if trace is None else int(trace)
     o.xtrace = None if xtrace is None else int(xtrace)
+    o.strategy = int(strategy)
+    o.omega_schedule = None if omega_schedule is None else omega_schedule.ctypes.data
+    o.omega_vertex = None if omega_vertex is None else int(omega_vertex)
     return o
 
 
@@ -224,9 +242,14 @@ class Plan:
         self.handle = sl_plan_create(g, dim, stream)
 
     def run(self, X, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0, trace=False,
-            trace_stress=False, trace_positions=False, use_graph=True, stream=None):
+            trace_stress=False, trace_positions=False, use_graph=True, stream=None, strategy="fixed",
+            omega_schedule=None, omega_vertex=None):
         """Run Algorithm 2 in place on the device tensor X (n x dim, float32).
 
+        strategy: "fixed" (omega), "schedule" (omega_schedule, one classical
+        factor per iteration; see auto_schedule) or "enum" (argmin over the
+        paper's factors 0, 0.5, ..., 9); omega_vertex: optional device tensor
+        of n classical factors (fixed strategy).
         Returns the sl_result fields; with ``trace`` also a ``trace`` array
         (iterations x 5) and with ``trace_positions`` the ``positions``
         (iterations x n x dim) on the host."""
@@ -239,8 +262,16 @@ class Plan:
             tr = torch.full((max(max_iter, 1), SL_TRACE_COLS), float("nan"), dtype=torch.float64, device=X.device)
         if trace_positions:
             xt = torch.zeros((max(max_iter, 1), self.n, self.dim), dtype=torch.float32, device=X.device)
+        strat = {"fixed": SL_OMEGA_FIXED, "schedule": SL_OMEGA_SCHEDULE, "enum": SL_OMEGA_ENUM}[strategy]
+        sched = None if omega_schedule is None else np.ascontiguousarray(omega_schedule, dtype=np.float64)
+        if sched is not None and len(sched) < max_iter:
+            raise ValueError("omega_schedule needs max_iter entries")
+        wv = None
+        if omega_vertex is not None:
+            wv = omega_vertex.to(device=X.device, dtype=torch.float32).contiguous()
         opt = make_options(self.dim, omega, tol, max_iter, safeguard, check_every, trace_stress, use_graph,
-                           None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr())
+                           None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr(),
+                           strat, sched, None if wv is None else wv.data_ptr())
         info = sl_plan_run(self.handle, X.data_ptr(), opt, stream)
         k = info["iterations"]
         if tr is not None:

@@ -100,6 +100,18 @@ sl_status check_options(const sl_options* o) {
   if (o->max_iter < 0) return fail(SL_EINVAL, "max_iter = %d is negative", o->max_iter);
   if (o->safeguard != 0 && o->safeguard != 1) return fail(SL_EINVAL, "safeguard must be 0 or 1");
   if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH)) return fail(SL_EINVAL, "unknown flag bits");
+  if (o->strategy != SL_OMEGA_FIXED && o->strategy != SL_OMEGA_SCHEDULE && o->strategy != SL_OMEGA_ENUM)
+    return fail(SL_EINVAL, "unknown relaxation strategy %d", o->strategy);
+  if (o->strategy == SL_OMEGA_SCHEDULE) {
+    if (!o->omega_schedule && o->max_iter > 0) return fail(SL_EINVAL, "SL_OMEGA_SCHEDULE needs omega_schedule");
+    for (int k = 0; k < o->max_iter; ++k)
+      if (!(std::isfinite(o->omega_schedule[k]) && o->omega_schedule[k] > 0.0 && o->omega_schedule[k] <= 16.0))
+        return fail(SL_EINVAL, "omega_schedule[%d] = %g outside (0, 16]", k, o->omega_schedule[k]);
+  } else if (o->omega_schedule) {
+    return fail(SL_EINVAL, "omega_schedule is only read with SL_OMEGA_SCHEDULE");
+  }
+  if (o->omega_vertex && o->strategy != SL_OMEGA_FIXED)
+    return fail(SL_EINVAL, "per-vertex factors need SL_OMEGA_FIXED");
   return SL_OK;
 }
 
@@ -126,6 +138,8 @@ struct sl_plan {
   int nred = 0;
   double* sgpart = nullptr;     // one double per safeguard work item
   int4* items = nullptr;        // safeguard work items
+  double* sched = nullptr;      // device copy of a relaxation schedule (paper's factors)
+  int sched_cap = 0;
   int nsg = 0;
   DevState* st = nullptr;       // loop state
   DevState* st_eval = nullptr;  // state for stand-alone stress passes
@@ -144,6 +158,7 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->Xb);
   (void)hipFree(p->Eb);
   (void)hipFree(p->items);
+  (void)hipFree(p->sched);
   (void)hipFree(p->fpart);
   (void)hipFree(p->spart);
   (void)hipFree(p->red);
@@ -264,11 +279,17 @@ sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* 
           "force kernel");
   HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
           "update kernel");
-  if (lp.safeguard && lp.omega_p != 0.0)
+  if (lp.enumerate)
+    HIP_TRY(launch_sgdelta_enum(p->dim, p->d, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart, p->sp,
+                                p->ps),
+            "enumeration kernel");
+  else if (lp.safeguard && (lp.omega_p != 0.0 || lp.omega_sched || lp.omega_vertex))
     HIP_TRY(launch_sgdelta(p->dim, p->d, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart, p->sp,
                            p->ps),
             "safeguard kernel");
   HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsg, p->st, o->trace, p->ps), "select kernel");
+  if (lp.enumerate)
+    HIP_TRY(launch_apply_enum(p->Eb, p->Xb, p->stride, p->st, p->n, p->dim, p->ps), "enumeration apply kernel");
   if (o->xtrace) HIP_TRY(launch_record(p->Xb, p->stride, p->st, o->xtrace, p->n, p->dim, p->ps), "record kernel");
   return SL_OK;
 }
@@ -348,7 +369,7 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess) e = hipMalloc(&p->fpart, sizeof(double) * p->sp.slices * 3 * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->spart, sizeof(double) * p->sp.slices * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(double) * 8 * p->nred);
-  if (e == hipSuccess) e = hipMalloc(&p->sgpart, sizeof(double) * p->nsg);
+  if (e == hipSuccess) e = hipMalloc(&p->sgpart, sizeof(double) * p->nsg * kEnumCandidates);
   if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
   if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
   if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
@@ -400,8 +421,39 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   lp.tol = o->tol;
   lp.safeguard = o->safeguard;
   lp.stress = (o->flags & SL_FLAG_TRACE_STRESS) ? 1 : 0;
+  lp.enumerate = o->strategy == SL_OMEGA_ENUM ? 1 : 0;
+  lp.omega_vertex = o->omega_vertex;
+  lp.omega_sched = nullptr;
 
   if ((s = join_from(p, user)) != SL_OK) return s;
+  if (o->omega_vertex && p->n > 0) {
+    std::vector<float> wv(p->n);
+    HIP_TRY(hipMemcpyAsync(wv.data(), o->omega_vertex, sizeof(float) * p->n, hipMemcpyDeviceToHost, p->ps),
+            "omega_vertex copy");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    for (int i = 0; i < p->n; ++i)
+      if (!(std::isfinite(wv[i]) && wv[i] > 0.f && wv[i] <= 16.f))
+        return fail(SL_EINVAL, "omega_vertex[%d] = %g outside (0, 16]", i, (double)wv[i]);
+  }
+  if (o->strategy == SL_OMEGA_SCHEDULE && o->max_iter > 0) {
+    if (p->sched_cap < o->max_iter) {
+      (void)hipFree(p->sched);
+      p->sched = nullptr;
+      p->sched_cap = 0;
+      HIP_TRY(hipMalloc(&p->sched, sizeof(double) * o->max_iter), "schedule buffer");
+      p->sched_cap = o->max_iter;
+      if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+      }
+    }
+    std::vector<double> wp(o->max_iter);
+    for (int k = 0; k < o->max_iter; ++k) wp[k] = o->omega_schedule[k] - 1.0;
+    HIP_TRY(hipMemcpyAsync(p->sched, wp.data(), sizeof(double) * o->max_iter, hipMemcpyHostToDevice, p->ps),
+            "schedule upload");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    lp.omega_sched = p->sched;
+  }
   if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
   DevState* h = p->host_st;
   std::memset(h, 0, sizeof(DevState));
@@ -415,7 +467,9 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   const bool use_graph = !(o->flags & SL_FLAG_NO_GRAPH);
   if (use_graph) {
     std::vector<double> key = {(double)p->dim, lp.omega_p, lp.tol, (double)lp.safeguard, (double)lp.stress,
-                               (double)chunk, (double)(uintptr_t)o->trace, (double)(uintptr_t)o->xtrace};
+                               (double)chunk, (double)(uintptr_t)o->trace, (double)(uintptr_t)o->xtrace,
+                               (double)lp.enumerate, (double)(uintptr_t)lp.omega_sched,
+                               (double)(uintptr_t)lp.omega_vertex};
     if (!p->gexec || key != p->gkey) {
       if (p->gexec) {
         (void)hipGraphExecDestroy(p->gexec);
@@ -709,6 +763,8 @@ sl_status batch_params(const sl_batch_plan* p, const sl_options* o, BatchParams*
   if (s != SL_OK) return s;
   if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
   if (o->trace || o->xtrace) return fail(SL_EINVAL, "traces are not available for batched layouts");
+  if (o->strategy != SL_OMEGA_FIXED || o->omega_vertex)
+    return fail(SL_EINVAL, "batched layouts take a fixed relaxation factor");
   bp->omega_p = o->omega - 1.0;
   bp->tol = o->tol;
   bp->max_iter = o->max_iter;

@@ -48,7 +48,13 @@ struct DevState {
   double residual;
   double last_df;
   double stress;      // f of the last evaluated placement (stress passes)
+  double omega_used;  // paper's factor of the last iteration
+  double enum_c;      // enumerating: factor picked by the last select
+  int32_t enum_pending;  // enumerating: X~ = X^H + enum_c * step is still to be formed
+  int32_t pad2;
 };
+
+constexpr int kEnumCandidates = 18;  // paper's factors 0.5, 1.0, ..., 9.0 (0 = keep X^H)
 
 // Scalars every kernel of the loop needs, passed by value.
 struct LoopParams {
@@ -57,6 +63,10 @@ struct LoopParams {
   double tol;
   int32_t safeguard;  // evaluate f(X~) - f(X^H) and select
   int32_t stress;     // accumulate f(X^k) in the force pass
+  int32_t enumerate;  // SL_OMEGA_ENUM
+  int32_t pad;
+  const double* omega_sched;  // device, paper's factors per iteration, or nullptr
+  const float* omega_vertex;  // device, classical factors per vertex, or nullptr
 };
 
 // Work split of the all-pairs passes for a graph of n_pad vertices.
@@ -95,6 +105,11 @@ hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t str
                           hipStream_t s);
 hipError_t launch_select(int dim, const LoopParams& p, const double* red, int nred, const double* sgpart,
                          int nsg, DevState* st, double* trace, hipStream_t s);
+hipError_t launch_sgdelta_enum(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
+                               const int4* items, int nitems, const DevState* st, double* sgpart, const Split& sp,
+                               hipStream_t s);
+hipError_t launch_apply_enum(const float* Eb, float* Xb, size_t stride, const DevState* st, int n, int dim,
+                             hipStream_t s);
 hipError_t launch_record(const float* Xb, size_t stride, const DevState* st, float* xtrace, int n, int dim,
                          hipStream_t s);
 hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevState* st, hipStream_t s);

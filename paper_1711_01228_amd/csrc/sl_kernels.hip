@@ -123,8 +123,12 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
   V* __restrict__ XH = reinterpret_cast<V*>(Xb + (size_t)h * stride);
   V* __restrict__ XT = reinterpret_cast<V*>(Xb + (size_t)t * stride);
   const int i = blockIdx.x * 256 + threadIdx.x;
+  // factor of this iteration (schedule) and of this vertex (per-vertex factors)
+  const double wp = p.omega_sched ? p.omega_sched[st->iter] : p.omega_p;
+  const bool extrapolate = p.enumerate || p.omega_vertex || wp != 0.0;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   if (i < p.n) {
+    const double wpi = p.omega_vertex ? (double)p.omega_vertex[i] - 1.0 : wp;
     double F[3] = {0.0, 0.0, 0.0};
     for (int s = 0; s < p.slices; ++s) {
       const double* fp = fpart + (size_t)s * DIM * p.n_pad + i;
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
     for (int c = 0; c < DIM; ++c) {
       xh[c] = (Wi > 0.0) ? (float)((double)xv[c] + F[c] / Wi) : xv[c];
       const double dl = (double)xh[c] - (double)xv[c];
-      xt[c] = (float)((double)xh[c] + p.omega_p * dl);
+      xt[c] = (float)((double)xh[c] + wpi * dl);
       v[0] += dl * dl;
       v[1] += (double)xh[c] * (double)xh[c];
       v[2 + c] = (double)xh[c];
@@ -150,13 +154,17 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
     V* __restrict__ E = reinterpret_cast<V*>(Eb);
     if constexpr (DIM == 2) {
       XH[i] = make_float2(xh[0], xh[1]);
-      if (p.omega_p != 0.0) {
+      if (p.enumerate) {
+        E[i] = make_float2(xh[0] - xv[0], xh[1] - xv[1]);  // the step X^H - X^k
+      } else if (extrapolate) {
         XT[i] = make_float2(xt[0], xt[1]);
         E[i] = make_float2(xt[0] - xh[0], xt[1] - xh[1]);
       }
     } else {
       XH[i] = make_float4(xh[0], xh[1], xh[2], 0.f);
-      if (p.omega_p != 0.0) {
+      if (p.enumerate) {
+        E[i] = make_float4(xh[0] - xv[0], xh[1] - xv[1], xh[2] - xv[2], 0.f);
+      } else if (extrapolate) {
         XT[i] = make_float4(xt[0], xt[1], xt[2], 0.f);
         E[i] = make_float4(xt[0] - xh[0], xt[1] - xh[1], xt[2] - xh[2], 0.f);
       }
@@ -262,24 +270,145 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
 }
 
 // ---------------------------------------------------------------------------
+// Enumerating strategy (Sec. 5.2): f(X^H + c D) - f(X^H) for the paper's
+// factors c = 0.5, 1.0, ..., 9.0 at once, D = X^H - X^k the stored step.  Per
+// pair, with h = x^H_i - x^H_j, s = D_i - D_j, a = h.s, b = s.s:
+//   r_c^2 - r^H^2 = c (2a + c b) =: m_c, and the term is m_c (1/d)(1/d - 2/(r_c + r^H))
+// as in the safeguard.  One double per candidate and work item.
+// ---------------------------------------------------------------------------
+template <int DIM, bool MASK>
+__device__ __forceinline__ void enum_group(const uint4& q, const float* lut, typename VecT<DIM>::T hi,
+                                           typename VecT<DIM>::T di, const typename VecT<DIM>::T* __restrict__ hj,
+                                           const typename VecT<DIM>::T* __restrict__ dj, int jrel,
+                                           float (&a)[kEnumCandidates]) {
+  using V = typename VecT<DIM>::T;
+#pragma unroll 2
+  for (int k = 0; k < kColGroup; ++k) {
+    const float inv = lut[byte_of(chunk_word(q, k), k & 3)];
+    const V ph = hj[k], pd = dj[k];
+    const float hx = hi.x - ph.x, hy = hi.y - ph.y;
+    const float sx = di.x - pd.x, sy = di.y - pd.y;
+    float rh2 = fmaf(hx, hx, kTiny);
+    rh2 = fmaf(hy, hy, rh2);
+    float aa = fmaf(hy, sy, hx * sx), bb = fmaf(sy, sy, sx * sx);
+    if constexpr (DIM == 3) {
+      const float hz = hi.z - ph.z, sz = di.z - pd.z;
+      rh2 = fmaf(hz, hz, rh2);
+      aa = fmaf(hz, sz, aa);
+      bb = fmaf(sz, sz, bb);
+    }
+    const float rh = rh2 * __builtin_amdgcn_rsqf(rh2);
+    float ik = inv;
+    if constexpr (MASK) {
+      if (k <= jrel) ik = 0.f;
+    }
+    const float a2 = 2.f * aa;
+#pragma unroll
+    for (int c = 0; c < kEnumCandidates; ++c) {
+      const float wc = 0.5f * (float)(c + 1);
+      const float m = wc * fmaf(wc, bb, a2);
+      const float rt2 = fabsf(rh2 + m);
+      const float sum = fmaf(rt2, __builtin_amdgcn_rsqf(rt2), rh);
+      a[c] = fmaf(m * ik, fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv), a[c]);
+    }
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_sgdelta_enum(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
+                                                      size_t stride, const float* __restrict__ Eb,
+                                                      const int4* __restrict__ items, int nitems,
+                                                      const DevState* __restrict__ st, double* __restrict__ sgpart,
+                                                      int ng) {
+  using V = typename VecT<DIM>::T;
+  __shared__ float lut[256];
+  if (st->done) return;
+  lut[threadIdx.x] = threadIdx.x ? 1.0f / (float)threadIdx.x : 0.f;
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int item = blockIdx.x * 4 + wave;
+  if (item >= nitems) return;
+  const int4 it = items[item];
+  const int rb = it.x, g0 = it.y, g1 = it.z;
+  const int h = (st->cur + 1) % 3;
+  const V* __restrict__ XH = reinterpret_cast<const V*>(Xb + (size_t)h * stride);
+  const V* __restrict__ Dl = reinterpret_cast<const V*>(Eb);
+  const int gdiag = rb * (kRowBlock / kColGroup);
+  const int gfree = gdiag + kRowBlock / kColGroup;
+  const int i = rb * kRowBlock + lane;
+  const V hi = XH[i], di = Dl[i];
+  const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
+  double acc[kEnumCandidates];
+#pragma unroll
+  for (int c = 0; c < kEnumCandidates; ++c) acc[c] = 0.0;
+  for (int g = g0; g < g1; ++g) {
+    const uint4 q = tile[(size_t)g * 64];
+    float a[kEnumCandidates];
+#pragma unroll
+    for (int c = 0; c < kEnumCandidates; ++c) a[c] = 0.f;
+    if (g < gfree)
+      enum_group<DIM, true>(q, lut, hi, di, XH + (size_t)g * kColGroup, Dl + (size_t)g * kColGroup,
+                            i - g * kColGroup, a);
+    else
+      enum_group<DIM, false>(q, lut, hi, di, XH + (size_t)g * kColGroup, Dl + (size_t)g * kColGroup, 0, a);
+#pragma unroll
+    for (int c = 0; c < kEnumCandidates; ++c) acc[c] += (double)a[c];
+  }
+#pragma unroll
+  for (int c = 0; c < kEnumCandidates; ++c) {
+    const double t = wave_sum(acc[c]);
+    if (lane == 0) sgpart[(size_t)item * kEnumCandidates + c] = t;
+  }
+}
+
+// X~ = X^H + c D for the factor the select picked (enumerating strategy).
+// Idempotent, so replays of a finished chunk leave X unchanged.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_apply_enum(const float* __restrict__ Eb, float* __restrict__ Xb, size_t stride,
+                                                    const DevState* __restrict__ st, int n) {
+  using V = typename VecT<DIM>::T;
+  if (!st->enum_pending) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int t = st->cur, h = (t + 2) % 3;
+  const double c = st->enum_c;
+  const V xh = reinterpret_cast<const V*>(Xb + (size_t)h * stride)[i];
+  const V dl = reinterpret_cast<const V*>(Eb)[i];
+  V* XT = reinterpret_cast<V*>(Xb + (size_t)t * stride);
+  if constexpr (DIM == 2) {
+    XT[i] = make_float2((float)((double)xh.x + c * dl.x), (float)((double)xh.y + c * dl.y));
+  } else {
+    XT[i] = make_float4((float)((double)xh.x + c * dl.x), (float)((double)xh.y + c * dl.y),
+                        (float)((double)xh.z + c * dl.z), 0.f);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Alg. 2 lines 6-9 and the termination test, one workgroup.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __restrict__ red, int nred,
                                                 const double* __restrict__ sgpart, int nsg,
                                                 DevState* __restrict__ st, double* __restrict__ trace, int dim) {
   __shared__ double sh[8][256];
+  __shared__ double cand[kEnumCandidates];
   if (st->done) return;
+  const int k = st->iter;
+  const double wp = p.omega_sched ? p.omega_sched[k] : p.omega_p;
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nred; b += 256) {
 #pragma unroll
-    for (int k = 0; k < 7; ++k) v[k] += red[(size_t)b * 8 + k];
+    for (int q = 0; q < 7; ++q) v[q] += red[(size_t)b * 8 + q];
   }
-  const bool sg = p.safeguard && p.omega_p != 0.0;
+  const bool sg = !p.enumerate && p.safeguard && (wp != 0.0 || p.omega_vertex);
   if (sg)
     for (int b = threadIdx.x; b < nsg; b += 256) v[7] += sgpart[b];
+  if (p.enumerate && threadIdx.x < kEnumCandidates) {
+    double t = 0.0;  // items in order
+    for (int b = 0; b < nsg; ++b) t += sgpart[(size_t)b * kEnumCandidates + threadIdx.x];
+    cand[threadIdx.x] = t;
+  }
   block_sum<8>(v, sh);
   if (threadIdx.x != 0) return;
-  const int k = st->iter;
   if (v[6] > 0.0) {  // a non-finite coordinate: keep the last finite iterate
     st->status = -5;
     st->done = 1;
@@ -291,8 +420,31 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
   const double res = dsq > 0.0 ? sqrt(dsq) / sqrt(den2 > 0.0 ? den2 : 0.0) : 0.0;
   const int cur = st->cur, h = (cur + 1) % 3, t = (cur + 2) % 3;
   double accepted;
-  const double df = sg ? v[7] : 0.0;
-  if (p.omega_p == 0.0) {
+  double df = sg ? v[7] : 0.0;
+  double used = p.omega_vertex ? __builtin_nan("") : wp;
+  st->enum_pending = 0;
+  if (p.enumerate) {
+    int best = -1;  // -1: c = 0, difference 0; ties keep the smaller factor
+    double bv = 0.0;
+    for (int c = 0; c < kEnumCandidates; ++c)
+      if (cand[c] < bv) {
+        bv = cand[c];
+        best = c;
+      }
+    df = bv;
+    used = 0.5 * (best + 1);
+    if (best < 0) {
+      used = 0.0;
+      st->cur = h;
+      accepted = 0.0;
+      st->rejected += 1;
+    } else {
+      st->cur = t;
+      st->enum_c = used;
+      st->enum_pending = 1;
+      accepted = 1.0;
+    }
+  } else if (wp == 0.0 && !p.omega_vertex) {
     st->cur = h;
     accepted = -1.0;
   } else if (p.safeguard) {
@@ -304,6 +456,7 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     st->cur = t;
     accepted = 1.0;
   }
+  st->omega_used = used;
   st->iter = k + 1;
   st->residual = res;
   st->last_df = df;
@@ -312,7 +465,7 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     row[0] = res;
     row[1] = accepted;
     row[2] = df;
-    row[3] = 0.0;
+    row[3] = used;
     row[4] = p.stress ? 0.5 * v[5] : __builtin_nan("");
   }
   if (res <= p.tol) {
@@ -605,6 +758,23 @@ hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t str
   const unsigned nb = (unsigned)((nitems + 3) / 4);
   if (dim == 2) k_sgdelta<2><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
   else k_sgdelta<3><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_sgdelta_enum(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
+                               const int4* items, int nitems, const DevState* st, double* sgpart, const Split& sp,
+                               hipStream_t s) {
+  const unsigned nb = (unsigned)((nitems + 3) / 4);
+  if (dim == 2) k_sgdelta_enum<2><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+  else k_sgdelta_enum<3><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_enum(const float* Eb, float* Xb, size_t stride, const DevState* st, int n, int dim,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (dim == 2) k_apply_enum<2><<<blocks_for(n), 256, 0, s>>>(Eb, Xb, stride, st, n);
+  else k_apply_enum<3><<<blocks_for(n), 256, 0, s>>>(Eb, Xb, stride, st, n);
   return hipGetLastError();
 }
 

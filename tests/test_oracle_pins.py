@@ -434,3 +434,52 @@ def test_sor_saves_iterations_like_table_1():
         assert a["converged"] and b["converged"]
         ratios.append(b["iterations"] / a["iterations"])
     assert 0.5 < np.mean(ratios) < 0.85
+
+
+# ---------------------------------------------------------------------------
+# relaxation strategies of Sec. 5.2
+# ---------------------------------------------------------------------------
+def test_schedule_is_composition_of_single_steps():
+    D, X0 = _er_case(n=60, m=120, seed=41)
+    sched = np.array([1.5, 2.0, 1.0, 3.0, 1.5, 2.5])
+    X, info = oracle.layout(D, X0, tol=0, max_iter=len(sched), omega_schedule=sched)
+    Y = X0.copy()
+    for w in sched:
+        Y, _ = oracle.layout(D, Y, omega=w, tol=0, max_iter=1)
+    np.testing.assert_array_equal(X, Y)
+    np.testing.assert_array_equal(info["trace"][:, 5], sched - 1.0)
+    Xf, _ = oracle.layout(D, X0, omega=1.7, tol=0, max_iter=5)
+    Xs, _ = oracle.layout(D, X0, tol=0, max_iter=5, omega_schedule=np.full(5, 1.7))
+    np.testing.assert_array_equal(Xf, Xs)
+
+
+def test_uniform_per_vertex_factors_equal_fixed_factor():
+    D, X0 = _er_case(n=60, m=120, seed=42)
+    Xf, a = oracle.layout(D, X0, omega=1.6, tol=0, max_iter=8)
+    Xv, b = oracle.layout(D, X0, tol=0, max_iter=8, omega_vertex=np.full(60, 1.6))
+    np.testing.assert_array_equal(Xf, Xv)
+    assert a["rejected"] == b["rejected"]
+    # one step by hand with different factors per vertex and no safeguard
+    w = np.linspace(1.0, 2.5, 60)
+    X1, _ = oracle.layout(D, X0, tol=0, max_iter=1, omega_vertex=w, safeguard=False)
+    XH = oracle.h_jacobi(D, X0)
+    np.testing.assert_allclose(X1, XH + (w - 1.0)[:, None] * (XH - X0), rtol=1e-14, atol=1e-14)
+
+
+def test_enumeration_picks_the_stress_minimizing_candidate():
+    D, X0 = _er_case(n=50, m=100, seed=43)
+    X = X0.copy()
+    for k in range(5):
+        XH = oracle.h_jacobi(D, X)
+        fs = [oracle.stress(D, XH + c * (XH - X)) for c in oracle.ENUM_FACTORS]
+        X1, info = oracle.layout(D, X, tol=0, max_iter=1, enumerate=True)
+        c = info["trace"][0, 5]
+        assert fs[int(round(2 * c))] == pytest.approx(min(fs), rel=1e-12)
+        assert oracle.stress(D, X1) <= oracle.stress(D, XH) * (1 + 1e-14)
+        np.testing.assert_allclose(X1, XH + c * (XH - X), rtol=1e-14, atol=1e-14)
+        X = X1
+
+
+def test_auto_roulette_distribution():
+    assert sum(oracle.AUTO_PROBS) == pytest.approx(1.0)
+    assert oracle.ENUM_FACTORS[0] == 0.0 and oracle.ENUM_FACTORS[-1] == 9.0 and len(oracle.ENUM_FACTORS) == 19
