@@ -9,7 +9,8 @@ and weights) is built before the timed region, so inputs are resident in HBM.
 value = n (n - 1) * steps / seconds   (pair interactions of the force pass)
 
 Also reported: time-to-converge (res <= 1e-3) for omega = 1 and omega = 1.5
-from the same start, the roofline of the force kernel (HIP-event time), and
+from the same start, the same for the relaxation strategies of Sec. 5.2
+(probabilistic, enumerating, per-vertex factors), the roofline of the force kernel (HIP-event time), and
 the FP64 oracle's pair rate on a sample of rows on the host cores.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dim 2] [--quick]
@@ -114,6 +115,40 @@ def bench_batch(omega, count=2048):
             "rejected_total": int(tot["rejected"]), "tuned_config": cfg.tolist()}
 
 
+def bench_strategies(plan, Xdev0, n):
+    """The relaxation strategies of Sec. 5.2 on the same plan and start: per
+    iteration device time (20 iterations, tol 0) and time to res <= 1e-3."""
+    import numpy as np
+    import torch
+
+    from paper_1711_01228_amd import binding
+
+    rng = np.random.default_rng(77)
+    cases = {
+        "fixed omega=1.5": dict(omega=1.5),
+        "probabilistic (seed 5)": dict(strategy="schedule", omega_schedule=binding.auto_schedule(3000, 5)),
+        "enumerating": dict(strategy="enum"),
+        "per-vertex omega_i ~ U[1,2] (seed 77)": dict(
+            omega_vertex=torch.tensor(rng.uniform(1.0, 2.0, n).astype(np.float32), device="cuda")),
+    }
+    res = {}
+    for name, kw in cases.items():
+        X = Xdev0.clone()
+        r = plan.run(X, tol=0.0, max_iter=20, **kw)
+        per_it = r["run_ms"] / r["iterations"]
+        X = Xdev0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = plan.run(X, tol=1e-3, max_iter=3000, **kw)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t
+        res[name] = {"ms_per_iteration": round(per_it, 4), "seconds_to_tol": round(w, 4),
+                     "iterations": r["iterations"], "converged": bool(r["converged"]), "rejected": r["rejected"],
+                     "final_residual": r["residual"], "final_stress": r["stress"]}
+        log("strategy %s: %s" % (name, res[name]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +161,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D run of the same workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched small-graph run")
+    ap.add_argument("--no-strategies", action="store_true", help="skip the relaxation-strategy comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -207,6 +243,8 @@ def main():
         ttc["speedup"] = round(a["seconds"] / b["seconds"], 3)
         ttc["tol"] = 1e-3
         out["time_to_converge"] = ttc
+        if not args.no_strategies:
+            out["strategies"] = bench_strategies(plan, Xdev0, n)
     plan.close()
     del plan
 
