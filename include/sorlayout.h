@@ -9,9 +9,13 @@
  *                             placement X in R^{n x dim}
  *   stress (eq. 1)            f(X) = sum_{i<j} w_ij (||x_i - x_j|| - d_ij)^2,
  *                             d_ij = graph distance, w_ij = d_ij^-2 (Sec. 5.1)
- *   step H (Prop. 2.3, eq. 5) L^W X^H = L^X X; this library applies one Jacobi
+ *   step H (Prop. 2.3, eq. 5) L^W X^H = L^X X, in one of two orderings:
+ *                             SL_ORDER_JACOBI (default) applies one Jacobi
  *                             sweep of eq. 5 per iteration:
  *                             x_i^H = x_i + (1/W_i) sum_j w_ij (d_ij - r_ij) u_ij
+ *                             SL_ORDER_EXACT solves eq. 5 (the paper's step,
+ *                             Alg. 1/2 line 4) by preconditioned conjugate
+ *                             gradients
  *   SOR (Alg. 2, eq. 11)      X~ = X^H + (omega - 1)(X^H - X); keep X~ only if
  *                             f(X~) <= f(X^H) (Alg. 2, lines 6-8)
  *   termination               res_k = ||X^H - X^k||_F / ||X^H - mean(X^H)||_F
@@ -72,6 +76,14 @@ typedef enum {
                                 the argmin of f(X^H + c (X^H - X^k)) over
                                 c in {0, 0.5, ..., 9}; c = 0 keeps X^H (counted rejected) */
 
+/* Orderings of the step H (eq. 5). */
+#define SL_ORDER_JACOBI 0    /* one Jacobi sweep: X^H = X^k + F / W                       */
+#define SL_ORDER_EXACT 1     /* eq. 5 solved: conjugate gradients on L^W Y = L^X X^k from
+                                Y = X^k, preconditioned by W, to ||r|| <= inner_tol ||r_0||;
+                                L^W is singular, and the lowest-numbered vertex of each
+                                connected component keeps its place (the paper fixes x_1,
+                                Sec. 2: a translation of the same solution)               */
+
 #define SL_FLAG_TRACE_STRESS 1u  /* evaluate f(X^k) every iteration into trace[4]  */
 #define SL_FLAG_NO_GRAPH 2u      /* launch kernels one by one instead of replaying a
                                     captured HIP graph of `check_every` iterations */
@@ -97,7 +109,7 @@ typedef struct {
   int32_t check_every;      /* iterations between host polls of the stop flag;
                                <= 0 selects a default from the graph size          */
   uint32_t flags;           /* SL_FLAG_*                                           */
-  int32_t reserved;
+  int32_t ordering;         /* SL_ORDER_JACOBI (default) or SL_ORDER_EXACT           */
   double* trace;            /* NULL or device buffer of max_iter * SL_TRACE_COLS
                                doubles, row k written by iteration k               */
   float* xtrace;            /* NULL or device buffer of max_iter * n * dim floats:
@@ -109,13 +121,18 @@ typedef struct {
   const float* omega_vertex;    /* NULL, or device, n classical factors in (0, 16]: vertex i
                                    extrapolates by omega_vertex[i] - 1 (SL_OMEGA_FIXED only;
                                    `omega` is then unused)                           */
+  double inner_tol;         /* SL_ORDER_EXACT: relative residual of each solve, in [0, 1);
+                               0 selects 1e-6                                        */
+  int32_t inner_max_iter;   /* SL_ORDER_EXACT: conjugate-gradient steps per solve, >= 0;
+                               0 selects 500                                         */
+  int32_t reserved3;
 } sl_options;
 
 typedef struct {
   int32_t iterations;       /* steps taken                                         */
   int32_t converged;        /* 1 if res <= tol was reached (or n <= 1)             */
   int32_t rejected;         /* extrapolations refused by the safeguard            */
-  int32_t reserved;
+  int32_t inner_iterations; /* SL_ORDER_EXACT: conjugate-gradient steps, summed    */
   double residual;          /* res of the last step                               */
   double stress;            /* f of the returned placement                        */
   double plan_ms;           /* time of sl_plan_create (sl_layout: distances+weights) */
@@ -143,7 +160,9 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
 /* Run Algorithm 2 from the placement in X (device, n * dim floats, row-major)
  * and write the final placement back to X.  Each iteration:
  *   1. F_i = sum_j w_ij (d_ij - r_ij) u_ij at X^k (eq. 5 residual, all pairs)
- *   2. X^H = X^k + F / W (W_i = 0: the vertex keeps its place), res_k
+ *   2. X^H = X^k + F / W (W_i = 0: the vertex keeps its place), or with
+ *      SL_ORDER_EXACT the solution of eq. 5 by conjugate gradients started
+ *      from X^k (whose residual is F); res_k
  *   3. X~ = X^H + (omega - 1)(X^H - X^k)          (eq. 11)
  *   4. keep X~ iff f(X~) - f(X^H) <= 0              (Alg. 2, lines 6-8)
  *   5. stop when res_k <= tol or after max_iter steps
@@ -170,6 +189,8 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  * modified) with relaxation factor `omega`:
  *   ms[0] all-pairs force pass   ms[1] Jacobi update + extrapolation
  *   ms[2] safeguard pass         ms[3] select + termination test
+ *   ms[4] one application of L^W (the all-pairs matvec of a conjugate-
+ *         gradient step of SL_ORDER_EXACT)
  * For profilers and benchmarks; the iterate buffers of the plan are left in an
  * unspecified state (a later sl_plan_run starts from its own X). */
 sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,
@@ -217,7 +238,8 @@ sl_status sl_batch_plan_tune(sl_batch_plan* plan, const float* X, const sl_optio
 
 /* Lay out every graph from the concatenated device placement X
  * (graph_ptr[num_graphs] x dim floats, row-major) in place.  opt->trace,
- * opt->xtrace and opt->omega_vertex must be NULL and the strategy fixed.  per_graph (host, num_graphs entries) and total may
+ * opt->xtrace and opt->omega_vertex must be NULL, the strategy fixed and the
+ * ordering SL_ORDER_JACOBI (others: SL_ENOTSUP).  per_graph (host, num_graphs entries) and total may
  * be NULL; total holds the largest iteration count and residual, converged = 1
  * iff every graph converged, the sum of rejections, and run_ms. */
 sl_status sl_batch_plan_run(sl_batch_plan* plan, float* X, const sl_options* opt, void* stream, sl_result* per_graph,

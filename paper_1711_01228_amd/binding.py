@@ -22,6 +22,8 @@ SL_TRACE_COLS = 5
 SL_FLAG_TRACE_STRESS = 1
 SL_FLAG_NO_GRAPH = 2
 SL_OMEGA_FIXED, SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM = 0, 1, 2
+SL_ORDER_JACOBI, SL_ORDER_EXACT = 0, 1
+ORDERINGS = {"jacobi": SL_ORDER_JACOBI, "exact": SL_ORDER_EXACT}
 # probabilistic strategy (Sec. 5.2): roulette over the paper's factors
 AUTO_FACTORS = (0.5, 1.0, 1.5, 2.0)
 AUTO_PROBS = (0.3, 0.3, 0.2, 0.2)
@@ -55,9 +57,10 @@ class sl_graph(ctypes.Structure):
 class sl_options(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("tol", ctypes.c_double), ("safeguard", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32), ("ordering", ctypes.c_int32), ("trace", ctypes.c_void_p),
                 ("xtrace", ctypes.c_void_p), ("strategy", ctypes.c_int32), ("reserved2", ctypes.c_int32),
-                ("omega_schedule", ctypes.c_void_p), ("omega_vertex", ctypes.c_void_p)]
+                ("omega_schedule", ctypes.c_void_p), ("omega_vertex", ctypes.c_void_p),
+                ("inner_tol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
 
 
 class sl_batch(ctypes.Structure):
@@ -67,11 +70,11 @@ class sl_batch(ctypes.Structure):
 
 class sl_result(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("rejected", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("residual", ctypes.c_double), ("stress", ctypes.c_double),
+                ("inner_iterations", ctypes.c_int32), ("residual", ctypes.c_double), ("stress", ctypes.c_double),
                 ("plan_ms", ctypes.c_double), ("run_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def _load():
@@ -144,7 +147,8 @@ def graph_args(g) -> _GraphArgs:
 
 def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0,
                  trace_stress=False, use_graph=True, trace=None, xtrace=None, strategy=SL_OMEGA_FIXED,
-                 omega_schedule=None, omega_vertex=None) -> sl_options:
+                 omega_schedule=None, omega_vertex=None, ordering=SL_ORDER_JACOBI, inner_tol=0.0,
+                 inner_max_iter=0) -> sl_options:
     """omega_schedule: host float64 array (kept alive by the caller);
     omega_vertex: device pointer (int) or None."""
     o = sl_options()
@@ -157,6 +161,8 @@ def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, chec
     o.strategy = int(strategy)
     o.omega_schedule = None if omega_schedule is None else omega_schedule.ctypes.data
     o.omega_vertex = None if omega_vertex is None else int(omega_vertex)
+    o.ordering = int(ordering)
+    o.inner_tol, o.inner_max_iter = float(inner_tol), int(inner_max_iter)
     return o
 
 
@@ -214,7 +220,7 @@ def sl_plan_weights(plan: int, n: int, stream=None) -> np.ndarray:
 
 
 def sl_plan_profile(plan: int, X_ptr: int, dim: int, omega: float, reps: int, stream=None) -> np.ndarray:
-    ms = np.zeros(4, dtype=np.float64)
+    ms = np.zeros(5, dtype=np.float64)
     _check(LIB.sl_plan_profile(plan, X_ptr, int(dim), float(omega), int(reps), _stream_handle(stream),
                                ms.ctypes.data))
     return ms
@@ -243,13 +249,15 @@ class Plan:
 
     def run(self, X, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0, trace=False,
             trace_stress=False, trace_positions=False, use_graph=True, stream=None, strategy="fixed",
-            omega_schedule=None, omega_vertex=None):
+            omega_schedule=None, omega_vertex=None, ordering="jacobi", inner_tol=0.0, inner_max_iter=0):
         """Run Algorithm 2 in place on the device tensor X (n x dim, float32).
 
         strategy: "fixed" (omega), "schedule" (omega_schedule, one classical
         factor per iteration; see auto_schedule) or "enum" (argmin over the
         paper's factors 0, 0.5, ..., 9); omega_vertex: optional device tensor
-        of n classical factors (fixed strategy).
+        of n classical factors (fixed strategy).  ordering: "jacobi" (one
+        sweep of eq. 5) or "exact" (eq. 5 solved by conjugate gradients to
+        inner_tol, at most inner_max_iter steps; 0 selects the defaults).
         Returns the sl_result fields; with ``trace`` also a ``trace`` array
         (iterations x 5) and with ``trace_positions`` the ``positions``
         (iterations x n x dim) on the host."""
@@ -271,7 +279,8 @@ class Plan:
             wv = omega_vertex.to(device=X.device, dtype=torch.float32).contiguous()
         opt = make_options(self.dim, omega, tol, max_iter, safeguard, check_every, trace_stress, use_graph,
                            None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr(),
-                           strat, sched, None if wv is None else wv.data_ptr())
+                           strat, sched, None if wv is None else wv.data_ptr(), ORDERINGS[ordering], inner_tol,
+                           inner_max_iter)
         info = sl_plan_run(self.handle, X.data_ptr(), opt, stream)
         k = info["iterations"]
         if tr is not None:
@@ -292,7 +301,7 @@ class Plan:
     def profile(self, X, omega=1.5, reps=5, stream=None) -> dict:
         """Average device ms of each kernel of one iteration (HIP events)."""
         ms = sl_plan_profile(self.handle, X.data_ptr(), self.dim, omega, reps, stream)
-        return dict(zip(("force", "update", "safeguard", "select"), ms.tolist()))
+        return dict(zip(("force", "update", "safeguard", "select", "lw_matvec"), ms.tolist()))
 
     def close(self):
         if self.handle:

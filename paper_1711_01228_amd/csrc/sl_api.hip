@@ -112,6 +112,11 @@ sl_status check_options(const sl_options* o) {
   }
   if (o->omega_vertex && o->strategy != SL_OMEGA_FIXED)
     return fail(SL_EINVAL, "per-vertex factors need SL_OMEGA_FIXED");
+  if (o->ordering != SL_ORDER_JACOBI && o->ordering != SL_ORDER_EXACT)
+    return fail(SL_EINVAL, "unknown ordering %d", o->ordering);
+  if (!(std::isfinite(o->inner_tol) && o->inner_tol >= 0.0 && o->inner_tol < 1.0))
+    return fail(SL_EINVAL, "inner_tol = %g outside [0, 1)", o->inner_tol);
+  if (o->inner_max_iter < 0) return fail(SL_EINVAL, "inner_max_iter = %d is negative", o->inner_max_iter);
   return SL_OK;
 }
 
@@ -148,6 +153,14 @@ struct sl_plan {
   // captured chunk of iterations, rebuilt when the loop parameters change
   hipGraphExec_t gexec = nullptr;
   std::vector<double> gkey;
+  // exact step (allocated on first use)
+  int32_t* comp = nullptr;      // lowest vertex of each vertex's component
+  CgVectors cg{};               // y, r, z (columns) and p (per vertex), double
+  double* cg_part = nullptr;    // (kCgSlots x cg_blocks(n_pad) + matvec blocks) x 8
+  CgState* cg_st = nullptr;
+  CgState* host_cg = nullptr;   // pinned mirror
+  hipGraphExec_t cg_gexec = nullptr;  // a group of conjugate-gradient steps
+  std::vector<double> cg_gkey;
 };
 
 namespace {
@@ -167,6 +180,13 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->st_eval);
   if (p->host_st) (void)hipHostFree(p->host_st);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  (void)hipFree(p->comp);
+  (void)hipFree(p->cg.y);
+  (void)hipFree(p->cg.pd);
+  (void)hipFree(p->cg_part);
+  (void)hipFree(p->cg_st);
+  if (p->host_cg) (void)hipHostFree(p->host_cg);
+  if (p->cg_gexec) (void)hipGraphExecDestroy(p->cg_gexec);
   if (p->ev_a) (void)hipEventDestroy(p->ev_a);
   if (p->ev_b) (void)hipEventDestroy(p->ev_b);
   if (p->ev_sync) (void)hipEventDestroy(p->ev_sync);
@@ -273,10 +293,10 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
   return SL_OK;
 }
 
-sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* o) {
-  HIP_TRY(launch_force(p->dim, lp.stress != 0, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
-                       p->ps),
-          "force kernel");
+// The steps of one iteration after X^H is known (or, for the Jacobi step, after
+// the force pass): update + extrapolation, safeguard or enumeration, select,
+// and the optional position trace.
+sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options* o) {
   HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
           "update kernel");
   if (lp.enumerate)
@@ -291,6 +311,115 @@ sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* 
   if (lp.enumerate)
     HIP_TRY(launch_apply_enum(p->Eb, p->Xb, p->stride, p->st, p->n, p->dim, p->ps), "enumeration apply kernel");
   if (o->xtrace) HIP_TRY(launch_record(p->Xb, p->stride, p->st, o->xtrace, p->n, p->dim, p->ps), "record kernel");
+  return SL_OK;
+}
+
+sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
+  HIP_TRY(launch_force(p->dim, lp.stress != 0, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
+                       p->ps),
+          "force kernel");
+  return SL_OK;
+}
+
+sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* o) {
+  sl_status s = enqueue_force(p, lp);
+  if (s != SL_OK) return s;
+  return enqueue_after_force(p, lp, o);
+}
+
+// Buffers of the exact step and the component of every vertex.
+sl_status ensure_exact(sl_plan* p) {
+  if (p->cg_st) return SL_OK;
+  const size_t col = (size_t)3 * p->n_pad;
+  const size_t nrec = (size_t)kCgSlots * cg_blocks(p->n_pad) + (size_t)p->sp.blocks_x * p->sp.slices;
+  hipError_t e = hipMalloc(&p->comp, sizeof(int32_t) * p->n_pad);
+  if (e == hipSuccess) e = hipMalloc(&p->cg.y, sizeof(double) * 3 * col);
+  if (e == hipSuccess) e = hipMalloc(&p->cg.pd, sizeof(double) * p->stride);
+  if (e == hipSuccess) e = hipMalloc(&p->cg_part, sizeof(double) * nrec * 8);
+  if (e == hipSuccess) e = hipHostMalloc(&p->host_cg, sizeof(CgState), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(&p->cg_st, sizeof(CgState));
+  if (e != hipSuccess) {
+    (void)hipFree(p->cg_st);
+    p->cg_st = nullptr;
+    return hip_fail(e, "exact-step buffers");
+  }
+  p->cg.n_pad = p->n_pad;
+  p->cg.r = p->cg.y + col;
+  p->cg.z = p->cg.y + 2 * col;
+  HIP_TRY(hipMemsetAsync(p->cg.y, 0, sizeof(double) * 3 * col, p->ps), "hipMemsetAsync");
+  HIP_TRY(hipMemsetAsync(p->cg.pd, 0, sizeof(double) * p->stride, p->ps), "hipMemsetAsync");
+  HIP_TRY(hipMemsetAsync(p->cg_part, 0, sizeof(double) * nrec * 8, p->ps), "hipMemsetAsync");
+  HIP_TRY(hipMemsetAsync(p->cg_st, 0, sizeof(CgState), p->ps), "hipMemsetAsync");
+  HIP_TRY(launch_components(p->d, p->comp, p->n, p->n_pad, p->sp.ng, p->ps), "components kernel");
+  return SL_OK;
+}
+
+constexpr int kCgGroup = 8;  // conjugate-gradient steps per launch between host polls
+
+sl_status enqueue_cg_group(sl_plan* p, double itol, int imax) {
+  for (int k = 0; k < kCgGroup; ++k)
+    HIP_TRY(launch_cg_step(p->dim, p->cg, p->d, p->W, p->comp, p->n, p->st, p->cg_st, p->cg_part, p->fpart, p->sp,
+                           itol, imax, p->ps),
+            "conjugate-gradient kernels");
+  return SL_OK;
+}
+
+// Algorithm 2 with the exact step: per iteration the force pass (r_0), the
+// solve in groups of kCgGroup steps until its stop flag, then the common tail.
+sl_status run_exact(sl_plan* p, LoopParams lp, const sl_options* o, bool use_graph, int* inner_total) {
+  sl_status s = ensure_exact(p);
+  if (s != SL_OK) return s;
+  lp.exact_y = p->cg.y;
+  const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-6;
+  const int imax = o->inner_max_iter > 0 ? o->inner_max_iter : 500;
+  if (use_graph) {
+    const std::vector<double> key = {(double)p->dim, itol, (double)imax};
+    if (!p->cg_gexec || key != p->cg_gkey) {
+      if (p->cg_gexec) {
+        (void)hipGraphExecDestroy(p->cg_gexec);
+        p->cg_gexec = nullptr;
+      }
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      const sl_status cs = enqueue_cg_group(p, itol, imax);
+      const hipError_t ce = hipStreamEndCapture(p->ps, &graph);
+      if (cs != SL_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cs;
+      }
+      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+      const hipError_t ie = hipGraphInstantiate(&p->cg_gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        p->cg_gexec = nullptr;
+        return hip_fail(ie, "hipGraphInstantiate");
+      }
+      p->cg_gkey = key;
+    }
+  }
+  DevState* h = p->host_st;
+  CgState* hc = p->host_cg;
+  const int max_groups = imax / kCgGroup + 2;
+  *inner_total = 0;
+  for (int k = 0; k < o->max_iter && !h->done; ++k) {
+    if ((s = enqueue_force(p, lp)) != SL_OK) return s;
+    HIP_TRY(launch_cg_init(p->dim, p->cg, p->fpart, p->sp.slices, p->W, p->comp, p->n, p->Xb, p->stride, p->st, p->cg_st,
+                           p->cg_part, p->ps),
+            "conjugate-gradient init kernel");
+    bool stopped = false;
+    for (int G = 0; G < max_groups && !stopped; ++G) {
+      if (use_graph) HIP_TRY(hipGraphLaunch(p->cg_gexec, p->ps), "hipGraphLaunch");
+      else if ((s = enqueue_cg_group(p, itol, imax)) != SL_OK) return s;
+      HIP_TRY(hipMemcpyAsync(hc, p->cg_st, sizeof(CgState), hipMemcpyDeviceToHost, p->ps), "solver state download");
+      HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+      stopped = hc->done != 0;
+    }
+    if (!stopped) return fail(SL_EDEVICE, "the conjugate-gradient solve did not reach its stop flag");
+    *inner_total += hc->iters;
+    if ((s = enqueue_after_force(p, lp, o)) != SL_OK) return s;
+    HIP_TRY(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->ps), "state download");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  }
   return SL_OK;
 }
 
@@ -465,7 +594,8 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   int chunk = o->check_every > 0 ? o->check_every : (p->n <= 8192 ? 32 : 4);
   chunk = std::max(1, std::min(chunk, std::max(1, o->max_iter)));
   const bool use_graph = !(o->flags & SL_FLAG_NO_GRAPH);
-  if (use_graph) {
+  const bool exact = o->ordering == SL_ORDER_EXACT;
+  if (use_graph && !exact) {
     std::vector<double> key = {(double)p->dim, lp.omega_p, lp.tol, (double)lp.safeguard, (double)lp.stress,
                                (double)chunk, (double)(uintptr_t)o->trace, (double)(uintptr_t)o->xtrace,
                                (double)lp.enumerate, (double)(uintptr_t)lp.omega_sched,
@@ -495,7 +625,12 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
     }
   }
   HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
-  const int max_launches = o->max_iter / chunk + 2;
+  if (exact) {
+    int inner = 0;
+    if ((s = run_exact(p, lp, o, use_graph, &inner)) != SL_OK) return s;
+    res.inner_iterations = inner;
+  }
+  const int max_launches = exact ? 0 : o->max_iter / chunk + 2;
   for (int L = 0; L < max_launches; ++L) {
     if (use_graph) {
       HIP_TRY(hipGraphLaunch(p->gexec, p->ps), "hipGraphLaunch");
@@ -555,8 +690,9 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   if (!(std::isfinite(omega) && omega > 0.0 && omega <= 16.0)) return fail(SL_EINVAL, "omega outside (0, 16]");
   sl_status s = join_from(p, (hipStream_t)stream);
   if (s != SL_OK) return s;
-  for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+  for (int k = 0; k < 5; ++k) ms[k] = 0.0;
   if (p->n <= 1) return SL_OK;
+  if ((s = ensure_exact(p)) != SL_OK) return s;
   LoopParams lp{};
   lp.n = p->n;
   lp.n_pad = p->n_pad;
@@ -573,10 +709,22 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   std::memset(h, 0, sizeof(DevState));
   h->max_iter = INT32_MAX;
   HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
-  for (int which = 0; which < 4; ++which) {
+  for (int which = 0; which < 5; ++which) {
+    if (which == 4) {  // a solver state from the current placement: r_0, z
+      HIP_TRY(launch_force(p->dim, false, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
+                           p->ps), "force kernel");
+      HIP_TRY(launch_cg_init(p->dim, p->cg, p->fpart, p->sp.slices, p->W, p->comp, p->n, p->Xb, p->stride, p->st, p->cg_st,
+                             p->cg_part, p->ps),
+              "conjugate-gradient init kernel");
+    }
     for (int r = -1; r < reps; ++r) {  // one untimed launch first
       if (r == 0) HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
       switch (which) {
+        case 4:
+          HIP_TRY(launch_lw(p->dim, p->cg, p->d, p->st, p->cg_st, p->fpart,
+                            p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->sp, p->ps),
+                  "L^W kernel");
+          break;
         case 0:
           HIP_TRY(launch_force(p->dim, false, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                                p->ps), "force kernel");
@@ -765,6 +913,7 @@ sl_status batch_params(const sl_batch_plan* p, const sl_options* o, BatchParams*
   if (o->trace || o->xtrace) return fail(SL_EINVAL, "traces are not available for batched layouts");
   if (o->strategy != SL_OMEGA_FIXED || o->omega_vertex)
     return fail(SL_EINVAL, "batched layouts take a fixed relaxation factor");
+  if (o->ordering != SL_ORDER_JACOBI) return fail(SL_ENOTSUP, "batched layouts use the Jacobi step");
   bp->omega_p = o->omega - 1.0;
   bp->tol = o->tol;
   bp->max_iter = o->max_iter;

@@ -67,7 +67,41 @@ struct LoopParams {
   int32_t pad;
   const double* omega_sched;  // device, paper's factors per iteration, or nullptr
   const float* omega_vertex;  // device, classical factors per vertex, or nullptr
+  // exact step: X^H = Y, the conjugate-gradient solution (double, column c at
+  // c * n_pad); nullptr for the Jacobi step
+  const double* exact_y;
 };
+
+// ---------------------------------------------------------------------------
+// Exact step H (eq. 5 solved by preconditioned conjugate gradients)
+// ---------------------------------------------------------------------------
+struct CgVectors {
+  int32_t n_pad, pad;
+  double *y, *r, *z;  // dim x n_pad each (column c at c * n_pad)
+  double* pd;         // search direction as double2 (dim 2) / double4 (dim 3), n_pad entries
+};
+
+// Step counters: `ja` is read by the update and direction kernels and copied
+// from `jb` by the matvec; `jb` is written by the direction kernel.  No kernel
+// reads a field it writes, so blocks of one launch never race on them.
+struct CgState {
+  int32_t ja, jb;
+  int32_t done;   // 1: converged or step limit; the remaining kernels return
+  int32_t iters;  // steps taken for the current H
+  double rel;     // ||r|| / ||r_0|| when the solve stopped
+};
+
+inline int cg_blocks(int n_pad) { return (n_pad + 255) / 256; }
+// Partial-sum records (8 doubles per block): two rotating slots of
+// [r.z, ||r||^2] per column, the initial slot, then one p.q record per matvec block.
+constexpr int kCgInitial = 2;
+constexpr int kCgSlots = 3;
+
+hipError_t launch_components(const uint8_t* d, int32_t* comp, int n, int n_pad, int ng, hipStream_t s);
+hipError_t launch_cg_init(int dim, const CgVectors& v, const double* fpart, int slices, const double* W,
+                          const int32_t* comp, int n, const float* Xb, size_t stride, const DevState* st, CgState* cg,
+                          double* part, hipStream_t s);
+
 
 // Work split of the all-pairs passes for a graph of n_pad vertices.
 struct Split {
@@ -78,6 +112,13 @@ struct Split {
   int blocks_x;         // workgroups along rows (4 waves each)
 };
 Split make_split(int n_pad);
+// One step: matvec (with the stop test), p/q update, Y/r/z update.
+hipError_t launch_cg_step(int dim, const CgVectors& v, const uint8_t* d, const double* W, const int32_t* comp, int n,
+                          const DevState* st, CgState* cg, double* part, double* qpart, const Split& sp, double tol,
+                          int max_steps, hipStream_t s);
+// One application of L^W to p (also used by the profiler).
+hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const DevState* st, CgState* cg, double* qpart,
+                     double* pqrec, const Split& sp, hipStream_t s);
 
 // ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);

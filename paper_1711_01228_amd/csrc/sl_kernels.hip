@@ -130,10 +130,12 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
   if (i < p.n) {
     const double wpi = p.omega_vertex ? (double)p.omega_vertex[i] - 1.0 : wp;
     double F[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < p.slices; ++s) {
-      const double* fp = fpart + (size_t)s * DIM * p.n_pad + i;
+    if (!p.exact_y) {
+      for (int s = 0; s < p.slices; ++s) {
+        const double* fp = fpart + (size_t)s * DIM * p.n_pad + i;
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) F[c] += fp[(size_t)c * p.n_pad];
+        for (int c = 0; c < DIM; ++c) F[c] += fp[(size_t)c * p.n_pad];
+      }
     }
     const V x = X[i];
     const double Wi = W[i];
@@ -143,7 +145,10 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
     bool bad = false;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      xh[c] = (Wi > 0.0) ? (float)((double)xv[c] + F[c] / Wi) : xv[c];
+      if (p.exact_y)  // the solve starts at Y = X^k and never moves held vertices
+        xh[c] = (float)p.exact_y[(size_t)c * p.n_pad + i];
+      else
+        xh[c] = (Wi > 0.0) ? (float)((double)xv[c] + F[c] / Wi) : xv[c];
       const double dl = (double)xh[c] - (double)xv[c];
       xt[c] = (float)((double)xh[c] + wpi * dl);
       v[0] += dl * dl;
