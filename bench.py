@@ -10,7 +10,8 @@ value = n (n - 1) * steps / seconds   (pair interactions of the force pass)
 
 Also reported: time-to-converge (res <= 1e-3) for omega = 1 and omega = 1.5
 from the same start, the same for the relaxation strategies of Sec. 5.2
-(probabilistic, enumerating, per-vertex factors), the roofline of the force kernel (HIP-event time), and
+(probabilistic, enumerating, per-vertex factors) and for the exact step H
+(eq. 5 solved by conjugate gradients), the roofline of the force kernel (HIP-event time), and
 the FP64 oracle's pair rate on a sample of rows on the host cores.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dim 2] [--quick]
@@ -27,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair-interactions/s + time-to-converge (SOR-ω vs ω=1) at n=65,536, 1 MI355X"
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed-FMA issue)
+PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 FLOPS_PER_PAIR = {2: 12, 3: 17}  # algorithmic flops of one ordered pair of the force pass
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_ba65536_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1711_01228_amd", "csrc", "sl_kernels.hip")
@@ -149,6 +151,37 @@ def bench_strategies(plan, Xdev0, n):
     return res
 
 
+def bench_exact(plan, Xdev0, n, ms):
+    """The paper's exact step H (eq. 5 solved by preconditioned CG on the
+    device) on the same plan and start: time to res <= 1e-3 at omega = 1 and
+    1.5, and the HBM roofline of the L^W matvec (one distance byte per ordered
+    pair)."""
+    import torch
+
+    res = {}
+    for om in (1.0, 1.5):
+        X = Xdev0.clone()
+        plan.run(X, omega=om, tol=0.0, max_iter=1, ordering="exact")  # warm (allocation, capture)
+        X = Xdev0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = plan.run(X, omega=om, tol=1e-3, max_iter=500, ordering="exact")
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t
+        res["omega=%g" % om] = {"seconds_to_tol": round(w, 4), "iterations": r["iterations"],
+                                "cg_steps": r["inner_iterations"], "converged": bool(r["converged"]),
+                                "rejected": r["rejected"], "final_residual": r["residual"],
+                                "final_stress": r["stress"]}
+        log("exact omega=%g: %s" % (om, res["omega=%g" % om]))
+    t_lw = ms["lw_matvec"] * 1e-3
+    gbs = float(n) * n / t_lw / 1e9
+    res["lw_matvec_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                 "frac": round(gbs / PEAK_HBM_GBPS, 4), "kernel": "k_lw",
+                                 "kernel_ms": round(ms["lw_matvec"], 4), "algorithmic_bytes_per_launch": float(n) * n}
+    res["inner_tol"] = 1e-6
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +195,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D run of the same workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched small-graph run")
     ap.add_argument("--no-strategies", action="store_true", help="skip the relaxation-strategy comparison")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact-step (eq. 5 solved) comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -245,6 +279,8 @@ def main():
         out["time_to_converge"] = ttc
         if not args.no_strategies:
             out["strategies"] = bench_strategies(plan, Xdev0, n)
+        if not args.no_exact:
+            out["exact"] = bench_exact(plan, Xdev0, n, ms)
     plan.close()
     del plan
 
