@@ -8,8 +8,9 @@ A thin ctypes wrapper over ``sorlayout_oracle.c``: plain IEEE-double C that
 writes out the paper's definitions (Wang & Wang 2012): the stress (eq. 1), the
 Laplacians and majorant (Prop. 2.1, eq. 2), the majorization step as the
 solution of eq. 5 (Prop. 2.3) in three orderings, and Algorithm 2 with the
-extrapolation of eq. 10/11.  See the C file for the definitions; this module
-only marshals numpy arrays.
+extrapolation of eq. 10/11, and the reverse-mode derivative of the unrolled
+iteration (initial placement and, through the shortest paths, edge lengths).
+See the C file for the definitions; this module only marshals numpy arrays.
 
 Relaxation factor convention: ``omega`` is the classical factor, the paper's
 factor is ``omega - 1`` (``omega = 1`` is Algorithm 1).
@@ -82,6 +83,10 @@ def _load():
                 "slo_residual": (f64, [i32, i32, P, P]),
                 "slo_layout": (ctypes.c_int, [i32, i32, P, P, f64, f64, i32, i32, i32, i32, P, P, i32, P, P,
                                               ctypes.POINTER(_Result)]),
+                "slo_sp_trees": (ctypes.c_int, [i32, P, P, P, P, P]),
+                "slo_stress_grad": (None, [i32, i32, P, P, P]),
+                "slo_layout_vjp": (ctypes.c_int, [i32, i32, P, P, f64, i32, P, P, P, P]),
+                "slo_edge_grad": (ctypes.c_int, [i32, P, P, P, P, P]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(lib, name)
@@ -284,3 +289,62 @@ def layout(D, X0, omega=1.0, tol=1e-3, max_iter=200, ordering="jacobi", safeguar
 AUTO_FACTORS = (0.5, 1.0, 1.5, 2.0)
 AUTO_PROBS = (0.3, 0.3, 0.2, 0.2)
 ENUM_FACTORS = tuple(0.5 * c for c in range(19))
+
+
+# --------------------------------------------------------------------------
+# Derivatives of the unrolled iteration (reverse mode, FP64)
+# --------------------------------------------------------------------------
+def sp_trees(row_ptr, col_idx, lengths):
+    """(D, pred): shortest-path distances for positive edge lengths and the
+    shortest-path tree of every source (pred[s][v] = lowest-numbered neighbour
+    on a shortest path, -1 for s and unreachable v).  D is made symmetric from
+    its upper triangle: d_ts := d_st for s < t (the tree of the lower-numbered
+    end defines the pair)."""
+    lib = _load()
+    rp, ci, ln = _csr(row_ptr, col_idx, lengths)
+    n = len(rp) - 1
+    D = np.empty((n, n), dtype=np.float64)
+    P = np.empty((n, n), dtype=np.int32)
+    _check(lib.slo_sp_trees(n, _p(rp), _p(ci), _p(ln), _p(D), _p(P)), "sp_trees")
+    iu = np.triu_indices(n, 1)
+    D.T[iu] = D[iu]
+    return D, P
+
+
+def stress_grad(D, X) -> np.ndarray:
+    """Gradient of eq. 1 with respect to X."""
+    lib = _load()
+    D, X = _f64(D), _f64(X)
+    G = np.empty_like(X)
+    lib.slo_stress_grad(D.shape[0], X.shape[1], _p(D), _p(X), _p(G))
+    return G
+
+
+def layout_vjp(D, X0, omega, iters, accepted, G):
+    """(dL/dX0, dL/dD) for L a function of X^K after K = iters Jacobi-SOR
+    iterations with the safeguard decisions held at ``accepted`` (trace column
+    1 of ``layout``); G = dL/dX^K.  dL/dD is symmetric: d_ij and d_ji are one
+    variable."""
+    lib = _load()
+    D, X0, G = _f64(D), _f64(X0), _f64(G)
+    acc = _f64(accepted)
+    n, dim = X0.shape
+    assert len(acc) >= iters
+    gX0 = np.empty_like(X0)
+    gD = np.empty((n, n), dtype=np.float64)
+    _check(lib.slo_layout_vjp(n, dim, _p(D), _p(X0), float(omega), int(iters), _p(acc), _p(G), _p(gX0), _p(gD)),
+           "layout_vjp")
+    return gX0, gD
+
+
+def edge_grad(row_ptr, col_idx, pred, gD) -> np.ndarray:
+    """dL/dlen per CSR entry from dL/dD through the shortest-path trees."""
+    lib = _load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    P = np.ascontiguousarray(pred, dtype=np.int32)
+    gD = _f64(gD)
+    n = len(rp) - 1
+    out = np.empty(int(rp[-1]), dtype=np.float64)
+    _check(lib.slo_edge_grad(n, _p(rp), _p(ci), _p(P), _p(gD), _p(out)), "edge_grad")
+    return out

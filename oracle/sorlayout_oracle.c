@@ -651,3 +651,181 @@ int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega,
   out->status = status;
   return status;
 }
+
+/* ====================================================================== */
+/* Derivatives (reverse mode) of the unrolled Jacobi-SOR iteration.       */
+/* ====================================================================== */
+
+/* Shortest-path tree of source src for positive edge lengths: drow as
+ * slo_sssp computes it (Dijkstra), pred[v] = the lowest-numbered neighbour u
+ * with drow[u] + len(u, v) == drow[v] (ties broken by the lowest id), -1 for
+ * src and for vertices with no path.  Lengths must be symmetric. */
+int slo_sp_tree(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* len, int32_t src,
+                double* drow, int32_t* pred) {
+  int r = slo_sssp(n, row_ptr, col_idx, len, src, drow);
+  if (r != SLO_OK) return r;
+  for (int32_t v = 0; v < n; ++v) {
+    pred[v] = -1;
+    if (v == src || isinf(drow[v])) continue;
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      int32_t u = col_idx[e];
+      double l = len ? len[e] : 1.0;
+      if (drow[u] + l == drow[v] && (pred[v] < 0 || u < pred[v])) pred[v] = u;
+    }
+  }
+  return SLO_OK;
+}
+
+int slo_sp_trees(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* len, double* D,
+                 int32_t* P) {
+  int status = SLO_OK;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t s = 0; s < n; ++s) {
+    int r = slo_sp_tree(n, row_ptr, col_idx, len, s, D + (size_t)s * n, P + (size_t)s * n);
+    if (r != SLO_OK) {
+#pragma omp critical
+      status = r;
+    }
+  }
+  return status;
+}
+
+/* Gradient of the stress (eq. 1): G_i = sum_{j != i} 2 w_ij (r_ij - d_ij) u_ij,
+ * u_ij = (x_i - x_j) / r_ij (pairs with r_ij = 0 contribute 0). */
+void slo_stress_grad(int32_t n, int32_t dim, const double* D, const double* X, double* G) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t c = 0; c < dim; ++c) G[(size_t)i * dim + c] = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double d = D[(size_t)i * n + j];
+      double w = w_of(d);
+      double r = dist(dim, X + (size_t)i * dim, X + (size_t)j * dim);
+      if (w == 0.0 || r == 0.0) continue;
+      for (int32_t c = 0; c < dim; ++c)
+        G[(size_t)i * dim + c] += 2.0 * w * (r - d) * (X[(size_t)i * dim + c] - X[(size_t)j * dim + c]) / r;
+    }
+  }
+}
+
+/* Reverse mode through K iterations of Algorithm 2 with the Jacobi step and
+ * a fixed omega, the safeguard decisions held at acc[k] (1: X~ kept, else
+ * X^H kept; as the trace column of slo_layout records them).
+ *
+ * Forward, row form of eq. 5 (one sweep, the other vertices at X):
+ *   x^H_i = (1/W_i) [ sum_j w_ij x_j + sum_j (1/d_ij) u_ij ],  W_i = sum_j w_ij,
+ *   X^{k+1} = a X^H - b X,   (a, b) = (omega, omega - 1) if acc[k] = 1, else (1, 0).
+ * Backward, with h = dL/dX^H = a Gbar and g_i = h_i / W_i:
+ *   dx^H_i/dx_i = (1/W_i) sum_j P_ij,  dx^H_i/dx_j = (1/W_i) (w_ij I - P_ij),
+ *   P_ij = (1/(d_ij r_ij)) (I - u_ij u_ij^T),
+ *   dL/dx_m = sum_j P_mj (g_m - g_j) + sum_j w_mj g_j - b Gbar_m,
+ *   dL/dd_ij (row i's use of d_ij) += g_i . [ -2 w_ij (1/d_ij) (x_j - x^H_i) - w_ij u_ij ].
+ * A vertex with W_i = 0 keeps its place: dL/dx_i gets h_i.
+ * Outputs: gX0 = dL/dX^0 (n x dim), gD (n x n) = dL/dd with d_ij and d_ji one
+ * variable (gD[i][j] = gD[j][i] = the two row uses summed). */
+int slo_layout_vjp(int32_t n, int32_t dim, const double* D, const double* X0, double omega, int32_t K,
+                   const double* acc, const double* G, double* gX0, double* gD) {
+  size_t nd = (size_t)n * dim;
+  double* Xs = (double*)malloc(sizeof(double) * nd * (size_t)(K + 1));
+  double* XHs = (double*)malloc(sizeof(double) * nd * (size_t)(K > 0 ? K : 1));
+  double* W = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* gb = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  double* gw = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  double* gn = (double*)malloc(sizeof(double) * (nd ? nd : 1));
+  if (!Xs || !XHs || !W || !gb || !gw || !gn) {
+    free(Xs); free(XHs); free(W); free(gb); free(gw); free(gn);
+    return SLO_ENOMEM;
+  }
+  slo_weight_sums(n, D, W);
+  memcpy(Xs, X0, sizeof(double) * nd);
+  for (int32_t k = 0; k < K; ++k) {
+    const double* X = Xs + (size_t)k * nd;
+    double* XH = XHs + (size_t)k * nd;
+    double* Xn = Xs + (size_t)(k + 1) * nd;
+    slo_h_jacobi(n, dim, D, X, XH);
+    double a = acc[k] == 1.0 ? omega : 1.0, b = acc[k] == 1.0 ? omega - 1.0 : 0.0;
+    for (size_t q = 0; q < nd; ++q) Xn[q] = a * XH[q] - b * X[q];
+  }
+  memcpy(gb, G, sizeof(double) * nd);
+  memset(gD, 0, sizeof(double) * (size_t)n * n);
+  for (int32_t k = K - 1; k >= 0; --k) {
+    const double* X = Xs + (size_t)k * nd;
+    const double* XH = XHs + (size_t)k * nd;
+    double a = acc[k] == 1.0 ? omega : 1.0, b = acc[k] == 1.0 ? omega - 1.0 : 0.0;
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t c = 0; c < dim; ++c)
+        gw[(size_t)i * dim + c] = W[i] > 0.0 ? a * gb[(size_t)i * dim + c] / W[i] : 0.0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t m = 0; m < n; ++m) {
+      double acc_m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (W[m] == 0.0)
+        for (int32_t c = 0; c < dim; ++c) acc_m[c] = a * gb[(size_t)m * dim + c];
+      for (int32_t j = 0; j < n; ++j) {
+        if (j == m) continue;
+        double d = D[(size_t)m * n + j];
+        double w = w_of(d);
+        if (w == 0.0) continue;
+        const double* xm = X + (size_t)m * dim;
+        const double* xj = X + (size_t)j * dim;
+        double r = dist(dim, xm, xj);
+        const double* gm = gw + (size_t)m * dim;
+        const double* gj = gw + (size_t)j * dim;
+        /* sum_j w_mj g_j */
+        for (int32_t c = 0; c < dim; ++c) acc_m[c] += w * gj[c];
+        if (r == 0.0) continue;
+        /* P_mj (g_m - g_j) = (1/(d r)) [e - u (u . e)],  e = g_m - g_j */
+        double ue = 0.0;
+        for (int32_t c = 0; c < dim; ++c) ue += (xm[c] - xj[c]) / r * (gm[c] - gj[c]);
+        for (int32_t c = 0; c < dim; ++c)
+          acc_m[c] += ((gm[c] - gj[c]) - (xm[c] - xj[c]) / r * ue) / (d * r);
+        /* row m's use of d_mj */
+        double t = 0.0;
+        for (int32_t c = 0; c < dim; ++c)
+          t += gm[c] * (-2.0 * w / d * (xj[c] - XH[(size_t)m * dim + c]) - w * (xm[c] - xj[c]) / r);
+        gD[(size_t)m * n + j] += t;
+      }
+      for (int32_t c = 0; c < dim; ++c) gn[(size_t)m * dim + c] = acc_m[c] - b * gb[(size_t)m * dim + c];
+    }
+    memcpy(gb, gn, sizeof(double) * nd);
+  }
+  memcpy(gX0, gb, sizeof(double) * nd);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t j = i + 1; j < n; ++j) {
+      double s = gD[(size_t)i * n + j] + gD[(size_t)j * n + i];
+      gD[(size_t)i * n + j] = s;
+      gD[(size_t)j * n + i] = s;
+    }
+  free(Xs); free(XHs); free(W); free(gb); free(gw); free(gn);
+  return SLO_OK;
+}
+
+/* dL/dlen for every CSR entry, by the chain rule through the shortest paths:
+ * the distance of a pair s < t is the length of the tree path from s to t in
+ * the tree of source s (pred, n x n), so every edge on that path receives
+ * gD[s][t].  Both CSR entries of an edge get the edge's derivative.  Walks
+ * every pair's path explicitly. */
+int slo_edge_grad(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* P, const double* gD,
+                  double* glen) {
+  int64_t nnz = row_ptr[n];
+  double* ge = (double*)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(double));
+  if (!ge) return SLO_ENOMEM;
+  for (int32_t s = 0; s < n; ++s) {
+    const int32_t* pr = P + (size_t)s * n;
+    for (int32_t t = s + 1; t < n; ++t) {
+      if (pr[t] < 0) continue;
+      double g = gD[(size_t)s * n + t];
+      int32_t v = t;
+      while (v != s) {
+        int32_t u = pr[v];
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+          if (col_idx[e] == u) ge[e] += g;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+          if (col_idx[e] == v) ge[e] += g;
+        v = u;
+      }
+    }
+  }
+  memcpy(glen, ge, sizeof(double) * (size_t)nnz);
+  free(ge);
+  return SLO_OK;
+}
