@@ -96,9 +96,14 @@ typedef struct {
   int64_t nnz;              /* 2|E| = row_ptr[n]                                   */
   const int64_t* row_ptr;   /* n + 1 offsets, row_ptr[0] = 0, non-decreasing        */
   const int32_t* col_idx;   /* nnz neighbour ids in [0, n)                         */
-  const float* edge_len;    /* NULL: unit edges (hop distances).  Edge lengths are
-                               not handled by this build: non-NULL -> SL_ENOTSUP  */
+  const float* edge_len;    /* NULL: unit edges, d_ij = hop count (bytes on the device,
+                               at most 255).  Else nnz positive lengths, equal on both
+                               entries of an edge: d_ij = shortest-path length, summed
+                               in FP32 along the path (Sec. 5.4 lays out a net with edge
+                               lengths); n <= SL_WEIGHTED_MAX_N (else SL_ENOTSUP)     */
 } sl_graph;
+
+#define SL_WEIGHTED_MAX_N 16384  /* vertices of a graph with edge lengths */
 
 typedef struct {
   int32_t dim;              /* 2 or 3                                              */
@@ -167,17 +172,36 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
  *   4. keep X~ iff f(X~) - f(X^H) <= 0              (Alg. 2, lines 6-8)
  *   5. stop when res_k <= tol or after max_iter steps
  * `out` may be NULL.  Not converging within max_iter is not an error.
+ * Edge-length plans run the Jacobi step with a fixed, scheduled or per-vertex
+ * factor (SL_OMEGA_ENUM and SL_ORDER_EXACT: SL_ENOTSUP).
  * Errors: SL_EINVAL (opt, or opt->dim differs from the plan's), SL_ENUMERIC
- * (X is then the last finite iterate), SL_EDEVICE. */
+ * (X is then the last finite iterate), SL_ENOTSUP, SL_EDEVICE. */
 sl_status sl_plan_run(sl_plan* plan, float* X, const sl_options* opt, void* stream, sl_result* out);
 
 /* f(X) of eq. 1 for a device placement X (n * dim floats), into *f (host). */
 sl_status sl_plan_stress(sl_plan* plan, const float* X, int32_t dim, void* stream, double* f);
 
-/* Copy distance rows out of a plan: out[k * n + j] = d(rows[k], j) as stored
- * (0 for j = rows[k] or no path).  `rows` and `out` are host memory. */
+/* Copy distance rows out of a hop-count plan: out[k * n + j] = d(rows[k], j)
+ * as stored (0 for j = rows[k] or no path).  `rows` and `out` are host memory.
+ * SL_EINVAL for an edge-length plan. */
 sl_status sl_plan_distance_rows(sl_plan* plan, const int32_t* rows, int32_t nrows, void* stream,
                                 uint8_t* out);
+
+/* The same as floats, for both kinds of plan: hop counts or path lengths
+ * (0 for j = rows[k] or no path).  `rows` and `out` (nrows * n) are host memory. */
+sl_status sl_plan_distance_rows_f32(sl_plan* plan, const int32_t* rows, int32_t nrows, void* stream, float* out);
+
+/* Edge-length plans: rows of the shortest-path trees, out[k * n + v] = the
+ * predecessor of v on the path from rows[k] (the lowest-numbered neighbour u
+ * with d(rows[k], u) + len(u, v) = d(rows[k], v)), -1 for v = rows[k] or no
+ * path.  The distance of a pair s < t is the length of the tree path of s
+ * (d_ts is set to d_st).  Host memory; SL_EINVAL for hop-count plans. */
+sl_status sl_plan_tree_rows(sl_plan* plan, const int32_t* rows, int32_t nrows, void* stream, int32_t* out);
+
+/* Edge-length plans: replace the lengths (host, nnz, same graph) and rebuild
+ * the distances, trees and weight sums.  Errors: SL_EINVAL (not an
+ * edge-length plan, lengths invalid), SL_EDEVICE. */
+sl_status sl_plan_set_lengths(sl_plan* plan, const float* edge_len, void* stream);
 
 /* Copy the weight sums W_i (n doubles) to host memory. */
 sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
@@ -190,7 +214,7 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  *   ms[0] all-pairs force pass   ms[1] Jacobi update + extrapolation
  *   ms[2] safeguard pass         ms[3] select + termination test
  *   ms[4] one application of L^W (the all-pairs matvec of a conjugate-
- *         gradient step of SL_ORDER_EXACT)
+ *         gradient step of SL_ORDER_EXACT; 0 for edge-length plans)
  * For profilers and benchmarks; the iterate buffers of the plan are left in an
  * unspecified state (a later sl_plan_run starts from its own X). */
 sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,

@@ -38,7 +38,8 @@ def auto_schedule(max_iter: int, seed: int) -> np.ndarray:
 EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run", "sl_plan_stress",
             "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
             "sl_last_error", "sl_batch_plan_create", "sl_batch_plan_tune", "sl_batch_plan_run",
-            "sl_batch_plan_destroy")
+            "sl_batch_plan_destroy", "sl_plan_distance_rows_f32", "sl_plan_tree_rows", "sl_plan_set_lengths")
+SL_WEIGHTED_MAX_N = 16384
 SL_BATCH_MAX_N = 1024
 SL_BATCH_CLASSES = 16
 
@@ -99,6 +100,9 @@ def _load():
         "sl_plan_stress": (st, [P, P, i32, P, ctypes.POINTER(ctypes.c_double)]),
         "sl_plan_distance_rows": (st, [P, P, i32, P, P]),
         "sl_plan_weights": (st, [P, P, P]),
+        "sl_plan_distance_rows_f32": (st, [P, P, i32, P, P]),
+        "sl_plan_tree_rows": (st, [P, P, i32, P, P]),
+        "sl_plan_set_lengths": (st, [P, P, P]),
         "sl_plan_profile": (st, [P, P, i32, ctypes.c_double, i32, P, P]),
         "sl_plan_destroy": (st, [P]),
         "sl_layout": (st, [ctypes.POINTER(sl_graph), P, ctypes.POINTER(sl_options), P, ctypes.POINTER(sl_result)]),
@@ -213,6 +217,25 @@ def sl_plan_distance_rows(plan: int, rows, n: int, stream=None) -> np.ndarray:
     return out
 
 
+def sl_plan_distance_rows_f32(plan: int, rows, n: int, stream=None) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((len(rows), n), dtype=np.float32)
+    _check(LIB.sl_plan_distance_rows_f32(plan, rows.ctypes.data, len(rows), _stream_handle(stream), out.ctypes.data))
+    return out
+
+
+def sl_plan_tree_rows(plan: int, rows, n: int, stream=None) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((len(rows), n), dtype=np.int32)
+    _check(LIB.sl_plan_tree_rows(plan, rows.ctypes.data, len(rows), _stream_handle(stream), out.ctypes.data))
+    return out
+
+
+def sl_plan_set_lengths(plan: int, edge_len, stream=None) -> None:
+    ln = np.ascontiguousarray(edge_len, dtype=np.float32)
+    _check(LIB.sl_plan_set_lengths(plan, ln.ctypes.data, _stream_handle(stream)))
+
+
 def sl_plan_weights(plan: int, n: int, stream=None) -> np.ndarray:
     W = np.zeros(n, dtype=np.float64)
     _check(LIB.sl_plan_weights(plan, _stream_handle(stream), W.ctypes.data))
@@ -297,6 +320,16 @@ class Plan:
 
     def weights(self, stream=None) -> np.ndarray:
         return sl_plan_weights(self.handle, self.n, stream)
+
+    def distance_rows_f32(self, rows, stream=None) -> np.ndarray:
+        return sl_plan_distance_rows_f32(self.handle, rows, self.n, stream)
+
+    def tree_rows(self, rows, stream=None) -> np.ndarray:
+        return sl_plan_tree_rows(self.handle, rows, self.n, stream)
+
+    def set_lengths(self, edge_len, stream=None) -> None:
+        """New lengths per CSR entry (same graph); rebuilds distances and trees."""
+        sl_plan_set_lengths(self.handle, edge_len, stream)
 
     def profile(self, X, omega=1.5, reps=5, stream=None) -> dict:
         """Average device ms of each kernel of one iteration (HIP events)."""

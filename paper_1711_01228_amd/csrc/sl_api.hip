@@ -43,6 +43,23 @@ sl_status hip_fail(hipError_t e, const char* what) {
 // ---------------------------------------------------------------------------
 // Host-side validation (no HIP calls)
 // ---------------------------------------------------------------------------
+// Edge lengths: positive, finite, the same on both entries of an edge.
+sl_status check_lengths(const sl_graph* g, const float* len) {
+  for (int64_t e = 0; e < g->nnz; ++e)
+    if (!(std::isfinite(len[e]) && len[e] > 0.f))
+      return fail(SL_EINVAL, "edge_len[%lld] is not a positive finite number", (long long)e);
+  for (int64_t v = 0; v < g->n; ++v)
+    for (int64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e) {
+      const int32_t u = g->col_idx[e];
+      for (int64_t f = g->row_ptr[u]; f < g->row_ptr[u + 1]; ++f)
+        if (g->col_idx[f] == v && len[f] != len[e])
+          return fail(SL_EINVAL, "edge (%lld, %d) has two different lengths", (long long)v, u);
+    }
+  if (g->n > kWeightedMaxN)
+    return fail(SL_ENOTSUP, "weighted graphs are limited to %d vertices (n = %d)", kWeightedMaxN, g->n);
+  return SL_OK;
+}
+
 sl_status check_graph(const sl_graph* g) {
   if (!g) return fail(SL_EINVAL, "graph is NULL");
   if (g->n < 0) return fail(SL_EINVAL, "n = %d is negative", g->n);
@@ -82,12 +99,7 @@ sl_status check_graph(const sl_graph* g) {
         return fail(SL_EINVAL, "graph is not symmetric: (%lld, %d) has no reverse entry", (long long)v, u);
     }
   }
-  if (g->edge_len) {
-    for (int64_t e = 0; e < g->nnz; ++e)
-      if (!(std::isfinite(g->edge_len[e]) && g->edge_len[e] > 0.f))
-        return fail(SL_EINVAL, "edge_len[%lld] is not a positive finite number", (long long)e);
-    return fail(SL_ENOTSUP, "edge lengths (weighted distances) are not supported by this build");
-  }
+  if (g->edge_len) return check_lengths(g, g->edge_len);
   return SL_OK;
 }
 
@@ -132,7 +144,15 @@ struct sl_plan {
   Split sp{};
   hipStream_t ps = nullptr;     // the plan's own stream (default priority)
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_sync = nullptr;
-  uint8_t* d = nullptr;         // n_pad^2 bytes, tile-major
+  uint8_t* d = nullptr;         // n_pad^2 bytes, tile-major (hop counts)
+  // weighted graphs: FP32 distances instead of d, the shortest-path trees and
+  // the CSR on the device (lengths can be replaced: sl_plan_set_lengths)
+  float* df = nullptr;          // n_pad^2 floats, tile-major
+  int32_t* pred = nullptr;      // n x n, row-major
+  int64_t* g_row_ptr = nullptr;
+  int32_t* g_col_idx = nullptr;
+  float* g_len = nullptr;
+  int64_t nnz = 0;
   double* W = nullptr;          // n_pad
   float* Xb = nullptr;          // 3 iterate buffers
   float* Eb = nullptr;          // x~ - x^H, same format as one iterate buffer
@@ -167,6 +187,11 @@ namespace {
 
 sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->d);
+  (void)hipFree(p->df);
+  (void)hipFree(p->pred);
+  (void)hipFree(p->g_row_ptr);
+  (void)hipFree(p->g_col_idx);
+  (void)hipFree(p->g_len);
   (void)hipFree(p->W);
   (void)hipFree(p->Xb);
   (void)hipFree(p->Eb);
@@ -227,8 +252,19 @@ sl_status join_to(sl_plan* p, hipStream_t user) {
 
 // Multi-source BFS, bfs_sources_per_sweep() sources per sweep, then W.
 // Distances above 255 hops are refused (SL_ERANGE).
+// Weighted graphs: shortest paths on the device from the plan's CSR copy.
+sl_status build_weighted(sl_plan* p) {
+  HIP_TRY(hipMemsetAsync(p->df, 0, sizeof(float) * (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
+  HIP_TRY(launch_wsssp(p->g_row_ptr, p->g_col_idx, p->g_len, p->n, p->sp.ng, p->df, p->pred, p->ps),
+          "shortest-path kernel");
+  HIP_TRY(launch_wsym(p->df, p->n_pad, p->sp.ng, p->ps), "symmetrize kernel");
+  HIP_TRY(launch_weights(nullptr, p->df, p->W, p->sp, p->n, p->ps), "weights kernel");
+  return SL_OK;
+}
+
 sl_status build_distances(sl_plan* p, const sl_graph* g) {
   const int n = p->n;
+  if (p->df) return build_weighted(p);
   HIP_TRY(hipMemsetAsync(p->d, 0, (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
   if (n > 1 && g->nnz > 0) {
     // source row of every CSR entry, for the edge-parallel gather
@@ -289,7 +325,7 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     if (e != hipSuccess) return hip_fail(e, "breadth-first search");
     if (status != SL_OK) return status;
   }
-  HIP_TRY(launch_weights(p->d, p->W, p->sp, n, p->ps), "weights kernel");
+  HIP_TRY(launch_weights(p->d, nullptr, p->W, p->sp, n, p->ps), "weights kernel");
   return SL_OK;
 }
 
@@ -304,7 +340,7 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
                                 p->ps),
             "enumeration kernel");
   else if (lp.safeguard && (lp.omega_p != 0.0 || lp.omega_sched || lp.omega_vertex))
-    HIP_TRY(launch_sgdelta(p->dim, p->d, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart, p->sp,
+    HIP_TRY(launch_sgdelta(p->dim, p->d, p->df, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart, p->sp,
                            p->ps),
             "safeguard kernel");
   HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsg, p->st, o->trace, p->ps), "select kernel");
@@ -315,7 +351,7 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
 }
 
 sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
-  HIP_TRY(launch_force(p->dim, lp.stress != 0, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
+  HIP_TRY(launch_force(p->dim, lp.stress != 0, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                        p->ps),
           "force kernel");
   return SL_OK;
@@ -428,7 +464,7 @@ sl_status stress_pass(sl_plan* p, int cur, double* f) {
   std::memset(h, 0, sizeof(DevState));
   h->cur = cur;
   HIP_TRY(hipMemcpyAsync(p->st_eval, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
-  HIP_TRY(launch_force(p->dim, true, p->d, p->Xb, p->stride, p->st_eval, p->fpart, p->spart, p->sp, p->n_pad,
+  HIP_TRY(launch_force(p->dim, true, p->d, p->df, p->Xb, p->stride, p->st_eval, p->fpart, p->spart, p->sp, p->n_pad,
                        p->ps),
           "force kernel");
   HIP_TRY(launch_stress_sum(p->spart, p->sp.slices, p->n_pad, p->st_eval, p->ps), "stress kernel");
@@ -490,7 +526,22 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess) e = hipEventCreate(&p->ev_a);
   if (e == hipSuccess) e = hipEventCreate(&p->ev_b);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_sync, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMalloc(&p->d, (size_t)p->n_pad * p->n_pad);
+  if (g->edge_len) {
+    p->nnz = g->nnz;
+    if (e == hipSuccess) e = hipMalloc(&p->df, sizeof(float) * (size_t)p->n_pad * p->n_pad);
+    if (e == hipSuccess) e = hipMalloc(&p->pred, sizeof(int32_t) * std::max<size_t>(1, (size_t)p->n * p->n));
+    if (e == hipSuccess) e = hipMalloc(&p->g_row_ptr, sizeof(int64_t) * (p->n + 1));
+    if (e == hipSuccess) e = hipMalloc(&p->g_col_idx, sizeof(int32_t) * std::max<int64_t>(1, g->nnz));
+    if (e == hipSuccess) e = hipMalloc(&p->g_len, sizeof(float) * std::max<int64_t>(1, g->nnz));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->g_row_ptr, g->row_ptr, sizeof(int64_t) * (p->n + 1), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess && g->nnz > 0)
+      e = hipMemcpyAsync(p->g_col_idx, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess && g->nnz > 0)
+      e = hipMemcpyAsync(p->g_len, g->edge_len, sizeof(float) * g->nnz, hipMemcpyHostToDevice, p->ps);
+  } else if (e == hipSuccess) {
+    e = hipMalloc(&p->d, (size_t)p->n_pad * p->n_pad);
+  }
   if (e == hipSuccess) e = hipMalloc(&p->W, sizeof(double) * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->Xb, sizeof(float) * 3 * p->stride);
   if (e == hipSuccess) e = hipMalloc(&p->Eb, sizeof(float) * p->stride);
@@ -536,6 +587,8 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   if (s != SL_OK) return s;
   if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
   if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
+  if (p->df && (o->strategy == SL_OMEGA_ENUM || o->ordering == SL_ORDER_EXACT))
+    return fail(SL_ENOTSUP, "edge-length plans run the Jacobi step with a fixed, scheduled or per-vertex factor");
   hipStream_t user = (hipStream_t)stream;
   sl_result res{};
   res.plan_ms = p->plan_ms;
@@ -692,7 +745,8 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   if (s != SL_OK) return s;
   for (int k = 0; k < 5; ++k) ms[k] = 0.0;
   if (p->n <= 1) return SL_OK;
-  if ((s = ensure_exact(p)) != SL_OK) return s;
+  const int kinds = p->df ? 4 : 5;  // the L^W matvec exists for hop-count plans
+  if (kinds == 5 && (s = ensure_exact(p)) != SL_OK) return s;
   LoopParams lp{};
   lp.n = p->n;
   lp.n_pad = p->n_pad;
@@ -709,9 +763,9 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   std::memset(h, 0, sizeof(DevState));
   h->max_iter = INT32_MAX;
   HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
-  for (int which = 0; which < 5; ++which) {
+  for (int which = 0; which < kinds; ++which) {
     if (which == 4) {  // a solver state from the current placement: r_0, z
-      HIP_TRY(launch_force(p->dim, false, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
+      HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                            p->ps), "force kernel");
       HIP_TRY(launch_cg_init(p->dim, p->cg, p->fpart, p->sp.slices, p->W, p->comp, p->n, p->Xb, p->stride, p->st, p->cg_st,
                              p->cg_part, p->ps),
@@ -726,7 +780,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                   "L^W kernel");
           break;
         case 0:
-          HIP_TRY(launch_force(p->dim, false, p->d, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
+          HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                                p->ps), "force kernel");
           break;
         case 1:
@@ -735,7 +789,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                   "update kernel");
           break;
         case 2:
-          HIP_TRY(launch_sgdelta(p->dim, p->d, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart,
+          HIP_TRY(launch_sgdelta(p->dim, p->d, p->df, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart,
                                  p->sp, p->ps),
                   "safeguard kernel");
           break;
@@ -753,30 +807,101 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   return join_to(p, (hipStream_t)stream);
 }
 
-sl_status sl_plan_distance_rows(sl_plan* p, const int32_t* rows, int32_t nrows, void* stream, uint8_t* out) {
-  g_err.clear();
+namespace {
+
+sl_status check_rows(const sl_plan* p, const int32_t* rows, int32_t nrows, const void* out) {
   if (!p) return fail(SL_EINVAL, "plan is NULL");
   if (nrows < 0) return fail(SL_EINVAL, "nrows is negative");
-  if (nrows == 0) return SL_OK;
-  if (!rows || !out) return fail(SL_EINVAL, "rows or out is NULL");
+  if (nrows > 0 && (!rows || !out)) return fail(SL_EINVAL, "rows or out is NULL");
   for (int k = 0; k < nrows; ++k)
     if (rows[k] < 0 || rows[k] >= p->n) return fail(SL_EINVAL, "row %d outside [0, n)", rows[k]);
-  if (p->n == 0) return SL_OK;
-  sl_status s = join_from(p, (hipStream_t)stream);
+  return SL_OK;
+}
+
+// Distances of the listed rows as floats (hop counts or lengths) into host out.
+sl_status gather_rows(sl_plan* p, const int32_t* rows, int32_t nrows, hipStream_t stream, float* out) {
+  sl_status s = join_from(p, stream);
   if (s != SL_OK) return s;
   int32_t* drows = nullptr;
-  uint8_t* dout = nullptr;
-  const size_t bytes = (size_t)nrows * p->n;
+  float* dout = nullptr;
+  const size_t count = (size_t)nrows * p->n;
   hipError_t e = hipMalloc(&drows, sizeof(int32_t) * nrows);
-  if (e == hipSuccess) e = hipMalloc(&dout, bytes);
+  if (e == hipSuccess) e = hipMalloc(&dout, sizeof(float) * count);
   if (e == hipSuccess) e = hipMemcpyAsync(drows, rows, sizeof(int32_t) * nrows, hipMemcpyHostToDevice, p->ps);
-  if (e == hipSuccess) e = launch_gather_rows(p->d, drows, nrows, p->n, p->sp.ng, dout, p->ps);
-  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, p->ps);
+  if (e == hipSuccess) e = launch_gather_rows(p->d, p->df, drows, nrows, p->n, p->sp.ng, dout, p->ps);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(float) * count, hipMemcpyDeviceToHost, p->ps);
   if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
   (void)hipFree(drows);
   (void)hipFree(dout);
   if (e != hipSuccess) return hip_fail(e, "distance rows");
   return SL_OK;
+}
+
+}  // namespace
+
+sl_status sl_plan_distance_rows(sl_plan* p, const int32_t* rows, int32_t nrows, void* stream, uint8_t* out) {
+  g_err.clear();
+  sl_status s = check_rows(p, rows, nrows, out);
+  if (s != SL_OK) return s;
+  if (p->df) return fail(SL_EINVAL, "the plan holds edge-length distances: use sl_plan_distance_rows_f32");
+  if (nrows == 0 || p->n == 0) return SL_OK;
+  std::vector<float> tmp((size_t)nrows * p->n);
+  if ((s = gather_rows(p, rows, nrows, (hipStream_t)stream, tmp.data())) != SL_OK) return s;
+  for (size_t q = 0; q < tmp.size(); ++q) out[q] = (uint8_t)tmp[q];
+  return SL_OK;
+}
+
+sl_status sl_plan_distance_rows_f32(sl_plan* p, const int32_t* rows, int32_t nrows, void* stream, float* out) {
+  g_err.clear();
+  sl_status s = check_rows(p, rows, nrows, out);
+  if (s != SL_OK) return s;
+  if (nrows == 0 || p->n == 0) return SL_OK;
+  return gather_rows(p, rows, nrows, (hipStream_t)stream, out);
+}
+
+sl_status sl_plan_tree_rows(sl_plan* p, const int32_t* rows, int32_t nrows, void* stream, int32_t* out) {
+  g_err.clear();
+  sl_status s = check_rows(p, rows, nrows, out);
+  if (s != SL_OK) return s;
+  if (!p->pred) return fail(SL_EINVAL, "shortest-path trees are kept for edge-length plans only");
+  if (nrows == 0 || p->n == 0) return SL_OK;
+  if ((s = join_from(p, (hipStream_t)stream)) != SL_OK) return s;
+  for (int k = 0; k < nrows; ++k)
+    HIP_TRY(hipMemcpyAsync(out + (size_t)k * p->n, p->pred + (size_t)rows[k] * p->n, sizeof(int32_t) * p->n,
+                           hipMemcpyDeviceToHost, p->ps),
+            "tree rows copy");
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  return SL_OK;
+}
+
+sl_status sl_plan_set_lengths(sl_plan* p, const float* edge_len, void* stream) {
+  g_err.clear();
+  if (!p) return fail(SL_EINVAL, "plan is NULL");
+  if (!p->df) return fail(SL_EINVAL, "the plan was created without edge lengths");
+  if (p->nnz > 0 && !edge_len) return fail(SL_EINVAL, "edge_len is NULL");
+  std::vector<int64_t> rp(p->n + 1);
+  std::vector<int32_t> ci((size_t)p->nnz);
+  sl_status s = join_from(p, (hipStream_t)stream);
+  if (s != SL_OK) return s;
+  HIP_TRY(hipMemcpyAsync(rp.data(), p->g_row_ptr, sizeof(int64_t) * (p->n + 1), hipMemcpyDeviceToHost, p->ps),
+          "graph copy");
+  if (p->nnz > 0)
+    HIP_TRY(hipMemcpyAsync(ci.data(), p->g_col_idx, sizeof(int32_t) * p->nnz, hipMemcpyDeviceToHost, p->ps),
+            "graph copy");
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  sl_graph g{p->n, p->nnz, rp.data(), ci.data(), edge_len};
+  if ((s = check_lengths(&g, edge_len)) != SL_OK) return s;
+  if (p->nnz > 0)
+    HIP_TRY(hipMemcpyAsync(p->g_len, edge_len, sizeof(float) * p->nnz, hipMemcpyHostToDevice, p->ps),
+            "lengths upload");
+  HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+  if ((s = build_weighted(p)) != SL_OK) return s;
+  HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+  p->plan_ms = ms;
+  return join_to(p, (hipStream_t)stream);
 }
 
 sl_status sl_plan_weights(sl_plan* p, void* stream, double* W) {

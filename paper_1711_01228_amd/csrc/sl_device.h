@@ -92,4 +92,57 @@ __device__ __forceinline__ uint32_t byte_mask4(uint32_t nib) {
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t word, int b) { return (word >> (8 * b)) & 0xffu; }
 
+// ---------------------------------------------------------------------------
+// Distance storage.  Hop counts are bytes (a lane chunk of 16 columns is one
+// uint4); lengths of weighted graphs are floats in the same tile-major order
+// (a lane chunk is 64 bytes, four float4).  0 stands for the same vertex, no
+// path or padding in both.
+// ---------------------------------------------------------------------------
+struct FChunk {
+  float4 a, b, c, e;
+};
+
+template <bool FD> struct DChunkT { using T = uint4; };
+template <> struct DChunkT<true> { using T = FChunk; };
+
+__device__ __forceinline__ float fchunk_at(const FChunk& q, int k) {
+  const float4& v = (k < 4) ? q.a : (k < 8) ? q.b : (k < 12) ? q.c : q.e;
+  switch (k & 3) {
+    case 0: return v.x;
+    case 1: return v.y;
+    case 2: return v.z;
+    default: return v.w;
+  }
+}
+
+// The lane chunk of row block rb, column group g (d: bytes, df: floats).
+template <bool FD>
+__device__ __forceinline__ typename DChunkT<FD>::T load_chunk(const uint8_t* __restrict__ d,
+                                                              const float* __restrict__ df, int rb, int ng, int g,
+                                                              int lane) {
+  if constexpr (FD) {
+    const float4* p = reinterpret_cast<const float4*>(df + ((size_t)rb * ng + g) * kTileBytes) + lane * 4;
+    return FChunk{p[0], p[1], p[2], p[3]};
+  } else {
+    return reinterpret_cast<const uint4*>(d + ((size_t)rb * ng + g) * kTileBytes)[lane];
+  }
+}
+
+template <bool FD>
+__device__ __forceinline__ typename DChunkT<FD>::T zero_chunk() {
+  if constexpr (FD) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    return FChunk{z, z, z, z};
+  } else {
+    return make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
+// Distance k of a chunk as a float (bytes: the hop count).
+template <bool FD>
+__device__ __forceinline__ float chunk_dist(const typename DChunkT<FD>::T& q, int k) {
+  if constexpr (FD) return fchunk_at(q, k);
+  else return (float)byte_of(chunk_word(q, k), k & 3);
+}
+
 }  // namespace sl

@@ -25,6 +25,7 @@ namespace sl {
 //   E      the extrapolation step e_i = x~_i - x^H_i as stored (same format),
 //          read by the safeguard pass.
 // ---------------------------------------------------------------------------
+constexpr int kWeightedMaxN = 16384;  // weighted graphs: one source's distance row fits in LDS
 constexpr int kRowBlock = 64;   // rows per wave (one per lane)
 constexpr int kColGroup = 16;   // columns per 16-byte lane chunk
 constexpr int kTileBytes = kRowBlock * kColGroup;
@@ -128,11 +129,17 @@ hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, uint64_t* acc,
 hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* frontier,
                             uint64_t* acc, uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base,
                             int level, int write, int32_t* flag, hipStream_t s);
-hipError_t launch_weights(const uint8_t* d, double* W, const Split& sp, int n, hipStream_t s);
+hipError_t launch_weights(const uint8_t* d, const float* df, double* W, const Split& sp, int n, hipStream_t s);
+// Weighted graphs: FP32 shortest-path distances (tile-major, 0 = no path) and
+// trees (pred[s][v], row-major int32), then the lower triangle := the upper.
+hipError_t launch_wsssp(const int64_t* row_ptr, const int32_t* col_idx, const float* len, int n, int ng, float* df,
+                        int32_t* pred, hipStream_t s);
+hipError_t launch_wsym(float* df, int n_pad, int ng, hipStream_t s);
 hipError_t launch_pack_in(const float* X, float* Xb, int n, int n_pad, int dim, hipStream_t s);
 hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, float* X, int n, int dim,
                            hipStream_t s);
-hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* Xb, size_t stride,
+// Distances are bytes (d) or, for weighted graphs, floats (df); the other pointer is null.
+hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                         const DevState* st, double* fpart, double* spart, const Split& sp, int n_pad,
                         hipStream_t s);
 hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, const double* spart,
@@ -141,9 +148,9 @@ hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, cons
 // Work items (row block, first column group, end group, 0) of the safeguard
 // pass: the upper triangle in equal runs of column groups.
 std::vector<int4> triangle_items(const Split& sp);
-hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
-                          const int4* items, int nitems, const DevState* st, double* sgpart, const Split& sp,
-                          hipStream_t s);
+hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                          const float* Eb, const int4* items, int nitems, const DevState* st, double* sgpart,
+                          const Split& sp, hipStream_t s);
 hipError_t launch_select(int dim, const LoopParams& p, const double* red, int nred, const double* sgpart,
                          int nsg, DevState* st, double* trace, hipStream_t s);
 hipError_t launch_sgdelta_enum(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
@@ -154,8 +161,8 @@ hipError_t launch_apply_enum(const float* Eb, float* Xb, size_t stride, const De
 hipError_t launch_record(const float* Xb, size_t stride, const DevState* st, float* xtrace, int n, int dim,
                          hipStream_t s);
 hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevState* st, hipStream_t s);
-hipError_t launch_gather_rows(const uint8_t* d, const int32_t* rows, int nrows, int n, int ng, uint8_t* out,
-                              hipStream_t s);
+hipError_t launch_gather_rows(const uint8_t* d, const float* df, const int32_t* rows, int nrows, int n, int ng,
+                              float* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched layouts: many independent graphs of at most kBatchMaxN vertices.

@@ -38,17 +38,35 @@ namespace {
 // Sixteen pairs are summed in float, then folded into double accumulators.
 // Pairs with d = 0 (i = j, no path, padding) give c = 0.
 // ---------------------------------------------------------------------------
-template <int DIM, bool STRESS>
-__global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
-                                               size_t stride, const DevState* __restrict__ st,
-                                               double* __restrict__ fpart, double* __restrict__ spart, int nrb,
-                                               int ng, int gps, int n_pad) {
+// Weights of distance k of a chunk: (1/d, 1/d^2) and, for the stress terms, 1
+// when a path exists.  Bytes look the table up; floats divide (rcp).
+template <bool FD, bool STRESS>
+__device__ __forceinline__ typename WeightEntry<STRESS>::T pair_weights(const typename DChunkT<FD>::T& q, int k,
+                                                                       const typename WeightEntry<STRESS>::T* lut) {
+  if constexpr (FD) {
+    const float dv = fchunk_at(q, k);
+    const float inv = dv > 0.f ? __builtin_amdgcn_rcpf(dv) : 0.f;
+    if constexpr (STRESS) return make_float4(inv, inv * inv, dv > 0.f ? 1.f : 0.f, 0.f);
+    else return make_float2(inv, inv * inv);
+  } else {
+    return lut[byte_of(chunk_word(q, k), k & 3)];
+  }
+}
+
+template <int DIM, bool STRESS, bool FD>
+__global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                               const float* __restrict__ Xb, size_t stride,
+                                               const DevState* __restrict__ st, double* __restrict__ fpart,
+                                               double* __restrict__ spart, int nrb, int ng, int gps, int n_pad) {
   using V = typename VecT<DIM>::T;
   using E = typename WeightEntry<STRESS>::T;
+  using C = typename DChunkT<FD>::T;
   __shared__ E lut[256];
   if (st->done) return;
-  fill_weight_table<STRESS>(lut);
-  __syncthreads();
+  if constexpr (!FD) {
+    fill_weight_table<STRESS>(lut);
+    __syncthreads();
+  }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int rb = blockIdx.x * 4 + wave;
   if (rb >= nrb) return;
@@ -58,18 +76,17 @@ __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, co
   const V* __restrict__ X = reinterpret_cast<const V*>(Xb + (size_t)st->cur * stride);
   const int i = rb * kRowBlock + lane;
   const V xi = X[i];
-  const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
   double F0 = 0.0, F1 = 0.0, F2 = 0.0, Sd = 0.0;
   if (g0 < g1) {
-    uint4 q = tile[(size_t)g0 * 64];
+    C q = load_chunk<FD>(d, df, rb, ng, g0, lane);
     for (int g = g0; g < g1; ++g) {
-      uint4 qn = make_uint4(0u, 0u, 0u, 0u);
-      if (g + 1 < g1) qn = tile[(size_t)(g + 1) * 64];
+      C qn = zero_chunk<FD>();
+      if (g + 1 < g1) qn = load_chunk<FD>(d, df, rb, ng, g + 1, lane);
       const V* __restrict__ xj = X + (size_t)g * kColGroup;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
 #pragma unroll
       for (int k = 0; k < kColGroup; ++k) {
-        const E wt = lut[byte_of(chunk_word(q, k), k & 3)];
+        const E wt = pair_weights<FD, STRESS>(q, k, lut);
         const V p = xj[k];
         const float dx = xi.x - p.x, dy = xi.y - p.y;
         float r2 = fmaf(dx, dx, kTiny);
@@ -199,16 +216,22 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
 // (row block, first group, end group); in the diagonal block pairs with
 // j <= i are masked.  One double per wave, summed later in item order.
 // ---------------------------------------------------------------------------
-template <int DIM, bool MASK>
-__device__ __forceinline__ float safeguard_group(const uint4& q, const float* lut, typename VecT<DIM>::T hi,
-                                                 typename VecT<DIM>::T ei,
+template <int DIM, bool MASK, bool FD>
+__device__ __forceinline__ float safeguard_group(const typename DChunkT<FD>::T& q, const float* lut,
+                                                 typename VecT<DIM>::T hi, typename VecT<DIM>::T ei,
                                                  const typename VecT<DIM>::T* __restrict__ hj,
                                                  const typename VecT<DIM>::T* __restrict__ ej, int jrel) {
   using V = typename VecT<DIM>::T;
   float a = 0.f;
 #pragma unroll
   for (int k = 0; k < kColGroup; ++k) {
-    const float inv = lut[byte_of(chunk_word(q, k), k & 3)];
+    float inv;
+    if constexpr (FD) {
+      const float dv = fchunk_at(q, k);
+      inv = dv > 0.f ? __builtin_amdgcn_rcpf(dv) : 0.f;
+    } else {
+      inv = lut[byte_of(chunk_word(q, k), k & 3)];
+    }
     const V ph = hj[k], pe = ej[k];
     const float hx = hi.x - ph.x, hy = hi.y - ph.y;
     const float ex = ei.x - pe.x, ey = ei.y - pe.y;
@@ -233,17 +256,19 @@ __device__ __forceinline__ float safeguard_group(const uint4& q, const float* lu
   return a;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
-                                                 size_t stride, const float* __restrict__ Eb,
-                                                 const int4* __restrict__ items, int nitems,
-                                                 const DevState* __restrict__ st, double* __restrict__ sgpart,
-                                                 int ng) {
+template <int DIM, bool FD>
+__global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                                 const float* __restrict__ Xb, size_t stride,
+                                                 const float* __restrict__ Eb, const int4* __restrict__ items,
+                                                 int nitems, const DevState* __restrict__ st,
+                                                 double* __restrict__ sgpart, int ng) {
   using V = typename VecT<DIM>::T;
   __shared__ float lut[256];
   if (st->done) return;
-  lut[threadIdx.x] = threadIdx.x ? 1.0f / (float)threadIdx.x : 0.f;
-  __syncthreads();
+  if constexpr (!FD) {
+    lut[threadIdx.x] = threadIdx.x ? 1.0f / (float)threadIdx.x : 0.f;
+    __syncthreads();
+  }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int item = blockIdx.x * 4 + wave;
   if (item >= nitems) return;
@@ -256,19 +281,18 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
   const int gfree = gdiag + kRowBlock / kColGroup;  // first group right of the diagonal block
   const int i = rb * kRowBlock + lane;
   const V hi = XH[i], ei = E[i];
-  const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
   double acc = 0.0;
   int g = g0;
   for (; g < g1 && g < gfree; ++g) {
-    const uint4 q = tile[(size_t)g * 64];
+    const auto q = load_chunk<FD>(d, df, rb, ng, g, lane);
     // pair (i, j) with j = 16 g + k is kept iff j > i, i.e. k > i - 16 g
-    acc += (double)safeguard_group<DIM, true>(q, lut, hi, ei, XH + (size_t)g * kColGroup,
-                                              E + (size_t)g * kColGroup, i - g * kColGroup);
+    acc += (double)safeguard_group<DIM, true, FD>(q, lut, hi, ei, XH + (size_t)g * kColGroup,
+                                                  E + (size_t)g * kColGroup, i - g * kColGroup);
   }
   for (; g < g1; ++g) {
-    const uint4 q = tile[(size_t)g * 64];
-    acc += (double)safeguard_group<DIM, false>(q, lut, hi, ei, XH + (size_t)g * kColGroup,
-                                               E + (size_t)g * kColGroup, 0);
+    const auto q = load_chunk<FD>(d, df, rb, ng, g, lane);
+    acc += (double)safeguard_group<DIM, false, FD>(q, lut, hi, ei, XH + (size_t)g * kColGroup,
+                                                   E + (size_t)g * kColGroup, 0);
   }
   acc = wave_sum(acc);
   if (lane == 0) sgpart[item] = acc;
@@ -626,31 +650,42 @@ __global__ __launch_bounds__(256) void k_bfs_update(uint64_t* __restrict__ acc, 
 
 // W_i = sum_j d_ij^-2 in double, columns in ascending order (one wave per row
 // block, lane = row, the same tile stream as the force pass).
-__global__ __launch_bounds__(256) void k_weights(const uint8_t* __restrict__ d, double* __restrict__ W, int nrb,
-                                                 int ng, int n) {
+template <bool FD>
+__global__ __launch_bounds__(256) void k_weights(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                                 double* __restrict__ W, int nrb, int ng, int n) {
   __shared__ double lut[256];
-  lut[threadIdx.x] = threadIdx.x ? 1.0 / ((double)threadIdx.x * (double)threadIdx.x) : 0.0;
-  __syncthreads();
+  if constexpr (!FD) {
+    lut[threadIdx.x] = threadIdx.x ? 1.0 / ((double)threadIdx.x * (double)threadIdx.x) : 0.0;
+    __syncthreads();
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rb = blockIdx.x * 4 + wave;
   if (rb >= nrb) return;
-  const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(d + (size_t)rb * ng * kTileBytes) + lane;
   double s = 0.0;
   for (int g = 0; g < ng; ++g) {
-    const uint4 q = tile[(size_t)g * 64];
+    const auto q = load_chunk<FD>(d, df, rb, ng, g, lane);
 #pragma unroll
-    for (int k = 0; k < kColGroup; ++k) s += lut[(chunk_word(q, k) >> (8 * (k & 3))) & 0xffu];
+    for (int k = 0; k < kColGroup; ++k) {
+      if constexpr (FD) {
+        const double dv = (double)fchunk_at(q, k);
+        s += dv > 0.0 ? 1.0 / (dv * dv) : 0.0;
+      } else {
+        s += lut[(chunk_word(q, k) >> (8 * (k & 3))) & 0xffu];
+      }
+    }
   }
   const int i = rb * kRowBlock + lane;
   W[i] = (i < n) ? s : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_gather_rows(const uint8_t* __restrict__ d, const int32_t* __restrict__ rows,
-                                                     int nrows, int n, int ng, uint8_t* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_gather_rows(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                                     const int32_t* __restrict__ rows, int nrows, int n, int ng,
+                                                     float* __restrict__ out) {
   const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= (size_t)nrows * n) return;
   const int k = (int)(q / n), j = (int)(q % n);
-  out[q] = d[tile_offset(rows[k], j, ng)];
+  const size_t o = tile_offset(rows[k], j, ng);
+  out[q] = df ? df[o] : (float)d[o];
 }
 
 inline unsigned blocks_for(size_t items) { return (unsigned)((items + 255) / 256); }
@@ -696,8 +731,9 @@ hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_weights(const uint8_t* d, double* W, const Split& sp, int n, hipStream_t s) {
-  k_weights<<<sp.blocks_x, 256, 0, s>>>(d, W, sp.nrb, sp.ng, n);
+hipError_t launch_weights(const uint8_t* d, const float* df, double* W, const Split& sp, int n, hipStream_t s) {
+  if (df) k_weights<true><<<sp.blocks_x, 256, 0, s>>>(d, df, W, sp.nrb, sp.ng, n);
+  else k_weights<false><<<sp.blocks_x, 256, 0, s>>>(d, df, W, sp.nrb, sp.ng, n);
   return hipGetLastError();
 }
 
@@ -713,20 +749,27 @@ hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, f
   return hipGetLastError();
 }
 
-hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* Xb, size_t stride,
+template <int DIM, bool STRESS>
+static void force_launch(const uint8_t* d, const float* df, const float* Xb, size_t stride, const DevState* st,
+                         double* fpart, double* spart, const Split& sp, int n_pad, hipStream_t s) {
+  const dim3 grid(sp.blocks_x, sp.slices);
+  if (df)
+    k_force<DIM, STRESS, true><<<grid, 256, 0, s>>>(d, df, Xb, stride, st, fpart, spart, sp.nrb, sp.ng,
+                                                     sp.groups_per_slice, n_pad);
+  else
+    k_force<DIM, STRESS, false><<<grid, 256, 0, s>>>(d, df, Xb, stride, st, fpart, spart, sp.nrb, sp.ng,
+                                                      sp.groups_per_slice, n_pad);
+}
+
+hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                         const DevState* st, double* fpart, double* spart, const Split& sp, int n_pad,
                         hipStream_t s) {
-  const dim3 grid(sp.blocks_x, sp.slices);
   if (dim == 2) {
-    if (stress)
-      k_force<2, true><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
-    else
-      k_force<2, false><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+    if (stress) force_launch<2, true>(d, df, Xb, stride, st, fpart, spart, sp, n_pad, s);
+    else force_launch<2, false>(d, df, Xb, stride, st, fpart, spart, sp, n_pad, s);
   } else {
-    if (stress)
-      k_force<3, true><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
-    else
-      k_force<3, false><<<grid, 256, 0, s>>>(d, Xb, stride, st, fpart, spart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+    if (stress) force_launch<3, true>(d, df, Xb, stride, st, fpart, spart, sp, n_pad, s);
+    else force_launch<3, false>(d, df, Xb, stride, st, fpart, spart, sp, n_pad, s);
   }
   return hipGetLastError();
 }
@@ -757,12 +800,17 @@ std::vector<int4> triangle_items(const Split& sp) {
   return items;
 }
 
-hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
-                          const int4* items, int nitems, const DevState* st, double* sgpart, const Split& sp,
-                          hipStream_t s) {
+hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                          const float* Eb, const int4* items, int nitems, const DevState* st, double* sgpart,
+                          const Split& sp, hipStream_t s) {
   const unsigned nb = (unsigned)((nitems + 3) / 4);
-  if (dim == 2) k_sgdelta<2><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
-  else k_sgdelta<3><<<nb, 256, 0, s>>>(d, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+  if (dim == 2) {
+    if (df) k_sgdelta<2, true><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+    else k_sgdelta<2, false><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+  } else {
+    if (df) k_sgdelta<3, true><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+    else k_sgdelta<3, false><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+  }
   return hipGetLastError();
 }
 
@@ -801,11 +849,11 @@ hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevStat
   return hipGetLastError();
 }
 
-hipError_t launch_gather_rows(const uint8_t* d, const int32_t* rows, int nrows, int n, int ng, uint8_t* out,
-                              hipStream_t s) {
+hipError_t launch_gather_rows(const uint8_t* d, const float* df, const int32_t* rows, int nrows, int n, int ng,
+                              float* out, hipStream_t s) {
   const size_t items = (size_t)nrows * n;
   if (items == 0) return hipSuccess;
-  k_gather_rows<<<blocks_for(items), 256, 0, s>>>(d, rows, nrows, n, ng, out);
+  k_gather_rows<<<blocks_for(items), 256, 0, s>>>(d, df, rows, nrows, n, ng, out);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ HEADER = os.path.join(ROOT, "include", "sorlayout.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sl_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(sl_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_function():
@@ -82,12 +82,19 @@ def test_validation_rejects_asymmetric_and_nnz_mismatch():
     assert b.LIB.sl_validate(ctypes.byref(ga.s), None) == b.SL_EINVAL and "nnz" in b.last_error()
 
 
-def test_edge_lengths_are_refused_as_unsupported():
+def test_edge_length_validation():
     g = _tri()
     g.edge_len = np.ones(len(g.col_idx), dtype=np.float32)
-    assert b.sl_validate_status(g) == b.SL_ENOTSUP
+    assert b.sl_validate_status(g) == b.SL_OK
     g.edge_len[2] = -1.0
+    assert b.sl_validate_status(g) == b.SL_EINVAL and "positive" in b.last_error()
+    g.edge_len[2] = np.nan
     assert b.sl_validate_status(g) == b.SL_EINVAL
+    g.edge_len[2] = 2.0  # its twin entry still holds 1.0
+    assert b.sl_validate_status(g) == b.SL_EINVAL and "two different lengths" in b.last_error()
+    big = inputs.path_graph(b.SL_WEIGHTED_MAX_N + 1)
+    big.edge_len = np.ones(big.nnz, dtype=np.float32)
+    assert b.sl_validate_status(big) == b.SL_ENOTSUP
 
 
 @pytest.mark.parametrize("field,value", [
