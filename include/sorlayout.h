@@ -220,6 +220,39 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
 sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,
                           double* ms);
 
+/* ---------------------------------------------------------------------------
+ * Reverse mode (the unrolled layout as a differentiable function).
+ *
+ * The unrolled layout maps the initial placement X^0 and, for edge-length
+ * plans, the edge lengths (through d_ij = shortest-path length) to X^K after
+ * exactly K iterations of Algorithm 2 with the Jacobi step and a fixed omega.
+ * Its derivative holds the safeguard decisions (Alg. 2, lines 6-8) at those
+ * the forward run took: they are piecewise constant in the inputs.
+ * ------------------------------------------------------------------------- */
+
+/* f(X) of eq. 1 into *f and its gradient G_i = sum_j 2 w_ij (r_ij - d_ij) u_ij
+ * into G (device, n * dim floats); X is a device placement (n * dim floats). */
+sl_status sl_plan_stress_grad(sl_plan* plan, const float* X, int32_t dim, void* stream, double* f, float* G);
+
+/* Run exactly opt->max_iter = K iterations from X (device, n * dim floats, in
+ * place; opt->tol is not used) and keep a tape for sl_plan_unroll_backward:
+ * the placements X^{m c} (c = ckpt_every >= 1) and the decision of every
+ * iteration.  The strategy must be SL_OMEGA_FIXED without per-vertex factors
+ * and the ordering SL_ORDER_JACOBI (else SL_ENOTSUP); opt->trace and
+ * opt->xtrace must be NULL.  A later call replaces the tape. */
+sl_status sl_plan_unroll(sl_plan* plan, float* X, const sl_options* opt, int32_t ckpt_every, void* stream,
+                         sl_result* out);
+
+/* Reverse mode through the last sl_plan_unroll: given G = dL/dX^K (device,
+ * n * dim floats) write dL/dX^0 into gX0 (device, n * dim floats) and, if
+ * glen is not NULL (edge-length plans only), dL/dlen into glen (device, nnz
+ * floats: both entries of an edge hold the edge's derivative).  Each segment
+ * of c iterations is recomputed from its checkpoint.  Edge-length derivatives
+ * route dL/dd_st of each pair s < t along the tree path of s (the plan's
+ * trees: sl_plan_tree_rows).  Errors: SL_EINVAL (no tape, glen on a hop-count
+ * plan), SL_ENOMEM, SL_EDEVICE. */
+sl_status sl_plan_unroll_backward(sl_plan* plan, const float* G, float* gX0, float* glen, void* stream);
+
 /* Release a plan and all its device memory.  NULL is accepted. */
 sl_status sl_plan_destroy(sl_plan* plan);
 

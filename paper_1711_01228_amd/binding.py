@@ -38,7 +38,8 @@ def auto_schedule(max_iter: int, seed: int) -> np.ndarray:
 EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run", "sl_plan_stress",
             "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
             "sl_last_error", "sl_batch_plan_create", "sl_batch_plan_tune", "sl_batch_plan_run",
-            "sl_batch_plan_destroy", "sl_plan_distance_rows_f32", "sl_plan_tree_rows", "sl_plan_set_lengths")
+            "sl_batch_plan_destroy", "sl_plan_distance_rows_f32", "sl_plan_tree_rows", "sl_plan_set_lengths",
+            "sl_plan_stress_grad", "sl_plan_unroll", "sl_plan_unroll_backward")
 SL_WEIGHTED_MAX_N = 16384
 SL_BATCH_MAX_N = 1024
 SL_BATCH_CLASSES = 16
@@ -103,6 +104,9 @@ def _load():
         "sl_plan_distance_rows_f32": (st, [P, P, i32, P, P]),
         "sl_plan_tree_rows": (st, [P, P, i32, P, P]),
         "sl_plan_set_lengths": (st, [P, P, P]),
+        "sl_plan_stress_grad": (st, [P, P, i32, P, ctypes.POINTER(ctypes.c_double), P]),
+        "sl_plan_unroll": (st, [P, P, ctypes.POINTER(sl_options), i32, P, ctypes.POINTER(sl_result)]),
+        "sl_plan_unroll_backward": (st, [P, P, P, P, P]),
         "sl_plan_profile": (st, [P, P, i32, ctypes.c_double, i32, P, P]),
         "sl_plan_destroy": (st, [P]),
         "sl_layout": (st, [ctypes.POINTER(sl_graph), P, ctypes.POINTER(sl_options), P, ctypes.POINTER(sl_result)]),
@@ -236,6 +240,23 @@ def sl_plan_set_lengths(plan: int, edge_len, stream=None) -> None:
     _check(LIB.sl_plan_set_lengths(plan, ln.ctypes.data, _stream_handle(stream)))
 
 
+def sl_plan_stress_grad(plan: int, X_ptr: int, dim: int, G_ptr: int, stream=None) -> float:
+    f = ctypes.c_double()
+    _check(LIB.sl_plan_stress_grad(plan, X_ptr, int(dim), _stream_handle(stream), ctypes.byref(f), G_ptr))
+    return f.value
+
+
+def sl_plan_unroll(plan: int, X_ptr: int, opt: sl_options, ckpt_every: int, stream=None) -> dict:
+    res = sl_result()
+    _check(LIB.sl_plan_unroll(plan, X_ptr, ctypes.byref(opt), int(ckpt_every), _stream_handle(stream),
+                              ctypes.byref(res)))
+    return res.as_dict()
+
+
+def sl_plan_unroll_backward(plan: int, G_ptr: int, gX0_ptr: int, glen_ptr=None, stream=None) -> None:
+    _check(LIB.sl_plan_unroll_backward(plan, G_ptr, gX0_ptr, glen_ptr, _stream_handle(stream)))
+
+
 def sl_plan_weights(plan: int, n: int, stream=None) -> np.ndarray:
     W = np.zeros(n, dtype=np.float64)
     _check(LIB.sl_plan_weights(plan, _stream_handle(stream), W.ctypes.data))
@@ -330,6 +351,20 @@ class Plan:
     def set_lengths(self, edge_len, stream=None) -> None:
         """New lengths per CSR entry (same graph); rebuilds distances and trees."""
         sl_plan_set_lengths(self.handle, edge_len, stream)
+
+    def stress_grad(self, X, G, stream=None) -> float:
+        """f(X) (eq. 1) and its gradient into the device tensor G (n x dim)."""
+        return sl_plan_stress_grad(self.handle, X.data_ptr(), self.dim, G.data_ptr(), stream)
+
+    def unroll(self, X, omega=1.5, iters=100, ckpt_every=10, safeguard=True, stream=None) -> dict:
+        """Exactly `iters` iterations in place on X, keeping the tape for unroll_backward."""
+        opt = make_options(self.dim, omega, 0.0, iters, safeguard)
+        return sl_plan_unroll(self.handle, X.data_ptr(), opt, ckpt_every, stream)
+
+    def unroll_backward(self, G, gX0, glen=None, stream=None) -> None:
+        """dL/dX0 (and dL/dlen per CSR entry) from G = dL/dX^K; device tensors."""
+        sl_plan_unroll_backward(self.handle, G.data_ptr(), gX0.data_ptr(),
+                                None if glen is None else glen.data_ptr(), stream)
 
     def profile(self, X, omega=1.5, reps=5, stream=None) -> dict:
         """Average device ms of each kernel of one iteration (HIP events)."""

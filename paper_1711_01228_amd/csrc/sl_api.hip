@@ -152,7 +152,24 @@ struct sl_plan {
   int64_t* g_row_ptr = nullptr;
   int32_t* g_col_idx = nullptr;
   float* g_len = nullptr;
+  int32_t* g_erow = nullptr;    // source row of every CSR entry
   int64_t nnz = 0;
+  // tape of the last sl_plan_unroll: checkpoints X^{m c} and the trace rows
+  // (decisions) of every iteration; reverse-mode work buffers
+  int tape_K = -1, tape_c = 1, tape_safeguard = 1;
+  double tape_omega = 1.0;
+  float* ckpt = nullptr;
+  size_t ckpt_cap = 0;          // floats
+  double* tape_trace = nullptr;
+  int tape_cap = 0;             // rows
+  float* segX = nullptr;
+  int seg_cap = 0;              // iterates
+  double* gb = nullptr;         // 3 x n_pad adjoint of the iterate
+  float* gvec = nullptr;        // stride floats
+  float* wbar = nullptr;        // n_pad
+  float* Dbar = nullptr;        // n_pad^2 (edge-length plans)
+  float* Sbuf = nullptr;        // n x n (edge-length plans)
+  double* Gedge = nullptr;      // nnz
   double* W = nullptr;          // n_pad
   float* Xb = nullptr;          // 3 iterate buffers
   float* Eb = nullptr;          // x~ - x^H, same format as one iterate buffer
@@ -192,6 +209,16 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->g_row_ptr);
   (void)hipFree(p->g_col_idx);
   (void)hipFree(p->g_len);
+  (void)hipFree(p->g_erow);
+  (void)hipFree(p->ckpt);
+  (void)hipFree(p->tape_trace);
+  (void)hipFree(p->segX);
+  (void)hipFree(p->gb);
+  (void)hipFree(p->gvec);
+  (void)hipFree(p->wbar);
+  (void)hipFree(p->Dbar);
+  (void)hipFree(p->Sbuf);
+  (void)hipFree(p->Gedge);
   (void)hipFree(p->W);
   (void)hipFree(p->Xb);
   (void)hipFree(p->Eb);
@@ -539,6 +566,13 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
       e = hipMemcpyAsync(p->g_col_idx, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess && g->nnz > 0)
       e = hipMemcpyAsync(p->g_len, g->edge_len, sizeof(float) * g->nnz, hipMemcpyHostToDevice, p->ps);
+    std::vector<int32_t> erow((size_t)g->nnz);
+    for (int v = 0; v < g->n; ++v)
+      for (int64_t q = g->row_ptr[v]; q < g->row_ptr[v + 1]; ++q) erow[(size_t)q] = v;
+    if (e == hipSuccess) e = hipMalloc(&p->g_erow, sizeof(int32_t) * std::max<int64_t>(1, g->nnz));
+    if (e == hipSuccess && g->nnz > 0)
+      e = hipMemcpyAsync(p->g_erow, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->ps);  // erow is a host temporary
   } else if (e == hipSuccess) {
     e = hipMalloc(&p->d, (size_t)p->n_pad * p->n_pad);
   }
@@ -913,6 +947,218 @@ sl_status sl_plan_weights(sl_plan* p, void* stream, double* W) {
   HIP_TRY(hipMemcpyAsync(W, p->W, sizeof(double) * p->n, hipMemcpyDeviceToHost, p->ps), "weights copy");
   HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
   return SL_OK;
+}
+
+namespace {
+
+sl_status grow(void** ptr, size_t* cap, size_t want, size_t elem, const char* what) {
+  if (*cap >= want && *ptr) return SL_OK;
+  (void)hipFree(*ptr);
+  *ptr = nullptr;
+  *cap = 0;
+  HIP_TRY(hipMalloc(ptr, elem * std::max<size_t>(want, 1)), what);
+  *cap = want;
+  return SL_OK;
+}
+
+LoopParams unroll_params(const sl_plan* p, double omega, int safeguard) {
+  LoopParams lp{};
+  lp.n = p->n;
+  lp.n_pad = p->n_pad;
+  lp.ng = p->sp.ng;
+  lp.nrb = p->sp.nrb;
+  lp.slices = p->sp.slices;
+  lp.groups_per_slice = p->sp.groups_per_slice;
+  lp.omega_p = omega - 1.0;
+  lp.tol = -1.0;  // an unrolled run takes every one of its iterations
+  lp.safeguard = safeguard;
+  return lp;
+}
+
+// Upload a loop state: X^k in buffer 0, iteration k of max_iter.
+sl_status set_state(sl_plan* p, DevState* dst, int iter, int max_iter) {
+  DevState* h = p->host_st;
+  std::memset(h, 0, sizeof(DevState));
+  h->iter = iter;
+  h->max_iter = max_iter;
+  h->done = (iter >= max_iter || p->n <= 1) ? 1 : 0;
+  h->converged = p->n <= 1 ? 1 : 0;
+  HIP_TRY(hipMemcpyAsync(dst, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  return SL_OK;
+}
+
+}  // namespace
+
+sl_status sl_plan_stress_grad(sl_plan* p, const float* X, int32_t dim, void* stream, double* f, float* G) {
+  g_err.clear();
+  if (!p || !f) return fail(SL_EINVAL, "plan or f is NULL");
+  if (dim != p->dim) return fail(SL_EINVAL, "dim %d differs from the plan's %d", dim, p->dim);
+  if ((!X || !G) && p->n > 0) return fail(SL_EINVAL, "X or G is NULL");
+  sl_status s = join_from(p, (hipStream_t)stream);
+  if (s != SL_OK) return s;
+  *f = 0.0;
+  if (p->n == 0) return SL_OK;
+  if (p->n == 1) {
+    HIP_TRY(hipMemsetAsync(G, 0, sizeof(float) * dim, p->ps), "hipMemsetAsync");
+    return join_to(p, (hipStream_t)stream);
+  }
+  HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
+  if ((s = stress_pass(p, 0, f)) != SL_OK) return s;
+  HIP_TRY(launch_stress_grad_out(p->fpart, p->sp.slices, p->n, p->n_pad, p->dim, G, p->ps), "gradient kernel");
+  return join_to(p, (hipStream_t)stream);
+}
+
+sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt_every, void* stream,
+                         sl_result* out) {
+  g_err.clear();
+  if (!p) return fail(SL_EINVAL, "plan is NULL");
+  sl_status s = check_options(o);
+  if (s != SL_OK) return s;
+  if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
+  if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
+  if (o->strategy != SL_OMEGA_FIXED || o->omega_vertex || o->ordering != SL_ORDER_JACOBI)
+    return fail(SL_ENOTSUP, "unrolled runs take the Jacobi step with a fixed omega");
+  if (o->trace || o->xtrace) return fail(SL_EINVAL, "unrolled runs keep their own trace");
+  if (ckpt_every < 1) return fail(SL_EINVAL, "ckpt_every = %d must be >= 1", ckpt_every);
+  const int K = o->max_iter, c = ckpt_every;
+  const int nseg = (K + c - 1) / c;
+  if ((s = join_from(p, (hipStream_t)stream)) != SL_OK) return s;
+  size_t cap = p->ckpt_cap;
+  if ((s = grow((void**)&p->ckpt, &cap, (size_t)std::max(nseg, 1) * p->stride, sizeof(float), "checkpoints")) != SL_OK)
+    return s;
+  p->ckpt_cap = cap;
+  size_t tcap = (size_t)p->tape_cap * SL_TRACE_COLS;
+  if ((s = grow((void**)&p->tape_trace, &tcap, (size_t)std::max(K, 1) * SL_TRACE_COLS, sizeof(double), "tape")) != SL_OK)
+    return s;
+  p->tape_cap = (int)(tcap / SL_TRACE_COLS);
+  p->tape_K = -1;
+  sl_options oo = *o;
+  oo.trace = p->tape_trace;
+  oo.xtrace = nullptr;
+  oo.flags &= ~SL_FLAG_TRACE_STRESS;
+  const LoopParams lp = unroll_params(p, o->omega, o->safeguard);
+  sl_result res{};
+  res.plan_ms = p->plan_ms;
+  if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
+  if ((s = set_state(p, p->st, 0, K)) != SL_OK) return s;
+  HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+  if (K > 0) HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->ckpt, p->ps), "checkpoint kernel");
+  for (int k = 0; k < K && p->n > 1; ++k) {
+    if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
+    if ((k + 1) % c == 0 && k + 1 < K)
+      HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->ckpt + (size_t)((k + 1) / c) * p->stride, p->ps),
+              "checkpoint kernel");
+  }
+  HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+  DevState* h = p->host_st;
+  HIP_TRY(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->ps), "state download");
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+  res.run_ms = ms;
+  const DevState fin = *h;
+  if (p->n > 0) HIP_TRY(launch_pack_out(p->Xb, p->st, p->stride, X, p->n, p->dim, p->ps), "unpack kernel");
+  res.iterations = fin.iter;
+  res.converged = fin.converged;
+  res.rejected = fin.rejected;
+  res.residual = fin.residual;
+  double f = 0.0;
+  if (p->n > 1 && (s = stress_pass(p, fin.cur, &f)) != SL_OK) return s;
+  res.stress = f;
+  if ((s = join_to(p, (hipStream_t)stream)) != SL_OK) return s;
+  if (out) *out = res;
+  if (fin.status != 0)
+    return fail(SL_ENUMERIC, "non-finite coordinate at iteration %d; X holds the last finite iterate", fin.iter + 1);
+  p->tape_K = K;
+  p->tape_c = c;
+  p->tape_omega = o->omega;
+  p->tape_safeguard = o->safeguard;
+  return SL_OK;
+}
+
+sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float* glen, void* stream) {
+  g_err.clear();
+  if (!p) return fail(SL_EINVAL, "plan is NULL");
+  if (p->tape_K < 0) return fail(SL_EINVAL, "no unrolled run to differentiate (call sl_plan_unroll first)");
+  if ((!G || !gX0) && p->n > 0) return fail(SL_EINVAL, "G or gX0 is NULL");
+  if (glen && !p->df) return fail(SL_EINVAL, "edge-length derivatives need a plan created with edge lengths");
+  const int K = p->tape_K, c = p->tape_c;
+  const int nseg = (K + c - 1) / c;
+  sl_status s = join_from(p, (hipStream_t)stream);
+  if (s != SL_OK) return s;
+  if (p->n == 0) return SL_OK;
+  const size_t col = (size_t)3 * p->n_pad;
+  size_t cap = p->gb ? col : 0;
+  if ((s = grow((void**)&p->gb, &cap, col, sizeof(double), "adjoint buffers")) != SL_OK) return s;
+  cap = p->gvec ? p->stride : 0;
+  if ((s = grow((void**)&p->gvec, &cap, p->stride, sizeof(float), "adjoint buffers")) != SL_OK) return s;
+  cap = p->wbar ? (size_t)p->n_pad : 0;
+  if ((s = grow((void**)&p->wbar, &cap, p->n_pad, sizeof(float), "adjoint buffers")) != SL_OK) return s;
+  size_t scap = (size_t)p->seg_cap * p->stride;
+  if ((s = grow((void**)&p->segX, &scap, (size_t)std::max(c, 1) * p->stride, sizeof(float), "segment buffer")) != SL_OK)
+    return s;
+  p->seg_cap = (int)(scap / p->stride);
+  if (glen) {
+    cap = p->Dbar ? (size_t)p->n_pad * p->n_pad : 0;
+    if ((s = grow((void**)&p->Dbar, &cap, (size_t)p->n_pad * p->n_pad, sizeof(float), "distance adjoint")) != SL_OK)
+      return s;
+    cap = p->Sbuf ? (size_t)p->n * p->n : 0;
+    if ((s = grow((void**)&p->Sbuf, &cap, (size_t)p->n * p->n, sizeof(float), "distance adjoint")) != SL_OK) return s;
+    cap = p->Gedge ? (size_t)p->nnz : 0;
+    if ((s = grow((void**)&p->Gedge, &cap, (size_t)std::max<int64_t>(p->nnz, 1), sizeof(double), "edge adjoint")) !=
+        SL_OK)
+      return s;
+    HIP_TRY(hipMemsetAsync(p->Dbar, 0, sizeof(float) * (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync");
+  }
+  std::vector<double> tr((size_t)std::max(K, 1) * SL_TRACE_COLS);
+  if (K > 0)
+    HIP_TRY(hipMemcpyAsync(tr.data(), p->tape_trace, sizeof(double) * K * SL_TRACE_COLS, hipMemcpyDeviceToHost,
+                           p->ps),
+            "tape download");
+  HIP_TRY(launch_grad_in(G, p->gb, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
+  const LoopParams lp = unroll_params(p, p->tape_omega, p->tape_safeguard);
+  sl_options oo;
+  sl_default_options(&oo);
+  oo.dim = p->dim;
+  if ((s = set_state(p, p->st_eval, 0, 1)) != SL_OK) return s;  // cur = 0: force passes read the pointer given
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  for (int m = nseg - 1; m >= 0 && p->n > 1; --m) {
+    const int k0 = m * c, k1 = std::min(k0 + c, K);
+    // recompute X^{k0} .. X^{k1-1} from the checkpoint
+    HIP_TRY(hipMemcpyAsync(p->segX, p->ckpt + (size_t)m * p->stride, sizeof(float) * p->stride,
+                           hipMemcpyDeviceToDevice, p->ps),
+            "checkpoint copy");
+    if (k1 - k0 > 1) {
+      HIP_TRY(hipMemcpyAsync(p->Xb, p->segX, sizeof(float) * p->stride, hipMemcpyDeviceToDevice, p->ps),
+              "checkpoint copy");
+      if ((s = set_state(p, p->st, k0, K)) != SL_OK) return s;
+      for (int q = 1; q < k1 - k0; ++q) {
+        if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
+        HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->segX + (size_t)q * p->stride, p->ps), "save kernel");
+      }
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      const float* Xk = p->segX + (size_t)(k - k0) * p->stride;
+      HIP_TRY(launch_force(p->dim, false, p->d, p->df, Xk, 0, p->st_eval, p->fpart, p->spart, p->sp, p->n_pad,
+                           p->ps),
+              "force kernel");
+      const double a = tr[(size_t)k * SL_TRACE_COLS + 1] == 1.0 ? p->tape_omega : 1.0;
+      HIP_TRY(launch_adjoint_step(p->dim, p->d, p->df, Xk, p->fpart, p->W, a, p->gb, p->gvec, p->wbar,
+                                  glen ? p->Dbar : nullptr, p->fpart, p->sp, p->n_pad, p->ps),
+              "adjoint kernels");
+    }
+  }
+  HIP_TRY(launch_grad_out(p->gb, gX0, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
+  if (glen) {
+    HIP_TRY(launch_edge_grad(p->Dbar, p->Sbuf, p->g_row_ptr, p->g_col_idx, p->g_erow, p->pred, p->Gedge, glen,
+                             p->n, p->nnz, p->n_pad, p->sp.ng, p->ps),
+            "edge-length gradient kernels");
+    if (p->n <= 1 || p->nnz == 0)
+      HIP_TRY(hipMemsetAsync(glen, 0, sizeof(float) * std::max<int64_t>(p->nnz, 0), p->ps), "hipMemsetAsync");
+  }
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  return join_to(p, (hipStream_t)stream);
 }
 
 sl_status sl_layout(const sl_graph* g, float* X, const sl_options* o, void* stream, sl_result* out) {

@@ -135,6 +135,23 @@ hipError_t launch_weights(const uint8_t* d, const float* df, double* W, const Sp
 hipError_t launch_wsssp(const int64_t* row_ptr, const int32_t* col_idx, const float* len, int n, int ng, float* df,
                         int32_t* pred, hipStream_t s);
 hipError_t launch_wsym(float* df, int n_pad, int ng, hipStream_t s);
+// Reverse mode (sl_diff.hip).
+hipError_t launch_grad_in(const float* G, double* gb, int n, int n_pad, int dim, hipStream_t s);
+hipError_t launch_grad_out(const double* gb, float* G, int n, int n_pad, int dim, hipStream_t s);
+hipError_t launch_stress_grad_out(const double* fpart, int slices, int n, int n_pad, int dim, float* G,
+                                  hipStream_t s);
+hipError_t launch_save(const float* Xb, size_t stride, const DevState* st, float* dst, hipStream_t s);
+// One backward iteration at X^k (Xk, iterate layout) given the force sums at X^k
+// in fpart: gb += Xbar; with Dbar, dL/dd of every row added into it.  The
+// adjoint pass reuses apart (may be fpart).
+hipError_t launch_adjoint_step(int dim, const uint8_t* d, const float* df, const float* Xk, const double* fpart,
+                               const double* W, double a, double* gb, float* gvec, float* wbar, float* Dbar,
+                               double* apart, const struct Split& sp, int n_pad, hipStream_t s);
+// dL/dlen per CSR entry from Dbar through the shortest-path trees (S: n x n
+// floats of scratch, G: nnz doubles of scratch, erow: source row of each entry).
+hipError_t launch_edge_grad(const float* Dbar, float* S, const int64_t* row_ptr, const int32_t* col_idx,
+                            const int32_t* erow, const int32_t* pred, double* G, float* glen, int n, int64_t nnz,
+                            int n_pad, int ng, hipStream_t s);
 hipError_t launch_pack_in(const float* X, float* Xb, int n, int n_pad, int dim, hipStream_t s);
 hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, float* X, int n, int dim,
                            hipStream_t s);
