@@ -182,6 +182,57 @@ def bench_exact(plan, Xdev0, n, ms):
     return res
 
 
+def bench_diff(steps=3):
+    """Differentiation: ER n=16,384, mean degree 8, edge lengths 1 +- 0.1, 100
+    unrolled iterations at omega = 1.5 with checkpoints every 10; loss = stress
+    against hop distances.  Forward = shortest paths for the current lengths +
+    unrolled iterations; backward = gradients w.r.t. X0 and every edge length."""
+    import numpy as np
+    import torch
+
+    from paper_1711_01228_amd import autograd as ag
+    from paper_1711_01228_amd import inputs
+
+    n, K = 16384, 100
+    g = inputs.erdos_renyi(n, n * 8 // 2, inputs.workload_seed(5))
+    rng = np.random.default_rng(inputs.workload_seed(5) + 1)
+    ln = (1.0 + rng.uniform(-0.1, 0.1, g.num_edges)).astype(np.float32)
+    X0 = inputs.uniform_positions(n, 2, inputs.workload_seed(5) + 2, 0.0, float(np.sqrt(n)))
+    t = time.perf_counter()
+    lay = ag.DifferentiableLayout(g, 2, ln)
+    plan_s = time.perf_counter() - t
+    fw, bw, tot = [], [], []
+    for rep in range(steps + 1):
+        X0t = torch.tensor(X0.astype(np.float32), device="cuda", requires_grad=True)
+        lt = torch.tensor(ln, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = ag.unrolled_layout(X0t, lt, lay, omega=1.5, iters=K, ckpt_every=10)
+        loss = ag.stress_loss(X, lay)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep > 0:  # the first pass allocates the tape and adjoint buffers
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+            tot.append(t2 - t0)
+    gX0 = X0t.grad.cpu().numpy().astype(np.float64)
+    glen = lt.grad.cpu().numpy().astype(np.float64)
+    lay.close()
+    pairs = float(n) * (n - 1)
+    return {"workload": "Erdos-Renyi n=%d, %d edges (mean degree 8), lengths U[0.9,1.1], start U[0,%d]^2, "
+                        "%d unrolled iterations at omega=1.5 with safeguard, checkpoints every 10, stress loss vs "
+                        "hop distances; gradients w.r.t. X0 and every edge length" % (n, g.num_edges, int(np.sqrt(n)), K),
+            "plan_s": round(plan_s, 3), "forward_s": round(float(np.median(fw)), 4),
+            "backward_s": round(float(np.median(bw)), 4), "step_s": round(float(np.median(tot)), 4),
+            "steps_timed": steps, "loss": float(loss.detach()),
+            "forward_pair_interactions_per_s": K * pairs / float(np.median(fw)),
+            "grad_translation_residual": float(np.abs(gX0.sum(0)).max() / np.abs(gX0).sum()),
+            "grad_len_norm": float(np.linalg.norm(glen)), "grad_x0_norm": float(np.linalg.norm(gX0))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +247,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched small-graph run")
     ap.add_argument("--no-strategies", action="store_true", help="skip the relaxation-strategy comparison")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-step (eq. 5 solved) comparison")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -315,6 +367,10 @@ def main():
                        "force_frac": round(a3 / PEAK_FP32_TFLOPS, 4),
                        "step_kernel_ms": {k: round(v, 4) for k, v in ms3.items()}, "time_to_converge": ttc3}
         log("3-D:", out["dim3"])
+    # ---- differentiation: gradients through 100 unrolled iterations at n = 16,384
+    if not args.quick and not args.no_diff:
+        out["differentiation"] = bench_diff()
+        log("differentiation:", out["differentiation"])
     # ---- batched: 2,048 small graphs, one persistent launch, each to its own tol
     if not args.quick and not args.no_batch:
         out["batched"] = bench_batch(args.omega)

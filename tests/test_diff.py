@@ -188,3 +188,33 @@ def test_backward_without_tape_and_length_gradient_on_hop_plan_are_refused():
         with pytest.raises(b.SlError) as e:
             plan.unroll_backward(G, dev(np.zeros_like(X0)), torch.zeros(g.nnz, device="cuda"))
         assert e.value.status == b.SL_EINVAL
+
+
+def test_full_size_gradient_invariants():
+    """ER n = 16,384, mean degree 8, 100 iterations at omega = 1.5, checkpoints
+    every 10: gradients finite, translation- and rotation-invariant."""
+    import torch
+
+    from paper_1711_01228_amd import autograd as ag
+
+    n = 16384
+    g = inputs.erdos_renyi(n, n * 4, inputs.workload_seed(5))
+    rng = np.random.default_rng(inputs.workload_seed(5) + 1)
+    ln = (1.0 + rng.uniform(-0.1, 0.1, g.num_edges)).astype(np.float32)
+    X0 = inputs.uniform_positions(n, 2, inputs.workload_seed(5) + 2, 0.0, float(np.sqrt(n)))
+    print("case er16384 diff", flush=True)
+    lay = ag.DifferentiableLayout(g, 2, ln)
+    try:
+        X0t = dev(X0).requires_grad_(True)
+        lt = torch.tensor(ln, device="cuda", requires_grad=True)
+        loss = ag.stress_loss(ag.unrolled_layout(X0t, lt, lay, omega=1.5, iters=100, ckpt_every=10), lay)
+        loss.backward()
+        gX0 = X0t.grad.cpu().numpy().astype(np.float64)
+        glen = lt.grad.cpu().numpy().astype(np.float64)
+    finally:
+        lay.close()
+    assert np.all(np.isfinite(gX0)) and np.all(np.isfinite(glen))
+    assert np.abs(glen).max() > 0
+    assert np.abs(gX0.sum(0)).max() <= 1e-4 * np.abs(gX0).sum()
+    scale = np.sum(np.abs(X0) * np.abs(gX0[:, ::-1]))
+    assert abs(np.sum(X0[:, 0] * gX0[:, 1] - X0[:, 1] * gX0[:, 0])) <= 1e-4 * scale
