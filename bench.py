@@ -30,6 +30,9 @@ METRIC = "pair-interactions/s + time-to-converge (SOR-ω vs ω=1) at n=65,536, 1
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed-FMA issue)
 PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 FLOPS_PER_PAIR = {2: 12, 3: 17}  # algorithmic flops of one ordered pair of the force pass
+# the opt-in pass evaluates each unordered pair once: differences, r^2, c, and
+# c [x - ref, 1] accumulated for both ends (2-D: 2 + 3 + 2 + 2 * 6; 3-D: 3 + 5 + 2 + 2 * 8)
+FLOPS_PER_UNORDERED_PAIR = {2: 19, 3: 26}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_ba65536_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1711_01228_amd", "csrc", "sl_kernels.hip")
 
@@ -287,18 +290,22 @@ def main():
     log("timed: %d steps %.3f s wall (%.3f s device), %.4g pair-interactions/s" % (args.steps, wall,
                                                                                    info["run_ms"] / 1e3, value))
 
-    # ---- force-kernel roofline (HIP events on the kernels' stream)
+    # ---- force-pass roofline (HIP events on the kernels' stream)
     ms = plan.profile(Xdev0, omega=args.omega, reps=5)
     t_force = ms["force"] * 1e-3
     flops = FLOPS_PER_PAIR[dim] * pairs
     achieved = flops / t_force / 1e12
     traffic = measured_traffic(dim)
+    t_sym = ms["force_sym"] * 1e-3
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_force", "kernel_ms": round(ms["force"], 4),
                 "pairs_per_launch": pairs, "flops_per_pair": FLOPS_PER_PAIR[dim],
                 "algorithmic_bytes_per_launch": float(n) * n,
                 "hbm_GBps_algorithmic": round(float(n) * n / t_force / 1e9, 1),
+                "unordered_pass": {"kernel": "k_force_sym + k_sym_reduce (opt-in)", "kernel_ms": round(ms["force_sym"], 4),
+                                   "TFLOPs": round(FLOPS_PER_UNORDERED_PAIR[dim] * pairs / 2 / t_sym / 1e12, 3)
+                                   if t_sym > 0 else None},
                 "step_kernel_ms": {k: round(v, 4) for k, v in ms.items()}}
     log("kernels (ms):", ms)
 

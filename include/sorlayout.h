@@ -87,6 +87,14 @@ typedef enum {
 #define SL_FLAG_TRACE_STRESS 1u  /* evaluate f(X^k) every iteration into trace[4]  */
 #define SL_FLAG_NO_GRAPH 2u      /* launch kernels one by one instead of replaying a
                                     captured HIP graph of `check_every` iterations */
+#define SL_FLAG_SYM_FORCE 4u     /* hop-count plans, SL_ORDER_JACOBI, no stress trace:
+                                    evaluate the force pass once per unordered pair
+                                    (F_j takes -c_ij (x_i - x_j), Newton's third law),
+                                    accumulating on the matrix cores; the same sums in
+                                    another order.  The first such run allocates an
+                                    upper-triangle copy of d (about n^2 / 2 bytes).
+                                    Otherwise SL_ENOTSUP.  Default: every ordered pair
+                                    from its row end, which is faster on gfx950     */
 
 /* The graph G = (V, E) of the problem statement (Sec. 1), host memory, CSR.
  * Symmetric: (u, v) present iff (v, u) present.  Vertex ids 0 .. n-1.  No self
@@ -211,10 +219,15 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  * the kernels run on (the plan's own stream, ordered after `stream`).  The
  * iteration starts from the device placement X (n * dim floats, not
  * modified) with relaxation factor `omega`:
- *   ms[0] all-pairs force pass   ms[1] Jacobi update + extrapolation
+ *   ms[0] all-pairs force pass as sl_plan_run runs it by default (every
+ *         ordered pair)
+ *   ms[1] Jacobi update + extrapolation
  *   ms[2] safeguard pass         ms[3] select + termination test
  *   ms[4] one application of L^W (the all-pairs matvec of a conjugate-
  *         gradient step of SL_ORDER_EXACT; 0 for edge-length plans)
+ *   ms[5] the force pass once per unordered pair with its reduction kernel
+ *         (SL_FLAG_SYM_FORCE; allocates its buffers on first use; 0 for
+ *         edge-length plans)
  * For profilers and benchmarks; the iterate buffers of the plan are left in an
  * unspecified state (a later sl_plan_run starts from its own X). */
 sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,

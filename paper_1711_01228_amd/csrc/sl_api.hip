@@ -111,7 +111,8 @@ sl_status check_options(const sl_options* o) {
   if (!(o->tol >= 0.0)) return fail(SL_EINVAL, "tol = %g must be >= 0", o->tol);
   if (o->max_iter < 0) return fail(SL_EINVAL, "max_iter = %d is negative", o->max_iter);
   if (o->safeguard != 0 && o->safeguard != 1) return fail(SL_EINVAL, "safeguard must be 0 or 1");
-  if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH)) return fail(SL_EINVAL, "unknown flag bits");
+  if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH | SL_FLAG_SYM_FORCE))
+    return fail(SL_EINVAL, "unknown flag bits");
   if (o->strategy != SL_OMEGA_FIXED && o->strategy != SL_OMEGA_SCHEDULE && o->strategy != SL_OMEGA_ENUM)
     return fail(SL_EINVAL, "unknown relaxation strategy %d", o->strategy);
   if (o->strategy == SL_OMEGA_SCHEDULE) {
@@ -170,6 +171,13 @@ struct sl_plan {
   float* Dbar = nullptr;        // n_pad^2 (edge-length plans)
   float* Sbuf = nullptr;        // n x n (edge-length plans)
   double* Gedge = nullptr;      // nnz
+  // force pass over unordered pairs (hop-count plans)
+  uint8_t* dsym = nullptr;      // upper triangle of d in that pass's order
+  int4* sym_items = nullptr;
+  int32_t* sym_panel_items = nullptr;
+  int nsym_items = 0;
+  double* Pi = nullptr;         // row partials: items x 512 x 4
+  float* Pj = nullptr;          // column partials: panels x n_pad x 4
   double* W = nullptr;          // n_pad
   float* Xb = nullptr;          // 3 iterate buffers
   float* Eb = nullptr;          // x~ - x^H, same format as one iterate buffer
@@ -219,6 +227,11 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->Dbar);
   (void)hipFree(p->Sbuf);
   (void)hipFree(p->Gedge);
+  (void)hipFree(p->dsym);
+  (void)hipFree(p->sym_items);
+  (void)hipFree(p->sym_panel_items);
+  (void)hipFree(p->Pi);
+  (void)hipFree(p->Pj);
   (void)hipFree(p->W);
   (void)hipFree(p->Xb);
   (void)hipFree(p->Eb);
@@ -377,7 +390,54 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
   return SL_OK;
 }
 
+// Buffers of the unordered-pair force pass (hop-count plans), made on first use:
+// the upper triangle of d in that pass's order (n_pad^2 / 2 bytes), its work
+// items and the row and column partial sums.
+sl_status ensure_sym(sl_plan* p) {
+  if (p->dsym) return SL_OK;
+  if (!p->d || p->n <= 1) return fail(SL_ENOTSUP, "the unordered-pair force pass needs a hop-count plan with n > 1");
+  const SymSplit ss = make_sym_split(p->n_pad, 32);
+  uint8_t* dsym = nullptr;
+  int4* items = nullptr;
+  int32_t* panel_items = nullptr;
+  double* Pi = nullptr;
+  float* Pj = nullptr;
+  hipError_t e = hipMalloc(&dsym, sym_bytes(p->n_pad));
+  if (e == hipSuccess) e = hipMalloc(&items, sizeof(int4) * ss.items.size());
+  if (e == hipSuccess) e = hipMalloc(&panel_items, sizeof(int32_t) * ss.panel_items.size());
+  if (e == hipSuccess) e = hipMalloc(&Pi, sizeof(double) * ss.items.size() * 512 * 4);
+  if (e == hipSuccess) e = hipMalloc(&Pj, sizeof(float) * (size_t)ss.npanels * p->n_pad * 4);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(items, ss.items.data(), sizeof(int4) * ss.items.size(), hipMemcpyHostToDevice, p->ps);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(panel_items, ss.panel_items.data(), sizeof(int32_t) * ss.panel_items.size(),
+                       hipMemcpyHostToDevice, p->ps);
+  if (e == hipSuccess) e = launch_build_sym(p->d, dsym, p->n_pad, p->sp.ng, p->ps);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->ps);  // the split's host vectors are temporaries
+  if (e != hipSuccess) {
+    (void)hipFree(dsym);
+    (void)hipFree(items);
+    (void)hipFree(panel_items);
+    (void)hipFree(Pi);
+    (void)hipFree(Pj);
+    return hip_fail(e, "unordered-pair force pass setup");
+  }
+  p->dsym = dsym;
+  p->sym_items = items;
+  p->sym_panel_items = panel_items;
+  p->Pi = Pi;
+  p->Pj = Pj;
+  p->nsym_items = (int)ss.items.size();
+  return SL_OK;
+}
+
 sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
+  if (lp.sym) {
+    HIP_TRY(launch_force_sym(p->dim, p->dsym, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+                             p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
+            "symmetric force kernels");
+    return SL_OK;
+  }
   HIP_TRY(launch_force(p->dim, lp.stress != 0, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                        p->ps),
           "force kernel");
@@ -640,6 +700,14 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   lp.enumerate = o->strategy == SL_OMEGA_ENUM ? 1 : 0;
   lp.omega_vertex = o->omega_vertex;
   lp.omega_sched = nullptr;
+  lp.sym = (o->flags & SL_FLAG_SYM_FORCE) ? 1 : 0;
+  if (lp.sym) {
+    if (p->df || lp.stress || o->ordering != SL_ORDER_JACOBI)
+      return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: hop-count plans, Jacobi ordering, no stress trace");
+    if (p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
+    if (p->n <= 1) lp.sym = 0;
+    else lp.slices = 1;
+  }
 
   if ((s = join_from(p, user)) != SL_OK) return s;
   if (o->omega_vertex && p->n > 0) {
@@ -684,6 +752,7 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   const bool exact = o->ordering == SL_ORDER_EXACT;
   if (use_graph && !exact) {
     std::vector<double> key = {(double)p->dim, lp.omega_p, lp.tol, (double)lp.safeguard, (double)lp.stress,
+                               (double)lp.sym,
                                (double)chunk, (double)(uintptr_t)o->trace, (double)(uintptr_t)o->xtrace,
                                (double)lp.enumerate, (double)(uintptr_t)lp.omega_sched,
                                (double)(uintptr_t)lp.omega_vertex};
@@ -777,10 +846,9 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   if (!(std::isfinite(omega) && omega > 0.0 && omega <= 16.0)) return fail(SL_EINVAL, "omega outside (0, 16]");
   sl_status s = join_from(p, (hipStream_t)stream);
   if (s != SL_OK) return s;
-  for (int k = 0; k < 5; ++k) ms[k] = 0.0;
+  for (int k = 0; k < 6; ++k) ms[k] = 0.0;
   if (p->n <= 1) return SL_OK;
-  const int kinds = p->df ? 4 : 5;  // the L^W matvec exists for hop-count plans
-  if (kinds == 5 && (s = ensure_exact(p)) != SL_OK) return s;
+  if (!p->df && (s = ensure_exact(p)) != SL_OK) return s;  // the L^W matvec exists for hop-count plans
   LoopParams lp{};
   lp.n = p->n;
   lp.n_pad = p->n_pad;
@@ -792,12 +860,15 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   lp.tol = -1.0;  // never stop while timing
   lp.safeguard = 1;
   lp.stress = 0;
+  lp.sym = 0;  // the force pass sl_plan_run uses by default
+  if (!p->df && (s = ensure_sym(p)) != SL_OK) return s;  // for ms[5]
   HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
   DevState* h = p->host_st;
   std::memset(h, 0, sizeof(DevState));
   h->max_iter = INT32_MAX;
   HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
-  for (int which = 0; which < kinds; ++which) {
+  for (int which = 0; which < 6; ++which) {
+    if ((which == 4 || which == 5) && p->df) continue;
     if (which == 4) {  // a solver state from the current placement: r_0, z
       HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                            p->ps), "force kernel");
@@ -814,8 +885,12 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                   "L^W kernel");
           break;
         case 0:
-          HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
-                               p->ps), "force kernel");
+          if ((s = enqueue_force(p, lp)) != SL_OK) return s;
+          break;
+        case 5:
+          HIP_TRY(launch_force_sym(p->dim, p->dsym, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+                                   p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
+                  "symmetric force kernels");
           break;
         case 1:
           HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red,

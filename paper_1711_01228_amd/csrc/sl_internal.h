@@ -71,6 +71,8 @@ struct LoopParams {
   // exact step: X^H = Y, the conjugate-gradient solution (double, column c at
   // c * n_pad); nullptr for the Jacobi step
   const double* exact_y;
+  int32_t sym;  // the force pass runs over unordered pairs (F in slice 0; slices = 1)
+  int32_t pad3;
 };
 
 // ---------------------------------------------------------------------------
@@ -117,6 +119,22 @@ Split make_split(int n_pad);
 hipError_t launch_cg_step(int dim, const CgVectors& v, const uint8_t* d, const double* W, const int32_t* comp, int n,
                           const DevState* st, CgState* cg, double* part, double* qpart, const Split& sp, double tol,
                           int max_steps, hipStream_t s);
+// Force pass over unordered pairs with MFMA accumulation (sl_sym.hip): work
+// items (panel of 8 row strips, first and end column strip, item index), the
+// items of each panel contiguous.
+struct SymSplit {
+  int nb = 0, npanels = 0;
+  std::vector<int4> items;
+  std::vector<int32_t> panel_items;  // npanels + 1 offsets into items
+};
+SymSplit make_sym_split(int n_pad, int chunk);
+size_t sym_bytes(int n_pad);  // the upper triangle of d in the symmetric pass's order
+hipError_t launch_build_sym(const uint8_t* d, uint8_t* dsym, int n_pad, int ng, hipStream_t s);
+// Writes F into force slice 0 of fpart (Pi: items x 512 x 4 doubles, Pj:
+// panels x n_pad x 4 floats of partial sums).
+hipError_t launch_force_sym(int dim, const uint8_t* dsym, const float* Xb, size_t stride, const DevState* st,
+                            const int4* items, int nitems, const int32_t* panel_items, double* Pi, float* Pj,
+                            double* fpart, int n_pad, hipStream_t s);
 // One application of L^W to p (also used by the profiler).
 hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const DevState* st, CgState* cg, double* qpart,
                      double* pqrec, const Split& sp, hipStream_t s);

@@ -1,0 +1,89 @@
+"""The force pass over unordered pairs (MFMA accumulation) against the pass
+over all ordered pairs: the same sums in another order and form.
+
+One Jacobi step from the same start: max |x^sym - x^direct| <= 2e-6 * diam
+(both sum FP32 pair terms; the unordered pass forms F as (x_i - ref) S_i -
+sum_j c_ij (x_j - ref) from FP32 partial sums).  Ragged sizes (n_pad not a
+multiple of the 512-row panel), tiny graphs, 2-D and 3-D.  The unordered pass
+is opt-in (SL_FLAG_SYM_FORCE); every other GPU test runs the default pass.
+"""
+import numpy as np
+import pytest
+
+from paper_1711_01228_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(X):
+    import torch
+
+    return torch.tensor(np.asarray(X, dtype=np.float32), device="cuda").contiguous()
+
+
+def diam(X):
+    return float(np.linalg.norm(X.max(0) - X.min(0)))
+
+
+def graphs():
+    return {
+        "path2": inputs.to_csr(2, [(0, 1)]),
+        "grid16": inputs.grid16(0)[0],
+        "ragged_129": inputs.erdos_renyi(129, 400, 5),
+        "tree700": inputs.random_tree(700, 3),
+        "ba3000": inputs.barabasi_albert(3000, 3, 11),
+        "er5000": inputs.erdos_renyi(5000, 15000, 2),
+    }
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("name", sorted(graphs()))
+def test_unordered_pass_matches_ordered_pass(name, dim):
+    from paper_1711_01228_amd import binding as b
+
+    g = graphs()[name]
+    print("case", name, dim, flush=True)
+    X0 = inputs.uniform_positions(g.n, dim, seed=41, hi=float(np.sqrt(g.n)))
+    with b.Plan(g, dim) as plan:
+        Xs, Xd = dev(X0), dev(X0)
+        plan.run(Xs, omega=1.0, tol=0.0, max_iter=1, sym_force=True)
+        plan.run(Xd, omega=1.0, tol=0.0, max_iter=1)
+        err = np.abs(Xs.cpu().numpy().astype(np.float64) - Xd.cpu().numpy()).max()
+        assert err <= 2e-6 * diam(X0), err
+        # a few steps with extrapolation and the safeguard stay together too
+        Xs, Xd = dev(X0), dev(X0)
+        ts = plan.run(Xs, omega=1.5, tol=0.0, max_iter=10, trace=True, sym_force=True)["trace"]
+        td = plan.run(Xd, omega=1.5, tol=0.0, max_iter=10, trace=True)["trace"]
+        if np.array_equal(ts[:, 1], td[:, 1]):
+            assert np.abs(Xs.cpu().numpy() - Xd.cpu().numpy()).max() <= 1e-5 * diam(Xd.cpu().numpy())
+
+
+def test_unordered_pass_is_bitwise_repeatable():
+    from paper_1711_01228_amd import binding as b
+
+    g, X0 = inputs.grid16(2)
+    with b.Plan(g, 2) as plan:
+        outs = []
+        for _ in range(3):
+            X = dev(X0)
+            plan.run(X, omega=1.5, tol=0.0, max_iter=25, sym_force=True)
+            outs.append(X.cpu().numpy())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+def test_unordered_pass_is_refused_where_it_does_not_apply():
+    from paper_1711_01228_amd import binding as b
+
+    g, X0 = inputs.grid16(0)
+    with b.Plan(g, 2) as plan:
+        for kw in ({"trace_stress": True}, {"ordering": "exact"}):
+            with pytest.raises(b.SlError) as e:
+                plan.run(dev(X0), max_iter=2, sym_force=True, **kw)
+            assert e.value.status == b.SL_ENOTSUP
+    gw = inputs.to_csr(g.n, g.edges(), np.ones(g.num_edges, dtype=np.float32))
+    with b.Plan(gw, 2) as plan:
+        with pytest.raises(b.SlError) as e:
+            plan.run(dev(X0), max_iter=2, sym_force=True)
+        assert e.value.status == b.SL_ENOTSUP
+        assert plan.profile(dev(X0), omega=1.5, reps=1)["force_sym"] == 0.0
