@@ -96,6 +96,16 @@ typedef enum {
                                     Otherwise SL_ENOTSUP.  Default: every ordered pair
                                     from its row end, which is faster on gfx950     */
 
+#define SL_FLAG_SEPARATE_SAFEGUARD 8u  /* evaluate f(X~) - f(X^H) in its own pass over
+                                          unordered pairs and the next force pass
+                                          after the decision.  Default (Jacobi
+                                          ordering, a safeguard to evaluate, no
+                                          enumeration or stress trace): the
+                                          safeguard is summed inside the next
+                                          iteration's force pass, taken at X~;
+                                          when X~ is rejected the force pass at
+                                          X^H runs again.  The same iterates. */
+
 /* The graph G = (V, E) of the problem statement (Sec. 1), host memory, CSR.
  * Symmetric: (u, v) present iff (v, u) present.  Vertex ids 0 .. n-1.  No self
  * loops, no duplicate entries; neighbours of each row in any order. */
@@ -219,8 +229,7 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  * the kernels run on (the plan's own stream, ordered after `stream`).  The
  * iteration starts from the device placement X (n * dim floats, not
  * modified) with relaxation factor `omega`:
- *   ms[0] all-pairs force pass as sl_plan_run runs it by default (every
- *         ordered pair)
+ *   ms[0] all-pairs force pass over every ordered pair (k_force)
  *   ms[1] Jacobi update + extrapolation
  *   ms[2] safeguard pass         ms[3] select + termination test
  *   ms[4] one application of L^W (the all-pairs matvec of a conjugate-
@@ -228,6 +237,9 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  *   ms[5] the force pass once per unordered pair with its reduction kernel
  *         (SL_FLAG_SYM_FORCE; allocates its buffers on first use; 0 for
  *         edge-length plans)
+ *   ms[6] the force pass at X~ with the safeguard summed in (the pass that
+ *         replaces ms[0] + ms[2] in an iteration that extrapolates)
+ * ms holds 7 doubles.
  * For profilers and benchmarks; the iterate buffers of the plan are left in an
  * unspecified state (a later sl_plan_run starts from its own X). */
 sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,

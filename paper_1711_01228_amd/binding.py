@@ -22,6 +22,7 @@ SL_TRACE_COLS = 5
 SL_FLAG_TRACE_STRESS = 1
 SL_FLAG_NO_GRAPH = 2
 SL_FLAG_SYM_FORCE = 4
+SL_FLAG_SEPARATE_SAFEGUARD = 8
 SL_OMEGA_FIXED, SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM = 0, 1, 2
 SL_ORDER_JACOBI, SL_ORDER_EXACT = 0, 1
 ORDERINGS = {"jacobi": SL_ORDER_JACOBI, "exact": SL_ORDER_EXACT}
@@ -157,7 +158,7 @@ def graph_args(g) -> _GraphArgs:
 def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0,
                  trace_stress=False, use_graph=True, trace=None, xtrace=None, strategy=SL_OMEGA_FIXED,
                  omega_schedule=None, omega_vertex=None, ordering=SL_ORDER_JACOBI, inner_tol=0.0,
-                 inner_max_iter=0, sym_force=False) -> sl_options:
+                 inner_max_iter=0, sym_force=False, separate_safeguard=False) -> sl_options:
     """omega_schedule: host float64 array (kept alive by the caller);
     omega_vertex: device pointer (int) or None."""
     o = sl_options()
@@ -165,7 +166,8 @@ def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, chec
     o.dim, o.omega, o.tol, o.max_iter = int(dim), float(omega), float(tol), int(max_iter)
     o.safeguard, o.check_every = int(bool(safeguard)), int(check_every)
     o.flags = (SL_FLAG_TRACE_STRESS if trace_stress else 0) | (0 if use_graph else SL_FLAG_NO_GRAPH) | \
-        (SL_FLAG_SYM_FORCE if sym_force else 0)
+        (SL_FLAG_SYM_FORCE if sym_force else 0) | \
+        (SL_FLAG_SEPARATE_SAFEGUARD if separate_safeguard else 0)
     o.trace = None if trace is None else int(trace)
     o.xtrace = None if xtrace is None else int(xtrace)
     o.strategy = int(strategy)
@@ -266,7 +268,7 @@ def sl_plan_weights(plan: int, n: int, stream=None) -> np.ndarray:
 
 
 def sl_plan_profile(plan: int, X_ptr: int, dim: int, omega: float, reps: int, stream=None) -> np.ndarray:
-    ms = np.zeros(6, dtype=np.float64)
+    ms = np.zeros(7, dtype=np.float64)
     _check(LIB.sl_plan_profile(plan, X_ptr, int(dim), float(omega), int(reps), _stream_handle(stream),
                                ms.ctypes.data))
     return ms
@@ -296,7 +298,7 @@ class Plan:
     def run(self, X, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0, trace=False,
             trace_stress=False, trace_positions=False, use_graph=True, stream=None, strategy="fixed",
             omega_schedule=None, omega_vertex=None, ordering="jacobi", inner_tol=0.0, inner_max_iter=0,
-            sym_force=False):
+            sym_force=False, separate_safeguard=False):
         """Run Algorithm 2 in place on the device tensor X (n x dim, float32).
 
         strategy: "fixed" (omega), "schedule" (omega_schedule, one classical
@@ -307,6 +309,8 @@ class Plan:
         inner_tol, at most inner_max_iter steps; 0 selects the defaults).
         sym_force: evaluate the force pass once per unordered pair
         (SL_FLAG_SYM_FORCE; hop-count plans, Jacobi ordering).
+        separate_safeguard: evaluate the safeguard in its own pass instead of
+        inside the next force pass (SL_FLAG_SEPARATE_SAFEGUARD).
         Returns the sl_result fields; with ``trace`` also a ``trace`` array
         (iterations x 5) and with ``trace_positions`` the ``positions``
         (iterations x n x dim) on the host."""
@@ -329,7 +333,7 @@ class Plan:
         opt = make_options(self.dim, omega, tol, max_iter, safeguard, check_every, trace_stress, use_graph,
                            None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr(),
                            strat, sched, None if wv is None else wv.data_ptr(), ORDERINGS[ordering], inner_tol,
-                           inner_max_iter, sym_force)
+                           inner_max_iter, sym_force, separate_safeguard)
         info = sl_plan_run(self.handle, X.data_ptr(), opt, stream)
         k = info["iterations"]
         if tr is not None:
@@ -374,7 +378,8 @@ class Plan:
     def profile(self, X, omega=1.5, reps=5, stream=None) -> dict:
         """Average device ms of each kernel of one iteration (HIP events)."""
         ms = sl_plan_profile(self.handle, X.data_ptr(), self.dim, omega, reps, stream)
-        return dict(zip(("force", "update", "safeguard", "select", "lw_matvec", "force_sym"), ms.tolist()))
+        return dict(zip(("force", "update", "safeguard", "select", "lw_matvec", "force_sym",
+                                  "force_safeguard"), ms.tolist()))
 
     def close(self):
         if self.handle:

@@ -111,7 +111,7 @@ sl_status check_options(const sl_options* o) {
   if (!(o->tol >= 0.0)) return fail(SL_EINVAL, "tol = %g must be >= 0", o->tol);
   if (o->max_iter < 0) return fail(SL_EINVAL, "max_iter = %d is negative", o->max_iter);
   if (o->safeguard != 0 && o->safeguard != 1) return fail(SL_EINVAL, "safeguard must be 0 or 1");
-  if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH | SL_FLAG_SYM_FORCE))
+  if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH | SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD))
     return fail(SL_EINVAL, "unknown flag bits");
   if (o->strategy != SL_OMEGA_FIXED && o->strategy != SL_OMEGA_SCHEDULE && o->strategy != SL_OMEGA_ENUM)
     return fail(SL_EINVAL, "unknown relaxation strategy %d", o->strategy);
@@ -445,6 +445,21 @@ sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
 }
 
 sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* o) {
+  if (lp.fuse) {
+    // the force of X^k came from the previous iteration (or the pass before the loop)
+    HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
+            "update kernel");
+    HIP_TRY(launch_force_sg(p->dim, lp, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart, p->sp,
+                            p->ps),
+            "fused force and safeguard kernel");
+    HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->sp.blocks_x * p->sp.slices, p->st, o->trace,
+                          p->ps),
+            "select kernel");
+    HIP_TRY(launch_force_cond(p->dim, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->sp, p->n_pad, p->ps),
+            "force kernel");
+    if (o->xtrace) HIP_TRY(launch_record(p->Xb, p->stride, p->st, o->xtrace, p->n, p->dim, p->ps), "record kernel");
+    return SL_OK;
+  }
   sl_status s = enqueue_force(p, lp);
   if (s != SL_OK) return s;
   return enqueue_after_force(p, lp, o);
@@ -643,7 +658,9 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess) e = hipMalloc(&p->fpart, sizeof(double) * p->sp.slices * 3 * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->spart, sizeof(double) * p->sp.slices * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(double) * 8 * p->nred);
-  if (e == hipSuccess) e = hipMalloc(&p->sgpart, sizeof(double) * p->nsg * kEnumCandidates);
+  if (e == hipSuccess)
+    e = hipMalloc(&p->sgpart, sizeof(double) * std::max<size_t>((size_t)p->nsg * kEnumCandidates,
+                                                                (size_t)p->sp.blocks_x * p->sp.slices));
   if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
   if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
   if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
@@ -700,6 +717,13 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   lp.enumerate = o->strategy == SL_OMEGA_ENUM ? 1 : 0;
   lp.omega_vertex = o->omega_vertex;
   lp.omega_sched = nullptr;
+  // the safeguard rides on the next force pass: Jacobi step, a safeguard to
+  // evaluate, no enumeration, stress trace or unordered-pair pass
+  lp.fuse = (o->ordering == SL_ORDER_JACOBI && lp.safeguard && !lp.enumerate && !lp.stress &&
+             !(o->flags & (SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD)) &&
+             (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->omega_vertex) && p->n > 1)
+                ? 1
+                : 0;
   lp.sym = (o->flags & SL_FLAG_SYM_FORCE) ? 1 : 0;
   if (lp.sym) {
     if (p->df || lp.stress || o->ordering != SL_ORDER_JACOBI)
@@ -746,13 +770,15 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   h->converged = p->n <= 1 ? 1 : 0;
   HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
 
-  int chunk = o->check_every > 0 ? o->check_every : (p->n <= 8192 ? 32 : 4);
+  // iterations per captured graph between looks at the stop flag (those after
+  // the stop return at once)
+  int chunk = o->check_every > 0 ? o->check_every : (p->n <= 8192 ? 32 : 8);
   chunk = std::max(1, std::min(chunk, std::max(1, o->max_iter)));
   const bool use_graph = !(o->flags & SL_FLAG_NO_GRAPH);
   const bool exact = o->ordering == SL_ORDER_EXACT;
   if (use_graph && !exact) {
     std::vector<double> key = {(double)p->dim, lp.omega_p, lp.tol, (double)lp.safeguard, (double)lp.stress,
-                               (double)lp.sym,
+                               (double)lp.sym, (double)lp.fuse,
                                (double)chunk, (double)(uintptr_t)o->trace, (double)(uintptr_t)o->xtrace,
                                (double)lp.enumerate, (double)(uintptr_t)lp.omega_sched,
                                (double)(uintptr_t)lp.omega_vertex};
@@ -781,6 +807,7 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
     }
   }
   HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+  if (lp.fuse && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^0
   if (exact) {
     int inner = 0;
     if ((s = run_exact(p, lp, o, use_graph, &inner)) != SL_OK) return s;
@@ -846,7 +873,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   if (!(std::isfinite(omega) && omega > 0.0 && omega <= 16.0)) return fail(SL_EINVAL, "omega outside (0, 16]");
   sl_status s = join_from(p, (hipStream_t)stream);
   if (s != SL_OK) return s;
-  for (int k = 0; k < 6; ++k) ms[k] = 0.0;
+  for (int k = 0; k < 7; ++k) ms[k] = 0.0;
   if (p->n <= 1) return SL_OK;
   if (!p->df && (s = ensure_exact(p)) != SL_OK) return s;  // the L^W matvec exists for hop-count plans
   LoopParams lp{};
@@ -867,7 +894,10 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   std::memset(h, 0, sizeof(DevState));
   h->max_iter = INT32_MAX;
   HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
-  for (int which = 0; which < 6; ++which) {
+  LoopParams lpf = lp;  // the fused pass, extrapolating with omega
+  lpf.fuse = 1;
+  lpf.safeguard = 1;
+  for (int which = 0; which < 7; ++which) {
     if ((which == 4 || which == 5) && p->df) continue;
     if (which == 4) {  // a solver state from the current placement: r_0, z
       HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
@@ -886,6 +916,11 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
           break;
         case 0:
           if ((s = enqueue_force(p, lp)) != SL_OK) return s;
+          break;
+        case 6:
+          HIP_TRY(launch_force_sg(p->dim, lpf, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart,
+                                  p->sp, p->ps),
+                  "fused force and safeguard kernel");
           break;
         case 5:
           HIP_TRY(launch_force_sym(p->dim, p->dsym, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,

@@ -52,7 +52,7 @@ struct DevState {
   double omega_used;  // paper's factor of the last iteration
   double enum_c;      // enumerating: factor picked by the last select
   int32_t enum_pending;  // enumerating: X~ = X^H + enum_c * step is still to be formed
-  int32_t pad2;
+  int32_t need_force;    // fused safeguard: X~ was rejected, the force at X^H is still to come
 };
 
 constexpr int kEnumCandidates = 18;  // paper's factors 0.5, 1.0, ..., 9.0 (0 = keep X^H)
@@ -71,8 +71,8 @@ struct LoopParams {
   // exact step: X^H = Y, the conjugate-gradient solution (double, column c at
   // c * n_pad); nullptr for the Jacobi step
   const double* exact_y;
-  int32_t sym;  // the force pass runs over unordered pairs (F in slice 0; slices = 1)
-  int32_t pad3;
+  int32_t sym;   // the force pass runs over unordered pairs (F in slice 0; slices = 1)
+  int32_t fuse;  // the safeguard rides on the next iteration's force pass (at X~)
 };
 
 // ---------------------------------------------------------------------------
@@ -177,6 +177,14 @@ hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, f
 hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                         const DevState* st, double* fpart, double* spart, const Split& sp, int n_pad,
                         hipStream_t s);
+// The force pass at X~ with the safeguard sums of the same iteration (one
+// double per workgroup into sgpart: slices * blocks_x of them).
+hipError_t launch_force_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
+                           size_t stride, const float* Eb, const DevState* st, double* fpart, double* sgpart,
+                           const Split& sp, hipStream_t s);
+// The force pass at X^k if the last select rejected X~ in a fused iteration.
+hipError_t launch_force_cond(int dim, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                             const DevState* st, double* fpart, const Split& sp, int n_pad, hipStream_t s);
 hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, const double* spart,
                          const double* W, float* Xb, size_t stride, float* Eb, const DevState* st, double* red,
                          hipStream_t s);

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace sl {
@@ -57,12 +58,13 @@ template <int DIM, bool STRESS, bool FD>
 __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, const float* __restrict__ df,
                                                const float* __restrict__ Xb, size_t stride,
                                                const DevState* __restrict__ st, double* __restrict__ fpart,
-                                               double* __restrict__ spart, int nrb, int ng, int gps, int n_pad) {
+                                               double* __restrict__ spart, int nrb, int ng, int gps, int n_pad,
+                                               int cond) {
   using V = typename VecT<DIM>::T;
   using E = typename WeightEntry<STRESS>::T;
   using C = typename DChunkT<FD>::T;
   __shared__ E lut[256];
-  if (st->done) return;
+  if (st->done || (cond && !st->need_force)) return;
   if constexpr (!FD) {
     fill_weight_table<STRESS>(lut);
     __syncthreads();
@@ -299,6 +301,160 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
 }
 
 // ---------------------------------------------------------------------------
+// The force pass at X~ with the safeguard of the same iteration folded in
+// (Alg. 2 line 6 and the next iteration's force pass need the same pair
+// geometry).  Every ordered pair takes its force term at X~ exactly as in
+// k_force (same order and precision), so that if X~ is accepted the next
+// iteration uses these sums as they are; otherwise k_force runs again at X^H.
+// The pairs j > i also add their share of f(X~) - f(X^H), with
+//   t = x~_i - x~_j,  e = e_i - e_j (e = x~ - x^H),  r~^2 = t.t,
+//   m = r~^2 - r^H^2 = e.(2t - e)  (no difference of nearly equal squares),
+//   r^H = sqrt|r~^2 - m|,  s = r~ + r^H,
+//   term = w (r~ - r^H)(r~ + r^H - 2d) = m (1/d^2 - (2/d) / s).
+// r^H^2 is formed as r~^2 - m: exact unless r^H << r~, where its error is
+// small against s.  An iteration that does not extrapolate (a scheduled factor
+// of 1) takes the force at X^H alone.  One double per workgroup (slice-major).
+// Slices run right to left, the heavier (mostly upper-triangle) ones first.
+// ---------------------------------------------------------------------------
+template <int DIM, bool FD, int MODE>  // MODE 0: force only; 1: diagonal block (mask j <= i); 2: j > i throughout
+__device__ __forceinline__ void force_sg_group(const typename DChunkT<FD>::T& q, const float4* lut,
+                                               const typename VecT<DIM>::T& xi, const typename VecT<DIM>::T& ei,
+                                               const typename VecT<DIM>::T* __restrict__ xj,
+                                               const typename VecT<DIM>::T* __restrict__ ej, int jrel, float& a0,
+                                               float& a1, float& a2, float& as) {
+  using V = typename VecT<DIM>::T;
+#pragma unroll
+  for (int k = 0; k < kColGroup; ++k) {
+    float inv, w, l2 = 0.f;
+    if constexpr (FD) {
+      const float dv = fchunk_at(q, k);
+      inv = dv > 0.f ? __builtin_amdgcn_rcpf(dv) : 0.f;
+      w = inv * inv;
+      if constexpr (MODE != 0) l2 = -2.f * inv;
+    } else {
+      const uint32_t b = byte_of(chunk_word(q, k), k & 3);
+      if constexpr (MODE != 0) {
+        const float4 e4 = lut[b];
+        inv = e4.x;
+        w = e4.y;
+        l2 = e4.z;
+      } else {
+        const float2 e2 = *reinterpret_cast<const float2*>(&lut[b]);
+        inv = e2.x;
+        w = e2.y;
+      }
+    }
+    const V p = xj[k];
+    const float tx = xi.x - p.x, ty = xi.y - p.y;
+    float r2 = fmaf(tx, tx, kTiny);
+    r2 = fmaf(ty, ty, r2);
+    float tz = 0.f;
+    if constexpr (DIM == 3) {
+      tz = xi.z - p.z;
+      r2 = fmaf(tz, tz, r2);
+    }
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float c = fmaf(inv, rinv, -w);
+    a0 = fmaf(c, tx, a0);
+    a1 = fmaf(c, ty, a1);
+    if constexpr (DIM == 3) a2 = fmaf(c, tz, a2);
+    if constexpr (MODE != 0) {
+      const V pe = ej[k];
+      const float ex = ei.x - pe.x, ey = ei.y - pe.y;
+      float m = ex * fmaf(2.f, tx, -ex);
+      m = fmaf(ey, fmaf(2.f, ty, -ey), m);
+      if constexpr (DIM == 3) {
+        const float ez = ei.z - pe.z;
+        m = fmaf(ez, fmaf(2.f, tz, -ez), m);
+      }
+      const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
+      const float sum = fmaf(r2, rinv, rh);
+      float term = m * fmaf(l2, __builtin_amdgcn_rcpf(sum), w);
+      if constexpr (MODE == 1) {
+        if (k <= jrel) term = 0.f;  // column j = i - jrel + k is not right of the diagonal
+      }
+      as += term;
+    }
+  }
+}
+
+template <int DIM, bool FD>
+__global__ __launch_bounds__(256) void k_force_sg(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                                  const float* __restrict__ Xb, size_t stride,
+                                                  const float* __restrict__ Eb, const double* __restrict__ omega_sched,
+                                                  double omega_p, int vertex_factors, const DevState* __restrict__ st,
+                                                  double* __restrict__ fpart, double* __restrict__ sgpart, int nrb,
+                                                  int ng, int gps, int n_pad) {
+  using V = typename VecT<DIM>::T;
+  using C = typename DChunkT<FD>::T;
+  __shared__ float4 lut[256];  // (1/d, 1/d^2, -2/d, 0)
+  if (st->done) return;
+  if constexpr (!FD) {
+    for (int b = threadIdx.x; b < 256; b += blockDim.x) {
+      const float fb = (float)b;
+      const float inv = b ? 1.0f / fb : 0.f;
+      lut[b] = make_float4(inv, b ? 1.0f / (fb * fb) : 0.f, -2.f * inv, 0.f);
+    }
+    __syncthreads();
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int rb = blockIdx.x * 4 + wave;
+  const int slice = gridDim.y - 1 - blockIdx.y;
+  if (rb >= nrb) {  // no rows: take part in the workgroup's sum only
+    __syncthreads();
+    return;
+  }
+  const int g0 = slice * gps;
+  const int g1 = min(g0 + gps, ng);
+  const double wp = omega_sched ? omega_sched[st->iter] : omega_p;
+  const bool sg = vertex_factors || wp != 0.0;
+  const int cur = st->cur;
+  const V* __restrict__ X = reinterpret_cast<const V*>(Xb + (size_t)(sg ? (cur + 2) % 3 : (cur + 1) % 3) * stride);
+  const V* __restrict__ E = reinterpret_cast<const V*>(Eb);
+  const int i = rb * kRowBlock + lane;
+  const V xi = X[i];
+  const V ei = sg ? E[i] : V{};
+  // column groups left of the diagonal block take the force only
+  const int gdiag = sg ? rb * (kRowBlock / kColGroup) : ng;
+  const int gfree = gdiag + kRowBlock / kColGroup;
+  double F0 = 0.0, F1 = 0.0, F2 = 0.0, S = 0.0;
+  auto run = [&](auto mode_tag, int ga, int gb) {
+    constexpr int MODE = decltype(mode_tag)::value;
+    if (ga >= gb) return;
+    C q = load_chunk<FD>(d, df, rb, ng, ga, lane);
+    for (int g = ga; g < gb; ++g) {
+      C qn = zero_chunk<FD>();
+      if (g + 1 < gb) qn = load_chunk<FD>(d, df, rb, ng, g + 1, lane);
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
+      force_sg_group<DIM, FD, MODE>(q, lut, xi, ei, X + (size_t)g * kColGroup, E + (size_t)g * kColGroup,
+                                    i - g * kColGroup, a0, a1, a2, as);
+      F0 += (double)a0;
+      F1 += (double)a1;
+      if constexpr (DIM == 3) F2 += (double)a2;
+      if constexpr (MODE != 0) S += (double)as;
+      q = qn;
+    }
+  };
+  run(std::integral_constant<int, 0>{}, g0, min(g1, gdiag));
+  run(std::integral_constant<int, 1>{}, max(g0, gdiag), min(g1, gfree));
+  run(std::integral_constant<int, 2>{}, max(g0, gfree), g1);
+  double* fp = fpart + (size_t)slice * DIM * n_pad + i;
+  fp[0] = F0;
+  fp[n_pad] = F1;
+  if constexpr (DIM == 3) fp[2 * (size_t)n_pad] = F2;
+  // one double per workgroup: the waves' sums in wave order
+  __shared__ double wsum[4];
+  S = wave_sum(S);
+  if (lane == 0) wsum[wave] = S;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 4 && blockIdx.x * 4 + w < nrb; ++w) t += wsum[w];
+    sgpart[(size_t)slice * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Enumerating strategy (Sec. 5.2): f(X^H + c D) - f(X^H) for the paper's
 // factors c = 0.5, 1.0, ..., 9.0 at once, D = X^H - X^k the stored step.  Per
 // pair, with h = x^H_i - x^H_j, s = D_i - D_j, a = h.s, b = s.s:
@@ -429,8 +585,17 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     for (int q = 0; q < 7; ++q) v[q] += red[(size_t)b * 8 + q];
   }
   const bool sg = !p.enumerate && p.safeguard && (wp != 0.0 || p.omega_vertex);
-  if (sg)
-    for (int b = threadIdx.x; b < nsg; b += 256) v[7] += sgpart[b];
+  if (sg) {
+    // eight independent sums per thread (loads in flight), added in a fixed order
+    double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nsg; b += 256 * 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (b + q * 256 < nsg) u[q] += sgpart[b + q * 256];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[7] += u[q];
+  }
   if (p.enumerate && threadIdx.x < kEnumCandidates) {
     double t = 0.0;  // items in order
     for (int b = 0; b < nsg; ++b) t += sgpart[(size_t)b * kEnumCandidates + threadIdx.x];
@@ -450,6 +615,7 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
   const int cur = st->cur, h = (cur + 1) % 3, t = (cur + 2) % 3;
   double accepted;
   double df = sg ? v[7] : 0.0;
+  st->need_force = 0;
   double used = p.omega_vertex ? __builtin_nan("") : wp;
   st->enum_pending = 0;
   if (p.enumerate) {
@@ -481,6 +647,7 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     st->cur = take ? t : h;
     accepted = take ? 1.0 : 0.0;
     if (!take) st->rejected += 1;
+    if (!take && p.fuse) st->need_force = 1;  // the pass after this one computed the force at X~
   } else {
     st->cur = t;
     accepted = 1.0;
@@ -696,10 +863,12 @@ Split make_split(int n_pad) {
   Split sp;
   sp.nrb = n_pad / kRowBlock;
   sp.ng = n_pad / kColGroup;
-  // About 8 waves per SIMD over the chip (256 CUs x 4 SIMDs), with at least
-  // 8 column groups (128 columns) per wave.
+  // About 32 waves per SIMD over the chip (256 CUs x 4 SIMDs): four rounds of
+  // 8 resident waves, so that the dispatcher can even out passes whose waves
+  // differ in work (the fused safeguard's upper triangle); at least 8 column
+  // groups (128 columns) per wave.
   const int max_slices = std::max(1, sp.ng / 8);
-  const int want = std::max(1, 8192 / std::max(1, sp.nrb));
+  const int want = std::max(1, 32768 / std::max(1, sp.nrb));
   int slices = std::min(max_slices, want);
   sp.groups_per_slice = (sp.ng + slices - 1) / slices;
   sp.slices = (sp.ng + sp.groups_per_slice - 1) / sp.groups_per_slice;
@@ -751,14 +920,44 @@ hipError_t launch_pack_out(const float* Xb, const DevState* st, size_t stride, f
 
 template <int DIM, bool STRESS>
 static void force_launch(const uint8_t* d, const float* df, const float* Xb, size_t stride, const DevState* st,
-                         double* fpart, double* spart, const Split& sp, int n_pad, hipStream_t s) {
+                         double* fpart, double* spart, const Split& sp, int n_pad, hipStream_t s, int cond = 0) {
   const dim3 grid(sp.blocks_x, sp.slices);
   if (df)
     k_force<DIM, STRESS, true><<<grid, 256, 0, s>>>(d, df, Xb, stride, st, fpart, spart, sp.nrb, sp.ng,
-                                                     sp.groups_per_slice, n_pad);
+                                                     sp.groups_per_slice, n_pad, cond);
   else
     k_force<DIM, STRESS, false><<<grid, 256, 0, s>>>(d, df, Xb, stride, st, fpart, spart, sp.nrb, sp.ng,
-                                                      sp.groups_per_slice, n_pad);
+                                                      sp.groups_per_slice, n_pad, cond);
+}
+
+hipError_t launch_force_cond(int dim, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                             const DevState* st, double* fpart, const Split& sp, int n_pad, hipStream_t s) {
+  if (dim == 2) force_launch<2, false>(d, df, Xb, stride, st, fpart, nullptr, sp, n_pad, s, 1);
+  else force_launch<3, false>(d, df, Xb, stride, st, fpart, nullptr, sp, n_pad, s, 1);
+  return hipGetLastError();
+}
+
+template <int DIM, bool FD>
+static void force_sg_launch(const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                            const float* Eb, const DevState* st, double* fpart, double* sgpart, const Split& sp,
+                            hipStream_t s) {
+  const dim3 grid(sp.blocks_x, sp.slices);
+  k_force_sg<DIM, FD><<<grid, 256, 0, s>>>(d, df, Xb, stride, Eb, lp.omega_sched, lp.omega_p,
+                                            lp.omega_vertex ? 1 : 0, st, fpart, sgpart, sp.nrb, sp.ng,
+                                            sp.groups_per_slice, lp.n_pad);
+}
+
+hipError_t launch_force_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
+                           size_t stride, const float* Eb, const DevState* st, double* fpart, double* sgpart,
+                           const Split& sp, hipStream_t s) {
+  if (dim == 2) {
+    if (df) force_sg_launch<2, true>(lp, d, df, Xb, stride, Eb, st, fpart, sgpart, sp, s);
+    else force_sg_launch<2, false>(lp, d, df, Xb, stride, Eb, st, fpart, sgpart, sp, s);
+  } else {
+    if (df) force_sg_launch<3, true>(lp, d, df, Xb, stride, Eb, st, fpart, sgpart, sp, s);
+    else force_sg_launch<3, false>(lp, d, df, Xb, stride, Eb, st, fpart, sgpart, sp, s);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_force(int dim, bool stress, const uint8_t* d, const float* df, const float* Xb, size_t stride,

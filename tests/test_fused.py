@@ -1,0 +1,107 @@
+"""The safeguard summed inside the next iteration's force pass (the default)
+against the safeguard in its own pass (SL_FLAG_SEPARATE_SAFEGUARD).
+
+Both take the same force sums in the same order, so where the two runs take
+the same decisions the iterates are equal bit for bit.  The safeguard sums
+differ in formula (r^H from r~^2 - m) and order: f(X~) - f(X^H) agrees to
+1e-3 relative, or 1e-6 of the largest |f(X~) - f(X^H)| of the run.  Cases:
+fixed omega with many rejections (the force at X^H runs again), a schedule
+with factors of 1 (iterations without extrapolation), per-vertex factors, 3-D,
+an edge-length plan, ragged sizes, with and without captured graphs.
+"""
+import numpy as np
+import pytest
+
+from paper_1711_01228_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(X):
+    import torch
+
+    return torch.tensor(np.asarray(X, dtype=np.float32), device="cuda").contiguous()
+
+
+def _both(plan, X0, **kw):
+    Xa, Xb = dev(X0), dev(X0)
+    ta = plan.run(Xa, trace=True, **kw)
+    tb = plan.run(Xb, trace=True, separate_safeguard=True, **kw)
+    return Xa.cpu().numpy(), ta, Xb.cpu().numpy(), tb
+
+
+def _check(Xa, ta, Xb, tb):
+    assert ta["iterations"] == tb["iterations"]
+    np.testing.assert_array_equal(ta["trace"][:, 1], tb["trace"][:, 1])  # the same decisions
+    da, db = ta["trace"][:, 2], tb["trace"][:, 2]
+    scale = np.nanmax(np.abs(db)) if len(db) else 0.0
+    np.testing.assert_allclose(da, db, rtol=1e-3, atol=1e-6 * scale)
+    np.testing.assert_array_equal(Xa, Xb)
+    assert ta["rejected"] == tb["rejected"]
+
+
+CASES = {
+    "grid16_w4": (lambda: inputs.grid16(3), 2, {"omega": 4.0, "tol": 0.0, "max_iter": 40}),
+    "ba3000_w15": (lambda: (inputs.barabasi_albert(3000, 3, 5), None), 2, {"omega": 1.5, "tol": 1e-4,
+                                                                            "max_iter": 200}),
+    "er1000_3d": (lambda: (inputs.erdos_renyi(1000, 3000, 7), None), 3, {"omega": 1.6, "tol": 0.0, "max_iter": 30}),
+    "tree700_nograph": (lambda: (inputs.random_tree(700, 4), None), 2, {"omega": 1.7, "tol": 0.0, "max_iter": 25,
+                                                                       "use_graph": False, "check_every": 3}),
+    "ragged_129": (lambda: (inputs.erdos_renyi(129, 400, 5), None), 2, {"omega": 1.5, "tol": 0.0, "max_iter": 30}),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fused_safeguard_matches_separate(name):
+    from paper_1711_01228_amd import binding as b
+
+    make, dim, kw = CASES[name]
+    g, X0 = make()
+    if X0 is None or dim != 2:
+        X0 = inputs.uniform_positions(g.n, dim, seed=31, hi=float(np.sqrt(g.n)))
+    print("case", name, flush=True)
+    with b.Plan(g, dim) as plan:
+        Xa, ta, Xb, tb = _both(plan, X0, **kw)
+    _check(Xa, ta, Xb, tb)
+    if name == "grid16_w4":
+        assert ta["rejected"] >= 5  # the force at X^H ran again (the oracle rejects 14 of 40)
+
+
+def test_fused_schedule_with_unit_factors_and_vertex_factors():
+    import torch
+
+    from paper_1711_01228_amd import binding as b
+
+    g, X0 = inputs.grid16(4)
+    K = 30
+    sched = np.where(np.arange(K) % 3 == 0, 1.0, 1.8)  # every third iteration does not extrapolate
+    print("case schedule", flush=True)
+    with b.Plan(g, 2) as plan:
+        Xa, ta, Xb, tb = _both(plan, X0, strategy="schedule", omega_schedule=sched, tol=0.0, max_iter=K)
+        _check(Xa, ta, Xb, tb)
+        assert np.all(ta["trace"][::3, 1] == -1.0)  # no safeguard on unit factors
+        wv = torch.tensor(np.random.default_rng(3).uniform(1.0, 2.0, g.n), dtype=torch.float32, device="cuda")
+        Xa, ta, Xb, tb = _both(plan, X0, omega_vertex=wv, tol=0.0, max_iter=K)
+        _check(Xa, ta, Xb, tb)
+
+
+def test_fused_on_edge_length_plan():
+    from paper_1711_01228_amd import binding as b
+
+    g = inputs.largest_component(inputs.erdos_renyi(400, 1200, 13))
+    ln = (1.0 + np.random.default_rng(14).uniform(-0.3, 0.3, g.num_edges)).astype(np.float32)
+    gw = inputs.to_csr(g.n, g.edges(), ln)
+    X0 = inputs.uniform_positions(g.n, 2, 15, hi=8.0)
+    print("case weighted", flush=True)
+    with b.Plan(gw, 2) as plan:
+        Xa, ta, Xb, tb = _both(plan, X0, omega=1.6, tol=0.0, max_iter=30)
+    _check(Xa, ta, Xb, tb)
+
+
+def test_fused_profile_slot():
+    from paper_1711_01228_amd import binding as b
+
+    g, X0 = inputs.grid16(0)
+    with b.Plan(g, 2) as plan:
+        ms = plan.profile(dev(X0), omega=1.5, reps=2)
+    assert ms["force_safeguard"] > 0.0 and ms["force"] > 0.0
