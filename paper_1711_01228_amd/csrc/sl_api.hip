@@ -295,7 +295,7 @@ sl_status join_to(sl_plan* p, hipStream_t user) {
 // Weighted graphs: shortest paths on the device from the plan's CSR copy.
 sl_status build_weighted(sl_plan* p) {
   HIP_TRY(hipMemsetAsync(p->df, 0, sizeof(float) * (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
-  HIP_TRY(launch_wsssp(p->g_row_ptr, p->g_col_idx, p->g_len, p->n, p->sp.ng, p->df, p->pred, p->ps),
+  HIP_TRY(launch_wsssp(p->g_erow, p->g_col_idx, p->g_len, p->nnz, p->n, p->sp.ng, p->df, p->pred, p->ps),
           "shortest-path kernel");
   HIP_TRY(launch_wsym(p->df, p->n_pad, p->sp.ng, p->ps), "symmetrize kernel");
   HIP_TRY(launch_weights(nullptr, p->df, p->W, p->sp, p->n, p->ps), "weights kernel");
@@ -1082,6 +1082,9 @@ LoopParams unroll_params(const sl_plan* p, double omega, int safeguard) {
   lp.omega_p = omega - 1.0;
   lp.tol = -1.0;  // an unrolled run takes every one of its iterations
   lp.safeguard = safeguard;
+  // the safeguard rides on the next force pass; a run (or a recomputed
+  // segment) starts with one plain force pass
+  lp.fuse = (safeguard && omega != 1.0 && p->n > 1) ? 1 : 0;
   return lp;
 }
 
@@ -1154,6 +1157,7 @@ sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt
   if ((s = set_state(p, p->st, 0, K)) != SL_OK) return s;
   HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
   if (K > 0) HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->ckpt, p->ps), "checkpoint kernel");
+  if (lp.fuse && K > 0 && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^0
   for (int k = 0; k < K && p->n > 1; ++k) {
     if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
     if ((k + 1) % c == 0 && k + 1 < K)
@@ -1243,6 +1247,7 @@ sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float*
       HIP_TRY(hipMemcpyAsync(p->Xb, p->segX, sizeof(float) * p->stride, hipMemcpyDeviceToDevice, p->ps),
               "checkpoint copy");
       if ((s = set_state(p, p->st, k0, K)) != SL_OK) return s;
+      if (lp.fuse && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^{k0}
       for (int q = 1; q < k1 - k0; ++q) {
         if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
         HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->segX + (size_t)q * p->stride, p->ps), "save kernel");

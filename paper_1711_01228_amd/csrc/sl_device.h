@@ -18,6 +18,22 @@ __device__ __forceinline__ uint32_t chunk_word(const uint4& q, int k) {
   return (k < 4) ? q.x : (k < 8) ? q.y : (k < 12) ? q.z : q.w;
 }
 
+// sum over s = 0, 1, ..., count - 1 of a[s * stride], added in that order, with
+// eight loads in flight (the partial sums of one vertex over column slices)
+__device__ __forceinline__ double sum_strided(const double* __restrict__ a, int count, size_t stride) {
+  double t = 0.0;
+  int s = 0;
+  for (; s + 8 <= count; s += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = a[(size_t)(s + q) * stride];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += v[q];
+  }
+  for (; s < count; ++s) t += a[(size_t)s * stride];
+  return t;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);

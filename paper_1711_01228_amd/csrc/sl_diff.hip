@@ -50,8 +50,7 @@ __global__ __launch_bounds__(256) void k_stress_grad_out(const double* __restric
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   for (int c = 0; c < dim; ++c) {
-    double f = 0.0;
-    for (int s = 0; s < slices; ++s) f += fpart[((size_t)s * dim + c) * n_pad + i];
+    const double f = sum_strided(fpart + (size_t)c * n_pad + i, slices, (size_t)dim * n_pad);
     G[(size_t)i * dim + c] = (float)(-2.0 * f);
   }
 }
@@ -78,8 +77,7 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ gb,
   if (Wi > 0.0) {
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      double f = 0.0;
-      for (int s = 0; s < slices; ++s) f += fpart[((size_t)s * DIM + c) * n_pad + i];
+      const double f = sum_strided(fpart + (size_t)c * n_pad + i, slices, (size_t)DIM * n_pad);
       const double gc = a * gb[(size_t)c * n_pad + i] / Wi;
       g[c] = (float)gc;
       wb -= gc * f / Wi;
@@ -199,9 +197,7 @@ __global__ __launch_bounds__(256) void k_adj_update(double* __restrict__ gb, con
   if (i >= n_pad) return;
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    double x = 0.0;
-    for (int s = 0; s < slices; ++s) x += apart[((size_t)s * DIM + c) * n_pad + i];
-    gb[(size_t)c * n_pad + i] += x;
+    gb[(size_t)c * n_pad + i] += sum_strided(apart + (size_t)c * n_pad + i, slices, (size_t)DIM * n_pad);
   }
 }
 

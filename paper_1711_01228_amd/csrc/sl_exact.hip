@@ -115,9 +115,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CgVectors v, const double* __re
     double pv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-      double r = 0.0;
-      if (!held)
-        for (int s = 0; s < slices; ++s) r += fpart[((size_t)s * DIM + c) * n_pad + i];
+      const double r = held ? 0.0 : sum_strided(fpart + (size_t)c * n_pad + i, slices, (size_t)DIM * n_pad);
       const double z = Wi > 0.0 ? r / Wi : 0.0;
       const size_t o = (size_t)c * n_pad + i;
       v.y[o] = (double)xv[c];
@@ -239,9 +237,7 @@ __global__ __launch_bounds__(256) void k_cg_update(CgVectors v, const double* __
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const size_t o = (size_t)c * n_pad + i;
-      double q = 0.0;
-      if (!held)
-        for (int s = 0; s < slices; ++s) q += qpart[((size_t)s * DIM + c) * n_pad + i];
+      const double q = held ? 0.0 : sum_strided(qpart + (size_t)c * n_pad + i, slices, (size_t)DIM * n_pad);
       v.y[o] += alpha[c] * pv[c];
       const double r = v.r[o] - alpha[c] * q;
       const double z = Wi > 0.0 ? r / Wi : 0.0;

@@ -150,8 +150,9 @@ hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t
 hipError_t launch_weights(const uint8_t* d, const float* df, double* W, const Split& sp, int n, hipStream_t s);
 // Weighted graphs: FP32 shortest-path distances (tile-major, 0 = no path) and
 // trees (pred[s][v], row-major int32), then the lower triangle := the upper.
-hipError_t launch_wsssp(const int64_t* row_ptr, const int32_t* col_idx, const float* len, int n, int ng, float* df,
-                        int32_t* pred, hipStream_t s);
+// erow: the row of every CSR entry.
+hipError_t launch_wsssp(const int32_t* erow, const int32_t* col_idx, const float* len, int64_t nnz, int n, int ng,
+                        float* df, int32_t* pred, hipStream_t s);
 hipError_t launch_wsym(float* df, int n_pad, int ng, hipStream_t s);
 // Reverse mode (sl_diff.hip).
 hipError_t launch_grad_in(const float* G, double* gb, int n, int n_pad, int dim, hipStream_t s);
@@ -203,7 +204,7 @@ hipError_t launch_apply_enum(const float* Eb, float* Xb, size_t stride, const De
                              hipStream_t s);
 hipError_t launch_record(const float* Xb, size_t stride, const DevState* st, float* xtrace, int n, int dim,
                          hipStream_t s);
-hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevState* st, hipStream_t s);
+hipError_t launch_stress_sum(double* spart, int slices, int n_pad, DevState* st, hipStream_t s);
 hipError_t launch_gather_rows(const uint8_t* d, const float* df, const int32_t* rows, int nrows, int n, int ng,
                               float* out, hipStream_t s);
 

@@ -150,11 +150,8 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
     const double wpi = p.omega_vertex ? (double)p.omega_vertex[i] - 1.0 : wp;
     double F[3] = {0.0, 0.0, 0.0};
     if (!p.exact_y) {
-      for (int s = 0; s < p.slices; ++s) {
-        const double* fp = fpart + (size_t)s * DIM * p.n_pad + i;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) F[c] += fp[(size_t)c * p.n_pad];
-      }
+      for (int c = 0; c < DIM; ++c) F[c] = sum_strided(fpart + (size_t)c * p.n_pad + i, p.slices, (size_t)DIM * p.n_pad);
     }
     const V x = X[i];
     const double Wi = W[i];
@@ -194,7 +191,7 @@ __global__ __launch_bounds__(256) void k_update(LoopParams p, const double* __re
       }
     }
     if constexpr (STRESS) {
-      for (int s = 0; s < p.slices; ++s) v[5] += spart[(size_t)s * p.n_pad + i];
+      v[5] += sum_strided(spart + i, p.slices, (size_t)p.n_pad);
     }
     v[6] = bad ? 1.0 : 0.0;
   }
@@ -686,12 +683,19 @@ __global__ __launch_bounds__(256) void k_record(const float* __restrict__ Xb, si
 }
 
 // f = (1/2) sum_i s_i over the stress partials of one force pass.
-__global__ __launch_bounds__(256) void k_stress_sum(const double* __restrict__ spart, int slices, int n_pad,
+// f = half the sum of the stress terms: first each vertex's sum over the slices
+// (into slice 0, which only that vertex's thread reads), then one block.
+__global__ __launch_bounds__(256) void k_stress_rows(double* __restrict__ spart, int slices, int n_pad) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n_pad) spart[i] = sum_strided(spart + i, slices, (size_t)n_pad);
+}
+
+__global__ __launch_bounds__(256) void k_stress_sum(const double* __restrict__ spart, int n_pad,
                                                     DevState* __restrict__ st) {
   __shared__ double sh[1][256];
-  double v[1] = {0.0};
-  const size_t total = (size_t)slices * n_pad;
-  for (size_t q = threadIdx.x; q < total; q += 256) v[0] += spart[q];
+  const int per = (n_pad + 255) / 256;
+  double v[1] = {threadIdx.x * per < n_pad ? sum_strided(spart + threadIdx.x * per,
+                                                         min(per, n_pad - (int)threadIdx.x * per), 1) : 0.0};
   block_sum<1>(v, sh);
   if (threadIdx.x == 0) st->stress = 0.5 * v[0];
 }
@@ -1043,8 +1047,9 @@ hipError_t launch_record(const float* Xb, size_t stride, const DevState* st, flo
   return hipGetLastError();
 }
 
-hipError_t launch_stress_sum(const double* spart, int slices, int n_pad, DevState* st, hipStream_t s) {
-  k_stress_sum<<<1, 256, 0, s>>>(spart, slices, n_pad, st);
+hipError_t launch_stress_sum(double* spart, int slices, int n_pad, DevState* st, hipStream_t s) {
+  k_stress_rows<<<blocks_for(n_pad), 256, 0, s>>>(spart, slices, n_pad);
+  k_stress_sum<<<1, 256, 0, s>>>(spart, n_pad, st);
   return hipGetLastError();
 }
 
