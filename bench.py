@@ -88,9 +88,11 @@ def cpu_baseline(g, X0, target_s=12.0):
     del Drows
     pairs = R * (n - 1)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+    rate = pairs / dt
+    return {"value": rate, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
             "sample": "FP64 Jacobi step (eq. 5 row solves) for %d random rows x all %d columns of the same "
-                      "BA graph and start, %.1f s; distance rows (BFS) not timed" % (R, n, dt)}
+                      "BA graph and start, %.1f s; distance rows (BFS) not timed" % (R, n, dt),
+            "seconds_per_jacobi_step": float(n) * (n - 1) / rate}
 
 
 def bench_batch(omega, count=2048):
@@ -408,6 +410,11 @@ def main():
 
     if not args.quick and not args.no_cpu:
         cb = cpu_baseline(g, X0)
+        if "time_to_converge" in out:  # omega = 1 takes one Jacobi step per iteration and no safeguard
+            it1 = out["time_to_converge"]["omega=1"]["iterations"]
+            cb["time_to_converge_omega1_extrapolated_s"] = round(cb["seconds_per_jacobi_step"] * it1, 2)
+            cb["extrapolation"] = ("the oracle's s per Jacobi step x the GPU's %d iterations to res <= 1e-3 at "
+                                   "omega = 1 (extrapolated, not run)" % it1)
         out["cpu_baseline"] = cb
         log("cpu baseline:", cb)
     print(json.dumps(out), flush=True)
