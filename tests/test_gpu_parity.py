@@ -235,6 +235,35 @@ def test_ba65536_one_step_sampled_rows(sl, dim):
     assert err <= 1e-5 * diam(X0), err
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ba65536_fused_iterations_sampled_rows(sl, dim):
+    """The launch configuration the benchmark times (n = 65,536, omega = 1.5 with
+    the safeguard): iteration 3 takes the force of X^2 from the fused force +
+    safeguard pass of iteration 2 (or from the force pass after a rejection).
+    Sampled rows of X^3 against the oracle's step from the GPU's own X^2 (all
+    rows), with the decision the GPU recorded."""
+    g, X0 = inputs.ba65536(dim)
+    print("case ba65536 fused dim", dim, flush=True)
+    rng = np.random.default_rng(10 + dim)
+    rows = np.unique(np.concatenate([rng.choice(g.n, 48, replace=False), [0, 1, 63, 64, g.n - 1]]))
+    Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
+    omega = 1.5
+    with sl.Plan(g, dim) as plan:
+        X2 = dev(X0)
+        plan.run(X2, omega=omega, tol=0.0, max_iter=2)
+        X3 = dev(X0)
+        info = plan.run(X3, omega=omega, tol=0.0, max_iter=3, trace=True)
+    assert info["iterations"] == 3
+    X2 = X2.cpu().numpy().astype(np.float64)
+    XH = oracle.h_jacobi_rows(Drows, rows, X2)
+    took = info["trace"][2, 1]
+    expect = XH + (omega - 1.0) * (XH - X2[rows]) if took == 1.0 else XH
+    got = X3.cpu().numpy().astype(np.float64)[rows]
+    err = np.abs(got - expect).max()
+    print("decisions", info["trace"][:, 1], "err", err, flush=True)
+    assert err <= 1e-5 * diam(X2), err
+
+
 # ---------------------------------------------------------------------------
 # edge cases and run-to-run behaviour
 # ---------------------------------------------------------------------------
