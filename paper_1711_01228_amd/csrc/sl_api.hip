@@ -166,8 +166,9 @@ struct sl_plan {
   float* segX = nullptr;
   int seg_cap = 0;              // iterates
   double* gb = nullptr;         // 3 x n_pad adjoint of the iterate
-  float* gvec = nullptr;        // stride floats
-  float* wbar = nullptr;        // n_pad
+  float* gvec = nullptr;        // per iteration of a segment: stride floats each
+  float* wbar = nullptr;        // per iteration of a segment: n_pad floats each
+  size_t gvec_cap = 0, wbar_cap = 0;  // floats allocated
   float* Dbar = nullptr;        // n_pad^2 (edge-length plans)
   float* Sbuf = nullptr;        // n x n (edge-length plans)
   double* Gedge = nullptr;      // nnz
@@ -1205,10 +1206,12 @@ sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float*
   const size_t col = (size_t)3 * p->n_pad;
   size_t cap = p->gb ? col : 0;
   if ((s = grow((void**)&p->gb, &cap, col, sizeof(double), "adjoint buffers")) != SL_OK) return s;
-  cap = p->gvec ? p->stride : 0;
-  if ((s = grow((void**)&p->gvec, &cap, p->stride, sizeof(float), "adjoint buffers")) != SL_OK) return s;
-  cap = p->wbar ? (size_t)p->n_pad : 0;
-  if ((s = grow((void**)&p->wbar, &cap, p->n_pad, sizeof(float), "adjoint buffers")) != SL_OK) return s;
+  if ((s = grow((void**)&p->gvec, &p->gvec_cap, (size_t)std::max(c, 1) * p->stride, sizeof(float),
+                "adjoint buffers")) != SL_OK)
+    return s;
+  if ((s = grow((void**)&p->wbar, &p->wbar_cap, (size_t)std::max(c, 1) * p->n_pad, sizeof(float),
+                "adjoint buffers")) != SL_OK)
+    return s;
   size_t scap = (size_t)p->seg_cap * p->stride;
   if ((s = grow((void**)&p->segX, &scap, (size_t)std::max(c, 1) * p->stride, sizeof(float), "segment buffer")) != SL_OK)
     return s;
@@ -1259,10 +1262,16 @@ sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float*
                            p->ps),
               "force kernel");
       const double a = tr[(size_t)k * SL_TRACE_COLS + 1] == 1.0 ? p->tape_omega : 1.0;
-      HIP_TRY(launch_adjoint_step(p->dim, p->d, p->df, Xk, p->fpart, p->W, a, p->gb, p->gvec, p->wbar,
-                                  glen ? p->Dbar : nullptr, p->fpart, p->sp, p->n_pad, p->ps),
+      HIP_TRY(launch_adjoint_step(p->dim, p->d, p->df, Xk, p->fpart, p->W, a, p->gb,
+                                  p->gvec + (size_t)(k - k0) * p->stride, p->wbar + (size_t)(k - k0) * p->n_pad,
+                                  p->fpart, p->sp, p->n_pad, p->ps),
               "adjoint kernels");
     }
+    // dL/dd of the segment's iterations, added once per pair
+    if (glen)
+      HIP_TRY(launch_dbar_segment(p->dim, p->d, p->df, p->segX, p->stride, p->gvec, p->wbar, k1 - k0, p->Dbar, p->sp,
+                                  p->n_pad, p->ps),
+              "distance adjoint kernel");
   }
   HIP_TRY(launch_grad_out(p->gb, gX0, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
   if (glen) {

@@ -91,12 +91,10 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ gb,
 
 // Xbar_i = sum_j J_ij (g_i - g_j) over all ordered pairs, in the tiling of the
 // force pass (one wave per row block and column slice, x_j and g_j through the
-// scalar cache), and, with DBAR, dL/dd_ij of row i added into Dbar (FP32,
-// the tile-major layout of the distances: each lane rewrites its own chunk).
-template <int DIM, bool FD, bool DBAR>
+// scalar cache).  dL/dd is added per segment of iterations by k_dbar_seg.
+template <int DIM, bool FD>
 __global__ __launch_bounds__(256) void k_adjoint(const uint8_t* __restrict__ d, const float* __restrict__ df,
                                                  const float* __restrict__ Xk, const float* __restrict__ gvec,
-                                                 const float* __restrict__ wbar, float* __restrict__ Dbar,
                                                  double* __restrict__ apart, int nrb, int ng, int gps, int n_pad) {
   using V = typename VecT<DIM>::T;
   using C = typename DChunkT<FD>::T;
@@ -115,14 +113,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const uint8_t* __restrict__ d, 
   const V* __restrict__ Gv = reinterpret_cast<const V*>(gvec);
   const int i = rb * kRowBlock + lane;
   const V xi = X[i], gi = Gv[i];
-  const float wbi = wbar[i];
   double A0 = 0.0, A1 = 0.0, A2 = 0.0;
   for (int g = g0; g < g1; ++g) {
     const C q = load_chunk<FD>(d, df, rb, ng, g, lane);
     const V* __restrict__ xj = X + (size_t)g * kColGroup;
     const V* __restrict__ gj = Gv + (size_t)g * kColGroup;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-    float h[kColGroup];
 #pragma unroll
     for (int k = 0; k < kColGroup; ++k) {
       float inv, w;
@@ -142,15 +138,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const uint8_t* __restrict__ d, 
       r2 = fmaf(dy, dy, r2);
       float de = dx * ex;
       de = fmaf(dy, ey, de);
-      float gd = gi.x * dx;
-      gd = fmaf(gi.y, dy, gd);
       float dz = 0.f, ez = 0.f;
       if constexpr (DIM == 3) {
         dz = xi.z - p.z;
         ez = gi.z - pg.z;
         r2 = fmaf(dz, dz, r2);
         de = fmaf(dz, ez, de);
-        gd = fmaf(gi.z, dz, gd);
       }
       const float rinv = __builtin_amdgcn_rsqf(r2);
       const float ir = inv * rinv;
@@ -165,28 +158,93 @@ __global__ __launch_bounds__(256) void k_adjoint(const uint8_t* __restrict__ d, 
         a2 = fmaf(c, ez, a2);
         a2 = fmaf(-t, dz, a2);
       }
-      if constexpr (DBAR) h[k] = w * fmaf(2.f, inv, -rinv) * gd - 2.f * w * inv * wbi;
     }
     A0 += (double)a0;
     A1 += (double)a1;
     if constexpr (DIM == 3) A2 += (double)a2;
-    if constexpr (DBAR) {
-      float4* p = reinterpret_cast<float4*>(Dbar + ((size_t)rb * ng + g) * kTileBytes) + lane * 4;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float4 o = p[v];
-        o.x += h[4 * v];
-        o.y += h[4 * v + 1];
-        o.z += h[4 * v + 2];
-        o.w += h[4 * v + 3];
-        p[v] = o;
-      }
-    }
   }
   double* ap = apart + (size_t)slice * DIM * n_pad + i;
   ap[0] = A0;
   ap[n_pad] = A1;
   if constexpr (DIM == 3) ap[2 * (size_t)n_pad] = A2;
+}
+
+// dL/dd_ij of a segment of nk iterations, added into Dbar (FP32, the tile-major
+// layout of the distances: each lane rewrites its own chunk once per segment).
+// Iteration m of the segment contributes, for every ordered pair,
+//   w (2/d - 1/r) (g_i . (x_i - x_j)) - 2 w (1/d) Wbar_i
+// with x = X^m (segX + m stride), g and Wbar the adjoint vectors of that
+// iteration (gseg + m stride, wseg + m n_pad); the terms of a pair are summed
+// newest first in registers.
+template <int DIM, bool FD>
+__global__ __launch_bounds__(256) void k_dbar_seg(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                                  const float* __restrict__ segX, size_t stride,
+                                                  const float* __restrict__ gseg, const float* __restrict__ wseg,
+                                                  int nk, float* __restrict__ Dbar, int nrb, int ng, int gps,
+                                                  int n_pad) {
+  using V = typename VecT<DIM>::T;
+  using C = typename DChunkT<FD>::T;
+  __shared__ float2 lut[256];
+  if constexpr (!FD) {
+    fill_weight_table<false>(lut);
+    __syncthreads();
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int rb = blockIdx.x * 4 + wave;
+  if (rb >= nrb) return;
+  const int g0 = blockIdx.y * gps;
+  const int g1 = min(g0 + gps, ng);
+  const int i = rb * kRowBlock + lane;
+  for (int g = g0; g < g1; ++g) {
+    const C q = load_chunk<FD>(d, df, rb, ng, g, lane);
+    float inv[kColGroup], w[kColGroup], h[kColGroup];
+#pragma unroll
+    for (int k = 0; k < kColGroup; ++k) {
+      if constexpr (FD) {
+        const float dv = fchunk_at(q, k);
+        inv[k] = dv > 0.f ? __builtin_amdgcn_rcpf(dv) : 0.f;
+        w[k] = inv[k] * inv[k];
+      } else {
+        const float2 wt = lut[byte_of(chunk_word(q, k), k & 3)];
+        inv[k] = wt.x;
+        w[k] = wt.y;
+      }
+      h[k] = 0.f;
+    }
+    for (int m = nk - 1; m >= 0; --m) {
+      const V* __restrict__ X = reinterpret_cast<const V*>(segX + (size_t)m * stride);
+      const V xi = X[i];
+      const V gi = reinterpret_cast<const V*>(gseg + (size_t)m * stride)[i];
+      const float wbi = wseg[(size_t)m * n_pad + i];
+      const V* __restrict__ xj = X + (size_t)g * kColGroup;
+#pragma unroll
+      for (int k = 0; k < kColGroup; ++k) {
+        const V p = xj[k];
+        const float dx = xi.x - p.x, dy = xi.y - p.y;
+        float r2 = fmaf(dx, dx, kTiny);
+        r2 = fmaf(dy, dy, r2);
+        float gd = gi.x * dx;
+        gd = fmaf(gi.y, dy, gd);
+        if constexpr (DIM == 3) {
+          const float dz = xi.z - p.z;
+          r2 = fmaf(dz, dz, r2);
+          gd = fmaf(gi.z, dz, gd);
+        }
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        h[k] += w[k] * fmaf(2.f, inv[k], -rinv) * gd - 2.f * w[k] * inv[k] * wbi;
+      }
+    }
+    float4* p = reinterpret_cast<float4*>(Dbar + ((size_t)rb * ng + g) * kTileBytes) + lane * 4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float4 o = p[v];
+      o.x += h[4 * v];
+      o.y += h[4 * v + 1];
+      o.z += h[4 * v + 2];
+      o.w += h[4 * v + 3];
+      p[v] = o;
+    }
+  }
 }
 
 // Gbar += Xbar (the slices of the adjoint pass).
@@ -352,30 +410,38 @@ hipError_t launch_save(const float* Xb, size_t stride, const DevState* st, float
 }
 
 hipError_t launch_adjoint_step(int dim, const uint8_t* d, const float* df, const float* Xk, const double* fpart,
-                               const double* W, double a, double* gb, float* gvec, float* wbar, float* Dbar,
-                               double* apart, const Split& sp, int n_pad, hipStream_t s) {
+                               const double* W, double a, double* gb, float* gvec, float* wbar, double* apart,
+                               const Split& sp, int n_pad, hipStream_t s) {
   const unsigned nb = blocks_for(n_pad);
   const dim3 grid(sp.blocks_x, sp.slices);
   const int gps = sp.groups_per_slice;
+  // the adjoint pass overwrites fpart (the force sums were read by k_adj_prep)
   if (dim == 2) {
     k_adj_prep<2><<<nb, 256, 0, s>>>(gb, fpart, sp.slices, W, a, n_pad, gvec, wbar);
-    // the adjoint pass overwrites fpart (the force sums were read above)
-    if (df) {
-      if (Dbar) k_adjoint<2, true, true><<<grid, 256, 0, s>>>(d, df, Xk, gvec, wbar, Dbar, apart, sp.nrb, sp.ng, gps, n_pad);
-      else k_adjoint<2, true, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, wbar, Dbar, apart, sp.nrb, sp.ng, gps, n_pad);
-    } else {
-      k_adjoint<2, false, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, wbar, Dbar, apart, sp.nrb, sp.ng, gps, n_pad);
-    }
+    if (df) k_adjoint<2, true><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
+    else k_adjoint<2, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
     k_adj_update<2><<<nb, 256, 0, s>>>(gb, apart, sp.slices, n_pad);
   } else {
     k_adj_prep<3><<<nb, 256, 0, s>>>(gb, fpart, sp.slices, W, a, n_pad, gvec, wbar);
-    if (df) {
-      if (Dbar) k_adjoint<3, true, true><<<grid, 256, 0, s>>>(d, df, Xk, gvec, wbar, Dbar, apart, sp.nrb, sp.ng, gps, n_pad);
-      else k_adjoint<3, true, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, wbar, Dbar, apart, sp.nrb, sp.ng, gps, n_pad);
-    } else {
-      k_adjoint<3, false, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, wbar, Dbar, apart, sp.nrb, sp.ng, gps, n_pad);
-    }
+    if (df) k_adjoint<3, true><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
+    else k_adjoint<3, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
     k_adj_update<3><<<nb, 256, 0, s>>>(gb, apart, sp.slices, n_pad);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dbar_segment(int dim, const uint8_t* d, const float* df, const float* segX, size_t stride,
+                               const float* gseg, const float* wseg, int nk, float* Dbar, const Split& sp, int n_pad,
+                               hipStream_t s) {
+  if (nk <= 0) return hipSuccess;
+  const dim3 grid(sp.blocks_x, sp.slices);
+  const int gps = sp.groups_per_slice;
+  if (dim == 2) {
+    if (df) k_dbar_seg<2, true><<<grid, 256, 0, s>>>(d, df, segX, stride, gseg, wseg, nk, Dbar, sp.nrb, sp.ng, gps, n_pad);
+    else k_dbar_seg<2, false><<<grid, 256, 0, s>>>(d, df, segX, stride, gseg, wseg, nk, Dbar, sp.nrb, sp.ng, gps, n_pad);
+  } else {
+    if (df) k_dbar_seg<3, true><<<grid, 256, 0, s>>>(d, df, segX, stride, gseg, wseg, nk, Dbar, sp.nrb, sp.ng, gps, n_pad);
+    else k_dbar_seg<3, false><<<grid, 256, 0, s>>>(d, df, segX, stride, gseg, wseg, nk, Dbar, sp.nrb, sp.ng, gps, n_pad);
   }
   return hipGetLastError();
 }
