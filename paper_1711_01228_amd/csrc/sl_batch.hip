@@ -3,10 +3,13 @@
 // ordered largest first, keeps its iterates, weights and force partials in
 // LDS, and runs Algorithm 2 for that graph to its own termination test: the
 // same arithmetic as the single-graph kernels (force pass, Jacobi update and
-// extrapolation of eq. 11, safeguard of Alg. 2 lines 6-8, residual test), with
-// workgroup barriers in place of kernel boundaries.  Distances come from a
+// extrapolation of eq. 11, safeguard of Alg. 2 lines 6-8 summed inside the pass
+// that takes the next force at X~, residual test), with workgroup barriers in
+// place of kernel boundaries.  Distances come from a
 // per-graph breadth-first search run the same way.
 #include "sl_device.h"
+
+#include <type_traits>
 
 namespace sl {
 
@@ -142,12 +145,12 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
   __shared__ float2 lut[256];
   __shared__ double red[8][NW];
   __shared__ double red_tot[8];
-  __shared__ float lut1[256];
+  __shared__ float lut2[256];  // -2/d
   __shared__ int sh_q;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   fill_weight_table<false>(lut);
-  for (int b = tid; b < 256; b += T) lut1[b] = b ? 1.0f / (float)b : 0.f;
+  for (int b = tid; b < 256; b += T) lut2[b] = b ? -2.f * (1.0f / (float)b) : 0.f;
   const bool sg = p.safeguard && p.omega_p != 0.0;
   for (;;) {
     __syncthreads();
@@ -178,9 +181,10 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
     __syncthreads();
     int cur = 0, it = 0, rejected = 0, converged = n <= 1 ? 1 : 0, status = 0;
     double resid = 0.0;
+    bool have_force = false;  // Fp holds the force at X^k (left by the last iteration's fused pass)
     while (it < p.max_iter && !converged && n > 1) {
       // ---- force pass at X^k: F_i = sum_j w (d - r) u_ij
-      for (int u = wave; u < units; u += NW) {
+      for (int u = have_force ? units : wave; u < units; u += NW) {
         const int rb = u % nrb, s = u / nrb;
         const int g0 = s * gps, g1 = min(g0 + gps, ng);
         const int i = rb * kRowBlock + lane;
@@ -255,45 +259,82 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
         if (bad) v[6] += 1.0;
       }
       block_sum_waves<8, NW>(v, red, red_tot);
-      // ---- safeguard: f(X~) - f(X^H) over the upper triangle
+      // ---- the force at X~ (the next iteration's, if X~ is kept) with the
+      // safeguard f(X~) - f(X^H) summed over the upper triangle in the same pass.
+      // The force terms are those of the pass above, in the same order.  For
+      // j > i, with t = x~_i - x~_j and e = e_i - e_j (e = x~ - x^H):
+      //   m = r~^2 - r^H^2 = e.(2t - e), r^H = sqrt|r~^2 - m|,
+      //   term = m (1/d^2 - (2/d) / (r~ + r^H)).
       double df = 0.0;
       if (sg) {
+        __syncthreads();  // the update has read every force partial
         double acc = 0.0;
         for (int u = wave; u < units; u += NW) {
           const int rb = u % nrb, s = u / nrb;
           const int gdiag = rb * (kRowBlock / kColGroup), gfree = gdiag + kRowBlock / kColGroup;
-          const int g0 = max(s * gps, gdiag), g1 = min(s * gps + gps, ng);
+          const int g0 = s * gps, g1 = min(g0 + gps, ng);
           const int i = rb * kRowBlock + lane;
-          const V hi = xs[h][i], ei = es[i];
+          const V xi = xs[t][i], ei = es[i];
           const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(dg + (size_t)rb * ng * kTileBytes) + lane;
-          for (int g = g0; g < g1; ++g) {
-            const uint4 qd = tile[(size_t)g * 64];
-            const int jrel = (g < gfree) ? i - g * kColGroup : -1;  // mask k <= jrel in the diagonal block
-            float a = 0.f;
+          double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+          // MODE 0: left of the diagonal block (force only); 1: the diagonal
+          // block (j <= i masked); 2: right of it
+          auto run = [&](auto mode_tag, int ga, int gb) {
+            constexpr int MODE = decltype(mode_tag)::value;
+            for (int g = ga; g < gb; ++g) {
+              const uint4 qd = tile[(size_t)g * 64];
+              const int jrel = i - g * kColGroup;
+              float a0 = 0.f, a1 = 0.f, a2 = 0.f, a = 0.f;
 #pragma unroll
-            for (int k = 0; k < kColGroup; ++k) {
-              const float inv = lut1[byte_of(chunk_word(qd, k), k & 3)];
-              const V ph = xs[h][g * kColGroup + k], pe = es[g * kColGroup + k];
-              const float hx = hi.x - ph.x, hy = hi.y - ph.y;
-              const float ex = ei.x - pe.x, ey = ei.y - pe.y;
-              float rh2 = fmaf(hx, hx, kTiny);
-              rh2 = fmaf(hy, hy, rh2);
-              float m = ex * fmaf(2.f, hx, ex);
-              m = fmaf(ey, fmaf(2.f, hy, ey), m);
-              if constexpr (DIM == 3) {
-                const float hz = hi.z - ph.z, ez = ei.z - pe.z;
-                rh2 = fmaf(hz, hz, rh2);
-                m = fmaf(ez, fmaf(2.f, hz, ez), m);
+              for (int k = 0; k < kColGroup; ++k) {
+                const uint32_t b = byte_of(chunk_word(qd, k), k & 3);
+                const float2 wt = lut[b];
+                const V pj = xs[t][g * kColGroup + k];
+                const float dx = xi.x - pj.x, dy = xi.y - pj.y;
+                float r2 = fmaf(dx, dx, kTiny);
+                r2 = fmaf(dy, dy, r2);
+                float dz = 0.f;
+                if constexpr (DIM == 3) {
+                  dz = xi.z - pj.z;
+                  r2 = fmaf(dz, dz, r2);
+                }
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float c = fmaf(wt.x, rinv, -wt.y);
+                a0 = fmaf(c, dx, a0);
+                a1 = fmaf(c, dy, a1);
+                if constexpr (DIM == 3) a2 = fmaf(c, dz, a2);
+                if constexpr (MODE != 0) {
+                  const V pe = es[g * kColGroup + k];
+                  const float ex = ei.x - pe.x, ey = ei.y - pe.y;
+                  float m = ex * fmaf(2.f, dx, -ex);
+                  m = fmaf(ey, fmaf(2.f, dy, -ey), m);
+                  if constexpr (DIM == 3) {
+                    const float ez = ei.z - pe.z;
+                    m = fmaf(ez, fmaf(2.f, dz, -ez), m);
+                  }
+                  const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
+                  const float sum = fmaf(r2, rinv, rh);
+                  float term = m * fmaf(lut2[b], __builtin_amdgcn_rcpf(sum), wt.y);
+                  if constexpr (MODE == 1) {
+                    if (k <= jrel) term = 0.f;
+                  }
+                  a += term;
+                }
+                if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
               }
-              const float rt2 = fabsf(rh2 + m);
-              const float sum = fmaf(rh2, __builtin_amdgcn_rsqf(rh2), rt2 * __builtin_amdgcn_rsqf(rt2));
-              float mi = m * inv;
-              if (k <= jrel) mi = 0.f;
-              a = fmaf(mi, fmaf(-2.f, __builtin_amdgcn_rcpf(sum), inv), a);
-              if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+              F0 += (double)a0;
+              F1 += (double)a1;
+              if constexpr (DIM == 3) F2 += (double)a2;
+              if constexpr (MODE != 0) acc += (double)a;
             }
-            acc += (double)a;
-          }
+          };
+          run(std::integral_constant<int, 0>{}, g0, min(g1, gdiag));
+          run(std::integral_constant<int, 1>{}, max(g0, gdiag), min(g1, gfree));
+          run(std::integral_constant<int, 2>{}, max(g0, gfree), g1);
+          double* fp = Fp + ((size_t)s * n_pad + i) * DIM;
+          fp[0] = F0;
+          fp[1] = F1;
+          if constexpr (DIM == 3) fp[2] = F2;
         }
         double vv[1] = {acc};
         block_sum_waves<1, NW>(vv, red, red_tot);
@@ -307,11 +348,13 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
       const double mean2 = (v[2] * v[2] + v[3] * v[3] + (DIM == 3 ? v[4] * v[4] : 0.0)) / (double)n;
       const double den2 = v[1] - mean2;
       const double r = v[0] > 0.0 ? sqrt(v[0]) / sqrt(den2 > 0.0 ? den2 : 0.0) : 0.0;
+      have_force = false;
       if (p.omega_p == 0.0) {
         cur = h;
       } else if (p.safeguard) {
         const bool take = df <= 0.0;
         cur = take ? t : h;
+        have_force = take;  // the fused pass took the force at X~
         if (!take) ++rejected;
       } else {
         cur = t;
@@ -321,6 +364,7 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
       if (r <= p.tol) converged = 1;
       // every thread computed the same decision from the same block sums
       cur = __builtin_amdgcn_readfirstlane(cur);
+      have_force = __builtin_amdgcn_readfirstlane(have_force ? 1 : 0) != 0;
       converged = __builtin_amdgcn_readfirstlane(converged);
       rejected = __builtin_amdgcn_readfirstlane(rejected);
     }
