@@ -332,7 +332,12 @@ def main():
            "config": {"workload": "Barabasi-Albert n=%d m=3 (%d edges), %d-D, start U[0,1]^%d, omega=%.2f "
                                   "with safeguard, Jacobi ordering" % (n, g.num_edges, dim, dim, args.omega),
                       "n": n, "dim": dim, "omega": args.omega, "step": "one iteration of Algorithm 2"},
-           "plan_ms": plan_ms, "roofline": roofline}
+           "plan_ms": plan_ms,
+           # the all-pairs BFS (row A0) writes one distance byte per pair; W follows from it
+           "plan_apsp": {"kernels": "k_bfs_init/gather/update (2,048 sources per sweep) + k_weights",
+                         "bytes_written": float(n) * n, "GBps": round(float(n) * n / (plan_ms * 1e-3) / 1e9, 1),
+                         "frac_of_hbm_peak": round(float(n) * n / (plan_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)},
+           "roofline": roofline}
 
     # ---- time to converge: SOR-omega vs omega = 1 at equal final residual
     if not args.quick:

@@ -291,6 +291,10 @@ sl_status join_to(sl_plan* p, hipStream_t user) {
   return SL_OK;
 }
 
+// Level kBfsMaxLevel of the search only detects a distance beyond the 255 hops
+// a byte holds.
+constexpr int kBfsMaxLevel = 256;
+
 // Multi-source BFS, bfs_sources_per_sweep() sources per sweep, then W.
 // Distances above 255 hops are refused (SL_ERANGE).
 // Weighted graphs: shortest paths on the device from the plan's CSR copy.
@@ -336,7 +340,7 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     if (e == hipSuccess) e = hipMalloc(&vis, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&nx, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&acc, sizeof(uint64_t) * words);
-    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t) * (kBfsMaxLevel + 1));
     if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemcpyAsync(er, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
@@ -345,21 +349,27 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       return hip_fail(e, "distance buffers");
     }
     const int sweep = bfs_sources_per_sweep();
+    constexpr int kLevelsPerPoll = 16;  // levels queued between looks at the flags
     for (int base = 0; base < n && status == SL_OK && e == hipSuccess; base += sweep) {
       e = launch_bfs_init(fr, vis, acc, n, base, p->ps);
-      for (int level = 1; e == hipSuccess; ++level) {
-        const int write = level <= 255;
-        e = hipMemsetAsync(flag, 0, sizeof(int32_t), p->ps);
-        if (e == hipSuccess)
-          e = launch_bfs_level(er, ci, g->nnz, fr, acc, vis, nx, p->d, n, p->sp.ng, base, level, write, flag, p->ps);
-        if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, p->ps);
+      // flags[l] = 0 for every level, flags[0] != 0 (the sources)
+      if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int32_t) * (kBfsMaxLevel + 1), p->ps);
+      if (e == hipSuccess) e = hipMemsetAsync(flag, 1, sizeof(int32_t), p->ps);
+      for (int level = 1; e == hipSuccess;) {
+        const int last = std::min(level + kLevelsPerPoll - 1, kBfsMaxLevel);
+        for (; level <= last && e == hipSuccess; ++level) {
+          // level 256 writes nothing: it only tells whether a distance exceeds 255
+          e = launch_bfs_level(er, ci, g->nnz, fr, acc, vis, nx, p->d, n, p->sp.ng, base, level,
+                               level < kBfsMaxLevel ? 1 : 0, flag, p->ps);
+          std::swap(fr, nx);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag + last, sizeof(int32_t), hipMemcpyDeviceToHost, p->ps);
         if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
         if (e != hipSuccess || *hflag == 0) break;
-        if (!write) {
+        if (last == kBfsMaxLevel) {
           status = fail(SL_ERANGE, "a graph distance exceeds 255 hops (sources %d..%d)", base, base + sweep - 1);
           break;
         }
-        std::swap(fr, nx);
       }
     }
     cleanup();

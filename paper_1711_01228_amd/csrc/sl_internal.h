@@ -144,9 +144,11 @@ hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);
 int bfs_sources_per_sweep();  // sources searched together (bits per vertex)
 int bfs_words();              // 64-bit words per vertex in the BFS buffers
 hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s);
+// One BFS level (1 .. 256).  flags[0 .. 256]: flags[l] != 0 iff level l found a
+// new vertex (flags[0]: the sources); a level after an empty one does nothing.
 hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* frontier,
                             uint64_t* acc, uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base,
-                            int level, int write, int32_t* flag, hipStream_t s);
+                            int level, int write, int32_t* flags, hipStream_t s);
 hipError_t launch_weights(const uint8_t* d, const float* df, double* W, const Split& sp, int n, hipStream_t s);
 // Weighted graphs: FP32 shortest-path distances (tile-major, 0 = no path) and
 // trees (pred[s][v], row-major int32), then the lower triangle := the upper.

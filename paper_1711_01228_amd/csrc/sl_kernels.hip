@@ -727,14 +727,18 @@ __global__ __launch_bounds__(256) void k_pack_out(const float* __restrict__ Xb, 
 //                 OR-reduced over each run of equal v inside the wave (a
 //                 segmented OR over the CSR row; rows are contiguous) and
 //                 folded into acc[v] by one atomic OR per run and word
-//   k_bfs_update  one thread per vertex: the new bits acc[v] & ~visited[v]
+//   k_bfs_update  one thread per vertex and word: the new bits acc[v] & ~visited[v]
 //                 become the next frontier, and the level is written into
 //                 d(v, s) for every new source s.  Distances are symmetric, so
 //                 row v is written: 16 sources share one 16-byte lane chunk of
 //                 the tile layout, read-modify-written by the only thread that
-//                 owns row v.
+//                 owns row v and that word.  A wave takes one word of 64
+//                 consecutive vertices (its chunk writes are 1 KiB contiguous).
+// Both return at once when the previous level found no new vertex (flags[l]
+// is set by level l's update; flags[0] stands for the sources), so the host
+// can queue many levels and look at the flags once per batch of levels.
 // ---------------------------------------------------------------------------
-constexpr int kBfsWords = 8;
+constexpr int kBfsWords = 32;
 constexpr int kBfsSources = 64 * kBfsWords;
 
 __global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ frontier, uint64_t* __restrict__ visited,
@@ -754,7 +758,9 @@ __global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ frontie
 __global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ erow,
                                                     const int32_t* __restrict__ col_idx, int64_t nnz,
                                                     const uint64_t* __restrict__ frontier,
-                                                    unsigned long long* __restrict__ acc) {
+                                                    unsigned long long* __restrict__ acc,
+                                                    const int32_t* __restrict__ flags, int level) {
+  if (flags[level - 1] == 0) return;  // the search of this sweep has ended
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = e < nnz;
@@ -784,39 +790,37 @@ __global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ 
 __global__ __launch_bounds__(256) void k_bfs_update(uint64_t* __restrict__ acc, uint64_t* __restrict__ visited,
                                                     uint64_t* __restrict__ next, uint8_t* __restrict__ d, int n,
                                                     int ng, int base, int level, int write,
-                                                    int32_t* __restrict__ flag) {
-  const int v = blockIdx.x * 256 + threadIdx.x;
+                                                    int32_t* __restrict__ flags) {
+  if (flags[level - 1] == 0) return;  // the search of this sweep has ended
+  // wave w: word k = w % kBfsWords of vertices 64 (w / kBfsWords) + lane
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int k = w % kBfsWords, v = (w / kBfsWords) * 64 + (threadIdx.x & 63);
   if (v >= n) return;
-  bool any = false;
   const uint32_t lv = (uint32_t)level * 0x01010101u;
+  const size_t q = (size_t)v * kBfsWords + k;
+  const uint64_t a = acc[q];
+  const uint64_t vis = visited[q];
+  const uint64_t nw = a & ~vis;
+  next[q] = nw;
+  if (a) acc[q] = 0ull;
+  if (nw == 0) return;
+  flags[level] = 1;
+  if (!write) return;
+  visited[q] = vis | nw;
 #pragma unroll
-  for (int k = 0; k < kBfsWords; ++k) {
-    const size_t q = (size_t)v * kBfsWords + k;
-    const uint64_t a = acc[q];
-    const uint64_t vis = visited[q];
-    const uint64_t nw = a & ~vis;
-    next[q] = nw;
-    if (a) acc[q] = 0ull;
-    if (nw == 0) continue;
-    any = true;
-    if (!write) continue;
-    visited[q] = vis | nw;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const uint32_t bits = (uint32_t)(nw >> (16 * c)) & 0xffffu;
-      if (bits == 0) continue;
-      const int s0 = base + 64 * k + 16 * c;
-      uint4* chunk = reinterpret_cast<uint4*>(d + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
-                                              (size_t)(v % kRowBlock) * kColGroup);
-      uint4 w = *chunk;
-      w.x |= lv & byte_mask4(bits & 0xfu);
-      w.y |= lv & byte_mask4((bits >> 4) & 0xfu);
-      w.z |= lv & byte_mask4((bits >> 8) & 0xfu);
-      w.w |= lv & byte_mask4((bits >> 12) & 0xfu);
-      *chunk = w;
-    }
+  for (int c = 0; c < 4; ++c) {
+    const uint32_t bits = (uint32_t)(nw >> (16 * c)) & 0xffffu;
+    if (bits == 0) continue;
+    const int s0 = base + 64 * k + 16 * c;
+    uint4* chunk = reinterpret_cast<uint4*>(d + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
+                                            (size_t)(v % kRowBlock) * kColGroup);
+    uint4 wd = *chunk;
+    wd.x |= lv & byte_mask4(bits & 0xfu);
+    wd.y |= lv & byte_mask4((bits >> 4) & 0xfu);
+    wd.z |= lv & byte_mask4((bits >> 8) & 0xfu);
+    wd.w |= lv & byte_mask4((bits >> 12) & 0xfu);
+    *chunk = wd;
   }
-  if (any) *flag = 1;
 }
 
 // W_i = sum_j d_ij^-2 in double, columns in ascending order (one wave per row
@@ -893,14 +897,15 @@ hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, uint64_t* acc,
 
 hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* frontier,
                             uint64_t* acc, uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base,
-                            int level, int write, int32_t* flag, hipStream_t s) {
+                            int level, int write, int32_t* flags, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (nnz > 0)
     k_bfs_gather<<<blocks_for((size_t)nnz), 256, 0, s>>>(erow, col_idx, nnz, frontier,
-                                                         reinterpret_cast<unsigned long long*>(acc));
+                                                         reinterpret_cast<unsigned long long*>(acc), flags, level);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_bfs_update<<<blocks_for(n), 256, 0, s>>>(acc, visited, next, d, n, ng, base, level, write, flag);
+  const unsigned waves = (unsigned)((n + 63) / 64) * kBfsWords;
+  k_bfs_update<<<(waves + 3) / 4, 256, 0, s>>>(acc, visited, next, d, n, ng, base, level, write, flags);
   return hipGetLastError();
 }
 
