@@ -48,6 +48,10 @@ CASES = {
     "tree700_nograph": (lambda: (inputs.random_tree(700, 4), None), 2, {"omega": 1.7, "tol": 0.0, "max_iter": 25,
                                                                        "use_graph": False, "check_every": 3}),
     "ragged_129": (lambda: (inputs.erdos_renyi(129, 400, 5), None), 2, {"omega": 1.5, "tol": 0.0, "max_iter": 30}),
+    # one row block, one slice, three idle waves in the workgroup
+    "path5": (lambda: (inputs.to_csr(5, [(0, 1), (1, 2), (2, 3), (3, 4)]), None), 2,
+              {"omega": 1.8, "tol": 0.0, "max_iter": 30}),
+    "two_vertices": (lambda: (inputs.to_csr(2, [(0, 1)]), None), 3, {"omega": 1.5, "tol": 0.0, "max_iter": 12}),
 }
 
 
