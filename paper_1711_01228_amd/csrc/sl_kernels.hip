@@ -79,40 +79,46 @@ __global__ __launch_bounds__(256) void k_force(const uint8_t* __restrict__ d, co
   const int i = rb * kRowBlock + lane;
   const V xi = X[i];
   double F0 = 0.0, F1 = 0.0, F2 = 0.0, Sd = 0.0;
-  if (g0 < g1) {
-    C q = load_chunk<FD>(d, df, rb, ng, g0, lane);
-    for (int g = g0; g < g1; ++g) {
-      C qn = zero_chunk<FD>();
-      if (g + 1 < g1) qn = load_chunk<FD>(d, df, rb, ng, g + 1, lane);
-      const V* __restrict__ xj = X + (size_t)g * kColGroup;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
+  auto group = [&](int g, const C& q) {
+    const V* __restrict__ xj = X + (size_t)g * kColGroup;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
 #pragma unroll
-      for (int k = 0; k < kColGroup; ++k) {
-        const E wt = pair_weights<FD, STRESS>(q, k, lut);
-        const V p = xj[k];
-        const float dx = xi.x - p.x, dy = xi.y - p.y;
-        float r2 = fmaf(dx, dx, kTiny);
-        r2 = fmaf(dy, dy, r2);
-        float dz = 0.f;
-        if constexpr (DIM == 3) {
-          dz = xi.z - p.z;
-          r2 = fmaf(dz, dz, r2);
-        }
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float c = fmaf(wt.x, rinv, -wt.y);
-        a0 = fmaf(c, dx, a0);
-        a1 = fmaf(c, dy, a1);
-        if constexpr (DIM == 3) a2 = fmaf(c, dz, a2);
-        if constexpr (STRESS) {
-          const float t = fmaf(r2 * rinv, wt.x, -wt.z);
-          as = fmaf(t, t, as);
-        }
+    for (int k = 0; k < kColGroup; ++k) {
+      const E wt = pair_weights<FD, STRESS>(q, k, lut);
+      const V p = xj[k];
+      const float dx = xi.x - p.x, dy = xi.y - p.y;
+      float r2 = fmaf(dx, dx, kTiny);
+      r2 = fmaf(dy, dy, r2);
+      float dz = 0.f;
+      if constexpr (DIM == 3) {
+        dz = xi.z - p.z;
+        r2 = fmaf(dz, dz, r2);
       }
-      F0 += (double)a0;
-      F1 += (double)a1;
-      if constexpr (DIM == 3) F2 += (double)a2;
-      if constexpr (STRESS) Sd += (double)as;
-      q = qn;
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float c = fmaf(wt.x, rinv, -wt.y);
+      a0 = fmaf(c, dx, a0);
+      a1 = fmaf(c, dy, a1);
+      if constexpr (DIM == 3) a2 = fmaf(c, dz, a2);
+      if constexpr (STRESS) {
+        const float t = fmaf(r2 * rinv, wt.x, -wt.z);
+        as = fmaf(t, t, as);
+      }
+    }
+    F0 += (double)a0;
+    F1 += (double)a1;
+    if constexpr (DIM == 3) F2 += (double)a2;
+    if constexpr (STRESS) Sd += (double)as;
+  };
+  if (g0 < g1) {
+    // two chunk registers in turn (past the end the last group is loaded again:
+    // in bounds, unused)
+    C qa = load_chunk<FD>(d, df, rb, ng, g0, lane);
+    for (int g = g0; g < g1; g += 2) {
+      const C qb = load_chunk<FD>(d, df, rb, ng, min(g + 1, g1 - 1), lane);
+      group(g, qa);
+      if (g + 1 >= g1) break;
+      qa = load_chunk<FD>(d, df, rb, ng, min(g + 2, g1 - 1), lane);
+      group(g + 1, qb);
     }
   }
   double* fp = fpart + (size_t)slice * DIM * n_pad + i;
@@ -418,10 +424,7 @@ __global__ __launch_bounds__(256) void k_force_sg(const uint8_t* __restrict__ d,
   auto run = [&](auto mode_tag, int ga, int gb) {
     constexpr int MODE = decltype(mode_tag)::value;
     if (ga >= gb) return;
-    C q = load_chunk<FD>(d, df, rb, ng, ga, lane);
-    for (int g = ga; g < gb; ++g) {
-      C qn = zero_chunk<FD>();
-      if (g + 1 < gb) qn = load_chunk<FD>(d, df, rb, ng, g + 1, lane);
+    auto group = [&](int g, const C& q) {
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
       force_sg_group<DIM, FD, MODE>(q, lut, xi, ei, X + (size_t)g * kColGroup, E + (size_t)g * kColGroup,
                                     i - g * kColGroup, a0, a1, a2, as);
@@ -429,7 +432,16 @@ __global__ __launch_bounds__(256) void k_force_sg(const uint8_t* __restrict__ d,
       F1 += (double)a1;
       if constexpr (DIM == 3) F2 += (double)a2;
       if constexpr (MODE != 0) S += (double)as;
-      q = qn;
+    };
+    // two chunk registers in turn: the next group loads while this one computes
+    // (past the end the last group is loaded again: in bounds, unused)
+    C qa = load_chunk<FD>(d, df, rb, ng, ga, lane);
+    for (int g = ga; g < gb; g += 2) {
+      const C qb = load_chunk<FD>(d, df, rb, ng, min(g + 1, gb - 1), lane);
+      group(g, qa);
+      if (g + 1 >= gb) break;
+      qa = load_chunk<FD>(d, df, rb, ng, min(g + 2, gb - 1), lane);
+      group(g + 1, qb);
     }
   };
   run(std::integral_constant<int, 0>{}, g0, min(g1, gdiag));
