@@ -737,8 +737,9 @@ __global__ __launch_bounds__(256) void k_pack_out(const float* __restrict__ Xb, 
 // is two kernels:
 //   k_bfs_gather  one thread per CSR entry (v, u): the frontier bits of u,
 //                 OR-reduced over each run of equal v inside the wave (a
-//                 segmented OR over the CSR row; rows are contiguous) and
-//                 folded into acc[v] by one atomic OR per run and word
+//                 segmented OR over the CSR row; rows are contiguous), stored
+//                 into acc[v] when the run is the whole row, else folded in by
+//                 an atomic OR per run and word
 //   k_bfs_update  one thread per vertex and word: the new bits acc[v] & ~visited[v]
 //                 become the next frontier, and the level is written into
 //                 d(v, s) for every new source s.  Distances are symmetric, so
@@ -787,6 +788,14 @@ __global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ 
   }
   const int pv = __shfl_up(v, 1, 64);
   const bool head = valid && (lane == 0 || pv != v);
+  // A run that holds all of row v (it starts the row and ends inside the wave,
+  // or at the row's end) is v's only writer: a plain store.  Rows that cross a
+  // wave boundary (long rows) take an atomic OR.
+  const int64_t e0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);  // first entry of the wave
+  const bool row_open_before = lane == 0 && e0 > 0 && valid && erow[e0 - 1] == v;
+  const int v_last = __shfl(v, 63, 64);
+  const bool tail_continues = (e0 + 63 + 1 < nnz) && erow[e0 + 64] == v_last;  // the wave's last row goes on
+  const bool whole = head && !row_open_before && !(v == v_last && tail_continues);
 #pragma unroll
   for (int k = 0; k < kBfsWords; ++k) {
     unsigned long long f = valid ? frontier[(size_t)u * kBfsWords + k] : 0ull;
@@ -795,7 +804,10 @@ __global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ 
       const unsigned long long o = __shfl_down(f, 1 << s, 64);
       if (same[s]) f |= o;
     }
-    if (head && f) atomicOr(&acc[(size_t)v * kBfsWords + k], f);
+    if (head && f) {
+      if (whole) acc[(size_t)v * kBfsWords + k] = f;
+      else atomicOr(&acc[(size_t)v * kBfsWords + k], f);
+    }
   }
 }
 
