@@ -921,7 +921,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
       if (r == 0) HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
       switch (which) {
         case 4:
-          HIP_TRY(launch_lw(p->dim, p->cg, p->d, p->st, p->cg_st, p->fpart,
+          HIP_TRY(launch_lw(p->dim, p->cg, p->d, p->W, p->st, p->cg_st, p->fpart,
                             p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->sp, p->ps),
                   "L^W kernel");
           break;

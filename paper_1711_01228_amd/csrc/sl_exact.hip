@@ -4,7 +4,7 @@
 //
 //   start      Y_0 = X^k, so r_0 = L^X X^k - L^W X^k = F, the force pass at X^k
 //              (Prop. 2.1: the force on i is the residual of eq. 5)
-//   step j     q = L^W p, (L^W p)_i = sum_j w_ij (p_i - p_j): an all-pairs pass
+//   step j     q = L^W p, (L^W p)_i = sum_j w_ij (p_i - p_j) = W_i p_i - sum_j w_ij p_j: an all-pairs pass
 //              that streams one distance byte per ordered pair;
 //              alpha = (r.z)/(p.q), Y += alpha p, r -= alpha q, z = r / W;
 //              stop when ||r|| <= tol ||r_0|| (Frobenius over the columns) or
@@ -146,12 +146,15 @@ __global__ __launch_bounds__(256) void k_cg_init(CgVectors v, const double* __re
 
 // q slices = L^W p over all ordered pairs, in the tiling of the force pass:
 // one wave per (row block, column slice), p_j (double) through the scalar
-// cache, w = 1/d^2 (double) from an LDS table, products and sums in double so
-// that L^W p is accurate for smooth p, where the terms w (p_i - p_j) nearly
-// cancel.  Each block also writes a record of sum_i p_i q_i(slice) per column
-// (q is linear in the slices).
+// cache, w = 1/d^2 (double) from an LDS table, products and sums in double.
+// (L^W p)_i = W_i p_i - sum_j w_ij p_j, with W_i the double row sum of the same
+// weights: the pairs take one FMA per column, the slices -sum_j w_ij p_j, and
+// slice 0 also W_i p_i.  For smooth p, where the terms w (p_i - p_j) nearly
+// cancel, the one subtraction is done in double.  Each block also writes a
+// record of sum_i p_i q_i(slice) per column (q is linear in the slices).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_lw(const uint8_t* __restrict__ d, const double* __restrict__ pdb,
+                                            const double* __restrict__ W,
                                             const DevState* __restrict__ st, CgState* __restrict__ cg,
                                             double* __restrict__ qpart, double* __restrict__ pqrec, int nrb, int ng,
                                             int gps, int n_pad) {
@@ -185,13 +188,17 @@ __global__ __launch_bounds__(256) void k_lw(const uint8_t* __restrict__ d, const
         for (int k = 0; k < kColGroup; ++k) {
           const double w = lut[byte_of(chunk_word(q, k), k & 3)];
           const P pp = pj[k];
-          Q0 = fma(w, pi.x - pp.x, Q0);
-          Q1 = fma(w, pi.y - pp.y, Q1);
-          if constexpr (DIM == 3) Q2 = fma(w, pi.z - pp.z, Q2);
+          Q0 = fma(w, pp.x, Q0);
+          Q1 = fma(w, pp.y, Q1);
+          if constexpr (DIM == 3) Q2 = fma(w, pp.z, Q2);
         }
         q = qn;
       }
     }
+    const double Wi = slice == 0 ? W[i] : 0.0;
+    Q0 = Wi * pi.x - Q0;
+    Q1 = Wi * pi.y - Q1;
+    if constexpr (DIM == 3) Q2 = Wi * pi.z - Q2;
     double* qp = qpart + (size_t)slice * DIM * n_pad + i;
     qp[0] = Q0;
     qp[n_pad] = Q1;
@@ -316,13 +323,13 @@ hipError_t launch_cg_init(int dim, const CgVectors& v, const double* fpart, int 
   return hipGetLastError();
 }
 
-hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const DevState* st, CgState* cg, double* qpart,
-                     double* pqrec, const Split& sp, hipStream_t s) {
+hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double* W, const DevState* st, CgState* cg,
+                     double* qpart, double* pqrec, const Split& sp, hipStream_t s) {
   const dim3 grid(sp.blocks_x, sp.slices);
   if (dim == 2)
-    k_lw<2><<<grid, 256, 0, s>>>(d, v.pd, st, cg, qpart, pqrec, sp.nrb, sp.ng, sp.groups_per_slice, v.n_pad);
+    k_lw<2><<<grid, 256, 0, s>>>(d, v.pd, W, st, cg, qpart, pqrec, sp.nrb, sp.ng, sp.groups_per_slice, v.n_pad);
   else
-    k_lw<3><<<grid, 256, 0, s>>>(d, v.pd, st, cg, qpart, pqrec, sp.nrb, sp.ng, sp.groups_per_slice, v.n_pad);
+    k_lw<3><<<grid, 256, 0, s>>>(d, v.pd, W, st, cg, qpart, pqrec, sp.nrb, sp.ng, sp.groups_per_slice, v.n_pad);
   return hipGetLastError();
 }
 
@@ -332,7 +339,7 @@ hipError_t launch_cg_step(int dim, const CgVectors& v, const uint8_t* d, const d
   const int nblk = cg_blocks(v.n_pad);
   double* pqrec = part + (size_t)kCgSlots * nblk * 8;
   const int npq = sp.blocks_x * sp.slices;
-  hipError_t e = launch_lw(dim, v, d, st, cg, qpart, pqrec, sp, s);
+  hipError_t e = launch_lw(dim, v, d, W, st, cg, qpart, pqrec, sp, s);
   if (e != hipSuccess) return e;
   if (dim == 2) {
     k_cg_update<2><<<nblk, 256, 0, s>>>(v, W, comp, n, qpart, sp.slices, st, cg, part, nblk, pqrec, npq);

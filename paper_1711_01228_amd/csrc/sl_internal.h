@@ -136,8 +136,8 @@ hipError_t launch_force_sym(int dim, const uint8_t* dsym, const float* Xb, size_
                             const int4* items, int nitems, const int32_t* panel_items, double* Pi, float* Pj,
                             double* fpart, int n_pad, hipStream_t s);
 // One application of L^W to p (also used by the profiler).
-hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const DevState* st, CgState* cg, double* qpart,
-                     double* pqrec, const Split& sp, hipStream_t s);
+hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double* W, const DevState* st, CgState* cg,
+                     double* qpart, double* pqrec, const Split& sp, hipStream_t s);
 
 // ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);
