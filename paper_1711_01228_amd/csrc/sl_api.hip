@@ -303,21 +303,20 @@ sl_status build_weighted(sl_plan* p) {
   HIP_TRY(launch_wsssp(p->g_erow, p->g_col_idx, p->g_len, p->nnz, p->n, p->sp.ng, p->df, p->pred, p->ps),
           "shortest-path kernel");
   HIP_TRY(launch_wsym(p->df, p->n_pad, p->sp.ng, p->ps), "symmetrize kernel");
-  HIP_TRY(launch_weights(nullptr, p->df, p->W, p->sp, p->n, p->ps), "weights kernel");
+  HIP_TRY(launch_weights(nullptr, p->df, p->W, p->fpart, p->sp, p->n, p->ps), "weights kernel");
   return SL_OK;
 }
 
 sl_status build_distances(sl_plan* p, const sl_graph* g) {
   const int n = p->n;
   if (p->df) return build_weighted(p);
-  HIP_TRY(hipMemsetAsync(p->d, 0, (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
   if (n > 1 && g->nnz > 0) {
     // source row of every CSR entry, for the edge-parallel gather
     std::vector<int32_t> erow((size_t)g->nnz);
     for (int v = 0; v < n; ++v)
       for (int64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e) erow[(size_t)e] = v;
     int32_t *er = nullptr, *ci = nullptr;
-    uint64_t *fr = nullptr, *vis = nullptr, *nx = nullptr, *acc = nullptr;
+    uint64_t *slots = nullptr, *vis = nullptr, *acc = nullptr;
     int32_t* flag = nullptr;
     int32_t* hflag = nullptr;
     sl_status status = SL_OK;
@@ -325,20 +324,19 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       (void)hipStreamSynchronize(p->ps);
       (void)hipFree(er);
       (void)hipFree(ci);
-      (void)hipFree(fr);
+      (void)hipFree(slots);
       (void)hipFree(vis);
-      (void)hipFree(nx);
       (void)hipFree(acc);
       (void)hipFree(flag);
       if (hflag) (void)hipHostFree(hflag);
     };
     hipError_t e = hipSuccess;
     const size_t words = (size_t)n * bfs_words();
+    const int nslots = bfs_slots();
     if (e == hipSuccess) e = hipMalloc(&er, sizeof(int32_t) * g->nnz);
     if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * g->nnz);
-    if (e == hipSuccess) e = hipMalloc(&fr, sizeof(uint64_t) * words);
+    if (e == hipSuccess) e = hipMalloc(&slots, sizeof(uint64_t) * words * nslots);
     if (e == hipSuccess) e = hipMalloc(&vis, sizeof(uint64_t) * words);
-    if (e == hipSuccess) e = hipMalloc(&nx, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&acc, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t) * (kBfsMaxLevel + 1));
     if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t), hipHostMallocDefault);
@@ -348,25 +346,26 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       cleanup();
       return hip_fail(e, "distance buffers");
     }
+    // Every byte of d is written by the first batch of levels of some sweep
+    // (the sweeps' column ranges cover [0, n_pad), and every row is stored).
     const int sweep = bfs_sources_per_sweep();
-    constexpr int kLevelsPerPoll = 16;  // levels queued between looks at the flags
     for (int base = 0; base < n && status == SL_OK && e == hipSuccess; base += sweep) {
-      e = launch_bfs_init(fr, vis, acc, n, base, p->ps);
+      e = launch_bfs_init(slots, vis, acc, n, base, p->ps);
       // flags[l] = 0 for every level, flags[0] != 0 (the sources)
       if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int32_t) * (kBfsMaxLevel + 1), p->ps);
       if (e == hipSuccess) e = hipMemsetAsync(flag, 1, sizeof(int32_t), p->ps);
-      for (int level = 1; e == hipSuccess;) {
-        const int last = std::min(level + kLevelsPerPoll - 1, kBfsMaxLevel);
-        for (; level <= last && e == hipSuccess; ++level) {
-          // level 256 writes nothing: it only tells whether a distance exceeds 255
-          e = launch_bfs_level(er, ci, g->nnz, fr, acc, vis, nx, p->d, n, p->sp.ng, base, level,
-                               level < kBfsMaxLevel ? 1 : 0, flag, p->ps);
-          std::swap(fr, nx);
-        }
-        if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag + last, sizeof(int32_t), hipMemcpyDeviceToHost, p->ps);
+      for (int l0 = 1; e == hipSuccess; l0 += nslots) {
+        // one batch: as many levels as there are slots, then their distances
+        const int l1 = std::min(l0 + nslots - 1, kBfsMaxLevel);
+        for (int level = l0; level <= l1 && e == hipSuccess; ++level)
+          e = launch_bfs_level(er, ci, g->nnz, slots, acc, vis, n, level, flag, p->ps);
+        // level 256 is not stored: it only tells whether a distance exceeds 255
+        if (e == hipSuccess)
+          e = launch_bfs_store(slots, flag, p->d, n, p->n_pad, base, l0, std::min(l1, kBfsMaxLevel - 1), p->ps);
+        if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag + l1, sizeof(int32_t), hipMemcpyDeviceToHost, p->ps);
         if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
         if (e != hipSuccess || *hflag == 0) break;
-        if (last == kBfsMaxLevel) {
+        if (l1 == kBfsMaxLevel) {
           status = fail(SL_ERANGE, "a graph distance exceeds 255 hops (sources %d..%d)", base, base + sweep - 1);
           break;
         }
@@ -375,8 +374,10 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     cleanup();
     if (e != hipSuccess) return hip_fail(e, "breadth-first search");
     if (status != SL_OK) return status;
+  } else {
+    HIP_TRY(hipMemsetAsync(p->d, 0, (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
   }
-  HIP_TRY(launch_weights(p->d, nullptr, p->W, p->sp, n, p->ps), "weights kernel");
+  HIP_TRY(launch_weights(p->d, nullptr, p->W, p->fpart, p->sp, n, p->ps), "weights kernel");
   return SL_OK;
 }
 

@@ -1,0 +1,294 @@
+// Hop distances of all vertex pairs and the weight row sums, built once per
+// graph: d_ij is the graph-theoretic distance (Sec. 2, eq. 1; Sec. 5.1),
+// w_ij = d_ij^-2, and W_i = sum_j w_ij is the diagonal of L^W (Prop. 2.1).
+//
+// Breadth-first search from kBfsSources sources at once.  Word k of vertex v
+// (index 32 v + k) holds one bit per source base + 64 k + b.  Per level l:
+//   k_bfs_gather  acc(v) = OR of the level l-1 frontier words of v's
+//                 neighbours.  A lane group of 16 lanes reads one neighbour's
+//                 256 bytes per step (one 16-byte load a lane) and keeps the OR
+//                 of its current CSR row in registers; a row held whole by a
+//                 group is stored, a row split over groups is folded in by
+//                 64-bit atomic ORs.
+//   k_bfs_update  N_l = acc & ~visited (the sources that reach v first at
+//                 level l), visited |= N_l, acc = 0.  N_l is kept in level slot
+//                 l mod kBfsSlots and is also the next frontier.
+// Every kBfsSlots levels, k_bfs_store turns the slots of that batch of levels
+// into distance bytes: it transposes a 64-row by 8-word block through LDS into
+// four bit planes of the level offset and one plane of "found", and writes
+// the 16-byte lane chunks of the tile layout, 1 KiB contiguous per wave.  The
+// first batch writes the sweep's whole column range (0 where no level found
+// the pair); later batches merge into what is there.
+// Levels after one that found nothing return at once (flags[l] is set by
+// level l's update, flags[0] stands for the sources), so the host queues a
+// batch of levels and reads one flag per batch.
+#include "sl_device.h"
+#include "sl_internal.h"
+
+namespace sl {
+
+namespace {
+
+constexpr int kBfsWords = 32;                 // 64-bit words per vertex
+constexpr int kBfsSources = 64 * kBfsWords;   // sources per sweep
+constexpr int kBfsSlots = 16;                 // level bitmaps kept between stores of d
+constexpr int kGatherLanes = 16;              // lanes per neighbour row (16 bytes each)
+constexpr int kGatherGroups = 64 / kGatherLanes;
+constexpr int kGatherRun = 16;                // CSR entries per lane group
+static_assert(kGatherGroups * kGatherRun == 64, "a wave takes one CSR entry per lane");
+constexpr int kStoreWords = 8;                // words per row in one store block
+
+inline unsigned blocks_for(size_t items) { return (unsigned)((items + 255) / 256); }
+
+__global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ slot0, uint64_t* __restrict__ visited,
+                                                  uint64_t* __restrict__ acc, size_t words, int base) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= words) return;
+  const int v = (int)(q / kBfsWords), k = (int)(q % kBfsWords);
+  const int s0 = base + 64 * k;
+  const uint64_t w = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
+  slot0[q] = w;
+  visited[q] = w;
+  acc[q] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ erow,
+                                                    const int32_t* __restrict__ col_idx, int64_t nnz,
+                                                    const uint64_t* __restrict__ frontier,
+                                                    unsigned long long* __restrict__ acc,
+                                                    const int32_t* __restrict__ flags, int level) {
+  if (flags[level - 1] == 0) return;  // the search of this sweep has ended
+  const int lane = threadIdx.x & 63, grp = lane / kGatherLanes, wl = lane % kGatherLanes;
+  const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;  // the wave's first CSR entry
+  if (e0 >= nnz) return;
+  // lane j holds entry e0 + j; lane group g walks entries e0 + 16 g .. + 15
+  const int64_t ej = e0 + lane;
+  const int vj = ej < nnz ? erow[ej] : -1;
+  const int uj = ej < nnz ? col_idx[ej] : 0;
+  const int64_t gs = e0 + (int64_t)kGatherRun * grp;
+  const int v_before = (gs > 0 && gs <= nnz) ? erow[gs - 1] : -1;
+  const int v_after = (gs + kGatherRun < nnz) ? erow[gs + kGatherRun] : -1;
+  const ulonglong2* __restrict__ F = reinterpret_cast<const ulonglong2*>(frontier);
+  ulonglong2 f[kGatherRun];
+  int vv[kGatherRun];
+#pragma unroll
+  for (int j = 0; j < kGatherRun; ++j) {
+    vv[j] = __shfl(vj, kGatherRun * grp + j, 64);
+    const int u = __shfl(uj, kGatherRun * grp + j, 64);
+    f[j] = vv[j] >= 0 ? F[(size_t)u * (kBfsWords / 2) + wl] : make_ulonglong2(0ull, 0ull);
+  }
+  int cur = -1;
+  bool from_before = false;
+  uint64_t a0 = 0ull, a1 = 0ull;
+  auto flush = [&](bool continues) {
+    unsigned long long* dst = acc + (size_t)cur * kBfsWords + 2 * wl;
+    if (!from_before && !continues) {  // the whole row is in this run: its only writer
+      if (a0 | a1) *reinterpret_cast<ulonglong2*>(dst) = make_ulonglong2(a0, a1);
+    } else {
+      if (a0) atomicOr(dst, (unsigned long long)a0);
+      if (a1) atomicOr(dst + 1, (unsigned long long)a1);
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < kGatherRun; ++j) {
+    const int v = vv[j];
+    if (v != cur) {
+      if (cur >= 0) flush(false);
+      cur = v;
+      from_before = j == 0 && v == v_before;
+      a0 = a1 = 0ull;
+    }
+    a0 |= f[j].x;
+    a1 |= f[j].y;
+  }
+  if (cur >= 0) flush(cur == v_after);
+}
+
+// Two words per thread.
+__global__ __launch_bounds__(256) void k_bfs_update(ulonglong2* __restrict__ acc, ulonglong2* __restrict__ visited,
+                                                    ulonglong2* __restrict__ slot, size_t pairs, int level,
+                                                    int32_t* __restrict__ flags) {
+  if (flags[level - 1] == 0) return;  // the search of this sweep has ended
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= pairs) return;
+  const ulonglong2 a = acc[q];
+  ulonglong2 nw = make_ulonglong2(0ull, 0ull);
+  if (a.x | a.y) {
+    const ulonglong2 vis = visited[q];
+    nw = make_ulonglong2(a.x & ~vis.x, a.y & ~vis.y);
+    acc[q] = make_ulonglong2(0ull, 0ull);
+    if (nw.x | nw.y) {
+      visited[q] = make_ulonglong2(vis.x | nw.x, vis.y | nw.y);
+      flags[level] = 1;
+    }
+  }
+  slot[q] = nw;
+}
+
+// Bit b of the nibble to bit 0 of byte b.
+__device__ __forceinline__ uint32_t spread4(uint32_t nib) { return ((nib & 0xfu) * 0x00204081u) & 0x01010101u; }
+
+// Levels l0..l1 (one batch, l1 - l0 < 16) into d.  Workgroup: row block rb,
+// words 8 kq .. 8 kq + 7 of the sweep.
+__global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ slots, size_t slot_words,
+                                                   const int32_t* __restrict__ flags, uint8_t* __restrict__ d,
+                                                   int n, int ng, int base, int l0, int l1) {
+  if (l0 > 1 && flags[l0] == 0) return;  // nothing found in this batch; the first batch writes every byte
+  __shared__ uint64_t planes[5][kRowBlock][kStoreWords + 1];
+  const int rb = blockIdx.x / (kBfsWords / kStoreWords), kq = blockIdx.x % (kBfsWords / kStoreWords);
+  const int t = threadIdx.x;
+  // planes 0..3: bits of l - l0; plane 4: found in this batch
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int p = t + 256 * r;
+    const int row = p / kStoreWords, kk = p % kStoreWords;
+    const int v = rb * kRowBlock + row;
+    const size_t q = (size_t)v * kBfsWords + kq * kStoreWords + kk;
+    uint64_t P0 = 0, P1 = 0, P2 = 0, P3 = 0, Fd = 0;
+    for (int l = l0; l <= l1; ++l) {
+      if (flags[l] == 0) break;  // levels after an empty one found nothing
+      const uint64_t nw = v < n ? slots[(size_t)(l % kBfsSlots) * slot_words + q] : 0ull;
+      const int off = l - l0;
+      Fd |= nw;
+      if (off & 1) P0 |= nw;
+      if (off & 2) P1 |= nw;
+      if (off & 4) P2 |= nw;
+      if (off & 8) P3 |= nw;
+    }
+    planes[0][row][kk] = P0;
+    planes[1][row][kk] = P1;
+    planes[2][row][kk] = P2;
+    planes[3][row][kk] = P3;
+    planes[4][row][kk] = Fd;
+  }
+  __syncthreads();
+  const int wave = t >> 6, row = t & 63;
+  const uint32_t lvl = (uint32_t)l0 * 0x01010101u;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int kk = 2 * wave + r;
+    const int k = kq * kStoreWords + kk;
+    const uint64_t P0 = planes[0][row][kk], P1 = planes[1][row][kk], P2 = planes[2][row][kk],
+                   P3 = planes[3][row][kk], Fd = planes[4][row][kk];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int cg = (base + 64 * k + 16 * c) / kColGroup;
+      if (cg >= ng) break;  // columns past the padded size
+      uint32_t val[4], msk[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int sh = 16 * c + 4 * m;
+        const uint32_t x = spread4((uint32_t)(P0 >> sh)) | (spread4((uint32_t)(P1 >> sh)) << 1) |
+                           (spread4((uint32_t)(P2 >> sh)) << 2) | (spread4((uint32_t)(P3 >> sh)) << 3);
+        msk[m] = spread4((uint32_t)(Fd >> sh)) * 0xffu;
+        val[m] = (x + lvl) & msk[m];  // l0 + offset <= 255 in every byte: no carry
+      }
+      uint4* chunk = reinterpret_cast<uint4*>(d + ((size_t)rb * ng + cg) * kTileBytes + (size_t)row * kColGroup);
+      if (l0 == 1) {
+        *chunk = make_uint4(val[0], val[1], val[2], val[3]);
+      } else if ((Fd >> (16 * c)) & 0xffffull) {
+        const uint4 o = *chunk;
+        *chunk = make_uint4(val[0] | (o.x & ~msk[0]), val[1] | (o.y & ~msk[1]), val[2] | (o.z & ~msk[2]),
+                            val[3] | (o.w & ~msk[3]));
+      }
+    }
+  }
+}
+
+// W_i = sum_j d_ij^-2 in double: each wave sums its row block over one column
+// slice (columns in ascending order, the tile stream of the force pass), then
+// k_weights_sum adds the slices in slice order.
+template <bool FD>
+__global__ __launch_bounds__(256) void k_weights(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                                 double* __restrict__ wpart, int nrb, int ng, int gps, int n_pad) {
+  __shared__ double lut[256];
+  if constexpr (!FD) {
+    lut[threadIdx.x] = threadIdx.x ? 1.0 / ((double)threadIdx.x * (double)threadIdx.x) : 0.0;
+    __syncthreads();
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb = blockIdx.x * 4 + wave;
+  if (rb >= nrb) return;
+  const int g0 = blockIdx.y * gps, g1 = min(g0 + gps, ng);
+  double s = 0.0;
+  if (g0 < g1) {
+    auto q = load_chunk<FD>(d, df, rb, ng, g0, lane);
+    for (int g = g0; g < g1; ++g) {
+      const auto qn = load_chunk<FD>(d, df, rb, ng, min(g + 1, g1 - 1), lane);
+#pragma unroll
+      for (int k = 0; k < kColGroup; ++k) {
+        if constexpr (FD) {
+          const double dv = (double)fchunk_at(q, k);
+          s += dv > 0.0 ? 1.0 / (dv * dv) : 0.0;
+        } else {
+          s += lut[byte_of(chunk_word(q, k), k & 3)];
+        }
+      }
+      q = qn;
+    }
+  }
+  wpart[(size_t)blockIdx.y * n_pad + rb * kRowBlock + lane] = s;
+}
+
+__global__ __launch_bounds__(256) void k_weights_sum(const double* __restrict__ wpart, int slices, double* __restrict__ W,
+                                                     int n, int n_pad) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_pad) return;
+  const double s = sum_strided(wpart + i, slices, (size_t)n_pad);
+  W[i] = i < n ? s : 0.0;
+}
+
+}  // namespace
+
+int bfs_sources_per_sweep() { return kBfsSources; }
+int bfs_words() { return kBfsWords; }
+int bfs_slots() { return kBfsSlots; }
+
+hipError_t launch_bfs_init(uint64_t* slot0, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t words = (size_t)n * kBfsWords;
+  k_bfs_init<<<blocks_for(words), 256, 0, s>>>(slot0, visited, acc, words, base);
+  return hipGetLastError();
+}
+
+hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* slots,
+                            uint64_t* acc, uint64_t* visited, int n, int level, int32_t* flags, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t words = (size_t)n * kBfsWords;
+  const uint64_t* frontier = slots + (size_t)((level - 1) % kBfsSlots) * words;
+  uint64_t* out = const_cast<uint64_t*>(slots) + (size_t)(level % kBfsSlots) * words;
+  if (nnz > 0) {
+    const size_t waves = ((size_t)nnz + 63) / 64;
+    k_bfs_gather<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(erow, col_idx, nnz, frontier,
+                                                             reinterpret_cast<unsigned long long*>(acc), flags, level);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_bfs_update<<<blocks_for(words / 2), 256, 0, s>>>(reinterpret_cast<ulonglong2*>(acc),
+                                                     reinterpret_cast<ulonglong2*>(visited),
+                                                     reinterpret_cast<ulonglong2*>(out), words / 2, level, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, int n, int n_pad, int base,
+                            int l0, int l1, hipStream_t s) {
+  if (n <= 0 || l1 < l0) return hipSuccess;
+  const int nrb = n_pad / kRowBlock;
+  k_bfs_store<<<(unsigned)nrb * (kBfsWords / kStoreWords), 256, 0, s>>>(slots, (size_t)n * kBfsWords, flags, d, n,
+                                                                        n_pad / kColGroup, base, l0, l1);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights(const uint8_t* d, const float* df, double* W, double* wpart, const Split& sp, int n,
+                          hipStream_t s) {
+  const int n_pad = sp.nrb * kRowBlock;
+  const dim3 grid(sp.blocks_x, sp.slices);
+  if (df) k_weights<true><<<grid, 256, 0, s>>>(d, df, wpart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+  else k_weights<false><<<grid, 256, 0, s>>>(d, df, wpart, sp.nrb, sp.ng, sp.groups_per_slice, n_pad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_weights_sum<<<blocks_for(n_pad), 256, 0, s>>>(wpart, sp.slices, W, n, n_pad);
+  return hipGetLastError();
+}
+
+}  // namespace sl

@@ -141,15 +141,25 @@ hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double
 
 // ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);
+// ---- distances and weights (sl_apsp.hip)
 int bfs_sources_per_sweep();  // sources searched together (bits per vertex)
 int bfs_words();              // 64-bit words per vertex in the BFS buffers
-hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s);
+int bfs_slots();              // level bitmaps kept (levels per batch)
+// slots: bfs_slots() buffers of n * bfs_words() words; slot l % bfs_slots()
+// holds the sources that first reach each vertex at level l (slot 0: level 0).
+hipError_t launch_bfs_init(uint64_t* slot0, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s);
 // One BFS level (1 .. 256).  flags[0 .. 256]: flags[l] != 0 iff level l found a
 // new vertex (flags[0]: the sources); a level after an empty one does nothing.
-hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* frontier,
-                            uint64_t* acc, uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base,
-                            int level, int write, int32_t* flags, hipStream_t s);
-hipError_t launch_weights(const uint8_t* d, const float* df, double* W, const Split& sp, int n, hipStream_t s);
+hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* slots,
+                            uint64_t* acc, uint64_t* visited, int n, int level, int32_t* flags, hipStream_t s);
+// Levels l0 .. l1 (l1 - l0 < bfs_slots(), l1 <= 255) of the sweep from sources
+// base .. base + bfs_sources_per_sweep() - 1 into d; the batch starting at
+// level 1 writes every byte of the sweep's columns (below n_pad) in all rows.
+hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, int n, int n_pad, int base,
+                            int l0, int l1, hipStream_t s);
+// W from d (or df); wpart: scratch of sp.slices * n_pad doubles.
+hipError_t launch_weights(const uint8_t* d, const float* df, double* W, double* wpart, const Split& sp, int n,
+                          hipStream_t s);
 // Weighted graphs: FP32 shortest-path distances (tile-major, 0 = no path) and
 // trees (pred[s][v], row-major int32), then the lower triangle := the upper.
 // erow: the row of every CSR entry.

@@ -10,10 +10,7 @@
 //   k_sgdelta  f(X~) - f(X^H) over unordered pairs (Alg. 2, line 6)
 //   k_select   the decision of Alg. 2 lines 6-8, the termination test and the
 //              iteration counter, in one workgroup
-// and once per graph
-//   k_bfs_*    breadth-first search from 256 sources at a time (bit-parallel
-//              frontiers) writing hop distances d_ij as bytes
-//   k_weights  W_i = sum_j d_ij^-2, the diagonal of L^W
+// The distances and W_i, built once per graph, are in sl_apsp.hip.
 //
 // Every cross-thread sum is taken in a fixed order (per-lane sequences, fixed
 // trees, fixed slice order), so results are bitwise repeatable run to run.
@@ -731,152 +728,6 @@ __global__ __launch_bounds__(256) void k_pack_out(const float* __restrict__ Xb, 
   for (int c = 0; c < dim; ++c) X[(size_t)i * dim + c] = src[c];
 }
 
-// ---------------------------------------------------------------------------
-// Breadth-first search from kBfsSources sources at once.  Word k of a vertex
-// holds one bit per source base + 64k + b (bit-parallel frontiers).  A level
-// is two kernels:
-//   k_bfs_gather  one thread per CSR entry (v, u): the frontier bits of u,
-//                 OR-reduced over each run of equal v inside the wave (a
-//                 segmented OR over the CSR row; rows are contiguous), stored
-//                 into acc[v] when the run is the whole row, else folded in by
-//                 an atomic OR per run and word
-//   k_bfs_update  one thread per vertex and word: the new bits acc[v] & ~visited[v]
-//                 become the next frontier, and the level is written into
-//                 d(v, s) for every new source s.  Distances are symmetric, so
-//                 row v is written: 16 sources share one 16-byte lane chunk of
-//                 the tile layout, read-modify-written by the only thread that
-//                 owns row v and that word.  A wave takes one word of 64
-//                 consecutive vertices (its chunk writes are 1 KiB contiguous).
-// Both return at once when the previous level found no new vertex (flags[l]
-// is set by level l's update; flags[0] stands for the sources), so the host
-// can queue many levels and look at the flags once per batch of levels.
-// ---------------------------------------------------------------------------
-constexpr int kBfsWords = 32;
-constexpr int kBfsSources = 64 * kBfsWords;
-
-__global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ frontier, uint64_t* __restrict__ visited,
-                                                  uint64_t* __restrict__ acc, int n, int base) {
-  const int v = blockIdx.x * 256 + threadIdx.x;
-  if (v >= n) return;
-#pragma unroll
-  for (int k = 0; k < kBfsWords; ++k) {
-    const int s0 = base + 64 * k;
-    const uint64_t w = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
-    frontier[(size_t)v * kBfsWords + k] = w;
-    visited[(size_t)v * kBfsWords + k] = w;
-    acc[(size_t)v * kBfsWords + k] = 0ull;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ erow,
-                                                    const int32_t* __restrict__ col_idx, int64_t nnz,
-                                                    const uint64_t* __restrict__ frontier,
-                                                    unsigned long long* __restrict__ acc,
-                                                    const int32_t* __restrict__ flags, int level) {
-  if (flags[level - 1] == 0) return;  // the search of this sweep has ended
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool valid = e < nnz;
-  const int v = valid ? erow[e] : -1 - lane;  // padding lanes never join a run
-  const int u = valid ? col_idx[e] : 0;
-  bool same[6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int off = 1 << s;
-    const int ov = __shfl_down(v, off, 64);
-    same[s] = (lane + off < 64) && ov == v;
-  }
-  const int pv = __shfl_up(v, 1, 64);
-  const bool head = valid && (lane == 0 || pv != v);
-  // A run that holds all of row v (it starts the row and ends inside the wave,
-  // or at the row's end) is v's only writer: a plain store.  Rows that cross a
-  // wave boundary (long rows) take an atomic OR.
-  const int64_t e0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);  // first entry of the wave
-  const bool row_open_before = lane == 0 && e0 > 0 && valid && erow[e0 - 1] == v;
-  const int v_last = __shfl(v, 63, 64);
-  const bool tail_continues = (e0 + 63 + 1 < nnz) && erow[e0 + 64] == v_last;  // the wave's last row goes on
-  const bool whole = head && !row_open_before && !(v == v_last && tail_continues);
-#pragma unroll
-  for (int k = 0; k < kBfsWords; ++k) {
-    unsigned long long f = valid ? frontier[(size_t)u * kBfsWords + k] : 0ull;
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      const unsigned long long o = __shfl_down(f, 1 << s, 64);
-      if (same[s]) f |= o;
-    }
-    if (head && f) {
-      if (whole) acc[(size_t)v * kBfsWords + k] = f;
-      else atomicOr(&acc[(size_t)v * kBfsWords + k], f);
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_bfs_update(uint64_t* __restrict__ acc, uint64_t* __restrict__ visited,
-                                                    uint64_t* __restrict__ next, uint8_t* __restrict__ d, int n,
-                                                    int ng, int base, int level, int write,
-                                                    int32_t* __restrict__ flags) {
-  if (flags[level - 1] == 0) return;  // the search of this sweep has ended
-  // wave w: word k = w % kBfsWords of vertices 64 (w / kBfsWords) + lane
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int k = w % kBfsWords, v = (w / kBfsWords) * 64 + (threadIdx.x & 63);
-  if (v >= n) return;
-  const uint32_t lv = (uint32_t)level * 0x01010101u;
-  const size_t q = (size_t)v * kBfsWords + k;
-  const uint64_t a = acc[q];
-  const uint64_t vis = visited[q];
-  const uint64_t nw = a & ~vis;
-  next[q] = nw;
-  if (a) acc[q] = 0ull;
-  if (nw == 0) return;
-  flags[level] = 1;
-  if (!write) return;
-  visited[q] = vis | nw;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const uint32_t bits = (uint32_t)(nw >> (16 * c)) & 0xffffu;
-    if (bits == 0) continue;
-    const int s0 = base + 64 * k + 16 * c;
-    uint4* chunk = reinterpret_cast<uint4*>(d + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
-                                            (size_t)(v % kRowBlock) * kColGroup);
-    uint4 wd = *chunk;
-    wd.x |= lv & byte_mask4(bits & 0xfu);
-    wd.y |= lv & byte_mask4((bits >> 4) & 0xfu);
-    wd.z |= lv & byte_mask4((bits >> 8) & 0xfu);
-    wd.w |= lv & byte_mask4((bits >> 12) & 0xfu);
-    *chunk = wd;
-  }
-}
-
-// W_i = sum_j d_ij^-2 in double, columns in ascending order (one wave per row
-// block, lane = row, the same tile stream as the force pass).
-template <bool FD>
-__global__ __launch_bounds__(256) void k_weights(const uint8_t* __restrict__ d, const float* __restrict__ df,
-                                                 double* __restrict__ W, int nrb, int ng, int n) {
-  __shared__ double lut[256];
-  if constexpr (!FD) {
-    lut[threadIdx.x] = threadIdx.x ? 1.0 / ((double)threadIdx.x * (double)threadIdx.x) : 0.0;
-    __syncthreads();
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rb = blockIdx.x * 4 + wave;
-  if (rb >= nrb) return;
-  double s = 0.0;
-  for (int g = 0; g < ng; ++g) {
-    const auto q = load_chunk<FD>(d, df, rb, ng, g, lane);
-#pragma unroll
-    for (int k = 0; k < kColGroup; ++k) {
-      if constexpr (FD) {
-        const double dv = (double)fchunk_at(q, k);
-        s += dv > 0.0 ? 1.0 / (dv * dv) : 0.0;
-      } else {
-        s += lut[(chunk_word(q, k) >> (8 * (k & 3))) & 0xffu];
-      }
-    }
-  }
-  const int i = rb * kRowBlock + lane;
-  W[i] = (i < n) ? s : 0.0;
-}
-
 __global__ __launch_bounds__(256) void k_gather_rows(const uint8_t* __restrict__ d, const float* __restrict__ df,
                                                      const int32_t* __restrict__ rows, int nrows, int n, int ng,
                                                      float* __restrict__ out) {
@@ -909,35 +760,6 @@ Split make_split(int n_pad) {
 }
 
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s) { return hipMemsetAsync(p, 0, bytes, s); }
-
-int bfs_sources_per_sweep() { return kBfsSources; }
-int bfs_words() { return kBfsWords; }
-
-hipError_t launch_bfs_init(uint64_t* frontier, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  k_bfs_init<<<blocks_for(n), 256, 0, s>>>(frontier, visited, acc, n, base);
-  return hipGetLastError();
-}
-
-hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* frontier,
-                            uint64_t* acc, uint64_t* visited, uint64_t* next, uint8_t* d, int n, int ng, int base,
-                            int level, int write, int32_t* flags, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (nnz > 0)
-    k_bfs_gather<<<blocks_for((size_t)nnz), 256, 0, s>>>(erow, col_idx, nnz, frontier,
-                                                         reinterpret_cast<unsigned long long*>(acc), flags, level);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const unsigned waves = (unsigned)((n + 63) / 64) * kBfsWords;
-  k_bfs_update<<<(waves + 3) / 4, 256, 0, s>>>(acc, visited, next, d, n, ng, base, level, write, flags);
-  return hipGetLastError();
-}
-
-hipError_t launch_weights(const uint8_t* d, const float* df, double* W, const Split& sp, int n, hipStream_t s) {
-  if (df) k_weights<true><<<sp.blocks_x, 256, 0, s>>>(d, df, W, sp.nrb, sp.ng, n);
-  else k_weights<false><<<sp.blocks_x, 256, 0, s>>>(d, df, W, sp.nrb, sp.ng, n);
-  return hipGetLastError();
-}
 
 hipError_t launch_pack_in(const float* X, float* Xb, int n, int n_pad, int dim, hipStream_t s) {
   k_pack_in<<<blocks_for(n_pad), 256, 0, s>>>(X, Xb, n, n_pad, dim);
