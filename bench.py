@@ -67,6 +67,34 @@ def measured_traffic(dim):
     return rec.get("bytes_per_launch")
 
 
+def measured_ceilings():
+    """What this device sustains, beside its data-sheet peaks: plain FP32 FMAs
+    (the build has no packed FP32) and the transcendentals of the force and
+    safeguard terms, from the library's calibration kernels, and a 1 GiB
+    device-to-device copy (read + write bytes over its HIP-event time)."""
+    import torch
+
+    from paper_1711_01228_amd import binding
+
+    res = {}
+    fma, _ = binding.sl_probe_rate("fma")
+    res["fp32_fma_TFLOPs"] = round(2.0 * fma / 1e12, 2)
+    for k in ("rsq", "sqrt", "rcp"):
+        res["%s_per_s" % k] = float("%.4g" % binding.sl_probe_rate(k)[0])
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    res["hbm_copy_GBps"] = round(5 * 2 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9, 1)
+    del src, dst
+    return res
+
+
 def cpu_baseline(g, X0, target_s=12.0):
     """The FP64 oracle's Jacobi step on a sample of rows of the same graph."""
     import numpy as np
@@ -90,7 +118,13 @@ def cpu_baseline(g, X0, target_s=12.0):
     pairs = R * (n - 1)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rate = pairs / dt
-    return {"value": rate, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
+    return {"value": rate, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle", "host_cpu": model,
             "sample": "FP64 Jacobi step (eq. 5 row solves) for %d random rows x all %d columns of the same "
                       "BA graph and start, %.1f s; distance rows (BFS) not timed" % (R, n, dt),
             "seconds_per_jacobi_step": float(n) * (n - 1) / rate}
@@ -363,8 +397,11 @@ def main():
                 "unordered_pass": {"kernel": "k_force_sym + k_sym_reduce (opt-in)", "kernel_ms": round(ms["force_sym"], 4),
                                    "TFLOPs": round(FLOPS_PER_UNORDERED_PAIR[dim] * pairs / 2 / t_sym / 1e12, 3)
                                    if t_sym > 0 else None},
-                "step_kernel_ms": {k: round(v, 4) for k, v in ms.items()}}
+                "step_kernel_ms": {k: round(v, 4) for k, v in ms.items()},
+                "measured_ceilings": measured_ceilings()}
+    roofline["frac_of_measured_fma"] = round(achieved / roofline["measured_ceilings"]["fp32_fma_TFLOPs"], 4)
     log("kernels (ms):", ms)
+    log("measured ceilings:", roofline["measured_ceilings"])
 
     out = {"metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,

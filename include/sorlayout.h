@@ -329,6 +329,19 @@ sl_status sl_batch_plan_run(sl_batch_plan* plan, float* X, const sl_options* opt
 
 sl_status sl_batch_plan_destroy(sl_batch_plan* plan);
 
+/* Calibration of the roofline (not an operation of the method): the rate at
+ * which this device issues one instruction kind, for comparing the force
+ * pass against what the hardware sustains rather than only its data sheet.
+ *   kind 0: FP32 FMA (the library is built without packed FP32, so this is
+ *           the attainable vector FP32 rate; an FMA is 2 flops)
+ *   kind 1, 2, 3: rsq, sqrt, rcp (the transcendentals of the force and
+ *           safeguard terms)
+ * One launch of 8 waves per SIMD on `stream`, each lane running 8
+ * independent chains, timed with HIP events after one untimed launch.
+ * *per_s: lane operations per second; *ms: the timed launch.  Allocates and
+ * frees a 2 MiB result buffer.  SL_EINVAL for another kind or NULL outputs. */
+sl_status sl_probe_rate(int32_t kind, void* stream, double* per_s, double* ms);
+
 /* layout(G, X0, omega, tol, max_iter) -> X: sl_plan_create + sl_plan_run +
  * sl_plan_destroy. */
 sl_status sl_layout(const sl_graph* g, float* X, const sl_options* opt, void* stream, sl_result* out);

@@ -41,7 +41,7 @@ EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run"
             "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
             "sl_last_error", "sl_batch_plan_create", "sl_batch_plan_tune", "sl_batch_plan_run",
             "sl_batch_plan_destroy", "sl_plan_distance_rows_f32", "sl_plan_tree_rows", "sl_plan_set_lengths",
-            "sl_plan_stress_grad", "sl_plan_unroll", "sl_plan_unroll_backward")
+            "sl_plan_stress_grad", "sl_plan_unroll", "sl_plan_unroll_backward", "sl_probe_rate")
 SL_WEIGHTED_MAX_N = 16384
 SL_BATCH_MAX_N = 1024
 SL_BATCH_CLASSES = 16
@@ -117,6 +117,7 @@ def _load():
         "sl_batch_plan_tune": (st, [P, P, ctypes.POINTER(sl_options), P, P]),
         "sl_batch_plan_run": (st, [P, P, ctypes.POINTER(sl_options), P, P, ctypes.POINTER(sl_result)]),
         "sl_batch_plan_destroy": (st, [P]),
+        "sl_probe_rate": (st, [i32, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -276,6 +277,16 @@ def sl_plan_profile(plan: int, X_ptr: int, dim: int, omega: float, reps: int, st
 
 def sl_plan_destroy(plan: int) -> None:
     _check(LIB.sl_plan_destroy(plan))
+
+
+PROBE_KINDS = {"fma": 0, "rsq": 1, "sqrt": 2, "rcp": 3}
+
+
+def sl_probe_rate(kind: str, stream=None) -> tuple:
+    """(lane operations per second, ms) of one instruction kind on the device."""
+    per_s, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(LIB.sl_probe_rate(PROBE_KINDS[kind], _stream_handle(stream), ctypes.byref(per_s), ctypes.byref(ms)))
+    return per_s.value, ms.value
 
 
 def sl_layout(g, X_ptr: int, opt: sl_options, stream=None) -> dict:

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsorlayout.so")
 SOURCES = [os.path.join(CSRC, "sl_kernels.hip"), os.path.join(CSRC, "sl_apsp.hip"), os.path.join(CSRC, "sl_batch.hip"),
            os.path.join(CSRC, "sl_exact.hip"), os.path.join(CSRC, "sl_weighted.hip"), os.path.join(CSRC, "sl_diff.hip"),
-           os.path.join(CSRC, "sl_sym.hip"), os.path.join(CSRC, "sl_api.hip")]
+           os.path.join(CSRC, "sl_sym.hip"), os.path.join(CSRC, "sl_probe.hip"), os.path.join(CSRC, "sl_api.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, "sl_internal.h"), os.path.join(CSRC, "sl_device.h"),
                   os.path.join(INCLUDE, "sorlayout.h")]
 ARCH = "gfx950"

@@ -875,6 +875,37 @@ sl_status sl_plan_stress(sl_plan* p, const float* X, int32_t dim, void* stream, 
   return join_to(p, (hipStream_t)stream);
 }
 
+sl_status sl_probe_rate(int32_t kind, void* stream, double* per_s, double* ms) {
+  g_err.clear();
+  if (!per_s || !ms) return fail(SL_EINVAL, "per_s or ms is NULL");
+  if (kind < 0 || kind > 3) return fail(SL_EINVAL, "kind %d is not 0 (FMA), 1 (rsq), 2 (sqrt) or 3 (rcp)", kind);
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  const int blocks = std::max(1, cus) * 8;  // 4 waves per workgroup: 8 waves per SIMD
+  const int iters = 2000;
+  const hipStream_t s = (hipStream_t)stream;
+  float* out = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipMalloc(&out, sizeof(float) * (size_t)blocks * 256);
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = launch_probe(kind, out, blocks, iters, s);
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = launch_probe(kind, out, blocks, iters, s);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (out) (void)hipFree(out);
+  if (e != hipSuccess) return hip_fail(e, "probe kernel");
+  *ms = t;
+  *per_s = (double)blocks * 256.0 * probe_ops_per_lane(iters) / (t * 1e-3);
+  return SL_OK;
+}
+
 sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega, int32_t reps, void* stream,
                           double* ms) {
   g_err.clear();

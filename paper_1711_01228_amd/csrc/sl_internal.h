@@ -141,6 +141,10 @@ hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double
 
 // ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);
+// ---- calibration kernels (sl_probe.hip): blocks x 256 lanes, each running
+// probe_ops_per_lane(iters) instructions of one kind into out[blocks * 256]
+int probe_ops_per_lane(int iters);
+hipError_t launch_probe(int kind, float* out, int blocks, int iters, hipStream_t s);
 // ---- distances and weights (sl_apsp.hip)
 int bfs_sources_per_sweep();  // sources searched together (bits per vertex)
 int bfs_words();              // 64-bit words per vertex in the BFS buffers

@@ -164,3 +164,10 @@ def test_ba_degree_is_heavy_tailed():
     ba = inputs.barabasi_albert(20000, 3, seed=5)
     deg = np.diff(ba.row_ptr)
     assert deg.min() >= 3 and deg.max() > 100
+
+
+def test_probe_rate_refuses_unknown_kind_before_any_device_call():
+    per_s, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    assert b.LIB.sl_probe_rate(4, None, ctypes.byref(per_s), ctypes.byref(ms)) == b.SL_EINVAL
+    assert "kind" in b.last_error()
+    assert b.LIB.sl_probe_rate(0, None, None, ctypes.byref(ms)) == b.SL_EINVAL

@@ -338,3 +338,11 @@ def test_layout_one_call_matches_plan(sl):
     np.testing.assert_array_equal(X1.cpu().numpy(), X.cpu().numpy())
     assert info["iterations"] == info2["iterations"] and info["converged"]
     assert info["plan_ms"] > 0 and info["run_ms"] > 0
+
+
+def test_probe_rates_are_plausible(sl):
+    # lane operations per second: 1,024 SIMDs x 16 lanes x ~2.4 GHz is ~3.9e13 at one instruction per 4 cycles
+    for kind in ("fma", "rsq", "sqrt", "rcp"):
+        per_s, ms = sl.sl_probe_rate(kind)
+        print(kind, per_s, ms, flush=True)
+        assert ms > 0.0 and 1e12 < per_s < 1.6e14
