@@ -284,30 +284,49 @@ __global__ __launch_bounds__(256) void k_dsym(const float* __restrict__ Dbar, fl
 }
 
 // Per source s (one workgroup): delta(v) = base(v) + sum over the children c
-// of v in the tree of s of delta(c), base(v) = S[s][v] for v > s, else 0;
-// repeated in place until a round changes nothing (a round per tree level).
-// Children of v are its neighbours with pred = v, visited in CSR order.  Row s
-// of S is replaced by delta_s.
+// of v in the tree of s of delta(c), base(v) = S[s][v] for v > s, else 0.
+// Children of v are its neighbours with pred = v, visited in CSR order.  The
+// tree depth of every vertex comes first (rounds over the vertices in LDS, one
+// per level); then the levels are taken deepest first, so each vertex scans its
+// CSR row once, after all its children are final.  Leaves (most vertices of a
+// shortest-path tree) keep delta = base without a scan.  Row s of S is
+// replaced by delta_s.
 __global__ __launch_bounds__(1024) void k_tree_accum(const int64_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ col_idx,
                                                      const int32_t* __restrict__ pred, float* __restrict__ S, int n) {
   constexpr int kPer = kWeightedMaxN / 1024;
+  constexpr uint16_t kUnknown = 0xffff;  // not reached (depths are below kWeightedMaxN)
   __shared__ float delta[kWeightedMaxN];
-  __shared__ int32_t pr[kWeightedMaxN];
+  __shared__ int16_t pr[kWeightedMaxN];
+  __shared__ uint16_t depth[kWeightedMaxN];
+  __shared__ uint8_t parent[kWeightedMaxN];  // v has a child in the tree
   __shared__ int changed;
   const int s = blockIdx.x;
   float base[kPer];
+  int32_t rb[kPer], re[kPer];  // CSR range of each of the thread's vertices (nnz < 2^31)
   float* row = S + (size_t)s * n;
 #pragma unroll
   for (int m = 0; m < kPer; ++m) {
     const int v = threadIdx.x + m * 1024;
     base[m] = (v < n && v > s) ? row[v] : 0.f;
+    rb[m] = v < n ? (int32_t)row_ptr[v] : 0;
+    re[m] = v < n ? (int32_t)row_ptr[v + 1] : 0;
     if (v < n) {
       delta[v] = base[m];
-      pr[v] = pred[(size_t)s * n + v];
+      pr[v] = (int16_t)pred[(size_t)s * n + v];  // -1: the source or not reached
+      depth[v] = v == s ? 0 : kUnknown;
+      parent[v] = 0;
     }
   }
-  for (int round = 0; round <= n; ++round) {
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int v = threadIdx.x + m * 1024;
+    if (v < n && pr[v] >= 0) parent[pr[v]] = 1;
+  }
+  // depth(v) = depth(pred(v)) + 1, one level per round
+  int height = 0;
+  for (int r = 1; r < n; ++r) {
     __syncthreads();
     if (threadIdx.x == 0) changed = 0;
     __syncthreads();
@@ -315,20 +334,36 @@ __global__ __launch_bounds__(1024) void k_tree_accum(const int64_t* __restrict__
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
       const int v = threadIdx.x + m * 1024;
-      if (v >= n) continue;
-      float x = base[m];
-      for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-        const int32_t c = col_idx[e];
-        if (pr[c] == v) x += delta[c];
-      }
-      if (x != delta[v]) {
-        delta[v] = x;
+      if (v >= n || depth[v] != kUnknown) continue;
+      const int p = pr[v];
+      if (p >= 0 && depth[p] == r - 1) {
+        depth[v] = (uint16_t)r;
         ch = true;
       }
     }
     if (ch) changed = 1;
     __syncthreads();
     if (!changed) break;
+    height = r;
+  }
+  // deepest level first: the children of a vertex at level L are at level L + 1
+  for (int L = height; L >= 0; --L) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int v = threadIdx.x + m * 1024;
+      if (v >= n || depth[v] != L || !parent[v]) continue;
+      float x = base[m];
+      for (int32_t e = rb[m]; e < re[m]; e += 8) {
+        int32_t cc[8];  // eight column loads in flight, then the sums in CSR order
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cc[q] = e + q < re[m] ? col_idx[e + q] : -1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (cc[q] >= 0 && pr[cc[q]] == v) x += delta[cc[q]];
+      }
+      delta[v] = x;
+    }
   }
   __syncthreads();
   for (int v = threadIdx.x; v < n; v += 1024) row[v] = delta[v];
