@@ -602,10 +602,30 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[7] += u[q];
   }
-  if (p.enumerate && threadIdx.x < kEnumCandidates) {
-    double t = 0.0;  // items in order
-    for (int b = 0; b < nsg; ++b) t += sgpart[(size_t)b * kEnumCandidates + threadIdx.x];
-    cand[threadIdx.x] = t;
+  if (p.enumerate) {
+    // 14 threads per candidate, each with eight independent sums over every
+    // 14th item (loads in flight); the partials are added in thread order
+    constexpr int kPerCand = 256 / kEnumCandidates;
+    __shared__ double cpart[kEnumCandidates][kPerCand];
+    const int c = threadIdx.x / kPerCand, j = threadIdx.x % kPerCand;
+    if (c < kEnumCandidates) {
+      double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int b = j; b < nsg; b += kPerCand * 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (b + q * kPerCand < nsg) u[q] += sgpart[(size_t)(b + q * kPerCand) * kEnumCandidates + c];
+      }
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += u[q];
+      cpart[c][j] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kEnumCandidates) {
+      double t = 0.0;
+      for (int q = 0; q < kPerCand; ++q) t += cpart[threadIdx.x][q];
+      cand[threadIdx.x] = t;
+    }
   }
   block_sum<8>(v, sh);
   if (threadIdx.x != 0) return;
