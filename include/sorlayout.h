@@ -98,7 +98,7 @@ typedef enum {
 
 #define SL_FLAG_SEPARATE_SAFEGUARD 8u  /* evaluate f(X~) - f(X^H) in its own pass over
                                           unordered pairs and the next force pass
-                                          after the decision.  Default (Jacobi
+                                          after the decision.  Default (either
                                           ordering, a safeguard to evaluate, no
                                           enumeration or stress trace): the
                                           safeguard is summed inside the next

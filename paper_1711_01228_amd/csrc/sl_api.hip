@@ -456,22 +456,26 @@ sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
   return SL_OK;
 }
 
+// The step tail with the safeguard in the next force pass: the update (X^H,
+// X~), the force at X~ with f(X~) - f(X^H) summed in, the decision, and the
+// force at X^H when X~ lost.  fpart then holds the force at X^{k+1}.
+sl_status enqueue_fused_tail(sl_plan* p, const LoopParams& lp, const sl_options* o) {
+  HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
+          "update kernel");
+  HIP_TRY(launch_force_sg(p->dim, lp, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart, p->sp, p->ps),
+          "fused force and safeguard kernel");
+  HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->sp.blocks_x * p->sp.slices, p->st, o->trace,
+                        p->ps),
+          "select kernel");
+  HIP_TRY(launch_force_cond(p->dim, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->sp, p->n_pad, p->ps),
+          "force kernel");
+  if (o->xtrace) HIP_TRY(launch_record(p->Xb, p->stride, p->st, o->xtrace, p->n, p->dim, p->ps), "record kernel");
+  return SL_OK;
+}
+
 sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* o) {
-  if (lp.fuse) {
-    // the force of X^k came from the previous iteration (or the pass before the loop)
-    HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
-            "update kernel");
-    HIP_TRY(launch_force_sg(p->dim, lp, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart, p->sp,
-                            p->ps),
-            "fused force and safeguard kernel");
-    HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->sp.blocks_x * p->sp.slices, p->st, o->trace,
-                          p->ps),
-            "select kernel");
-    HIP_TRY(launch_force_cond(p->dim, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->sp, p->n_pad, p->ps),
-            "force kernel");
-    if (o->xtrace) HIP_TRY(launch_record(p->Xb, p->stride, p->st, o->xtrace, p->n, p->dim, p->ps), "record kernel");
-    return SL_OK;
-  }
+  // fused: the force of X^k came from the previous iteration (or the pass before the loop)
+  if (lp.fuse) return enqueue_fused_tail(p, lp, o);
   sl_status s = enqueue_force(p, lp);
   if (s != SL_OK) return s;
   return enqueue_after_force(p, lp, o);
@@ -516,6 +520,8 @@ sl_status enqueue_cg_group(sl_plan* p, double itol, int imax) {
 
 // Algorithm 2 with the exact step: per iteration the force pass (r_0), the
 // solve in groups of kCgGroup steps until its stop flag, then the common tail.
+// With lp.fuse the force at X^k comes from the previous iteration's fused tail
+// (or the pass before the loop).
 sl_status run_exact(sl_plan* p, LoopParams lp, const sl_options* o, bool use_graph, int* inner_total) {
   sl_status s = ensure_exact(p);
   if (s != SL_OK) return s;
@@ -552,7 +558,7 @@ sl_status run_exact(sl_plan* p, LoopParams lp, const sl_options* o, bool use_gra
   const int max_groups = imax / kCgGroup + 2;
   *inner_total = 0;
   for (int k = 0; k < o->max_iter && !h->done; ++k) {
-    if ((s = enqueue_force(p, lp)) != SL_OK) return s;
+    if (!lp.fuse && (s = enqueue_force(p, lp)) != SL_OK) return s;
     HIP_TRY(launch_cg_init(p->dim, p->cg, p->fpart, p->sp.slices, p->W, p->comp, p->n, p->Xb, p->stride, p->st, p->cg_st,
                            p->cg_part, p->ps),
             "conjugate-gradient init kernel");
@@ -566,7 +572,7 @@ sl_status run_exact(sl_plan* p, LoopParams lp, const sl_options* o, bool use_gra
     }
     if (!stopped) return fail(SL_EDEVICE, "the conjugate-gradient solve did not reach its stop flag");
     *inner_total += hc->iters;
-    if ((s = enqueue_after_force(p, lp, o)) != SL_OK) return s;
+    if ((s = lp.fuse ? enqueue_fused_tail(p, lp, o) : enqueue_after_force(p, lp, o)) != SL_OK) return s;
     HIP_TRY(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->ps), "state download");
     HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
   }
@@ -729,9 +735,9 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   lp.enumerate = o->strategy == SL_OMEGA_ENUM ? 1 : 0;
   lp.omega_vertex = o->omega_vertex;
   lp.omega_sched = nullptr;
-  // the safeguard rides on the next force pass: Jacobi step, a safeguard to
-  // evaluate, no enumeration, stress trace or unordered-pair pass
-  lp.fuse = (o->ordering == SL_ORDER_JACOBI && lp.safeguard && !lp.enumerate && !lp.stress &&
+  // the safeguard rides on the next force pass: a safeguard to evaluate, no
+  // enumeration, stress trace or unordered-pair pass
+  lp.fuse = (lp.safeguard && !lp.enumerate && !lp.stress &&
              !(o->flags & (SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD)) &&
              (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->omega_vertex) && p->n > 1)
                 ? 1

@@ -7,7 +7,8 @@ differ in formula (r^H from r~^2 - m) and order: f(X~) - f(X^H) agrees to
 1e-3 relative, or 1e-6 of the largest |f(X~) - f(X^H)| of the run.  Cases:
 fixed omega with many rejections (the force at X^H runs again), a schedule
 with factors of 1 (iterations without extrapolation), per-vertex factors, 3-D,
-an edge-length plan, ragged sizes, with and without captured graphs.
+an edge-length plan, ragged sizes, with and without captured graphs, and the
+exact step.
 """
 import numpy as np
 import pytest
@@ -52,6 +53,11 @@ CASES = {
     "path5": (lambda: (inputs.to_csr(5, [(0, 1), (1, 2), (2, 3), (3, 4)]), None), 2,
               {"omega": 1.8, "tol": 0.0, "max_iter": 30}),
     "two_vertices": (lambda: (inputs.to_csr(2, [(0, 1)]), None), 3, {"omega": 1.5, "tol": 0.0, "max_iter": 12}),
+    # the exact step (eq. 5 by conjugate gradients) with the safeguard in the next force pass
+    "grid16_exact_w25": (lambda: inputs.grid16(3), 2, {"omega": 2.5, "tol": 0.0, "max_iter": 25,
+                                                      "ordering": "exact"}),
+    "er1000_exact_3d": (lambda: (inputs.erdos_renyi(1000, 3000, 7), None), 3, {"omega": 2.0, "tol": 0.0,
+                                                                             "max_iter": 12, "ordering": "exact"}),
 }
 
 
@@ -67,6 +73,8 @@ def test_fused_safeguard_matches_separate(name):
     with b.Plan(g, dim) as plan:
         Xa, ta, Xb, tb = _both(plan, X0, **kw)
     _check(Xa, ta, Xb, tb)
+    if name == "grid16_exact_w25":
+        assert ta["rejected"] >= 1  # the force at X^H ran again before the next solve
     if name == "grid16_w4":
         assert ta["rejected"] >= 5  # the force at X^H ran again (the oracle rejects 14 of 40)
 
