@@ -2,10 +2,11 @@
 n = 65,536, m = 3, 2-D, FP32, on one MI355X.
 
 A step is one iteration of Algorithm 2 at omega = 1.5 with the safeguard on:
-the Jacobi update and extrapolation, one all-pairs pass that takes the next
-force at X~ and sums the safeguard f(X~) - f(X^H) over the upper triangle,
-the select/termination kernel, and the force pass at X^H when X~ was rejected
-(the first force, at X^0, is inside the timed run).  The plan (distances and
+the Jacobi update and extrapolation, one pass over every vertex pair that takes
+the next force at X~ and sums the safeguard f(X~) - f(X^H) (in 2-D once per
+unordered pair, the library's default there), the select/termination kernel,
+and the force pass at X^H when X~ was rejected (the first force, at X^0, is
+inside the timed run).  The plan (distances and
 weights) is built before the timed region, so inputs are resident in HBM.
 
 value = n (n - 1) * steps / seconds   (pair interactions of the force pass)
@@ -14,8 +15,9 @@ Also reported: time-to-converge (res <= 1e-3) for omega = 1 and omega in
 {1.5, 2, 2.5, 3} from the same start (speedup quoted at omega = 2.5, the
 paper's w_p = 1.5), the same for the relaxation strategies of Sec. 5.2
 (probabilistic, enumerating, per-vertex factors) and for the exact step H
-(eq. 5 solved by conjugate gradients), the roofline of the fused force + safeguard kernel
-(HIP-event time) beside the plain force kernel of omega = 1 runs, and
+(eq. 5 solved by conjugate gradients), the roofline of the fused force +
+safeguard pass (HIP-event time) beside the plain force pass of omega = 1 runs
+and the other kind of pass, and
 the FP64 oracle's pair rate on a sample of rows on the host cores.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dim 2] [--quick]
@@ -34,35 +36,40 @@ METRIC = "pair-interactions/s + time-to-converge (SOR-ω vs ω=1) at n=65,536, 1
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed-FMA issue)
 PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 FLOPS_PER_PAIR = {2: 12, 3: 17}  # algorithmic flops of one ordered pair of the force pass
-# the opt-in pass evaluates each unordered pair once: differences, r^2, c, and
-# c [x - ref, 1] accumulated for both ends (2-D: 2 + 3 + 2 + 2 * 6; 3-D: 3 + 5 + 2 + 2 * 8)
-FLOPS_PER_UNORDERED_PAIR = {2: 19, 3: 26}
 # safeguard share of one unordered pair in the fused pass, beyond the force terms:
 # e (DIM), 2t - e (DIM fma), m (1 + 2 (DIM - 1)), r~^2 - m, sqrt, s (fma), rcp,
 # (2/d) / s + 1/d^2 (fma), times m, sum (2-D: 2 + 4 + 3 + 1 + 1 + 2 + 1 + 2 + 1 + 1)
 SG_FLOPS_PER_UNORDERED_PAIR = {2: 18, 3: 23}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_safeguard_ba65536_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1711_01228_amd", "csrc", "sl_kernels.hip")
+# the library's default force pass: once per unordered pair in 2-D, over every
+# ordered pair in 3-D (where it is the faster one)
+SYM_DEFAULT = {2: True, 3: False}
+CSRC = os.path.join(ROOT, "paper_1711_01228_amd", "csrc")
+# committed rocprofv3 traffic of the dominant kernel, with the source it was taken on
+TRAFFIC = {True: (os.path.join(ROOT, "profiles", "force_safeguard_sym_ba65536_traffic.json"),
+                  os.path.join(CSRC, "sl_sym.hip")),
+           False: (os.path.join(ROOT, "profiles", "force_safeguard_ba65536_traffic.json"),
+                   os.path.join(CSRC, "sl_kernels.hip"))}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_hash(path):
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(dim):
-    """HBM bytes per force-pass launch from committed rocprofv3 counters, if they
-    were taken on the current kernel source."""
+def measured_traffic(dim, sym):
+    """HBM bytes per launch of the fused pass from committed rocprofv3 counters,
+    if they were taken on the current kernel source."""
+    path, src = TRAFFIC[sym]
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha") != kernel_hash() or rec.get("dim") != dim:
+    if rec.get("kernel_sha") != kernel_hash(src) or rec.get("dim") != dim:
         return None
     return rec.get("bytes_per_launch")
 
@@ -373,30 +380,37 @@ def main():
     log("timed: %d steps %.3f s wall (%.3f s device), %.4g pair-interactions/s" % (args.steps, wall,
                                                                                    info["run_ms"] / 1e3, value))
 
-    # ---- roofline of the dominant kernel: the fused force + safeguard pass
-    # (HIP events on the kernels' stream); the plain force pass beside it
+    # ---- roofline of the dominant kernel: the fused force + safeguard pass of
+    # the default kind (HIP events on the kernels' stream); the force pass of
+    # omega = 1 iterations and the other kind beside it
     ms = plan.profile(Xdev0, omega=args.omega, reps=5)
-    t_fs = ms["force_safeguard"] * 1e-3
+    sym = SYM_DEFAULT[dim]
+    t_fs = (ms["force_safeguard_sym"] if sym else ms["force_safeguard"]) * 1e-3
     flops = FLOPS_PER_PAIR[dim] * pairs + SG_FLOPS_PER_UNORDERED_PAIR[dim] * pairs / 2
     achieved = flops / t_fs / 1e12
-    traffic = measured_traffic(dim)
-    t_force, t_sym = ms["force"] * 1e-3, ms["force_sym"] * 1e-3
+    t_force = (ms["force_sym"] if sym else ms["force"]) * 1e-3
     a_force = FLOPS_PER_PAIR[dim] * pairs / t_force / 1e12
+    abytes = float(n) * (n - 1) / 2 if sym else float(n) * n  # d read once per unordered / ordered pair
+    other = {"kernel": "k_force_sg (fused) and k_force over every ordered pair" if sym else
+             "k_force_sym<2, true> / <2, false> + k_sym_reduce over unordered pairs",
+             "fused_ms": round(ms["force_safeguard"] if sym else ms["force_safeguard_sym"], 4),
+             "force_ms": round(ms["force"] if sym else ms["force_sym"], 4)}
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_force_sg", "kernel_ms": round(ms["force_safeguard"], 4),
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dim, sym),
+                "kernel": ("k_force_sym<2, true> + k_sym_reduce<2> (unordered pairs)" if sym else
+                           "k_force_sg (ordered pairs)"),
+                "kernel_ms": round(t_fs * 1e3, 4),
                 "flops_per_launch": flops,
                 "flops_per_unit": {"ordered_pair_force": FLOPS_PER_PAIR[dim],
                                    "unordered_pair_safeguard": SG_FLOPS_PER_UNORDERED_PAIR[dim]},
-                "algorithmic_bytes_per_launch": float(n) * n,
-                "hbm_GBps_algorithmic": round(float(n) * n / t_fs / 1e9, 1),
-                "force_pass": {"kernel": "k_force (omega = 1 iterations; after a rejection)",
-                               "kernel_ms": round(ms["force"], 4), "TFLOPs": round(a_force, 3),
+                "algorithmic_bytes_per_launch": abytes,
+                "hbm_GBps_algorithmic": round(abytes / t_fs / 1e9, 1),
+                "force_pass": {"kernel": ("k_force_sym<2, false> + k_sym_reduce<2>" if sym else "k_force") +
+                               " (omega = 1 iterations; after a rejection)",
+                               "kernel_ms": round(t_force * 1e3, 4), "TFLOPs": round(a_force, 3),
                                "frac": round(a_force / PEAK_FP32_TFLOPS, 4)},
+                "other_kind": other,
                 "separate_passes_ms": round(ms["force"] + ms["safeguard"], 4),
-                "unordered_pass": {"kernel": "k_force_sym + k_sym_reduce (opt-in)", "kernel_ms": round(ms["force_sym"], 4),
-                                   "TFLOPs": round(FLOPS_PER_UNORDERED_PAIR[dim] * pairs / 2 / t_sym / 1e12, 3)
-                                   if t_sym > 0 else None},
                 "step_kernel_ms": {k: round(v, 4) for k, v in ms.items()},
                 "measured_ceilings": measured_ceilings()}
     roofline["frac_of_measured_fma"] = round(achieved / roofline["measured_ceilings"]["fp32_fma_TFLOPs"], 4)

@@ -87,15 +87,17 @@ typedef enum {
 #define SL_FLAG_TRACE_STRESS 1u  /* evaluate f(X^k) every iteration into trace[4]  */
 #define SL_FLAG_NO_GRAPH 2u      /* launch kernels one by one instead of replaying a
                                     captured HIP graph of `check_every` iterations */
-#define SL_FLAG_SYM_FORCE 4u     /* hop-count plans, SL_ORDER_JACOBI, no stress trace:
-                                    evaluate the force pass once per unordered pair
-                                    (F_j takes -c_ij (x_i - x_j), Newton's third law),
-                                    accumulating on the matrix cores; the same sums in
-                                    another order.  The first such run allocates an
-                                    upper-triangle copy of d (about n^2 / 2 bytes).
-                                    Otherwise SL_ENOTSUP.  Default: every ordered pair
-                                    from its row end, which is faster on gfx950     */
-
+#define SL_FLAG_SYM_FORCE 4u     /* evaluate the force pass once per unordered pair
+                                    (F_j takes -c_ij (x_i - x_j), Newton's third law;
+                                    the same sums in another order).  Hop-count plans,
+                                    SL_ORDER_JACOBI, no stress trace; otherwise
+                                    SL_ENOTSUP.  The default for 2-D hop-count plans
+                                    with the Jacobi step and no stress trace; the
+                                    first such run allocates the pass's partial sums */
+#define SL_FLAG_ORDERED_FORCE 16u /* evaluate the force pass over every ordered pair
+                                    from its row end (the default for 3-D, edge-length
+                                    plans, the exact step and stress traces).  Not
+                                    with SL_FLAG_SYM_FORCE (SL_EINVAL)                */
 #define SL_FLAG_SEPARATE_SAFEGUARD 8u  /* evaluate f(X~) - f(X^H) in its own pass over
                                           unordered pairs and the next force pass
                                           after the decision.  Default (either
@@ -239,7 +241,9 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  *         edge-length plans)
  *   ms[6] the force pass at X~ with the safeguard summed in (the pass that
  *         replaces ms[0] + ms[2] in an iteration that extrapolates)
- * ms holds 7 doubles.
+ *   ms[7] the same over unordered pairs with its reduction kernel
+ *         (SL_FLAG_SYM_FORCE; 0 for edge-length plans)
+ * ms holds 8 doubles.
  * For profilers and benchmarks; the iterate buffers of the plan are left in an
  * unspecified state (a later sl_plan_run starts from its own X). */
 sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,

@@ -23,6 +23,7 @@ SL_FLAG_TRACE_STRESS = 1
 SL_FLAG_NO_GRAPH = 2
 SL_FLAG_SYM_FORCE = 4
 SL_FLAG_SEPARATE_SAFEGUARD = 8
+SL_FLAG_ORDERED_FORCE = 16
 SL_OMEGA_FIXED, SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM = 0, 1, 2
 SL_ORDER_JACOBI, SL_ORDER_EXACT = 0, 1
 ORDERINGS = {"jacobi": SL_ORDER_JACOBI, "exact": SL_ORDER_EXACT}
@@ -159,7 +160,7 @@ def graph_args(g) -> _GraphArgs:
 def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0,
                  trace_stress=False, use_graph=True, trace=None, xtrace=None, strategy=SL_OMEGA_FIXED,
                  omega_schedule=None, omega_vertex=None, ordering=SL_ORDER_JACOBI, inner_tol=0.0,
-                 inner_max_iter=0, sym_force=False, separate_safeguard=False) -> sl_options:
+                 inner_max_iter=0, sym_force=False, separate_safeguard=False, ordered_force=False) -> sl_options:
     """omega_schedule: host float64 array (kept alive by the caller);
     omega_vertex: device pointer (int) or None."""
     o = sl_options()
@@ -168,7 +169,7 @@ def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, chec
     o.safeguard, o.check_every = int(bool(safeguard)), int(check_every)
     o.flags = (SL_FLAG_TRACE_STRESS if trace_stress else 0) | (0 if use_graph else SL_FLAG_NO_GRAPH) | \
         (SL_FLAG_SYM_FORCE if sym_force else 0) | \
-        (SL_FLAG_SEPARATE_SAFEGUARD if separate_safeguard else 0)
+        (SL_FLAG_SEPARATE_SAFEGUARD if separate_safeguard else 0) | (SL_FLAG_ORDERED_FORCE if ordered_force else 0)
     o.trace = None if trace is None else int(trace)
     o.xtrace = None if xtrace is None else int(xtrace)
     o.strategy = int(strategy)
@@ -269,7 +270,7 @@ def sl_plan_weights(plan: int, n: int, stream=None) -> np.ndarray:
 
 
 def sl_plan_profile(plan: int, X_ptr: int, dim: int, omega: float, reps: int, stream=None) -> np.ndarray:
-    ms = np.zeros(7, dtype=np.float64)
+    ms = np.zeros(8, dtype=np.float64)
     _check(LIB.sl_plan_profile(plan, X_ptr, int(dim), float(omega), int(reps), _stream_handle(stream),
                                ms.ctypes.data))
     return ms
@@ -309,7 +310,7 @@ class Plan:
     def run(self, X, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0, trace=False,
             trace_stress=False, trace_positions=False, use_graph=True, stream=None, strategy="fixed",
             omega_schedule=None, omega_vertex=None, ordering="jacobi", inner_tol=0.0, inner_max_iter=0,
-            sym_force=False, separate_safeguard=False):
+            sym_force=False, separate_safeguard=False, ordered_force=False):
         """Run Algorithm 2 in place on the device tensor X (n x dim, float32).
 
         strategy: "fixed" (omega), "schedule" (omega_schedule, one classical
@@ -318,8 +319,9 @@ class Plan:
         of n classical factors (fixed strategy).  ordering: "jacobi" (one
         sweep of eq. 5) or "exact" (eq. 5 solved by conjugate gradients to
         inner_tol, at most inner_max_iter steps; 0 selects the defaults).
-        sym_force: evaluate the force pass once per unordered pair
-        (SL_FLAG_SYM_FORCE; hop-count plans, Jacobi ordering).
+        sym_force / ordered_force: evaluate the force pass once per unordered
+        pair (SL_FLAG_SYM_FORCE; hop-count plans, Jacobi ordering; the default
+        in 2-D) or over every ordered pair (SL_FLAG_ORDERED_FORCE).
         separate_safeguard: evaluate the safeguard in its own pass instead of
         inside the next force pass (SL_FLAG_SEPARATE_SAFEGUARD).
         Returns the sl_result fields; with ``trace`` also a ``trace`` array
@@ -344,7 +346,7 @@ class Plan:
         opt = make_options(self.dim, omega, tol, max_iter, safeguard, check_every, trace_stress, use_graph,
                            None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr(),
                            strat, sched, None if wv is None else wv.data_ptr(), ORDERINGS[ordering], inner_tol,
-                           inner_max_iter, sym_force, separate_safeguard)
+                           inner_max_iter, sym_force, separate_safeguard, ordered_force)
         info = sl_plan_run(self.handle, X.data_ptr(), opt, stream)
         k = info["iterations"]
         if tr is not None:
@@ -390,7 +392,7 @@ class Plan:
         """Average device ms of each kernel of one iteration (HIP events)."""
         ms = sl_plan_profile(self.handle, X.data_ptr(), self.dim, omega, reps, stream)
         return dict(zip(("force", "update", "safeguard", "select", "lw_matvec", "force_sym",
-                                  "force_safeguard"), ms.tolist()))
+                                  "force_safeguard", "force_safeguard_sym"), ms.tolist()))
 
     def close(self):
         if self.handle:

@@ -111,7 +111,8 @@ sl_status check_options(const sl_options* o) {
   if (!(o->tol >= 0.0)) return fail(SL_EINVAL, "tol = %g must be >= 0", o->tol);
   if (o->max_iter < 0) return fail(SL_EINVAL, "max_iter = %d is negative", o->max_iter);
   if (o->safeguard != 0 && o->safeguard != 1) return fail(SL_EINVAL, "safeguard must be 0 or 1");
-  if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH | SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD))
+  if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH | SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD |
+                   SL_FLAG_ORDERED_FORCE))
     return fail(SL_EINVAL, "unknown flag bits");
   if (o->strategy != SL_OMEGA_FIXED && o->strategy != SL_OMEGA_SCHEDULE && o->strategy != SL_OMEGA_ENUM)
     return fail(SL_EINVAL, "unknown relaxation strategy %d", o->strategy);
@@ -173,12 +174,11 @@ struct sl_plan {
   float* Sbuf = nullptr;        // n x n (edge-length plans)
   double* Gedge = nullptr;      // nnz
   // force pass over unordered pairs (hop-count plans)
-  uint8_t* dsym = nullptr;      // upper triangle of d in that pass's order
   int4* sym_items = nullptr;
   int32_t* sym_panel_items = nullptr;
   int nsym_items = 0;
-  double* Pi = nullptr;         // row partials: items x 512 x 4
-  float* Pj = nullptr;          // column partials: panels x n_pad x 4
+  double* Pi = nullptr;         // row partials: items x 512 x dim
+  float* Pj = nullptr;          // column partials: panels x n_pad x dim
   double* W = nullptr;          // n_pad
   float* Xb = nullptr;          // 3 iterate buffers
   float* Eb = nullptr;          // x~ - x^H, same format as one iterate buffer
@@ -228,7 +228,6 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->Dbar);
   (void)hipFree(p->Sbuf);
   (void)hipFree(p->Gedge);
-  (void)hipFree(p->dsym);
   (void)hipFree(p->sym_items);
   (void)hipFree(p->sym_panel_items);
   (void)hipFree(p->Pi);
@@ -402,39 +401,33 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
   return SL_OK;
 }
 
-// Buffers of the unordered-pair force pass (hop-count plans), made on first use:
-// the upper triangle of d in that pass's order (n_pad^2 / 2 bytes), its work
-// items and the row and column partial sums.
+// Buffers of the unordered-pair force pass (hop-count plans), made on first
+// use: its work items and the row and column partial sums.
 sl_status ensure_sym(sl_plan* p) {
-  if (p->dsym) return SL_OK;
+  if (p->sym_items) return SL_OK;
   if (!p->d || p->n <= 1) return fail(SL_ENOTSUP, "the unordered-pair force pass needs a hop-count plan with n > 1");
-  const SymSplit ss = make_sym_split(p->n_pad, 32);
-  uint8_t* dsym = nullptr;
+  const SymSplit ss = make_sym_split(p->n_pad, kSymChunk);
   int4* items = nullptr;
   int32_t* panel_items = nullptr;
   double* Pi = nullptr;
   float* Pj = nullptr;
-  hipError_t e = hipMalloc(&dsym, sym_bytes(p->n_pad));
-  if (e == hipSuccess) e = hipMalloc(&items, sizeof(int4) * ss.items.size());
+  hipError_t e = hipMalloc(&items, sizeof(int4) * ss.items.size());
   if (e == hipSuccess) e = hipMalloc(&panel_items, sizeof(int32_t) * ss.panel_items.size());
-  if (e == hipSuccess) e = hipMalloc(&Pi, sizeof(double) * ss.items.size() * 512 * 4);
-  if (e == hipSuccess) e = hipMalloc(&Pj, sizeof(float) * (size_t)ss.npanels * p->n_pad * 4);
+  if (e == hipSuccess) e = hipMalloc(&Pi, sizeof(double) * ss.items.size() * 512 * p->dim);
+  if (e == hipSuccess) e = hipMalloc(&Pj, sizeof(float) * (size_t)ss.npanels * p->n_pad * p->dim);
   if (e == hipSuccess)
     e = hipMemcpyAsync(items, ss.items.data(), sizeof(int4) * ss.items.size(), hipMemcpyHostToDevice, p->ps);
   if (e == hipSuccess)
     e = hipMemcpyAsync(panel_items, ss.panel_items.data(), sizeof(int32_t) * ss.panel_items.size(),
                        hipMemcpyHostToDevice, p->ps);
-  if (e == hipSuccess) e = launch_build_sym(p->d, dsym, p->n_pad, p->sp.ng, p->ps);
   if (e == hipSuccess) e = hipStreamSynchronize(p->ps);  // the split's host vectors are temporaries
   if (e != hipSuccess) {
-    (void)hipFree(dsym);
     (void)hipFree(items);
     (void)hipFree(panel_items);
     (void)hipFree(Pi);
     (void)hipFree(Pj);
     return hip_fail(e, "unordered-pair force pass setup");
   }
-  p->dsym = dsym;
   p->sym_items = items;
   p->sym_panel_items = panel_items;
   p->Pi = Pi;
@@ -445,7 +438,7 @@ sl_status ensure_sym(sl_plan* p) {
 
 sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
   if (lp.sym) {
-    HIP_TRY(launch_force_sym(p->dim, p->dsym, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+    HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
                              p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
             "symmetric force kernels");
     return SL_OK;
@@ -462,13 +455,25 @@ sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
 sl_status enqueue_fused_tail(sl_plan* p, const LoopParams& lp, const sl_options* o) {
   HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
           "update kernel");
-  HIP_TRY(launch_force_sg(p->dim, lp, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart, p->sp, p->ps),
-          "fused force and safeguard kernel");
-  HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->sp.blocks_x * p->sp.slices, p->st, o->trace,
-                        p->ps),
-          "select kernel");
-  HIP_TRY(launch_force_cond(p->dim, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->sp, p->n_pad, p->ps),
-          "force kernel");
+  if (lp.sym) {
+    HIP_TRY(launch_force_sym_sg(p->dim, lp, p->d, p->Xb, p->stride, p->Eb, p->st, p->sym_items, p->nsym_items,
+                                p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->n_pad, p->ps),
+            "symmetric fused force and safeguard kernels");
+    HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsym_items, p->st, o->trace, p->ps),
+            "select kernel");
+    HIP_TRY(launch_force_sym(p->dim, 1, p->d, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+                             p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
+            "symmetric force kernels");
+  } else {
+    HIP_TRY(launch_force_sg(p->dim, lp, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart, p->sp,
+                            p->ps),
+            "fused force and safeguard kernel");
+    HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->sp.blocks_x * p->sp.slices, p->st, o->trace,
+                          p->ps),
+            "select kernel");
+    HIP_TRY(launch_force_cond(p->dim, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->sp, p->n_pad, p->ps),
+            "force kernel");
+  }
   if (o->xtrace) HIP_TRY(launch_record(p->Xb, p->stride, p->st, o->xtrace, p->n, p->dim, p->ps), "record kernel");
   return SL_OK;
 }
@@ -677,8 +682,9 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess) e = hipMalloc(&p->spart, sizeof(double) * p->sp.slices * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(double) * 8 * p->nred);
   if (e == hipSuccess)
-    e = hipMalloc(&p->sgpart, sizeof(double) * std::max<size_t>((size_t)p->nsg * kEnumCandidates,
-                                                                (size_t)p->sp.blocks_x * p->sp.slices));
+    e = hipMalloc(&p->sgpart, sizeof(double) * std::max<size_t>({(size_t)p->nsg * kEnumCandidates,
+                                                                 (size_t)p->sp.blocks_x * p->sp.slices,
+                                                                 make_sym_split(p->n_pad, kSymChunk).items.size()}));
   if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
   if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
   if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
@@ -738,14 +744,20 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   // the safeguard rides on the next force pass: a safeguard to evaluate, no
   // enumeration, stress trace or unordered-pair pass
   lp.fuse = (lp.safeguard && !lp.enumerate && !lp.stress &&
-             !(o->flags & (SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD)) &&
+             !(o->flags & SL_FLAG_SEPARATE_SAFEGUARD) &&
              (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->omega_vertex) && p->n > 1)
                 ? 1
                 : 0;
+  if ((o->flags & SL_FLAG_SYM_FORCE) && (o->flags & SL_FLAG_ORDERED_FORCE))
+    return fail(SL_EINVAL, "SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE exclude each other");
   lp.sym = (o->flags & SL_FLAG_SYM_FORCE) ? 1 : 0;
+  if (lp.sym && (p->df || lp.stress || o->ordering != SL_ORDER_JACOBI))
+    return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: hop-count plans, Jacobi ordering, no stress trace");
+  // the default pass: once per unordered pair where it is the faster one
+  // (hop counts, 2-D, Jacobi step, no stress trace), else every ordered pair
+  if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !p->df && !lp.stress && o->ordering == SL_ORDER_JACOBI && p->dim == 2)
+    lp.sym = 1;
   if (lp.sym) {
-    if (p->df || lp.stress || o->ordering != SL_ORDER_JACOBI)
-      return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: hop-count plans, Jacobi ordering, no stress trace");
     if (p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
     if (p->n <= 1) lp.sym = 0;
     else lp.slices = 1;
@@ -922,7 +934,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   if (!(std::isfinite(omega) && omega > 0.0 && omega <= 16.0)) return fail(SL_EINVAL, "omega outside (0, 16]");
   sl_status s = join_from(p, (hipStream_t)stream);
   if (s != SL_OK) return s;
-  for (int k = 0; k < 7; ++k) ms[k] = 0.0;
+  for (int k = 0; k < 8; ++k) ms[k] = 0.0;
   if (p->n <= 1) return SL_OK;
   if (!p->df && (s = ensure_exact(p)) != SL_OK) return s;  // the L^W matvec exists for hop-count plans
   LoopParams lp{};
@@ -937,7 +949,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   lp.safeguard = 1;
   lp.stress = 0;
   lp.sym = 0;  // the force pass sl_plan_run uses by default
-  if (!p->df && (s = ensure_sym(p)) != SL_OK) return s;  // for ms[5]
+  if (!p->df && (s = ensure_sym(p)) != SL_OK) return s;  // for ms[5] and ms[7]
   HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
   DevState* h = p->host_st;
   std::memset(h, 0, sizeof(DevState));
@@ -946,8 +958,8 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   LoopParams lpf = lp;  // the fused pass, extrapolating with omega
   lpf.fuse = 1;
   lpf.safeguard = 1;
-  for (int which = 0; which < 7; ++which) {
-    if ((which == 4 || which == 5) && p->df) continue;
+  for (int which = 0; which < 8; ++which) {
+    if ((which == 4 || which == 5 || which == 7) && p->df) continue;
     if (which == 4) {  // a solver state from the current placement: r_0, z
       HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                            p->ps), "force kernel");
@@ -972,9 +984,15 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                   "fused force and safeguard kernel");
           break;
         case 5:
-          HIP_TRY(launch_force_sym(p->dim, p->dsym, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+          HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
                                    p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
                   "symmetric force kernels");
+          break;
+        case 7:
+          HIP_TRY(launch_force_sym_sg(p->dim, lpf, p->d, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+                                      p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->n_pad,
+                                      p->ps),
+                  "symmetric fused force and safeguard kernels");
           break;
         case 1:
           HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red,
@@ -1134,6 +1152,11 @@ LoopParams unroll_params(const sl_plan* p, double omega, int safeguard) {
   // the safeguard rides on the next force pass; a run (or a recomputed
   // segment) starts with one plain force pass
   lp.fuse = (safeguard && omega != 1.0 && p->n > 1) ? 1 : 0;
+  // the force pass sl_plan_run takes by default (its buffers made by ensure_sym)
+  if (!p->df && p->dim == 2 && p->n > 1 && p->sym_items) {
+    lp.sym = 1;
+    lp.slices = 1;
+  }
   return lp;
 }
 
@@ -1199,6 +1222,7 @@ sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt
   oo.trace = p->tape_trace;
   oo.xtrace = nullptr;
   oo.flags &= ~SL_FLAG_TRACE_STRESS;
+  if (!p->df && p->dim == 2 && p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
   const LoopParams lp = unroll_params(p, o->omega, o->safeguard);
   sl_result res{};
   res.plan_ms = p->plan_ms;
@@ -1282,6 +1306,7 @@ sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float*
                            p->ps),
             "tape download");
   HIP_TRY(launch_grad_in(G, p->gb, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
+  if (!p->df && p->dim == 2 && p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
   const LoopParams lp = unroll_params(p, p->tape_omega, p->tape_safeguard);
   sl_options oo;
   sl_default_options(&oo);

@@ -119,22 +119,28 @@ Split make_split(int n_pad);
 hipError_t launch_cg_step(int dim, const CgVectors& v, const uint8_t* d, const double* W, const int32_t* comp, int n,
                           const DevState* st, CgState* cg, double* part, double* qpart, const Split& sp, double tol,
                           int max_steps, hipStream_t s);
-// Force pass over unordered pairs with MFMA accumulation (sl_sym.hip): work
-// items (panel of 8 row strips, first and end column strip, item index), the
-// items of each panel contiguous.
+// Force pass over unordered pairs (sl_sym.hip): work items (panel of 8 row
+// strips, first and end column strip, item index), the items of each panel
+// contiguous.
 struct SymSplit {
   int nb = 0, npanels = 0;
   std::vector<int4> items;
   std::vector<int32_t> panel_items;  // npanels + 1 offsets into items
 };
 SymSplit make_sym_split(int n_pad, int chunk);
-size_t sym_bytes(int n_pad);  // the upper triangle of d in the symmetric pass's order
-hipError_t launch_build_sym(const uint8_t* d, uint8_t* dsym, int n_pad, int ng, hipStream_t s);
-// Writes F into force slice 0 of fpart (Pi: items x 512 x 4 doubles, Pj:
-// panels x n_pad x 4 floats of partial sums).
-hipError_t launch_force_sym(int dim, const uint8_t* dsym, const float* Xb, size_t stride, const DevState* st,
+constexpr int kSymChunk = 32;  // column strips per work item
+// Writes F into force slice 0 of fpart (Pi: items x 512 x dim doubles, Pj:
+// panels x n_pad x dim floats of partial sums); cond: only when the state asks
+// for the force again (after a rejection).
+hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* Xb, size_t stride, const DevState* st,
                             const int4* items, int nitems, const int32_t* panel_items, double* Pi, float* Pj,
                             double* fpart, int n_pad, hipStream_t s);
+// The same pass at X~ with the safeguard summed in (one double per item into
+// sgpart), as launch_force_sg.
+hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* Xb, size_t stride,
+                               const float* Eb, const DevState* st, const int4* items, int nitems,
+                               const int32_t* panel_items, double* Pi, float* Pj, double* sgpart, double* fpart,
+                               int n_pad, hipStream_t s);
 // One application of L^W to p (also used by the profiler).
 hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double* W, const DevState* st, CgState* cg,
                      double* qpart, double* pqrec, const Split& sp, hipStream_t s);

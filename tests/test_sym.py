@@ -1,11 +1,12 @@
-"""The force pass over unordered pairs (MFMA accumulation) against the pass
-over all ordered pairs: the same sums in another order and form.
+"""The force pass over unordered pairs against the pass over all ordered
+pairs: the same sums in another order.
 
-One Jacobi step from the same start: max |x^sym - x^direct| <= 2e-6 * diam
-(both sum FP32 pair terms; the unordered pass forms F as (x_i - ref) S_i -
-sum_j c_ij (x_j - ref) from FP32 partial sums).  Ragged sizes (n_pad not a
-multiple of the 512-row panel), tiny graphs, 2-D and 3-D.  The unordered pass
-is opt-in (SL_FLAG_SYM_FORCE); every other GPU test runs the default pass.
+One Jacobi step from the same start: max |x^sym - x^ordered| <= 2e-6 * diam
+(both sum FP32 pair terms; the unordered pass adds each column's terms over
+512 rows in FP32 before FP64).  Ragged sizes (n_pad not a multiple of the
+512-row panel), tiny graphs, 2-D and 3-D.  The unordered pass is the default
+in 2-D (hop counts, Jacobi step, no stress trace); SL_FLAG_SYM_FORCE and
+SL_FLAG_ORDERED_FORCE pick either pass.
 """
 import numpy as np
 import pytest
@@ -47,13 +48,13 @@ def test_unordered_pass_matches_ordered_pass(name, dim):
     with b.Plan(g, dim) as plan:
         Xs, Xd = dev(X0), dev(X0)
         plan.run(Xs, omega=1.0, tol=0.0, max_iter=1, sym_force=True)
-        plan.run(Xd, omega=1.0, tol=0.0, max_iter=1)
+        plan.run(Xd, omega=1.0, tol=0.0, max_iter=1, ordered_force=True)
         err = np.abs(Xs.cpu().numpy().astype(np.float64) - Xd.cpu().numpy()).max()
         assert err <= 2e-6 * diam(X0), err
         # a few steps with extrapolation and the safeguard stay together too
         Xs, Xd = dev(X0), dev(X0)
         ts = plan.run(Xs, omega=1.5, tol=0.0, max_iter=10, trace=True, sym_force=True)["trace"]
-        td = plan.run(Xd, omega=1.5, tol=0.0, max_iter=10, trace=True)["trace"]
+        td = plan.run(Xd, omega=1.5, tol=0.0, max_iter=10, trace=True, ordered_force=True)["trace"]
         if np.array_equal(ts[:, 1], td[:, 1]):
             assert np.abs(Xs.cpu().numpy() - Xd.cpu().numpy()).max() <= 1e-5 * diam(Xd.cpu().numpy())
 
@@ -87,3 +88,21 @@ def test_unordered_pass_is_refused_where_it_does_not_apply():
             plan.run(dev(X0), max_iter=2, sym_force=True)
         assert e.value.status == b.SL_ENOTSUP
         assert plan.profile(dev(X0), omega=1.5, reps=1)["force_sym"] == 0.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_default_pass_is_the_unordered_one_in_2d(dim):
+    from paper_1711_01228_amd import binding as b
+
+    g, _ = inputs.grid16(1)
+    X0 = inputs.uniform_positions(g.n, dim, seed=43, hi=16.0)
+    with b.Plan(g, dim) as plan:
+        outs = {}
+        for name, kw in (("default", {}), ("sym", {"sym_force": True}), ("ordered", {"ordered_force": True})):
+            X = dev(X0)
+            plan.run(X, omega=1.5, tol=0.0, max_iter=15, **kw)
+            outs[name] = X.cpu().numpy()
+        with pytest.raises(b.SlError) as e:
+            plan.run(dev(X0), max_iter=2, sym_force=True, ordered_force=True)
+        assert e.value.status == b.SL_EINVAL
+    np.testing.assert_array_equal(outs["default"], outs["sym" if dim == 2 else "ordered"])
