@@ -406,7 +406,7 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
 sl_status ensure_sym(sl_plan* p) {
   if (p->sym_items) return SL_OK;
   if (!p->d || p->n <= 1) return fail(SL_ENOTSUP, "the unordered-pair force pass needs a hop-count plan with n > 1");
-  const SymSplit ss = make_sym_split(p->n_pad, kSymChunk);
+  const SymSplit ss = make_sym_split(p->n_pad);
   int4* items = nullptr;
   int32_t* panel_items = nullptr;
   double* Pi = nullptr;
@@ -684,7 +684,7 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess)
     e = hipMalloc(&p->sgpart, sizeof(double) * std::max<size_t>({(size_t)p->nsg * kEnumCandidates,
                                                                  (size_t)p->sp.blocks_x * p->sp.slices,
-                                                                 make_sym_split(p->n_pad, kSymChunk).items.size()}));
+                                                                 make_sym_split(p->n_pad).items.size()}));
   if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
   if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
   if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);

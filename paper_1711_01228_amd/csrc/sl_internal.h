@@ -127,8 +127,7 @@ struct SymSplit {
   std::vector<int4> items;
   std::vector<int32_t> panel_items;  // npanels + 1 offsets into items
 };
-SymSplit make_sym_split(int n_pad, int chunk);
-constexpr int kSymChunk = 32;  // column strips per work item
+SymSplit make_sym_split(int n_pad);
 // Writes F into force slice 0 of fpart (Pi: items x 512 x dim doubles, Pj:
 // panels x n_pad x dim floats of partial sums); cond: only when the state asks
 // for the force again (after a rejection).
