@@ -40,9 +40,13 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}  # algorithmic flops of one ordered pair of the 
 # e (DIM), 2t - e (DIM fma), m (1 + 2 (DIM - 1)), r~^2 - m, sqrt, s (fma), rcp,
 # (2/d) / s + 1/d^2 (fma), times m, sum (2-D: 2 + 4 + 3 + 1 + 1 + 2 + 1 + 2 + 1 + 1)
 SG_FLOPS_PER_UNORDERED_PAIR = {2: 18, 3: 23}
-# the library's default force pass: once per unordered pair in 2-D, over every
-# ordered pair in 3-D (where it is the faster one)
-SYM_DEFAULT = {2: True, 3: False}
+# the library's default force pass: once per unordered pair in 2-D from a
+# padded size of 32768 vertices, else over every ordered pair (the faster one)
+SYM_MIN_N_PAD = 32768
+
+
+def sym_default(dim, n):
+    return dim == 2 and max(64, -(-n // 64) * 64) >= SYM_MIN_N_PAD
 CSRC = os.path.join(ROOT, "paper_1711_01228_amd", "csrc")
 # committed rocprofv3 traffic of the dominant kernel, with the source it was taken on
 TRAFFIC = {True: (os.path.join(ROOT, "profiles", "force_safeguard_sym_ba65536_traffic.json"),
@@ -60,16 +64,16 @@ def kernel_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(dim, sym):
+def measured_traffic(dim, sym, n):
     """HBM bytes per launch of the fused pass from committed rocprofv3 counters,
-    if they were taken on the current kernel source."""
+    if they were taken on the current kernel source and this workload."""
     path, src = TRAFFIC[sym]
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha") != kernel_hash(src) or rec.get("dim") != dim:
+    if rec.get("kernel_sha") != kernel_hash(src) or rec.get("dim") != dim or rec.get("n", n) != n:
         return None
     return rec.get("bytes_per_launch")
 
@@ -384,7 +388,7 @@ def main():
     # the default kind (HIP events on the kernels' stream); the force pass of
     # omega = 1 iterations and the other kind beside it
     ms = plan.profile(Xdev0, omega=args.omega, reps=5)
-    sym = SYM_DEFAULT[dim]
+    sym = sym_default(dim, n)
     t_fs = (ms["force_safeguard_sym"] if sym else ms["force_safeguard"]) * 1e-3
     flops = FLOPS_PER_PAIR[dim] * pairs + SG_FLOPS_PER_UNORDERED_PAIR[dim] * pairs / 2
     achieved = flops / t_fs / 1e12
@@ -396,7 +400,7 @@ def main():
              "fused_ms": round(ms["force_safeguard"] if sym else ms["force_safeguard_sym"], 4),
              "force_ms": round(ms["force"] if sym else ms["force_sym"], 4)}
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dim, sym),
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dim, sym, n),
                 "kernel": ("k_force_sym<2, true> + k_sym_reduce<2> (unordered pairs)" if sym else
                            "k_force_sg (ordered pairs)"),
                 "kernel_ms": round(t_fs * 1e3, 4),

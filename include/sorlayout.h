@@ -89,15 +89,16 @@ typedef enum {
                                     captured HIP graph of `check_every` iterations */
 #define SL_FLAG_SYM_FORCE 4u     /* evaluate the force pass once per unordered pair
                                     (F_j takes -c_ij (x_i - x_j), Newton's third law;
-                                    the same sums in another order).  Hop-count plans,
-                                    SL_ORDER_JACOBI, no stress trace; otherwise
-                                    SL_ENOTSUP.  The default for 2-D hop-count plans
-                                    with the Jacobi step and no stress trace; the
-                                    first such run allocates the pass's partial sums */
+                                    the same sums in another order).  SL_ORDER_JACOBI,
+                                    no stress trace; otherwise SL_ENOTSUP.  Hop-count
+                                    and edge-length plans.  The default in 2-D with
+                                    n_pad >= 32768, the Jacobi step and no stress
+                                    trace (the faster pass there); the first such run
+                                    allocates the pass's partial sums                */
 #define SL_FLAG_ORDERED_FORCE 16u /* evaluate the force pass over every ordered pair
-                                    from its row end (the default for 3-D, edge-length
-                                    plans, the exact step and stress traces).  Not
-                                    with SL_FLAG_SYM_FORCE (SL_EINVAL)                */
+                                    from its row end (the default in 3-D, in 2-D below
+                                    n_pad = 32768, for the exact step and for stress
+                                    traces).  Not with SL_FLAG_SYM_FORCE (SL_EINVAL) */
 #define SL_FLAG_SEPARATE_SAFEGUARD 8u  /* evaluate f(X~) - f(X^H) in its own pass over
                                           unordered pairs and the next force pass
                                           after the decision.  Default (either
@@ -237,12 +238,11 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  *   ms[4] one application of L^W (the all-pairs matvec of a conjugate-
  *         gradient step of SL_ORDER_EXACT; 0 for edge-length plans)
  *   ms[5] the force pass once per unordered pair with its reduction kernel
- *         (SL_FLAG_SYM_FORCE; allocates its buffers on first use; 0 for
- *         edge-length plans)
+ *         (SL_FLAG_SYM_FORCE; allocates its buffers on first use)
  *   ms[6] the force pass at X~ with the safeguard summed in (the pass that
  *         replaces ms[0] + ms[2] in an iteration that extrapolates)
  *   ms[7] the same over unordered pairs with its reduction kernel
- *         (SL_FLAG_SYM_FORCE; 0 for edge-length plans)
+ *         (SL_FLAG_SYM_FORCE)
  * ms holds 8 doubles.
  * For profilers and benchmarks; the iterate buffers of the plan are left in an
  * unspecified state (a later sl_plan_run starts from its own X). */

@@ -401,11 +401,16 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
   return SL_OK;
 }
 
-// Buffers of the unordered-pair force pass (hop-count plans), made on first
-// use: its work items and the row and column partial sums.
+// Buffers of the unordered-pair force pass, made on first use: its work items
+// and the row and column partial sums.
+// The force pass taken by default: once per unordered pair where that is the
+// faster one (2-D and n_pad >= kSymMinN, measured), else every ordered pair.
+constexpr int kSymMinN = 32768;
+bool sym_by_default(const sl_plan* p) { return p->dim == 2 && p->n_pad >= kSymMinN && p->n > 1; }
+
 sl_status ensure_sym(sl_plan* p) {
   if (p->sym_items) return SL_OK;
-  if (!p->d || p->n <= 1) return fail(SL_ENOTSUP, "the unordered-pair force pass needs a hop-count plan with n > 1");
+  if (p->n <= 1) return fail(SL_ENOTSUP, "the unordered-pair force pass needs n > 1");
   const SymSplit ss = make_sym_split(p->n_pad);
   int4* items = nullptr;
   int32_t* panel_items = nullptr;
@@ -438,7 +443,7 @@ sl_status ensure_sym(sl_plan* p) {
 
 sl_status enqueue_force(sl_plan* p, const LoopParams& lp) {
   if (lp.sym) {
-    HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+    HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->df, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
                              p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
             "symmetric force kernels");
     return SL_OK;
@@ -456,12 +461,12 @@ sl_status enqueue_fused_tail(sl_plan* p, const LoopParams& lp, const sl_options*
   HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
           "update kernel");
   if (lp.sym) {
-    HIP_TRY(launch_force_sym_sg(p->dim, lp, p->d, p->Xb, p->stride, p->Eb, p->st, p->sym_items, p->nsym_items,
+    HIP_TRY(launch_force_sym_sg(p->dim, lp, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items, p->nsym_items,
                                 p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->n_pad, p->ps),
             "symmetric fused force and safeguard kernels");
     HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsym_items, p->st, o->trace, p->ps),
             "select kernel");
-    HIP_TRY(launch_force_sym(p->dim, 1, p->d, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+    HIP_TRY(launch_force_sym(p->dim, 1, p->d, p->df, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
                              p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
             "symmetric force kernels");
   } else {
@@ -742,7 +747,7 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   lp.omega_vertex = o->omega_vertex;
   lp.omega_sched = nullptr;
   // the safeguard rides on the next force pass: a safeguard to evaluate, no
-  // enumeration, stress trace or unordered-pair pass
+  // enumeration or stress trace
   lp.fuse = (lp.safeguard && !lp.enumerate && !lp.stress &&
              !(o->flags & SL_FLAG_SEPARATE_SAFEGUARD) &&
              (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->omega_vertex) && p->n > 1)
@@ -751,11 +756,9 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   if ((o->flags & SL_FLAG_SYM_FORCE) && (o->flags & SL_FLAG_ORDERED_FORCE))
     return fail(SL_EINVAL, "SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE exclude each other");
   lp.sym = (o->flags & SL_FLAG_SYM_FORCE) ? 1 : 0;
-  if (lp.sym && (p->df || lp.stress || o->ordering != SL_ORDER_JACOBI))
-    return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: hop-count plans, Jacobi ordering, no stress trace");
-  // the default pass: once per unordered pair where it is the faster one
-  // (hop counts, 2-D, Jacobi step, no stress trace), else every ordered pair
-  if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !p->df && !lp.stress && o->ordering == SL_ORDER_JACOBI && p->dim == 2)
+  if (lp.sym && (lp.stress || o->ordering != SL_ORDER_JACOBI))
+    return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: Jacobi ordering, no stress trace");
+  if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !lp.stress && o->ordering == SL_ORDER_JACOBI && sym_by_default(p))
     lp.sym = 1;
   if (lp.sym) {
     if (p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
@@ -949,7 +952,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   lp.safeguard = 1;
   lp.stress = 0;
   lp.sym = 0;  // the force pass sl_plan_run uses by default
-  if (!p->df && (s = ensure_sym(p)) != SL_OK) return s;  // for ms[5] and ms[7]
+  if ((s = ensure_sym(p)) != SL_OK) return s;  // for ms[5] and ms[7]
   HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
   DevState* h = p->host_st;
   std::memset(h, 0, sizeof(DevState));
@@ -959,7 +962,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   lpf.fuse = 1;
   lpf.safeguard = 1;
   for (int which = 0; which < 8; ++which) {
-    if ((which == 4 || which == 5 || which == 7) && p->df) continue;
+    if (which == 4 && p->df) continue;
     if (which == 4) {  // a solver state from the current placement: r_0, z
       HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
                            p->ps), "force kernel");
@@ -984,12 +987,12 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                   "fused force and safeguard kernel");
           break;
         case 5:
-          HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+          HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->df, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
                                    p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
                   "symmetric force kernels");
           break;
         case 7:
-          HIP_TRY(launch_force_sym_sg(p->dim, lpf, p->d, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+          HIP_TRY(launch_force_sym_sg(p->dim, lpf, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
                                       p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->n_pad,
                                       p->ps),
                   "symmetric fused force and safeguard kernels");
@@ -1153,7 +1156,7 @@ LoopParams unroll_params(const sl_plan* p, double omega, int safeguard) {
   // segment) starts with one plain force pass
   lp.fuse = (safeguard && omega != 1.0 && p->n > 1) ? 1 : 0;
   // the force pass sl_plan_run takes by default (its buffers made by ensure_sym)
-  if (!p->df && p->dim == 2 && p->n > 1 && p->sym_items) {
+  if (sym_by_default(p) && p->sym_items) {
     lp.sym = 1;
     lp.slices = 1;
   }
@@ -1222,7 +1225,7 @@ sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt
   oo.trace = p->tape_trace;
   oo.xtrace = nullptr;
   oo.flags &= ~SL_FLAG_TRACE_STRESS;
-  if (!p->df && p->dim == 2 && p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
+  if (sym_by_default(p) && (s = ensure_sym(p)) != SL_OK) return s;
   const LoopParams lp = unroll_params(p, o->omega, o->safeguard);
   sl_result res{};
   res.plan_ms = p->plan_ms;
@@ -1306,7 +1309,7 @@ sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float*
                            p->ps),
             "tape download");
   HIP_TRY(launch_grad_in(G, p->gb, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
-  if (!p->df && p->dim == 2 && p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
+  if (sym_by_default(p) && (s = ensure_sym(p)) != SL_OK) return s;
   const LoopParams lp = unroll_params(p, p->tape_omega, p->tape_safeguard);
   sl_options oo;
   sl_default_options(&oo);

@@ -131,13 +131,13 @@ SymSplit make_sym_split(int n_pad);
 // Writes F into force slice 0 of fpart (Pi: items x 512 x dim doubles, Pj:
 // panels x n_pad x dim floats of partial sums); cond: only when the state asks
 // for the force again (after a rejection).
-hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* Xb, size_t stride, const DevState* st,
-                            const int4* items, int nitems, const int32_t* panel_items, double* Pi, float* Pj,
-                            double* fpart, int n_pad, hipStream_t s);
+hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                            const DevState* st, const int4* items, int nitems, const int32_t* panel_items, double* Pi,
+                            float* Pj, double* fpart, int n_pad, hipStream_t s);
 // The same pass at X~ with the safeguard summed in (one double per item into
 // sgpart), as launch_force_sg.
-hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* Xb, size_t stride,
-                               const float* Eb, const DevState* st, const int4* items, int nitems,
+hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
+                               size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
                                const int32_t* panel_items, double* Pi, float* Pj, double* sgpart, double* fpart,
                                int n_pad, hipStream_t s);
 // One application of L^W to p (also used by the profiler).

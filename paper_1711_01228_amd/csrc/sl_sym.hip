@@ -2,8 +2,11 @@
 //
 // F_i = sum_j c_ij (x_i - x_j) with c_ij = (1/d)(1/r) - 1/d^2 = c_ji, so each
 // unordered pair i < j gives p = c_ij (x_i - x_j) to row i and -p to row j.
-// A work item (one wave) is a panel of 8 row strips (512 rows) and a run of 24
-// column groups right of the panel's diagonal block.  Per column group of 16
+// Distances are hop-count bytes (weights from a table) or, for edge-length
+// plans, floats (1/d by the reciprocal instruction, as the direct pass does).
+// A work item (one wave) is a panel of 8 row strips (512 rows) and a run of up
+// to 24 column groups right of the panel's diagonal block (shorter runs for
+// small n, so that there are enough waves).  Per column group of 16
 // columns the wave walks the strips (lane = row, the tile-major chunks of d as
 // in the direct pass; pairs with j <= i masked where the group meets the
 // diagonal):
@@ -17,12 +20,14 @@
 // iteration without extrapolation).
 // The column totals go out once per (panel, column) as FP32, the row sums once
 // per (item, row) as FP64; k_sym_reduce forms
-//   F_i = sum over the items of i's panel of the row partials (item order)
-//       - sum over the panels 0 .. panel(i) of the column partials (panel order)
-// in FP64 into force slice 0.  Every order is fixed, so results are bitwise
-// repeatable.
+//   F_i = sum over the items of i's panel of the row partials
+//       - sum over the panels 0 .. panel(i) of the column partials
+// in FP64 into force slice 0 (16 lanes per vertex, each over a fixed stride of
+// the partials, then a fixed butterfly).  Every order is fixed, so results are
+// bitwise repeatable.
 #include "sl_device.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace sl {
@@ -31,7 +36,8 @@ namespace {
 
 constexpr int kPanel = 8;   // row strips per work item (512 rows)
 constexpr int kWaves = 4;   // work items (waves) per workgroup
-constexpr int kChunk = 24;  // column groups per work item (measured: 20-24 best, 32 and up 8-10% slower)
+constexpr int kChunk = 24;  // column groups per work item at most (measured: 20-24 best, 32 and up 8-10% slower)
+constexpr int kMinItems = 8192;  // work items (waves) wanted at least: 8 per SIMD
 
 typedef float vf16 __attribute__((ext_vector_type(16)));
 
@@ -64,8 +70,9 @@ __device__ __forceinline__ float reduce_scatter(VF R, int lane) {
   return t;
 }
 
-template <int DIM, bool SG>
-__global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d, const float* __restrict__ Xb,
+template <int DIM, bool SG, bool FD>
+__global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d, const float* __restrict__ df,
+                                                   const float* __restrict__ Xb,
                                                    size_t stride, const float* __restrict__ Eb,
                                                    const double* __restrict__ omega_sched, double omega_p,
                                                    int vertex_factors, int cond, const DevState* __restrict__ st,
@@ -117,21 +124,31 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
       constexpr bool MASK = decltype(mask_tag)::value;
       constexpr bool SAFE = decltype(safe_tag)::value;
       if (ra >= rb) return;
-      const uint4* __restrict__ chunks = reinterpret_cast<const uint4*>(
-          d + ((size_t)(panel * kPanel) * ng + g) * kTileBytes) + lane;  // strip r: + r ng 64
-      uint4 q = chunks[(size_t)ra * ng * 64];
+      using C = typename DChunkT<FD>::T;
+      C q = load_chunk<FD>(d, df, panel * kPanel + ra, ng, g, lane);
 #pragma unroll 1
       for (int r = ra; r < rb; ++r) {
         const int ilo = (panel * kPanel + r) * 64;
         // the next strip's chunk loads while this one computes (the last strip loads itself again)
-        const uint4 qn = chunks[(size_t)(r + 1 < rb ? r + 1 : r) * ng * 64];
+        const C qn = load_chunk<FD>(d, df, panel * kPanel + (r + 1 < rb ? r + 1 : r), ng, g, lane);
         const V xi = X[ilo + lane];
         V ei{};
         if constexpr (SAFE) ei = E[ilo + lane];
         float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
 #pragma unroll
         for (int k = 0; k < kColGroup; ++k) {
-          const float4 e4 = lut[byte_of(chunk_word(q, k), k & 3)];
+          float inv, w, l2;  // 1/d, 1/d^2, -2/d (0 where d = 0)
+          if constexpr (FD) {
+            const float dv = fchunk_at(q, k);
+            inv = dv > 0.f ? __builtin_amdgcn_rcpf(dv) : 0.f;
+            w = inv * inv;
+            l2 = -2.f * inv;
+          } else {
+            const float4 e4 = lut[byte_of(chunk_word(q, k), k & 3)];
+            inv = e4.x;
+            w = e4.y;
+            l2 = e4.z;
+          }
           const V p = xj[k];
           const float tx = xi.x - p.x, ty = xi.y - p.y;
           float r2 = fmaf(tx, tx, kTiny);
@@ -142,7 +159,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
             r2 = fmaf(tz, tz, r2);
           }
           const float rinv = __builtin_amdgcn_rsqf(r2);
-          float c = fmaf(e4.x, rinv, -e4.y);
+          float c = fmaf(inv, rinv, -w);
           if constexpr (MASK) {
             if (jlo + k <= ilo + lane) c = 0.f;
           }
@@ -165,7 +182,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
             }
             const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
             const float sum = fmaf(r2, rinv, rh);
-            float term = m * fmaf(e4.z, __builtin_amdgcn_rcpf(sum), e4.y);
+            float term = m * fmaf(l2, __builtin_amdgcn_rcpf(sum), w);
             if constexpr (MASK) {
               if (jlo + k <= ilo + lane) term = 0.f;
             }
@@ -209,51 +226,89 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
   }
 }
 
+// 16 lanes per vertex: lane t of a vertex's group sums the row partials of
+// items t, t + 16, ... and the column partials of panels t, t + 16, ... in
+// FP64; the 16 sums are then added by a fixed butterfly, so every order is fixed.
+constexpr int kReduceLanes = 16;
+
 template <int DIM>
 __global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ Pi, const float* __restrict__ Pj,
                                                     const int32_t* __restrict__ panel_items, int cond,
                                                     const DevState* __restrict__ st, double* __restrict__ fpart,
                                                     int n_pad) {
   if (st->done || (cond && !st->need_force)) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n_pad) return;
-  const int strip = i / 64, panel = strip / kPanel, row = i % (kPanel * 64);
+  const int i = (blockIdx.x * 256 + threadIdx.x) / kReduceLanes;  // whole lane groups share i
+  const int t = threadIdx.x % kReduceLanes;
+  const bool live = i < n_pad;
+  const int ii = live ? i : 0;
+  const int strip = ii / 64, panel = strip / kPanel, row = ii % (kPanel * 64);
   double acc[DIM];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
-  for (int q = panel_items[panel]; q < panel_items[panel + 1]; ++q) {
-    const double* p = Pi + ((size_t)q * kPanel * 64 + row) * DIM;
+  if (live) {
+    for (int q = panel_items[panel] + t; q < panel_items[panel + 1]; q += kReduceLanes) {
+      const double* p = Pi + ((size_t)q * kPanel * 64 + row) * DIM;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) acc[c] += p[c];
+      for (int c = 0; c < DIM; ++c) acc[c] += p[c];
+    }
+    for (int p = t; p <= panel; p += kReduceLanes) {
+      const float* col = Pj + ((size_t)p * n_pad + ii) * DIM;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) acc[c] -= (double)col[c];
+    }
   }
-  for (int p = 0; p <= panel; ++p) {
-    const float* col = Pj + ((size_t)p * n_pad + i) * DIM;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) acc[c] -= (double)col[c];
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int off = kReduceLanes / 2; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+  if (live && t == 0) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) fpart[(size_t)c * n_pad + i] = acc[c];
   }
-#pragma unroll
-  for (int c = 0; c < DIM; ++c) fpart[(size_t)c * n_pad + i] = acc[c];
 }
 
-template <int DIM, bool SG>
-void sym_launch(const LoopParams* lp, int cond, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
-                const DevState* st, const int4* items, int nitems, const int32_t* panel_items, double* Pi, float* Pj,
-                double* sgpart, double* fpart, int n_pad, hipStream_t s) {
+template <int DIM, bool SG, bool FD>
+void sym_launch(const LoopParams* lp, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                const float* Eb, const DevState* st, const int4* items, int nitems, const int32_t* panel_items,
+                double* Pi, float* Pj, double* sgpart, double* fpart, int n_pad, hipStream_t s) {
   const int nb = n_pad / 64, ng = n_pad / kColGroup;
-  k_force_sym<DIM, SG><<<(nitems + kWaves - 1) / kWaves, kWaves * 64, 0, s>>>(
-      d, Xb, stride, Eb, lp ? lp->omega_sched : nullptr, lp ? lp->omega_p : 0.0, lp && lp->omega_vertex ? 1 : 0,
+  k_force_sym<DIM, SG, FD><<<(nitems + kWaves - 1) / kWaves, kWaves * 64, 0, s>>>(
+      d, df, Xb, stride, Eb, lp ? lp->omega_sched : nullptr, lp ? lp->omega_p : 0.0, lp && lp->omega_vertex ? 1 : 0,
       cond, st, items, nitems, Pi, Pj, sgpart, nb, ng, n_pad);
-  k_sym_reduce<DIM><<<(n_pad + 255) / 256, 256, 0, s>>>(Pi, Pj, panel_items, cond, st, fpart, n_pad);
+  k_sym_reduce<DIM><<<(unsigned)(((size_t)n_pad * kReduceLanes + 255) / 256), 256, 0, s>>>(Pi, Pj, panel_items, cond,
+                                                                                           st, fpart, n_pad);
+}
+
+template <bool SG>
+void sym_dispatch(int dim, const LoopParams* lp, int cond, const uint8_t* d, const float* df, const float* Xb,
+                  size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
+                  const int32_t* panel_items, double* Pi, float* Pj, double* sgpart, double* fpart, int n_pad,
+                  hipStream_t s) {
+  if (dim == 2) {
+    if (df) sym_launch<2, SG, true>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                    fpart, n_pad, s);
+    else sym_launch<2, SG, false>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                  fpart, n_pad, s);
+  } else {
+    if (df) sym_launch<3, SG, true>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                    fpart, n_pad, s);
+    else sym_launch<3, SG, false>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                  fpart, n_pad, s);
+  }
 }
 
 }  // namespace
 
 SymSplit make_sym_split(int n_pad) {
-  const int chunk = kChunk;
   SymSplit sp;
   sp.nb = n_pad / 64;
   sp.npanels = (sp.nb + kPanel - 1) / kPanel;
   const int ng = n_pad / kColGroup;
+  // column groups right of each panel's diagonal block, over all panels; the
+  // items shorten below kChunk groups until there are kMinItems of them
+  long long groups = 0;
+  for (int p = 0; p < sp.npanels; ++p) groups += ng - p * kPanel * (64 / kColGroup);
+  const int chunk = (int)std::max<long long>(1, std::min<long long>(kChunk, groups / kMinItems));
   sp.panel_items.assign(sp.npanels + 1, 0);
   for (int p = 0; p < sp.npanels; ++p) {
     // the column groups right of the panel's first row: from its diagonal block on
@@ -266,26 +321,20 @@ SymSplit make_sym_split(int n_pad) {
   return sp;
 }
 
-hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* Xb, size_t stride, const DevState* st,
-                            const int4* items, int nitems, const int32_t* panel_items, double* Pi, float* Pj,
-                            double* fpart, int n_pad, hipStream_t s) {
-  if (dim == 2)
-    sym_launch<2, false>(nullptr, cond, d, Xb, stride, nullptr, st, items, nitems, panel_items, Pi, Pj, nullptr,
-                         fpart, n_pad, s);
-  else
-    sym_launch<3, false>(nullptr, cond, d, Xb, stride, nullptr, st, items, nitems, panel_items, Pi, Pj, nullptr,
-                         fpart, n_pad, s);
+hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+                            const DevState* st, const int4* items, int nitems, const int32_t* panel_items, double* Pi,
+                            float* Pj, double* fpart, int n_pad, hipStream_t s) {
+  sym_dispatch<false>(dim, nullptr, cond, d, df, Xb, stride, nullptr, st, items, nitems, panel_items, Pi, Pj, nullptr,
+                      fpart, n_pad, s);
   return hipGetLastError();
 }
 
-hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* Xb, size_t stride,
-                               const float* Eb, const DevState* st, const int4* items, int nitems,
+hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
+                               size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
                                const int32_t* panel_items, double* Pi, float* Pj, double* sgpart, double* fpart,
                                int n_pad, hipStream_t s) {
-  if (dim == 2)
-    sym_launch<2, true>(&lp, 0, d, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart, fpart, n_pad, s);
-  else
-    sym_launch<3, true>(&lp, 0, d, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart, fpart, n_pad, s);
+  sym_dispatch<true>(dim, &lp, 0, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart, fpart, n_pad,
+                     s);
   return hipGetLastError();
 }
 

@@ -61,15 +61,20 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("force", ["default", "sym"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_fused_safeguard_matches_separate(name):
+def test_fused_safeguard_matches_separate(name, force):
     from paper_1711_01228_amd import binding as b
 
     make, dim, kw = CASES[name]
+    if force == "sym":
+        if kw.get("ordering") == "exact":
+            pytest.skip("the unordered pass serves the Jacobi step only")
+        kw = dict(kw, sym_force=True)  # the force pass once per unordered pair, either dimension
     g, X0 = make()
     if X0 is None or dim != 2:
         X0 = inputs.uniform_positions(g.n, dim, seed=31, hi=float(np.sqrt(g.n)))
-    print("case", name, flush=True)
+    print("case", name, force, flush=True)
     with b.Plan(g, dim) as plan:
         Xa, ta, Xb, tb = _both(plan, X0, **kw)
     _check(Xa, ta, Xb, tb)
@@ -88,13 +93,15 @@ def test_fused_schedule_with_unit_factors_and_vertex_factors():
     K = 30
     sched = np.where(np.arange(K) % 3 == 0, 1.0, 1.8)  # every third iteration does not extrapolate
     print("case schedule", flush=True)
+    wv = torch.tensor(np.random.default_rng(3).uniform(1.0, 2.0, g.n), dtype=torch.float32, device="cuda")
     with b.Plan(g, 2) as plan:
-        Xa, ta, Xb, tb = _both(plan, X0, strategy="schedule", omega_schedule=sched, tol=0.0, max_iter=K)
-        _check(Xa, ta, Xb, tb)
-        assert np.all(ta["trace"][::3, 1] == -1.0)  # no safeguard on unit factors
-        wv = torch.tensor(np.random.default_rng(3).uniform(1.0, 2.0, g.n), dtype=torch.float32, device="cuda")
-        Xa, ta, Xb, tb = _both(plan, X0, omega_vertex=wv, tol=0.0, max_iter=K)
-        _check(Xa, ta, Xb, tb)
+        for sym in (False, True):
+            Xa, ta, Xb, tb = _both(plan, X0, strategy="schedule", omega_schedule=sched, tol=0.0, max_iter=K,
+                                   sym_force=sym)
+            _check(Xa, ta, Xb, tb)
+            assert np.all(ta["trace"][::3, 1] == -1.0)  # no safeguard on unit factors
+            Xa, ta, Xb, tb = _both(plan, X0, omega_vertex=wv, tol=0.0, max_iter=K, sym_force=sym)
+            _check(Xa, ta, Xb, tb)
 
 
 def test_fused_on_edge_length_plan():
@@ -106,8 +113,9 @@ def test_fused_on_edge_length_plan():
     X0 = inputs.uniform_positions(g.n, 2, 15, hi=8.0)
     print("case weighted", flush=True)
     with b.Plan(gw, 2) as plan:
-        Xa, ta, Xb, tb = _both(plan, X0, omega=1.6, tol=0.0, max_iter=30)
-    _check(Xa, ta, Xb, tb)
+        for sym in (False, True):
+            Xa, ta, Xb, tb = _both(plan, X0, omega=1.6, tol=0.0, max_iter=30, sym_force=sym)
+            _check(Xa, ta, Xb, tb)
 
 
 def test_fused_profile_slot():

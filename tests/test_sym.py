@@ -4,9 +4,9 @@ pairs: the same sums in another order.
 One Jacobi step from the same start: max |x^sym - x^ordered| <= 2e-6 * diam
 (both sum FP32 pair terms; the unordered pass adds each column's terms over
 512 rows in FP32 before FP64).  Ragged sizes (n_pad not a multiple of the
-512-row panel), tiny graphs, 2-D and 3-D.  The unordered pass is the default
-in 2-D (hop counts, Jacobi step, no stress trace); SL_FLAG_SYM_FORCE and
-SL_FLAG_ORDERED_FORCE pick either pass.
+512-row panel), tiny graphs, 2-D and 3-D, hop counts and edge lengths.  The
+unordered pass is the default in 2-D (Jacobi step, no stress trace);
+SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE pick either pass.
 """
 import numpy as np
 import pytest
@@ -82,27 +82,50 @@ def test_unordered_pass_is_refused_where_it_does_not_apply():
             with pytest.raises(b.SlError) as e:
                 plan.run(dev(X0), max_iter=2, sym_force=True, **kw)
             assert e.value.status == b.SL_ENOTSUP
-    gw = inputs.to_csr(g.n, g.edges(), np.ones(g.num_edges, dtype=np.float32))
-    with b.Plan(gw, 2) as plan:
-        with pytest.raises(b.SlError) as e:
-            plan.run(dev(X0), max_iter=2, sym_force=True)
-        assert e.value.status == b.SL_ENOTSUP
-        assert plan.profile(dev(X0), omega=1.5, reps=1)["force_sym"] == 0.0
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-def test_default_pass_is_the_unordered_one_in_2d(dim):
+def test_unordered_pass_on_edge_length_plan(dim):
+    # FP32 path lengths (edge lengths 1 +- 0.3): 1/d by the reciprocal instruction on both passes
     from paper_1711_01228_amd import binding as b
 
-    g, _ = inputs.grid16(1)
-    X0 = inputs.uniform_positions(g.n, dim, seed=43, hi=16.0)
+    g = inputs.largest_component(inputs.erdos_renyi(700, 2100, 17))
+    ln = (1.0 + np.random.default_rng(18).uniform(-0.3, 0.3, g.num_edges)).astype(np.float32)
+    gw = inputs.to_csr(g.n, g.edges(), ln)
+    X0 = inputs.uniform_positions(g.n, dim, seed=19, hi=float(np.sqrt(g.n)))
+    print("case weighted", g.n, dim, flush=True)
+    with b.Plan(gw, dim) as plan:
+        Xs, Xd = dev(X0), dev(X0)
+        plan.run(Xs, omega=1.0, tol=0.0, max_iter=1, sym_force=True)
+        plan.run(Xd, omega=1.0, tol=0.0, max_iter=1, ordered_force=True)
+        err = np.abs(Xs.cpu().numpy().astype(np.float64) - Xd.cpu().numpy()).max()
+        assert err <= 2e-6 * diam(X0), err
+        ms = plan.profile(dev(X0), omega=1.5, reps=1)
+        assert ms["force_sym"] > 0.0 and ms["force_safeguard_sym"] > 0.0
+
+
+DEFAULT_CASES = {
+    "grid16": lambda: inputs.grid_graph(16, 16),              # n_pad 256: the ordered pass is faster
+    "ba32768": lambda: inputs.barabasi_albert(32768, 3, 61),  # n_pad 32768: the unordered one in 2-D
+}
+
+
+@pytest.mark.parametrize("name,dim,expect", [
+    ("grid16", 2, "ordered"), ("grid16", 3, "ordered"), ("ba32768", 2, "sym"), ("ba32768", 3, "ordered"),
+])
+def test_default_force_pass_by_size_and_dim(name, dim, expect):
+    from paper_1711_01228_amd import binding as b
+
+    g = DEFAULT_CASES[name]()
+    X0 = inputs.uniform_positions(g.n, dim, seed=43, hi=float(np.sqrt(g.n)))
+    print("case default pass", name, dim, flush=True)
     with b.Plan(g, dim) as plan:
         outs = {}
-        for name, kw in (("default", {}), ("sym", {"sym_force": True}), ("ordered", {"ordered_force": True})):
+        for kind, kw in (("default", {}), ("sym", {"sym_force": True}), ("ordered", {"ordered_force": True})):
             X = dev(X0)
-            plan.run(X, omega=1.5, tol=0.0, max_iter=15, **kw)
-            outs[name] = X.cpu().numpy()
+            plan.run(X, omega=1.5, tol=0.0, max_iter=6, **kw)
+            outs[kind] = X.cpu().numpy()
         with pytest.raises(b.SlError) as e:
             plan.run(dev(X0), max_iter=2, sym_force=True, ordered_force=True)
         assert e.value.status == b.SL_EINVAL
-    np.testing.assert_array_equal(outs["default"], outs["sym" if dim == 2 else "ordered"])
+    np.testing.assert_array_equal(outs["default"], outs[expect])
