@@ -310,11 +310,37 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
   const int n = p->n;
   if (p->df) return build_weighted(p);
   if (n > 1 && g->nnz > 0) {
-    // source row of every CSR entry, for the edge-parallel gather
-    std::vector<int32_t> erow((size_t)g->nnz);
-    for (int v = 0; v < n; ++v)
-      for (int64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e) erow[(size_t)e] = v;
-    int32_t *er = nullptr, *ci = nullptr;
+    if (g->nnz > (int64_t)INT32_MAX) return fail(SL_ERANGE, "more than 2^31 - 1 CSR entries");
+    // source row of every CSR entry; the gather's runs (whole rows of at most
+    // bfs_run_entries() entries packed together, longer rows in chunks) and the
+    // rows no run owns (the longer ones and isolated vertices)
+    std::vector<int32_t> erow((size_t)g->nnz), rows;
+    std::vector<int2> runs;
+    const int run_max = bfs_run_entries();
+    int2 open_run = make_int2(0, 0);
+    for (int v = 0; v < n; ++v) {
+      const int64_t b0 = g->row_ptr[v], deg = g->row_ptr[v + 1] - b0;
+      for (int64_t e = b0; e < b0 + deg; ++e) erow[(size_t)e] = v;
+      if (deg == 0) {
+        rows.push_back(v);
+      } else if (deg <= run_max) {
+        if (open_run.y > 0 && open_run.y + deg > run_max) {
+          runs.push_back(open_run);
+          open_run.y = 0;
+        }
+        if (open_run.y == 0) open_run.x = (int)b0;
+        open_run.y += (int)deg;
+      } else {
+        if (open_run.y > 0) runs.push_back(open_run);
+        open_run.y = 0;
+        for (int64_t c = 0; c < deg; c += run_max)
+          runs.push_back(make_int2((int)(b0 + c), (int)std::min<int64_t>(run_max, deg - c) | bfs_run_chunk_flag()));
+        rows.push_back(v);
+      }
+    }
+    if (open_run.y > 0) runs.push_back(open_run);
+    int32_t *er = nullptr, *ci = nullptr, *rl = nullptr;
+    int2* rn = nullptr;
     uint64_t *slots = nullptr, *vis = nullptr, *acc = nullptr;
     int32_t* flag = nullptr;
     int32_t* hflag = nullptr;
@@ -323,6 +349,8 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       (void)hipStreamSynchronize(p->ps);
       (void)hipFree(er);
       (void)hipFree(ci);
+      (void)hipFree(rn);
+      (void)hipFree(rl);
       (void)hipFree(slots);
       (void)hipFree(vis);
       (void)hipFree(acc);
@@ -341,6 +369,12 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemcpyAsync(er, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess) e = hipMalloc(&rn, sizeof(int2) * std::max<size_t>(1, runs.size()));
+    if (e == hipSuccess) e = hipMalloc(&rl, sizeof(int32_t) * std::max<size_t>(1, rows.size()));
+    if (e == hipSuccess && !runs.empty())
+      e = hipMemcpyAsync(rn, runs.data(), sizeof(int2) * runs.size(), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess && !rows.empty())
+      e = hipMemcpyAsync(rl, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, p->ps);
     if (e != hipSuccess) {
       cleanup();
       return hip_fail(e, "distance buffers");
@@ -357,7 +391,8 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
         // one batch: as many levels as there are slots, then their distances
         const int l1 = std::min(l0 + nslots - 1, kBfsMaxLevel);
         for (int level = l0; level <= l1 && e == hipSuccess; ++level)
-          e = launch_bfs_level(er, ci, g->nnz, slots, acc, vis, n, level, flag, p->ps);
+          e = launch_bfs_level(rn, (int)runs.size(), er, ci, rl, (int)rows.size(), slots, acc, vis, n, level, flag,
+                               p->ps);
         // level 256 is not stored: it only tells whether a distance exceeds 255
         if (e == hipSuccess)
           e = launch_bfs_store(slots, flag, p->d, n, p->n_pad, base, l0, std::min(l1, kBfsMaxLevel - 1), p->ps);

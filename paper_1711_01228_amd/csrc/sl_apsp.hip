@@ -3,16 +3,19 @@
 // w_ij = d_ij^-2, and W_i = sum_j w_ij is the diagonal of L^W (Prop. 2.1).
 //
 // Breadth-first search from kBfsSources sources at once.  Word k of vertex v
-// (index 32 v + k) holds one bit per source base + 64 k + b.  Per level l:
-//   k_bfs_gather  acc(v) = OR of the level l-1 frontier words of v's
-//                 neighbours.  A lane group of 16 lanes reads one neighbour's
-//                 256 bytes per step (one 16-byte load a lane) and keeps the OR
-//                 of its current CSR row in registers; a row held whole by a
-//                 group is stored, a row split over groups is folded in by
-//                 64-bit atomic ORs.
-//   k_bfs_update  N_l = acc & ~visited (the sources that reach v first at
-//                 level l), visited |= N_l, acc = 0.  N_l is kept in level slot
-//                 l mod kBfsSlots and is also the next frontier.
+// (index 32 v + k) holds one bit per source base + 64 k + b.  Level l takes
+// the level l-1 frontier F and finds N_l(v) = (OR of F over v's neighbours)
+// & ~visited(v), the sources that reach v first at level l; visited |= N_l.
+// N_l is kept in level slot l mod kBfsSlots and is the next frontier.
+//   k_bfs_gather  one lane group of 16 lanes per run of at most 16 CSR
+//                 entries (built with the plan), each lane reading 16 bytes
+//                 of a neighbour's 256-byte frontier row per entry, all 16
+//                 loads in flight.  A run holds whole rows of degree <= 16:
+//                 the group owns them and writes N_l, visited and the slot
+//                 itself.  A run that is a 16-entry chunk of a longer row
+//                 folds its OR into acc by 64-bit atomic ORs.
+//   k_bfs_finish  the rows no run owns (longer rows and isolated vertices):
+//                 N_l from acc, acc = 0.
 // Every kBfsSlots levels, k_bfs_store turns the slots of that batch of levels
 // into distance bytes: it transposes a 64-row by 8-word block through LDS into
 // four bit planes of the level offset and one plane of "found", and writes
@@ -52,22 +55,42 @@ __global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ slot0, 
   acc[q] = 0ull;
 }
 
-__global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ erow,
-                                                    const int32_t* __restrict__ col_idx, int64_t nnz,
+// N_l for the two words (one 16-byte chunk q) a lane holds of a row.
+__device__ __forceinline__ void bfs_settle(ulonglong2* __restrict__ visited, ulonglong2* __restrict__ slot,
+                                          size_t q, uint64_t a0, uint64_t a1, int32_t* __restrict__ flags,
+                                          int level) {
+  ulonglong2 nw = make_ulonglong2(0ull, 0ull);
+  if (a0 | a1) {
+    const ulonglong2 vis = visited[q];
+    nw = make_ulonglong2(a0 & ~vis.x, a1 & ~vis.y);
+    if (nw.x | nw.y) {
+      visited[q] = make_ulonglong2(vis.x | nw.x, vis.y | nw.y);
+      flags[level] = 1;
+    }
+  }
+  slot[q] = nw;
+}
+
+// Run descriptor: x = first CSR entry, y = entry count (1..16) | kRunChunk
+// when the run is a chunk of a row longer than 16 entries.
+constexpr int kRunChunk = 1 << 16;
+
+__global__ __launch_bounds__(256) void k_bfs_gather(const int2* __restrict__ runs, int nruns,
+                                                    const int32_t* __restrict__ erow,
+                                                    const int32_t* __restrict__ col_idx,
                                                     const uint64_t* __restrict__ frontier,
                                                     unsigned long long* __restrict__ acc,
-                                                    const int32_t* __restrict__ flags, int level) {
+                                                    ulonglong2* __restrict__ visited, ulonglong2* __restrict__ slot,
+                                                    int32_t* __restrict__ flags, int level) {
   if (flags[level - 1] == 0) return;  // the search of this sweep has ended
   const int lane = threadIdx.x & 63, grp = lane / kGatherLanes, wl = lane % kGatherLanes;
-  const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;  // the wave's first CSR entry
-  if (e0 >= nnz) return;
-  // lane j holds entry e0 + j; lane group g walks entries e0 + 16 g .. + 15
-  const int64_t ej = e0 + lane;
-  const int vj = ej < nnz ? erow[ej] : -1;
-  const int uj = ej < nnz ? col_idx[ej] : 0;
-  const int64_t gs = e0 + (int64_t)kGatherRun * grp;
-  const int v_before = (gs > 0 && gs <= nnz) ? erow[gs - 1] : -1;
-  const int v_after = (gs + kGatherRun < nnz) ? erow[gs + kGatherRun] : -1;
+  const int r = (int)(blockIdx.x * 4 + (threadIdx.x >> 6)) * kGatherGroups + grp;  // this group's run
+  const int2 rd = r < nruns ? runs[r] : make_int2(0, 0);
+  const int cnt = rd.y & (kRunChunk - 1);
+  const bool chunk = (rd.y & kRunChunk) != 0;
+  // lane wl of the group holds entry rd.x + wl
+  const int vj = wl < cnt ? erow[rd.x + wl] : -1;
+  const int uj = wl < cnt ? col_idx[rd.x + wl] : 0;
   const ulonglong2* __restrict__ F = reinterpret_cast<const ulonglong2*>(frontier);
   ulonglong2 f[kGatherRun];
   int vv[kGatherRun];
@@ -78,51 +101,43 @@ __global__ __launch_bounds__(256) void k_bfs_gather(const int32_t* __restrict__ 
     f[j] = vv[j] >= 0 ? F[(size_t)u * (kBfsWords / 2) + wl] : make_ulonglong2(0ull, 0ull);
   }
   int cur = -1;
-  bool from_before = false;
   uint64_t a0 = 0ull, a1 = 0ull;
-  auto flush = [&](bool continues) {
-    unsigned long long* dst = acc + (size_t)cur * kBfsWords + 2 * wl;
-    if (!from_before && !continues) {  // the whole row is in this run: its only writer
-      if (a0 | a1) *reinterpret_cast<ulonglong2*>(dst) = make_ulonglong2(a0, a1);
-    } else {
+  auto flush = [&]() {
+    const size_t q = (size_t)cur * (kBfsWords / 2) + wl;
+    if (chunk) {  // part of a longer row: k_bfs_finish settles it
+      unsigned long long* dst = acc + 2 * q;
       if (a0) atomicOr(dst, (unsigned long long)a0);
       if (a1) atomicOr(dst + 1, (unsigned long long)a1);
+    } else {  // the whole row is in this run
+      bfs_settle(visited, slot, q, a0, a1, flags, level);
     }
   };
 #pragma unroll
   for (int j = 0; j < kGatherRun; ++j) {
     const int v = vv[j];
     if (v != cur) {
-      if (cur >= 0) flush(false);
+      if (cur >= 0) flush();
       cur = v;
-      from_before = j == 0 && v == v_before;
       a0 = a1 = 0ull;
     }
     a0 |= f[j].x;
     a1 |= f[j].y;
   }
-  if (cur >= 0) flush(cur == v_after);
+  if (cur >= 0) flush();
 }
 
-// Two words per thread.
-__global__ __launch_bounds__(256) void k_bfs_update(ulonglong2* __restrict__ acc, ulonglong2* __restrict__ visited,
-                                                    ulonglong2* __restrict__ slot, size_t pairs, int level,
-                                                    int32_t* __restrict__ flags) {
-  if (flags[level - 1] == 0) return;  // the search of this sweep has ended
-  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= pairs) return;
+// Rows no run owns: 16 threads (two words each) per listed row.
+__global__ __launch_bounds__(256) void k_bfs_finish(const int32_t* __restrict__ rows, int nrows,
+                                                    ulonglong2* __restrict__ acc, ulonglong2* __restrict__ visited,
+                                                    ulonglong2* __restrict__ slot, int32_t* __restrict__ flags,
+                                                    int level) {
+  if (flags[level - 1] == 0) return;
+  const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (size_t)nrows * (kBfsWords / 2)) return;
+  const size_t q = (size_t)rows[t / (kBfsWords / 2)] * (kBfsWords / 2) + t % (kBfsWords / 2);
   const ulonglong2 a = acc[q];
-  ulonglong2 nw = make_ulonglong2(0ull, 0ull);
-  if (a.x | a.y) {
-    const ulonglong2 vis = visited[q];
-    nw = make_ulonglong2(a.x & ~vis.x, a.y & ~vis.y);
-    acc[q] = make_ulonglong2(0ull, 0ull);
-    if (nw.x | nw.y) {
-      visited[q] = make_ulonglong2(vis.x | nw.x, vis.y | nw.y);
-      flags[level] = 1;
-    }
-  }
-  slot[q] = nw;
+  if (a.x | a.y) acc[q] = make_ulonglong2(0ull, 0ull);
+  bfs_settle(visited, slot, q, a.x, a.y, flags, level);
 }
 
 // Bit b of the nibble to bit 0 of byte b.
@@ -251,22 +266,28 @@ hipError_t launch_bfs_init(uint64_t* slot0, uint64_t* visited, uint64_t* acc, in
   return hipGetLastError();
 }
 
-hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* slots,
-                            uint64_t* acc, uint64_t* visited, int n, int level, int32_t* flags, hipStream_t s) {
+int bfs_run_entries() { return kGatherRun; }
+int bfs_run_chunk_flag() { return kRunChunk; }
+
+hipError_t launch_bfs_level(const int2* runs, int nruns, const int32_t* erow, const int32_t* col_idx,
+                            const int32_t* rows, int nrows, const uint64_t* slots, uint64_t* acc, uint64_t* visited,
+                            int n, int level, int32_t* flags, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t words = (size_t)n * kBfsWords;
   const uint64_t* frontier = slots + (size_t)((level - 1) % kBfsSlots) * words;
   uint64_t* out = const_cast<uint64_t*>(slots) + (size_t)(level % kBfsSlots) * words;
-  if (nnz > 0) {
-    const size_t waves = ((size_t)nnz + 63) / 64;
-    k_bfs_gather<<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(erow, col_idx, nnz, frontier,
-                                                             reinterpret_cast<unsigned long long*>(acc), flags, level);
+  if (nruns > 0) {
+    const unsigned blocks = (unsigned)((nruns + 4 * kGatherGroups - 1) / (4 * kGatherGroups));
+    k_bfs_gather<<<blocks, 256, 0, s>>>(runs, nruns, erow, col_idx, frontier,
+                                        reinterpret_cast<unsigned long long*>(acc),
+                                        reinterpret_cast<ulonglong2*>(visited), reinterpret_cast<ulonglong2*>(out),
+                                        flags, level);
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_bfs_update<<<blocks_for(words / 2), 256, 0, s>>>(reinterpret_cast<ulonglong2*>(acc),
-                                                     reinterpret_cast<ulonglong2*>(visited),
-                                                     reinterpret_cast<ulonglong2*>(out), words / 2, level, flags);
+  if (e != hipSuccess || nrows <= 0) return e;
+  k_bfs_finish<<<blocks_for((size_t)nrows * (kBfsWords / 2)), 256, 0, s>>>(
+      rows, nrows, reinterpret_cast<ulonglong2*>(acc), reinterpret_cast<ulonglong2*>(visited),
+      reinterpret_cast<ulonglong2*>(out), flags, level);
   return hipGetLastError();
 }
 

@@ -157,10 +157,19 @@ int bfs_slots();              // level bitmaps kept (levels per batch)
 // slots: bfs_slots() buffers of n * bfs_words() words; slot l % bfs_slots()
 // holds the sources that first reach each vertex at level l (slot 0: level 0).
 hipError_t launch_bfs_init(uint64_t* slot0, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s);
+// Runs of the gather: int2 (first CSR entry, count | bfs_run_chunk_flag()),
+// count 1 .. bfs_run_entries().  Whole rows of at most that many entries are
+// packed into runs (a run never splits them); a longer row is cut into
+// chunk runs and listed, with every isolated vertex, in the rows given to
+// launch_bfs_level: every vertex is owned by one run or listed, not both.
+int bfs_run_entries();
+int bfs_run_chunk_flag();
 // One BFS level (1 .. 256).  flags[0 .. 256]: flags[l] != 0 iff level l found a
 // new vertex (flags[0]: the sources); a level after an empty one does nothing.
-hipError_t launch_bfs_level(const int32_t* erow, const int32_t* col_idx, int64_t nnz, const uint64_t* slots,
-                            uint64_t* acc, uint64_t* visited, int n, int level, int32_t* flags, hipStream_t s);
+// acc (n * bfs_words() words) is zero between levels.
+hipError_t launch_bfs_level(const int2* runs, int nruns, const int32_t* erow, const int32_t* col_idx,
+                            const int32_t* rows, int nrows, const uint64_t* slots, uint64_t* acc, uint64_t* visited,
+                            int n, int level, int32_t* flags, hipStream_t s);
 // Levels l0 .. l1 (l1 - l0 < bfs_slots(), l1 <= 255) of the sweep from sources
 // base .. base + bfs_sources_per_sweep() - 1 into d; the batch starting at
 // level 1 writes every byte of the sweep's columns (below n_pad) in all rows.

@@ -68,6 +68,10 @@ def small_graphs():
         "tree500": inputs.random_tree(500, 3),
         "ba2000": inputs.barabasi_albert(2000, 3, 11),
         "ragged_129": inputs.erdos_renyi(129, 400, 5),
+        # a hub of degree 219 (14 chunks of the BFS gather), its leaves and a path
+        "star260": inputs.to_csr(260, [(0, k) for k in range(1, 220)] + [(k, k + 1) for k in range(220, 259)] +
+                                 [(5, 220)]),
+        "k40": inputs.complete_graph(40),  # every row longer than one gather run
     }
 
 

@@ -4,9 +4,10 @@ pairs: the same sums in another order.
 One Jacobi step from the same start: max |x^sym - x^ordered| <= 2e-6 * diam
 (both sum FP32 pair terms; the unordered pass adds each column's terms over
 512 rows in FP32 before FP64).  Ragged sizes (n_pad not a multiple of the
-512-row panel), tiny graphs, 2-D and 3-D, hop counts and edge lengths.  The
-unordered pass is the default in 2-D (Jacobi step, no stress trace);
-SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE pick either pass.
+512-row panel), tiny graphs, a disconnected graph with isolated vertices
+(unreachable pairs carry no weight), 2-D and 3-D, hop counts and edge lengths.
+The unordered pass is the default in 2-D from n_pad = 32768 (Jacobi step, no
+stress trace); SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE pick either pass.
 """
 import numpy as np
 import pytest
@@ -34,7 +35,15 @@ def graphs():
         "tree700": inputs.random_tree(700, 3),
         "ba3000": inputs.barabasi_albert(3000, 3, 11),
         "er5000": inputs.erdos_renyi(5000, 15000, 2),
+        "disconnected_600": disconnected(),
     }
+
+
+def disconnected():
+    # two components (a tree of 300 and a cycle of 200) and 100 isolated vertices
+    t = inputs.random_tree(300, 8)
+    edges = [(u, v) for u, v in t.edges()] + [(300 + k, 300 + (k + 1) % 200) for k in range(200)]
+    return inputs.to_csr(600, edges)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -51,6 +60,8 @@ def test_unordered_pass_matches_ordered_pass(name, dim):
         plan.run(Xd, omega=1.0, tol=0.0, max_iter=1, ordered_force=True)
         err = np.abs(Xs.cpu().numpy().astype(np.float64) - Xd.cpu().numpy()).max()
         assert err <= 2e-6 * diam(X0), err
+        if name == "disconnected_600":  # isolated vertices have no pair with weight: they stay
+            np.testing.assert_array_equal(Xs.cpu().numpy()[500:], X0[500:].astype(np.float32))
         # a few steps with extrapolation and the safeguard stay together too
         Xs, Xd = dev(X0), dev(X0)
         ts = plan.run(Xs, omega=1.5, tol=0.0, max_iter=10, trace=True, sym_force=True)["trace"]
