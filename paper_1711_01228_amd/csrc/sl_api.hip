@@ -366,7 +366,7 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     if (e == hipSuccess) e = hipMalloc(&vis, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&acc, sizeof(uint64_t) * words);
     if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t) * (kBfsMaxLevel + 1));
-    if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t) * (nslots + 1), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemcpyAsync(er, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMalloc(&rn, sizeof(int2) * std::max<size_t>(1, runs.size()));
@@ -382,23 +382,33 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     // Every byte of d is written by the first batch of levels of some sweep
     // (the sweeps' column ranges cover [0, n_pad), and every row is stored).
     const int sweep = bfs_sources_per_sweep();
+    // The first batch of a sweep queues the previous sweep's depth + 3 levels
+    // (all the slots for the first sweep): a level after the search ended still
+    // costs two launches, a search deeper than the batch one more batch.
+    int depth = nslots;
     for (int base = 0; base < n && status == SL_OK && e == hipSuccess; base += sweep) {
       e = launch_bfs_init(slots, vis, acc, n, base, p->ps);
       // flags[l] = 0 for every level, flags[0] != 0 (the sources)
       if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int32_t) * (kBfsMaxLevel + 1), p->ps);
       if (e == hipSuccess) e = hipMemsetAsync(flag, 1, sizeof(int32_t), p->ps);
-      for (int l0 = 1; e == hipSuccess; l0 += nslots) {
-        // one batch: as many levels as there are slots, then their distances
-        const int l1 = std::min(l0 + nslots - 1, kBfsMaxLevel);
+      for (int l0 = 1, l1 = 0; e == hipSuccess; l0 = l1 + 1) {
+        // one batch of at most as many levels as there are slots, then their distances
+        l1 = std::min(l0 + (l0 == 1 ? std::min(depth + 3, nslots) : nslots) - 1, kBfsMaxLevel);
         for (int level = l0; level <= l1 && e == hipSuccess; ++level)
           e = launch_bfs_level(rn, (int)runs.size(), er, ci, rl, (int)rows.size(), slots, acc, vis, n, level, flag,
                                p->ps);
         // level 256 is not stored: it only tells whether a distance exceeds 255
         if (e == hipSuccess)
           e = launch_bfs_store(slots, flag, p->d, n, p->n_pad, base, l0, std::min(l1, kBfsMaxLevel - 1), p->ps);
-        if (e == hipSuccess) e = hipMemcpyAsync(hflag, flag + l1, sizeof(int32_t), hipMemcpyDeviceToHost, p->ps);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(hflag, flag + l0, sizeof(int32_t) * (l1 - l0 + 1), hipMemcpyDeviceToHost, p->ps);
         if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
-        if (e != hipSuccess || *hflag == 0) break;
+        if (e != hipSuccess) break;
+        if (hflag[l1 - l0] == 0) {  // the search ended in this batch: its depth
+          depth = l0 - 1;
+          for (int l = l0; l <= l1 && hflag[l - l0]; ++l) depth = l;
+          break;
+        }
         if (l1 == kBfsMaxLevel) {
           status = fail(SL_ERANGE, "a graph distance exceeds 255 hops (sources %d..%d)", base, base + sweep - 1);
           break;
