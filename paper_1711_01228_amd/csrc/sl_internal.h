@@ -128,7 +128,8 @@ struct SymSplit {
   std::vector<int32_t> panel_items;  // npanels + 1 offsets into items
 };
 SymSplit make_sym_split(int n_pad);
-// Writes F into force slice 0 of fpart (Pi: items x 512 x dim doubles, Pj:
+int sym_rows_per_item();  // rows of one work item (its panel of row strips)
+// Writes F into force slice 0 of fpart (Pi: items x sym_rows_per_item() x dim doubles, Pj:
 // panels x n_pad x dim floats of partial sums); cond: only when the state asks
 // for the force again (after a rejection).
 hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,

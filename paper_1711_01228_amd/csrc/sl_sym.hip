@@ -299,6 +299,8 @@ void sym_dispatch(int dim, const LoopParams* lp, int cond, const uint8_t* d, con
 
 }  // namespace
 
+int sym_rows_per_item() { return kPanel * 64; }
+
 SymSplit make_sym_split(int n_pad) {
   SymSplit sp;
   sp.nb = n_pad / 64;
