@@ -320,8 +320,8 @@ class Plan:
         sweep of eq. 5) or "exact" (eq. 5 solved by conjugate gradients to
         inner_tol, at most inner_max_iter steps; 0 selects the defaults).
         sym_force / ordered_force: evaluate the force pass once per unordered
-        pair (SL_FLAG_SYM_FORCE; Jacobi ordering; the default in 2-D) or over
-        every ordered pair (SL_FLAG_ORDERED_FORCE).
+        pair (SL_FLAG_SYM_FORCE; Jacobi ordering; the default in 2-D from
+        n_pad = 32768) or over every ordered pair (SL_FLAG_ORDERED_FORCE).
         separate_safeguard: evaluate the safeguard in its own pass instead of
         inside the next force pass (SL_FLAG_SEPARATE_SAFEGUARD).
         Returns the sl_result fields; with ``trace`` also a ``trace`` array
