@@ -108,6 +108,10 @@ typedef enum {
                                           iteration's force pass, taken at X~;
                                           when X~ is rejected the force pass at
                                           X^H runs again.  The same iterates. */
+#define SL_FLAG_NO_FINAL_STRESS 32u  /* do not evaluate f of the returned placement
+                                        (one pass over all pairs after the loop):
+                                        sl_result.stress is NaN.  The iterates are
+                                        the same.                                */
 
 /* The graph G = (V, E) of the problem statement (Sec. 1), host memory, CSR.
  * Symmetric: (u, v) present iff (v, u) present.  Vertex ids 0 .. n-1.  No self
@@ -160,7 +164,8 @@ typedef struct {
   int32_t rejected;         /* extrapolations refused by the safeguard            */
   int32_t inner_iterations; /* SL_ORDER_EXACT: conjugate-gradient steps, summed    */
   double residual;          /* res of the last step                               */
-  double stress;            /* f of the returned placement                        */
+  double stress;            /* f of the returned placement (NaN with
+                               SL_FLAG_NO_FINAL_STRESS)                           */
   double plan_ms;           /* time of sl_plan_create (sl_layout: distances+weights) */
   double run_ms;            /* device time of the iteration loop                  */
 } sl_result;

@@ -24,6 +24,7 @@ SL_FLAG_NO_GRAPH = 2
 SL_FLAG_SYM_FORCE = 4
 SL_FLAG_SEPARATE_SAFEGUARD = 8
 SL_FLAG_ORDERED_FORCE = 16
+SL_FLAG_NO_FINAL_STRESS = 32
 SL_OMEGA_FIXED, SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM = 0, 1, 2
 SL_ORDER_JACOBI, SL_ORDER_EXACT = 0, 1
 ORDERINGS = {"jacobi": SL_ORDER_JACOBI, "exact": SL_ORDER_EXACT}
@@ -160,7 +161,8 @@ def graph_args(g) -> _GraphArgs:
 def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0,
                  trace_stress=False, use_graph=True, trace=None, xtrace=None, strategy=SL_OMEGA_FIXED,
                  omega_schedule=None, omega_vertex=None, ordering=SL_ORDER_JACOBI, inner_tol=0.0,
-                 inner_max_iter=0, sym_force=False, separate_safeguard=False, ordered_force=False) -> sl_options:
+                 inner_max_iter=0, sym_force=False, separate_safeguard=False, ordered_force=False,
+                 final_stress=True) -> sl_options:
     """omega_schedule: host float64 array (kept alive by the caller);
     omega_vertex: device pointer (int) or None."""
     o = sl_options()
@@ -169,7 +171,8 @@ def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, chec
     o.safeguard, o.check_every = int(bool(safeguard)), int(check_every)
     o.flags = (SL_FLAG_TRACE_STRESS if trace_stress else 0) | (0 if use_graph else SL_FLAG_NO_GRAPH) | \
         (SL_FLAG_SYM_FORCE if sym_force else 0) | \
-        (SL_FLAG_SEPARATE_SAFEGUARD if separate_safeguard else 0) | (SL_FLAG_ORDERED_FORCE if ordered_force else 0)
+        (SL_FLAG_SEPARATE_SAFEGUARD if separate_safeguard else 0) | (SL_FLAG_ORDERED_FORCE if ordered_force else 0) | \
+        (0 if final_stress else SL_FLAG_NO_FINAL_STRESS)
     o.trace = None if trace is None else int(trace)
     o.xtrace = None if xtrace is None else int(xtrace)
     o.strategy = int(strategy)
@@ -310,7 +313,7 @@ class Plan:
     def run(self, X, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0, trace=False,
             trace_stress=False, trace_positions=False, use_graph=True, stream=None, strategy="fixed",
             omega_schedule=None, omega_vertex=None, ordering="jacobi", inner_tol=0.0, inner_max_iter=0,
-            sym_force=False, separate_safeguard=False, ordered_force=False):
+            sym_force=False, separate_safeguard=False, ordered_force=False, final_stress=True):
         """Run Algorithm 2 in place on the device tensor X (n x dim, float32).
 
         strategy: "fixed" (omega), "schedule" (omega_schedule, one classical
@@ -324,6 +327,8 @@ class Plan:
         n_pad = 32768) or over every ordered pair (SL_FLAG_ORDERED_FORCE).
         separate_safeguard: evaluate the safeguard in its own pass instead of
         inside the next force pass (SL_FLAG_SEPARATE_SAFEGUARD).
+        final_stress=False skips the pass that evaluates f of the result
+        (SL_FLAG_NO_FINAL_STRESS; ``stress`` is then NaN).
         Returns the sl_result fields; with ``trace`` also a ``trace`` array
         (iterations x 5) and with ``trace_positions`` the ``positions``
         (iterations x n x dim) on the host."""
@@ -346,7 +351,7 @@ class Plan:
         opt = make_options(self.dim, omega, tol, max_iter, safeguard, check_every, trace_stress, use_graph,
                            None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr(),
                            strat, sched, None if wv is None else wv.data_ptr(), ORDERINGS[ordering], inner_tol,
-                           inner_max_iter, sym_force, separate_safeguard, ordered_force)
+                           inner_max_iter, sym_force, separate_safeguard, ordered_force, final_stress)
         info = sl_plan_run(self.handle, X.data_ptr(), opt, stream)
         k = info["iterations"]
         if tr is not None:

@@ -112,7 +112,7 @@ sl_status check_options(const sl_options* o) {
   if (o->max_iter < 0) return fail(SL_EINVAL, "max_iter = %d is negative", o->max_iter);
   if (o->safeguard != 0 && o->safeguard != 1) return fail(SL_EINVAL, "safeguard must be 0 or 1");
   if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH | SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD |
-                   SL_FLAG_ORDERED_FORCE))
+                   SL_FLAG_ORDERED_FORCE | SL_FLAG_NO_FINAL_STRESS))
     return fail(SL_EINVAL, "unknown flag bits");
   if (o->strategy != SL_OMEGA_FIXED && o->strategy != SL_OMEGA_SCHEDULE && o->strategy != SL_OMEGA_ENUM)
     return fail(SL_EINVAL, "unknown relaxation strategy %d", o->strategy);
@@ -916,7 +916,8 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   res.rejected = fin.rejected;
   res.residual = fin.residual;
   double f = 0.0;
-  if (p->n > 1 && (s = stress_pass(p, fin.cur, &f)) != SL_OK) return s;
+  if (o->flags & SL_FLAG_NO_FINAL_STRESS) f = std::nan("");
+  else if (p->n > 1 && (s = stress_pass(p, fin.cur, &f)) != SL_OK) return s;
   res.stress = f;
   if ((s = join_to(p, user)) != SL_OK) return s;
   if (out) *out = res;

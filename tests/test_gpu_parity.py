@@ -333,6 +333,18 @@ def test_bitwise_repeatable_graph_and_resume(sl):
         np.testing.assert_array_equal(o, outs[0])
 
 
+def test_no_final_stress_keeps_the_iterates(sl):
+    g, X0 = inputs.grid16(1)
+    with sl.Plan(g, 2) as plan:
+        Xa, Xb = dev(X0), dev(X0)
+        ra = plan.run(Xa, omega=1.5, tol=1e-3, max_iter=300)
+        rb = plan.run(Xb, omega=1.5, tol=1e-3, max_iter=300, final_stress=False)
+        assert np.isnan(rb["stress"]) and np.isfinite(ra["stress"])
+        assert (ra["iterations"], ra["rejected"], ra["residual"]) == (rb["iterations"], rb["rejected"], rb["residual"])
+        np.testing.assert_array_equal(Xa.cpu().numpy(), Xb.cpu().numpy())
+        assert plan.stress(Xb) == ra["stress"]  # the same pass, asked for separately
+
+
 def test_layout_one_call_matches_plan(sl):
     g, X0 = inputs.grid16(2)
     X1, info = sl.layout(g, X0, omega=1.5, tol=1e-3, max_iter=500)
