@@ -110,6 +110,7 @@ def test_validation_rejects_bad_options(field, value):
 
 def test_valid_inputs_and_empty_graph():
     b.sl_validate(_tri(), b.make_options(dim=3, omega=2.5, tol=0.0, max_iter=0, safeguard=False))
+    b.sl_validate(_tri(), b.make_options(final_stress=False, ordered_force=True, separate_safeguard=True))
     b.sl_validate(G(0, [0], []))
     b.sl_validate(G(3, [0, 0, 0, 0], []))  # isolated vertices only
 
