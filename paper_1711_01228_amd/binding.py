@@ -324,7 +324,8 @@ class Plan:
         inner_tol, at most inner_max_iter steps; 0 selects the defaults).
         sym_force / ordered_force: evaluate the force pass once per unordered
         pair (SL_FLAG_SYM_FORCE; Jacobi ordering; the default in 2-D from
-        n_pad = 32768) or over every ordered pair (SL_FLAG_ORDERED_FORCE).
+        n_pad = 32768, 16384 for edge lengths) or over every ordered pair
+        (SL_FLAG_ORDERED_FORCE).
         separate_safeguard: evaluate the safeguard in its own pass instead of
         inside the next force pass (SL_FLAG_SEPARATE_SAFEGUARD).
         final_stress=False skips the pass that evaluates f of the result

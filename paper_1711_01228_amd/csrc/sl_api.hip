@@ -449,9 +449,14 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
 // Buffers of the unordered-pair force pass, made on first use: its work items
 // and the row and column partial sums.
 // The force pass taken by default: once per unordered pair where that is the
-// faster one (2-D and n_pad >= kSymMinN, measured), else every ordered pair.
+// faster one (2-D and n_pad >= kSymMinN, or kSymMinNLengths for edge-length
+// plans, whose ordered pass reads 4-byte distances; measured), else every
+// ordered pair.
 constexpr int kSymMinN = 32768;
-bool sym_by_default(const sl_plan* p) { return p->dim == 2 && p->n_pad >= kSymMinN && p->n > 1; }
+constexpr int kSymMinNLengths = 16384;
+bool sym_by_default(const sl_plan* p) {
+  return p->dim == 2 && p->n > 1 && p->n_pad >= (p->df ? kSymMinNLengths : kSymMinN);
+}
 
 sl_status ensure_sym(sl_plan* p) {
   if (p->sym_items) return SL_OK;

@@ -192,7 +192,9 @@ def test_backward_without_tape_and_length_gradient_on_hop_plan_are_refused():
 
 def test_full_size_gradient_invariants():
     """ER n = 16,384, mean degree 8, 100 iterations at omega = 1.5, checkpoints
-    every 10: gradients finite, translation- and rotation-invariant."""
+    every 10: gradients finite, translation- and rotation-invariant.  At this
+    size an edge-length plan takes the unordered force pass; the unrolled
+    forward equals sl_plan_run bit for bit on it."""
     import torch
 
     from paper_1711_01228_amd import autograd as ag
@@ -211,6 +213,10 @@ def test_full_size_gradient_invariants():
         loss.backward()
         gX0 = X0t.grad.cpu().numpy().astype(np.float64)
         glen = lt.grad.cpu().numpy().astype(np.float64)
+        Xa, Xb = dev(X0), dev(X0)
+        lay.plan.run(Xa, omega=1.5, tol=0.0, max_iter=20)
+        lay.plan.unroll(Xb, omega=1.5, iters=20, ckpt_every=10)
+        np.testing.assert_array_equal(Xa.cpu().numpy(), Xb.cpu().numpy())
     finally:
         lay.close()
     assert np.all(np.isfinite(gX0)) and np.all(np.isfinite(glen))
