@@ -1385,11 +1385,20 @@ sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float*
     }
     for (int k = k1 - 1; k >= k0; --k) {
       const float* Xk = p->segX + (size_t)(k - k0) * p->stride;
-      HIP_TRY(launch_force(p->dim, false, p->d, p->df, Xk, 0, p->st_eval, p->fpart, p->spart, p->sp, p->n_pad,
-                           p->ps),
-              "force kernel");
+      // F at X^k by the pass the forward took (the unordered one leaves F in force slice 0)
+      int fslices = p->sp.slices;
+      if (lp.sym) {
+        HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->df, Xk, 0, p->st_eval, p->sym_items, p->nsym_items,
+                                 p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
+                "force kernel");
+        fslices = 1;
+      } else {
+        HIP_TRY(launch_force(p->dim, false, p->d, p->df, Xk, 0, p->st_eval, p->fpart, p->spart, p->sp, p->n_pad,
+                             p->ps),
+                "force kernel");
+      }
       const double a = tr[(size_t)k * SL_TRACE_COLS + 1] == 1.0 ? p->tape_omega : 1.0;
-      HIP_TRY(launch_adjoint_step(p->dim, p->d, p->df, Xk, p->fpart, p->W, a, p->gb,
+      HIP_TRY(launch_adjoint_step(p->dim, p->d, p->df, Xk, p->fpart, fslices, p->W, a, p->gb,
                                   p->gvec + (size_t)(k - k0) * p->stride, p->wbar + (size_t)(k - k0) * p->n_pad,
                                   p->fpart, p->sp, p->n_pad, p->ps),
               "adjoint kernels");

@@ -445,19 +445,19 @@ hipError_t launch_save(const float* Xb, size_t stride, const DevState* st, float
 }
 
 hipError_t launch_adjoint_step(int dim, const uint8_t* d, const float* df, const float* Xk, const double* fpart,
-                               const double* W, double a, double* gb, float* gvec, float* wbar, double* apart,
-                               const Split& sp, int n_pad, hipStream_t s) {
+                               int fslices, const double* W, double a, double* gb, float* gvec, float* wbar,
+                               double* apart, const Split& sp, int n_pad, hipStream_t s) {
   const unsigned nb = blocks_for(n_pad);
   const dim3 grid(sp.blocks_x, sp.slices);
   const int gps = sp.groups_per_slice;
   // the adjoint pass overwrites fpart (the force sums were read by k_adj_prep)
   if (dim == 2) {
-    k_adj_prep<2><<<nb, 256, 0, s>>>(gb, fpart, sp.slices, W, a, n_pad, gvec, wbar);
+    k_adj_prep<2><<<nb, 256, 0, s>>>(gb, fpart, fslices, W, a, n_pad, gvec, wbar);
     if (df) k_adjoint<2, true><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
     else k_adjoint<2, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
     k_adj_update<2><<<nb, 256, 0, s>>>(gb, apart, sp.slices, n_pad);
   } else {
-    k_adj_prep<3><<<nb, 256, 0, s>>>(gb, fpart, sp.slices, W, a, n_pad, gvec, wbar);
+    k_adj_prep<3><<<nb, 256, 0, s>>>(gb, fpart, fslices, W, a, n_pad, gvec, wbar);
     if (df) k_adjoint<3, true><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
     else k_adjoint<3, false><<<grid, 256, 0, s>>>(d, df, Xk, gvec, apart, sp.nrb, sp.ng, gps, n_pad);
     k_adj_update<3><<<nb, 256, 0, s>>>(gb, apart, sp.slices, n_pad);

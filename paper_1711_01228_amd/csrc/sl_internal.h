@@ -195,8 +195,8 @@ hipError_t launch_save(const float* Xb, size_t stride, const DevState* st, float
 // in fpart: gb += Xbar; with Dbar, dL/dd of every row added into it.  The
 // adjoint pass reuses apart (may be fpart).
 hipError_t launch_adjoint_step(int dim, const uint8_t* d, const float* df, const float* Xk, const double* fpart,
-                               const double* W, double a, double* gb, float* gvec, float* wbar, double* apart,
-                               const struct Split& sp, int n_pad, hipStream_t s);
+                               int fslices, const double* W, double a, double* gb, float* gvec, float* wbar,
+                               double* apart, const struct Split& sp, int n_pad, hipStream_t s);
 // dL/dd of a segment of nk iterations into Dbar, from the iterates (segX) and
 // the adjoint vectors (gseg: nk x stride floats, wseg: nk x n_pad) of each.
 hipError_t launch_dbar_segment(int dim, const uint8_t* d, const float* df, const float* segX, size_t stride,
