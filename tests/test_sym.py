@@ -115,14 +115,23 @@ def test_unordered_pass_on_edge_length_plan(dim):
         assert ms["force_sym"] > 0.0 and ms["force_safeguard_sym"] > 0.0
 
 
+def lengths_graph(n, seed):
+    g = inputs.erdos_renyi(n, 4 * n, seed)
+    ln = (1.0 + np.random.default_rng(seed + 1).uniform(-0.1, 0.1, g.num_edges)).astype(np.float32)
+    return inputs.to_csr(g.n, g.edges(), ln)
+
+
 DEFAULT_CASES = {
     "grid16": lambda: inputs.grid_graph(16, 16),              # n_pad 256: the ordered pass is faster
     "ba32768": lambda: inputs.barabasi_albert(32768, 3, 61),  # n_pad 32768: the unordered one in 2-D
+    "er8192_lengths": lambda: lengths_graph(8192, 62),        # edge lengths: ordered below n_pad 16384
+    "er16384_lengths": lambda: lengths_graph(16384, 63),      # and unordered from there in 2-D
 }
 
 
 @pytest.mark.parametrize("name,dim,expect", [
     ("grid16", 2, "ordered"), ("grid16", 3, "ordered"), ("ba32768", 2, "sym"), ("ba32768", 3, "ordered"),
+    ("er8192_lengths", 2, "ordered"), ("er16384_lengths", 2, "sym"), ("er16384_lengths", 3, "ordered"),
 ])
 def test_default_force_pass_by_size_and_dim(name, dim, expect):
     from paper_1711_01228_amd import binding as b
