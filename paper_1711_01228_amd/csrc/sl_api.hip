@@ -177,7 +177,7 @@ struct sl_plan {
   int4* sym_items = nullptr;
   int32_t* sym_panel_items = nullptr;
   int nsym_items = 0;
-  double* Pi = nullptr;         // row partials: items x sym_rows_per_item() x dim
+  float* Pi = nullptr;          // row partials: items x sym_rows_per_item() x dim
   float* Pj = nullptr;          // column partials: panels x n_pad x dim
   double* W = nullptr;          // n_pad
   float* Xb = nullptr;          // 3 iterate buffers
@@ -464,11 +464,11 @@ sl_status ensure_sym(sl_plan* p) {
   const SymSplit ss = make_sym_split(p->n_pad);
   int4* items = nullptr;
   int32_t* panel_items = nullptr;
-  double* Pi = nullptr;
+  float* Pi = nullptr;
   float* Pj = nullptr;
   hipError_t e = hipMalloc(&items, sizeof(int4) * ss.items.size());
   if (e == hipSuccess) e = hipMalloc(&panel_items, sizeof(int32_t) * ss.panel_items.size());
-  if (e == hipSuccess) e = hipMalloc(&Pi, sizeof(double) * ss.items.size() * sym_rows_per_item() * p->dim);
+  if (e == hipSuccess) e = hipMalloc(&Pi, sizeof(float) * ss.items.size() * sym_rows_per_item() * p->dim);
   if (e == hipSuccess) e = hipMalloc(&Pj, sizeof(float) * (size_t)ss.npanels * p->n_pad * p->dim);
   if (e == hipSuccess)
     e = hipMemcpyAsync(items, ss.items.data(), sizeof(int4) * ss.items.size(), hipMemcpyHostToDevice, p->ps);

@@ -129,17 +129,17 @@ struct SymSplit {
 };
 SymSplit make_sym_split(int n_pad);
 int sym_rows_per_item();  // rows of one work item (its panel of row strips)
-// Writes F into force slice 0 of fpart (Pi: items x sym_rows_per_item() x dim doubles, Pj:
+// Writes F into force slice 0 of fpart (Pi: items x sym_rows_per_item() x dim floats, Pj:
 // panels x n_pad x dim floats of partial sums); cond: only when the state asks
 // for the force again (after a rejection).
 hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
-                            const DevState* st, const int4* items, int nitems, const int32_t* panel_items, double* Pi,
+                            const DevState* st, const int4* items, int nitems, const int32_t* panel_items, float* Pi,
                             float* Pj, double* fpart, int n_pad, hipStream_t s);
 // The same pass at X~ with the safeguard summed in (one double per item into
 // sgpart), as launch_force_sg.
 hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
                                size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
-                               const int32_t* panel_items, double* Pi, float* Pj, double* sgpart, double* fpart,
+                               const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart,
                                int n_pad, hipStream_t s);
 // One application of L^W to p (also used by the profiler).
 hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double* W, const DevState* st, CgState* cg,

@@ -18,8 +18,8 @@
 // With SG the safeguard term of Alg. 2 (the fused pass's formula; every pair
 // here has j > i) is summed too, and the pass is taken at X~ (or at X^H for an
 // iteration without extrapolation).
-// The column totals go out once per (panel, column) as FP32, the row sums once
-// per (item, row) as FP64; k_sym_reduce forms
+// The column totals go out once per (panel, column) and the row sums once per
+// (item, row), both as FP32; k_sym_reduce forms
 //   F_i = sum over the items of i's panel of the row partials
 //       - sum over the panels 0 .. panel(i) of the column partials
 // in FP64 into force slice 0 (16 lanes per vertex, each over a fixed stride of
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
                                                    const double* __restrict__ omega_sched, double omega_p,
                                                    int vertex_factors, int cond, const DevState* __restrict__ st,
                                                    const int4* __restrict__ items, int nitems,
-                                                   double* __restrict__ Pi, float* __restrict__ Pj,
+                                                   float* __restrict__ Pi, float* __restrict__ Pj,
                                                    double* __restrict__ sgpart, int nb, int ng, int n_pad) {
   using V = typename VecT<DIM>::T;
   __shared__ float4 lut[256];                             // (1/d, 1/d^2, -2/d, 0)
@@ -216,9 +216,9 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
     }
   }
   for (int r = 0; r < nstrips; ++r) {
-    double* out = Pi + ((size_t)item * kPanel * 64 + (size_t)r * 64 + lane) * DIM;
+    float* out = Pi + ((size_t)item * kPanel * 64 + (size_t)r * 64 + lane) * DIM;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) out[c] = racc[r][c][lane];
+    for (int c = 0; c < DIM; ++c) out[c] = (float)racc[r][c][lane];
   }
   if constexpr (SG) {
     S = wave_sum(S);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
 constexpr int kReduceLanes = 16;
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ Pi, const float* __restrict__ Pj,
+__global__ __launch_bounds__(256) void k_sym_reduce(const float* __restrict__ Pi, const float* __restrict__ Pj,
                                                     const int32_t* __restrict__ panel_items, int cond,
                                                     const DevState* __restrict__ st, double* __restrict__ fpart,
                                                     int n_pad) {
@@ -247,9 +247,9 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ P
   for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
   if (live) {
     for (int q = panel_items[panel] + t; q < panel_items[panel + 1]; q += kReduceLanes) {
-      const double* p = Pi + ((size_t)q * kPanel * 64 + row) * DIM;
+      const float* p = Pi + ((size_t)q * kPanel * 64 + row) * DIM;
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) acc[c] += p[c];
+      for (int c = 0; c < DIM; ++c) acc[c] += (double)p[c];
     }
     for (int p = t; p <= panel; p += kReduceLanes) {
       const float* col = Pj + ((size_t)p * n_pad + ii) * DIM;
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ P
 template <int DIM, bool SG, bool FD>
 void sym_launch(const LoopParams* lp, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                 const float* Eb, const DevState* st, const int4* items, int nitems, const int32_t* panel_items,
-                double* Pi, float* Pj, double* sgpart, double* fpart, int n_pad, hipStream_t s) {
+                float* Pi, float* Pj, double* sgpart, double* fpart, int n_pad, hipStream_t s) {
   const int nb = n_pad / 64, ng = n_pad / kColGroup;
   k_force_sym<DIM, SG, FD><<<(nitems + kWaves - 1) / kWaves, kWaves * 64, 0, s>>>(
       d, df, Xb, stride, Eb, lp ? lp->omega_sched : nullptr, lp ? lp->omega_p : 0.0, lp && lp->omega_vertex ? 1 : 0,
@@ -282,7 +282,7 @@ void sym_launch(const LoopParams* lp, int cond, const uint8_t* d, const float* d
 template <bool SG>
 void sym_dispatch(int dim, const LoopParams* lp, int cond, const uint8_t* d, const float* df, const float* Xb,
                   size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
-                  const int32_t* panel_items, double* Pi, float* Pj, double* sgpart, double* fpart, int n_pad,
+                  const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart, int n_pad,
                   hipStream_t s) {
   if (dim == 2) {
     if (df) sym_launch<2, SG, true>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
@@ -324,7 +324,7 @@ SymSplit make_sym_split(int n_pad) {
 }
 
 hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
-                            const DevState* st, const int4* items, int nitems, const int32_t* panel_items, double* Pi,
+                            const DevState* st, const int4* items, int nitems, const int32_t* panel_items, float* Pi,
                             float* Pj, double* fpart, int n_pad, hipStream_t s) {
   sym_dispatch<false>(dim, nullptr, cond, d, df, Xb, stride, nullptr, st, items, nitems, panel_items, Pi, Pj, nullptr,
                       fpart, n_pad, s);
@@ -333,7 +333,7 @@ hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df
 
 hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
                                size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
-                               const int32_t* panel_items, double* Pi, float* Pj, double* sgpart, double* fpart,
+                               const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart,
                                int n_pad, hipStream_t s) {
   sym_dispatch<true>(dim, &lp, 0, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart, fpart, n_pad,
                      s);
