@@ -36,10 +36,11 @@ METRIC = "pair-interactions/s + time-to-converge (SOR-ω vs ω=1) at n=65,536, 1
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed-FMA issue)
 PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 FLOPS_PER_PAIR = {2: 12, 3: 17}  # algorithmic flops of one ordered pair of the force pass
-# safeguard share of one unordered pair in the fused pass, beyond the force terms:
-# e (DIM), 2t - e (DIM fma), m (1 + 2 (DIM - 1)), r~^2 - m, sqrt, s (fma), rcp,
-# (2/d) / s + 1/d^2 (fma), times m, sum (2-D: 2 + 4 + 3 + 1 + 1 + 2 + 1 + 2 + 1 + 1)
-SG_FLOPS_PER_UNORDERED_PAIR = {2: 18, 3: 23}
+# algorithmic flops of the safeguard term of one unordered pair (the stress
+# difference w (r~ - r^H)(r~ + r^H - 2d)), transcendentals (rsq, sqrt, rcp)
+# counted as 0 flops as in the force term: 15 in 2-D, and 5 more in 3-D for the
+# third coordinate of e, 2t - e and m
+SG_FLOPS_PER_UNORDERED_PAIR = {2: 15, 3: 20}
 # the library's default force pass: once per unordered pair in 2-D from a
 # padded size of 32768 vertices, else over every ordered pair (the faster one)
 SYM_MIN_N_PAD = 32768
@@ -64,6 +65,27 @@ def kernel_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+VALU = {True: (os.path.join(ROOT, "profiles", "force_safeguard_sym_ba65536_valu.json"),
+                os.path.join(CSRC, "sl_sym.hip"))}
+
+
+def measured_valu(dim, sym, n):
+    """VALU utilisation of the fused pass from committed rocprofv3 counters
+    (SQ_ACTIVE_INST_VALU over GRBM_GUI_ACTIVE), if they were taken on the
+    current kernel source and this workload."""
+    if sym not in VALU:
+        return None
+    path, src = VALU[sym]
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha") != kernel_hash(src) or rec.get("dim") != dim or rec.get("n", n) != n:
+        return None
+    return {k: rec[k] for k in ("valu_busy", "valu_issue_slots_per_unordered_pair", "counters") if k in rec}
+
+
 def measured_traffic(dim, sym, n):
     """HBM bytes per launch of the fused pass from committed rocprofv3 counters,
     if they were taken on the current kernel source and this workload."""
@@ -78,6 +100,40 @@ def measured_traffic(dim, sym, n):
     return rec.get("bytes_per_launch")
 
 
+PROBE_KINDS = {"fma": 0, "rsq": 1, "sqrt": 2, "rcp": 3}
+
+
+def probe_library():
+    """libslprobe (include/slprobe.h), the calibration kernels of this benchmark."""
+    import ctypes
+
+    try:
+        import torch  # noqa: F401  (one HIP runtime for torch and the library)
+    except ImportError:
+        pass
+    from paper_1711_01228_amd import build_lib
+
+    lib = ctypes.CDLL(build_lib.PROBE_LIB)
+    d = ctypes.POINTER(ctypes.c_double)
+    lib.slp_probe_rate.argtypes = [ctypes.c_int32, ctypes.c_void_p, d, d]
+    lib.slp_probe_rate.restype = ctypes.c_int32
+    return lib
+
+
+def probe_rate(kind):
+    """(lane operations per second, ms) of one instruction kind on the device."""
+    import ctypes
+
+    import torch
+
+    per_s, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    st = probe_library().slp_probe_rate(PROBE_KINDS[kind], torch.cuda.current_stream().cuda_stream,
+                                        ctypes.byref(per_s), ctypes.byref(ms))
+    if st != 0:
+        raise RuntimeError("slp_probe_rate(%s) failed with %d" % (kind, st))
+    return per_s.value, ms.value
+
+
 def measured_ceilings():
     """What this device sustains, beside its data-sheet peaks: plain FP32 FMAs
     (the build has no packed FP32) and the transcendentals of the force and
@@ -85,13 +141,11 @@ def measured_ceilings():
     device-to-device copy (read + write bytes over its HIP-event time)."""
     import torch
 
-    from paper_1711_01228_amd import binding
-
     res = {}
-    fma, _ = binding.sl_probe_rate("fma")
+    fma, _ = probe_rate("fma")
     res["fp32_fma_TFLOPs"] = round(2.0 * fma / 1e12, 2)
     for k in ("rsq", "sqrt", "rcp"):
-        res["%s_per_s" % k] = float("%.4g" % binding.sl_probe_rate(k)[0])
+        res["%s_per_s" % k] = float("%.4g" % probe_rate(k)[0])
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -106,39 +160,199 @@ def measured_ceilings():
     return res
 
 
-def cpu_baseline(g, X0, target_s=12.0):
-    """The FP64 oracle's Jacobi step on a sample of rows of the same graph."""
+def host_cpu():
+    """Model, logical CPUs and clock of the host, from lscpu (or /proc/cpuinfo)."""
+    import subprocess
+
+    info = {"model": "unknown", "cpus": os.cpu_count(), "mhz": None}
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                             timeout=20).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "Model name":
+                info["model"] = v
+            elif k == "CPU(s)":
+                info["cpus"] = int(v)
+            elif k in ("CPU max MHz", "CPU MHz") and info["mhz"] is None:
+                info["mhz"] = float(v)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    if info["mhz"] is None:  # the clock named in the model string (e.g. "@ 2.70GHz")
+        import re
+
+        m = re.search(r"@\s*([0-9.]+)\s*GHz", info["model"])
+        if m:
+            info["mhz"] = float(m.group(1)) * 1000.0
+    return info
+
+
+def oracle_threads():
+    """Threads the oracle's OpenMP loops use in this process."""
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def _oracle_rows_rate(g, X0, rows, block=512):
+    """Pair rate of the oracle's Jacobi rows (eq. 5 row solves) for the given
+    rows, their distance rows found block by block (never all at once)."""
     import numpy as np
 
     import oracle
 
     n = g.n
+    dt = 0.0
+    for a in range(0, len(rows), block):
+        r = rows[a:a + block]
+        Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, r)
+        t = time.perf_counter()
+        oracle.h_jacobi_rows(Drows, r, X0)
+        dt += time.perf_counter() - t
+        del Drows
+    return len(rows) * (n - 1) / dt, dt
+
+
+def cpu_baseline(g, X0, target_s=12.0):
+    """The FP64 oracle's Jacobi step on a sample of rows of the same graph, on
+    all the threads this process gives it and (in a child process) on one."""
+    import subprocess
+
+    import numpy as np
+
+    n = g.n
     rng = np.random.default_rng(0)
-    rows = np.sort(rng.choice(n, 128, replace=False))
-    Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
-    t = time.perf_counter()
-    oracle.h_jacobi_rows(Drows, rows, X0)
-    t1 = time.perf_counter() - t
-    R = int(min(n, max(128, 128 * target_s / max(t1, 1e-3))))
+    rate0, _ = _oracle_rows_rate(g, X0, np.sort(rng.choice(n, 128, replace=False)))
+    R = int(min(n, max(128, rate0 * target_s / (n - 1))))
     rows = np.sort(rng.choice(n, R, replace=False))
-    Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
-    t = time.perf_counter()
-    oracle.h_jacobi_rows(Drows, rows, X0)
-    dt = time.perf_counter() - t
-    del Drows
-    pairs = R * (n - 1)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rate = pairs / dt
-    model = "unknown"
+    rate, dt = _oracle_rows_rate(g, X0, rows)
+    cores = oracle_threads()
+    one = None
+    code = ("import sys, numpy as np; sys.path.insert(0, %r); import bench; from paper_1711_01228_amd import inputs; "
+            "g, X0 = inputs.ba65536(%d, n=%d); rows = np.sort(np.random.default_rng(1).choice(g.n, 64, replace=False)); "
+            "print(bench._oracle_rows_rate(g, X0, rows)[0])" % (ROOT, X0.shape[1], n))
     try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
-    except OSError:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        out = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             env=env, text=True, timeout=300)
+        one = float(out.stdout.strip().splitlines()[-1])
+    except (OSError, ValueError, IndexError, subprocess.SubprocessError):
         pass
-    return {"value": rate, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle", "host_cpu": model,
+    return {"value": rate, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle", "host": host_cpu(),
             "sample": "FP64 Jacobi step (eq. 5 row solves) for %d random rows x all %d columns of the same "
-                      "BA graph and start, %.1f s; distance rows (BFS) not timed" % (R, n, dt),
+                      "BA graph and start, %.1f s on %d threads; distance rows (BFS) found in blocks of 512 rows "
+                      "and not timed" % (R, n, dt, cores),
+            "value_1_thread": one,
             "seconds_per_jacobi_step": float(n) * (n - 1) / rate}
+
+
+def _oracle_runs_seconds(cases, threads=None):
+    """Seconds of the oracle's Algorithm 2 run for each case (config, run, omega,
+    tol, max_iter), in this process or, with `threads`, in a child process with
+    OMP_NUM_THREADS = threads.  Returns [(seconds, iterations), ...]."""
+    import subprocess
+
+    if threads is not None:
+        code = ("import sys, json; sys.path.insert(0, %r); import bench; "
+                "print(json.dumps(bench._oracle_runs_seconds(%r)))" % (ROOT, cases))
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        out = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             env=env, text=True, timeout=3000)
+        return json.loads(out.stdout.strip().splitlines()[-1])
+    import oracle
+    from paper_1711_01228_amd import inputs
+
+    res = []
+    for config, run, omega, tol, max_iter in cases:
+        g, X0 = inputs.grid16(run) if config == 1 else inputs.er4096(run)
+        D = oracle.apsp(g.row_ptr, g.col_idx)  # distances once per graph, not timed
+        t = time.perf_counter()
+        _, info = oracle.layout(D, X0, omega=omega, tol=tol, max_iter=max_iter)
+        res.append((time.perf_counter() - t, info["iterations"]))
+    return res
+
+
+def bench_small_configs(seeds=20, full_oracle=False):
+    """The grid (16 x 16, 200 iterations at omega 1 and 1.5) and Erdos-Renyi
+    (n = 4096, mean degree 6, to res <= 1e-3 or 2,000 iterations over the omega
+    sweep 1.0 .. 1.6) workloads over `seeds` seeds each (config c, run r: seed
+    1000 c + r).  GPU: us per iteration (launch-bound sizes: device time of the
+    run over its iterations) and time to tol (wall, plan excluded, one untimed
+    run first); medians over the seeds.  Beside them the FP64 oracle runs the same
+    layouts to the end on all threads of this process (the grid: every seed;
+    Erdos-Renyi: seed 0 of every omega) and on one thread (the grid: every seed;
+    Erdos-Renyi seed 0 at omega 1 only with full_oracle)."""
+    import numpy as np
+    import torch
+
+    from paper_1711_01228_amd import binding, inputs
+
+    out = {"seeds": seeds}
+    # ---- grid 16 x 16, 200 iterations
+    c1 = {}
+    for om in (1.0, 1.5):
+        us, wall = [], []
+        for r in range(seeds):
+            g, X0 = inputs.grid16(r)
+            Xd0 = torch.tensor(X0.astype(np.float32), device="cuda")
+            with binding.Plan(g, 2) as plan:
+                plan.run(Xd0.clone(), omega=om, tol=0.0, max_iter=200)
+                X = Xd0.clone()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                info = plan.run(X, omega=om, tol=0.0, max_iter=200, final_stress=False)
+                torch.cuda.synchronize()
+                wall.append(time.perf_counter() - t)
+                us.append(1e3 * info["run_ms"] / info["iterations"])
+        c1["omega=%g" % om] = {"us_per_iteration_median": round(float(np.median(us)), 2),
+                               "us_per_iteration_range": [round(float(min(us)), 2), round(float(max(us)), 2)],
+                               "seconds_200_iterations_median": round(float(np.median(wall)), 5)}
+    out["grid16"] = c1
+    # ---- Erdos-Renyi n = 4096 to tol
+    c2 = {}
+    omegas = (1.0, 1.2, 1.4, 1.6)
+    per = {om: {"s": [], "it": [], "conv": 0} for om in omegas}
+    for r in range(seeds):
+        g, X0 = inputs.er4096(r)
+        Xd0 = torch.tensor(X0.astype(np.float32), device="cuda")
+        with binding.Plan(g, 2) as plan:
+            for om in omegas:
+                plan.run(Xd0.clone(), omega=om, tol=1e-3, max_iter=2000)
+                X = Xd0.clone()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                info = plan.run(X, omega=om, tol=1e-3, max_iter=2000, final_stress=False)
+                torch.cuda.synchronize()
+                per[om]["s"].append(time.perf_counter() - t)
+                per[om]["it"].append(info["iterations"])
+                per[om]["conv"] += int(info["converged"])
+    base = np.array(per[1.0]["s"])
+    for om in omegas:
+        sec, it = np.array(per[om]["s"]), np.array(per[om]["it"])
+        c2["omega=%g" % om] = {"seconds_to_tol_median": round(float(np.median(sec)), 5),
+                               "iterations_median": float(np.median(it)),
+                               "us_per_iteration_median": round(float(np.median(1e6 * sec / it)), 2),
+                               "converged": "%d/%d" % (per[om]["conv"], seeds),
+                               "speedup_vs_omega1_median": round(float(np.median(base / sec)), 3)}
+    out["er4096"] = c2
+    # ---- the oracle beside it
+    cases1 = [(1, r, om, 0.0, 200) for om in (1.0, 1.5) for r in range(seeds)]
+    cases2 = [(2, 0, om, 1e-3, 2000) for om in omegas]
+    orc = {"threads": oracle_threads(), "host": host_cpu()}
+    t1 = _oracle_runs_seconds(cases1)
+    orc["grid16_seconds_median"] = {"omega=%g" % om: round(float(np.median([t for (c, r, o, _, _), (t, _) in
+                                                                           zip(cases1, t1) if o == om])), 5)
+                                    for om in (1.0, 1.5)}
+    t1s = _oracle_runs_seconds(cases1, threads=1)
+    orc["grid16_seconds_median_1_thread"] = {"omega=%g" % om: round(float(np.median(
+        [t for (c, r, o, _, _), (t, _) in zip(cases1, t1s) if o == om])), 5) for om in (1.0, 1.5)}
+    t2 = _oracle_runs_seconds(cases2)
+    orc["er4096_seed0"] = {"omega=%g" % om: {"seconds_to_tol": round(t, 3), "iterations": it}
+                           for om, (t, it) in zip(omegas, t2)}
+    if full_oracle:
+        (t, it), = _oracle_runs_seconds([(2, 0, 1.0, 1e-3, 2000)], threads=1)
+        orc["er4096_seed0_1_thread"] = {"omega=1": {"seconds_to_tol": round(t, 3), "iterations": it}}
+    out["oracle"] = orc
+    return out
 
 
 def bench_batch(omega, count=2048):
@@ -223,7 +437,7 @@ def bench_strategies(plan, Xdev0, n):
     cases = {
         "fixed omega=1.5": dict(omega=1.5),
         "fixed omega=2.5": dict(omega=2.5),
-        "probabilistic (seed 5)": dict(strategy="schedule", omega_schedule=binding.auto_schedule(3000, 5)),
+        "probabilistic (seed 5)": dict(strategy="auto", seed=5),
         "enumerating": dict(strategy="enum"),
         "per-vertex omega_i ~ U[1,2] (seed 77)": dict(
             omega_vertex=torch.tensor(rng.uniform(1.0, 2.0, n).astype(np.float32), device="cuda")),
@@ -345,6 +559,9 @@ def main():
     ap.add_argument("--no-strategies", action="store_true", help="skip the relaxation-strategy comparison")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-step (eq. 5 solved) comparison")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the grid / Erdos-Renyi workloads over 20 seeds")
+    ap.add_argument("--full-oracle", action="store_true",
+                    help="also run the oracle on one thread to convergence on the Erdos-Renyi workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -419,6 +636,9 @@ def main():
                 "step_kernel_ms": {k: round(v, 4) for k, v in ms.items()},
                 "measured_ceilings": measured_ceilings()}
     roofline["frac_of_measured_fma"] = round(achieved / roofline["measured_ceilings"]["fp32_fma_TFLOPs"], 4)
+    roofline["valu"] = measured_valu(dim, sym, n)
+    if roofline["traffic"]:
+        roofline["traffic_over_algorithmic"] = round(roofline["traffic"] / abytes, 3)
     log("kernels (ms):", ms)
     log("measured ceilings:", roofline["measured_ceilings"])
 
@@ -472,6 +692,10 @@ def main():
     if not args.quick and not args.no_diff:
         out["differentiation"] = bench_diff()
         log("differentiation:", out["differentiation"])
+    # ---- the small workloads over 20 seeds, the oracle beside them
+    if not args.quick and not args.no_small:
+        out["small_configs"] = bench_small_configs(full_oracle=args.full_oracle)
+        log("small configs:", out["small_configs"])
     # ---- batched: 2,048 small graphs, one persistent launch, each to its own tol
     if not args.quick and not args.no_batch:
         out["batched"] = bench_batch(args.omega)

@@ -67,14 +67,21 @@ typedef enum {
  *   [4] f(X^k)                     stress at the iterate the step starts from
  *                                  (NaN unless SL_FLAG_TRACE_STRESS)                */
 
-/* Relaxation strategies (Sec. 5.2; per-vertex factors: Sec. 6, item 1). */
+/* Relaxation strategies (Sec. 5.2; per-vertex factors: Sec. 6, item 1).  Iterations
+ * are numbered globally: iteration k of a call is iteration g = iter_offset + k. */
 #define SL_OMEGA_FIXED 0     /* `omega` every iteration                                  */
-#define SL_OMEGA_SCHEDULE 1  /* omega_schedule[k] at iteration k (the probabilistic
-                                strategy draws this sequence by roulette; the draws are
-                                the caller's input)                                       */
+#define SL_OMEGA_SCHEDULE 1  /* omega_schedule[g] at iteration g (a caller's sequence)   */
 #define SL_OMEGA_ENUM 2      /* the paper's factor c = omega - 1 chosen each iteration as
                                 the argmin of f(X^H + c (X^H - X^k)) over
                                 c in {0, 0.5, ..., 9}; c = 0 keeps X^H (counted rejected) */
+#define SL_OMEGA_AUTO 3      /* the probabilistic strategy (Sec. 5.2): the paper's factor of
+                                iteration g is drawn by roulette from {0.5, 1.0, 1.5, 2.0}
+                                with probabilities 0.3, 0.3, 0.2, 0.2, from the uniform
+                                u = (z >> 11) 2^-53, z = output number g (from 0) of
+                                SplitMix64 seeded with `seed` (Steele, Lea and Flood,
+                                OOPSLA 2014): u < 0.3 -> 0.5, u < 0.6 -> 1.0,
+                                u < 0.8 -> 1.5, else 2.0.  A run resumed with iter_offset
+                                continues the sequence                                    */
 
 /* Orderings of the step H (eq. 5). */
 #define SL_ORDER_JACOBI 0    /* one Jacobi sweep: X^H = X^k + F / W                       */
@@ -145,10 +152,12 @@ typedef struct {
                                doubles, row k written by iteration k               */
   float* xtrace;            /* NULL or device buffer of max_iter * n * dim floats:
                                the placement after every iteration                  */
-  int32_t strategy;         /* SL_OMEGA_FIXED (default), SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM */
+  int32_t strategy;         /* SL_OMEGA_FIXED (default), SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM,
+                               SL_OMEGA_AUTO                                        */
   int32_t reserved2;
-  const double* omega_schedule; /* host, max_iter classical factors in (0, 16]
-                                   (SL_OMEGA_SCHEDULE), else NULL                  */
+  const double* omega_schedule; /* host, iter_offset + max_iter classical factors: entries
+                                   iter_offset .. iter_offset + max_iter - 1 are read and
+                                   must lie in (0, 16] (SL_OMEGA_SCHEDULE), else NULL */
   const float* omega_vertex;    /* NULL, or device, n classical factors in (0, 16]: vertex i
                                    extrapolates by omega_vertex[i] - 1 (SL_OMEGA_FIXED only;
                                    `omega` is then unused)                           */
@@ -157,6 +166,11 @@ typedef struct {
   int32_t inner_max_iter;   /* SL_ORDER_EXACT: conjugate-gradient steps per solve, >= 0;
                                0 selects 500                                         */
   int32_t reserved3;
+  uint64_t seed;            /* SL_OMEGA_AUTO: seed of the roulette's generator       */
+  int64_t iter_offset;      /* >= 0: global number of this call's first iteration, for
+                               resuming a run from its returned placement: the factor
+                               schedule and the probabilistic draws continue from there
+                               (trace rows stay local: row k is iteration iter_offset + k) */
 } sl_options;
 
 typedef struct {
@@ -169,11 +183,17 @@ typedef struct {
                                SL_FLAG_NO_FINAL_STRESS)                           */
   double plan_ms;           /* time of sl_plan_create (sl_layout: distances+weights) */
   double run_ms;            /* device time of the iteration loop                  */
+  double rel_stress_drop;   /* (f(X^{K-1}) - f(X^K)) / f(X^{K-1}) over the last
+                               iteration K of the call: the relative stress decrease
+                               the paper's "rel err" column (Table 1) is read as; NaN
+                               with SL_FLAG_NO_FINAL_STRESS, when no iteration ran or
+                               f(X^{K-1}) = 0                                         */
 } sl_result;
 
 typedef struct sl_plan sl_plan;
 
-/* Fill `opt` with defaults: dim 2, omega 1, tol 1e-3, max_iter 1000, safeguard 1. */
+/* Fill `opt` with defaults: dim 2, omega 1, tol 1e-3, max_iter 1000, safeguard 1,
+ * everything else 0 / NULL. */
 void sl_default_options(sl_options* opt);
 
 /* Check a graph and options on the host, with no HIP call.  `opt` may be NULL
@@ -338,19 +358,6 @@ sl_status sl_batch_plan_run(sl_batch_plan* plan, float* X, const sl_options* opt
                             sl_result* total);
 
 sl_status sl_batch_plan_destroy(sl_batch_plan* plan);
-
-/* Calibration of the roofline (not an operation of the method): the rate at
- * which this device issues one instruction kind, for comparing the force
- * pass against what the hardware sustains rather than only its data sheet.
- *   kind 0: FP32 FMA (the library is built without packed FP32, so this is
- *           the attainable vector FP32 rate; an FMA is 2 flops)
- *   kind 1, 2, 3: rsq, sqrt, rcp (the transcendentals of the force and
- *           safeguard terms)
- * One launch of 8 waves per SIMD on `stream`, each lane running 8
- * independent chains, timed with HIP events after one untimed launch.
- * *per_s: lane operations per second; *ms: the timed launch.  Allocates and
- * frees a 2 MiB result buffer.  SL_EINVAL for another kind or NULL outputs. */
-sl_status sl_probe_rate(int32_t kind, void* stream, double* per_s, double* ms);
 
 /* layout(G, X0, omega, tol, max_iter) -> X: sl_plan_create + sl_plan_run +
  * sl_plan_destroy. */

@@ -87,6 +87,10 @@ def _load():
                 "slo_stress_grad": (None, [i32, i32, P, P, P]),
                 "slo_layout_vjp": (ctypes.c_int, [i32, i32, P, P, f64, i32, P, P, P, P]),
                 "slo_edge_grad": (ctypes.c_int, [i32, P, P, P, P, P]),
+                "slo_h_jacobi_graph": (ctypes.c_int, [i32, i32, P, P, P, P, P]),
+                "slo_stress_delta_graph": (ctypes.c_int, [i32, i32, P, P, P, P, P, P, P]),
+                "slo_splitmix64": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
+                "slo_auto_factors": (None, [ctypes.c_uint64, ctypes.c_int64, i32, P]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(lib, name)
@@ -168,6 +172,17 @@ def stress_delta(D, XA, XB):
     return a.value, b.value
 
 
+def stress_delta_graph(row_ptr, col_idx, XA, XB, lengths=None):
+    """stress_delta with each distance row found from the graph when needed."""
+    lib = _load()
+    rp, ci, ln = _csr(row_ptr, col_idx, lengths)
+    XA, XB = _f64(XA), _f64(XB)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib.slo_stress_delta_graph(XA.shape[0], XA.shape[1], _p(rp), _p(ci), _p(ln), _p(XA), _p(XB),
+                                      ctypes.byref(a), ctypes.byref(b)), "stress_delta_graph")
+    return a.value, b.value
+
+
 def apply_LW(D, X) -> np.ndarray:
     lib = _load()
     D, X = _f64(D), _f64(X)
@@ -209,6 +224,17 @@ def h_jacobi_rows(Drows, rows, X) -> np.ndarray:
     out = np.empty((len(rows), X.shape[1]), dtype=np.float64)
     lib.slo_h_jacobi_rows(X.shape[0], X.shape[1], _p(Drows), _p(rows), len(rows), _p(X), _p(out))
     return out
+
+
+def h_jacobi_graph(row_ptr, col_idx, X, lengths=None) -> np.ndarray:
+    """X^H of the Jacobi step for every vertex, each distance row found from
+    the graph when it is needed (no n x n matrix): equals h_jacobi(apsp(...), X)."""
+    lib = _load()
+    rp, ci, ln = _csr(row_ptr, col_idx, lengths)
+    X = _f64(X)
+    XH = np.empty_like(X)
+    _check(lib.slo_h_jacobi_graph(X.shape[0], X.shape[1], _p(rp), _p(ci), _p(ln), _p(X), _p(XH)), "h_jacobi_graph")
+    return XH
 
 
 def h_gauss_seidel(D, X) -> np.ndarray:
@@ -288,6 +314,21 @@ def layout(D, X0, omega=1.0, tol=1e-3, max_iter=200, ordering="jacobi", safeguar
 # 0.5, 1.0, 1.5, 2.0 with probabilities 0.3, 0.3, 0.2, 0.2.
 AUTO_FACTORS = (0.5, 1.0, 1.5, 2.0)
 AUTO_PROBS = (0.3, 0.3, 0.2, 0.2)
+
+
+def splitmix64(seed: int, g: int) -> int:
+    """Output number g (from 0) of SplitMix64 seeded with seed."""
+    return int(_load().slo_splitmix64(int(seed) & (2 ** 64 - 1), int(g)))
+
+
+def auto_factors(seed: int, first: int, count: int) -> np.ndarray:
+    """The paper's factors the probabilistic strategy draws at iterations
+    first .. first + count - 1 (SplitMix64 variate of the iteration index)."""
+    out = np.empty(max(int(count), 0), dtype=np.float64)
+    _load().slo_auto_factors(int(seed) & (2 ** 64 - 1), int(first), int(count), _p(out))
+    return out
+
+
 ENUM_FACTORS = tuple(0.5 * c for c in range(19))
 
 

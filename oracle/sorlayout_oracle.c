@@ -205,28 +205,32 @@ double slo_stress(int32_t n, int32_t dim, const double* D, const double* X) {
 
 /* f(XA) - f(XB), summed pair by pair as sum_{i<j} [w(rA-d)^2 - w(rB-d)^2],
  * plus the scale sum_{i<j} |w(rA-d)^2 - w(rB-d)^2| of that sum: the
- * comparison of Algorithm 2 (line 6) and the size of the terms it rests on. */
+ * comparison of Algorithm 2 (line 6) and the size of the terms it rests on.
+ * Row i's share (pairs j > i) from its distance row drow. */
+static void stress_delta_row(int32_t n, int32_t dim, const double* drow, int32_t i, const double* XA,
+                             const double* XB, double* sd_out, double* ss_out) {
+  double sd = 0.0, ss = 0.0;
+  for (int32_t j = i + 1; j < n; ++j) {
+    double d = drow[j];
+    double w = w_of(d);
+    if (w == 0.0) continue;
+    double ea = dist(dim, XA + (size_t)i * dim, XA + (size_t)j * dim) - d;
+    double eb = dist(dim, XB + (size_t)i * dim, XB + (size_t)j * dim) - d;
+    double t = w * ea * ea - w * eb * eb;
+    sd += t;
+    ss += fabs(t);
+  }
+  *sd_out = sd;
+  *ss_out = ss;
+}
+
 void slo_stress_delta(int32_t n, int32_t dim, const double* D, const double* XA, const double* XB,
                       double* delta, double* scale) {
   double* pd = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
   double* ps = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
   if (!pd || !ps) { free(pd); free(ps); *delta = NAN; *scale = NAN; return; }
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int32_t i = 0; i < n; ++i) {
-    double sd = 0.0, ss = 0.0;
-    for (int32_t j = i + 1; j < n; ++j) {
-      double d = D[(size_t)i * n + j];
-      double w = w_of(d);
-      if (w == 0.0) continue;
-      double ea = dist(dim, XA + (size_t)i * dim, XA + (size_t)j * dim) - d;
-      double eb = dist(dim, XB + (size_t)i * dim, XB + (size_t)j * dim) - d;
-      double t = w * ea * ea - w * eb * eb;
-      sd += t;
-      ss += fabs(t);
-    }
-    pd[i] = sd;
-    ps[i] = ss;
-  }
+  for (int32_t i = 0; i < n; ++i) stress_delta_row(n, dim, D + (size_t)i * n, i, XA, XB, pd + i, ps + i);
   double a = 0.0, b = 0.0;
   for (int32_t i = 0; i < n; ++i) { a += pd[i]; b += ps[i]; }
   *delta = a;
@@ -828,4 +832,104 @@ int slo_edge_grad(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, con
   memcpy(glen, ge, sizeof(double) * (size_t)nnz);
   free(ge);
   return SLO_OK;
+}
+
+/* ====================================================================== */
+/* Graph forms for layouts too large for an n x n distance matrix.         */
+/* Each row's distances come from the graph (slo_sssp) when the row is     */
+/* needed and are dropped after it, so memory is O(n) per thread.  Every   */
+/* row is the same row function as the matrix form, and row sums are added */
+/* in the same order, so the results equal the matrix forms bit for bit.   */
+/* ====================================================================== */
+
+/* X^H of the Jacobi step (eq. 5, one sweep from X) for every vertex. */
+int slo_h_jacobi_graph(int32_t n, int32_t dim, const int64_t* row_ptr, const int32_t* col_idx, const double* len,
+                       const double* X, double* XH) {
+  int status = SLO_OK;
+#pragma omp parallel
+  {
+    double* drow = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!drow) {
+#pragma omp critical
+      status = SLO_ENOMEM;
+    }
+#pragma omp for schedule(dynamic, 64)
+    for (int32_t i = 0; i < n; ++i) {
+      if (!drow) continue;
+      int r = slo_sssp(n, row_ptr, col_idx, len, i, drow);
+      if (r != SLO_OK) {
+#pragma omp critical
+        status = r;
+        continue;
+      }
+      slo_h_jacobi_row(n, dim, drow, i, X, XH + (size_t)i * dim);
+    }
+    free(drow);
+  }
+  return status;
+}
+
+/* f(XA) - f(XB) and its term scale, as slo_stress_delta. */
+int slo_stress_delta_graph(int32_t n, int32_t dim, const int64_t* row_ptr, const int32_t* col_idx, const double* len,
+                           const double* XA, const double* XB, double* delta, double* scale) {
+  double* pd = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* ps = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  int status = SLO_OK;
+  if (!pd || !ps) { free(pd); free(ps); return SLO_ENOMEM; }
+#pragma omp parallel
+  {
+    double* drow = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!drow) {
+#pragma omp critical
+      status = SLO_ENOMEM;
+    }
+#pragma omp for schedule(dynamic, 64)
+    for (int32_t i = 0; i < n; ++i) {
+      if (!drow) continue;
+      int r = slo_sssp(n, row_ptr, col_idx, len, i, drow);
+      if (r != SLO_OK) {
+#pragma omp critical
+        status = r;
+        continue;
+      }
+      stress_delta_row(n, dim, drow, i, XA, XB, pd + i, ps + i);
+    }
+    free(drow);
+  }
+  double a = 0.0, b = 0.0;
+  for (int32_t i = 0; i < n; ++i) { a += pd[i]; b += ps[i]; }
+  *delta = a;
+  *scale = b;
+  free(pd);
+  free(ps);
+  return status;
+}
+
+/* ====================================================================== */
+/* Probabilistic strategy (Sec. 5.2): the paper's factor of each iteration */
+/* is drawn by roulette from {0.5, 1.0, 1.5, 2.0} with probabilities       */
+/* 0.3, 0.3, 0.2, 0.2.  The draw of iteration g (counted from the start of */
+/* the layout, so a resumed run continues the sequence) uses the uniform   */
+/* variate u = (z >> 11) * 2^-53, z = the output number g (from 0) of the   */
+/* SplitMix64 generator seeded with `seed` (Steele, Lea and Flood, "Fast    */
+/* splittable pseudorandom number generators", OOPSLA 2014):               */
+/*   state_g = seed + (g + 1) * 0x9E3779B97F4A7C15 (mod 2^64), then the    */
+/*   finalizer z ^= z >> 30; z *= 0xBF58476D1CE4E5B9; z ^= z >> 27;         */
+/*   z *= 0x94D049BB133111EB; z ^= z >> 31.                                 */
+/* The roulette takes the first factor whose cumulative probability        */
+/* exceeds u: u < 0.3 -> 0.5, u < 0.6 -> 1.0, u < 0.8 -> 1.5, else 2.0.     */
+/* ====================================================================== */
+uint64_t slo_splitmix64(uint64_t seed, uint64_t g) {
+  uint64_t z = seed + (g + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* out[k] = the paper's factor of iteration first + k, k < count. */
+void slo_auto_factors(uint64_t seed, int64_t first, int32_t count, double* out) {
+  for (int32_t k = 0; k < count; ++k) {
+    const double u = (double)(slo_splitmix64(seed, (uint64_t)(first + k)) >> 11) * 0x1.0p-53;
+    out[k] = u < 0.3 ? 0.5 : u < 0.6 ? 1.0 : u < 0.8 ? 1.5 : 2.0;
+  }
 }

@@ -63,11 +63,12 @@ class DifferentiableLayout:
 
 class UnrolledLayout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, X0, lengths, layout, omega, iters, ckpt_every, safeguard):
+    def forward(ctx, X0, lengths, layout, omega, iters, ckpt_every, safeguard, force):
         if lengths is not None:
             layout.set_lengths(lengths.detach().float().cpu().numpy())
         X = X0.detach().to(device="cuda", dtype=torch.float32).contiguous().clone()
-        info = layout.plan.unroll(X, omega=omega, iters=iters, ckpt_every=ckpt_every, safeguard=safeguard)
+        info = layout.plan.unroll(X, omega=omega, iters=iters, ckpt_every=ckpt_every, safeguard=safeguard,
+                                  sym_force=force == "unordered", ordered_force=force == "ordered")
         ctx.layout = layout
         ctx.has_len = lengths is not None
         ctx.info = info
@@ -85,7 +86,7 @@ class UnrolledLayout(torch.autograd.Function):
         glen = None
         if glen_csr is not None:
             glen = glen_csr[torch.as_tensor(lay.entry_fwd, device=G.device)]
-        return gX0, glen, None, None, None, None, None
+        return gX0, glen, None, None, None, None, None, None
 
 
 class StressLoss(torch.autograd.Function):
@@ -106,8 +107,14 @@ class StressLoss(torch.autograd.Function):
 
 
 def unrolled_layout(X0, lengths, layout: DifferentiableLayout, omega=1.5, iters=100, ckpt_every=10,
-                    safeguard=True):
-    return UnrolledLayout.apply(X0, lengths, layout, float(omega), int(iters), int(ckpt_every), bool(safeguard))
+                    safeguard=True, force="default"):
+    """force: the force pass of the forward and backward, "default" (the
+    library's choice by size), "unordered" (once per unordered pair) or
+    "ordered" (every ordered pair)."""
+    if force not in ("default", "unordered", "ordered"):
+        raise ValueError("force must be 'default', 'unordered' or 'ordered'")
+    return UnrolledLayout.apply(X0, lengths, layout, float(omega), int(iters), int(ckpt_every), bool(safeguard),
+                                force)
 
 
 def stress_loss(X, layout: DifferentiableLayout):

@@ -25,25 +25,16 @@ SL_FLAG_SYM_FORCE = 4
 SL_FLAG_SEPARATE_SAFEGUARD = 8
 SL_FLAG_ORDERED_FORCE = 16
 SL_FLAG_NO_FINAL_STRESS = 32
-SL_OMEGA_FIXED, SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM = 0, 1, 2
+SL_OMEGA_FIXED, SL_OMEGA_SCHEDULE, SL_OMEGA_ENUM, SL_OMEGA_AUTO = 0, 1, 2, 3
+STRATEGIES = {"fixed": SL_OMEGA_FIXED, "schedule": SL_OMEGA_SCHEDULE, "enum": SL_OMEGA_ENUM, "auto": SL_OMEGA_AUTO}
 SL_ORDER_JACOBI, SL_ORDER_EXACT = 0, 1
 ORDERINGS = {"jacobi": SL_ORDER_JACOBI, "exact": SL_ORDER_EXACT}
-# probabilistic strategy (Sec. 5.2): roulette over the paper's factors
-AUTO_FACTORS = (0.5, 1.0, 1.5, 2.0)
-AUTO_PROBS = (0.3, 0.3, 0.2, 0.2)
-
-
-def auto_schedule(max_iter: int, seed: int) -> np.ndarray:
-    """Classical factors 1 + c for max_iter iterations, c drawn by the paper's
-    roulette P(0.5) = P(1.0) = 0.3, P(1.5) = P(2.0) = 0.2 (seeded)."""
-    rng = np.random.Generator(np.random.PCG64(int(seed)))
-    return 1.0 + rng.choice(np.array(AUTO_FACTORS), size=int(max_iter), p=np.array(AUTO_PROBS))
 
 EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run", "sl_plan_stress",
             "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
             "sl_last_error", "sl_batch_plan_create", "sl_batch_plan_tune", "sl_batch_plan_run",
             "sl_batch_plan_destroy", "sl_plan_distance_rows_f32", "sl_plan_tree_rows", "sl_plan_set_lengths",
-            "sl_plan_stress_grad", "sl_plan_unroll", "sl_plan_unroll_backward", "sl_probe_rate")
+            "sl_plan_stress_grad", "sl_plan_unroll", "sl_plan_unroll_backward")
 SL_WEIGHTED_MAX_N = 16384
 SL_BATCH_MAX_N = 1024
 SL_BATCH_CLASSES = 16
@@ -66,7 +57,8 @@ class sl_options(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("ordering", ctypes.c_int32), ("trace", ctypes.c_void_p),
                 ("xtrace", ctypes.c_void_p), ("strategy", ctypes.c_int32), ("reserved2", ctypes.c_int32),
                 ("omega_schedule", ctypes.c_void_p), ("omega_vertex", ctypes.c_void_p),
-                ("inner_tol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32), ("reserved3", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("iter_offset", ctypes.c_int64)]
 
 
 class sl_batch(ctypes.Structure):
@@ -77,7 +69,7 @@ class sl_batch(ctypes.Structure):
 class sl_result(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("rejected", ctypes.c_int32),
                 ("inner_iterations", ctypes.c_int32), ("residual", ctypes.c_double), ("stress", ctypes.c_double),
-                ("plan_ms", ctypes.c_double), ("run_ms", ctypes.c_double)]
+                ("plan_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("rel_stress_drop", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -119,7 +111,6 @@ def _load():
         "sl_batch_plan_tune": (st, [P, P, ctypes.POINTER(sl_options), P, P]),
         "sl_batch_plan_run": (st, [P, P, ctypes.POINTER(sl_options), P, P, ctypes.POINTER(sl_result)]),
         "sl_batch_plan_destroy": (st, [P]),
-        "sl_probe_rate": (st, [i32, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -162,9 +153,9 @@ def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, chec
                  trace_stress=False, use_graph=True, trace=None, xtrace=None, strategy=SL_OMEGA_FIXED,
                  omega_schedule=None, omega_vertex=None, ordering=SL_ORDER_JACOBI, inner_tol=0.0,
                  inner_max_iter=0, sym_force=False, separate_safeguard=False, ordered_force=False,
-                 final_stress=True) -> sl_options:
-    """omega_schedule: host float64 array (kept alive by the caller);
-    omega_vertex: device pointer (int) or None."""
+                 final_stress=True, seed=0, iter_offset=0) -> sl_options:
+    """omega_schedule: host float64 array (kept alive by the caller), indexed by
+    the global iteration (iter_offset + k); omega_vertex: device pointer (int) or None."""
     o = sl_options()
     LIB.sl_default_options(ctypes.byref(o))
     o.dim, o.omega, o.tol, o.max_iter = int(dim), float(omega), float(tol), int(max_iter)
@@ -180,6 +171,7 @@ def make_options(dim=2, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, chec
     o.omega_vertex = None if omega_vertex is None else int(omega_vertex)
     o.ordering = int(ordering)
     o.inner_tol, o.inner_max_iter = float(inner_tol), int(inner_max_iter)
+    o.seed, o.iter_offset = int(seed) & (2 ** 64 - 1), int(iter_offset)
     return o
 
 
@@ -283,16 +275,6 @@ def sl_plan_destroy(plan: int) -> None:
     _check(LIB.sl_plan_destroy(plan))
 
 
-PROBE_KINDS = {"fma": 0, "rsq": 1, "sqrt": 2, "rcp": 3}
-
-
-def sl_probe_rate(kind: str, stream=None) -> tuple:
-    """(lane operations per second, ms) of one instruction kind on the device."""
-    per_s, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    _check(LIB.sl_probe_rate(PROBE_KINDS[kind], _stream_handle(stream), ctypes.byref(per_s), ctypes.byref(ms)))
-    return per_s.value, ms.value
-
-
 def sl_layout(g, X_ptr: int, opt: sl_options, stream=None) -> dict:
     ga = graph_args(g)
     res = sl_result()
@@ -313,13 +295,17 @@ class Plan:
     def run(self, X, omega=1.0, tol=1e-3, max_iter=1000, safeguard=True, check_every=0, trace=False,
             trace_stress=False, trace_positions=False, use_graph=True, stream=None, strategy="fixed",
             omega_schedule=None, omega_vertex=None, ordering="jacobi", inner_tol=0.0, inner_max_iter=0,
-            sym_force=False, separate_safeguard=False, ordered_force=False, final_stress=True):
+            sym_force=False, separate_safeguard=False, ordered_force=False, final_stress=True, seed=0,
+            iter_offset=0):
         """Run Algorithm 2 in place on the device tensor X (n x dim, float32).
 
         strategy: "fixed" (omega), "schedule" (omega_schedule, one classical
-        factor per iteration; see auto_schedule) or "enum" (argmin over the
-        paper's factors 0, 0.5, ..., 9); omega_vertex: optional device tensor
-        of n classical factors (fixed strategy).  ordering: "jacobi" (one
+        factor per global iteration), "auto" (the probabilistic strategy of
+        Sec. 5.2, drawn in the library from seed and the iteration number) or
+        "enum" (argmin over the paper's factors 0, 0.5, ..., 9); omega_vertex:
+        optional device tensor of n classical factors (fixed strategy).
+        iter_offset: global number of the first iteration, for resuming a run
+        (schedules and draws continue; trace rows stay local).  ordering: "jacobi" (one
         sweep of eq. 5) or "exact" (eq. 5 solved by conjugate gradients to
         inner_tol, at most inner_max_iter steps; 0 selects the defaults).
         sym_force / ordered_force: evaluate the force pass once per unordered
@@ -342,17 +328,18 @@ class Plan:
             tr = torch.full((max(max_iter, 1), SL_TRACE_COLS), float("nan"), dtype=torch.float64, device=X.device)
         if trace_positions:
             xt = torch.zeros((max(max_iter, 1), self.n, self.dim), dtype=torch.float32, device=X.device)
-        strat = {"fixed": SL_OMEGA_FIXED, "schedule": SL_OMEGA_SCHEDULE, "enum": SL_OMEGA_ENUM}[strategy]
+        strat = STRATEGIES[strategy]
         sched = None if omega_schedule is None else np.ascontiguousarray(omega_schedule, dtype=np.float64)
-        if sched is not None and len(sched) < max_iter:
-            raise ValueError("omega_schedule needs max_iter entries")
+        if sched is not None and len(sched) < iter_offset + max_iter:
+            raise ValueError("omega_schedule needs iter_offset + max_iter entries")
         wv = None
         if omega_vertex is not None:
             wv = omega_vertex.to(device=X.device, dtype=torch.float32).contiguous()
         opt = make_options(self.dim, omega, tol, max_iter, safeguard, check_every, trace_stress, use_graph,
                            None if tr is None else tr.data_ptr(), None if xt is None else xt.data_ptr(),
                            strat, sched, None if wv is None else wv.data_ptr(), ORDERINGS[ordering], inner_tol,
-                           inner_max_iter, sym_force, separate_safeguard, ordered_force, final_stress)
+                           inner_max_iter, sym_force, separate_safeguard, ordered_force, final_stress, seed,
+                           iter_offset)
         info = sl_plan_run(self.handle, X.data_ptr(), opt, stream)
         k = info["iterations"]
         if tr is not None:
@@ -384,9 +371,12 @@ class Plan:
         """f(X) (eq. 1) and its gradient into the device tensor G (n x dim)."""
         return sl_plan_stress_grad(self.handle, X.data_ptr(), self.dim, G.data_ptr(), stream)
 
-    def unroll(self, X, omega=1.5, iters=100, ckpt_every=10, safeguard=True, stream=None) -> dict:
-        """Exactly `iters` iterations in place on X, keeping the tape for unroll_backward."""
-        opt = make_options(self.dim, omega, 0.0, iters, safeguard)
+    def unroll(self, X, omega=1.5, iters=100, ckpt_every=10, safeguard=True, sym_force=False, ordered_force=False,
+               stream=None) -> dict:
+        """Exactly `iters` iterations in place on X, keeping the tape for
+        unroll_backward; sym_force / ordered_force pick the force pass of the
+        forward and the backward (default: the library's choice by size)."""
+        opt = make_options(self.dim, omega, 0.0, iters, safeguard, sym_force=sym_force, ordered_force=ordered_force)
         return sl_plan_unroll(self.handle, X.data_ptr(), opt, ckpt_every, stream)
 
     def unroll_backward(self, G, gX0, glen=None, stream=None) -> None:
@@ -520,3 +510,4 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+

@@ -1,4 +1,5 @@
-"""Build libsorlayout.so (HIP for gfx950) in place.
+"""Build libsorlayout.so (HIP for gfx950) and the benchmark's calibration
+library libslprobe.so in place.
 
 usage: python -m paper_1711_01228_amd.build_lib [--force]
 """
@@ -16,7 +17,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsorlayout.so")
 SOURCES = [os.path.join(CSRC, "sl_kernels.hip"), os.path.join(CSRC, "sl_apsp.hip"), os.path.join(CSRC, "sl_batch.hip"),
            os.path.join(CSRC, "sl_exact.hip"), os.path.join(CSRC, "sl_weighted.hip"), os.path.join(CSRC, "sl_diff.hip"),
-           os.path.join(CSRC, "sl_sym.hip"), os.path.join(CSRC, "sl_probe.hip"), os.path.join(CSRC, "sl_api.hip")]
+           os.path.join(CSRC, "sl_sym.hip"), os.path.join(CSRC, "sl_api.hip")]
+PROBE_LIB = os.path.join(PKG, "libslprobe.so")
+PROBE_SOURCES = [os.path.join(CSRC, "sl_probe.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, "sl_internal.h"), os.path.join(CSRC, "sl_device.h"),
                   os.path.join(INCLUDE, "sorlayout.h")]
 ARCH = "gfx950"
@@ -29,13 +32,13 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def command(out: str = LIB) -> list:
+def command(out: str = LIB, sources=None) -> list:
     return [
         hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
         # packed FP32 instructions stay off: ordinary float code only
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-I", INCLUDE, "-I", CSRC, "-o", out,
-    ] + SOURCES
+    ] + (SOURCES if sources is None else sources)
 
 
 def stale() -> bool:
@@ -45,12 +48,9 @@ def stale() -> bool:
     return any(os.path.getmtime(p) > t for p in DEPS)
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
-    """Compile the library (always when force, else only when sources are newer)."""
-    if not force and not stale():
-        return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = command(tmp)
+def _compile(lib: str, sources: list, verbose: bool) -> None:
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = command(tmp, sources)
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -59,7 +59,16 @@ def build(force: bool = True, verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed (%d):\n%s" % (proc.returncode, "\n".join(lines)))
     if verbose and lines:
         print("\n".join(lines), flush=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    """Compile both libraries (always when force, else only when sources are newer)."""
+    if force or stale():
+        _compile(LIB, SOURCES, verbose)
+    if force or not os.path.exists(PROBE_LIB) or \
+            os.path.getmtime(PROBE_LIB) < max(os.path.getmtime(p) for p in PROBE_SOURCES):
+        _compile(PROBE_LIB, PROBE_SOURCES, verbose)
     return LIB
 
 

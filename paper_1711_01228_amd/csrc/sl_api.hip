@@ -17,15 +17,20 @@ using namespace sl;
 
 namespace {
 
-thread_local std::string g_err;
+// The calling thread's last error message: a fixed buffer, so that reporting an
+// error allocates nothing.
+struct ErrorText {
+  char text[512] = {0};
+  void clear() { text[0] = 0; }
+  const char* c_str() const { return text; }
+};
+thread_local ErrorText g_err;
 
 sl_status fail(sl_status st, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err.text, sizeof g_err.text, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return st;
 }
 
@@ -114,18 +119,23 @@ sl_status check_options(const sl_options* o) {
   if (o->flags & ~(SL_FLAG_TRACE_STRESS | SL_FLAG_NO_GRAPH | SL_FLAG_SYM_FORCE | SL_FLAG_SEPARATE_SAFEGUARD |
                    SL_FLAG_ORDERED_FORCE | SL_FLAG_NO_FINAL_STRESS))
     return fail(SL_EINVAL, "unknown flag bits");
-  if (o->strategy != SL_OMEGA_FIXED && o->strategy != SL_OMEGA_SCHEDULE && o->strategy != SL_OMEGA_ENUM)
+  if (o->strategy != SL_OMEGA_FIXED && o->strategy != SL_OMEGA_SCHEDULE && o->strategy != SL_OMEGA_ENUM &&
+      o->strategy != SL_OMEGA_AUTO)
     return fail(SL_EINVAL, "unknown relaxation strategy %d", o->strategy);
+  if (o->iter_offset < 0 || o->iter_offset > (int64_t)INT32_MAX * 64)
+    return fail(SL_EINVAL, "iter_offset = %lld outside [0, 2^37]", (long long)o->iter_offset);
   if (o->strategy == SL_OMEGA_SCHEDULE) {
     if (!o->omega_schedule && o->max_iter > 0) return fail(SL_EINVAL, "SL_OMEGA_SCHEDULE needs omega_schedule");
-    for (int k = 0; k < o->max_iter; ++k)
-      if (!(std::isfinite(o->omega_schedule[k]) && o->omega_schedule[k] > 0.0 && o->omega_schedule[k] <= 16.0))
-        return fail(SL_EINVAL, "omega_schedule[%d] = %g outside (0, 16]", k, o->omega_schedule[k]);
+    for (int64_t g = o->iter_offset; g < o->iter_offset + o->max_iter; ++g)
+      if (!(std::isfinite(o->omega_schedule[g]) && o->omega_schedule[g] > 0.0 && o->omega_schedule[g] <= 16.0))
+        return fail(SL_EINVAL, "omega_schedule[%lld] = %g outside (0, 16]", (long long)g, o->omega_schedule[g]);
   } else if (o->omega_schedule) {
     return fail(SL_EINVAL, "omega_schedule is only read with SL_OMEGA_SCHEDULE");
   }
   if (o->omega_vertex && o->strategy != SL_OMEGA_FIXED)
     return fail(SL_EINVAL, "per-vertex factors need SL_OMEGA_FIXED");
+  if (o->seed != 0 && o->strategy != SL_OMEGA_AUTO)
+    return fail(SL_EINVAL, "seed is only read with SL_OMEGA_AUTO");
   if (o->ordering != SL_ORDER_JACOBI && o->ordering != SL_ORDER_EXACT)
     return fail(SL_EINVAL, "unknown ordering %d", o->ordering);
   if (!(std::isfinite(o->inner_tol) && o->inner_tol >= 0.0 && o->inner_tol < 1.0))
@@ -158,7 +168,7 @@ struct sl_plan {
   int64_t nnz = 0;
   // tape of the last sl_plan_unroll: checkpoints X^{m c} and the trace rows
   // (decisions) of every iteration; reverse-mode work buffers
-  int tape_K = -1, tape_c = 1, tape_safeguard = 1;
+  int tape_K = -1, tape_c = 1, tape_safeguard = 1, tape_sym = 0;
   double tape_omega = 1.0;
   float* ckpt = nullptr;
   size_t ckpt_cap = 0;          // floats
@@ -654,6 +664,64 @@ sl_status stress_pass(sl_plan* p, int cur, double* f) {
   return SL_OK;
 }
 
+// The probabilistic strategy's draw of iteration g (Sec. 5.2): output number g
+// (from 0) of SplitMix64 seeded with `seed` (Steele, Lea and Flood, OOPSLA 2014),
+// as a uniform u = (z >> 11) 2^-53 in [0, 1), through the roulette over the
+// paper's factors 0.5, 1.0, 1.5, 2.0 with probabilities 0.3, 0.3, 0.2, 0.2.
+double auto_factor(uint64_t seed, uint64_t g) {
+  uint64_t z = seed + (g + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const double u = (double)(z >> 11) * 0x1.0p-53;
+  return u < 0.3 ? 0.5 : (u < 0.6 ? 1.0 : (u < 0.8 ? 1.5 : 2.0));
+}
+
+// The paper's factors of iterations iter_offset .. iter_offset + max_iter - 1
+// (a caller's schedule, or the probabilistic strategy's draws) into the plan's
+// device array, indexed by the iteration of the call.
+sl_status upload_schedule(sl_plan* p, const sl_options* o) {
+  if (p->sched_cap < o->max_iter) {
+    (void)hipFree(p->sched);
+    p->sched = nullptr;
+    p->sched_cap = 0;
+    HIP_TRY(hipMalloc(&p->sched, sizeof(double) * o->max_iter), "schedule buffer");
+    p->sched_cap = o->max_iter;
+    if (p->gexec) {  // the captured iterations read the old array
+      (void)hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+    }
+  }
+  std::vector<double> wp(o->max_iter);
+  for (int k = 0; k < o->max_iter; ++k) {
+    const int64_t g = o->iter_offset + k;
+    wp[k] = o->strategy == SL_OMEGA_AUTO ? auto_factor(o->seed, (uint64_t)g) : o->omega_schedule[g] - 1.0;
+  }
+  HIP_TRY(hipMemcpyAsync(p->sched, wp.data(), sizeof(double) * o->max_iter, hipMemcpyHostToDevice, p->ps),
+          "schedule upload");
+  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");  // wp is a host temporary
+  return SL_OK;
+}
+
+// f of the returned placement (eq. 1) and the relative stress decrease of the
+// last iteration, (f(X^{K-1}) - f(X^K)) / f(X^{K-1}), the reading of the
+// paper's "rel err" (Table 1); NaN with SL_FLAG_NO_FINAL_STRESS.
+sl_status final_stress(sl_plan* p, const DevState& fin, uint32_t flags, sl_result* res) {
+  res->stress = std::nan("");
+  res->rel_stress_drop = std::nan("");
+  if (flags & SL_FLAG_NO_FINAL_STRESS) return SL_OK;
+  double f = 0.0;
+  sl_status s;
+  if (p->n > 1 && (s = stress_pass(p, fin.cur, &f)) != SL_OK) return s;
+  res->stress = f;
+  if (p->n > 1 && fin.iter > 0 && fin.status == 0) {  // X^{K-1} is intact after a completed iteration
+    double fp = 0.0;
+    if ((s = stress_pass(p, fin.prev, &fp)) != SL_OK) return s;
+    if (fp != 0.0) res->rel_stress_drop = (fp - f) / fp;
+  }
+  return SL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -800,7 +868,9 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   // enumeration or stress trace
   lp.fuse = (lp.safeguard && !lp.enumerate && !lp.stress &&
              !(o->flags & SL_FLAG_SEPARATE_SAFEGUARD) &&
-             (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->omega_vertex) && p->n > 1)
+             (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->strategy == SL_OMEGA_AUTO ||
+              o->omega_vertex) &&
+             p->n > 1)
                 ? 1
                 : 0;
   if ((o->flags & SL_FLAG_SYM_FORCE) && (o->flags & SL_FLAG_ORDERED_FORCE))
@@ -826,23 +896,8 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
       if (!(std::isfinite(wv[i]) && wv[i] > 0.f && wv[i] <= 16.f))
         return fail(SL_EINVAL, "omega_vertex[%d] = %g outside (0, 16]", i, (double)wv[i]);
   }
-  if (o->strategy == SL_OMEGA_SCHEDULE && o->max_iter > 0) {
-    if (p->sched_cap < o->max_iter) {
-      (void)hipFree(p->sched);
-      p->sched = nullptr;
-      p->sched_cap = 0;
-      HIP_TRY(hipMalloc(&p->sched, sizeof(double) * o->max_iter), "schedule buffer");
-      p->sched_cap = o->max_iter;
-      if (p->gexec) {
-        (void)hipGraphExecDestroy(p->gexec);
-        p->gexec = nullptr;
-      }
-    }
-    std::vector<double> wp(o->max_iter);
-    for (int k = 0; k < o->max_iter; ++k) wp[k] = o->omega_schedule[k] - 1.0;
-    HIP_TRY(hipMemcpyAsync(p->sched, wp.data(), sizeof(double) * o->max_iter, hipMemcpyHostToDevice, p->ps),
-            "schedule upload");
-    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+  if ((o->strategy == SL_OMEGA_SCHEDULE || o->strategy == SL_OMEGA_AUTO) && o->max_iter > 0) {
+    if ((s = upload_schedule(p, o)) != SL_OK) return s;
     lp.omega_sched = p->sched;
   }
   if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
@@ -855,8 +910,9 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
 
   // iterations per captured graph between looks at the stop flag (those after
   // the stop return at once)
-  int chunk = o->check_every > 0 ? o->check_every : (p->n <= 8192 ? 32 : 8);
-  chunk = std::max(1, std::min(chunk, std::max(1, o->max_iter)));
+  // (not capped by max_iter: runs of any length replay the same captured graph,
+  // whose iterations after the stop return at once)
+  const int chunk = o->check_every > 0 ? o->check_every : (p->n <= 8192 ? 32 : 8);
   const bool use_graph = !(o->flags & SL_FLAG_NO_GRAPH);
   const bool exact = o->ordering == SL_ORDER_EXACT;
   if (use_graph && !exact) {
@@ -920,10 +976,7 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   res.converged = fin.converged;
   res.rejected = fin.rejected;
   res.residual = fin.residual;
-  double f = 0.0;
-  if (o->flags & SL_FLAG_NO_FINAL_STRESS) f = std::nan("");
-  else if (p->n > 1 && (s = stress_pass(p, fin.cur, &f)) != SL_OK) return s;
-  res.stress = f;
+  if ((s = final_stress(p, fin, o->flags, &res)) != SL_OK) return s;
   if ((s = join_to(p, user)) != SL_OK) return s;
   if (out) *out = res;
   if (fin.status != 0)
@@ -945,37 +998,6 @@ sl_status sl_plan_stress(sl_plan* p, const float* X, int32_t dim, void* stream, 
   HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
   if ((s = stress_pass(p, 0, f)) != SL_OK) return s;
   return join_to(p, (hipStream_t)stream);
-}
-
-sl_status sl_probe_rate(int32_t kind, void* stream, double* per_s, double* ms) {
-  g_err.clear();
-  if (!per_s || !ms) return fail(SL_EINVAL, "per_s or ms is NULL");
-  if (kind < 0 || kind > 3) return fail(SL_EINVAL, "kind %d is not 0 (FMA), 1 (rsq), 2 (sqrt) or 3 (rcp)", kind);
-  int dev = 0, cus = 0;
-  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
-  const int blocks = std::max(1, cus) * 8;  // 4 waves per workgroup: 8 waves per SIMD
-  const int iters = 2000;
-  const hipStream_t s = (hipStream_t)stream;
-  float* out = nullptr;
-  hipEvent_t a = nullptr, b = nullptr;
-  hipError_t e = hipMalloc(&out, sizeof(float) * (size_t)blocks * 256);
-  if (e == hipSuccess) e = hipEventCreate(&a);
-  if (e == hipSuccess) e = hipEventCreate(&b);
-  if (e == hipSuccess) e = launch_probe(kind, out, blocks, iters, s);
-  if (e == hipSuccess) e = hipEventRecord(a, s);
-  if (e == hipSuccess) e = launch_probe(kind, out, blocks, iters, s);
-  if (e == hipSuccess) e = hipEventRecord(b, s);
-  if (e == hipSuccess) e = hipEventSynchronize(b);
-  float t = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
-  if (a) (void)hipEventDestroy(a);
-  if (b) (void)hipEventDestroy(b);
-  if (out) (void)hipFree(out);
-  if (e != hipSuccess) return hip_fail(e, "probe kernel");
-  *ms = t;
-  *per_s = (double)blocks * 256.0 * probe_ops_per_lane(iters) / (t * 1e-3);
-  return SL_OK;
 }
 
 sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega, int32_t reps, void* stream,
@@ -1192,7 +1214,19 @@ sl_status grow(void** ptr, size_t* cap, size_t want, size_t elem, const char* wh
   return SL_OK;
 }
 
-LoopParams unroll_params(const sl_plan* p, double omega, int safeguard) {
+// The force pass an unrolled run takes: SL_FLAG_SYM_FORCE / SL_FLAG_ORDERED_FORCE
+// as in sl_plan_run, else the default by size; SL_ENOTSUP where the unordered
+// pass does not apply (n <= 1).
+sl_status unroll_sym(sl_plan* p, uint32_t flags, int* sym) {
+  if ((flags & SL_FLAG_SYM_FORCE) && (flags & SL_FLAG_ORDERED_FORCE))
+    return fail(SL_EINVAL, "SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE exclude each other");
+  *sym = (flags & SL_FLAG_SYM_FORCE) ? 1 : (flags & SL_FLAG_ORDERED_FORCE) ? 0 : (sym_by_default(p) ? 1 : 0);
+  if (p->n <= 1) *sym = 0;
+  if (*sym) return ensure_sym(p);
+  return SL_OK;
+}
+
+LoopParams unroll_params(const sl_plan* p, double omega, int safeguard, int sym) {
   LoopParams lp{};
   lp.n = p->n;
   lp.n_pad = p->n_pad;
@@ -1206,8 +1240,8 @@ LoopParams unroll_params(const sl_plan* p, double omega, int safeguard) {
   // the safeguard rides on the next force pass; a run (or a recomputed
   // segment) starts with one plain force pass
   lp.fuse = (safeguard && omega != 1.0 && p->n > 1) ? 1 : 0;
-  // the force pass sl_plan_run takes by default (its buffers made by ensure_sym)
-  if (sym_by_default(p) && p->sym_items) {
+  // the force pass of the run (its buffers made by ensure_sym)
+  if (sym) {
     lp.sym = 1;
     lp.slices = 1;
   }
@@ -1276,8 +1310,9 @@ sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt
   oo.trace = p->tape_trace;
   oo.xtrace = nullptr;
   oo.flags &= ~SL_FLAG_TRACE_STRESS;
-  if (sym_by_default(p) && (s = ensure_sym(p)) != SL_OK) return s;
-  const LoopParams lp = unroll_params(p, o->omega, o->safeguard);
+  int sym = 0;
+  if ((s = unroll_sym(p, o->flags, &sym)) != SL_OK) return s;
+  const LoopParams lp = unroll_params(p, o->omega, o->safeguard, sym);
   sl_result res{};
   res.plan_ms = p->plan_ms;
   if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
@@ -1304,13 +1339,12 @@ sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt
   res.converged = fin.converged;
   res.rejected = fin.rejected;
   res.residual = fin.residual;
-  double f = 0.0;
-  if (p->n > 1 && (s = stress_pass(p, fin.cur, &f)) != SL_OK) return s;
-  res.stress = f;
+  if ((s = final_stress(p, fin, o->flags, &res)) != SL_OK) return s;
   if ((s = join_to(p, (hipStream_t)stream)) != SL_OK) return s;
   if (out) *out = res;
   if (fin.status != 0)
     return fail(SL_ENUMERIC, "non-finite coordinate at iteration %d; X holds the last finite iterate", fin.iter + 1);
+  p->tape_sym = sym;
   p->tape_K = K;
   p->tape_c = c;
   p->tape_omega = o->omega;
@@ -1360,8 +1394,7 @@ sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float*
                            p->ps),
             "tape download");
   HIP_TRY(launch_grad_in(G, p->gb, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
-  if (sym_by_default(p) && (s = ensure_sym(p)) != SL_OK) return s;
-  const LoopParams lp = unroll_params(p, p->tape_omega, p->tape_safeguard);
+  const LoopParams lp = unroll_params(p, p->tape_omega, p->tape_safeguard, p->tape_sym);
   sl_options oo;
   sl_default_options(&oo);
   oo.dim = p->dim;
@@ -1428,7 +1461,7 @@ sl_status sl_layout(const sl_graph* g, float* X, const sl_options* o, void* stre
   sl_plan* p = nullptr;
   if ((s = sl_plan_create(g, o->dim, stream, &p)) != SL_OK) return s;
   s = sl_plan_run(p, X, o, stream, out);
-  const std::string keep = g_err;
+  const ErrorText keep = g_err;
   sl_plan_destroy(p);
   g_err = keep;
   return s;
@@ -1511,13 +1544,7 @@ void free_batch(sl_batch_plan* p) {
 
 // Column slices that give every wave of a `threads` workgroup a unit, within
 // the LDS budget of the force partials.
-int default_slices(int n_pad, int threads) {
-  const int nrb = n_pad / kRowBlock, ng = n_pad / kColGroup, nw = threads / 64;
-  int s = std::max(1, nw / nrb);
-  s = std::min(s, ng);
-  s = std::min(s, kBatchMaxPartial / n_pad);
-  return std::max(1, s);
-}
+int default_slices(int n_pad, int threads) { return batch_default_slices(n_pad, threads); }
 
 bool slices_ok(int n_pad, int s) { return s >= 1 && s <= n_pad / kColGroup && s * n_pad <= kBatchMaxPartial; }
 
@@ -1822,6 +1849,7 @@ sl_status sl_batch_plan_run(sl_batch_plan* p, float* X, const sl_options* o, voi
       o2.stress = r.stress;
       o2.plan_ms = p->plan_ms;
       o2.run_ms = tot.run_ms;
+      o2.rel_stress_drop = std::nan("");
     }
     tot.iterations = std::max(tot.iterations, r.iterations);
     tot.converged = tot.converged && r.converged;
@@ -1829,6 +1857,7 @@ sl_status sl_batch_plan_run(sl_batch_plan* p, float* X, const sl_options* o, voi
     tot.residual = std::max(tot.residual, r.residual);
     if (r.status != 0 && bad < 0) bad = g;
   }
+  tot.rel_stress_drop = std::nan("");
   if (total) *total = tot;
   if (bad >= 0) return fail(SL_ENUMERIC, "graph %d: non-finite coordinate; its X holds the last finite iterate", bad);
   return SL_OK;

@@ -58,6 +58,7 @@ __global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restr
       uint64_t* N = fb;
       __syncthreads();
       for (int level = 1;; ++level) {
+        __syncthreads();  // every wave has read the previous level's flag before it is cleared
         if (tid == 0) sh_any = 0;
         __syncthreads();
         bool any = false;

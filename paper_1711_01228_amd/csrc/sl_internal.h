@@ -45,7 +45,7 @@ struct DevState {
   int32_t rejected;
   int32_t status;     // 0 or SL_ENUMERIC
   int32_t max_iter;
-  int32_t pad;
+  int32_t prev;       // buffer index of the iterate the last completed iteration started from
   double residual;
   double last_df;
   double stress;      // f of the last evaluated placement (stress passes)
@@ -147,10 +147,6 @@ hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double
 
 // ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);
-// ---- calibration kernels (sl_probe.hip): blocks x 256 lanes, each running
-// probe_ops_per_lane(iters) instructions of one kind into out[blocks * 256]
-int probe_ops_per_lane(int iters);
-hipError_t launch_probe(int kind, float* out, int blocks, int iters, hipStream_t s);
 // ---- distances and weights (sl_apsp.hip)
 int bfs_sources_per_sweep();  // sources searched together (bits per vertex)
 int bfs_words();              // 64-bit words per vertex in the BFS buffers
@@ -271,6 +267,16 @@ struct BatchParams {
   double omega_p, tol;
   int32_t max_iter, safeguard;
 };
+
+// Column slices that give every wave of a `threads` workgroup a unit, within
+// the LDS budget of the force partials (the default of a batch plan).
+__host__ __device__ inline int batch_default_slices(int n_pad, int threads) {
+  const int nrb = n_pad / kRowBlock, ng = n_pad / kColGroup, nw = threads / 64;
+  int s = nw / nrb > 1 ? nw / nrb : 1;
+  s = s < ng ? s : ng;
+  s = s < kBatchMaxPartial / n_pad ? s : kBatchMaxPartial / n_pad;
+  return s > 1 ? s : 1;
+}
 
 hipError_t launch_batch_reset(int32_t* queue, hipStream_t s);
 hipError_t launch_batch_distances(int threads, int blocks, const BatchGraph* graphs, const int32_t* order, int count,

@@ -679,6 +679,7 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     accepted = 1.0;
   }
   st->omega_used = used;
+  st->prev = cur;
   st->iter = k + 1;
   st->residual = res;
   st->last_df = df;

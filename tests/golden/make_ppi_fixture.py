@@ -2,12 +2,12 @@
 
 Fig. 4(a) of the paper draws a 179-vertex protein-protein interaction module
 laid out by the SOR method (Sec. 5.4).  Its TikZ source lists every vertex
-coordinate and every edge.  This script reads that source from the paper's
-LaTeX text and writes the vertex coordinates and the edge list, 0-based, as a
-plain-text fixture.  It runs once when the fixture is (re)made; no test reads
-the paper.
+coordinate and every edge.  This script reads that source from a text file
+holding the paper's LaTeX (the figure's TikZ code) and writes the vertex
+coordinates and the edge list, 0-based, as a plain-text fixture.  It runs once
+when the fixture is (re)made; no test reads the paper.
 
-usage: python tests/golden/make_ppi_fixture.py /root/reference/PAPER.md
+usage: python tests/golden/make_ppi_fixture.py PAPER_LATEX_FILE
 """
 import os
 import re
@@ -38,7 +38,9 @@ def parse(text: str):
 
 
 def main():
-    src = sys.argv[1] if len(sys.argv) > 1 else "/root/reference/PAPER.md"
+    if len(sys.argv) != 2:
+        sys.exit("usage: make_ppi_fixture.py PAPER_LATEX_FILE (the text holding the TikZ source of Fig. 4(a))")
+    src = sys.argv[1]
     with open(src, encoding="utf-8", errors="replace") as f:
         text = f.read()
     coords, edges = parse(text)

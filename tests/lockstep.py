@@ -1,0 +1,49 @@
+"""Lockstep check of the safeguard (Alg. 2 lines 5-8) along a GPU run.
+
+For every iteration k of a run that recorded its trace and placements, the
+oracle takes the GPU's own X^k, forms X^H (the Jacobi step of eq. 5), X~
+(eq. 11 with the factor the GPU recorded, or the per-vertex factors) and
+f(X~) - f(X^H) (eq. 1, pair by pair), so that the comparison isolates the
+GPU's arithmetic of that iteration from the drift of a free run:
+  * the GPU's f(X~) - f(X^H) (trace column 2) within 1e-4 of the oracle's
+    value or the FP32 band 64 * 2^-24 of its term scale;
+  * the GPU's decision (trace column 1) equal to the oracle's outside that band.
+The enumerating strategy (Sec. 5.2) checks the kept candidate's difference and
+that no candidate beats it by more than the band.
+"""
+import numpy as np
+
+import oracle
+
+AMBIG = 64 * 2.0 ** -24
+
+
+def check_safeguard_lockstep(D, X0, info, omega_vertex=None, enumerate=False, ordering="jacobi"):
+    P, T = info["positions"].astype(np.float64), info["trace"]
+    checked = 0
+    for k in range(len(T)):
+        if T[k, 1] == -1.0:  # no extrapolation formed: nothing to decide
+            continue
+        Xk = np.asarray(X0, dtype=np.float64) if k == 0 else P[k - 1]
+        XH = oracle.h_jacobi(D, Xk) if ordering == "jacobi" else oracle.h_exact(D, Xk)
+        if enumerate:
+            dfs = [oracle.stress_delta(D, XH + c * (XH - Xk), XH) for c in oracle.ENUM_FACTORS[1:]]
+            c = T[k, 3]
+            df, sc = (0.0, 0.0) if c == 0.0 else dfs[int(round(2 * c)) - 1]
+            tol = max(1e-4 * abs(df), AMBIG * sc)
+            assert abs(T[k, 2] - df) <= tol, (k, T[k], df, sc)
+            best = min([0.0] + [d for d, _ in dfs])
+            assert df <= best + max(AMBIG * max(s for _, s in dfs), 1e-4 * abs(best)), (k, df, best)
+            checked += 1
+            continue
+        if omega_vertex is not None:
+            XT = XH + (np.asarray(omega_vertex, dtype=np.float64) - 1.0)[:, None] * (XH - Xk)
+        else:
+            XT = XH + T[k, 3] * (XH - Xk)
+        df, sc = oracle.stress_delta(D, XT, XH)
+        tol = max(1e-4 * abs(df), AMBIG * sc)
+        assert abs(T[k, 2] - df) <= tol, (k, T[k, 2], df, sc)
+        if abs(df) > AMBIG * sc:
+            assert T[k, 1] == (1.0 if df <= 0.0 else 0.0), (k, T[k, 1], df, sc)
+        checked += 1
+    return checked

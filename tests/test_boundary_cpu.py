@@ -16,12 +16,18 @@ from paper_1711_01228_amd import inputs
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "sorlayout.h")
+PROBE_HEADER = os.path.join(ROOT, "include", "slprobe.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER, prefix="sl_"):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sl_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(%s[a-z0-9_]+)\s*\(" % prefix, text)))
+
+
+def exported_symbols(path):
+    out = subprocess.run(["nm", "-D", "--defined-only", path], stdout=subprocess.PIPE, text=True).stdout
+    return set(re.findall(r"\sT\s+(\S+)", out))
 
 
 def test_library_exports_every_declared_function():
@@ -29,10 +35,19 @@ def test_library_exports_every_declared_function():
     assert len(names) >= 9
     for name in names:
         assert hasattr(b.LIB, name), name
-    out = subprocess.run(["nm", "-D", "--defined-only", b.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
-    exported = set(re.findall(r"\sT\s+(\S+)", out))
+    exported = exported_symbols(b.LIB_PATH)
     assert set(names) <= exported
     assert set(b.EXPORTED) == set(names)
+    # the calibration probe is the benchmark's own library, not part of the method's ABI
+    assert not any(name.startswith("slp_") or "probe" in name for name in exported)
+
+
+def test_probe_library_exports_its_header():
+    from paper_1711_01228_amd import build_lib
+
+    names = declared_functions(PROBE_HEADER, "slp_")
+    assert names == ["slp_probe_rate"]
+    assert set(names) <= exported_symbols(build_lib.PROBE_LIB)
 
 
 def test_default_options():
@@ -100,12 +115,31 @@ def test_edge_length_validation():
 @pytest.mark.parametrize("field,value", [
     ("dim", 1), ("dim", 4), ("omega", 0.0), ("omega", float("nan")), ("omega", float("inf")),
     ("omega", 17.0), ("tol", -1e-3), ("tol", float("nan")), ("max_iter", -1), ("safeguard", 2), ("flags", 64),
+    ("iter_offset", -1), ("strategy", 4), ("seed", 5),  # a seed without the probabilistic strategy
 ])
 def test_validation_rejects_bad_options(field, value):
     o = b.make_options()
     setattr(o, field, value)
     assert b.sl_validate_status(_tri(), o) == b.SL_EINVAL
     assert b.last_error()
+
+
+def test_probabilistic_strategy_and_resume_options():
+    b.sl_validate(_tri(), b.make_options(strategy=b.SL_OMEGA_AUTO, seed=2 ** 64 - 1, iter_offset=10 ** 6))
+    # a schedule is read at the global iterations iter_offset .. iter_offset + max_iter - 1
+    sched = np.array([0.0, 0.0, 1.5, 2.0, 2.5])
+    b.sl_validate(_tri(), b.make_options(strategy=b.SL_OMEGA_SCHEDULE, omega_schedule=sched, max_iter=3,
+                                         iter_offset=2))
+    o = b.make_options(strategy=b.SL_OMEGA_SCHEDULE, omega_schedule=sched, max_iter=3, iter_offset=1)
+    assert b.sl_validate_status(_tri(), o) == b.SL_EINVAL and "omega_schedule[1]" in b.last_error()
+
+
+def test_result_and_options_layout_match_the_header():
+    # the new fields sit at the end of each struct, after the ones of the first layout
+    assert b.sl_options.seed.offset == b.sl_options.reserved3.offset + 4
+    assert b.sl_options.iter_offset.offset == b.sl_options.seed.offset + 8
+    assert ctypes.sizeof(b.sl_options) == b.sl_options.iter_offset.offset + 8
+    assert b.sl_result.rel_stress_drop.offset == b.sl_result.run_ms.offset + 8
 
 
 def test_valid_inputs_and_empty_graph():
@@ -168,7 +202,10 @@ def test_ba_degree_is_heavy_tailed():
 
 
 def test_probe_rate_refuses_unknown_kind_before_any_device_call():
+    import bench
+
+    lib = bench.probe_library()
     per_s, ms = ctypes.c_double(0.0), ctypes.c_double(0.0)
-    assert b.LIB.sl_probe_rate(4, None, ctypes.byref(per_s), ctypes.byref(ms)) == b.SL_EINVAL
-    assert "kind" in b.last_error()
-    assert b.LIB.sl_probe_rate(0, None, None, ctypes.byref(ms)) == b.SL_EINVAL
+    assert lib.slp_probe_rate(4, None, ctypes.byref(per_s), ctypes.byref(ms)) == -1
+    assert lib.slp_probe_rate(0, None, None, ctypes.byref(ms)) == -1
+

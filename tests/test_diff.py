@@ -71,8 +71,11 @@ def test_unroll_equals_run_and_hop_gradient_matches_oracle():
     print("info", info, "relerr", _relerr(gX0, ref), flush=True)
 
 
+# "unordered": the force pass the differentiation workload takes at its size
+# (once per unordered pair, FP32 edge-length distances), forward and backward
+@pytest.mark.parametrize("force", ["default", "unordered"])
 @pytest.mark.parametrize("omega,safeguard", [(1.0, True), (1.5, True), (1.5, False)])
-def test_weighted_gradients_match_oracle(omega, safeguard):
+def test_weighted_gradients_match_oracle(omega, safeguard, force):
     import torch
 
     from paper_1711_01228_amd import autograd as ag
@@ -84,7 +87,8 @@ def test_weighted_gradients_match_oracle(omega, safeguard):
     try:
         X0t = dev(X0).requires_grad_(True)
         lt = torch.tensor(ln, device="cuda", requires_grad=True)
-        X = ag.unrolled_layout(X0t, lt, lay, omega=omega, iters=K, ckpt_every=7, safeguard=safeguard)
+        print("case weighted gradients omega", omega, "safeguard", safeguard, force, flush=True)
+        X = ag.unrolled_layout(X0t, lt, lay, omega=omega, iters=K, ckpt_every=7, safeguard=safeguard, force=force)
         loss = ag.stress_loss(X, lay)
         loss.backward()
         gX0 = X0t.grad.cpu().numpy().astype(np.float64)
@@ -117,7 +121,8 @@ def _fd(fun, h):
     return (4 * d2 - d1) / 3
 
 
-def test_gpu_gradient_vs_fp64_finite_differences_and_invariants():
+@pytest.mark.parametrize("force", ["default", "unordered"])
+def test_gpu_gradient_vs_fp64_finite_differences_and_invariants(force):
     import torch
 
     from paper_1711_01228_amd import autograd as ag
@@ -126,14 +131,16 @@ def test_gpu_gradient_vs_fp64_finite_differences_and_invariants():
     X0 = inputs.uniform_positions(g.n, 2, 22, hi=10.0)
     K, omega = 30, 1.5
     lay = ag.DifferentiableLayout(g, 2, ln)
+    print("case finite differences", force, flush=True)
     try:
         X0t = dev(X0).requires_grad_(True)
         lt = torch.tensor(ln, device="cuda", requires_grad=True)
-        loss = ag.stress_loss(ag.unrolled_layout(X0t, lt, lay, omega=omega, iters=K, ckpt_every=10), lay)
+        loss = ag.stress_loss(ag.unrolled_layout(X0t, lt, lay, omega=omega, iters=K, ckpt_every=10, force=force),
+                              lay)
         loss.backward()
         gX0 = X0t.grad.cpu().numpy().astype(np.float64)
         glen = lt.grad.cpu().numpy().astype(np.float64)
-        info = lay.plan.unroll(dev(X0), omega=omega, iters=K, ckpt_every=10)
+        info = lay.plan.unroll(dev(X0), omega=omega, iters=K, ckpt_every=10, sym_force=force == "unordered")
     finally:
         lay.close()
     # finite differences of the FP64 forward (the oracle), same decisions and trees

@@ -20,6 +20,7 @@ import pytest
 
 import oracle
 from fixtures import GOLDEN, ppi_fig4a
+from lockstep import check_safeguard_lockstep
 from paper_1711_01228_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -134,13 +135,13 @@ def test_one_jacobi_step(sl, name, dim):
 # ---------------------------------------------------------------------------
 # free runs against the oracle trajectory
 # ---------------------------------------------------------------------------
-def compare_runs(g, X0, D, omega, iters, safeguard=True, sl=None, dim=2):
+def compare_runs(g, X0, D, omega, iters, safeguard=True, sl=None, dim=2, **kw):
     Xo, io = oracle.layout(D, X0, omega=omega, tol=0.0, max_iter=iters, safeguard=safeguard,
                            trace_positions=True)
     X = dev(X0)
     with sl.Plan(g, dim) as plan:
         ig = plan.run(X, omega=omega, tol=0.0, max_iter=iters, safeguard=safeguard, trace=True,
-                      trace_positions=True)
+                      trace_positions=True, **kw)
     assert ig["iterations"] == iters == io["iterations"]
     Pg, Po = ig["positions"].astype(np.float64), io["positions"]
     tg, to = ig["trace"], io["trace"]
@@ -155,25 +156,32 @@ def compare_runs(g, X0, D, omega, iters, safeguard=True, sl=None, dim=2):
         # residual: FP32 storage of x^H bounds its accuracy to ~1e-7 absolute
         np.testing.assert_allclose(tg[k, 0], to[k, 0], rtol=2e-3, atol=2e-6)
         compared += 1
+    if safeguard:  # every iteration, from the GPU's own iterate
+        check_safeguard_lockstep(D, X0, ig)
     return compared, ig, io
 
 
+FORCE_PASSES = {"default": {}, "unordered": {"sym_force": True}}
+
+
+@pytest.mark.parametrize("force", sorted(FORCE_PASSES))
 @pytest.mark.parametrize("omega", [1.0, 1.5])
-def test_grid16_free_run_200_iterations(sl, omega):
+def test_grid16_free_run_200_iterations(sl, omega, force):
     g, X0 = inputs.grid16(0)
-    print("case grid16 omega", omega, flush=True)
-    compared, ig, io = compare_runs(g, X0, oracle_D(g), omega, 200, sl=sl)
+    print("case grid16 omega", omega, force, flush=True)
+    compared, ig, io = compare_runs(g, X0, oracle_D(g), omega, 200, sl=sl, **FORCE_PASSES[force])
     assert compared >= 150
     if omega == 1.0:
         assert np.all(ig["trace"][:, 1] == -1)
 
 
+@pytest.mark.parametrize("force", sorted(FORCE_PASSES))
 @pytest.mark.parametrize("dim", [2, 3])
-def test_ppi_free_run_with_rejections(sl, dim):
+def test_ppi_free_run_with_rejections(sl, dim, force):
     g = ppi_graph()
     X0 = inputs.uniform_positions(g.n, dim, seed=5)
-    print("case ppi omega 3.0 dim", dim, flush=True)
-    compared, ig, io = compare_runs(g, X0, oracle_D(g), 3.0, 60, sl=sl, dim=dim)
+    print("case ppi omega 3.0 dim", dim, force, flush=True)
+    compared, ig, io = compare_runs(g, X0, oracle_D(g), 3.0, 60, sl=sl, dim=dim, **FORCE_PASSES[force])
     assert compared >= 30
     assert io["rejected"] > 0  # a long stride is refused at least once
 
@@ -211,11 +219,29 @@ def test_er4096_iterations_to_tol(sl, omega):
     assert info["stress"] == pytest.approx(ref["stress"], rel=1e-4)
 
 
+@pytest.mark.parametrize("force", sorted(FORCE_PASSES))
 @pytest.mark.parametrize("omega", [1.0, 1.6])
-def test_er4096_first_iterations_track_oracle(sl, omega):
+def test_er4096_first_iterations_track_oracle(sl, omega, force):
     g, X0 = inputs.er4096(0)
-    compared, _, _ = compare_runs(g, X0, oracle_D(g), omega, 25, sl=sl)
+    print("case er4096 omega", omega, force, flush=True)
+    compared, _, _ = compare_runs(g, X0, oracle_D(g), omega, 25, sl=sl, **FORCE_PASSES[force])
     assert compared >= 20
+
+
+def test_rel_stress_drop_is_the_last_iterations_relative_decrease(sl):
+    g, X0 = inputs.grid16(5)
+    D = oracle_D(g)
+    for omega, iters in ((1.0, 7), (1.5, 12)):
+        X = dev(X0)
+        with sl.Plan(g, 2) as plan:
+            info = plan.run(X, omega=omega, tol=0.0, max_iter=iters, trace=True, trace_positions=True)
+            none = plan.run(dev(X0), omega=omega, tol=0.0, max_iter=iters, final_stress=False)
+            zero = plan.run(dev(X0), omega=omega, max_iter=0)
+        P = info["positions"].astype(np.float64)
+        f_prev, f_last = oracle.stress(D, P[-2]), oracle.stress(D, P[-1])
+        assert info["stress"] == pytest.approx(f_last, rel=1e-5)
+        assert info["rel_stress_drop"] == pytest.approx((f_prev - f_last) / f_prev, rel=1e-4, abs=1e-6)
+        assert np.isnan(none["rel_stress_drop"]) and np.isnan(zero["rel_stress_drop"])
 
 
 # ---------------------------------------------------------------------------
@@ -239,33 +265,48 @@ def test_ba65536_one_step_sampled_rows(sl, dim):
     assert err <= 1e-5 * diam(X0), err
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_ba65536_fused_iterations_sampled_rows(sl, dim):
-    """The launch configuration the benchmark times (n = 65,536, omega = 1.5 with
-    the safeguard): iteration 3 takes the force of X^2 from the fused force +
-    safeguard pass of iteration 2 (or from the force pass after a rejection).
-    Sampled rows of X^3 against the oracle's step from the GPU's own X^2 (all
-    rows), with the decision the GPU recorded."""
+# (dimension, iteration k from 0): 2-D takes the fused pass over unordered pairs,
+# 3-D the one over ordered pairs; each case costs the oracle two passes over all
+# pairs with every distance row found by breadth-first search (~25 s on 16 threads)
+BA_LOCKSTEP = [(2, 0), (2, 1), (2, 2), (3, 1)]
+
+
+@pytest.mark.parametrize("dim,k", BA_LOCKSTEP)
+def test_ba65536_safeguard_lockstep(sl, dim, k):
+    """The launch configuration the benchmark times (n = 65,536, omega = 1.5,
+    the safeguard summed inside the pass that takes the next force at X~).
+    Iteration k from the GPU's own X^k: the oracle forms X^H for every vertex,
+    X~ and f(X~) - f(X^H) (distance rows found from the graph one at a time,
+    never the n x n matrix), and these are compared with the GPU's trace
+    column 2 (within 1e-4 of the value or the FP32 band 64 * 2^-24 of the term
+    scale), its decision (equal outside that band) and all rows of X^{k+1}
+    (X~ or X^H by the oracle's decision, within 1e-5 of the layout's
+    diameter)."""
     g, X0 = inputs.ba65536(dim)
-    print("case ba65536 fused dim", dim, flush=True)
-    rng = np.random.default_rng(10 + dim)
-    rows = np.unique(np.concatenate([rng.choice(g.n, 48, replace=False), [0, 1, 63, 64, g.n - 1]]))
-    Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
     omega = 1.5
+    print("case ba65536 lockstep dim", dim, "iteration", k, flush=True)
+    X = dev(X0)
     with sl.Plan(g, dim) as plan:
-        X2 = dev(X0)
-        plan.run(X2, omega=omega, tol=0.0, max_iter=2)
-        X3 = dev(X0)
-        info = plan.run(X3, omega=omega, tol=0.0, max_iter=3, trace=True)
-    assert info["iterations"] == 3
-    X2 = X2.cpu().numpy().astype(np.float64)
-    XH = oracle.h_jacobi_rows(Drows, rows, X2)
-    took = info["trace"][2, 1]
-    expect = XH + (omega - 1.0) * (XH - X2[rows]) if took == 1.0 else XH
-    got = X3.cpu().numpy().astype(np.float64)[rows]
-    err = np.abs(got - expect).max()
-    print("decisions", info["trace"][:, 1], "err", err, flush=True)
-    assert err <= 1e-5 * diam(X2), err
+        info = plan.run(X, omega=omega, tol=0.0, max_iter=k + 1, trace=True, trace_positions=True,
+                        final_stress=False)
+    assert info["iterations"] == k + 1
+    P = info["positions"].astype(np.float64)
+    Xk = X0 if k == 0 else P[k - 1]
+    XH = oracle.h_jacobi_graph(g.row_ptr, g.col_idx, Xk)
+    XT = XH + (omega - 1.0) * (XH - Xk)
+    df, scale = oracle.stress_delta_graph(g.row_ptr, g.col_idx, XT, XH)
+    tg = info["trace"][k]
+    print("f(X~) - f(X^H): gpu %.10g oracle %.10g scale %.4g; decision gpu %g" % (tg[2], df, scale, tg[1]),
+          flush=True)
+    assert abs(tg[2] - df) <= max(1e-4 * abs(df), AMBIG * scale)
+    take = df <= 0.0
+    if abs(df) > AMBIG * scale:
+        assert tg[1] == (1.0 if take else 0.0)
+    else:  # inside the FP32 band either decision is correct: follow the GPU's
+        take = tg[1] == 1.0
+    expect = XT if take else XH
+    err = np.abs(P[k] - expect).max()
+    assert err <= 1e-5 * max(diam(Xk), diam(XH)), err
 
 
 # ---------------------------------------------------------------------------
@@ -357,8 +398,10 @@ def test_layout_one_call_matches_plan(sl):
 
 
 def test_probe_rates_are_plausible(sl):
+    import bench
+
     # lane operations per second: 1,024 SIMDs x 16 lanes x ~2.4 GHz is ~3.9e13 at one instruction per 4 cycles
     for kind in ("fma", "rsq", "sqrt", "rcp"):
-        per_s, ms = sl.sl_probe_rate(kind)
+        per_s, ms = bench.probe_rate(kind)
         print(kind, per_s, ms, flush=True)
         assert ms > 0.0 and 1e12 < per_s < 1.6e14

@@ -27,7 +27,7 @@ def dmat(g):
 # ---------------------------------------------------------------------------
 # hand-computed steps
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("name", sorted(k for k in CASES if "jacobi" in CASES[k]))
 def test_hand_case_steps(name):
     c = CASES[name]
     g = inputs.to_csr(c["n"], c["edges"])
@@ -483,3 +483,85 @@ def test_enumeration_picks_the_stress_minimizing_candidate():
 def test_auto_roulette_distribution():
     assert sum(oracle.AUTO_PROBS) == pytest.approx(1.0)
     assert oracle.ENUM_FACTORS[0] == 0.0 and oracle.ENUM_FACTORS[-1] == 9.0 and len(oracle.ENUM_FACTORS) == 19
+
+
+# ---------------------------------------------------------------------------
+# the safeguard's term scale (the band in which FP32 decisions are ambiguous)
+# ---------------------------------------------------------------------------
+def test_stress_delta_and_scale_hand_values():
+    c = CASES["path3_delta"]
+    D = dmat(inputs.to_csr(c["n"], c["edges"]))
+    XB = np.array(c["xb"]).reshape(3, 2)
+    for k in (1, 2, 3):
+        XA = np.array(c["xa%d" % k]).reshape(3, 2)
+        delta, scale = oracle.stress_delta(D, XA, XB)
+        assert delta == pytest.approx(c["delta%d" % k], abs=1e-14)
+        assert scale == pytest.approx(c["scale%d" % k], abs=1e-14)
+        # the scale bounds the sum, and swapping the placements flips the sum only
+        d2, s2 = oracle.stress_delta(D, XB, XA)
+        assert d2 == pytest.approx(-delta, abs=1e-14) and s2 == pytest.approx(scale, abs=1e-14)
+        assert abs(delta) <= scale + 1e-15
+
+
+# ---------------------------------------------------------------------------
+# sampled rows and graph forms (the checkers of the full-size GPU tests)
+# ---------------------------------------------------------------------------
+def test_h_jacobi_rows_are_rows_of_h_jacobi():
+    g = inputs.erdos_renyi(150, 400, 51)  # small components and isolated vertices too
+    D = dmat(g)
+    X = inputs.uniform_positions(g.n, 2, 52, hi=12.0)
+    full = oracle.h_jacobi(D, X)
+    rows = np.array([149, 0, 77, 3, 77, 148, 1])  # unsorted, repeated, both ends
+    got = oracle.h_jacobi_rows(D[rows], rows, X)
+    np.testing.assert_array_equal(got, full[rows])
+    # a row given another vertex's distance row is a different step: the index is used
+    wrong = oracle.h_jacobi_rows(D[rows[::-1]], rows, X)
+    assert np.abs(wrong - full[rows]).max() > 1e-3
+    # 3-D and the hand case of the path (x^H = 0.2, 1.5, 2)
+    X3 = inputs.uniform_positions(g.n, 3, 53, hi=12.0)
+    np.testing.assert_array_equal(oracle.h_jacobi_rows(D[rows], rows, X3), oracle.h_jacobi(D, X3)[rows])
+    c = CASES["path3"]
+    Dp = dmat(inputs.to_csr(3, c["edges"]))
+    np.testing.assert_allclose(oracle.h_jacobi_rows(Dp[[2, 0]], [2, 0], c["x0"]), c["jacobi"][[2, 0]], atol=1e-15)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_graph_forms_equal_matrix_forms(weighted, dim):
+    g = inputs.erdos_renyi(200, 500, 54)
+    ln = None
+    if weighted:
+        ln = 1.0 + np.random.default_rng(55).uniform(-0.4, 0.4, g.num_edges)
+        g = inputs.to_csr(g.n, g.edges(), ln)
+    D = oracle.apsp(g.row_ptr, g.col_idx, g.edge_len)
+    X = inputs.uniform_positions(g.n, dim, 56, hi=10.0)
+    XH = oracle.h_jacobi_graph(g.row_ptr, g.col_idx, X, g.edge_len)
+    np.testing.assert_array_equal(XH, oracle.h_jacobi(D, X))
+    XT = XH + 0.7 * (XH - X)
+    assert oracle.stress_delta_graph(g.row_ptr, g.col_idx, XT, XH, g.edge_len) == oracle.stress_delta(D, XT, XH)
+
+
+# ---------------------------------------------------------------------------
+# the probabilistic strategy's generator and roulette (Sec. 5.2)
+# ---------------------------------------------------------------------------
+def test_splitmix64_published_values():
+    from fixtures import GOLDEN
+
+    with open(GOLDEN + "/splitmix64.txt") as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) >= 3
+    for seed, g, z in rows:
+        assert oracle.splitmix64(int(seed), int(g)) == int(z, 16)
+
+
+def test_auto_roulette_frequencies_and_windows():
+    f = oracle.auto_factors(3, 0, 200000)
+    vals, counts = np.unique(f, return_counts=True)
+    np.testing.assert_array_equal(vals, oracle.AUTO_FACTORS)
+    # binomial standard deviation ~ 0.001 at these counts
+    np.testing.assert_allclose(counts / len(f), oracle.AUTO_PROBS, atol=0.005)
+    # the draw of an iteration depends only on the seed and its number
+    np.testing.assert_array_equal(oracle.auto_factors(3, 5, 10), f[5:15])
+    assert not np.array_equal(oracle.auto_factors(4, 0, 64), f[:64])
+    # consecutive draws are not correlated (lag-1 correlation of the factors)
+    assert abs(np.corrcoef(f[:-1], f[1:])[0, 1]) < 0.01

@@ -1,5 +1,6 @@
-"""Relaxation strategies of Sec. 5.2 (schedule / probabilistic, enumerating,
-per-vertex factors): host validation and GPU parity with the oracle.
+"""Relaxation strategies of Sec. 5.2 (schedule, probabilistic, enumerating,
+per-vertex factors): host validation and GPU parity with the oracle, and runs
+resumed from their returned placement (iter_offset).
 
 GPU trace column 3 holds the paper's factor used; the oracle's column 5.
 Tolerances as in test_gpu_parity.py (1e-4 * diam per iteration), the
@@ -12,18 +13,11 @@ import pytest
 
 import oracle
 from fixtures import ppi_fig4a
+from lockstep import check_safeguard_lockstep
 from paper_1711_01228_amd import binding as b
 from paper_1711_01228_amd import inputs
 
 AMBIG = 64 * 2.0 ** -24
-
-
-def test_auto_schedule_distribution():
-    s = b.auto_schedule(20000, seed=3)
-    vals, counts = np.unique(s, return_counts=True)
-    np.testing.assert_array_equal(vals, [1.5, 2.0, 2.5, 3.0])
-    np.testing.assert_allclose(counts / len(s), b.AUTO_PROBS, atol=0.015)
-    np.testing.assert_array_equal(b.auto_schedule(50, 7), b.auto_schedule(50, 7))
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -65,17 +59,48 @@ def _compare(g, X0, iters, dim=2, gpu_kw=None, orc_kw=None, enum=False):
         diam = float(np.linalg.norm(Po[k].max(0) - Po[k].min(0)))
         assert np.abs(Pg[k] - Po[k]).max() <= 1e-4 * diam, k
         compared += 1
+    # every iteration, from the GPU's own iterate
+    check_safeguard_lockstep(D, X0, ig, omega_vertex=orc_kw.get("omega_vertex"), enumerate=enum)
     return compared, ig, io
 
 
 @pytest.mark.gpu
-def test_probabilistic_schedule_matches_oracle():
+def test_probabilistic_strategy_matches_oracle():
+    # the library draws the factors itself (SplitMix64 of the seed and the
+    # iteration number); the oracle's own generator gives the same sequence
     g, X0 = inputs.grid16(3)
-    sched = b.auto_schedule(120, seed=11)
-    compared, ig, io = _compare(g, X0, 120, gpu_kw=dict(strategy="schedule", omega_schedule=sched),
+    sched = 1.0 + oracle.auto_factors(11, 0, 120)
+    compared, ig, io = _compare(g, X0, 120, gpu_kw=dict(strategy="auto", seed=11),
                                 orc_kw=dict(omega_schedule=sched))
     assert compared >= 80
-    np.testing.assert_array_equal(ig["trace"][:compared, 3], sched[:compared] - 1.0)
+    np.testing.assert_array_equal(ig["trace"][:, 3], sched - 1.0)  # every draw, also past the compared part
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind", ["fixed", "schedule", "auto", "fixed_unordered"])
+def test_resume_with_iter_offset_equals_one_run(kind):
+    """k iterations, then k more from the returned placement with iter_offset
+    = k, equal 2k iterations in one call bit for bit (the schedule and the
+    probabilistic draws continue where the first call stopped)."""
+    import torch
+
+    g, X0 = inputs.grid16(6)
+    k = 17
+    sched = 1.0 + 0.25 * (np.arange(2 * k) % 7)  # 1.0 .. 2.5, factors of 1 included
+    kw = {"fixed": dict(omega=1.7), "schedule": dict(strategy="schedule", omega_schedule=sched),
+          "auto": dict(strategy="auto", seed=2024), "fixed_unordered": dict(omega=1.7, sym_force=True)}[kind]
+    X1 = torch.tensor(X0.astype(np.float32), device="cuda")
+    X2 = X1.clone()
+    with b.Plan(g, 2) as plan:
+        one = plan.run(X1, tol=0.0, max_iter=2 * k, trace=True, **kw)
+        a = plan.run(X2, tol=0.0, max_iter=k, trace=True, **kw)
+        c = plan.run(X2, tol=0.0, max_iter=k, trace=True, iter_offset=k, **kw)
+    np.testing.assert_array_equal(X1.cpu().numpy(), X2.cpu().numpy())
+    np.testing.assert_array_equal(one["trace"], np.concatenate([a["trace"], c["trace"]]))
+    assert one["rejected"] == a["rejected"] + c["rejected"]
+    if kind == "auto":  # the draws of iterations k .. 2k-1, not a restart of the sequence
+        np.testing.assert_array_equal(c["trace"][:, 3], oracle.auto_factors(2024, k, k))
+        assert not np.array_equal(c["trace"][:, 3], a["trace"][:, 3])
 
 
 @pytest.mark.gpu
