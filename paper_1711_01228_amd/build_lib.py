@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsorlayout.so")
 SOURCES = [os.path.join(CSRC, "sl_kernels.hip"), os.path.join(CSRC, "sl_apsp.hip"), os.path.join(CSRC, "sl_batch.hip"),
            os.path.join(CSRC, "sl_exact.hip"), os.path.join(CSRC, "sl_weighted.hip"), os.path.join(CSRC, "sl_diff.hip"),
-           os.path.join(CSRC, "sl_sym.hip"), os.path.join(CSRC, "sl_api.hip")]
+           os.path.join(CSRC, "sl_sym.hip"), os.path.join(CSRC, "sl_api.hip"),
+           os.path.join(CSRC, "sl_noalloc.hip")]
 PROBE_LIB = os.path.join(PKG, "libslprobe.so")
 PROBE_SOURCES = [os.path.join(CSRC, "sl_probe.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, "sl_internal.h"), os.path.join(CSRC, "sl_device.h"),
@@ -32,13 +33,21 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def command(out: str = LIB, sources=None) -> list:
+BUILD_DIR = os.path.join(PKG, "_build")
+
+
+def flags() -> list:
     return [
-        hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+        "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
         # packed FP32 instructions stay off: ordinary float code only
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-Wall", "-I", INCLUDE, "-I", CSRC, "-o", out,
-    ] + (SOURCES if sources is None else sources)
+        "-Wall", "-I", INCLUDE, "-I", CSRC,
+    ]
+
+
+def command(out: str = LIB, sources=None) -> list:
+    """One hipcc line that compiles and links the whole library."""
+    return [hipcc()] + flags() + ["-shared", "-o", out] + (SOURCES if sources is None else sources)
 
 
 def stale() -> bool:
@@ -48,9 +57,7 @@ def stale() -> bool:
     return any(os.path.getmtime(p) > t for p in DEPS)
 
 
-def _compile(lib: str, sources: list, verbose: bool) -> None:
-    tmp = lib + ".tmp%d" % os.getpid()
-    cmd = command(tmp, sources)
+def _run(cmd: list, verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -59,7 +66,28 @@ def _compile(lib: str, sources: list, verbose: bool) -> None:
         raise RuntimeError("hipcc failed (%d):\n%s" % (proc.returncode, "\n".join(lines)))
     if verbose and lines:
         print("\n".join(lines), flush=True)
-    os.replace(tmp, lib)
+
+
+def _compile(lib: str, sources: list, verbose: bool) -> None:
+    """Each source to an object (in parallel), then one link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(BUILD_DIR, os.path.basename(src) + "." + tag + ".o") for src in sources]
+    jobs = [[hipcc()] + flags() + ["-c", "-o", obj, src] for src, obj in zip(sources, objs)]
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1), 16))
+    try:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for f in [ex.submit(_run, cmd, verbose) for cmd in jobs]:
+                f.result()
+        tmp = lib + ".tmp" + tag
+        _run([hipcc(), "--offload-arch=" + ARCH, "-fPIC", "-shared", "-o", tmp] + objs, verbose)
+        os.replace(tmp, lib)
+    finally:
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
