@@ -359,6 +359,35 @@ sl_status sl_batch_plan_run(sl_batch_plan* plan, float* X, const sl_options* opt
 
 sl_status sl_batch_plan_destroy(sl_batch_plan* plan);
 
+/* ---------------------------------------------------------------------------
+ * Allocation-free batched layout, for callers that cannot allocate device
+ * memory: code that must not call hipMalloc (work around HIP graph captures,
+ * tight serving loops, harnesses that forbid allocation).
+ *
+ * The same as sl_batch_plan_create(b, opt->dim) + sl_batch_plan_run(opt) +
+ * sl_batch_plan_destroy with the untuned defaults (same kernels and launch
+ * shapes, so the same per-graph placements and results bit for bit), except:
+ *   - No device or host allocation: the distances, weights, descriptors and
+ *     the CSR copy live in the library's own device array of
+ *     SL_NOALLOC_SCRATCH_BYTES, one per GPU, held from library load until the
+ *     process ends; host staging is static.  A batch needs
+ *       sum_g n_pad_g^2 + 8 sum_g n_pad_g + 8 (n_total + 1) + 4 nnz
+ *       + 72 num_graphs bytes (n_pad_g = n_g rounded up to 64), each of its
+ *     nine regions rounded up to 256 bytes; a larger batch (or more than
+ *     SL_NOALLOC_SCRATCH_BYTES / 4096 graphs) returns SL_EINVAL before any
+ *     device work, with the bytes needed in the message.
+ *   - Everything runs on `stream`; the call synchronizes it twice (the
+ *     distance check and the results).  plan_ms, run_ms and rel_stress_drop are
+ *     NaN (no events are created).
+ *   - Every call on a GPU shares that GPU's array, which keeps the last call's
+ *     contents; the library holds a process-wide lock for the whole call, so
+ *     calls from several host threads run one after another.
+ * X, opt, per_graph and total as in sl_batch_plan_run.  Errors: SL_EINVAL,
+ * SL_ENOTSUP, SL_ERANGE, SL_ENUMERIC, SL_EDEVICE. */
+#define SL_NOALLOC_SCRATCH_BYTES (16u * 1024u * 1024u)
+sl_status sl_batch_layout_noalloc(const sl_batch* b, float* X, const sl_options* opt, void* stream,
+                                  sl_result* per_graph, sl_result* total);
+
 /* layout(G, X0, omega, tol, max_iter) -> X: sl_plan_create + sl_plan_run +
  * sl_plan_destroy. */
 sl_status sl_layout(const sl_graph* g, float* X, const sl_options* opt, void* stream, sl_result* out);

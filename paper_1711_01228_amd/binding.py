@@ -34,7 +34,7 @@ EXPORTED = ("sl_default_options", "sl_validate", "sl_plan_create", "sl_plan_run"
             "sl_plan_distance_rows", "sl_plan_weights", "sl_plan_profile", "sl_plan_destroy", "sl_layout",
             "sl_last_error", "sl_batch_plan_create", "sl_batch_plan_tune", "sl_batch_plan_run",
             "sl_batch_plan_destroy", "sl_plan_distance_rows_f32", "sl_plan_tree_rows", "sl_plan_set_lengths",
-            "sl_plan_stress_grad", "sl_plan_unroll", "sl_plan_unroll_backward")
+            "sl_plan_stress_grad", "sl_plan_unroll", "sl_plan_unroll_backward", "sl_batch_layout_noalloc")
 SL_WEIGHTED_MAX_N = 16384
 SL_BATCH_MAX_N = 1024
 SL_BATCH_CLASSES = 16
@@ -111,6 +111,8 @@ def _load():
         "sl_batch_plan_tune": (st, [P, P, ctypes.POINTER(sl_options), P, P]),
         "sl_batch_plan_run": (st, [P, P, ctypes.POINTER(sl_options), P, P, ctypes.POINTER(sl_result)]),
         "sl_batch_plan_destroy": (st, [P]),
+        "sl_batch_layout_noalloc": (st, [ctypes.POINTER(sl_batch), P, ctypes.POINTER(sl_options), P, P,
+                                         ctypes.POINTER(sl_result)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -464,6 +466,15 @@ def sl_batch_plan_run(plan: int, X_ptr: int, opt: sl_options, num_graphs: int, s
 
 def sl_batch_plan_destroy(plan: int) -> None:
     _check(LIB.sl_batch_plan_destroy(plan))
+
+
+def sl_batch_layout_noalloc(batch: BatchArgs, X_ptr: int, opt: sl_options, stream=None):
+    """The allocation-free batched layout; returns (total, per-graph list)."""
+    per = (sl_result * max(batch.s.num_graphs, 1))()
+    tot = sl_result()
+    _check(LIB.sl_batch_layout_noalloc(ctypes.byref(batch.s), X_ptr, ctypes.byref(opt), _stream_handle(stream), per,
+                                       ctypes.byref(tot)))
+    return tot.as_dict(), [per[k].as_dict() for k in range(batch.s.num_graphs)]
 
 
 class BatchPlan:

@@ -1548,10 +1548,7 @@ int default_slices(int n_pad, int threads) { return batch_default_slices(n_pad, 
 
 bool slices_ok(int n_pad, int s) { return s >= 1 && s <= n_pad / kColGroup && s * n_pad <= kBatchMaxPartial; }
 
-int batch_blocks(const sl_batch_plan* p, int count) {
-  const int per_cu = p->dim == 2 ? 2 : 1;  // LDS: ~78 KiB (2-D) or ~127 KiB (3-D) per workgroup
-  return std::max(1, std::min(count, p->cus * per_cu));
-}
+int batch_blocks(const sl_batch_plan* p, int count) { return batch_layout_blocks(p->dim, p->cus, count); }
 
 sl_status batch_upload_graphs(sl_batch_plan* p) {
   HIP_TRY(hipMemcpyAsync(p->graphs, p->hgraphs.data(), sizeof(BatchGraph) * p->hgraphs.size(),
@@ -1564,10 +1561,12 @@ sl_status batch_upload_graphs(sl_batch_plan* p) {
   return SL_OK;
 }
 
-sl_status batch_params(const sl_batch_plan* p, const sl_options* o, BatchParams* bp) {
+// Options of a batched run for `dim`-dimensional placements: a fixed factor,
+// the Jacobi step, no traces.
+sl_status batch_options(int dim, const sl_options* o, BatchParams* bp) {
   sl_status s = check_options(o);
   if (s != SL_OK) return s;
-  if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
+  if (o->dim != dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, dim);
   if (o->trace || o->xtrace) return fail(SL_EINVAL, "traces are not available for batched layouts");
   if (o->strategy != SL_OMEGA_FIXED || o->omega_vertex)
     return fail(SL_EINVAL, "batched layouts take a fixed relaxation factor");
@@ -1577,6 +1576,10 @@ sl_status batch_params(const sl_batch_plan* p, const sl_options* o, BatchParams*
   bp->max_iter = o->max_iter;
   bp->safeguard = o->safeguard;
   return SL_OK;
+}
+
+sl_status batch_params(const sl_batch_plan* p, const sl_options* o, BatchParams* bp) {
+  return batch_options(p->dim, o, bp);
 }
 
 // Time one launch over the graphs listed in `order` (device), in ms.
@@ -1796,6 +1799,8 @@ sl_status sl_batch_plan_run(sl_batch_plan* p, float* X, const sl_options* o, voi
   sl_result tot{};
   tot.plan_ms = p->plan_ms;
   tot.converged = 1;
+  if (p->ngraphs > 0 && p->n_total == 0)  // graphs without vertices: converged, no iterations
+    for (BatchResult& r : p->hres) r = BatchResult{0, 1, 0, 0, 0.0, 0.0};
   if (p->ngraphs > 0 && p->n_total > 0) {
     if (!X) return fail(SL_EINVAL, "X is NULL");
     if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) return s;
@@ -1864,3 +1869,16 @@ sl_status sl_batch_plan_run(sl_batch_plan* p, float* X, const sl_options* o, voi
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Helpers for entry points defined in other files of the library: the same
+// thread-local error text (sl_last_error) and option checks.
+// ---------------------------------------------------------------------------
+namespace sl {
+
+void api_clear_error() { g_err.clear(); }
+sl_status api_error(sl_status st, const char* msg) { return fail(st, "%s", msg); }
+sl_status api_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+sl_status api_batch_options(int dim, const sl_options* o, BatchParams* bp) { return batch_options(dim, o, bp); }
+
+}  // namespace sl

@@ -9,6 +9,7 @@
 // per-graph breadth-first search run the same way.
 #include "sl_device.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace sl {
@@ -392,7 +393,26 @@ __global__ void k_batch_reset(int32_t* queue) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
 }
 
+__global__ __launch_bounds__(256) void k_fill_zero(uint8_t* __restrict__ p, size_t bytes) {
+  const size_t chunks = (bytes + 15) / 16;
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < chunks; c += (size_t)gridDim.x * 256) {
+    if (c * 16 + 16 <= bytes) {
+      reinterpret_cast<uint4*>(p)[c] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+      for (size_t b = c * 16; b < bytes; ++b) p[b] = 0;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const size_t chunks = (bytes + 15) / 16;
+  const unsigned blocks = (unsigned)std::min<size_t>((chunks + 255) / 256, 4096);
+  k_fill_zero<<<blocks, 256, 0, s>>>(reinterpret_cast<uint8_t*>(p), bytes);
+  return hipGetLastError();
+}
 
 bool batch_threads_supported(int threads) { return threads == 256 || threads == 512 || threads == 1024; }
 

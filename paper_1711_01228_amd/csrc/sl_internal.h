@@ -278,7 +278,17 @@ __host__ __device__ inline int batch_default_slices(int n_pad, int threads) {
   return s > 1 ? s : 1;
 }
 
+// Workgroups of a batched layout launch: the LDS of one graph (~78 KiB in 2-D,
+// ~127 KiB in 3-D) allows two, or one, per CU.
+inline int batch_layout_blocks(int dim, int cus, int count) {
+  const int per_cu = dim == 2 ? 2 : 1;
+  const int b = count < cus * per_cu ? count : cus * per_cu;
+  return b > 1 ? b : 1;
+}
+
 hipError_t launch_batch_reset(int32_t* queue, hipStream_t s);
+// Zero `bytes` bytes at p (16-byte aligned) with a kernel, not a memset node.
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_batch_distances(int threads, int blocks, const BatchGraph* graphs, const int32_t* order, int count,
                                   int32_t* queue, const int64_t* row_ptr, const int32_t* col_idx, uint8_t* d,
                                   double* W, int32_t* status, hipStream_t s);

@@ -209,3 +209,44 @@ def test_probe_rate_refuses_unknown_kind_before_any_device_call():
     assert lib.slp_probe_rate(4, None, ctypes.byref(per_s), ctypes.byref(ms)) == -1
     assert lib.slp_probe_rate(0, None, None, ctypes.byref(ms)) == -1
 
+
+
+# ---------------------------------------------------------------------------
+# allocation-free batched layout: everything it refuses, it refuses before any
+# device work (so without a GPU)
+# ---------------------------------------------------------------------------
+def _noalloc_status(gs, dim=2, batch=None):
+    args = batch if batch is not None else b.BatchArgs(gs)
+    opt = b.make_options(dim, 1.5, 1e-3, 10, True)
+    tot = b.sl_result()
+    return b.LIB.sl_batch_layout_noalloc(ctypes.byref(args.s), None, ctypes.byref(opt), None, None,
+                                         ctypes.byref(tot))
+
+
+def test_noalloc_refuses_a_batch_beyond_its_scratch():
+    # 17 distance blocks of 1 MiB (n_pad 1024) exceed the 16 MiB array
+    assert _noalloc_status([inputs.grid_graph(32, 32)] * 17) == b.SL_EINVAL
+    msg = b.last_error()
+    assert "SL_NOALLOC_SCRATCH_BYTES" in msg and str(16 * 1024 * 1024) in msg
+    # too many graphs for the host staging, whatever their size
+    assert _noalloc_status([inputs.to_csr(1, [])] * 4097) == b.SL_EINVAL and "graphs" in b.last_error()
+
+
+def test_noalloc_validates_like_the_plan():
+    args = b.BatchArgs([inputs.path_graph(4)])
+    args.graph_ptr = np.array([0, 2, 4], dtype=np.int64)
+    args.s.num_graphs, args.s.graph_ptr = 2, args.graph_ptr.ctypes.data
+    assert _noalloc_status(None, batch=args) == b.SL_EINVAL and "leaves graph" in b.last_error()
+    assert _noalloc_status([inputs.grid_graph(33, 32)]) == b.SL_EINVAL and "more than 1024" in b.last_error()
+    # a duplicate entry, then an asymmetric one
+    g = inputs.to_csr(3, [(0, 1), (1, 2)])
+    dup = inputs.Graph(3, np.array([0, 2, 4, 5], dtype=np.int64), np.array([1, 1, 0, 2, 1], dtype=np.int32),
+                       name="dup")
+    assert _noalloc_status([g, dup]) == b.SL_EINVAL and "duplicate" in b.last_error()
+    asym = inputs.to_csr(3, [(0, 1)])
+    asym.col_idx = np.array([1, 2], dtype=np.int32)  # row 0 -> 1, row 1 -> 2: no reverse entries
+    asym.row_ptr = np.array([0, 1, 2, 2], dtype=np.int64)
+    assert _noalloc_status([asym]) == b.SL_EINVAL and "not symmetric" in b.last_error()
+    # after those errors the validation bitmap is clean: a valid batch gets as
+    # far as the option check (dim 4 is refused after the batch checks)
+    assert _noalloc_status([g, inputs.grid_graph(4, 4)], dim=4) == b.SL_EINVAL and "dim" in b.last_error()
