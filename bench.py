@@ -39,8 +39,13 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}  # algorithmic flops of one ordered pair of the 
 # algorithmic flops of the safeguard term of one unordered pair (the stress
 # difference w (r~ - r^H)(r~ + r^H - 2d)), transcendentals (rsq, sqrt, rcp)
 # counted as 0 flops as in the force term: 15 in 2-D, and 5 more in 3-D for the
-# third coordinate of e, 2t - e and m
+# third coordinate of e, 2t - e and m (the pass over ordered pairs)
 SG_FLOPS_PER_UNORDERED_PAIR = {2: 15, 3: 20}
+# the pass over unordered pairs sums the bounds U = -2 sum_i e_i.F_i + sum c |e|^2
+# and L = -2 sum_i e_i.F_i - sum w |e|^2 instead: per pair e = e_i - e_j (2),
+# |e|^2 (3), and the two accumulating FMAs (4): 9 in 2-D, 12 in 3-D (the
+# O(n) dot product e.F is left out)
+SG_BOUNDS_FLOPS_PER_UNORDERED_PAIR = {2: 9, 3: 12}
 # the library's default force pass: once per unordered pair in 2-D from a
 # padded size of 32768 vertices, else over every ordered pair (the faster one)
 SYM_MIN_N_PAD = 32768
@@ -399,11 +404,17 @@ def time_to_converge(plan, Xdev0, omegas=(1.0,) + SOR_OMEGAS):
     """Wall time to res <= 1e-3 from the same start for each fixed omega (one
     untimed run first, so that every timed run replays captured graphs), and
     the speedup of omega = 2.5 and of the fastest omega over omega = 1."""
+    import numpy as np
     import torch
 
     ttc = {}
     for om in omegas:
-        plan.run(Xdev0.clone(), omega=om, tol=1e-3, max_iter=3000)
+        # untimed run with a trace: how each safeguard decision was taken
+        warm = plan.run(Xdev0.clone(), omega=om, tol=1e-3, max_iter=3000, trace=True)
+        tr = warm["trace"][:warm["iterations"]]
+        decided = tr[:, 1] >= 0
+        by_bounds = int(np.sum(decided & np.isnan(tr[:, 2])))
+        exact_after_bounds = int(np.sum(decided & ~np.isnan(tr[:, 2]) & ~np.isnan(tr[:, 5])))
         X = Xdev0.clone()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -414,6 +425,10 @@ def time_to_converge(plan, Xdev0, omegas=(1.0,) + SOR_OMEGAS):
                                 "iterations": r["iterations"], "converged": bool(r["converged"]),
                                 "rejected": r["rejected"], "final_residual": r["residual"],
                                 "final_stress": plan.stress(X)}
+        if om != 1.0:
+            ttc["omega=%g" % om]["safeguard_decisions"] = {"by_bounds": by_bounds,
+                                                           "exact_pass": exact_after_bounds,
+                                                           "total": int(np.sum(decided))}
         log("time-to-converge omega=%g: %s" % (om, ttc["omega=%g" % om]))
     base = ttc["omega=1"]["seconds"]
     best = min((o for o in omegas if o != 1.0), key=lambda o: ttc["omega=%g" % o]["seconds"])
@@ -608,7 +623,8 @@ def main():
     ms = plan.profile(Xdev0, omega=args.omega, reps=5)
     sym = sym_default(dim, n)
     t_fs = (ms["force_safeguard_sym"] if sym else ms["force_safeguard"]) * 1e-3
-    flops = FLOPS_PER_PAIR[dim] * pairs + SG_FLOPS_PER_UNORDERED_PAIR[dim] * pairs / 2
+    sg_flops = (SG_BOUNDS_FLOPS_PER_UNORDERED_PAIR if sym else SG_FLOPS_PER_UNORDERED_PAIR)[dim]
+    flops = FLOPS_PER_PAIR[dim] * pairs + sg_flops * pairs / 2
     achieved = flops / t_fs / 1e12
     t_force = (ms["force_sym"] if sym else ms["force"]) * 1e-3
     a_force = FLOPS_PER_PAIR[dim] * pairs / t_force / 1e12
@@ -624,7 +640,9 @@ def main():
                 "kernel_ms": round(t_fs * 1e3, 4),
                 "flops_per_launch": flops,
                 "flops_per_unit": {"ordered_pair_force": FLOPS_PER_PAIR[dim],
-                                   "unordered_pair_safeguard": SG_FLOPS_PER_UNORDERED_PAIR[dim]},
+                                   "unordered_pair_safeguard": sg_flops},
+                "safeguard": ("bounds U >= f(X~) - f(X^H) >= L; the exact difference only when they leave "
+                              "its sign open" if sym else "the exact difference, pair by pair"),
                 "algorithmic_bytes_per_launch": abytes,
                 "hbm_GBps_algorithmic": round(abytes / t_fs / 1e9, 1),
                 "force_pass": {"kernel": ("k_force_sym<2, false> + k_sym_reduce<2>" if sym else "k_force") +
@@ -633,6 +651,7 @@ def main():
                                "frac": round(a_force / PEAK_FP32_TFLOPS, 4)},
                 "other_kind": other,
                 "separate_passes_ms": round(ms["force"] + ms["safeguard"], 4),
+                "exact_variant_ms": round(ms["force_safeguard_sym_exact"], 4) if sym else None,
                 "step_kernel_ms": {k: round(v, 4) for k, v in ms.items()},
                 "measured_ceilings": measured_ceilings()}
     roofline["frac_of_measured_fma"] = round(achieved / roofline["measured_ceilings"]["fp32_fma_TFLOPs"], 4)

@@ -57,15 +57,27 @@ typedef enum {
 } sl_status;
 
 /* Columns of one trace row (one row per iteration, doubles). */
-#define SL_TRACE_COLS 5
+#define SL_TRACE_COLS 7
 /*   [0] res_k                      relative step ||X^H - X^k|| / ||X^H - mean||
  *   [1] accepted                   1 / 0 for the safeguard decision, -1 when no
  *                                  extrapolation is formed (omega == 1)
- *   [2] f(X~) - f(X^H)             summed pair by pair (0 when not evaluated)
+ *   [2] f(X~) - f(X^H)             summed pair by pair (0 when no safeguard is
+ *                                  evaluated; NaN when the bounds [5], [6] decided)
  *   [3] paper's factor used        omega - 1 of this iteration (NaN with per-vertex
  *                                  factors)
  *   [4] f(X^k)                     stress at the iterate the step starts from
- *                                  (NaN unless SL_FLAG_TRACE_STRESS)                */
+ *                                  (NaN unless SL_FLAG_TRACE_STRESS)
+ *   [5] U >= f(X~) - f(X^H)        bounds formed by the force pass over unordered
+ *   [6] L <= f(X~) - f(X^H)        pairs (SL_FLAG_SYM_FORCE with the fused
+ *                                  safeguard): each pair's term w (r~ - r^H)
+ *                                  (r~ + r^H - 2d) equals -c m - kappa delta^2 with
+ *                                  c = 1/(d r~) - 1/d^2, m = r~^2 - r^H^2,
+ *                                  kappa = 1/(d r~), delta = r~ - r^H, and
+ *                                  delta^2 <= |e_i - e_j|^2 (e = X~ - X^H), so
+ *                                  U = sum -c m and L = U - sum kappa |e_i - e_j|^2.
+ *                                  U <= 0 keeps X~ and L > 0 keeps X^H without [2];
+ *                                  otherwise [2] is summed and decides.  NaN when
+ *                                  no bounds are formed                          */
 
 /* Relaxation strategies (Sec. 5.2; per-vertex factors: Sec. 6, item 1).  Iterations
  * are numbered globally: iteration k of a call is iteration g = iter_offset + k. */
@@ -267,9 +279,12 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  *         (SL_FLAG_SYM_FORCE; allocates its buffers on first use)
  *   ms[6] the force pass at X~ with the safeguard summed in (the pass that
  *         replaces ms[0] + ms[2] in an iteration that extrapolates)
- *   ms[7] the same over unordered pairs with its reduction kernel
- *         (SL_FLAG_SYM_FORCE)
- * ms holds 8 doubles.
+ *   ms[7] the force pass over unordered pairs at X~ with the bounds of the
+ *         safeguard (trace columns 5 and 6) summed in, with its reduction
+ *         kernel (SL_FLAG_SYM_FORCE)
+ *   ms[8] the same with f(X~) - f(X^H) itself summed in as well (the variant an
+ *         iteration takes after one whose bounds left the decision open)
+ * ms holds 9 doubles.
  * For profilers and benchmarks; the iterate buffers of the plan are left in an
  * unspecified state (a later sl_plan_run starts from its own X). */
 sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double omega, int32_t reps, void* stream,

@@ -71,6 +71,8 @@ def _load():
                 "slo_weight_sums": (None, [i32, P, P]),
                 "slo_stress": (f64, [i32, i32, P, P]),
                 "slo_stress_delta": (None, [i32, i32, P, P, P, P, P]),
+                "slo_stress_delta_bounds": (None, [i32, i32, P, P, P, P]),
+                "slo_stress_delta_bounds_graph": (ctypes.c_int, [i32, i32, P, P, P, P, P, P]),
                 "slo_apply_LW": (None, [i32, i32, P, P, P]),
                 "slo_apply_LY": (None, [i32, i32, P, P, P]),
                 "slo_majorant": (f64, [i32, i32, P, P, P]),
@@ -170,6 +172,29 @@ def stress_delta(D, XA, XB):
     a, b = ctypes.c_double(), ctypes.c_double()
     lib.slo_stress_delta(D.shape[0], XA.shape[1], _p(D), _p(XA), _p(XB), ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
+
+
+def stress_delta_bounds(D, XA, XB):
+    """(U, L, sum |c m|, sum kappa |e|^2): U >= f(XA) - f(XB) >= L from the
+    pair terms' first-order parts (see the C source)."""
+    lib = _load()
+    D, XA, XB = _f64(D), _f64(XA), _f64(XB)
+    out = np.zeros(4)
+    lib.slo_stress_delta_bounds(D.shape[0], XA.shape[1], _p(D), _p(XA), _p(XB), _p(out))
+    return tuple(float(v) for v in out)
+
+
+def stress_delta_bounds_graph(row_ptr, col_idx, XA, XB, lengths=None):
+    """stress_delta_bounds with each distance row found from the graph when
+    needed, followed by stress_delta's (difference, scale) from the same rows:
+    (U, L, sum |c m|, sum kappa |e|^2, f(XA) - f(XB), scale)."""
+    lib = _load()
+    rp, ci, ln = _csr(row_ptr, col_idx, lengths)
+    XA, XB = _f64(XA), _f64(XB)
+    out = np.zeros(6)
+    _check(lib.slo_stress_delta_bounds_graph(XA.shape[0], XA.shape[1], _p(rp), _p(ci), _p(ln), _p(XA), _p(XB),
+                                             _p(out)), "stress_delta_bounds_graph")
+    return tuple(float(v) for v in out)
 
 
 def stress_delta_graph(row_ptr, col_idx, XA, XB, lengths=None):

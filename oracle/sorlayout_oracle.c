@@ -239,6 +239,64 @@ void slo_stress_delta(int32_t n, int32_t dim, const double* D, const double* XA,
   free(ps);
 }
 
+/* Bounds of the safeguard's sum f(XA) - f(XB) from first-order terms.   */
+/* With t = xA_i - xA_j, rA = |t|, rB = |xB_i - xB_j|, e = (xA_i - xB_i)  */
+/* - (xA_j - xB_j), m = rA^2 - rB^2, c = 1/(d rA) - 1/d^2 (the pair's     */
+/* coefficient in the eq. 5 residual at XA), kappa = 1/(d rA) and        */
+/* delta = rA - rB, each pair's term of eq. 1's difference is             */
+/*   w (rA - d)^2 - w (rB - d)^2 = w m - (2/d) delta = -c m - kappa delta^2 */
+/* (m = delta (2 rA - delta)), and 0 <= delta^2 <= |e|^2 (triangle        */
+/* inequality).  So U = sum -c m >= f(XA) - f(XB) >= U - sum kappa |e|^2 = L. */
+/* out = {U, L, sum |c m|, sum kappa |e|^2}; U = +inf when two vertices   */
+/* with a path between them coincide in XA (c is unbounded there).        */
+/* Test infrastructure for the bounds the GPU's unordered pass reports;   */
+/* the method's own decision is slo_stress_delta's.                       */
+static void stress_bounds_row(int32_t n, int32_t dim, const double* drow, int32_t i, const double* XA,
+                              const double* XB, double out[4]) {
+  double u = 0.0, q = 0.0, su = 0.0;
+  for (int32_t j = i + 1; j < n; ++j) {
+    const double d = drow[j];
+    const double w = w_of(d);
+    if (w == 0.0) continue;
+    const double ra = dist(dim, XA + (size_t)i * dim, XA + (size_t)j * dim);
+    const double rb = dist(dim, XB + (size_t)i * dim, XB + (size_t)j * dim);
+    double e2 = 0.0;
+    for (int32_t k = 0; k < dim; ++k) {
+      const double e = (XA[(size_t)i * dim + k] - XB[(size_t)i * dim + k]) -
+                       (XA[(size_t)j * dim + k] - XB[(size_t)j * dim + k]);
+      e2 += e * e;
+    }
+    if (ra == 0.0) {
+      u = INFINITY;
+      continue;
+    }
+    const double kappa = 1.0 / (d * ra);
+    const double c = kappa - w;
+    const double m = ra * ra - rb * rb;
+    u += -c * m;
+    su += fabs(c * m);
+    q += kappa * e2;
+  }
+  out[0] = u;
+  out[1] = u - q;
+  out[2] = su;
+  out[3] = q;
+}
+
+void slo_stress_delta_bounds(int32_t n, int32_t dim, const double* D, const double* XA, const double* XB,
+                             double out[4]) {
+  double* part = (double*)malloc(sizeof(double) * 4 * (size_t)(n > 0 ? n : 1));
+  if (!part) { for (int k = 0; k < 4; ++k) out[k] = NAN; return; }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t i = 0; i < n; ++i) stress_bounds_row(n, dim, D + (size_t)i * n, i, XA, XB, part + 4 * (size_t)i);
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t i = 0; i < n; ++i)
+    for (int k = 0; k < 4; ++k) t[k] += part[4 * (size_t)i + k];
+  t[1] = t[0] - t[3];  /* L as U - sum kappa |e|^2 of the totals */
+  for (int k = 0; k < 4; ++k) out[k] = t[k];
+  free(part);
+}
+
 /* ---------------------------------------------------------------------- */
 /* Laplacians of Prop. 2.1, applied to a placement.                       */
 /*   l^W_ij = -w_ij (i != j),  l^W_ii = -sum_{k != i} l^W_ik              */
@@ -902,6 +960,44 @@ int slo_stress_delta_graph(int32_t n, int32_t dim, const int64_t* row_ptr, const
   *scale = b;
   free(pd);
   free(ps);
+  return status;
+}
+
+/* The bounds of slo_stress_delta_bounds with each distance row found from */
+/* the graph when needed, and from the same rows the difference and scale of */
+/* slo_stress_delta: out = {U, L, sum |c m|, sum kappa |e|^2, delta, scale}. */
+int slo_stress_delta_bounds_graph(int32_t n, int32_t dim, const int64_t* row_ptr, const int32_t* col_idx,
+                                  const double* len, const double* XA, const double* XB, double out[6]) {
+  double* part = (double*)malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1));
+  int status = SLO_OK;
+  if (!part) return SLO_ENOMEM;
+#pragma omp parallel
+  {
+    double* drow = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!drow) {
+#pragma omp critical
+      status = SLO_ENOMEM;
+    }
+#pragma omp for schedule(dynamic, 64)
+    for (int32_t i = 0; i < n; ++i) {
+      if (!drow) continue;
+      int r = slo_sssp(n, row_ptr, col_idx, len, i, drow);
+      if (r != SLO_OK) {
+#pragma omp critical
+        status = r;
+        continue;
+      }
+      stress_bounds_row(n, dim, drow, i, XA, XB, part + 6 * (size_t)i);
+      stress_delta_row(n, dim, drow, i, XA, XB, part + 6 * (size_t)i + 4, part + 6 * (size_t)i + 5);
+    }
+    free(drow);
+  }
+  double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int32_t i = 0; i < n; ++i)
+    for (int k = 0; k < 6; ++k) t[k] += part[6 * (size_t)i + k];
+  t[1] = t[0] - t[3];
+  for (int k = 0; k < 6; ++k) out[k] = t[k];
+  free(part);
   return status;
 }
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libsorlayout.so")
 SL_OK, SL_EINVAL, SL_ENOMEM, SL_EDEVICE, SL_ERANGE, SL_ENUMERIC, SL_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "SL_OK", -1: "SL_EINVAL", -2: "SL_ENOMEM", -3: "SL_EDEVICE", -4: "SL_ERANGE",
                 -5: "SL_ENUMERIC", -6: "SL_ENOTSUP"}
-SL_TRACE_COLS = 5
+SL_TRACE_COLS = 7
 SL_FLAG_TRACE_STRESS = 1
 SL_FLAG_NO_GRAPH = 2
 SL_FLAG_SYM_FORCE = 4
@@ -267,7 +267,7 @@ def sl_plan_weights(plan: int, n: int, stream=None) -> np.ndarray:
 
 
 def sl_plan_profile(plan: int, X_ptr: int, dim: int, omega: float, reps: int, stream=None) -> np.ndarray:
-    ms = np.zeros(8, dtype=np.float64)
+    ms = np.zeros(9, dtype=np.float64)
     _check(LIB.sl_plan_profile(plan, X_ptr, int(dim), float(omega), int(reps), _stream_handle(stream),
                                ms.ctypes.data))
     return ms
@@ -390,7 +390,7 @@ class Plan:
         """Average device ms of each kernel of one iteration (HIP events)."""
         ms = sl_plan_profile(self.handle, X.data_ptr(), self.dim, omega, reps, stream)
         return dict(zip(("force", "update", "safeguard", "select", "lw_matvec", "force_sym",
-                                  "force_safeguard", "force_safeguard_sym"), ms.tolist()))
+                         "force_safeguard", "force_safeguard_sym", "force_safeguard_sym_exact"), ms.tolist()))
 
     def close(self):
         if self.handle:

@@ -15,6 +15,8 @@
 
 using namespace sl;
 
+static_assert(SL_TRACE_COLS == kTraceCols, "trace row layout");
+
 namespace {
 
 // The calling thread's last error message: a fixed buffer, so that reporting an
@@ -189,6 +191,7 @@ struct sl_plan {
   int nsym_items = 0;
   float* Pi = nullptr;          // row partials: items x sym_rows_per_item() x dim
   float* Pj = nullptr;          // column partials: panels x n_pad x dim
+  double* edot = nullptr;       // unordered fused pass: per reduction workgroup, sum e_i . F_i(X~)
   double* W = nullptr;          // n_pad
   float* Xb = nullptr;          // 3 iterate buffers
   float* Eb = nullptr;          // x~ - x^H, same format as one iterate buffer
@@ -242,6 +245,7 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->sym_panel_items);
   (void)hipFree(p->Pi);
   (void)hipFree(p->Pj);
+  (void)hipFree(p->edot);
   (void)hipFree(p->W);
   (void)hipFree(p->Xb);
   (void)hipFree(p->Eb);
@@ -476,7 +480,9 @@ sl_status ensure_sym(sl_plan* p) {
   int32_t* panel_items = nullptr;
   float* Pi = nullptr;
   float* Pj = nullptr;
+  double* edot = nullptr;
   hipError_t e = hipMalloc(&items, sizeof(int4) * ss.items.size());
+  if (e == hipSuccess) e = hipMalloc(&edot, sizeof(double) * sym_reduce_blocks(p->n_pad));
   if (e == hipSuccess) e = hipMalloc(&panel_items, sizeof(int32_t) * ss.panel_items.size());
   if (e == hipSuccess) e = hipMalloc(&Pi, sizeof(float) * ss.items.size() * sym_rows_per_item() * p->dim);
   if (e == hipSuccess) e = hipMalloc(&Pj, sizeof(float) * (size_t)ss.npanels * p->n_pad * p->dim);
@@ -491,8 +497,10 @@ sl_status ensure_sym(sl_plan* p) {
     (void)hipFree(panel_items);
     (void)hipFree(Pi);
     (void)hipFree(Pj);
+    (void)hipFree(edot);
     return hip_fail(e, "unordered-pair force pass setup");
   }
+  p->edot = edot;
   p->sym_items = items;
   p->sym_panel_items = panel_items;
   p->Pi = Pi;
@@ -521,10 +529,22 @@ sl_status enqueue_fused_tail(sl_plan* p, const LoopParams& lp, const sl_options*
   HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red, p->ps),
           "update kernel");
   if (lp.sym) {
-    HIP_TRY(launch_force_sym_sg(p->dim, lp, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items, p->nsym_items,
-                                p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->n_pad, p->ps),
-            "symmetric fused force and safeguard kernels");
-    HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsym_items, p->st, o->trace, p->ps),
+    // the pass at X~ with the bounds U >= f(X~) - f(X^H) >= L; the exact
+    // difference (and its select) only when they leave its sign open
+    // (the exact variant instead after an iteration whose bounds left it open,
+    // until they would have decided again: both launches are gated by the state)
+    for (int exact = 0; exact < 2; ++exact)
+      HIP_TRY(launch_force_sym_sg(p->dim, lp, exact, 1, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+                                  p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
+                                  p->n_pad, p->ps),
+              "symmetric fused force and safeguard kernels");
+    HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsym_items, p->st, o->trace, p->ps,
+                          kSelectBounds, p->edot, (int)sym_reduce_blocks(p->n_pad)),
+            "select kernel");
+    HIP_TRY(launch_sgdelta(p->dim, p->d, p->df, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart, p->sp,
+                           p->ps, 1),
+            "safeguard kernel");
+    HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsg, p->st, o->trace, p->ps, kSelectExact),
             "select kernel");
     HIP_TRY(launch_force_sym(p->dim, 1, p->d, p->df, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
                              p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
@@ -807,7 +827,7 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess)
     e = hipMalloc(&p->sgpart, sizeof(double) * std::max<size_t>({(size_t)p->nsg * kEnumCandidates,
                                                                  (size_t)p->sp.blocks_x * p->sp.slices,
-                                                                 make_sym_split(p->n_pad).items.size()}));
+                                                                 3 * make_sym_split(p->n_pad).items.size()}));
   if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
   if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
   if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
@@ -1010,7 +1030,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   if (!(std::isfinite(omega) && omega > 0.0 && omega <= 16.0)) return fail(SL_EINVAL, "omega outside (0, 16]");
   sl_status s = join_from(p, (hipStream_t)stream);
   if (s != SL_OK) return s;
-  for (int k = 0; k < 8; ++k) ms[k] = 0.0;
+  for (int k = 0; k < 9; ++k) ms[k] = 0.0;
   if (p->n <= 1) return SL_OK;
   if (!p->df && (s = ensure_exact(p)) != SL_OK) return s;  // the L^W matvec exists for hop-count plans
   LoopParams lp{};
@@ -1034,7 +1054,7 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   LoopParams lpf = lp;  // the fused pass, extrapolating with omega
   lpf.fuse = 1;
   lpf.safeguard = 1;
-  for (int which = 0; which < 8; ++which) {
+  for (int which = 0; which < 9; ++which) {
     if (which == 4 && p->df) continue;
     if (which == 4) {  // a solver state from the current placement: r_0, z
       HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
@@ -1065,10 +1085,16 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                   "symmetric force kernels");
           break;
         case 7:
-          HIP_TRY(launch_force_sym_sg(p->dim, lpf, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
-                                      p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->n_pad,
-                                      p->ps),
+          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 0, 0, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+                                      p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
+                                      p->n_pad, p->ps),
                   "symmetric fused force and safeguard kernels");
+          break;
+        case 8:
+          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 1, 0, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+                                      p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
+                                      p->n_pad, p->ps),
+                  "symmetric fused force and exact safeguard kernels");
           break;
         case 1:
           HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red,

@@ -53,7 +53,15 @@ struct DevState {
   double enum_c;      // enumerating: factor picked by the last select
   int32_t enum_pending;  // enumerating: X~ = X^H + enum_c * step is still to be formed
   int32_t need_force;    // fused safeguard: X~ was rejected, the force at X^H is still to come
+  int32_t need_exact;    // bounded safeguard: the bounds left the sign of f(X~) - f(X^H) open,
+                         // the exact pass and the second select are still to come
+  int32_t exact_next;    // bounded safeguard: the next extrapolating iteration sums the exact
+                         // difference in its fused pass (the bounds left the last one open)
+  double bound_u, bound_l;  // bounded safeguard: U >= f(X~) - f(X^H) >= L of this iteration
 };
+
+// Columns of a trace row (SL_TRACE_COLS of sorlayout.h).
+constexpr int kTraceCols = 7;
 
 constexpr int kEnumCandidates = 18;  // paper's factors 0.5, 1.0, ..., 9.0 (0 = keep X^H)
 
@@ -73,6 +81,10 @@ struct LoopParams {
   const double* exact_y;
   int32_t sym;   // the force pass runs over unordered pairs (F in slice 0; slices = 1)
   int32_t fuse;  // the safeguard rides on the next iteration's force pass (at X~)
+  // the fused pass forms bounds U >= f(X~) - f(X^H) >= L instead of the
+  // difference itself; the exact pass runs only when they leave its sign open
+  int32_t bounds;
+  int32_t pad2;
 };
 
 // ---------------------------------------------------------------------------
@@ -135,12 +147,17 @@ int sym_rows_per_item();  // rows of one work item (its panel of row strips)
 hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                             const DevState* st, const int4* items, int nitems, const int32_t* panel_items, float* Pi,
                             float* Pj, double* fpart, int n_pad, hipStream_t s);
-// The same pass at X~ with the safeguard summed in (one double per item into
-// sgpart), as launch_force_sg.
-hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
-                               size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
-                               const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart,
-                               int n_pad, hipStream_t s);
+// The same pass at X~ with the bounds of the safeguard summed in: B and C of
+// each item into sgpart[2 item], sgpart[2 item + 1], and sum e_i . F_i of each
+// reduction workgroup into edot (sym_reduce_blocks(n_pad) doubles).  With
+// `exact` the difference f(X~) - f(X^H) itself too, into sgpart[2 nitems + item].
+// With `gated` the launch does work only in the iterations the state gives to
+// it (DevState::exact_next: the exact variant, else the bounds alone).
+hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, int exact, int gated, const uint8_t* d, const float* df,
+                               const float* Xb, size_t stride, const float* Eb, const DevState* st, const int4* items,
+                               int nitems, const int32_t* panel_items, float* Pi, float* Pj, double* sgpart,
+                               double* fpart, double* edot, int n_pad, hipStream_t s);
+unsigned sym_reduce_blocks(int n_pad);
 // One application of L^W to p (also used by the profiler).
 hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double* W, const DevState* st, CgState* cg,
                      double* qpart, double* pqrec, const Split& sp, hipStream_t s);
@@ -224,11 +241,20 @@ hipError_t launch_update(int dim, const LoopParams& p, const double* fpart, cons
 // Work items (row block, first column group, end group, 0) of the safeguard
 // pass: the upper triangle in equal runs of column groups.
 std::vector<int4> triangle_items(const Split& sp);
+// gate: run only when the state asks for the exact difference (need_exact).
 hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                           const float* Eb, const int4* items, int nitems, const DevState* st, double* sgpart,
-                          const Split& sp, hipStream_t s);
+                          const Split& sp, hipStream_t s, int gate = 0);
+// Modes of the select kernel.
+constexpr int kSelectPlain = 0;   // sgpart: nsg partial sums of f(X~) - f(X^H)
+constexpr int kSelectBounds = 1;  // sgpart: (B, C) of nsg items, edot: nedot partial sums of e . F, and
+                                  // after the exact variant (exact_next) the nsg differences from
+                                  // sgpart + 2 nsg; decides from those, from U and L, or leaves the
+                                  // iteration to kSelectExact (need_exact)
+constexpr int kSelectExact = 2;   // only after kSelectBounds left the sign open: sgpart as kSelectPlain
 hipError_t launch_select(int dim, const LoopParams& p, const double* red, int nred, const double* sgpart,
-                         int nsg, DevState* st, double* trace, hipStream_t s);
+                         int nsg, DevState* st, double* trace, hipStream_t s, int mode = kSelectPlain,
+                         const double* edot = nullptr, int nedot = 0);
 hipError_t launch_sgdelta_enum(int dim, const uint8_t* d, const float* Xb, size_t stride, const float* Eb,
                                const int4* items, int nitems, const DevState* st, double* sgpart, const Split& sp,
                                hipStream_t s);

@@ -263,10 +263,10 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
                                                  const float* __restrict__ Xb, size_t stride,
                                                  const float* __restrict__ Eb, const int4* __restrict__ items,
                                                  int nitems, const DevState* __restrict__ st,
-                                                 double* __restrict__ sgpart, int ng) {
+                                                 double* __restrict__ sgpart, int ng, int gate) {
   using V = typename VecT<DIM>::T;
   __shared__ float lut[256];
-  if (st->done) return;
+  if (st->done || (gate && !st->need_exact)) return;
   if constexpr (!FD) {
     lut[threadIdx.x] = threadIdx.x ? 1.0f / (float)threadIdx.x : 0.f;
     __syncthreads();
@@ -576,31 +576,53 @@ __global__ __launch_bounds__(256) void k_apply_enum(const float* __restrict__ Eb
 
 // ---------------------------------------------------------------------------
 // Alg. 2 lines 6-9 and the termination test, one workgroup.
+// mode kSelectPlain: sgpart holds partial sums of f(X~) - f(X^H).
+// mode kSelectBounds: sgpart holds (B, C) per item and edot partial sums of
+//   P = sum_i e_i . F_i(X~): U = -2P + B >= f(X~) - f(X^H) >= -2P - C = L.  U <= 0
+//   keeps X~, L > 0 keeps X^H; otherwise the iteration is left open (need_exact)
+//   for the exact pass and a kSelectExact select.
+// mode kSelectExact: only when need_exact is set; as kSelectPlain.
 // ---------------------------------------------------------------------------
+// Sum of x[b * step + off] over b < count: eight independent sums per thread
+// (loads in flight), added in a fixed order; every thread's share.
+__device__ __forceinline__ double strided_share(const double* __restrict__ x, int count, int step, int off) {
+  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < count; b += 256 * 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (b + q * 256 < count) u[q] += x[(size_t)(b + q * 256) * step + off];
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) t += u[q];
+  return t;
+}
+
 __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __restrict__ red, int nred,
                                                 const double* __restrict__ sgpart, int nsg,
-                                                DevState* __restrict__ st, double* __restrict__ trace, int dim) {
-  __shared__ double sh[8][256];
+                                                DevState* __restrict__ st, double* __restrict__ trace, int dim,
+                                                int mode, const double* __restrict__ edot, int nedot) {
+  __shared__ double sh[11][256];
   __shared__ double cand[kEnumCandidates];
   if (st->done) return;
+  if (mode == kSelectExact && !st->need_exact) return;
   const int k = st->iter;
   const double wp = p.omega_sched ? p.omega_sched[k] : p.omega_p;
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int ran_exact = st->exact_next;  // which variant of the unordered fused pass ran
+  double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nred; b += 256) {
 #pragma unroll
     for (int q = 0; q < 7; ++q) v[q] += red[(size_t)b * 8 + q];
   }
   const bool sg = !p.enumerate && p.safeguard && (wp != 0.0 || p.omega_vertex);
-  if (sg) {
-    // eight independent sums per thread (loads in flight), added in a fixed order
-    double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nsg; b += 256 * 8) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (b + q * 256 < nsg) u[q] += sgpart[b + q * 256];
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[7] += u[q];
+  const bool bounds = sg && mode == kSelectBounds;
+  if (bounds) {
+    v[7] = strided_share(sgpart, nsg, 2, 0);  // B
+    v[8] = strided_share(sgpart, nsg, 2, 1);  // C
+    v[9] = strided_share(edot, nedot, 1, 0);  // P
+    if (ran_exact) v[10] = strided_share(sgpart + 2 * (size_t)nsg, nsg, 1, 0);
+  } else if (sg) {
+    v[7] = strided_share(sgpart, nsg, 1, 0);
   }
   if (p.enumerate) {
     // 14 threads per candidate, each with eight independent sums over every
@@ -627,12 +649,42 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
       cand[threadIdx.x] = t;
     }
   }
-  block_sum<8>(v, sh);
+  block_sum<11>(v, sh);
   if (threadIdx.x != 0) return;
   if (v[6] > 0.0) {  // a non-finite coordinate: keep the last finite iterate
     st->status = -5;
     st->done = 1;
     return;
+  }
+  const double nan = __builtin_nan("");
+  double df = sg ? v[7] : 0.0, bu = nan, bl = nan;
+  bool take = true;
+  if (bounds) {
+    bu = -2.0 * v[9] + v[7];
+    bl = -2.0 * v[9] - v[8];
+    st->bound_u = bu;
+    st->bound_l = bl;
+    const bool decisive = bu <= 0.0 || bl > 0.0;
+    if (ran_exact) {  // the pass summed the difference too: it decides
+      df = v[10];
+      take = df <= 0.0;
+      st->exact_next = decisive ? 0 : 1;  // back to the bounds alone once they would have decided
+    } else if (decisive) {
+      df = nan;  // the difference itself is not formed when the bounds decide
+      take = bu <= 0.0;
+    } else {  // sign open: the exact pass and the second select take the iteration
+      st->need_force = 0;
+      st->need_exact = 1;
+      return;
+    }
+  } else if (mode == kSelectExact) {
+    take = df <= 0.0;
+    bu = st->bound_u;
+    bl = st->bound_l;
+    st->need_exact = 0;
+    st->exact_next = 1;  // the next fused pass sums the difference in as well
+  } else {
+    take = df <= 0.0;
   }
   const double dsq = v[0], hsq = v[1];
   const double mean2 = (v[2] * v[2] + v[3] * v[3] + (dim == 3 ? v[4] * v[4] : 0.0)) / (double)p.n;
@@ -640,7 +692,6 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
   const double res = dsq > 0.0 ? sqrt(dsq) / sqrt(den2 > 0.0 ? den2 : 0.0) : 0.0;
   const int cur = st->cur, h = (cur + 1) % 3, t = (cur + 2) % 3;
   double accepted;
-  double df = sg ? v[7] : 0.0;
   st->need_force = 0;
   double used = p.omega_vertex ? __builtin_nan("") : wp;
   st->enum_pending = 0;
@@ -669,7 +720,6 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     st->cur = h;
     accepted = -1.0;
   } else if (p.safeguard) {
-    const bool take = df <= 0.0;
     st->cur = take ? t : h;
     accepted = take ? 1.0 : 0.0;
     if (!take) st->rejected += 1;
@@ -684,12 +734,14 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
   st->residual = res;
   st->last_df = df;
   if (trace) {
-    double* row = trace + (size_t)k * 5;
+    double* row = trace + (size_t)k * kTraceCols;
     row[0] = res;
     row[1] = accepted;
     row[2] = df;
     row[3] = used;
-    row[4] = p.stress ? 0.5 * v[5] : __builtin_nan("");
+    row[4] = p.stress ? 0.5 * v[5] : nan;
+    row[5] = bu;
+    row[6] = bl;
   }
   if (res <= p.tol) {
     st->converged = 1;
@@ -877,14 +929,14 @@ std::vector<int4> triangle_items(const Split& sp) {
 
 hipError_t launch_sgdelta(int dim, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                           const float* Eb, const int4* items, int nitems, const DevState* st, double* sgpart,
-                          const Split& sp, hipStream_t s) {
+                          const Split& sp, hipStream_t s, int gate) {
   const unsigned nb = (unsigned)((nitems + 3) / 4);
   if (dim == 2) {
-    if (df) k_sgdelta<2, true><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
-    else k_sgdelta<2, false><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+    if (df) k_sgdelta<2, true><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng, gate);
+    else k_sgdelta<2, false><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng, gate);
   } else {
-    if (df) k_sgdelta<3, true><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
-    else k_sgdelta<3, false><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng);
+    if (df) k_sgdelta<3, true><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng, gate);
+    else k_sgdelta<3, false><<<nb, 256, 0, s>>>(d, df, Xb, stride, Eb, items, nitems, st, sgpart, sp.ng, gate);
   }
   return hipGetLastError();
 }
@@ -907,8 +959,9 @@ hipError_t launch_apply_enum(const float* Eb, float* Xb, size_t stride, const De
 }
 
 hipError_t launch_select(int dim, const LoopParams& p, const double* red, int nred, const double* sgpart,
-                         int nsg, DevState* st, double* trace, hipStream_t s) {
-  k_select<<<1, 256, 0, s>>>(p, red, nred, sgpart, nsg, st, trace, dim);
+                         int nsg, DevState* st, double* trace, hipStream_t s, int mode, const double* edot,
+                         int nedot) {
+  k_select<<<1, 256, 0, s>>>(p, red, nred, sgpart, nsg, st, trace, dim, mode, edot, nedot);
   return hipGetLastError();
 }
 

@@ -15,9 +15,18 @@
 //   columns  per-lane FP32 sums of p over the 8 strips, then one
 //            reduce-scatter across the wave (an exchange per lane bit), so that
 //            lane 4 k holds the panel's total for column k of the group
-// With SG the safeguard term of Alg. 2 (the fused pass's formula; every pair
-// here has j > i) is summed too, and the pass is taken at X~ (or at X^H for an
-// iteration without extrapolation).
+// With SG the pass is taken at X~ (or at X^H for an iteration without
+// extrapolation) and sums what bounds the safeguard of Alg. 2: with
+// t = x~_i - x~_j, e = e_i - e_j (e = x~ - x^H as stored), c the pair's force
+// coefficient at X~ and w = 1/d^2, each pair's share of f(X~) - f(X^H) is
+//   w (r~ - r^H)(r~ + r^H - 2d) = -c m - kappa delta^2,
+// m = r~^2 - r^H^2 = 2 e.t - |e|^2, kappa = 1/(d r~) >= 0, delta = r~ - r^H,
+// and 0 <= delta^2 <= |e|^2 (triangle inequality).  So
+//   U = sum -c m >= f(X~) - f(X^H) >= U - sum kappa |e|^2 = L,
+// and since sum_{i<j} c (e_i - e_j).t = sum_i e_i . F_i(X~),
+//   U = -2 P + B,  L = -2 P - C,  P = sum_i e_i . F_i,  B = sum c |e|^2,  C = sum w |e|^2.
+// Per pair the pass adds B and C (every pair here has j > i); P comes from the
+// reduction kernel, which has F_i.
 // The column totals go out once per (panel, column) and the row sums once per
 // (item, row), both as FP32; k_sym_reduce forms
 //   F_i = sum over the items of i's panel of the row partials
@@ -70,23 +79,47 @@ __device__ __forceinline__ float reduce_scatter(VF R, int lane) {
   return t;
 }
 
-template <int DIM, bool SG, bool FD>
+// Gates of the pass (the state decides at run time which launches do work).
+constexpr int kGateNone = 0;    // always
+constexpr int kGateForce = 1;   // only when the force at X^H is still needed (after a rejection)
+constexpr int kGateBounds = 2;  // only when the bounds alone are tried this iteration
+constexpr int kGateExact = 3;   // only when the exact difference is summed in this iteration
+
+__device__ __forceinline__ bool gate_closed(int gate, const DevState* st) {
+  return st->done || (gate == kGateForce && !st->need_force) || (gate == kGateBounds && st->exact_next) ||
+         (gate == kGateExact && !st->exact_next);
+}
+
+// -2/d of a weight-table entry (the entries of the exact variant carry it).
+template <typename T>
+__device__ __forceinline__ float lut_l2(const T& e) {
+  if constexpr (std::is_same<T, float4>::value) return e.z;
+  else return 0.f;
+}
+
+// SG = 0: force only.  SG = 1: the pass at X~ with the bounds' B and C.
+// SG = 2: the same with the exact f(X~) - f(X^H) summed in as well,
+//   term = m (1/d^2 - (2/d) / s),  m = 2 e.t - |e|^2,  s = r~ + r^H,
+//   r^H = sqrt|r~^2 - m|  (no difference of nearly equal squares).
+template <int DIM, int SG, bool FD>
 __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d, const float* __restrict__ df,
                                                    const float* __restrict__ Xb,
                                                    size_t stride, const float* __restrict__ Eb,
                                                    const double* __restrict__ omega_sched, double omega_p,
-                                                   int vertex_factors, int cond, const DevState* __restrict__ st,
+                                                   int vertex_factors, int gate, const DevState* __restrict__ st,
                                                    const int4* __restrict__ items, int nitems,
                                                    float* __restrict__ Pi, float* __restrict__ Pj,
                                                    double* __restrict__ sgpart, int nb, int ng, int n_pad) {
   using V = typename VecT<DIM>::T;
-  __shared__ float4 lut[256];                             // (1/d, 1/d^2, -2/d, 0)
+  using L = std::conditional_t<SG == 2, float4, float2>;
+  __shared__ L lut[256];                                  // (1/d, 1/d^2 [, -2/d, 0])
   __shared__ double rows[kWaves][kPanel][DIM][64];        // each wave's FP64 row sums of its 8 strips
-  if (st->done || (cond && !st->need_force)) return;
+  if (gate_closed(gate, st)) return;
   {
     const float fb = (float)threadIdx.x;
-    const float inv = threadIdx.x ? 1.0f / fb : 0.f;
-    lut[threadIdx.x] = make_float4(inv, threadIdx.x ? 1.0f / (fb * fb) : 0.f, -2.f * inv, 0.f);
+    const float inv = threadIdx.x ? 1.0f / fb : 0.f, w = threadIdx.x ? 1.0f / (fb * fb) : 0.f;
+    if constexpr (SG == 2) lut[threadIdx.x] = make_float4(inv, w, -2.f * inv, 0.f);
+    else lut[threadIdx.x] = make_float2(inv, w);
   }
   __syncthreads();  // the weight table; the waves are independent from here on
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -96,7 +129,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
   const int panel = it.x, g0 = it.y, g1 = it.z, item = it.w;
   bool sg = false;
   int xbuf = st->cur;
-  if constexpr (SG) {
+  if constexpr (SG != 0) {
     const double wp = omega_sched ? omega_sched[st->iter] : omega_p;
     sg = vertex_factors || wp != 0.0;
     xbuf = sg ? (st->cur + 2) % 3 : (st->cur + 1) % 3;  // X~, or X^H without extrapolation
@@ -108,7 +141,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
   for (int r = 0; r < kPanel; ++r)
 #pragma unroll
     for (int c = 0; c < DIM; ++c) racc[r][c][lane] = 0.0;
-  double S = 0.0;
+  double SB = 0.0, SC = 0.0, SD = 0.0;  // the item's B, C and exact difference
 
   for (int g = g0; g < g1; ++g) {
     const int jlo = g * kColGroup;
@@ -122,7 +155,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
     const int rfull = max(0, min(rlast, jlo / 64 - panel * kPanel));
     auto strips = [&](auto mask_tag, auto safe_tag, int ra, int rb) {
       constexpr bool MASK = decltype(mask_tag)::value;
-      constexpr bool SAFE = decltype(safe_tag)::value;
+      constexpr int SAFE = decltype(safe_tag)::value;  // 0, or SG
       if (ra >= rb) return;
       using C = typename DChunkT<FD>::T;
       C q = load_chunk<FD>(d, df, panel * kPanel + ra, ng, g, lane);
@@ -133,21 +166,21 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
         const C qn = load_chunk<FD>(d, df, panel * kPanel + (r + 1 < rb ? r + 1 : r), ng, g, lane);
         const V xi = X[ilo + lane];
         V ei{};
-        if constexpr (SAFE) ei = E[ilo + lane];
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, as = 0.f;
+        if constexpr (SAFE != 0) ei = E[ilo + lane];
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, ab = 0.f, ac = 0.f, ad = 0.f;
 #pragma unroll
         for (int k = 0; k < kColGroup; ++k) {
-          float inv, w, l2;  // 1/d, 1/d^2, -2/d (0 where d = 0)
+          float inv, w, l2 = 0.f;  // 1/d, 1/d^2, -2/d (0 where d = 0)
           if constexpr (FD) {
             const float dv = fchunk_at(q, k);
             inv = dv > 0.f ? __builtin_amdgcn_rcpf(dv) : 0.f;
             w = inv * inv;
-            l2 = -2.f * inv;
+            if constexpr (SAFE == 2) l2 = -2.f * inv;
           } else {
-            const float4 e4 = lut[byte_of(chunk_word(q, k), k & 3)];
+            const L e4 = lut[byte_of(chunk_word(q, k), k & 3)];
             inv = e4.x;
             w = e4.y;
-            l2 = e4.z;
+            if constexpr (SAFE == 2) l2 = lut_l2(e4);
           }
           const V p = xj[k];
           const float tx = xi.x - p.x, ty = xi.y - p.y;
@@ -171,37 +204,48 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
             a2 = fmaf(c, tz, a2);
             Cz[k] = fmaf(c, tz, Cz[k]);
           }
-          if constexpr (SAFE) {
+          if constexpr (SAFE != 0) {
             const V pe = ej[k];
             const float ex = ei.x - pe.x, ey = ei.y - pe.y;
-            float m = ex * fmaf(2.f, tx, -ex);
-            m = fmaf(ey, fmaf(2.f, ty, -ey), m);
+            float e2 = fmaf(ex, ex, ey * ey);
+            float et = fmaf(ex, tx, ey * ty);
             if constexpr (DIM == 3) {
               const float ez = ei.z - pe.z;
-              m = fmaf(ez, fmaf(2.f, tz, -ez), m);
+              e2 = fmaf(ez, ez, e2);
+              et = fmaf(ez, tz, et);
             }
-            const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
-            const float sum = fmaf(r2, rinv, rh);
-            float term = m * fmaf(l2, __builtin_amdgcn_rcpf(sum), w);
+            float mk = 1.f;  // 0 for the pairs j <= i of a diagonal group
             if constexpr (MASK) {
-              if (jlo + k <= ilo + lane) term = 0.f;
+              if (jlo + k <= ilo + lane) mk = 0.f;
             }
-            as += term;
+            e2 *= mk;
+            ab = fmaf(c, e2, ab);
+            ac = fmaf(w, e2, ac);
+            if constexpr (SAFE == 2) {
+              const float m = fmaf(2.f, et, -e2);  // r~^2 - r^H^2 (0 where masked)
+              const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
+              const float sum = fmaf(r2, rinv, rh);
+              ad = fmaf(m * mk, fmaf(l2, __builtin_amdgcn_rcpf(sum), w), ad);
+            }
           }
         }
         racc[r][0][lane] += (double)a0;
         racc[r][1][lane] += (double)a1;
         if constexpr (DIM == 3) racc[r][2][lane] += (double)a2;
-        if constexpr (SAFE) S += (double)as;
+        if constexpr (SAFE != 0) {
+          SB += (double)ab;
+          SC += (double)ac;
+        }
+        if constexpr (SAFE == 2) SD += (double)ad;
         q = qn;
       }
     };
     if (sg) {
-      strips(std::false_type{}, std::integral_constant<bool, SG>{}, 0, rfull);
-      strips(std::true_type{}, std::integral_constant<bool, SG>{}, rfull, rlast);
+      strips(std::false_type{}, std::integral_constant<int, SG>{}, 0, rfull);
+      strips(std::true_type{}, std::integral_constant<int, SG>{}, rfull, rlast);
     } else {
-      strips(std::false_type{}, std::false_type{}, 0, rfull);
-      strips(std::true_type{}, std::false_type{}, rfull, rlast);
+      strips(std::false_type{}, std::integral_constant<int, 0>{}, 0, rfull);
+      strips(std::true_type{}, std::integral_constant<int, 0>{}, rfull, rlast);
     }
     // the group's column totals over the panel: lane l holds column l >> 2
     float* pj = Pj + ((size_t)panel * n_pad + jlo) * DIM;
@@ -220,9 +264,17 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
 #pragma unroll
     for (int c = 0; c < DIM; ++c) out[c] = (float)racc[r][c][lane];
   }
-  if constexpr (SG) {
-    S = wave_sum(S);
-    if (lane == 0) sgpart[item] = S;
+  if constexpr (SG != 0) {
+    SB = wave_sum(SB);
+    SC = wave_sum(SC);
+    if (lane == 0) {
+      sgpart[2 * (size_t)item] = SB;
+      sgpart[2 * (size_t)item + 1] = SC;
+    }
+  }
+  if constexpr (SG == 2) {
+    SD = wave_sum(SD);
+    if (lane == 0) sgpart[2 * (size_t)nitems + item] = SD;
   }
 }
 
@@ -231,12 +283,17 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
 // FP64; the 16 sums are then added by a fixed butterfly, so every order is fixed.
 constexpr int kReduceLanes = 16;
 
+// With E (the fused pass), each workgroup also writes the sum of e_i . F_i over
+// its 16 vertices into edot[block] (the P of the safeguard's bounds).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_sym_reduce(const float* __restrict__ Pi, const float* __restrict__ Pj,
-                                                    const int32_t* __restrict__ panel_items, int cond,
+                                                    const int32_t* __restrict__ panel_items, int gate,
                                                     const DevState* __restrict__ st, double* __restrict__ fpart,
+                                                    const float* __restrict__ Eb, double* __restrict__ edot,
                                                     int n_pad) {
-  if (st->done || (cond && !st->need_force)) return;
+  using V = typename VecT<DIM>::T;
+  __shared__ double dots[256 / kReduceLanes];
+  if (gate_closed(gate, st)) return;
   const int i = (blockIdx.x * 256 + threadIdx.x) / kReduceLanes;  // whole lane groups share i
   const int t = threadIdx.x % kReduceLanes;
   const bool live = i < n_pad;
@@ -265,41 +322,60 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const float* __restrict__ Pi
 #pragma unroll
     for (int c = 0; c < DIM; ++c) fpart[(size_t)c * n_pad + i] = acc[c];
   }
+  if (Eb) {
+    if (t == 0) {
+      double dot = 0.0;
+      if (live) {
+        const V e = reinterpret_cast<const V*>(Eb)[i];
+        dot = (double)e.x * acc[0] + (double)e.y * acc[1];
+        if constexpr (DIM == 3) dot += (double)e.z * acc[2];
+      }
+      dots[threadIdx.x / kReduceLanes] = dot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int g = 0; g < 256 / kReduceLanes; ++g) s += dots[g];
+      edot[blockIdx.x] = s;
+    }
+  }
 }
 
-template <int DIM, bool SG, bool FD>
-void sym_launch(const LoopParams* lp, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
+template <int DIM, int SG, bool FD>
+void sym_launch(const LoopParams* lp, int gate, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                 const float* Eb, const DevState* st, const int4* items, int nitems, const int32_t* panel_items,
-                float* Pi, float* Pj, double* sgpart, double* fpart, int n_pad, hipStream_t s) {
+                float* Pi, float* Pj, double* sgpart, double* fpart, double* edot, int n_pad, hipStream_t s) {
   const int nb = n_pad / 64, ng = n_pad / kColGroup;
   k_force_sym<DIM, SG, FD><<<(nitems + kWaves - 1) / kWaves, kWaves * 64, 0, s>>>(
       d, df, Xb, stride, Eb, lp ? lp->omega_sched : nullptr, lp ? lp->omega_p : 0.0, lp && lp->omega_vertex ? 1 : 0,
-      cond, st, items, nitems, Pi, Pj, sgpart, nb, ng, n_pad);
-  k_sym_reduce<DIM><<<(unsigned)(((size_t)n_pad * kReduceLanes + 255) / 256), 256, 0, s>>>(Pi, Pj, panel_items, cond,
-                                                                                           st, fpart, n_pad);
+      gate, st, items, nitems, Pi, Pj, sgpart, nb, ng, n_pad);
+  k_sym_reduce<DIM><<<sym_reduce_blocks(n_pad), 256, 0, s>>>(Pi, Pj, panel_items, gate, st, fpart,
+                                                             SG != 0 ? Eb : nullptr, edot, n_pad);
 }
 
-template <bool SG>
-void sym_dispatch(int dim, const LoopParams* lp, int cond, const uint8_t* d, const float* df, const float* Xb,
+template <int SG>
+void sym_dispatch(int dim, const LoopParams* lp, int gate, const uint8_t* d, const float* df, const float* Xb,
                   size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
-                  const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart, int n_pad,
-                  hipStream_t s) {
+                  const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart, double* edot,
+                  int n_pad, hipStream_t s) {
   if (dim == 2) {
-    if (df) sym_launch<2, SG, true>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                    fpart, n_pad, s);
-    else sym_launch<2, SG, false>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                  fpart, n_pad, s);
+    if (df) sym_launch<2, SG, true>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                    fpart, edot, n_pad, s);
+    else sym_launch<2, SG, false>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                  fpart, edot, n_pad, s);
   } else {
-    if (df) sym_launch<3, SG, true>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                    fpart, n_pad, s);
-    else sym_launch<3, SG, false>(lp, cond, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                  fpart, n_pad, s);
+    if (df) sym_launch<3, SG, true>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                    fpart, edot, n_pad, s);
+    else sym_launch<3, SG, false>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
+                                  fpart, edot, n_pad, s);
   }
 }
 
 }  // namespace
 
 int sym_rows_per_item() { return kPanel * 64; }
+
+unsigned sym_reduce_blocks(int n_pad) { return (unsigned)(((size_t)n_pad * kReduceLanes + 255) / 256); }
 
 SymSplit make_sym_split(int n_pad) {
   SymSplit sp;
@@ -326,17 +402,21 @@ SymSplit make_sym_split(int n_pad) {
 hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                             const DevState* st, const int4* items, int nitems, const int32_t* panel_items, float* Pi,
                             float* Pj, double* fpart, int n_pad, hipStream_t s) {
-  sym_dispatch<false>(dim, nullptr, cond, d, df, Xb, stride, nullptr, st, items, nitems, panel_items, Pi, Pj, nullptr,
-                      fpart, n_pad, s);
+  sym_dispatch<0>(dim, nullptr, cond ? kGateForce : kGateNone, d, df, Xb, stride, nullptr, st, items, nitems,
+                  panel_items, Pi, Pj, nullptr, fpart, nullptr, n_pad, s);
   return hipGetLastError();
 }
 
-hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, const uint8_t* d, const float* df, const float* Xb,
-                               size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
-                               const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart,
-                               int n_pad, hipStream_t s) {
-  sym_dispatch<true>(dim, &lp, 0, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart, fpart, n_pad,
-                     s);
+hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, int exact, int gated, const uint8_t* d, const float* df,
+                               const float* Xb, size_t stride, const float* Eb, const DevState* st, const int4* items,
+                               int nitems, const int32_t* panel_items, float* Pi, float* Pj, double* sgpart,
+                               double* fpart, double* edot, int n_pad, hipStream_t s) {
+  if (exact)
+    sym_dispatch<2>(dim, &lp, gated ? kGateExact : kGateNone, d, df, Xb, stride, Eb, st, items, nitems, panel_items,
+                    Pi, Pj, sgpart, fpart, edot, n_pad, s);
+  else
+    sym_dispatch<1>(dim, &lp, gated ? kGateBounds : kGateNone, d, df, Xb, stride, Eb, st, items, nitems, panel_items,
+                    Pi, Pj, sgpart, fpart, edot, n_pad, s);
   return hipGetLastError();
 }
 

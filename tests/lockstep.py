@@ -10,6 +10,12 @@ GPU's arithmetic of that iteration from the drift of a free run:
   * the GPU's decision (trace column 1) equal to the oracle's outside that band.
 The enumerating strategy (Sec. 5.2) checks the kept candidate's difference and
 that no candidate beats it by more than the band.
+Where the unordered force pass reports bounds U >= f(X~) - f(X^H) >= L
+(trace columns 5 and 6) they are compared with the oracle's bounds within 1e-4
+or the band of their own term scale, and the decision they took (U <= 0 keeps
+X~, L > 0 keeps X^H; column 2 is then NaN) must match the oracle's exact one
+outside its band; where the exact difference was summed (after bounds that
+left the sign open), column 2 holds it, checked as above.
 """
 import numpy as np
 
@@ -41,8 +47,16 @@ def check_safeguard_lockstep(D, X0, info, omega_vertex=None, enumerate=False, or
         else:
             XT = XH + T[k, 3] * (XH - Xk)
         df, sc = oracle.stress_delta(D, XT, XH)
-        tol = max(1e-4 * abs(df), AMBIG * sc)
-        assert abs(T[k, 2] - df) <= tol, (k, T[k, 2], df, sc)
+        if T.shape[1] > 6 and np.isfinite(T[k, 5]):
+            u, lo, su, q = oracle.stress_delta_bounds(D, XT, XH)
+            btol = AMBIG * (su + q)
+            assert abs(T[k, 5] - u) <= max(1e-4 * abs(u), btol), (k, T[k, 5], u, su, q)
+            assert abs(T[k, 6] - lo) <= max(1e-4 * abs(lo), btol), (k, T[k, 6], lo, su, q)
+            if np.isnan(T[k, 2]):  # decided by a bound
+                assert (T[k, 5] <= 0.0) if T[k, 1] == 1.0 else (T[k, 6] > 0.0), (k, T[k])
+        if not np.isnan(T[k, 2]):
+            tol = max(1e-4 * abs(df), AMBIG * sc)
+            assert abs(T[k, 2] - df) <= tol, (k, T[k, 2], df, sc)
         if abs(df) > AMBIG * sc:
             assert T[k, 1] == (1.0 if df <= 0.0 else 0.0), (k, T[k, 1], df, sc)
         checked += 1

@@ -294,11 +294,22 @@ def test_ba65536_safeguard_lockstep(sl, dim, k):
     Xk = X0 if k == 0 else P[k - 1]
     XH = oracle.h_jacobi_graph(g.row_ptr, g.col_idx, Xk)
     XT = XH + (omega - 1.0) * (XH - Xk)
-    df, scale = oracle.stress_delta_graph(g.row_ptr, g.col_idx, XT, XH)
     tg = info["trace"][k]
+    if np.isfinite(tg[5]):  # the unordered pass reports the bounds U >= f(X~) - f(X^H) >= L
+        u, lo, su, q, df, scale = oracle.stress_delta_bounds_graph(g.row_ptr, g.col_idx, XT, XH)
+        print("bounds: U gpu %.10g oracle %.10g, L gpu %.10g oracle %.10g (scales %.4g, %.4g)"
+              % (tg[5], u, tg[6], lo, su, q), flush=True)
+        assert abs(tg[5] - u) <= max(1e-4 * abs(u), AMBIG * (su + q))
+        assert abs(tg[6] - lo) <= max(1e-4 * abs(lo), AMBIG * (su + q))
+        assert lo <= df <= u
+    else:
+        df, scale = oracle.stress_delta_graph(g.row_ptr, g.col_idx, XT, XH)
     print("f(X~) - f(X^H): gpu %.10g oracle %.10g scale %.4g; decision gpu %g" % (tg[2], df, scale, tg[1]),
           flush=True)
-    assert abs(tg[2] - df) <= max(1e-4 * abs(df), AMBIG * scale)
+    if np.isnan(tg[2]):  # decided by a bound
+        assert (tg[5] <= 0.0) if tg[1] == 1.0 else (tg[6] > 0.0)
+    else:
+        assert abs(tg[2] - df) <= max(1e-4 * abs(df), AMBIG * scale)
     take = df <= 0.0
     if abs(df) > AMBIG * scale:
         assert tg[1] == (1.0 if take else 0.0)

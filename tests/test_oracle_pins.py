@@ -565,3 +565,73 @@ def test_auto_roulette_frequencies_and_windows():
     assert not np.array_equal(oracle.auto_factors(4, 0, 64), f[:64])
     # consecutive draws are not correlated (lag-1 correlation of the factors)
     assert abs(np.corrcoef(f[:-1], f[1:])[0, 1]) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# bounds of the safeguard's sum from its pairs' first-order parts (what the
+# unordered force pass reports instead of the sum when they decide its sign)
+# ---------------------------------------------------------------------------
+def test_stress_delta_bounds_hand_values():
+    c = CASES["path3_bounds"]
+    D = dmat(inputs.to_csr(c["n"], c["edges"]))
+    XB = np.array(c["xb"]).reshape(3, 2)
+    for k in (1, 2):
+        XA = np.array(c["xa%d" % k]).reshape(3, 2)
+        u, lo, su, q = oracle.stress_delta_bounds(D, XA, XB)
+        assert u == pytest.approx(c["u%d" % k], abs=1e-14)
+        assert lo == pytest.approx(c["l%d" % k], abs=1e-14)
+        assert oracle.stress_delta(D, XA, XB)[0] == pytest.approx(c["delta%d" % k], abs=1e-14)
+        assert lo <= c["delta%d" % k] + 1e-15 <= u + 2e-15 and q >= 0.0 and su >= abs(u) - 1e-15
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_stress_delta_bounds_bracket_the_difference(seed):
+    """L <= f(XA) - f(XB) <= U for random placements and moves of every size,
+    and U - (f(XA) - f(XB)) = sum kappa delta^2 with delta = rA - rB taken
+    directly (an identity of the split -c m - kappa delta^2 of each term)."""
+    rng = np.random.default_rng(seed)
+    g = inputs.erdos_renyi(40, 90, 50 + seed)
+    D = dmat(g)
+    XB = rng.uniform(0, 5, (g.n, 2))
+    for scale in (1e-6, 1e-3, 0.1, 1.0, 10.0):
+        XA = XB + scale * rng.standard_normal(XB.shape)
+        df = oracle.stress_delta(D, XA, XB)[0]
+        u, lo, su, q = oracle.stress_delta_bounds(D, XA, XB)
+        # the difference of eq. 1 is summed from squares: FP64 rounding of f itself
+        tol = 1e-13 * (su + q + oracle.stress(D, XA) + oracle.stress(D, XB))
+        assert lo - tol <= df <= u + tol
+        kd = 0.0
+        for i in range(g.n):
+            for j in range(i + 1, g.n):
+                d = D[i, j]
+                if np.isfinite(d) and d > 0:
+                    ra, rb = np.linalg.norm(XA[i] - XA[j]), np.linalg.norm(XB[i] - XB[j])
+                    kd += (ra - rb) ** 2 / (d * ra)
+        assert u - df == pytest.approx(kd, rel=1e-9, abs=tol)
+
+
+def test_stress_delta_bounds_tighten_as_the_move_shrinks():
+    """U - f-difference and f-difference - L are second order in the move,
+    the difference itself first order: their ratio to it shrinks linearly."""
+    rng = np.random.default_rng(3)
+    g = inputs.grid_graph(5, 5)
+    D = dmat(g)
+    XB = rng.uniform(0, 4, (g.n, 2))
+    E = rng.standard_normal(XB.shape)
+    gaps = []
+    for h in (1e-2, 5e-3, 2.5e-3):
+        df = oracle.stress_delta(D, XB + h * E, XB)[0]
+        u, lo, _, _ = oracle.stress_delta_bounds(D, XB + h * E, XB)
+        gaps.append(((u - df) / abs(df), (df - lo) / abs(df)))
+    for a, b in zip(gaps, gaps[1:]):
+        assert b[0] == pytest.approx(a[0] / 2, rel=0.1) and b[1] == pytest.approx(a[1] / 2, rel=0.1)
+
+
+def test_stress_delta_bounds_graph_form_equals_matrix_form():
+    g = inputs.random_tree(60, 4)
+    rng = np.random.default_rng(8)
+    XB = rng.uniform(0, 3, (g.n, 3))
+    XA = XB + 0.05 * rng.standard_normal(XB.shape)
+    a = oracle.stress_delta_bounds(dmat(g), XA, XB)
+    b = oracle.stress_delta_bounds_graph(g.row_ptr, g.col_idx, XA, XB)
+    assert a == b[:4] and oracle.stress_delta(dmat(g), XA, XB) == b[4:]
