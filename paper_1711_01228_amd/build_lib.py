@@ -82,7 +82,8 @@ def _compile(lib: str, sources: list, verbose: bool) -> None:
             for f in [ex.submit(_run, cmd, verbose) for cmd in jobs]:
                 f.result()
         tmp = lib + ".tmp" + tag
-        _run([hipcc(), "--offload-arch=" + ARCH, "-fPIC", "-shared", "-o", tmp] + objs, verbose)
+        # every symbol resolved at link time: a missing definition fails the build, not the first load
+        _run([hipcc(), "--offload-arch=" + ARCH, "-fPIC", "-shared", "-Wl,--no-undefined", "-o", tmp] + objs, verbose)
         os.replace(tmp, lib)
     finally:
         for obj in objs:

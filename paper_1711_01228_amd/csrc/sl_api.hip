@@ -326,37 +326,43 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
   if (n > 1 && g->nnz > 0) {
     if (g->nnz > (int64_t)INT32_MAX) return fail(SL_ERANGE, "more than 2^31 - 1 CSR entries");
     // source row of every CSR entry; the gather's runs (whole rows of at most
-    // bfs_run_entries() entries packed together, longer rows in chunks) and the
-    // rows no run owns (the longer ones and isolated vertices)
-    std::vector<int32_t> erow((size_t)g->nnz), rows;
+    // bfs_run_entries() entries packed together) and the rows that take a wave
+    // each (longer ones and isolated vertices)
+    std::vector<int32_t> erow((size_t)g->nnz);
     std::vector<int2> runs;
+    std::vector<int4> longrows;
     const int run_max = bfs_run_entries();
     int2 open_run = make_int2(0, 0);
     for (int v = 0; v < n; ++v) {
       const int64_t b0 = g->row_ptr[v], deg = g->row_ptr[v + 1] - b0;
       for (int64_t e = b0; e < b0 + deg; ++e) erow[(size_t)e] = v;
-      if (deg == 0) {
-        rows.push_back(v);
-      } else if (deg <= run_max) {
+      if (deg == 0 || deg > run_max) {
+        longrows.push_back(make_int4(v, (int)b0, (int)deg, 0));
+        if (deg > 0 && open_run.y > 0) {  // a run holds consecutive CSR entries: close it before this row's
+          runs.push_back(open_run);
+          open_run.y = 0;
+        }
+      } else {
         if (open_run.y > 0 && open_run.y + deg > run_max) {
           runs.push_back(open_run);
           open_run.y = 0;
         }
         if (open_run.y == 0) open_run.x = (int)b0;
         open_run.y += (int)deg;
-      } else {
-        if (open_run.y > 0) runs.push_back(open_run);
-        open_run.y = 0;
-        for (int64_t c = 0; c < deg; c += run_max)
-          runs.push_back(make_int2((int)(b0 + c), (int)std::min<int64_t>(run_max, deg - c) | bfs_run_chunk_flag()));
-        rows.push_back(v);
       }
     }
     if (open_run.y > 0) runs.push_back(open_run);
-    int32_t *er = nullptr, *ci = nullptr, *rl = nullptr;
+    // the rows above the middle degree first (a workgroup each), then the others (a wave each)
+    const int mid_max = bfs_mid_max_degree();
+    std::stable_partition(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
+    const int nbig = (int)std::count_if(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
+    const int nmid = (int)longrows.size() - nbig;
+    int32_t *er = nullptr, *ci = nullptr;
     int2* rn = nullptr;
-    uint64_t *slots = nullptr, *vis = nullptr, *acc = nullptr;
+    int4* lrows = nullptr;
+    uint64_t *slots = nullptr, *vis = nullptr;
     int32_t* flag = nullptr;
+    double* wq = nullptr;
     int32_t* hflag = nullptr;
     sl_status status = SL_OK;
     auto cleanup = [&]() {
@@ -364,77 +370,108 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       (void)hipFree(er);
       (void)hipFree(ci);
       (void)hipFree(rn);
-      (void)hipFree(rl);
+      (void)hipFree(lrows);
       (void)hipFree(slots);
       (void)hipFree(vis);
-      (void)hipFree(acc);
       (void)hipFree(flag);
+      (void)hipFree(wq);
       if (hflag) (void)hipHostFree(hflag);
     };
     hipError_t e = hipSuccess;
     const size_t words = (size_t)n * bfs_words();
     const int nslots = bfs_slots();
+    const int sweep = bfs_sources_per_sweep();
+    const int nsweeps = (n + sweep - 1) / sweep;
+    constexpr int kStride = kBfsMaxLevel + 1;  // one flag row per sweep: flags[l], l = 0 .. 256
     if (e == hipSuccess) e = hipMalloc(&er, sizeof(int32_t) * g->nnz);
     if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * g->nnz);
     if (e == hipSuccess) e = hipMalloc(&slots, sizeof(uint64_t) * words * nslots);
     if (e == hipSuccess) e = hipMalloc(&vis, sizeof(uint64_t) * words);
-    if (e == hipSuccess) e = hipMalloc(&acc, sizeof(uint64_t) * words);
-    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t) * (kBfsMaxLevel + 1));
-    if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t) * (nslots + 1), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t) * kStride * nsweeps);
+    if (e == hipSuccess) e = hipMalloc(&wq, sizeof(double) * (size_t)bfs_weight_partials() * p->n_pad);
+    if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t) * kStride * nsweeps, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemcpyAsync(er, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMalloc(&rn, sizeof(int2) * std::max<size_t>(1, runs.size()));
-    if (e == hipSuccess) e = hipMalloc(&rl, sizeof(int32_t) * std::max<size_t>(1, rows.size()));
+    if (e == hipSuccess) e = hipMalloc(&lrows, sizeof(int4) * std::max<size_t>(1, longrows.size()));
     if (e == hipSuccess && !runs.empty())
       e = hipMemcpyAsync(rn, runs.data(), sizeof(int2) * runs.size(), hipMemcpyHostToDevice, p->ps);
-    if (e == hipSuccess && !rows.empty())
-      e = hipMemcpyAsync(rl, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess && !longrows.empty())
+      e = hipMemcpyAsync(lrows, longrows.data(), sizeof(int4) * longrows.size(), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess) e = hipMemsetAsync(wq, 0, sizeof(double) * (size_t)bfs_weight_partials() * p->n_pad, p->ps);
+    if (e == hipSuccess) e = launch_bfs_flags(flag, nsweeps, kStride, p->ps);
     if (e != hipSuccess) {
       cleanup();
       return hip_fail(e, "distance buffers");
     }
     // Every byte of d is written by the first batch of levels of some sweep
     // (the sweeps' column ranges cover [0, n_pad), and every row is stored).
-    const int sweep = bfs_sources_per_sweep();
-    // The first batch of a sweep queues the previous sweep's depth + 3 levels
-    // (all the slots for the first sweep): a level after the search ended still
-    // costs two launches, a search deeper than the batch one more batch.
-    int depth = nslots;
-    for (int base = 0; base < n && status == SL_OK && e == hipSuccess; base += sweep) {
-      e = launch_bfs_init(slots, vis, acc, n, base, p->ps);
-      // flags[l] = 0 for every level, flags[0] != 0 (the sources)
-      if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int32_t) * (kBfsMaxLevel + 1), p->ps);
-      if (e == hipSuccess) e = hipMemsetAsync(flag, 1, sizeof(int32_t), p->ps);
-      for (int l0 = 1, l1 = 0; e == hipSuccess; l0 = l1 + 1) {
-        // one batch of at most as many levels as there are slots, then their distances
-        l1 = std::min(l0 + (l0 == 1 ? std::min(depth + 3, nslots) : nslots) - 1, kBfsMaxLevel);
-        for (int level = l0; level <= l1 && e == hipSuccess; ++level)
-          e = launch_bfs_level(rn, (int)runs.size(), er, ci, rl, (int)rows.size(), slots, acc, vis, n, level, flag,
-                               p->ps);
-        // level 256 is not stored: it only tells whether a distance exceeds 255
-        if (e == hipSuccess)
-          e = launch_bfs_store(slots, flag, p->d, n, p->n_pad, base, l0, std::min(l1, kBfsMaxLevel - 1), p->ps);
-        if (e == hipSuccess)
-          e = hipMemcpyAsync(hflag, flag + l0, sizeof(int32_t) * (l1 - l0 + 1), hipMemcpyDeviceToHost, p->ps);
-        if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
-        if (e != hipSuccess) break;
-        if (hflag[l1 - l0] == 0) {  // the search ended in this batch: its depth
-          depth = l0 - 1;
-          for (int l = l0; l <= l1 && hflag[l - l0]; ++l) depth = l;
+    // Levels l0 .. l1 of sweep sw (one batch, at most nslots levels), then their distances.
+    auto queue_levels = [&](int sw, int l0, int l1, int count_from) -> hipError_t {
+      int32_t* fl = flag + (size_t)sw * kStride;
+      hipError_t le = hipSuccess;
+      for (int level = l0; level <= l1 && le == hipSuccess; ++level)
+        le = launch_bfs_level(rn, (int)runs.size(), lrows, nbig, nmid, er, ci, slots, vis, n, sw * sweep, level, fl,
+                              p->ps);
+      // level 256 is not stored: it only tells whether a distance exceeds 255
+      if (le == hipSuccess)
+        le = launch_bfs_store(slots, fl, p->d, wq, n, p->n_pad, sw * sweep, l0, std::min(l1, kBfsMaxLevel - 1),
+                              count_from, p->ps);
+      return le;
+    };
+    // A sweep run batch by batch, the host reading the batch's flags after each
+    // one, until its search ends (its depth) or passes 255 hops.  Levels below
+    // count_from are not counted again (a sweep redone after a shorter run).
+    auto sweep_synced = [&](int sw, int first_batch, int count_from, int* depth) -> hipError_t {
+      int32_t* fl = flag + (size_t)sw * kStride;
+      hipError_t le = launch_bfs_init(vis, n, sw * sweep, p->ps);
+      if (le == hipSuccess) le = launch_bfs_flags(fl, 1, kStride, p->ps);
+      for (int l0 = 1, l1 = 0; le == hipSuccess; l0 = l1 + 1) {
+        l1 = std::min(l0 + (l0 == 1 ? first_batch : nslots) - 1, kBfsMaxLevel);
+        le = queue_levels(sw, l0, l1, count_from);
+        if (le == hipSuccess)
+          le = hipMemcpyAsync(hflag, fl + l0, sizeof(int32_t) * (l1 - l0 + 1), hipMemcpyDeviceToHost, p->ps);
+        if (le == hipSuccess) le = hipStreamSynchronize(p->ps);
+        if (le != hipSuccess) break;
+        if (hflag[l1 - l0] == 0) {  // the search ended in this batch
+          *depth = l0 - 1;
+          for (int l = l0; l <= l1 && hflag[l - l0]; ++l) *depth = l;
           break;
         }
         if (l1 == kBfsMaxLevel) {
-          status = fail(SL_ERANGE, "a graph distance exceeds 255 hops (sources %d..%d)", base, base + sweep - 1);
+          status = fail(SL_ERANGE, "a graph distance exceeds 255 hops (sources %d..%d)", sw * sweep,
+                        sw * sweep + sweep - 1);
           break;
         }
       }
+      return le;
+    };
+    // The first sweep learns the search depth D.  The others are queued back
+    // to back with D + 2 levels each and no host wait; a sweep whose level
+    // D + 2 still found something is redone batch by batch afterwards.
+    int depth = 0;
+    e = sweep_synced(0, nslots, 1, &depth);
+    const int L = std::min(depth + 2, kBfsMaxLevel);
+    for (int sw = 1; sw < nsweeps && e == hipSuccess && status == SL_OK; ++sw) {
+      e = launch_bfs_init(vis, n, sw * sweep, p->ps);
+      for (int l0 = 1; l0 <= L && e == hipSuccess; l0 += nslots) e = queue_levels(sw, l0, std::min(l0 + nslots - 1, L), 1);
     }
+    if (e == hipSuccess && status == SL_OK && nsweeps > 1) {
+      e = hipMemcpyAsync(hflag, flag, sizeof(int32_t) * kStride * nsweeps, hipMemcpyDeviceToHost, p->ps);
+      if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
+      for (int sw = 1; sw < nsweeps && e == hipSuccess && status == SL_OK; ++sw) {
+        if (!hflag[(size_t)sw * kStride + L]) continue;
+        // levels 1 .. L of this sweep are in d and the weights; find the rest
+        int dsw = 0;
+        e = sweep_synced(sw, nslots, L + 1, &dsw);
+      }
+    }
+    if (e == hipSuccess && status == SL_OK) e = launch_weights_from_partials(wq, p->W, n, p->n_pad, p->ps);
     cleanup();
     if (e != hipSuccess) return hip_fail(e, "breadth-first search");
-    if (status != SL_OK) return status;
-  } else {
-    HIP_TRY(hipMemsetAsync(p->d, 0, (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
+    return status;
   }
+  HIP_TRY(hipMemsetAsync(p->d, 0, (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync(d)");
   HIP_TRY(launch_weights(p->d, nullptr, p->W, p->fpart, p->sp, n, p->ps), "weights kernel");
   return SL_OK;
 }

@@ -10,12 +10,13 @@
 //   k_bfs_gather  one lane group of 16 lanes per run of at most 16 CSR
 //                 entries (built with the plan), each lane reading 16 bytes
 //                 of a neighbour's 256-byte frontier row per entry, all 16
-//                 loads in flight.  A run holds whole rows of degree <= 16:
-//                 the group owns them and writes N_l, visited and the slot
-//                 itself.  A run that is a 16-entry chunk of a longer row
-//                 folds its OR into acc by 64-bit atomic ORs.
-//   k_bfs_finish  the rows no run owns (longer rows and isolated vertices):
-//                 N_l from acc, acc = 0.
+//                 loads in flight (level 1 forms the sources' bits instead).
+//                 A run holds whole rows of degree <= 16: the group owns them
+//                 and writes N_l, visited and the slot itself.  A row of 17 to
+//                 64 entries (or an isolated vertex) takes a wave of its own,
+//                 whose four groups share its entries and combine their ORs by
+//                 shuffles; a longer row a 1024-thread workgroup, whose waves
+//                 combine theirs through LDS.
 // Every kBfsSlots levels, k_bfs_store turns the slots of that batch of levels
 // into distance bytes: it transposes a 64-row by 8-word block through LDS into
 // four bit planes of the level offset and one plane of "found", and writes
@@ -27,6 +28,8 @@
 // batch of levels and reads one flag per batch.
 #include "sl_device.h"
 #include "sl_internal.h"
+
+#include <algorithm>
 
 namespace sl {
 
@@ -43,16 +46,14 @@ constexpr int kStoreWords = 8;                // words per row in one store bloc
 
 inline unsigned blocks_for(size_t items) { return (unsigned)((items + 255) / 256); }
 
-__global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ slot0, uint64_t* __restrict__ visited,
-                                                  uint64_t* __restrict__ acc, size_t words, int base) {
+// visited = the sources themselves (level 0; the level-1 gather forms their
+// frontier bits directly, so no slot holds level 0).
+__global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ visited, size_t words, int base) {
   const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= words) return;
   const int v = (int)(q / kBfsWords), k = (int)(q % kBfsWords);
   const int s0 = base + 64 * k;
-  const uint64_t w = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
-  slot0[q] = w;
-  visited[q] = w;
-  acc[q] = 0ull;
+  visited[q] = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
 }
 
 // N_l for the two words (one 16-byte chunk q) a lane holds of a row.
@@ -71,73 +72,140 @@ __device__ __forceinline__ void bfs_settle(ulonglong2* __restrict__ visited, ulo
   slot[q] = nw;
 }
 
-// Run descriptor: x = first CSR entry, y = entry count (1..16) | kRunChunk
-// when the run is a chunk of a row longer than 16 entries.
-constexpr int kRunChunk = 1 << 16;
+// Frontier chunk (lane wl's 16 bytes) of neighbour u; at level 1 the frontier
+// is the sources themselves: u's own bit, in the chunk of lane (u - base) / 128.
+__device__ __forceinline__ ulonglong2 frontier_chunk(const ulonglong2* __restrict__ F, int u, int wl, int level,
+                                                     int base) {
+  if (u < 0) return make_ulonglong2(0ull, 0ull);
+  if (level == 1) {
+    const int sb = u - base;
+    if (sb < 0 || sb >= kBfsSources || sb / 128 != wl) return make_ulonglong2(0ull, 0ull);
+    const uint64_t bit = 1ull << (sb & 63);
+    return (sb & 64) ? make_ulonglong2(0ull, bit) : make_ulonglong2(bit, 0ull);
+  }
+  return F[(size_t)u * (kBfsWords / 2) + wl];
+}
 
-__global__ __launch_bounds__(256) void k_bfs_gather(const int2* __restrict__ runs, int nruns,
-                                                    const int32_t* __restrict__ erow,
-                                                    const int32_t* __restrict__ col_idx,
-                                                    const uint64_t* __restrict__ frontier,
-                                                    unsigned long long* __restrict__ acc,
-                                                    ulonglong2* __restrict__ visited, ulonglong2* __restrict__ slot,
-                                                    int32_t* __restrict__ flags, int level) {
+constexpr int kGatherThreads = 1024;           // threads per gather workgroup (16 waves)
+constexpr int kGatherWaves = kGatherThreads / 64;
+constexpr int kMidMax = 64;                     // rows up to this degree take one wave
+
+// The OR of lane wl's chunk over entries e0 .. e0 + 63 of a row (CSR entries
+// from b), the wave's lane groups each taking 16 of them: lane l holds entry
+// e0 + l; the groups' ORs are then combined, so every group holds the total.
+__device__ __forceinline__ void row_chunk_or(const ulonglong2* __restrict__ F, const int32_t* __restrict__ col_idx,
+                                             int b, int deg, int e0, int lane, int grp, int wl, int level, int base,
+                                             uint64_t& a0, uint64_t& a1) {
+  const int uj = e0 + lane < deg ? col_idx[b + e0 + lane] : -1;
+  ulonglong2 f[kGatherRun];
+#pragma unroll
+  for (int j = 0; j < kGatherRun; ++j) f[j] = frontier_chunk(F, __shfl(uj, kGatherRun * grp + j, 64), wl, level, base);
+#pragma unroll
+  for (int j = 0; j < kGatherRun; ++j) {
+    a0 |= f[j].x;
+    a1 |= f[j].y;
+  }
+}
+
+// Three kinds of workgroup, by index:
+//   [0, nbig)                 one row of degree above kMidMax each: its 16 waves
+//                             share the entries, 1024 per pass, and combine
+//                             their ORs through LDS; wave 0's first group settles
+//   [nbig, nbig + mid blocks) one row of degree 17 .. kMidMax, or an isolated
+//                             vertex, per wave
+//   the rest                  the runs, one lane group per run
+__global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __restrict__ runs, int nruns,
+                                                               const int4* __restrict__ longrows, int nbig, int nmid,
+                                                               const int32_t* __restrict__ erow,
+                                                               const int32_t* __restrict__ col_idx,
+                                                               const uint64_t* __restrict__ frontier,
+                                                               ulonglong2* __restrict__ visited,
+                                                               ulonglong2* __restrict__ slot,
+                                                               int32_t* __restrict__ flags, int level, int base) {
+  __shared__ ulonglong2 wor[kGatherWaves][kGatherLanes];
   if (flags[level - 1] == 0) return;  // the search of this sweep has ended
-  const int lane = threadIdx.x & 63, grp = lane / kGatherLanes, wl = lane % kGatherLanes;
-  const int r = (int)(blockIdx.x * 4 + (threadIdx.x >> 6)) * kGatherGroups + grp;  // this group's run
-  const int2 rd = r < nruns ? runs[r] : make_int2(0, 0);
-  const int cnt = rd.y & (kRunChunk - 1);
-  const bool chunk = (rd.y & kRunChunk) != 0;
-  // lane wl of the group holds entry rd.x + wl
-  const int vj = wl < cnt ? erow[rd.x + wl] : -1;
-  const int uj = wl < cnt ? col_idx[rd.x + wl] : 0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / kGatherLanes, wl = lane % kGatherLanes;
   const ulonglong2* __restrict__ F = reinterpret_cast<const ulonglong2*>(frontier);
+  const int nmid_blocks = (nmid + kGatherWaves - 1) / kGatherWaves;
+  if ((int)blockIdx.x < nbig) {
+    const int4 lr = longrows[blockIdx.x];  // (vertex, first CSR entry, degree, 0)
+    uint64_t a0 = 0ull, a1 = 0ull;
+    for (int e0 = wave * 64; e0 < lr.z; e0 += kGatherThreads)
+      row_chunk_or(F, col_idx, lr.y, lr.z, e0, lane, grp, wl, level, base, a0, a1);
+    a0 |= __shfl_xor(a0, 16, 64);
+    a1 |= __shfl_xor(a1, 16, 64);
+    a0 |= __shfl_xor(a0, 32, 64);
+    a1 |= __shfl_xor(a1, 32, 64);
+    if (grp == 0) wor[wave][wl] = make_ulonglong2(a0, a1);
+    __syncthreads();
+    if (wave == 0 && grp == 0) {
+#pragma unroll
+      for (int w = 1; w < kGatherWaves; ++w) {
+        a0 |= wor[w][wl].x;
+        a1 |= wor[w][wl].y;
+      }
+      bfs_settle(visited, slot, (size_t)lr.x * (kBfsWords / 2) + wl, a0, a1, flags, level);
+    }
+    return;
+  }
+  if ((int)blockIdx.x < nbig + nmid_blocks) {
+    const int k = ((int)blockIdx.x - nbig) * kGatherWaves + wave;
+    if (k >= nmid) return;
+    const int4 lr = longrows[nbig + k];
+    uint64_t a0 = 0ull, a1 = 0ull;
+    if (lr.z > 0) row_chunk_or(F, col_idx, lr.y, lr.z, 0, lane, grp, wl, level, base, a0, a1);
+    a0 |= __shfl_xor(a0, 16, 64);
+    a1 |= __shfl_xor(a1, 16, 64);
+    a0 |= __shfl_xor(a0, 32, 64);
+    a1 |= __shfl_xor(a1, 32, 64);
+    if (grp == 0) bfs_settle(visited, slot, (size_t)lr.x * (kBfsWords / 2) + wl, a0, a1, flags, level);
+    return;
+  }
+  const int r = (((int)blockIdx.x - nbig - nmid_blocks) * kGatherWaves + wave) * kGatherGroups + grp;
+  const int2 rd = r < nruns ? runs[r] : make_int2(0, 0);  // (first CSR entry, entry count)
+  // lane wl of the group holds entry rd.x + wl
+  const int vj = wl < rd.y ? erow[rd.x + wl] : -1;
+  const int uj = wl < rd.y ? col_idx[rd.x + wl] : 0;
   ulonglong2 f[kGatherRun];
   int vv[kGatherRun];
 #pragma unroll
   for (int j = 0; j < kGatherRun; ++j) {
     vv[j] = __shfl(vj, kGatherRun * grp + j, 64);
     const int u = __shfl(uj, kGatherRun * grp + j, 64);
-    f[j] = vv[j] >= 0 ? F[(size_t)u * (kBfsWords / 2) + wl] : make_ulonglong2(0ull, 0ull);
+    f[j] = frontier_chunk(F, vv[j] >= 0 ? u : -1, wl, level, base);
   }
   int cur = -1;
   uint64_t a0 = 0ull, a1 = 0ull;
-  auto flush = [&]() {
-    const size_t q = (size_t)cur * (kBfsWords / 2) + wl;
-    if (chunk) {  // part of a longer row: k_bfs_finish settles it
-      unsigned long long* dst = acc + 2 * q;
-      if (a0) atomicOr(dst, (unsigned long long)a0);
-      if (a1) atomicOr(dst + 1, (unsigned long long)a1);
-    } else {  // the whole row is in this run
-      bfs_settle(visited, slot, q, a0, a1, flags, level);
-    }
-  };
 #pragma unroll
   for (int j = 0; j < kGatherRun; ++j) {
     const int v = vv[j];
     if (v != cur) {
-      if (cur >= 0) flush();
+      if (cur >= 0) bfs_settle(visited, slot, (size_t)cur * (kBfsWords / 2) + wl, a0, a1, flags, level);
       cur = v;
       a0 = a1 = 0ull;
     }
     a0 |= f[j].x;
     a1 |= f[j].y;
   }
-  if (cur >= 0) flush();
+  if (cur >= 0) bfs_settle(visited, slot, (size_t)cur * (kBfsWords / 2) + wl, a0, a1, flags, level);
 }
 
-// Rows no run owns: 16 threads (two words each) per listed row.
-__global__ __launch_bounds__(256) void k_bfs_finish(const int32_t* __restrict__ rows, int nrows,
-                                                    ulonglong2* __restrict__ acc, ulonglong2* __restrict__ visited,
-                                                    ulonglong2* __restrict__ slot, int32_t* __restrict__ flags,
-                                                    int level) {
-  if (flags[level - 1] == 0) return;
-  const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (size_t)nrows * (kBfsWords / 2)) return;
-  const size_t q = (size_t)rows[t / (kBfsWords / 2)] * (kBfsWords / 2) + t % (kBfsWords / 2);
-  const ulonglong2 a = acc[q];
-  if (a.x | a.y) acc[q] = make_ulonglong2(0ull, 0ull);
-  bfs_settle(visited, slot, q, a.x, a.y, flags, level);
+// W_v = the sum of the store kernels' partials wq[kq][v] over the four word
+// blocks kq, in order.
+__global__ __launch_bounds__(256) void k_weights_from_partials(const double* __restrict__ wq, double* __restrict__ W,
+                                                               int n, int n_pad) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n_pad) return;
+  double s = 0.0;
+  if (v < n)
+    for (int kq = 0; kq < kBfsWords / kStoreWords; ++kq) s += wq[(size_t)kq * n_pad + v];
+  W[v] = s;
+}
+
+// Flag rows of `sweeps` sweeps: flags[s][0] = 1 (the sources), the rest 0.
+__global__ __launch_bounds__(256) void k_bfs_flags(int32_t* __restrict__ flags, int sweeps, int stride) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < (size_t)sweeps * stride) flags[q] = (q % stride) == 0 ? 1 : 0;
 }
 
 // Bit b of the nibble to bit 0 of byte b.
@@ -145,9 +213,14 @@ __device__ __forceinline__ uint32_t spread4(uint32_t nib) { return ((nib & 0xfu)
 
 // Levels l0..l1 (one batch, l1 - l0 < 16) into d.  Workgroup: row block rb,
 // words 8 kq .. 8 kq + 7 of the sweep.
+// Also the pairs' weights: each row's sum of d^-2 over the found pairs of its
+// 8 words (the sources at level l count popcount / l^2, levels from
+// count_from on) is added into wq[kq][v], one partial per word block, by one
+// thread in a fixed order, so W = sum over kq of wq is the same on every run.
 __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ slots, size_t slot_words,
                                                    const int32_t* __restrict__ flags, uint8_t* __restrict__ d,
-                                                   int n, int ng, int base, int l0, int l1) {
+                                                   double* __restrict__ wq, int n, int n_pad, int ng, int base,
+                                                   int l0, int l1, int count_from) {
   if (l0 > 1 && flags[l0] == 0) return;  // nothing found in this batch; the first batch writes every byte
   __shared__ uint64_t planes[5][kRowBlock][kStoreWords + 1];
   const int rb = blockIdx.x / (kBfsWords / kStoreWords), kq = blockIdx.x % (kBfsWords / kStoreWords);
@@ -160,6 +233,7 @@ __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ 
     const int v = rb * kRowBlock + row;
     const size_t q = (size_t)v * kBfsWords + kq * kStoreWords + kk;
     uint64_t P0 = 0, P1 = 0, P2 = 0, P3 = 0, Fd = 0;
+    double ws = 0.0;
     for (int l = l0; l <= l1; ++l) {
       if (flags[l] == 0) break;  // levels after an empty one found nothing
       const uint64_t nw = v < n ? slots[(size_t)(l % kBfsSlots) * slot_words + q] : 0ull;
@@ -169,7 +243,13 @@ __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ 
       if (off & 2) P1 |= nw;
       if (off & 4) P2 |= nw;
       if (off & 8) P3 |= nw;
+      if (l >= count_from) ws += (double)__popcll(nw) / ((double)l * (double)l);
     }
+    // the row's 8 threads are consecutive lanes: add their sums in a fixed tree
+    ws += __shfl_xor(ws, 4, kStoreWords);
+    ws += __shfl_xor(ws, 2, kStoreWords);
+    ws += __shfl_xor(ws, 1, kStoreWords);
+    if (kk == 0 && v < n && ws != 0.0) wq[(size_t)kq * n_pad + v] += ws;
     planes[0][row][kk] = P0;
     planes[1][row][kk] = P1;
     planes[2][row][kk] = P2;
@@ -259,44 +339,52 @@ int bfs_sources_per_sweep() { return kBfsSources; }
 int bfs_words() { return kBfsWords; }
 int bfs_slots() { return kBfsSlots; }
 
-hipError_t launch_bfs_init(uint64_t* slot0, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s) {
+hipError_t launch_bfs_init(uint64_t* visited, int n, int base, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t words = (size_t)n * kBfsWords;
-  k_bfs_init<<<blocks_for(words), 256, 0, s>>>(slot0, visited, acc, words, base);
+  k_bfs_init<<<blocks_for(words), 256, 0, s>>>(visited, words, base);
   return hipGetLastError();
 }
 
 int bfs_run_entries() { return kGatherRun; }
-int bfs_run_chunk_flag() { return kRunChunk; }
 
-hipError_t launch_bfs_level(const int2* runs, int nruns, const int32_t* erow, const int32_t* col_idx,
-                            const int32_t* rows, int nrows, const uint64_t* slots, uint64_t* acc, uint64_t* visited,
-                            int n, int level, int32_t* flags, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const size_t words = (size_t)n * kBfsWords;
-  const uint64_t* frontier = slots + (size_t)((level - 1) % kBfsSlots) * words;
-  uint64_t* out = const_cast<uint64_t*>(slots) + (size_t)(level % kBfsSlots) * words;
-  if (nruns > 0) {
-    const unsigned blocks = (unsigned)((nruns + 4 * kGatherGroups - 1) / (4 * kGatherGroups));
-    k_bfs_gather<<<blocks, 256, 0, s>>>(runs, nruns, erow, col_idx, frontier,
-                                        reinterpret_cast<unsigned long long*>(acc),
-                                        reinterpret_cast<ulonglong2*>(visited), reinterpret_cast<ulonglong2*>(out),
-                                        flags, level);
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || nrows <= 0) return e;
-  k_bfs_finish<<<blocks_for((size_t)nrows * (kBfsWords / 2)), 256, 0, s>>>(
-      rows, nrows, reinterpret_cast<ulonglong2*>(acc), reinterpret_cast<ulonglong2*>(visited),
-      reinterpret_cast<ulonglong2*>(out), flags, level);
+hipError_t launch_bfs_flags(int32_t* flags, int sweeps, int stride, hipStream_t s) {
+  const size_t q = (size_t)sweeps * stride;
+  if (q == 0) return hipSuccess;
+  k_bfs_flags<<<blocks_for(q), 256, 0, s>>>(flags, sweeps, stride);
   return hipGetLastError();
 }
 
-hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, int n, int n_pad, int base,
-                            int l0, int l1, hipStream_t s) {
+hipError_t launch_weights_from_partials(const double* wq, double* W, int n, int n_pad, hipStream_t s) {
+  k_weights_from_partials<<<blocks_for(n_pad), 256, 0, s>>>(wq, W, n, n_pad);
+  return hipGetLastError();
+}
+
+int bfs_weight_partials() { return kBfsWords / kStoreWords; }
+
+int bfs_mid_max_degree() { return kMidMax; }
+
+hipError_t launch_bfs_level(const int2* runs, int nruns, const int4* longrows, int nbig, int nmid, const int32_t* erow,
+                            const int32_t* col_idx, const uint64_t* slots, uint64_t* visited, int n, int base,
+                            int level, int32_t* flags, hipStream_t s) {
+  if (n <= 0 || nruns + nbig + nmid == 0) return hipSuccess;
+  const size_t words = (size_t)n * kBfsWords;
+  const uint64_t* frontier = slots + (size_t)((level - 1) % kBfsSlots) * words;
+  uint64_t* out = const_cast<uint64_t*>(slots) + (size_t)(level % kBfsSlots) * words;
+  const int per_block = kGatherWaves * kGatherGroups;
+  const unsigned blocks = (unsigned)(nbig + (nmid + kGatherWaves - 1) / kGatherWaves + (nruns + per_block - 1) / per_block);
+  k_bfs_gather<<<blocks, kGatherThreads, 0, s>>>(runs, nruns, longrows, nbig, nmid, erow, col_idx, frontier,
+                                                 reinterpret_cast<ulonglong2*>(visited),
+                                                 reinterpret_cast<ulonglong2*>(out), flags, level, base);
+  return hipGetLastError();
+}
+
+hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, double* wq, int n, int n_pad,
+                            int base, int l0, int l1, int count_from, hipStream_t s) {
   if (n <= 0 || l1 < l0) return hipSuccess;
   const int nrb = n_pad / kRowBlock;
-  k_bfs_store<<<(unsigned)nrb * (kBfsWords / kStoreWords), 256, 0, s>>>(slots, (size_t)n * kBfsWords, flags, d, n,
-                                                                        n_pad / kColGroup, base, l0, l1);
+  k_bfs_store<<<(unsigned)nrb * (kBfsWords / kStoreWords), 256, 0, s>>>(
+      slots, (size_t)n * kBfsWords, flags, d, wq, n, n_pad, n_pad / kColGroup, base, l0, l1, count_from);
   return hipGetLastError();
 }
 

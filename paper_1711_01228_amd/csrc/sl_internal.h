@@ -169,26 +169,35 @@ int bfs_sources_per_sweep();  // sources searched together (bits per vertex)
 int bfs_words();              // 64-bit words per vertex in the BFS buffers
 int bfs_slots();              // level bitmaps kept (levels per batch)
 // slots: bfs_slots() buffers of n * bfs_words() words; slot l % bfs_slots()
-// holds the sources that first reach each vertex at level l (slot 0: level 0).
-hipError_t launch_bfs_init(uint64_t* slot0, uint64_t* visited, uint64_t* acc, int n, int base, hipStream_t s);
-// Runs of the gather: int2 (first CSR entry, count | bfs_run_chunk_flag()),
-// count 1 .. bfs_run_entries().  Whole rows of at most that many entries are
-// packed into runs (a run never splits them); a longer row is cut into
-// chunk runs and listed, with every isolated vertex, in the rows given to
-// launch_bfs_level: every vertex is owned by one run or listed, not both.
+// holds the sources that first reach each vertex at level l >= 1.
+// visited := the sweep's sources (from base).
+hipError_t launch_bfs_init(uint64_t* visited, int n, int base, hipStream_t s);
+// Runs of the gather: int2 (first CSR entry, count), count 1 .. bfs_run_entries():
+// whole rows of at most that many entries packed together (a run never splits
+// one).  Every other row is listed in longrows as int4 (vertex, first CSR
+// entry, degree, 0): first the nbig rows of degree above bfs_mid_max_degree()
+// (a workgroup each), then the nmid others (degree up to that, or 0: a wave each).
 int bfs_run_entries();
-int bfs_run_chunk_flag();
-// One BFS level (1 .. 256).  flags[0 .. 256]: flags[l] != 0 iff level l found a
-// new vertex (flags[0]: the sources); a level after an empty one does nothing.
-// acc (n * bfs_words() words) is zero between levels.
-hipError_t launch_bfs_level(const int2* runs, int nruns, const int32_t* erow, const int32_t* col_idx,
-                            const int32_t* rows, int nrows, const uint64_t* slots, uint64_t* acc, uint64_t* visited,
-                            int n, int level, int32_t* flags, hipStream_t s);
+int bfs_mid_max_degree();
+// One BFS level (1 .. 256) of the sweep from sources base ...  flags[0 .. 256]:
+// flags[l] != 0 iff level l found a new vertex (flags[0]: the sources); a level
+// after an empty one does nothing.
+hipError_t launch_bfs_level(const int2* runs, int nruns, const int4* longrows, int nbig, int nmid, const int32_t* erow,
+                            const int32_t* col_idx, const uint64_t* slots, uint64_t* visited, int n, int base,
+                            int level, int32_t* flags, hipStream_t s);
+// `sweeps` flag rows of `stride` ints: [s][0] = 1, the rest 0.
+hipError_t launch_bfs_flags(int32_t* flags, int sweeps, int stride, hipStream_t s);
+// Weight partials of the stores: bfs_weight_partials() x n_pad doubles, zero
+// before the first sweep; W_v = their sum in order (0 past n).
+int bfs_weight_partials();
+hipError_t launch_weights_from_partials(const double* wq, double* W, int n, int n_pad, hipStream_t s);
 // Levels l0 .. l1 (l1 - l0 < bfs_slots(), l1 <= 255) of the sweep from sources
 // base .. base + bfs_sources_per_sweep() - 1 into d; the batch starting at
 // level 1 writes every byte of the sweep's columns (below n_pad) in all rows.
-hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, int n, int n_pad, int base,
-                            int l0, int l1, hipStream_t s);
+// The weights d^-2 of the pairs found at levels >= count_from are added into
+// the partials wq.
+hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, double* wq, int n, int n_pad,
+                            int base, int l0, int l1, int count_from, hipStream_t s);
 // W from d (or df); wpart: scratch of sp.slices * n_pad doubles.
 hipError_t launch_weights(const uint8_t* d, const float* df, double* W, double* wpart, const Split& sp, int n,
                           hipStream_t s);

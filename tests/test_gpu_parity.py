@@ -90,6 +90,29 @@ def test_distances_and_weights(sl, name):
         np.testing.assert_allclose(plan.weights(), oracle.weight_sums(D), rtol=1e-12, atol=0)
 
 
+def multi_sweep_graphs():
+    """Graphs searched in several sweeps of 2,048 sources."""
+    # a star of 2,048 vertices with two paths of 100 hung on its centre: the
+    # first sweep (the star) is 101 levels deep, the second (the paths) 200, so
+    # the second outlasts the levels queued from the first sweep's depth
+    edges = [(0, k) for k in range(1, 2048)] + [(0, 2048), (0, 2148)]
+    edges += [(k, k + 1) for k in range(2048, 2147)] + [(k, k + 1) for k in range(2148, 2247)]
+    return {
+        "two_tails_2248": inputs.to_csr(2248, edges),
+        "er5000_components": inputs.erdos_renyi(5000, 4000, 9),  # isolated vertices and many components
+    }
+
+
+@pytest.mark.parametrize("name", sorted(multi_sweep_graphs()))
+def test_distances_and_weights_several_sweeps(sl, name):
+    g = multi_sweep_graphs()[name]
+    print("case", name, g.n, flush=True)
+    D = oracle_D(g)
+    with sl.Plan(g, 2) as plan:
+        np.testing.assert_array_equal(plan.distance_rows(np.arange(g.n)), as_u8(D))
+        np.testing.assert_allclose(plan.weights(), oracle.weight_sums(D), rtol=1e-12, atol=0)
+
+
 def test_distances_er4096_and_ba65536_sampled(sl):
     for g in (inputs.er4096(0)[0], inputs.ba65536(2)[0]):
         print("case", g.name, flush=True)
