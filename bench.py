@@ -46,13 +46,15 @@ SG_FLOPS_PER_UNORDERED_PAIR = {2: 15, 3: 20}
 # |e|^2 (3), and the two accumulating FMAs (4): 9 in 2-D, 12 in 3-D (the
 # O(n) dot product e.F is left out)
 SG_BOUNDS_FLOPS_PER_UNORDERED_PAIR = {2: 9, 3: 12}
-# the library's default force pass: once per unordered pair in 2-D from a
-# padded size of 32768 vertices, else over every ordered pair (the faster one)
-SYM_MIN_N_PAD = 32768
+# the library's default force pass for hop-count plans: once per unordered
+# pair from a padded size of 24576 vertices (16384 in runs that extrapolate with
+# the safeguard), else over every ordered pair (the faster one, 2-D and 3-D)
+SYM_MIN_N_PAD = 24576
+SYM_MIN_N_PAD_FUSED = 16384
 
 
-def sym_default(dim, n):
-    return dim == 2 and max(64, -(-n // 64) * 64) >= SYM_MIN_N_PAD
+def sym_default(dim, n, fused=True):
+    return max(64, -(-n // 64) * 64) >= (SYM_MIN_N_PAD_FUSED if fused else SYM_MIN_N_PAD)
 CSRC = os.path.join(ROOT, "paper_1711_01228_amd", "csrc")
 # committed rocprofv3 traffic of the dominant kernel, with the source it was taken on
 TRAFFIC = {True: (os.path.join(ROOT, "profiles", "force_safeguard_sym_ba65536_traffic.json"),
@@ -630,13 +632,13 @@ def main():
     a_force = FLOPS_PER_PAIR[dim] * pairs / t_force / 1e12
     abytes = float(n) * (n - 1) / 2 if sym else float(n) * n  # d read once per unordered / ordered pair
     other = {"kernel": "k_force_sg (fused) and k_force over every ordered pair" if sym else
-             "k_force_sym<2, true> / <2, false> + k_sym_reduce over unordered pairs",
+             "k_force_sym<2, 1> / <2, 0> + k_sym_reduce over unordered pairs",
              "fused_ms": round(ms["force_safeguard"] if sym else ms["force_safeguard_sym"], 4),
              "force_ms": round(ms["force"] if sym else ms["force_sym"], 4)}
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dim, sym, n),
-                "kernel": ("k_force_sym<2, true> + k_sym_reduce<2> (unordered pairs)" if sym else
-                           "k_force_sg (ordered pairs)"),
+                "kernel": ("k_force_sym<2, 1> + k_sym_reduce<2> (unordered pairs, bounds of the safeguard)" if sym
+                           else "k_force_sg (ordered pairs)"),
                 "kernel_ms": round(t_fs * 1e3, 4),
                 "flops_per_launch": flops,
                 "flops_per_unit": {"ordered_pair_force": FLOPS_PER_PAIR[dim],
@@ -645,7 +647,7 @@ def main():
                               "its sign open" if sym else "the exact difference, pair by pair"),
                 "algorithmic_bytes_per_launch": abytes,
                 "hbm_GBps_algorithmic": round(abytes / t_fs / 1e9, 1),
-                "force_pass": {"kernel": ("k_force_sym<2, false> + k_sym_reduce<2>" if sym else "k_force") +
+                "force_pass": {"kernel": ("k_force_sym<2, 0> + k_sym_reduce<2>" if sym else "k_force") +
                                " (omega = 1 iterations; after a rejection)",
                                "kernel_ms": round(t_force * 1e3, 4), "TFLOPs": round(a_force, 3),
                                "frac": round(a_force / PEAK_FP32_TFLOPS, 4)},
@@ -700,10 +702,14 @@ def main():
         ms3 = plan3.profile(X3dev0, omega=args.omega, reps=5)
         ttc3 = time_to_converge(plan3, X3dev0)
         plan3.close()
-        a3 = (FLOPS_PER_PAIR[3] * pairs + SG_FLOPS_PER_UNORDERED_PAIR[3] * pairs / 2) / (
-            ms3["force_safeguard"] * 1e-3) / 1e12
+        sym3 = sym_default(3, n)
+        t3 = ms3["force_safeguard_sym"] if sym3 else ms3["force_safeguard"]
+        sg3 = (SG_BOUNDS_FLOPS_PER_UNORDERED_PAIR if sym3 else SG_FLOPS_PER_UNORDERED_PAIR)[3]
+        a3 = (FLOPS_PER_PAIR[3] * pairs + sg3 * pairs / 2) / (t3 * 1e-3) / 1e12
         out["dim3"] = {"value": pairs * args.steps / w3, "ms_per_step": w3 * 1e3 / args.steps,
-                       "fused_kernel_ms": round(ms3["force_safeguard"], 4), "fused_TFLOPs": round(a3, 3),
+                       "fused_kernel": ("k_force_sym<3, 1> + k_sym_reduce<3> (unordered pairs, bounds)" if sym3
+                                        else "k_force_sg<3> (ordered pairs)"),
+                       "fused_kernel_ms": round(t3, 4), "fused_TFLOPs": round(a3, 3),
                        "fused_frac": round(a3 / PEAK_FP32_TFLOPS, 4),
                        "step_kernel_ms": {k: round(v, 4) for k, v in ms3.items()}, "time_to_converge": ttc3}
         log("3-D:", out["dim3"])

@@ -110,15 +110,16 @@ typedef enum {
                                     (F_j takes -c_ij (x_i - x_j), Newton's third law;
                                     the same sums in another order).  SL_ORDER_JACOBI,
                                     no stress trace; otherwise SL_ENOTSUP.  Hop-count
-                                    and edge-length plans.  The default in 2-D with
-                                    n_pad >= 32768 (16384 for edge-length plans), the
-                                    Jacobi step and no stress trace (the faster pass
-                                    there); the first such run allocates the pass's
-                                    partial sums                                     */
+                                    and edge-length plans.  The default, with the
+                                    Jacobi step and no stress trace, from n_pad 24576
+                                    (16384 for a run that extrapolates with the
+                                    safeguard, and for edge-length plans), in 2-D and
+                                    3-D: the faster pass there.  The first such run
+                                    allocates the pass's partial sums               */
 #define SL_FLAG_ORDERED_FORCE 16u /* evaluate the force pass over every ordered pair
-                                    from its row end (the default in 3-D, in 2-D below
-                                    those sizes, for the exact step and for stress
-                                    traces).  Not with SL_FLAG_SYM_FORCE (SL_EINVAL) */
+                                    from its row end (the default below those sizes,
+                                    for the exact step and for stress traces).  Not
+                                    with SL_FLAG_SYM_FORCE (SL_EINVAL)               */
 #define SL_FLAG_SEPARATE_SAFEGUARD 8u  /* evaluate f(X~) - f(X^H) in its own pass over
                                           unordered pairs and the next force pass
                                           after the decision.  Default (either

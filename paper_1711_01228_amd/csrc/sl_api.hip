@@ -500,13 +500,19 @@ sl_status enqueue_after_force(sl_plan* p, const LoopParams& lp, const sl_options
 // Buffers of the unordered-pair force pass, made on first use: its work items
 // and the row and column partial sums.
 // The force pass taken by default: once per unordered pair where that is the
-// faster one (2-D and n_pad >= kSymMinN, or kSymMinNLengths for edge-length
-// plans, whose ordered pass reads 4-byte distances; measured), else every
-// ordered pair.
-constexpr int kSymMinN = 32768;
+// faster one, else every ordered pair (measured in 2-D and 3-D, BA graphs):
+//   hop counts     n_pad >= kSymMinN; from kSymMinNFused in a run whose passes
+//                  carry the safeguard (their bounds cost far less than the
+//                  difference the ordered pass sums)
+//   edge lengths   n_pad >= kSymMinNLengths (the ordered pass reads 4-byte
+//                  distances twice)
+constexpr int kSymMinN = 24576;
+constexpr int kSymMinNFused = 16384;
 constexpr int kSymMinNLengths = 16384;
-bool sym_by_default(const sl_plan* p) {
-  return p->dim == 2 && p->n > 1 && p->n_pad >= (p->df ? kSymMinNLengths : kSymMinN);
+bool sym_by_default(const sl_plan* p, bool fused) {
+  if (p->n <= 1) return false;
+  if (p->df) return p->n_pad >= kSymMinNLengths;
+  return p->n_pad >= (fused ? kSymMinNFused : kSymMinN);
 }
 
 sl_status ensure_sym(sl_plan* p) {
@@ -935,7 +941,8 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
   lp.sym = (o->flags & SL_FLAG_SYM_FORCE) ? 1 : 0;
   if (lp.sym && (lp.stress || o->ordering != SL_ORDER_JACOBI))
     return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: Jacobi ordering, no stress trace");
-  if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !lp.stress && o->ordering == SL_ORDER_JACOBI && sym_by_default(p))
+  if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !lp.stress && o->ordering == SL_ORDER_JACOBI &&
+      sym_by_default(p, lp.fuse != 0))
     lp.sym = 1;
   if (lp.sym) {
     if (p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
@@ -1280,10 +1287,10 @@ sl_status grow(void** ptr, size_t* cap, size_t want, size_t elem, const char* wh
 // The force pass an unrolled run takes: SL_FLAG_SYM_FORCE / SL_FLAG_ORDERED_FORCE
 // as in sl_plan_run, else the default by size; SL_ENOTSUP where the unordered
 // pass does not apply (n <= 1).
-sl_status unroll_sym(sl_plan* p, uint32_t flags, int* sym) {
+sl_status unroll_sym(sl_plan* p, uint32_t flags, bool fused, int* sym) {
   if ((flags & SL_FLAG_SYM_FORCE) && (flags & SL_FLAG_ORDERED_FORCE))
     return fail(SL_EINVAL, "SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE exclude each other");
-  *sym = (flags & SL_FLAG_SYM_FORCE) ? 1 : (flags & SL_FLAG_ORDERED_FORCE) ? 0 : (sym_by_default(p) ? 1 : 0);
+  *sym = (flags & SL_FLAG_SYM_FORCE) ? 1 : (flags & SL_FLAG_ORDERED_FORCE) ? 0 : (sym_by_default(p, fused) ? 1 : 0);
   if (p->n <= 1) *sym = 0;
   if (*sym) return ensure_sym(p);
   return SL_OK;
@@ -1374,7 +1381,8 @@ sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt
   oo.xtrace = nullptr;
   oo.flags &= ~SL_FLAG_TRACE_STRESS;
   int sym = 0;
-  if ((s = unroll_sym(p, o->flags, &sym)) != SL_OK) return s;
+  // the rule of sl_plan_run, so that the unrolled run equals it bit for bit
+  if ((s = unroll_sym(p, o->flags, o->safeguard && o->omega != 1.0 && p->n > 1, &sym)) != SL_OK) return s;
   const LoopParams lp = unroll_params(p, o->omega, o->safeguard, sym);
   sl_result res{};
   res.plan_ms = p->plan_ms;

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
   using V = typename VecT<DIM>::T;
   using L = std::conditional_t<SG == 2, float4, float2>;
   __shared__ L lut[256];                                  // (1/d, 1/d^2 [, -2/d, 0])
-  __shared__ double rows[kWaves][kPanel][DIM][64];        // each wave's FP64 row sums of its 8 strips
+  __shared__ float rows[kWaves][kPanel][DIM][64];         // each wave's row sums of its 8 strips
   if (gate_closed(gate, st)) return;
   {
     const float fb = (float)threadIdx.x;
@@ -137,10 +137,10 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
   const V* __restrict__ X = reinterpret_cast<const V*>(Xb + (size_t)xbuf * stride);
   const V* __restrict__ E = reinterpret_cast<const V*>(Eb);
   const int nstrips = min(kPanel, nb - panel * kPanel);
-  double (*racc)[DIM][64] = rows[wave];
+  float (*racc)[DIM][64] = rows[wave];
   for (int r = 0; r < kPanel; ++r)
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) racc[r][c][lane] = 0.0;
+    for (int c = 0; c < DIM; ++c) racc[r][c][lane] = 0.f;
   double SB = 0.0, SC = 0.0, SD = 0.0;  // the item's B, C and exact difference
 
   for (int g = g0; g < g1; ++g) {
@@ -229,9 +229,9 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
             }
           }
         }
-        racc[r][0][lane] += (double)a0;
-        racc[r][1][lane] += (double)a1;
-        if constexpr (DIM == 3) racc[r][2][lane] += (double)a2;
+        racc[r][0][lane] += a0;
+        racc[r][1][lane] += a1;
+        if constexpr (DIM == 3) racc[r][2][lane] += a2;
         if constexpr (SAFE != 0) {
           SB += (double)ab;
           SC += (double)ac;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
   for (int r = 0; r < nstrips; ++r) {
     float* out = Pi + ((size_t)item * kPanel * 64 + (size_t)r * 64 + lane) * DIM;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) out[c] = (float)racc[r][c][lane];
+    for (int c = 0; c < DIM; ++c) out[c] = racc[r][c][lane];
   }
   if constexpr (SG != 0) {
     SB = wave_sum(SB);

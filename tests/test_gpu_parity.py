@@ -288,9 +288,10 @@ def test_ba65536_one_step_sampled_rows(sl, dim):
     assert err <= 1e-5 * diam(X0), err
 
 
-# (dimension, iteration k from 0): 2-D takes the fused pass over unordered pairs,
-# 3-D the one over ordered pairs; each case costs the oracle two passes over all
-# pairs with every distance row found by breadth-first search (~25 s on 16 threads)
+# (dimension, iteration k from 0): both take the fused pass over unordered pairs
+# (the bounds of the safeguard, the exact difference when they leave its sign
+# open); each case costs the oracle two passes over all pairs with every distance
+# row found by breadth-first search (~25 s on 16 threads)
 BA_LOCKSTEP = [(2, 0), (2, 1), (2, 2), (3, 1)]
 
 

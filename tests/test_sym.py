@@ -123,17 +123,21 @@ def lengths_graph(n, seed):
 
 DEFAULT_CASES = {
     "grid16": lambda: inputs.grid_graph(16, 16),              # n_pad 256: the ordered pass is faster
-    "ba32768": lambda: inputs.barabasi_albert(32768, 3, 61),  # n_pad 32768: the unordered one in 2-D
+    "ba16384": lambda: inputs.barabasi_albert(16384, 3, 64),  # n_pad 16384: unordered only for fused runs
+    "ba24576": lambda: inputs.barabasi_albert(24576, 3, 61),  # n_pad 24576: the unordered one
     "er8192_lengths": lambda: lengths_graph(8192, 62),        # edge lengths: ordered below n_pad 16384
-    "er16384_lengths": lambda: lengths_graph(16384, 63),      # and unordered from there in 2-D
+    "er16384_lengths": lambda: lengths_graph(16384, 63),      # and unordered from there
 }
 
 
-@pytest.mark.parametrize("name,dim,expect", [
-    ("grid16", 2, "ordered"), ("grid16", 3, "ordered"), ("ba32768", 2, "sym"), ("ba32768", 3, "ordered"),
-    ("er8192_lengths", 2, "ordered"), ("er16384_lengths", 2, "sym"), ("er16384_lengths", 3, "ordered"),
+# (graph, dim, omega of the run, the pass it takes by default)
+@pytest.mark.parametrize("name,dim,omega,expect", [
+    ("grid16", 2, 1.5, "ordered"), ("grid16", 3, 1.5, "ordered"),
+    ("ba16384", 2, 1.0, "ordered"), ("ba16384", 2, 1.5, "sym"), ("ba16384", 3, 1.5, "sym"),
+    ("ba24576", 2, 1.0, "sym"), ("ba24576", 3, 1.0, "sym"),
+    ("er8192_lengths", 2, 1.5, "ordered"), ("er16384_lengths", 2, 1.5, "sym"), ("er16384_lengths", 3, 1.0, "sym"),
 ])
-def test_default_force_pass_by_size_and_dim(name, dim, expect):
+def test_default_force_pass_by_size_and_dim(name, dim, omega, expect):
     from paper_1711_01228_amd import binding as b
 
     g = DEFAULT_CASES[name]()
@@ -143,7 +147,7 @@ def test_default_force_pass_by_size_and_dim(name, dim, expect):
         outs = {}
         for kind, kw in (("default", {}), ("sym", {"sym_force": True}), ("ordered", {"ordered_force": True})):
             X = dev(X0)
-            plan.run(X, omega=1.5, tol=0.0, max_iter=6, **kw)
+            plan.run(X, omega=omega, tol=0.0, max_iter=6, **kw)
             outs[kind] = X.cpu().numpy()
         with pytest.raises(b.SlError) as e:
             plan.run(dev(X0), max_iter=2, sym_force=True, ordered_force=True)
