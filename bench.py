@@ -671,7 +671,7 @@ def main():
                       "n": n, "dim": dim, "omega": args.omega, "step": "one iteration of Algorithm 2"},
            "plan_ms": plan_ms,
            # the all-pairs BFS (row A0) writes one distance byte per pair; W follows from it
-           "plan_apsp": {"kernels": "k_bfs_init/gather/finish/store (2,048 sources per sweep) + k_weights",
+           "plan_apsp": {"kernels": "k_bfs_pairs, k_bfs_gather/store (8,192 sources per sweep; W summed in the store) + k_weights_from_partials",
                          "bytes_written": float(n) * n, "GBps": round(float(n) * n / (plan_ms * 1e-3) / 1e9, 1),
                          "frac_of_hbm_peak": round(float(n) * n / (plan_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4)},
            "roofline": roofline}

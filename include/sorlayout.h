@@ -76,8 +76,10 @@ typedef enum {
  *                                  delta^2 <= |e_i - e_j|^2 (e = X~ - X^H), so
  *                                  U = sum -c m and L = U - sum kappa |e_i - e_j|^2.
  *                                  U <= 0 keeps X~ and L > 0 keeps X^H without [2];
- *                                  otherwise [2] is summed and decides.  NaN when
- *                                  no bounds are formed                          */
+ *                                  otherwise [2] is summed and decides, and the
+ *                                  next iterations sum [2] and U in the force
+ *                                  pass itself ([6] NaN) until U <= 0 again.
+ *                                  NaN when no bounds are formed                 */
 
 /* Relaxation strategies (Sec. 5.2; per-vertex factors: Sec. 6, item 1).  Iterations
  * are numbered globally: iteration k of a call is iteration g = iter_offset + k. */

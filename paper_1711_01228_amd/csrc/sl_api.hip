@@ -208,6 +208,7 @@ struct sl_plan {
   DevState* st = nullptr;       // loop state
   DevState* st_eval = nullptr;  // state for stand-alone stress passes
   DevState* host_st = nullptr;  // pinned mirror
+  int32_t* host_flags = nullptr;  // pinned: the level flags of the breadth-first sweeps
   double plan_ms = 0.0;
   // captured chunk of iterations, rebuilt when the loop parameters change
   hipGraphExec_t gexec = nullptr;
@@ -258,6 +259,7 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->st);
   (void)hipFree(p->st_eval);
   if (p->host_st) (void)hipHostFree(p->host_st);
+  if (p->host_flags) (void)hipHostFree(p->host_flags);
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   (void)hipFree(p->comp);
   (void)hipFree(p->cg.y);
@@ -325,17 +327,15 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
   if (p->df) return build_weighted(p);
   if (n > 1 && g->nnz > 0) {
     if (g->nnz > (int64_t)INT32_MAX) return fail(SL_ERANGE, "more than 2^31 - 1 CSR entries");
-    // source row of every CSR entry; the gather's runs (whole rows of at most
-    // bfs_run_entries() entries packed together) and the rows that take a wave
-    // each (longer ones and isolated vertices)
-    std::vector<int32_t> erow((size_t)g->nnz);
-    std::vector<int2> runs;
+    // the gather's runs (whole rows of at most bfs_run_entries() entries packed
+    // together) and the rows that take a wave or a workgroup each (longer ones,
+    // and isolated vertices)
+    std::vector<int4> runs;
     std::vector<int4> longrows;
     const int run_max = bfs_run_entries();
-    int2 open_run = make_int2(0, 0);
+    int4 open_run = make_int4(0, 0, 0, 0);
     for (int v = 0; v < n; ++v) {
       const int64_t b0 = g->row_ptr[v], deg = g->row_ptr[v + 1] - b0;
-      for (int64_t e = b0; e < b0 + deg; ++e) erow[(size_t)e] = v;
       if (deg == 0 || deg > run_max) {
         longrows.push_back(make_int4(v, (int)b0, (int)deg, 0));
         if (deg > 0 && open_run.y > 0) {  // a run holds consecutive CSR entries: close it before this row's
@@ -347,7 +347,7 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
           runs.push_back(open_run);
           open_run.y = 0;
         }
-        if (open_run.y == 0) open_run.x = (int)b0;
+        if (open_run.y == 0) open_run = make_int4((int)b0, 0, v, 0);
         open_run.y += (int)deg;
       }
     }
@@ -357,47 +357,48 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     std::stable_partition(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
     const int nbig = (int)std::count_if(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
     const int nmid = (int)longrows.size() - nbig;
-    int32_t *er = nullptr, *ci = nullptr;
-    int2* rn = nullptr;
-    int4* lrows = nullptr;
-    uint64_t *slots = nullptr, *vis = nullptr;
-    int32_t* flag = nullptr;
-    double* wq = nullptr;
-    int32_t* hflag = nullptr;
-    sl_status status = SL_OK;
-    auto cleanup = [&]() {
-      (void)hipStreamSynchronize(p->ps);
-      (void)hipFree(er);
-      (void)hipFree(ci);
-      (void)hipFree(rn);
-      (void)hipFree(lrows);
-      (void)hipFree(slots);
-      (void)hipFree(vis);
-      (void)hipFree(flag);
-      (void)hipFree(wq);
-      if (hflag) (void)hipHostFree(hflag);
-    };
-    hipError_t e = hipSuccess;
+    const int nruns = (int)runs.size();
     const size_t words = (size_t)n * bfs_words();
     const int nslots = bfs_slots();
     const int sweep = bfs_sources_per_sweep();
     const int nsweeps = (n + sweep - 1) / sweep;
     constexpr int kStride = kBfsMaxLevel + 1;  // one flag row per sweep: flags[l], l = 0 .. 256
-    if (e == hipSuccess) e = hipMalloc(&er, sizeof(int32_t) * g->nnz);
-    if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * g->nnz);
-    if (e == hipSuccess) e = hipMalloc(&slots, sizeof(uint64_t) * words * nslots);
-    if (e == hipSuccess) e = hipMalloc(&vis, sizeof(uint64_t) * words);
-    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int32_t) * kStride * nsweeps);
-    if (e == hipSuccess) e = hipMalloc(&wq, sizeof(double) * (size_t)bfs_weight_partials() * p->n_pad);
-    if (e == hipSuccess) e = hipHostMalloc(&hflag, sizeof(int32_t) * kStride * nsweeps, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMemcpyAsync(er, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
-    if (e == hipSuccess) e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
-    if (e == hipSuccess) e = hipMalloc(&rn, sizeof(int2) * std::max<size_t>(1, runs.size()));
-    if (e == hipSuccess) e = hipMalloc(&lrows, sizeof(int4) * std::max<size_t>(1, longrows.size()));
-    if (e == hipSuccess && !runs.empty())
-      e = hipMemcpyAsync(rn, runs.data(), sizeof(int2) * runs.size(), hipMemcpyHostToDevice, p->ps);
+    // one device allocation for the search's buffers, 256-byte aligned parts
+    size_t off = 0;
+    auto part = [&](size_t bytes) {
+      const size_t at = off;
+      off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+      return at;
+    };
+    const size_t o_ci = part(sizeof(int32_t) * g->nnz), o_rp = part(sizeof(int64_t) * (n + 1)),
+                 o_rn = part(sizeof(int4) * nruns), o_pairs = part(sizeof(int2) * (size_t)nruns * run_max),
+                 o_lrows = part(sizeof(int4) * longrows.size()), o_slots = part(sizeof(uint64_t) * words * nslots),
+                 o_flag = part(sizeof(int32_t) * kStride * nsweeps),
+                 o_wq = part(sizeof(double) * (size_t)bfs_weight_partials() * p->n_pad);
+    char* buf = nullptr;
+    sl_status status = SL_OK;
+    auto cleanup = [&]() {
+      (void)hipStreamSynchronize(p->ps);
+      (void)hipFree(buf);
+    };
+    hipError_t e = hipMalloc(&buf, off);
+    if (e != hipSuccess) return hip_fail(e, "distance buffers");
+    int32_t* ci = reinterpret_cast<int32_t*>(buf + o_ci);
+    int64_t* rp = reinterpret_cast<int64_t*>(buf + o_rp);
+    int4* rn = reinterpret_cast<int4*>(buf + o_rn);
+    int2* pairs = reinterpret_cast<int2*>(buf + o_pairs);
+    int4* lrows = reinterpret_cast<int4*>(buf + o_lrows);
+    uint64_t* slots = reinterpret_cast<uint64_t*>(buf + o_slots);
+    int32_t* flag = reinterpret_cast<int32_t*>(buf + o_flag);
+    double* wq = reinterpret_cast<double*>(buf + o_wq);
+    int32_t* hflag = p->host_flags;
+    e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess) e = hipMemcpyAsync(rp, g->row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess && nruns > 0)
+      e = hipMemcpyAsync(rn, runs.data(), sizeof(int4) * nruns, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess && !longrows.empty())
       e = hipMemcpyAsync(lrows, longrows.data(), sizeof(int4) * longrows.size(), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess) e = launch_bfs_pairs(rn, nruns, rp, ci, pairs, p->ps);
     if (e == hipSuccess) e = hipMemsetAsync(wq, 0, sizeof(double) * (size_t)bfs_weight_partials() * p->n_pad, p->ps);
     if (e == hipSuccess) e = launch_bfs_flags(flag, nsweeps, kStride, p->ps);
     if (e != hipSuccess) {
@@ -411,8 +412,7 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       int32_t* fl = flag + (size_t)sw * kStride;
       hipError_t le = hipSuccess;
       for (int level = l0; level <= l1 && le == hipSuccess; ++level)
-        le = launch_bfs_level(rn, (int)runs.size(), lrows, nbig, nmid, er, ci, slots, vis, n, sw * sweep, level, fl,
-                              p->ps);
+        le = launch_bfs_level(pairs, nruns, lrows, nbig, nmid, ci, slots, n, sw * sweep, level, fl, p->ps);
       // level 256 is not stored: it only tells whether a distance exceeds 255
       if (le == hipSuccess)
         le = launch_bfs_store(slots, fl, p->d, wq, n, p->n_pad, sw * sweep, l0, std::min(l1, kBfsMaxLevel - 1),
@@ -424,8 +424,7 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     // count_from are not counted again (a sweep redone after a shorter run).
     auto sweep_synced = [&](int sw, int first_batch, int count_from, int* depth) -> hipError_t {
       int32_t* fl = flag + (size_t)sw * kStride;
-      hipError_t le = launch_bfs_init(vis, n, sw * sweep, p->ps);
-      if (le == hipSuccess) le = launch_bfs_flags(fl, 1, kStride, p->ps);
+      hipError_t le = launch_bfs_flags(fl, 1, kStride, p->ps);
       for (int l0 = 1, l1 = 0; le == hipSuccess; l0 = l1 + 1) {
         l1 = std::min(l0 + (l0 == 1 ? first_batch : nslots) - 1, kBfsMaxLevel);
         le = queue_levels(sw, l0, l1, count_from);
@@ -452,10 +451,8 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     int depth = 0;
     e = sweep_synced(0, nslots, 1, &depth);
     const int L = std::min(depth + 2, kBfsMaxLevel);
-    for (int sw = 1; sw < nsweeps && e == hipSuccess && status == SL_OK; ++sw) {
-      e = launch_bfs_init(vis, n, sw * sweep, p->ps);
+    for (int sw = 1; sw < nsweeps && e == hipSuccess && status == SL_OK; ++sw)
       for (int l0 = 1; l0 <= L && e == hipSuccess; l0 += nslots) e = queue_levels(sw, l0, std::min(l0 + nslots - 1, L), 1);
-    }
     if (e == hipSuccess && status == SL_OK && nsweeps > 1) {
       e = hipMemcpyAsync(hflag, flag, sizeof(int32_t) * kStride * nsweeps, hipMemcpyDeviceToHost, p->ps);
       if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
@@ -874,6 +871,10 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
   if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
   if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
   if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
+  if (e == hipSuccess && !g->edge_len && g->n > 1 && g->nnz > 0) {
+    const size_t sweeps = ((size_t)g->n + bfs_sources_per_sweep() - 1) / bfs_sources_per_sweep();
+    e = hipHostMalloc(&p->host_flags, sizeof(int32_t) * (kBfsMaxLevel + 1) * sweeps, hipHostMallocDefault);
+  }
   if (e != hipSuccess) return bail(hip_fail(e, "plan allocation"));
   e = hipMemsetAsync(p->Xb, 0, sizeof(float) * 3 * p->stride, p->ps);
   if (e == hipSuccess) e = hipMemsetAsync(p->Eb, 0, sizeof(float) * p->stride, p->ps);

@@ -2,21 +2,20 @@
 // graph: d_ij is the graph-theoretic distance (Sec. 2, eq. 1; Sec. 5.1),
 // w_ij = d_ij^-2, and W_i = sum_j w_ij is the diagonal of L^W (Prop. 2.1).
 //
-// Breadth-first search from kBfsSources sources at once.  Word k of vertex v
-// (index 32 v + k) holds one bit per source base + 64 k + b.  Level l takes
+// Breadth-first search from kBfsSources (8192) sources at once.  Word k of
+// vertex v (index 128 v + k) holds one bit per source base + 64 k + b.  Level l takes
 // the level l-1 frontier F and finds N_l(v) = (OR of F over v's neighbours)
-// & ~visited(v), the sources that reach v first at level l; visited |= N_l.
-// N_l is kept in level slot l mod kBfsSlots and is the next frontier.
-//   k_bfs_gather  one lane group of 16 lanes per run of at most 16 CSR
-//                 entries (built with the plan), each lane reading 16 bytes
-//                 of a neighbour's 256-byte frontier row per entry, all 16
-//                 loads in flight (level 1 forms the sources' bits instead).
-//                 A run holds whole rows of degree <= 16: the group owns them
-//                 and writes N_l, visited and the slot itself.  A row of 17 to
-//                 64 entries (or an isolated vertex) takes a wave of its own,
-//                 whose four groups share its entries and combine their ORs by
-//                 shuffles; a longer row a 1024-thread workgroup, whose waves
-//                 combine theirs through LDS.
+// & ~(N_{l-1}(v) | N_{l-2}(v)), the sources that reach v first at level l (no
+// visited set: see bfs_settle).  N_l is kept in level slot l mod kBfsSlots and
+// is the next frontier.
+//   k_bfs_gather  one wave per run of at most 16 CSR entries (built with the
+//                 plan), each lane reading 16 bytes of a neighbour's 1 KiB
+//                 frontier row per entry, all 16 loads in flight (level 1
+//                 forms the sources' bits instead).  A run holds whole rows of
+//                 degree <= 16: the wave owns them and writes their N_l.  A
+//                 row of 17 to 64 entries (or an isolated vertex) takes a wave
+//                 of its own, 16 entries a pass; a longer row a 1024-thread
+//                 workgroup, whose waves combine their ORs through LDS.
 // Every kBfsSlots levels, k_bfs_store turns the slots of that batch of levels
 // into distance bytes: it transposes a 64-row by 8-word block through LDS into
 // four bit planes of the level offset and one plane of "found", and writes
@@ -35,54 +34,63 @@ namespace sl {
 
 namespace {
 
-constexpr int kBfsWords = 32;                 // 64-bit words per vertex
+constexpr int kGatherLanes = 64;              // lanes per neighbour row (16 bytes each; a lane group)
+constexpr int kBfsWords = 2 * kGatherLanes;   // 64-bit words per vertex
 constexpr int kBfsSources = 64 * kBfsWords;   // sources per sweep
 constexpr int kBfsSlots = 16;                 // level bitmaps kept between stores of d
-constexpr int kGatherLanes = 16;              // lanes per neighbour row (16 bytes each)
 constexpr int kGatherGroups = 64 / kGatherLanes;
 constexpr int kGatherRun = 16;                // CSR entries per lane group
-static_assert(kGatherGroups * kGatherRun == 64, "a wave takes one CSR entry per lane");
+constexpr int kWaveEntries = kGatherGroups * kGatherRun;  // CSR entries a wave takes per pass
+static_assert(kGatherRun <= kGatherLanes && kWaveEntries <= 64, "a group's entries sit in its own lanes");
 constexpr int kStoreWords = 8;                // words per row in one store block
 
 inline unsigned blocks_for(size_t items) { return (unsigned)((items + 255) / 256); }
 
-// visited = the sources themselves (level 0; the level-1 gather forms their
-// frontier bits directly, so no slot holds level 0).
-__global__ __launch_bounds__(256) void k_bfs_init(uint64_t* __restrict__ visited, size_t words, int base) {
-  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= words) return;
-  const int v = (int)(q / kBfsWords), k = (int)(q % kBfsWords);
-  const int s0 = base + 64 * k;
-  visited[q] = (v >= s0 && v < s0 + 64) ? (1ull << (v - s0)) : 0ull;
+// The sources' own bits (level 0): lane wl's chunk of vertex u, u's bit in the
+// chunk of lane (u - base) / 128.  No slot holds level 0.
+__device__ __forceinline__ ulonglong2 source_chunk(int u, int wl, int base) {
+  const int sb = u - base;
+  if (sb < 0 || sb >= kBfsSources || sb / 128 != wl) return make_ulonglong2(0ull, 0ull);
+  const uint64_t bit = 1ull << (sb & 63);
+  return (sb & 64) ? make_ulonglong2(0ull, bit) : make_ulonglong2(bit, 0ull);
 }
 
-// N_l for the two words (one 16-byte chunk q) a lane holds of a row.
-__device__ __forceinline__ void bfs_settle(ulonglong2* __restrict__ visited, ulonglong2* __restrict__ slot,
-                                          size_t q, uint64_t a0, uint64_t a1, int32_t* __restrict__ flags,
-                                          int level) {
+// N_l for the two words (one 16-byte chunk q of vertex v) a lane holds of a
+// row: the OR a of the neighbours' level l-1 bits without v's own bits of levels
+// l-1 and l-2.  On an undirected graph a neighbour's distance from a source
+// differs from v's by at most one, so a source in a is at distance l-2, l-1 or
+// l from v, and the last exactly when it is in neither of v's two previous
+// levels: no visited set is kept.  `found` is set when N_l is not empty (the
+// wave raises the level's flag once).
+__device__ __forceinline__ void bfs_settle(const ulonglong2* __restrict__ F, const ulonglong2* __restrict__ P2,
+                                          ulonglong2* __restrict__ slot, int v, int wl, int level, int base,
+                                          uint64_t a0, uint64_t a1, bool& found) {
+  const size_t q = (size_t)v * (kBfsWords / 2) + wl;
   ulonglong2 nw = make_ulonglong2(0ull, 0ull);
   if (a0 | a1) {
-    const ulonglong2 vis = visited[q];
-    nw = make_ulonglong2(a0 & ~vis.x, a1 & ~vis.y);
-    if (nw.x | nw.y) {
-      visited[q] = make_ulonglong2(vis.x | nw.x, vis.y | nw.y);
-      flags[level] = 1;
-    }
+    // v's bits of levels l-1 and l-2 (level 0: the sources)
+    const ulonglong2 p1 = level == 1 ? source_chunk(v, wl, base) : F[q];
+    const ulonglong2 p2 = level == 1 ? make_ulonglong2(0ull, 0ull)
+                          : level == 2 ? source_chunk(v, wl, base) : P2[q];
+    nw = make_ulonglong2(a0 & ~(p1.x | p2.x), a1 & ~(p1.y | p2.y));
+    if (nw.x | nw.y) found = true;
   }
   slot[q] = nw;
 }
 
+// flags[level] = 1, stored by one lane of the wave where any lane found a new
+// pair (the lowest such lane, which is active here).
+__device__ __forceinline__ void raise_flag(bool found, int32_t* __restrict__ flags, int level) {
+  const uint64_t any = __ballot(found);
+  if (found && (threadIdx.x & 63) == (unsigned)__builtin_ctzll(any)) flags[level] = 1;
+}
+
 // Frontier chunk (lane wl's 16 bytes) of neighbour u; at level 1 the frontier
-// is the sources themselves: u's own bit, in the chunk of lane (u - base) / 128.
+// is the sources themselves.
 __device__ __forceinline__ ulonglong2 frontier_chunk(const ulonglong2* __restrict__ F, int u, int wl, int level,
                                                      int base) {
   if (u < 0) return make_ulonglong2(0ull, 0ull);
-  if (level == 1) {
-    const int sb = u - base;
-    if (sb < 0 || sb >= kBfsSources || sb / 128 != wl) return make_ulonglong2(0ull, 0ull);
-    const uint64_t bit = 1ull << (sb & 63);
-    return (sb & 64) ? make_ulonglong2(0ull, bit) : make_ulonglong2(bit, 0ull);
-  }
+  if (level == 1) return source_chunk(u, wl, base);
   return F[(size_t)u * (kBfsWords / 2) + wl];
 }
 
@@ -90,9 +98,9 @@ constexpr int kGatherThreads = 1024;           // threads per gather workgroup (
 constexpr int kGatherWaves = kGatherThreads / 64;
 constexpr int kMidMax = 64;                     // rows up to this degree take one wave
 
-// The OR of lane wl's chunk over entries e0 .. e0 + 63 of a row (CSR entries
-// from b), the wave's lane groups each taking 16 of them: lane l holds entry
-// e0 + l; the groups' ORs are then combined, so every group holds the total.
+// The OR of lane wl's chunk over entries e0 .. e0 + kWaveEntries - 1 of a row
+// (CSR entries from b), the wave's lane groups each taking kGatherRun of them:
+// lane l holds entry e0 + l.
 __device__ __forceinline__ void row_chunk_or(const ulonglong2* __restrict__ F, const int32_t* __restrict__ col_idx,
                                              int b, int deg, int e0, int lane, int grp, int wl, int level, int base,
                                              uint64_t& a0, uint64_t& a1) {
@@ -107,45 +115,54 @@ __device__ __forceinline__ void row_chunk_or(const ulonglong2* __restrict__ F, c
   }
 }
 
+// OR across the wave's lane groups (lanes wl of every group): each group then holds the total.
+__device__ __forceinline__ void groups_or(uint64_t& a0, uint64_t& a1) {
+#pragma unroll
+  for (int m = kGatherLanes; m < 64; m <<= 1) {
+    a0 |= __shfl_xor(a0, m, 64);
+    a1 |= __shfl_xor(a1, m, 64);
+  }
+}
+
 // Three kinds of workgroup, by index:
 //   [0, nbig)                 one row of degree above kMidMax each: its 16 waves
-//                             share the entries, 1024 per pass, and combine
+//                             share the entries, 256 per pass, and combine
 //                             their ORs through LDS; wave 0's first group settles
 //   [nbig, nbig + mid blocks) one row of degree 17 .. kMidMax, or an isolated
 //                             vertex, per wave
-//   the rest                  the runs, one lane group per run
-__global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __restrict__ runs, int nruns,
+//   the rest                  the runs, one lane group per run (its entries'
+//                             (neighbour, vertex) pairs, one load per lane)
+__global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __restrict__ pairs, int nruns,
                                                                const int4* __restrict__ longrows, int nbig, int nmid,
-                                                               const int32_t* __restrict__ erow,
                                                                const int32_t* __restrict__ col_idx,
                                                                const uint64_t* __restrict__ frontier,
-                                                               ulonglong2* __restrict__ visited,
+                                                               const uint64_t* __restrict__ prev2,
                                                                ulonglong2* __restrict__ slot,
                                                                int32_t* __restrict__ flags, int level, int base) {
   __shared__ ulonglong2 wor[kGatherWaves][kGatherLanes];
   if (flags[level - 1] == 0) return;  // the search of this sweep has ended
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / kGatherLanes, wl = lane % kGatherLanes;
   const ulonglong2* __restrict__ F = reinterpret_cast<const ulonglong2*>(frontier);
+  const ulonglong2* __restrict__ P2 = reinterpret_cast<const ulonglong2*>(prev2);
   const int nmid_blocks = (nmid + kGatherWaves - 1) / kGatherWaves;
   if ((int)blockIdx.x < nbig) {
     const int4 lr = longrows[blockIdx.x];  // (vertex, first CSR entry, degree, 0)
     uint64_t a0 = 0ull, a1 = 0ull;
-    for (int e0 = wave * 64; e0 < lr.z; e0 += kGatherThreads)
+    for (int e0 = wave * kWaveEntries; e0 < lr.z; e0 += kGatherWaves * kWaveEntries)
       row_chunk_or(F, col_idx, lr.y, lr.z, e0, lane, grp, wl, level, base, a0, a1);
-    a0 |= __shfl_xor(a0, 16, 64);
-    a1 |= __shfl_xor(a1, 16, 64);
-    a0 |= __shfl_xor(a0, 32, 64);
-    a1 |= __shfl_xor(a1, 32, 64);
+    groups_or(a0, a1);
     if (grp == 0) wor[wave][wl] = make_ulonglong2(a0, a1);
     __syncthreads();
+    bool found = false;
     if (wave == 0 && grp == 0) {
 #pragma unroll
       for (int w = 1; w < kGatherWaves; ++w) {
         a0 |= wor[w][wl].x;
         a1 |= wor[w][wl].y;
       }
-      bfs_settle(visited, slot, (size_t)lr.x * (kBfsWords / 2) + wl, a0, a1, flags, level);
+      bfs_settle(F, P2, slot, lr.x, wl, level, base, a0, a1, found);
     }
+    raise_flag(found, flags, level);
     return;
   }
   if ((int)blockIdx.x < nbig + nmid_blocks) {
@@ -153,44 +170,63 @@ __global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __res
     if (k >= nmid) return;
     const int4 lr = longrows[nbig + k];
     uint64_t a0 = 0ull, a1 = 0ull;
-    if (lr.z > 0) row_chunk_or(F, col_idx, lr.y, lr.z, 0, lane, grp, wl, level, base, a0, a1);
-    a0 |= __shfl_xor(a0, 16, 64);
-    a1 |= __shfl_xor(a1, 16, 64);
-    a0 |= __shfl_xor(a0, 32, 64);
-    a1 |= __shfl_xor(a1, 32, 64);
-    if (grp == 0) bfs_settle(visited, slot, (size_t)lr.x * (kBfsWords / 2) + wl, a0, a1, flags, level);
+    for (int e0 = 0; e0 < lr.z; e0 += kWaveEntries)
+      row_chunk_or(F, col_idx, lr.y, lr.z, e0, lane, grp, wl, level, base, a0, a1);
+    groups_or(a0, a1);
+    bool found = false;
+    if (grp == 0) bfs_settle(F, P2, slot, lr.x, wl, level, base, a0, a1, found);
+    raise_flag(found, flags, level);
     return;
   }
   const int r = (((int)blockIdx.x - nbig - nmid_blocks) * kGatherWaves + wave) * kGatherGroups + grp;
-  const int2 rd = r < nruns ? runs[r] : make_int2(0, 0);  // (first CSR entry, entry count)
-  // lane wl of the group holds entry rd.x + wl
-  const int vj = wl < rd.y ? erow[rd.x + wl] : -1;
-  const int uj = wl < rd.y ? col_idx[rd.x + wl] : 0;
+  // lane wl < kGatherRun of the group holds the run's entry wl: (neighbour, vertex), or (-1, -1)
+  const int2 pr = r < nruns && wl < kGatherRun ? pairs[(size_t)r * kGatherRun + wl] : make_int2(-1, -1);
+  const int vj = pr.y, uj = pr.x;
   ulonglong2 f[kGatherRun];
-  int vv[kGatherRun];
 #pragma unroll
   for (int j = 0; j < kGatherRun; ++j) {
-    vv[j] = __shfl(vj, kGatherRun * grp + j, 64);
-    const int u = __shfl(uj, kGatherRun * grp + j, 64);
-    f[j] = frontier_chunk(F, vv[j] >= 0 ? u : -1, wl, level, base);
+    const int u = __shfl(uj, kGatherLanes * grp + j, 64);  // -1 past the run
+    f[j] = frontier_chunk(F, u, wl, level, base);
   }
   int cur = -1;
   uint64_t a0 = 0ull, a1 = 0ull;
+  bool found = false;
 #pragma unroll
   for (int j = 0; j < kGatherRun; ++j) {
-    const int v = vv[j];
+    const int v = __shfl(vj, kGatherLanes * grp + j, 64);
     if (v != cur) {
-      if (cur >= 0) bfs_settle(visited, slot, (size_t)cur * (kBfsWords / 2) + wl, a0, a1, flags, level);
+      if (cur >= 0) bfs_settle(F, P2, slot, cur, wl, level, base, a0, a1, found);
       cur = v;
       a0 = a1 = 0ull;
     }
     a0 |= f[j].x;
     a1 |= f[j].y;
   }
-  if (cur >= 0) bfs_settle(visited, slot, (size_t)cur * (kBfsWords / 2) + wl, a0, a1, flags, level);
+  if (cur >= 0) bfs_settle(F, P2, slot, cur, wl, level, base, a0, a1, found);
+  raise_flag(found, flags, level);
 }
 
-// W_v = the sum of the store kernels' partials wq[kq][v] over the four word
+// The runs' entries as the gather reads them: lane j of run r gets
+// pairs[16 r + j] = (col_idx[e], row of e) for e = first + j below first + count,
+// else (-1, -1).  runs[r] = (first CSR entry, count, row of the first entry, 0).
+__global__ __launch_bounds__(256) void k_bfs_pairs(const int4* __restrict__ runs, int nruns,
+                                                   const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx, int2* __restrict__ pairs) {
+  const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (size_t)nruns * kGatherRun) return;
+  const int4 rd = runs[q / kGatherRun];
+  const int j = (int)(q % kGatherRun);
+  int2 out = make_int2(-1, -1);
+  if (j < rd.y) {
+    const int64_t e = (int64_t)rd.x + j;
+    int v = rd.z;
+    while (row_ptr[v + 1] <= e) ++v;  // the run's rows and the empty rows between them
+    out = make_int2(col_idx[e], v);
+  }
+  pairs[q] = out;
+}
+
+// W_v = the sum of the store kernels' partials wq[kq][v] over the sixteen word
 // blocks kq, in order.
 __global__ __launch_bounds__(256) void k_weights_from_partials(const double* __restrict__ wq, double* __restrict__ W,
                                                                int n, int n_pad) {
@@ -227,7 +263,7 @@ __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ 
   const int t = threadIdx.x;
   // planes 0..3: bits of l - l0; plane 4: found in this batch
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < kRowBlock * kStoreWords / 256; ++r) {
     const int p = t + 256 * r;
     const int row = p / kStoreWords, kk = p % kStoreWords;
     const int v = rb * kRowBlock + row;
@@ -245,10 +281,9 @@ __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ 
       if (off & 8) P3 |= nw;
       if (l >= count_from) ws += (double)__popcll(nw) / ((double)l * (double)l);
     }
-    // the row's 8 threads are consecutive lanes: add their sums in a fixed tree
-    ws += __shfl_xor(ws, 4, kStoreWords);
-    ws += __shfl_xor(ws, 2, kStoreWords);
-    ws += __shfl_xor(ws, 1, kStoreWords);
+    // the row's kStoreWords threads are consecutive lanes: add their sums in a fixed tree
+#pragma unroll
+    for (int m = kStoreWords / 2; m > 0; m >>= 1) ws += __shfl_xor(ws, m, kStoreWords);
     if (kk == 0 && v < n && ws != 0.0) wq[(size_t)kq * n_pad + v] += ws;
     planes[0][row][kk] = P0;
     planes[1][row][kk] = P1;
@@ -260,8 +295,8 @@ __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ 
   const int wave = t >> 6, row = t & 63;
   const uint32_t lvl = (uint32_t)l0 * 0x01010101u;
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int kk = 2 * wave + r;
+  for (int r = 0; r < kStoreWords / 4; ++r) {
+    const int kk = (kStoreWords / 4) * wave + r;
     const int k = kq * kStoreWords + kk;
     const uint64_t P0 = planes[0][row][kk], P1 = planes[1][row][kk], P2 = planes[2][row][kk],
                    P3 = planes[3][row][kk], Fd = planes[4][row][kk];
@@ -339,13 +374,6 @@ int bfs_sources_per_sweep() { return kBfsSources; }
 int bfs_words() { return kBfsWords; }
 int bfs_slots() { return kBfsSlots; }
 
-hipError_t launch_bfs_init(uint64_t* visited, int n, int base, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const size_t words = (size_t)n * kBfsWords;
-  k_bfs_init<<<blocks_for(words), 256, 0, s>>>(visited, words, base);
-  return hipGetLastError();
-}
-
 int bfs_run_entries() { return kGatherRun; }
 
 hipError_t launch_bfs_flags(int32_t* flags, int sweeps, int stride, hipStream_t s) {
@@ -364,17 +392,24 @@ int bfs_weight_partials() { return kBfsWords / kStoreWords; }
 
 int bfs_mid_max_degree() { return kMidMax; }
 
-hipError_t launch_bfs_level(const int2* runs, int nruns, const int4* longrows, int nbig, int nmid, const int32_t* erow,
-                            const int32_t* col_idx, const uint64_t* slots, uint64_t* visited, int n, int base,
-                            int level, int32_t* flags, hipStream_t s) {
+hipError_t launch_bfs_pairs(const int4* runs, int nruns, const int64_t* row_ptr, const int32_t* col_idx, int2* pairs,
+                            hipStream_t s) {
+  if (nruns <= 0) return hipSuccess;
+  k_bfs_pairs<<<blocks_for((size_t)nruns * kGatherRun), 256, 0, s>>>(runs, nruns, row_ptr, col_idx, pairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_bfs_level(const int2* pairs, int nruns, const int4* longrows, int nbig, int nmid,
+                            const int32_t* col_idx, const uint64_t* slots, int n, int base, int level,
+                            int32_t* flags, hipStream_t s) {
   if (n <= 0 || nruns + nbig + nmid == 0) return hipSuccess;
   const size_t words = (size_t)n * kBfsWords;
   const uint64_t* frontier = slots + (size_t)((level - 1) % kBfsSlots) * words;
+  const uint64_t* prev2 = slots + (size_t)((level + kBfsSlots - 2) % kBfsSlots) * words;  // read from level 3 on
   uint64_t* out = const_cast<uint64_t*>(slots) + (size_t)(level % kBfsSlots) * words;
   const int per_block = kGatherWaves * kGatherGroups;
   const unsigned blocks = (unsigned)(nbig + (nmid + kGatherWaves - 1) / kGatherWaves + (nruns + per_block - 1) / per_block);
-  k_bfs_gather<<<blocks, kGatherThreads, 0, s>>>(runs, nruns, longrows, nbig, nmid, erow, col_idx, frontier,
-                                                 reinterpret_cast<ulonglong2*>(visited),
+  k_bfs_gather<<<blocks, kGatherThreads, 0, s>>>(pairs, nruns, longrows, nbig, nmid, col_idx, frontier, prev2,
                                                  reinterpret_cast<ulonglong2*>(out), flags, level, base);
   return hipGetLastError();
 }

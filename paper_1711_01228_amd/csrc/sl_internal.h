@@ -169,22 +169,26 @@ int bfs_sources_per_sweep();  // sources searched together (bits per vertex)
 int bfs_words();              // 64-bit words per vertex in the BFS buffers
 int bfs_slots();              // level bitmaps kept (levels per batch)
 // slots: bfs_slots() buffers of n * bfs_words() words; slot l % bfs_slots()
-// holds the sources that first reach each vertex at level l >= 1.
-// visited := the sweep's sources (from base).
-hipError_t launch_bfs_init(uint64_t* visited, int n, int base, hipStream_t s);
-// Runs of the gather: int2 (first CSR entry, count), count 1 .. bfs_run_entries():
-// whole rows of at most that many entries packed together (a run never splits
-// one).  Every other row is listed in longrows as int4 (vertex, first CSR
-// entry, degree, 0): first the nbig rows of degree above bfs_mid_max_degree()
-// (a workgroup each), then the nmid others (degree up to that, or 0: a wave each).
+// holds the sources that first reach each vertex at level l >= 1 (the sources
+// themselves, level 0, are formed where needed).
+// Runs of the gather: int4 (first CSR entry, count, row of that entry, 0),
+// count 1 .. bfs_run_entries(): whole rows of at most that many entries packed
+// together (a run never splits one).  Every other row is listed in longrows as
+// int4 (vertex, first CSR entry, degree, 0): first the nbig rows of degree above
+// bfs_mid_max_degree() (a workgroup each), then the nmid others (degree up to
+// that, or 0: a wave each).
 int bfs_run_entries();
 int bfs_mid_max_degree();
+// pairs (nruns * bfs_run_entries() int2): the runs' entries as (neighbour, row),
+// (-1, -1) past a run's count; row_ptr and col_idx on the device.
+hipError_t launch_bfs_pairs(const int4* runs, int nruns, const int64_t* row_ptr, const int32_t* col_idx, int2* pairs,
+                            hipStream_t s);
 // One BFS level (1 .. 256) of the sweep from sources base ...  flags[0 .. 256]:
 // flags[l] != 0 iff level l found a new vertex (flags[0]: the sources); a level
 // after an empty one does nothing.
-hipError_t launch_bfs_level(const int2* runs, int nruns, const int4* longrows, int nbig, int nmid, const int32_t* erow,
-                            const int32_t* col_idx, const uint64_t* slots, uint64_t* visited, int n, int base,
-                            int level, int32_t* flags, hipStream_t s);
+hipError_t launch_bfs_level(const int2* pairs, int nruns, const int4* longrows, int nbig, int nmid,
+                            const int32_t* col_idx, const uint64_t* slots, int n, int base, int level,
+                            int32_t* flags, hipStream_t s);
 // `sweeps` flag rows of `stride` ints: [s][0] = 1, the rest 0.
 hipError_t launch_bfs_flags(int32_t* flags, int sweeps, int stride, hipStream_t s);
 // Weight partials of the stores: bfs_weight_partials() x n_pad doubles, zero

@@ -665,10 +665,14 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     st->bound_u = bu;
     st->bound_l = bl;
     const bool decisive = bu <= 0.0 || bl > 0.0;
-    if (ran_exact) {  // the pass summed the difference too: it decides
+    if (ran_exact) {  // the pass summed the difference and U = sum -c m itself (no L)
       df = v[10];
       take = df <= 0.0;
-      st->exact_next = decisive ? 0 : 1;  // back to the bounds alone once they would have decided
+      bu = v[7];
+      bl = nan;
+      st->bound_u = bu;
+      st->bound_l = bl;
+      st->exact_next = bu <= 0.0 ? 0 : 1;  // back to the bounds alone once U would have decided
     } else if (decisive) {
       df = nan;  // the difference itself is not formed when the bounds decide
       take = bu <= 0.0;

@@ -98,9 +98,11 @@ __device__ __forceinline__ float lut_l2(const T& e) {
 }
 
 // SG = 0: force only.  SG = 1: the pass at X~ with the bounds' B and C.
-// SG = 2: the same with the exact f(X~) - f(X^H) summed in as well,
-//   term = m (1/d^2 - (2/d) / s),  m = 2 e.t - |e|^2,  s = r~ + r^H,
-//   r^H = sqrt|r~^2 - m|  (no difference of nearly equal squares).
+// SG = 2: the pass at X~ with the exact f(X~) - f(X^H) summed in,
+//   term = m (1/d^2 - (2/d) / s),  m = e.(2t - e),  s = r~ + r^H,
+//   r^H = sqrt|r~^2 - m|  (no difference of nearly equal squares),
+// and U = sum -c m pair by pair (its first B slot; C stays 0): whether the
+// bounds alone would have decided the acceptance.
 template <int DIM, int SG, bool FD>
 __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d, const float* __restrict__ df,
                                                    const float* __restrict__ Xb,
@@ -170,6 +172,11 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
         float a0 = 0.f, a1 = 0.f, a2 = 0.f, ab = 0.f, ac = 0.f, ad = 0.f;
 #pragma unroll
         for (int k = 0; k < kColGroup; ++k) {
+          if constexpr (SAFE != 0 && DIM == 3) {
+            // the columns' x_j and e_j are lane-uniform (scalar registers): 16 of
+            // each in 3-D do not fit, so the second half loads after the first
+            if (k % (kColGroup / 2) == 0) asm volatile("" ::: "memory");
+          }
           float inv, w, l2 = 0.f;  // 1/d, 1/d^2, -2/d (0 where d = 0)
           if constexpr (FD) {
             const float dv = fchunk_at(q, k);
@@ -204,29 +211,37 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
             a2 = fmaf(c, tz, a2);
             Cz[k] = fmaf(c, tz, Cz[k]);
           }
-          if constexpr (SAFE != 0) {
+          if constexpr (SAFE == 1) {  // B and C
             const V pe = ej[k];
             const float ex = ei.x - pe.x, ey = ei.y - pe.y;
             float e2 = fmaf(ex, ex, ey * ey);
-            float et = fmaf(ex, tx, ey * ty);
             if constexpr (DIM == 3) {
               const float ez = ei.z - pe.z;
               e2 = fmaf(ez, ez, e2);
-              et = fmaf(ez, tz, et);
             }
-            float mk = 1.f;  // 0 for the pairs j <= i of a diagonal group
             if constexpr (MASK) {
-              if (jlo + k <= ilo + lane) mk = 0.f;
+              if (jlo + k <= ilo + lane) e2 = 0.f;  // the pairs j <= i of a diagonal group
             }
-            e2 *= mk;
             ab = fmaf(c, e2, ab);
             ac = fmaf(w, e2, ac);
-            if constexpr (SAFE == 2) {
-              const float m = fmaf(2.f, et, -e2);  // r~^2 - r^H^2 (0 where masked)
-              const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
-              const float sum = fmaf(r2, rinv, rh);
-              ad = fmaf(m * mk, fmaf(l2, __builtin_amdgcn_rcpf(sum), w), ad);
+          }
+          if constexpr (SAFE == 2) {  // the difference itself, and U = sum -c m (c is 0 where masked)
+            const V pe = ej[k];
+            const float ex = ei.x - pe.x, ey = ei.y - pe.y;
+            float m = ex * fmaf(2.f, tx, -ex);  // r~^2 - r^H^2 = e.(2t - e)
+            m = fmaf(ey, fmaf(2.f, ty, -ey), m);
+            if constexpr (DIM == 3) {
+              const float ez = ei.z - pe.z;
+              m = fmaf(ez, fmaf(2.f, tz, -ez), m);
             }
+            const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
+            const float sum = fmaf(r2, rinv, rh);
+            float term = m * fmaf(l2, __builtin_amdgcn_rcpf(sum), w);
+            if constexpr (MASK) {
+              if (jlo + k <= ilo + lane) term = 0.f;
+            }
+            ad += term;
+            ab = fmaf(-c, m, ab);
           }
         }
         racc[r][0][lane] += a0;
@@ -236,7 +251,7 @@ __global__ __launch_bounds__(256) void k_force_sym(const uint8_t* __restrict__ d
           SB += (double)ab;
           SC += (double)ac;
         }
-        if constexpr (SAFE == 2) SD += (double)ad;
+        if constexpr (SAFE == 2) SD += (double)ad;  // (SB holds U's partial here, SC stays 0)
         q = qn;
       }
     };
