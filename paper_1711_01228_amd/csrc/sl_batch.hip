@@ -262,15 +262,21 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
       }
       block_sum_waves<8, NW>(v, red, red_tot);
       // ---- the force at X~ (the next iteration's, if X~ is kept) with the
-      // safeguard f(X~) - f(X^H) summed over the upper triangle in the same pass.
-      // The force terms are those of the pass above, in the same order.  For
-      // j > i, with t = x~_i - x~_j and e = e_i - e_j (e = x~ - x^H):
-      //   m = r~^2 - r^H^2 = e.(2t - e), r^H = sqrt|r~^2 - m|,
-      //   term = m (1/d^2 - (2/d) / (r~ + r^H)).
+      // safeguard's bounds summed over the upper triangle in the same pass.  The
+      // force terms are those of the pass above, in the same order.  For j > i,
+      // with t = x~_i - x~_j, e = e_i - e_j (e = x~ - x^H), c the force
+      // coefficient and w = 1/d^2, the pair's share of f(X~) - f(X^H) is
+      // -c m - kappa delta^2 with m = e.(2t - e), kappa = 1/(d r~) >= 0 and
+      // delta^2 <= |e|^2, so with P = sum_i e_i . F_i(X~):
+      //   U = -2P + sum c |e|^2  >=  f(X~) - f(X^H)  >=  -2P - sum w |e|^2 = L.
+      // U <= 0 keeps X~ and L > 0 keeps X^H; otherwise a pass over the upper
+      // triangle sums the difference itself:
+      //   r^H = sqrt|r~^2 - m|, term = m (1/d^2 - (2/d) / (r~ + r^H)).
       double df = 0.0;
+      bool take_t = true;
       if (sg) {
         __syncthreads();  // the update has read every force partial
-        double acc = 0.0;
+        double accB = 0.0, accC = 0.0;
         for (int u = wave; u < units; u += NW) {
           const int rb = u % nrb, s = u / nrb;
           const int gdiag = rb * (kRowBlock / kColGroup), gfree = gdiag + kRowBlock / kColGroup;
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
             for (int g = ga; g < gb; ++g) {
               const uint4 qd = tile[(size_t)g * 64];
               const int jrel = i - g * kColGroup;
-              float a0 = 0.f, a1 = 0.f, a2 = 0.f, a = 0.f;
+              float a0 = 0.f, a1 = 0.f, a2 = 0.f, ab = 0.f, ac = 0.f;
 #pragma unroll
               for (int k = 0; k < kColGroup; ++k) {
                 const uint32_t b = byte_of(chunk_word(qd, k), k & 3);
@@ -300,34 +306,33 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
                   dz = xi.z - pj.z;
                   r2 = fmaf(dz, dz, r2);
                 }
-                const float rinv = __builtin_amdgcn_rsqf(r2);
-                const float c = fmaf(wt.x, rinv, -wt.y);
+                const float c = fmaf(wt.x, __builtin_amdgcn_rsqf(r2), -wt.y);
                 a0 = fmaf(c, dx, a0);
                 a1 = fmaf(c, dy, a1);
                 if constexpr (DIM == 3) a2 = fmaf(c, dz, a2);
                 if constexpr (MODE != 0) {
                   const V pe = es[g * kColGroup + k];
                   const float ex = ei.x - pe.x, ey = ei.y - pe.y;
-                  float m = ex * fmaf(2.f, dx, -ex);
-                  m = fmaf(ey, fmaf(2.f, dy, -ey), m);
+                  float e2 = fmaf(ex, ex, ey * ey);
                   if constexpr (DIM == 3) {
                     const float ez = ei.z - pe.z;
-                    m = fmaf(ez, fmaf(2.f, dz, -ez), m);
+                    e2 = fmaf(ez, ez, e2);
                   }
-                  const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
-                  const float sum = fmaf(r2, rinv, rh);
-                  float term = m * fmaf(lut2[b], __builtin_amdgcn_rcpf(sum), wt.y);
                   if constexpr (MODE == 1) {
-                    if (k <= jrel) term = 0.f;
+                    if (k <= jrel) e2 = 0.f;
                   }
-                  a += term;
+                  ab = fmaf(c, e2, ab);
+                  ac = fmaf(wt.y, e2, ac);
                 }
                 if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
               }
               F0 += (double)a0;
               F1 += (double)a1;
               if constexpr (DIM == 3) F2 += (double)a2;
-              if constexpr (MODE != 0) acc += (double)a;
+              if constexpr (MODE != 0) {
+                accB += (double)ab;
+                accC += (double)ac;
+              }
             }
           };
           run(std::integral_constant<int, 0>{}, g0, min(g1, gdiag));
@@ -338,9 +343,77 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
           fp[1] = F1;
           if constexpr (DIM == 3) fp[2] = F2;
         }
-        double vv[1] = {acc};
-        block_sum_waves<1, NW>(vv, red, red_tot);
-        df = vv[0];
+        __syncthreads();  // every force partial at X~ is written
+        double pe = 0.0;  // P = sum_i e_i . F_i(X~), the force summed over slices as the update does
+        for (int i = tid; i < n; i += T) {
+          double F[3] = {0.0, 0.0, 0.0};
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) F[c] += Fp[((size_t)s * n_pad + i) * DIM + c];
+          const V e = es[i];
+          pe += (double)e.x * F[0] + (double)e.y * F[1];
+          if constexpr (DIM == 3) pe += (double)e.z * F[2];
+        }
+        double vb[3] = {accB, accC, pe};
+        block_sum_waves<3, NW>(vb, red, red_tot);
+        const double bu = -2.0 * vb[2] + vb[0], bl = -2.0 * vb[2] - vb[1];
+        if (bu <= 0.0) {
+          take_t = true;
+        } else if (bl > 0.0) {
+          take_t = false;
+        } else {  // the bounds leave the sign open: the difference itself
+          double acc = 0.0;
+          for (int u = wave; u < units; u += NW) {
+            const int rb = u % nrb, s = u / nrb;
+            const int gdiag = rb * (kRowBlock / kColGroup), gfree = gdiag + kRowBlock / kColGroup;
+            const int g0 = s * gps, g1 = min(g0 + gps, ng);
+            const int i = rb * kRowBlock + lane;
+            const V xi = xs[t][i], ei = es[i];
+            const uint4* __restrict__ tile = reinterpret_cast<const uint4*>(dg + (size_t)rb * ng * kTileBytes) + lane;
+            auto run = [&](auto mode_tag, int ga, int gb) {
+              constexpr int MODE = decltype(mode_tag)::value;
+              for (int g = ga; g < gb; ++g) {
+                const uint4 qd = tile[(size_t)g * 64];
+                const int jrel = i - g * kColGroup;
+                float a = 0.f;
+#pragma unroll
+                for (int k = 0; k < kColGroup; ++k) {
+                  const uint32_t b = byte_of(chunk_word(qd, k), k & 3);
+                  const float2 wt = lut[b];
+                  const V pj = xs[t][g * kColGroup + k];
+                  const V pe = es[g * kColGroup + k];
+                  const float dx = xi.x - pj.x, dy = xi.y - pj.y;
+                  float r2 = fmaf(dx, dx, kTiny);
+                  r2 = fmaf(dy, dy, r2);
+                  const float ex = ei.x - pe.x, ey = ei.y - pe.y;
+                  float m = ex * fmaf(2.f, dx, -ex);
+                  m = fmaf(ey, fmaf(2.f, dy, -ey), m);
+                  if constexpr (DIM == 3) {
+                    const float dz = xi.z - pj.z, ez = ei.z - pe.z;
+                    r2 = fmaf(dz, dz, r2);
+                    m = fmaf(ez, fmaf(2.f, dz, -ez), m);
+                  }
+                  const float rinv = __builtin_amdgcn_rsqf(r2);
+                  const float rh = __builtin_amdgcn_sqrtf(fabsf(r2 - m));
+                  const float sum = fmaf(r2, rinv, rh);
+                  float term = m * fmaf(lut2[b], __builtin_amdgcn_rcpf(sum), wt.y);
+                  if constexpr (MODE == 1) {
+                    if (k <= jrel) term = 0.f;
+                  }
+                  a += term;
+                  if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+                }
+                acc += (double)a;
+              }
+            };
+            run(std::integral_constant<int, 1>{}, max(g0, gdiag), min(g1, gfree));
+            run(std::integral_constant<int, 2>{}, max(g0, gfree), g1);
+          }
+          double vv[1] = {acc};
+          block_sum_waves<1, NW>(vv, red, red_tot);
+          df = vv[0];
+          take_t = df <= 0.0;
+        }
       }
       // ---- decision and termination test (every thread holds the same sums)
       if (__builtin_amdgcn_readfirstlane(v[6] > 0.0 ? 1 : 0)) {
@@ -354,7 +427,7 @@ __global__ __launch_bounds__(T) void k_batch_layout(const BatchGraph* __restrict
       if (p.omega_p == 0.0) {
         cur = h;
       } else if (p.safeguard) {
-        const bool take = df <= 0.0;
+        const bool take = take_t;
         cur = take ? t : h;
         have_force = take;  // the fused pass took the force at X~
         if (!take) ++rejected;

@@ -171,8 +171,10 @@ def test_batch_2048_generator_runs_to_tol():
         tot, per = plan.run(X, omega=1.5, tol=1e-3, max_iter=3000)
     print("2048 graphs:", tot, flush=True)
     assert tot["converged"] == 1
-    # spot-check a few graphs against the oracle's iteration counts
-    for k in (0, 1, 777, 2047):
+    # spot-check graphs of every size against the oracle's iteration counts:
+    # the largest one (the launch's critical path) and 12 more across the batch
+    kmax = max(range(len(gs)), key=lambda k: gs[k].n)
+    for k in sorted({0, 1, 777, 2047, kmax, 128, 384, 640, 1024, 1280, 1536, 1792, 1999}):
         g, x0 = gs[k], xs[k]
         D = oracle.apsp(g.row_ptr, g.col_idx)
         _, io = oracle.layout(D, x0, omega=1.5, tol=1e-3, max_iter=3000)
