@@ -376,7 +376,9 @@ def bench_batch(omega, count=2048):
     t = time.perf_counter()
     plan = binding.BatchPlan(gs, 2)
     plan_s = time.perf_counter() - t
-    cfg = plan.tune(X0, omega=omega)
+    t = time.perf_counter()
+    cfg = plan.tune(X0, omega=omega, tol=1e-3, max_iter=3000)  # the workgroup size on whole runs to tol
+    tune_s = time.perf_counter() - t
     X = X0.clone()
     plan.run(X, omega=omega, tol=1e-3, max_iter=3000)  # warm (graph capture)
     X = X0.clone()
@@ -391,6 +393,7 @@ def bench_batch(omega, count=2048):
     pairs = float(np.sum(ns * (ns - 1) * its))
     return {"graphs": count, "vertices": int(ns.sum()), "pairs_per_pass": float(np.sum(ns * (ns - 1))),
             "seconds": round(wall, 4), "device_ms": round(tot["run_ms"], 3), "plan_s": round(plan_s, 3),
+            "tune_s": round(tune_s, 3),
             "pair_interactions_per_s": pairs / wall, "iterations_mean": float(its.mean()),
             "iterations_max": int(its.max()), "all_converged": bool(tot["converged"]),
             "rejected_total": int(tot["rejected"]), "tuned_config": cfg.tolist()}

@@ -357,10 +357,12 @@ typedef struct sl_batch_plan sl_batch_plan;
  * above 255 hops), SL_ENOMEM, SL_EDEVICE. */
 sl_status sl_batch_plan_create(const sl_batch* b, int32_t dim, void* stream, sl_batch_plan** out);
 
-/* Autotuner: times short runs (tol 0, min(opt->max_iter, 8) iterations) from
- * the device placement X (not modified) for workgroup sizes 256/512/1024 and,
- * per size class, the number of column slices of the all-pairs passes, and
- * keeps the fastest in the plan.  config (host, may be NULL) receives
+/* Autotuner: times runs from the device placement X (not modified) for
+ * workgroup sizes 256/512/1024 (whole runs with opt's tol and max_iter when
+ * opt->tol > 0: a launch lasts as long as its slowest graph; else short runs)
+ * and, per size class, the number of column slices of the all-pairs passes
+ * (short runs: tol 0, min(opt->max_iter, 8) iterations), and keeps the
+ * fastest in the plan.  config (host, may be NULL) receives
  * 1 + SL_BATCH_CLASSES ints: the workgroup size, then the slices per class
  * (0 for classes with no graph). */
 sl_status sl_batch_plan_tune(sl_batch_plan* plan, const float* X, const sl_options* opt, void* stream,

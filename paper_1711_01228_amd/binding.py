@@ -494,9 +494,10 @@ class BatchPlan:
             raise ValueError("X must be a contiguous cuda float32 tensor of shape (%d, %d)" % (self.args.n_total,
                                                                                           self.dim))
 
-    def tune(self, X, omega=1.5, max_iter=8, safeguard=True, stream=None) -> np.ndarray:
+    def tune(self, X, omega=1.5, max_iter=8, safeguard=True, stream=None, tol=0.0) -> np.ndarray:
+        """Autotune the launch; with tol > 0 the workgroup size is timed on whole runs to tol."""
         self._check_x(X)
-        opt = make_options(self.dim, omega, 0.0, max_iter, safeguard)
+        opt = make_options(self.dim, omega, tol, max_iter, safeguard)
         return sl_batch_plan_tune(self.handle, X.data_ptr(), opt, stream)
 
     def run(self, X, omega=1.5, tol=1e-3, max_iter=1000, safeguard=True, stream=None):

@@ -1783,6 +1783,12 @@ sl_status sl_batch_plan_tune(sl_batch_plan* p, const float* X, const sl_options*
   if (s != SL_OK) return s;
   if (p->ngraphs == 0 || p->n_total == 0) return SL_OK;
   if (!X) return fail(SL_EINVAL, "X is NULL");
+  // The workgroup size is timed on whole runs to the caller's tolerance: a
+  // launch lasts as long as its slowest graph, which short runs do not see
+  // (a graph that needs many iterations runs faster on a larger workgroup
+  // alone on its CU).  The slices per size class are timed on short runs.
+  const BatchParams bp_run = bp;
+  const bool whole = o->tol > 0.0;
   bp.tol = 0.0;
   bp.max_iter = std::max(1, std::min(o->max_iter, 8));
   const size_t xbytes = sizeof(float) * (size_t)p->n_total * p->dim;
@@ -1798,9 +1804,9 @@ sl_status sl_batch_plan_tune(sl_batch_plan* p, const float* X, const sl_options*
     (void)hipFree(tmp);
     (void)hipFree(sub);
   };
-  auto timed = [&](const int32_t* order, int count, float* ms) -> sl_status {
+  auto timed = [&](const int32_t* order, int count, const BatchParams& params, float* ms) -> sl_status {
     HIP_TRY(hipMemcpyAsync(tmp, X, xbytes, hipMemcpyDeviceToDevice, p->ps), "tuning copy");
-    return batch_time(p, tmp, order, count, bp, ms);
+    return batch_time(p, tmp, order, count, params, ms);
   };
   if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) {
     cleanup();
@@ -1814,7 +1820,7 @@ sl_status sl_batch_plan_tune(sl_batch_plan* p, const float* X, const sl_options*
     for (auto& G : p->hgraphs) G.slices = default_slices(G.n_pad, t);
     if ((s = batch_upload_graphs(p)) != SL_OK) break;
     float ms = 0.f;
-    if ((s = timed(p->order, p->ngraphs, &ms)) != SL_OK) break;
+    if ((s = timed(p->order, p->ngraphs, whole ? bp_run : bp, &ms)) != SL_OK) break;
     if (ms < best_ms) {
       best_ms = ms;
       best_t = t;
@@ -1842,7 +1848,7 @@ sl_status sl_batch_plan_tune(sl_batch_plan* p, const float* X, const sl_options*
       for (int g : members) p->hgraphs[g].slices = cand;
       if ((s = batch_upload_graphs(p)) != SL_OK) break;
       float ms = 0.f;
-      if ((s = timed(sub, (int)members.size(), &ms)) != SL_OK) break;
+      if ((s = timed(sub, (int)members.size(), bp, &ms)) != SL_OK) break;
       if (ms < best) {
         best = ms;
         best_s = cand;
