@@ -110,18 +110,22 @@ typedef enum {
                                     captured HIP graph of `check_every` iterations */
 #define SL_FLAG_SYM_FORCE 4u     /* evaluate the force pass once per unordered pair
                                     (F_j takes -c_ij (x_i - x_j), Newton's third law;
-                                    the same sums in another order).  SL_ORDER_JACOBI,
-                                    no stress trace; otherwise SL_ENOTSUP.  Hop-count
-                                    and edge-length plans.  The default, with the
-                                    Jacobi step and no stress trace, from n_pad 24576
-                                    (16384 for a run that extrapolates with the
-                                    safeguard, and for edge-length plans), in 2-D and
-                                    3-D: the faster pass there.  The first such run
-                                    allocates the pass's partial sums               */
-#define SL_FLAG_ORDERED_FORCE 16u /* evaluate the force pass over every ordered pair
-                                    from its row end (the default below those sizes,
-                                    for the exact step and for stress traces).  Not
-                                    with SL_FLAG_SYM_FORCE (SL_EINVAL)               */
+                                    the same sums in another order).  No stress trace
+                                    (SL_ENOTSUP).  Hop-count and edge-length plans.
+                                    The default, with the Jacobi step and no stress
+                                    trace, from n_pad 24576 (16384 for a run that
+                                    extrapolates with the safeguard, and for
+                                    edge-length plans), in 2-D and 3-D: the faster
+                                    pass there.  With SL_ORDER_EXACT it selects the
+                                    L^W matvec of the conjugate gradients over
+                                    unordered pairs (the default from n_pad 24576;
+                                    the force pass there stays over ordered pairs).
+                                    The first such run allocates the partial sums   */
+#define SL_FLAG_ORDERED_FORCE 16u /* evaluate the force pass (and the exact step's
+                                    L^W matvec) over every ordered pair from its row
+                                    end (the default below those sizes, for the
+                                    exact step's force pass and for stress traces).
+                                    Not with SL_FLAG_SYM_FORCE (SL_EINVAL)           */
 #define SL_FLAG_SEPARATE_SAFEGUARD 8u  /* evaluate f(X~) - f(X^H) in its own pass over
                                           unordered pairs and the next force pass
                                           after the decision.  Default (either
@@ -277,7 +281,9 @@ sl_status sl_plan_weights(sl_plan* plan, void* stream, double* W);
  *   ms[1] Jacobi update + extrapolation
  *   ms[2] safeguard pass         ms[3] select + termination test
  *   ms[4] one application of L^W (the all-pairs matvec of a conjugate-
- *         gradient step of SL_ORDER_EXACT; 0 for edge-length plans)
+ *         gradient step of SL_ORDER_EXACT, over unordered pairs with its
+ *         reduction kernel from n_pad 24576 as the step takes it; 0 for
+ *         edge-length plans)
  *   ms[5] the force pass once per unordered pair with its reduction kernel
  *         (SL_FLAG_SYM_FORCE; allocates its buffers on first use)
  *   ms[6] the force pass at X~ with the safeguard summed in (the pass that

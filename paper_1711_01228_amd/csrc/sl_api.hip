@@ -216,6 +216,7 @@ struct sl_plan {
   // exact step (allocated on first use)
   int32_t* comp = nullptr;      // lowest vertex of each vertex's component
   CgVectors cg{};               // y, r, z (columns) and p (per vertex), double
+  LwSym lw_sym{};               // the L^W matvec over unordered pairs: work items and FP64 partials
   double* cg_part = nullptr;    // (kCgSlots x cg_blocks(n_pad) + matvec blocks) x 8
   CgState* cg_st = nullptr;
   CgState* host_cg = nullptr;   // pinned mirror
@@ -242,6 +243,8 @@ sl_status free_plan_memory(sl_plan* p) {
   (void)hipFree(p->Dbar);
   (void)hipFree(p->Sbuf);
   (void)hipFree(p->Gedge);
+  (void)hipFree(p->lw_sym.Pi);
+  (void)hipFree(p->lw_sym.Pj);
   (void)hipFree(p->sym_items);
   (void)hipFree(p->sym_panel_items);
   (void)hipFree(p->Pi);
@@ -615,7 +618,8 @@ sl_status enqueue_iteration(sl_plan* p, const LoopParams& lp, const sl_options* 
 sl_status ensure_exact(sl_plan* p) {
   if (p->cg_st) return SL_OK;
   const size_t col = (size_t)3 * p->n_pad;
-  const size_t nrec = (size_t)kCgSlots * cg_blocks(p->n_pad) + (size_t)p->sp.blocks_x * p->sp.slices;
+  const size_t nrec = (size_t)kCgSlots * cg_blocks(p->n_pad) +
+                      std::max<size_t>((size_t)p->sp.blocks_x * p->sp.slices, lw_sym_reduce_blocks(p->n_pad));
   hipError_t e = hipMalloc(&p->comp, sizeof(int32_t) * p->n_pad);
   if (e == hipSuccess) e = hipMalloc(&p->cg.y, sizeof(double) * 3 * col);
   if (e == hipSuccess) e = hipMalloc(&p->cg.pd, sizeof(double) * p->stride);
@@ -638,12 +642,47 @@ sl_status ensure_exact(sl_plan* p) {
   return SL_OK;
 }
 
+// The exact step's L^W matvec over unordered pairs (hop-count plans): by
+// default in 2-D from n_pad = kLwSymMinN, where reading d once per unordered
+// pair pays for the column reductions; SL_FLAG_SYM_FORCE / SL_FLAG_ORDERED_FORCE
+// choose.
+constexpr int kLwSymMinN = 24576;
+bool lw_sym_for(const sl_plan* p, uint32_t flags) {
+  if (p->n <= 1 || p->df) return false;
+  if (flags & SL_FLAG_SYM_FORCE) return true;
+  if (flags & SL_FLAG_ORDERED_FORCE) return false;
+  return p->dim == 2 && p->n_pad >= kLwSymMinN;
+}
+
+// Its FP64 partial sums (and the force pass's work items), made on first use.
+sl_status ensure_lw_sym(sl_plan* p) {
+  if (p->lw_sym.Pi) return SL_OK;
+  sl_status s = ensure_sym(p);
+  if (s != SL_OK) return s;
+  const int rows = sym_rows_per_item();
+  const size_t npanels = ((size_t)p->n_pad + rows - 1) / rows;
+  double *Pi = nullptr, *Pj = nullptr;
+  hipError_t e = hipMalloc(&Pi, sizeof(double) * (size_t)p->nsym_items * rows * p->dim);
+  if (e == hipSuccess) e = hipMalloc(&Pj, sizeof(double) * npanels * p->n_pad * p->dim);
+  if (e != hipSuccess) {
+    (void)hipFree(Pi);
+    (void)hipFree(Pj);
+    return hip_fail(e, "unordered-pair matvec buffers");
+  }
+  p->lw_sym.items = p->sym_items;
+  p->lw_sym.nitems = p->nsym_items;
+  p->lw_sym.panel_items = p->sym_panel_items;
+  p->lw_sym.Pi = Pi;
+  p->lw_sym.Pj = Pj;
+  return SL_OK;
+}
+
 constexpr int kCgGroup = 8;  // conjugate-gradient steps per launch between host polls
 
-sl_status enqueue_cg_group(sl_plan* p, double itol, int imax) {
+sl_status enqueue_cg_group(sl_plan* p, double itol, int imax, bool lws) {
   for (int k = 0; k < kCgGroup; ++k)
     HIP_TRY(launch_cg_step(p->dim, p->cg, p->d, p->W, p->comp, p->n, p->st, p->cg_st, p->cg_part, p->fpart, p->sp,
-                           itol, imax, p->ps),
+                           itol, imax, lws ? &p->lw_sym : nullptr, p->ps),
             "conjugate-gradient kernels");
   return SL_OK;
 }
@@ -655,11 +694,13 @@ sl_status enqueue_cg_group(sl_plan* p, double itol, int imax) {
 sl_status run_exact(sl_plan* p, LoopParams lp, const sl_options* o, bool use_graph, int* inner_total) {
   sl_status s = ensure_exact(p);
   if (s != SL_OK) return s;
+  const bool lws = lw_sym_for(p, o->flags);
+  if (lws && (s = ensure_lw_sym(p)) != SL_OK) return s;
   lp.exact_y = p->cg.y;
   const double itol = o->inner_tol > 0.0 ? o->inner_tol : 1e-6;
   const int imax = o->inner_max_iter > 0 ? o->inner_max_iter : 500;
   if (use_graph) {
-    const std::vector<double> key = {(double)p->dim, itol, (double)imax};
+    const std::vector<double> key = {(double)p->dim, itol, (double)imax, lws ? 1.0 : 0.0};
     if (!p->cg_gexec || key != p->cg_gkey) {
       if (p->cg_gexec) {
         (void)hipGraphExecDestroy(p->cg_gexec);
@@ -667,7 +708,7 @@ sl_status run_exact(sl_plan* p, LoopParams lp, const sl_options* o, bool use_gra
       }
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-      const sl_status cs = enqueue_cg_group(p, itol, imax);
+      const sl_status cs = enqueue_cg_group(p, itol, imax, lws);
       const hipError_t ce = hipStreamEndCapture(p->ps, &graph);
       if (cs != SL_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -695,7 +736,7 @@ sl_status run_exact(sl_plan* p, LoopParams lp, const sl_options* o, bool use_gra
     bool stopped = false;
     for (int G = 0; G < max_groups && !stopped; ++G) {
       if (use_graph) HIP_TRY(hipGraphLaunch(p->cg_gexec, p->ps), "hipGraphLaunch");
-      else if ((s = enqueue_cg_group(p, itol, imax)) != SL_OK) return s;
+      else if ((s = enqueue_cg_group(p, itol, imax, lws)) != SL_OK) return s;
       HIP_TRY(hipMemcpyAsync(hc, p->cg_st, sizeof(CgState), hipMemcpyDeviceToHost, p->ps), "solver state download");
       HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
       stopped = hc->done != 0;
@@ -939,9 +980,9 @@ sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, s
                 : 0;
   if ((o->flags & SL_FLAG_SYM_FORCE) && (o->flags & SL_FLAG_ORDERED_FORCE))
     return fail(SL_EINVAL, "SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE exclude each other");
-  lp.sym = (o->flags & SL_FLAG_SYM_FORCE) ? 1 : 0;
-  if (lp.sym && (lp.stress || o->ordering != SL_ORDER_JACOBI))
-    return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: Jacobi ordering, no stress trace");
+  // with the exact step the flag chooses the L^W matvec (run_exact); the force pass stays ordered
+  lp.sym = (o->flags & SL_FLAG_SYM_FORCE) && o->ordering == SL_ORDER_JACOBI ? 1 : 0;
+  if ((o->flags & SL_FLAG_SYM_FORCE) && lp.stress) return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: no stress trace");
   if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !lp.stress && o->ordering == SL_ORDER_JACOBI &&
       sym_by_default(p, lp.fuse != 0))
     lp.sym = 1;
@@ -1078,6 +1119,8 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
   for (int k = 0; k < 9; ++k) ms[k] = 0.0;
   if (p->n <= 1) return SL_OK;
   if (!p->df && (s = ensure_exact(p)) != SL_OK) return s;  // the L^W matvec exists for hop-count plans
+  const bool lws = lw_sym_for(p, 0);  // the exact step's default matvec
+  if (lws && (s = ensure_lw_sym(p)) != SL_OK) return s;
   LoopParams lp{};
   lp.n = p->n;
   lp.n_pad = p->n_pad;
@@ -1112,9 +1155,14 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
       if (r == 0) HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
       switch (which) {
         case 4:
-          HIP_TRY(launch_lw(p->dim, p->cg, p->d, p->W, p->st, p->cg_st, p->fpart,
-                            p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->sp, p->ps),
-                  "L^W kernel");
+          if (lws)
+            HIP_TRY(launch_lw_sym(p->dim, p->cg.pd, p->d, p->W, p->st, p->cg_st, p->lw_sym, p->fpart,
+                                  p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->n_pad, p->ps),
+                    "L^W kernels");
+          else
+            HIP_TRY(launch_lw(p->dim, p->cg, p->d, p->W, p->st, p->cg_st, p->fpart,
+                              p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->sp, p->ps),
+                    "L^W kernel");
           break;
         case 0:
           if ((s = enqueue_force(p, lp)) != SL_OK) return s;

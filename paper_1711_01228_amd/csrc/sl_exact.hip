@@ -335,17 +335,19 @@ hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double
 
 hipError_t launch_cg_step(int dim, const CgVectors& v, const uint8_t* d, const double* W, const int32_t* comp, int n,
                           const DevState* st, CgState* cg, double* part, double* qpart, const Split& sp, double tol,
-                          int max_steps, hipStream_t s) {
+                          int max_steps, const LwSym* sym, hipStream_t s) {
   const int nblk = cg_blocks(v.n_pad);
   double* pqrec = part + (size_t)kCgSlots * nblk * 8;
-  const int npq = sp.blocks_x * sp.slices;
-  hipError_t e = launch_lw(dim, v, d, W, st, cg, qpart, pqrec, sp, s);
+  const int npq = sym ? (int)lw_sym_reduce_blocks(v.n_pad) : sp.blocks_x * sp.slices;
+  const int slices = sym ? 1 : sp.slices;
+  hipError_t e = sym ? launch_lw_sym(dim, v.pd, d, W, st, cg, *sym, qpart, pqrec, v.n_pad, s)
+                     : launch_lw(dim, v, d, W, st, cg, qpart, pqrec, sp, s);
   if (e != hipSuccess) return e;
   if (dim == 2) {
-    k_cg_update<2><<<nblk, 256, 0, s>>>(v, W, comp, n, qpart, sp.slices, st, cg, part, nblk, pqrec, npq);
+    k_cg_update<2><<<nblk, 256, 0, s>>>(v, W, comp, n, qpart, slices, st, cg, part, nblk, pqrec, npq);
     k_cg_dir<2><<<nblk, 256, 0, s>>>(v, st, cg, part, nblk, tol * tol, max_steps);
   } else {
-    k_cg_update<3><<<nblk, 256, 0, s>>>(v, W, comp, n, qpart, sp.slices, st, cg, part, nblk, pqrec, npq);
+    k_cg_update<3><<<nblk, 256, 0, s>>>(v, W, comp, n, qpart, slices, st, cg, part, nblk, pqrec, npq);
     k_cg_dir<3><<<nblk, 256, 0, s>>>(v, st, cg, part, nblk, tol * tol, max_steps);
   }
   return hipGetLastError();

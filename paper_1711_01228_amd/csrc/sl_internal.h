@@ -127,10 +127,12 @@ struct Split {
   int blocks_x;         // workgroups along rows (4 waves each)
 };
 Split make_split(int n_pad);
-// One step: matvec (with the stop test), p/q update, Y/r/z update.
+struct LwSym;
+// One step: matvec (with the stop test), p/q update, Y/r/z update; the matvec
+// over unordered pairs when `sym` is given.
 hipError_t launch_cg_step(int dim, const CgVectors& v, const uint8_t* d, const double* W, const int32_t* comp, int n,
                           const DevState* st, CgState* cg, double* part, double* qpart, const Split& sp, double tol,
-                          int max_steps, hipStream_t s);
+                          int max_steps, const LwSym* sym, hipStream_t s);
 // Force pass over unordered pairs (sl_sym.hip): work items (panel of 8 row
 // strips, first and end column strip, item index), the items of each panel
 // contiguous.
@@ -161,6 +163,20 @@ unsigned sym_reduce_blocks(int n_pad);
 // One application of L^W to p (also used by the profiler).
 hipError_t launch_lw(int dim, const CgVectors& v, const uint8_t* d, const double* W, const DevState* st, CgState* cg,
                      double* qpart, double* pqrec, const Split& sp, hipStream_t s);
+// The same over unordered pairs (sl_sym.hip): the force pass's work items, FP64
+// row partials Pi (items x sym_rows_per_item() x dim) and column partials Pj
+// (panels x n_pad x dim); q into slice 0 of qpart and lw_sym_reduce_blocks(n_pad)
+// p.q records into pqrec.
+struct LwSym {
+  const int4* items = nullptr;
+  int nitems = 0;
+  const int32_t* panel_items = nullptr;
+  double* Pi = nullptr;
+  double* Pj = nullptr;
+};
+unsigned lw_sym_reduce_blocks(int n_pad);
+hipError_t launch_lw_sym(int dim, const double* pd, const uint8_t* d, const double* W, const DevState* st, CgState* cg,
+                         const LwSym& ls, double* qpart, double* pqrec, int n_pad, hipStream_t s);
 
 // ---- launchers (sl_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_fill_u8(uint8_t* p, size_t bytes, hipStream_t s);

@@ -79,6 +79,28 @@ __device__ __forceinline__ float reduce_scatter(VF R, int lane) {
   return t;
 }
 
+// The same reduce-scatter for FP64 elements (the L^W matvec of the exact step).
+typedef double vd16 __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ double reduce_scatter_d16(vd16 R, int lane) {
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int bit = 5 - step;
+    const int half = 8 >> step;
+    const bool up = (lane >> bit) & 1;
+#pragma unroll
+    for (int r = 0; r < half; ++r) {
+      const double lo = R[r], hi = R[r + half];
+      const double send = up ? lo : hi;
+      const double keep = up ? hi : lo;
+      R[r] = keep + __shfl_xor(send, 1 << bit, 64);
+    }
+  }
+  double t = R[0];
+#pragma unroll
+  for (int bit = 1; bit >= 0; --bit) t += __shfl_xor(t, 1 << bit, 64);
+  return t;
+}
+
 // Gates of the pass (the state decides at run time which launches do work).
 constexpr int kGateNone = 0;    // always
 constexpr int kGateForce = 1;   // only when the force at X^H is still needed (after a rejection)
@@ -356,6 +378,167 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const float* __restrict__ Pi
   }
 }
 
+// L^W p over unordered pairs, for the exact step's conjugate gradients (eq. 5):
+// S_i = sum_{j != i} w_ij p_j with w = 1/d^2 = w_ji, so each unordered pair
+// i < j gives w p_j to row i and w p_i to row j.  The work items, the strips and
+// the tile-major chunks of d are those of the force pass; every product and sum
+// is FP64 (an FP32 matvec stalls CG, see the exact step), the column totals of a
+// group by the reduce-scatter, the row sums in LDS.  Row partials go out once
+// per (item, row), column partials once per (panel, column), both FP64, and
+// k_lw_sym_reduce forms q_i = W_i p_i - S_i.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_lw_sym(const uint8_t* __restrict__ d, const double* __restrict__ pdb,
+                                                const DevState* __restrict__ st, const CgState* __restrict__ cg,
+                                                const int4* __restrict__ items, int nitems, double* __restrict__ Pi,
+                                                double* __restrict__ Pj, int nb, int ng, int n_pad) {
+  using P = std::conditional_t<DIM == 2, double2, double4>;
+  __shared__ double lut[256];
+  __shared__ double rows[kWaves][kPanel][DIM][64];  // each wave's FP64 row sums of its strips
+  if (st->done || cg->done) return;
+  lut[threadIdx.x] = threadIdx.x ? 1.0 / ((double)threadIdx.x * (double)threadIdx.x) : 0.0;
+  __syncthreads();  // the weight table; the waves are independent from here on
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int w_item = blockIdx.x * kWaves + wave;
+  if (w_item >= nitems) return;
+  const int4 it = items[w_item];
+  const int panel = it.x, g0 = it.y, g1 = it.z, item = it.w;
+  const P* __restrict__ Pv = reinterpret_cast<const P*>(pdb);
+  const int nstrips = min(kPanel, nb - panel * kPanel);
+  double (*racc)[DIM][64] = rows[wave];
+  for (int r = 0; r < kPanel; ++r)
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) racc[r][c][lane] = 0.0;
+
+  for (int g = g0; g < g1; ++g) {
+    const int jlo = g * kColGroup;
+    const P* __restrict__ pj = Pv + jlo;
+    vd16 Cx = {}, Cy = {}, Cz = {};  // per-lane column sums of the group over the panel's strips
+    const int rlast = min(nstrips, (jlo + kColGroup - 1) / 64 - panel * kPanel + 1);
+    const int rfull = max(0, min(rlast, jlo / 64 - panel * kPanel));
+    auto strips = [&](auto mask_tag, int ra, int rb) {
+      constexpr bool MASK = decltype(mask_tag)::value;
+      if (ra >= rb) return;
+      uint4 q = load_chunk<false>(d, nullptr, panel * kPanel + ra, ng, g, lane);
+#pragma unroll 1
+      for (int r = ra; r < rb; ++r) {
+        const int ilo = (panel * kPanel + r) * 64;
+        // the next strip's chunk loads while this one computes
+        const uint4 qn = load_chunk<false>(d, nullptr, panel * kPanel + (r + 1 < rb ? r + 1 : r), ng, g, lane);
+        const P pi = Pv[ilo + lane];
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kColGroup; ++k) {
+          // 16 columns' FP64 p_j (lane-uniform, scalar registers) do not fit at
+          // once: each half (quarter in 3-D) loads after the previous one's work
+          if (k % (DIM == 3 ? kColGroup / 4 : kColGroup / 2) == 0) asm volatile("" ::: "memory");
+          double w = lut[byte_of(chunk_word(q, k), k & 3)];
+          if constexpr (MASK) {
+            if (jlo + k <= ilo + lane) w = 0.0;  // the pairs j <= i of a diagonal group
+          }
+          const P pv = pj[k];
+          q0 = fma(w, pv.x, q0);
+          q1 = fma(w, pv.y, q1);
+          Cx[k] = fma(w, pi.x, Cx[k]);
+          Cy[k] = fma(w, pi.y, Cy[k]);
+          if constexpr (DIM == 3) {
+            q2 = fma(w, pv.z, q2);
+            Cz[k] = fma(w, pi.z, Cz[k]);
+          }
+        }
+        racc[r][0][lane] += q0;
+        racc[r][1][lane] += q1;
+        if constexpr (DIM == 3) racc[r][2][lane] += q2;
+        q = qn;
+      }
+    };
+    strips(std::false_type{}, 0, rfull);
+    strips(std::true_type{}, rfull, rlast);
+    // the group's column totals over the panel: lane l holds column l >> 2
+    double* pjo = Pj + ((size_t)panel * n_pad + jlo) * DIM;
+    const double tx = reduce_scatter_d16(Cx, lane), ty = reduce_scatter_d16(Cy, lane);
+    if ((lane & 3) == 0) {
+      pjo[(lane >> 2) * DIM] = tx;
+      pjo[(lane >> 2) * DIM + 1] = ty;
+    }
+    if constexpr (DIM == 3) {
+      const double tz = reduce_scatter_d16(Cz, lane);
+      if ((lane & 3) == 0) pjo[(lane >> 2) * DIM + 2] = tz;
+    }
+  }
+  for (int r = 0; r < nstrips; ++r) {
+    double* out = Pi + ((size_t)item * kPanel * 64 + (size_t)r * 64 + lane) * DIM;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) out[c] = racc[r][c][lane];
+  }
+}
+
+// q_i = W_i p_i - S_i, S_i = the row partials of the items of i's panel plus the
+// column partials of panels 0 .. panel(i) (16 lanes per vertex, each over a
+// fixed stride, then a fixed butterfly; a workgroup takes 64 vertices in four
+// rounds), into slice 0 of qpart (column c at c n_pad), and the workgroup's
+// record of sum_i p_i q_i per column.  The first workgroup also starts the
+// step's counter (cg->ja = cg->jb), as the ordered matvec does.
+constexpr int kLwReduceVertices = 64;
+template <int DIM>
+__global__ __launch_bounds__(256) void k_lw_sym_reduce(const double* __restrict__ Pi, const double* __restrict__ Pj,
+                                                       const int32_t* __restrict__ panel_items,
+                                                       const double* __restrict__ pdb, const double* __restrict__ W,
+                                                       const DevState* __restrict__ st, CgState* __restrict__ cg,
+                                                       double* __restrict__ qpart, double* __restrict__ pqrec,
+                                                       int n_pad) {
+  using P = std::conditional_t<DIM == 2, double2, double4>;
+  __shared__ double sh[3][4];
+  __shared__ double tot[3];
+  if (st->done || cg->done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cg->ja = cg->jb;
+  const int t = threadIdx.x % kReduceLanes, grp = threadIdx.x / kReduceLanes;
+  double pq[3] = {0.0, 0.0, 0.0};
+  for (int round = 0; round < kLwReduceVertices / (256 / kReduceLanes); ++round) {
+    const int i = blockIdx.x * kLwReduceVertices + round * (256 / kReduceLanes) + grp;
+    const bool live = i < n_pad;
+    const int ii = live ? i : 0;
+    const int strip = ii / 64, panel = strip / kPanel, row = ii % (kPanel * 64);
+    double acc[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
+    if (live) {
+      for (int q = panel_items[panel] + t; q < panel_items[panel + 1]; q += kReduceLanes) {
+        const double* p = Pi + ((size_t)q * kPanel * 64 + row) * DIM;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += p[c];
+      }
+      for (int p = t; p <= panel; p += kReduceLanes) {
+        const double* col = Pj + ((size_t)p * n_pad + ii) * DIM;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] += col[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int off = kReduceLanes / 2; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    if (live && t == 0) {
+      const P pv = reinterpret_cast<const P*>(pdb)[i];
+      double pc[3] = {pv.x, pv.y, 0.0};
+      if constexpr (DIM == 3) pc[2] = pv.z;
+      const double Wi = W[i];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        const double q = Wi * pc[c] - acc[c];
+        qpart[(size_t)c * n_pad + i] = q;
+        pq[c] += pc[c] * q;
+      }
+    }
+  }
+  block_sum_waves<3, 4>(pq, sh, tot);
+  if (threadIdx.x == 0) {
+    double* rec = pqrec + (size_t)blockIdx.x * 8;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rec[k] = pq[k];
+    for (int k = 3; k < 8; ++k) rec[k] = 0.0;
+  }
+}
+
 template <int DIM, int SG, bool FD>
 void sym_launch(const LoopParams* lp, int gate, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                 const float* Eb, const DevState* st, const int4* items, int nitems, const int32_t* panel_items,
@@ -419,6 +602,24 @@ hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df
                             float* Pj, double* fpart, int n_pad, hipStream_t s) {
   sym_dispatch<0>(dim, nullptr, cond ? kGateForce : kGateNone, d, df, Xb, stride, nullptr, st, items, nitems,
                   panel_items, Pi, Pj, nullptr, fpart, nullptr, n_pad, s);
+  return hipGetLastError();
+}
+
+unsigned lw_sym_reduce_blocks(int n_pad) { return (unsigned)((n_pad + kLwReduceVertices - 1) / kLwReduceVertices); }
+
+hipError_t launch_lw_sym(int dim, const double* pd, const uint8_t* d, const double* W, const DevState* st, CgState* cg,
+                         const LwSym& ls, double* qpart, double* pqrec, int n_pad, hipStream_t s) {
+  const int nb = n_pad / 64, ng = n_pad / kColGroup;
+  const unsigned blocks = (unsigned)((ls.nitems + kWaves - 1) / kWaves);
+  if (dim == 2) {
+    k_lw_sym<2><<<blocks, kWaves * 64, 0, s>>>(d, pd, st, cg, ls.items, ls.nitems, ls.Pi, ls.Pj, nb, ng, n_pad);
+    k_lw_sym_reduce<2><<<lw_sym_reduce_blocks(n_pad), 256, 0, s>>>(ls.Pi, ls.Pj, ls.panel_items, pd, W, st, cg, qpart,
+                                                                   pqrec, n_pad);
+  } else {
+    k_lw_sym<3><<<blocks, kWaves * 64, 0, s>>>(d, pd, st, cg, ls.items, ls.nitems, ls.Pi, ls.Pj, nb, ng, n_pad);
+    k_lw_sym_reduce<3><<<lw_sym_reduce_blocks(n_pad), 256, 0, s>>>(ls.Pi, ls.Pj, ls.panel_items, pd, W, st, cg, qpart,
+                                                                   pqrec, n_pad);
+  }
   return hipGetLastError();
 }
 

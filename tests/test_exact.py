@@ -65,28 +65,34 @@ def graphs():
         "er300_sparse": inputs.erdos_renyi(300, 280, 7),  # many components and isolated vertices
         "tree500": inputs.random_tree(500, 3),
         "ragged_129": inputs.erdos_renyi(129, 400, 5),
+        "ba1500": inputs.barabasi_albert(1500, 3, 11),  # several panels of the unordered matvec
     }
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("sym", [False, True])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("name", sorted(graphs()))
-def test_one_exact_step(name, dim):
+def test_one_exact_step(name, dim, sym):
+    """One exact step against the oracle's Cholesky solve of eq. 5, with the
+    conjugate gradients' L^W matvec over every ordered pair and (sym) over
+    unordered pairs."""
     b = _binding()
     g = graphs()[name]
-    print("case", name, dim, flush=True)
+    print("case", name, dim, "unordered matvec" if sym else "ordered matvec", flush=True)
     X0 = inputs.uniform_positions(g.n, dim, seed=78, lo=0.0, hi=float(np.sqrt(g.n)))
     D = oracle.apsp(g.row_ptr, g.col_idx)
     XH = oracle.h_exact(D, X0)
     X = dev(X0)
     with b.Plan(g, dim) as plan:
-        info = plan.run(X, omega=1.0, tol=0.0, max_iter=1, ordering="exact", inner_tol=1e-6, inner_max_iter=500)
+        info = plan.run(X, omega=1.0, tol=0.0, max_iter=1, ordering="exact", inner_tol=1e-6, inner_max_iter=500,
+                        sym_force=sym)
     assert info["iterations"] == 1 and 0 < info["inner_iterations"] < 500, info
     err = np.abs(X.cpu().numpy().astype(np.float64) - XH).max()
     assert err <= 2e-5 * diam(X0), err
 
 
-def _compare(g, X0, omega, iters, dim=2, safeguard=True):
+def _compare(g, X0, omega, iters, dim=2, safeguard=True, sym=False):
     b = _binding()
     D = oracle.apsp(g.row_ptr, g.col_idx)
     Xo, io = oracle.layout(D, X0, omega=omega, tol=0.0, max_iter=iters, ordering="exact", safeguard=safeguard,
@@ -94,7 +100,7 @@ def _compare(g, X0, omega, iters, dim=2, safeguard=True):
     X = dev(X0)
     with b.Plan(g, dim) as plan:
         ig = plan.run(X, omega=omega, tol=0.0, max_iter=iters, safeguard=safeguard, ordering="exact", trace=True,
-                      trace_positions=True)
+                      trace_positions=True, sym_force=sym)
     assert ig["iterations"] == io["iterations"] == iters
     tg, to = ig["trace"], io["trace"]
     Pg, Po = ig["positions"].astype(np.float64), io["positions"]
@@ -110,22 +116,24 @@ def _compare(g, X0, omega, iters, dim=2, safeguard=True):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("sym", [False, True])
 @pytest.mark.parametrize("omega", [1.0, 1.5])
-def test_grid16_exact_free_run(omega):
+def test_grid16_exact_free_run(omega, sym):
     g, X0 = inputs.grid16(0)
-    print("case grid16 exact omega", omega, flush=True)
-    compared, ig, io = _compare(g, X0, omega, 60)
+    print("case grid16 exact omega", omega, "unordered matvec" if sym else "", flush=True)
+    compared, ig, io = _compare(g, X0, omega, 60, sym=sym)
     assert compared >= 40
     assert ig["inner_iterations"] > 60
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("sym", [False, True])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_ppi_exact_free_run_with_rejections(dim):
+def test_ppi_exact_free_run_with_rejections(dim, sym):
     g = ppi_graph()
     X0 = inputs.uniform_positions(g.n, dim, seed=5)
-    print("case ppi exact omega 2.6 dim", dim, flush=True)
-    compared, ig, io = _compare(g, X0, 2.6, 40, dim=dim)
+    print("case ppi exact omega 2.6 dim", dim, "unordered matvec" if sym else "", flush=True)
+    compared, ig, io = _compare(g, X0, 2.6, 40, dim=dim, sym=sym)
     assert compared >= 20
 
 

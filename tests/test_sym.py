@@ -89,7 +89,7 @@ def test_unordered_pass_is_refused_where_it_does_not_apply():
 
     g, X0 = inputs.grid16(0)
     with b.Plan(g, 2) as plan:
-        for kw in ({"trace_stress": True}, {"ordering": "exact"}):
+        for kw in ({"trace_stress": True}, {"trace_stress": True, "ordering": "exact"}):
             with pytest.raises(b.SlError) as e:
                 plan.run(dev(X0), max_iter=2, sym_force=True, **kw)
             assert e.value.status == b.SL_ENOTSUP
