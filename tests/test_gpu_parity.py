@@ -129,6 +129,32 @@ def test_distances_er4096_and_ba65536_sampled(sl):
         np.testing.assert_allclose(W[rows], w, rtol=1e-12)
 
 
+def test_distances_four_sweeps_and_a_deeper_last_sweep(sl):
+    """Four sweeps queued after the first one's depth: the last sweep (two paths
+    of 7 hung on the star's centre and on a leaf) is 15 levels deep where the
+    first is 9, so it is redone after the others.  Sampled rows bit-exact
+    against the oracle's BFS, W to rounding."""
+    S = SWEEP
+    n_leaves = 3 * S - 1
+    edges = [(0, k) for k in range(1, n_leaves + 1)]
+    p0 = n_leaves + 1                       # path P from the centre
+    edges += [(0, p0)] + [(p0 + k, p0 + k + 1) for k in range(6)]
+    q0 = p0 + 7                             # path Q from leaf 1
+    edges += [(1, q0)] + [(q0 + k, q0 + k + 1) for k in range(6)]
+    n = q0 + 7
+    g = inputs.to_csr(n, edges)
+    print("case star_two_paths", n, flush=True)
+    rows = np.unique(np.concatenate([np.arange(0, n, 997), [0, 1, 2, S, 2 * S, 3 * S - 1, p0, p0 + 6, q0, q0 + 6,
+                                                            n - 1]]))
+    D = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
+    assert D[np.searchsorted(rows, p0 + 6)].max() == 15 and D[np.searchsorted(rows, 2)].max() == 9
+    with sl.Plan(g, 2) as plan:
+        np.testing.assert_array_equal(plan.distance_rows(rows), as_u8(D))
+        W = plan.weights()
+    w = np.where((D > 0) & np.isfinite(D), 1.0 / np.where(D > 0, D, 1.0) ** 2, 0.0).sum(1)
+    np.testing.assert_allclose(W[rows], w, rtol=1e-12)
+
+
 def test_distance_above_255_hops_is_refused(sl):
     g = inputs.path_graph(300)
     with pytest.raises(sl.SlError) as e:
