@@ -298,7 +298,7 @@ def bench_small_configs(seeds=20, full_oracle=False):
     # ---- grid 16 x 16, 200 iterations
     c1 = {}
     for om in (1.0, 1.5):
-        us, wall = [], []
+        us, wall, us_wg = [], [], []
         for r in range(seeds):
             g, X0 = inputs.grid16(r)
             Xd0 = torch.tensor(X0.astype(np.float32), device="cuda")
@@ -311,9 +311,15 @@ def bench_small_configs(seeds=20, full_oracle=False):
                 torch.cuda.synchronize()
                 wall.append(time.perf_counter() - t)
                 us.append(1e3 * info["run_ms"] / info["iterations"])
+            # the same 200 iterations inside one workgroup (the batched layout of one graph)
+            with binding.BatchPlan([g], 2) as bplan:
+                bplan.run(Xd0.clone(), omega=om, tol=0.0, max_iter=200)
+                tot, _ = bplan.run(Xd0.clone(), omega=om, tol=0.0, max_iter=200)
+                us_wg.append(1e3 * tot["run_ms"] / max(tot["iterations"], 1))
         c1["omega=%g" % om] = {"us_per_iteration_median": round(float(np.median(us)), 2),
                                "us_per_iteration_range": [round(float(min(us)), 2), round(float(max(us)), 2)],
-                               "seconds_200_iterations_median": round(float(np.median(wall)), 5)}
+                               "seconds_200_iterations_median": round(float(np.median(wall)), 5),
+                               "one_workgroup_us_per_iteration_median": round(float(np.median(us_wg)), 2)}
     out["grid16"] = c1
     # ---- Erdos-Renyi n = 4096 to tol
     c2 = {}
