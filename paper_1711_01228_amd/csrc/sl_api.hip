@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace sl;
@@ -330,37 +331,47 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
   if (p->df) return build_weighted(p);
   if (n > 1 && g->nnz > 0) {
     if (g->nnz > (int64_t)INT32_MAX) return fail(SL_ERANGE, "more than 2^31 - 1 CSR entries");
-    // the gather's runs (whole rows of at most bfs_run_entries() entries packed
+    // The gather's runs (whole rows of at most bfs_run_entries() entries packed
     // together) and the rows that take a wave or a workgroup each (longer ones,
-    // and isolated vertices)
+    // and isolated vertices), packed on a host thread of their own while this
+    // one allocates the buffers (sized for at most n of each) and sends the CSR.
     std::vector<int4> runs;
     std::vector<int4> longrows;
-    const int run_max = bfs_run_entries();
-    int4 open_run = make_int4(0, 0, 0, 0);
-    for (int v = 0; v < n; ++v) {
-      const int64_t b0 = g->row_ptr[v], deg = g->row_ptr[v + 1] - b0;
-      if (deg == 0 || deg > run_max) {
-        longrows.push_back(make_int4(v, (int)b0, (int)deg, 0));
-        if (deg > 0 && open_run.y > 0) {  // a run holds consecutive CSR entries: close it before this row's
-          runs.push_back(open_run);
-          open_run.y = 0;
+    const int run_max = bfs_run_entries(), mid_max = bfs_mid_max_degree();
+    int nbig = 0;
+    auto pack = [&]() {
+      int4 open_run = make_int4(0, 0, 0, 0);
+      for (int v = 0; v < n; ++v) {
+        const int64_t b0 = g->row_ptr[v], deg = g->row_ptr[v + 1] - b0;
+        if (deg == 0 || deg > run_max) {
+          longrows.push_back(make_int4(v, (int)b0, (int)deg, 0));
+          if (deg > 0 && open_run.y > 0) {  // a run holds consecutive CSR entries: close it before this row's
+            runs.push_back(open_run);
+            open_run.y = 0;
+          }
+        } else {
+          if (open_run.y > 0 && open_run.y + deg > run_max) {
+            runs.push_back(open_run);
+            open_run.y = 0;
+          }
+          if (open_run.y == 0) open_run = make_int4((int)b0, 0, v, 0);
+          open_run.y += (int)deg;
         }
-      } else {
-        if (open_run.y > 0 && open_run.y + deg > run_max) {
-          runs.push_back(open_run);
-          open_run.y = 0;
-        }
-        if (open_run.y == 0) open_run = make_int4((int)b0, 0, v, 0);
-        open_run.y += (int)deg;
       }
+      if (open_run.y > 0) runs.push_back(open_run);
+      // the rows above the middle degree first (a workgroup each), then the others (a wave each)
+      std::stable_partition(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
+      nbig = (int)std::count_if(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
+    };
+    std::thread packer;
+    try {
+      packer = std::thread(pack);
+    } catch (...) {
+      pack();  // no thread to be had: pack here
     }
-    if (open_run.y > 0) runs.push_back(open_run);
-    // the rows above the middle degree first (a workgroup each), then the others (a wave each)
-    const int mid_max = bfs_mid_max_degree();
-    std::stable_partition(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
-    const int nbig = (int)std::count_if(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
-    const int nmid = (int)longrows.size() - nbig;
-    const int nruns = (int)runs.size();
+    auto join = [&]() {
+      if (packer.joinable()) packer.join();
+    };
     const size_t words = (size_t)n * bfs_words();
     const int nslots = bfs_slots();
     const int sweep = bfs_sources_per_sweep();
@@ -374,8 +385,9 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       return at;
     };
     const size_t o_ci = part(sizeof(int32_t) * g->nnz), o_rp = part(sizeof(int64_t) * (n + 1)),
-                 o_rn = part(sizeof(int4) * nruns), o_pairs = part(sizeof(int2) * (size_t)nruns * run_max),
-                 o_lrows = part(sizeof(int4) * longrows.size()), o_slots = part(sizeof(uint64_t) * words * nslots),
+                 o_rn = part(sizeof(int4) * n), o_pairs = part(sizeof(int2) * (size_t)n * run_max),
+                 o_lrows = part(sizeof(int4) * n), o_slots = part(sizeof(uint64_t) * words * nslots),
+                 o_masks = part(sizeof(uint64_t) * (size_t)n * nslots),
                  o_flag = part(sizeof(int32_t) * kStride * nsweeps),
                  o_wq = part(sizeof(double) * (size_t)bfs_weight_partials() * p->n_pad);
     char* buf = nullptr;
@@ -385,18 +397,25 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       (void)hipFree(buf);
     };
     hipError_t e = hipMalloc(&buf, off);
-    if (e != hipSuccess) return hip_fail(e, "distance buffers");
+    if (e != hipSuccess) {
+      join();
+      return hip_fail(e, "distance buffers");
+    }
     int32_t* ci = reinterpret_cast<int32_t*>(buf + o_ci);
     int64_t* rp = reinterpret_cast<int64_t*>(buf + o_rp);
     int4* rn = reinterpret_cast<int4*>(buf + o_rn);
     int2* pairs = reinterpret_cast<int2*>(buf + o_pairs);
     int4* lrows = reinterpret_cast<int4*>(buf + o_lrows);
     uint64_t* slots = reinterpret_cast<uint64_t*>(buf + o_slots);
+    uint64_t* masks = reinterpret_cast<uint64_t*>(buf + o_masks);
     int32_t* flag = reinterpret_cast<int32_t*>(buf + o_flag);
     double* wq = reinterpret_cast<double*>(buf + o_wq);
     int32_t* hflag = p->host_flags;
     e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMemcpyAsync(rp, g->row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, p->ps);
+    join();
+    const int nruns = (int)runs.size();
+    const int nmid = (int)longrows.size() - nbig;
     if (e == hipSuccess && nruns > 0)
       e = hipMemcpyAsync(rn, runs.data(), sizeof(int4) * nruns, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess && !longrows.empty())
@@ -415,10 +434,10 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       int32_t* fl = flag + (size_t)sw * kStride;
       hipError_t le = hipSuccess;
       for (int level = l0; level <= l1 && le == hipSuccess; ++level)
-        le = launch_bfs_level(pairs, nruns, lrows, nbig, nmid, ci, slots, n, sw * sweep, level, fl, p->ps);
+        le = launch_bfs_level(pairs, nruns, lrows, nbig, nmid, ci, slots, masks, n, sw * sweep, level, fl, p->ps);
       // level 256 is not stored: it only tells whether a distance exceeds 255
       if (le == hipSuccess)
-        le = launch_bfs_store(slots, fl, p->d, wq, n, p->n_pad, sw * sweep, l0, std::min(l1, kBfsMaxLevel - 1),
+        le = launch_bfs_store(slots, masks, fl, p->d, wq, n, p->n_pad, sw * sweep, l0, std::min(l1, kBfsMaxLevel - 1),
                               count_from, p->ps);
       return le;
     };

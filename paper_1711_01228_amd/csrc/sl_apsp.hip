@@ -7,7 +7,10 @@
 // the level l-1 frontier F and finds N_l(v) = (OR of F over v's neighbours)
 // & ~(N_{l-1}(v) | N_{l-2}(v)), the sources that reach v first at level l (no
 // visited set: see bfs_settle).  N_l is kept in level slot l mod kBfsSlots and
-// is the next frontier.
+// is the next frontier.  Beside each slot, one 64-bit mask per vertex marks the
+// 16-byte chunks of its row that are not zero; only those chunks are written,
+// and every reader loads a chunk only where its bit is set (the frontier is
+// sparse at the first and last levels of a sweep).
 //   k_bfs_gather  one wave per run of at most 16 CSR entries (built with the
 //                 plan), each lane reading 16 bytes of a neighbour's 1 KiB
 //                 frontier row per entry, all 16 loads in flight (level 1
@@ -43,6 +46,8 @@ constexpr int kGatherRun = 16;                // CSR entries per lane group
 constexpr int kWaveEntries = kGatherGroups * kGatherRun;  // CSR entries a wave takes per pass
 static_assert(kGatherRun <= kGatherLanes && kWaveEntries <= 64, "a group's entries sit in its own lanes");
 constexpr int kStoreWords = 8;                // words per row in one store block
+constexpr int kXcds = 8;                      // workgroup b runs on XCD b mod 8
+constexpr int kStoreBlocksPerLine = 128 / (8 * kStoreWords);  // word blocks of one 128-byte line
 
 inline unsigned blocks_for(size_t items) { return (unsigned)((items + 255) / 256); }
 
@@ -55,27 +60,43 @@ __device__ __forceinline__ ulonglong2 source_chunk(int u, int wl, int base) {
   return (sb & 64) ? make_ulonglong2(0ull, bit) : make_ulonglong2(bit, 0ull);
 }
 
+// Chunk wl (16 bytes) of row v of a level slot whose chunk masks are M: zero
+// unless the chunk's bit is set (the other chunks are not written).
+__device__ __forceinline__ ulonglong2 masked_chunk(const ulonglong2* __restrict__ S, const uint64_t* __restrict__ M,
+                                                   int v, int wl) {
+  if (((M[v] >> wl) & 1ull) == 0) return make_ulonglong2(0ull, 0ull);
+  return S[(size_t)v * (kBfsWords / 2) + wl];
+}
+
 // N_l for the two words (one 16-byte chunk q of vertex v) a lane holds of a
 // row: the OR a of the neighbours' level l-1 bits without v's own bits of levels
 // l-1 and l-2.  On an undirected graph a neighbour's distance from a source
 // differs from v's by at most one, so a source in a is at distance l-2, l-1 or
 // l from v, and the last exactly when it is in neither of v's two previous
-// levels: no visited set is kept.  `found` is set when N_l is not empty (the
-// wave raises the level's flag once).
-__device__ __forceinline__ void bfs_settle(const ulonglong2* __restrict__ F, const ulonglong2* __restrict__ P2,
-                                          ulonglong2* __restrict__ slot, int v, int wl, int level, int base,
-                                          uint64_t a0, uint64_t a1, bool& found) {
-  const size_t q = (size_t)v * (kBfsWords / 2) + wl;
+// levels: no visited set is kept.  The whole wave calls this for one v (its 64
+// lanes are the row's 64 chunks): the chunks that are not zero are stored and
+// their mask written.  `found` is set when N_l is not empty (the wave raises
+// the level's flag once).
+__device__ __forceinline__ void bfs_settle(const ulonglong2* __restrict__ F, const uint64_t* __restrict__ M1,
+                                          const ulonglong2* __restrict__ P2, const uint64_t* __restrict__ M2,
+                                          ulonglong2* __restrict__ slot, uint64_t* __restrict__ mout, int v, int wl,
+                                          int level, int base, uint64_t a0, uint64_t a1, bool& found) {
   ulonglong2 nw = make_ulonglong2(0ull, 0ull);
   if (a0 | a1) {
     // v's bits of levels l-1 and l-2 (level 0: the sources)
-    const ulonglong2 p1 = level == 1 ? source_chunk(v, wl, base) : F[q];
-    const ulonglong2 p2 = level == 1 ? make_ulonglong2(0ull, 0ull)
-                          : level == 2 ? source_chunk(v, wl, base) : P2[q];
+    const ulonglong2 p1 = level == 1 ? source_chunk(v, wl, base) : masked_chunk(F, M1, v, wl);
+    const ulonglong2 p2 = level == 1   ? make_ulonglong2(0ull, 0ull)
+                          : level == 2 ? source_chunk(v, wl, base)
+                                       : masked_chunk(P2, M2, v, wl);
     nw = make_ulonglong2(a0 & ~(p1.x | p2.x), a1 & ~(p1.y | p2.y));
-    if (nw.x | nw.y) found = true;
   }
-  slot[q] = nw;
+  const bool nz = (nw.x | nw.y) != 0ull;
+  const uint64_t m = __ballot(nz);
+  if (nz) {
+    slot[(size_t)v * (kBfsWords / 2) + wl] = nw;
+    found = true;
+  }
+  if (wl == 0) mout[v] = m;
 }
 
 // flags[level] = 1, stored by one lane of the wave where any lane found a new
@@ -85,33 +106,67 @@ __device__ __forceinline__ void raise_flag(bool found, int32_t* __restrict__ fla
   if (found && (threadIdx.x & 63) == (unsigned)__builtin_ctzll(any)) flags[level] = 1;
 }
 
-// Frontier chunk (lane wl's 16 bytes) of neighbour u; at level 1 the frontier
-// is the sources themselves.
-__device__ __forceinline__ ulonglong2 frontier_chunk(const ulonglong2* __restrict__ F, int u, int wl, int level,
-                                                     int base) {
-  if (u < 0) return make_ulonglong2(0ull, 0ull);
-  if (level == 1) return source_chunk(u, wl, base);
-  return F[(size_t)u * (kBfsWords / 2) + wl];
-}
-
 constexpr int kGatherThreads = 1024;           // threads per gather workgroup (16 waves)
 constexpr int kGatherWaves = kGatherThreads / 64;
 constexpr int kMidMax = 64;                     // rows up to this degree take one wave
 
+// The OR into (a0, a1) of the frontier chunks (lane wl's 16 bytes) of N
+// neighbours: entry j's neighbour u (-1 for none) and, from level 2 on, its
+// chunk mask are held by lane l0 + j.  At level 1 the frontier is the sources
+// themselves.  A chunk is loaded only where its mask bit is set, and all N
+// loads are issued before the first is used: a lane whose bit is clear leaves
+// its load register unwritten (not zeroed, which would make each load wait for
+// the one before) and masks it out afterwards.
+template <int N>
+__device__ __forceinline__ void frontier_or(const ulonglong2* __restrict__ F, int uj, uint64_t mj, int l0, int wl,
+                                            int level, int base, uint64_t (&c0)[N], uint64_t (&c1)[N]) {
+  if (level == 1) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const int u = __builtin_amdgcn_readlane(uj, l0 + j);
+      const ulonglong2 c = u < 0 ? make_ulonglong2(0ull, 0ull) : source_chunk(u, wl, base);
+      c0[j] = c.x;
+      c1[j] = c.y;
+    }
+    return;
+  }
+  ulonglong2 f[N];
+  bool on[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const int u = __builtin_amdgcn_readlane(uj, l0 + j);
+    const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mj >> 32), l0 + j) << 32) |
+                       (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mj, l0 + j);
+    on[j] = (u >= 0) & (((m >> wl) & 1ull) != 0ull);
+    if (on[j]) f[j] = F[(size_t)u * (kBfsWords / 2) + wl];
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    c0[j] = on[j] ? f[j].x : 0ull;
+    c1[j] = on[j] ? f[j].y : 0ull;
+  }
+}
+
+// The chunk mask of frontier row u, for lanes that hold an entry (0 for none
+// and at level 1, where the frontier is formed, not read).
+__device__ __forceinline__ uint64_t entry_mask(const uint64_t* __restrict__ M, int u, int level) {
+  return u >= 0 && level > 1 ? M[u] : 0ull;
+}
+
 // The OR of lane wl's chunk over entries e0 .. e0 + kWaveEntries - 1 of a row
 // (CSR entries from b), the wave's lane groups each taking kGatherRun of them:
 // lane l holds entry e0 + l.
-__device__ __forceinline__ void row_chunk_or(const ulonglong2* __restrict__ F, const int32_t* __restrict__ col_idx,
-                                             int b, int deg, int e0, int lane, int grp, int wl, int level, int base,
-                                             uint64_t& a0, uint64_t& a1) {
+__device__ __forceinline__ void row_chunk_or(const ulonglong2* __restrict__ F, const uint64_t* __restrict__ M,
+                                             const int32_t* __restrict__ col_idx, int b, int deg, int e0, int lane,
+                                             int grp, int wl, int level, int base, uint64_t& a0, uint64_t& a1) {
   const int uj = e0 + lane < deg ? col_idx[b + e0 + lane] : -1;
-  ulonglong2 f[kGatherRun];
-#pragma unroll
-  for (int j = 0; j < kGatherRun; ++j) f[j] = frontier_chunk(F, __shfl(uj, kGatherRun * grp + j, 64), wl, level, base);
+  const uint64_t mj = entry_mask(M, uj, level);
+  uint64_t c0[kGatherRun], c1[kGatherRun];
+  frontier_or(F, uj, mj, kGatherRun * grp, wl, level, base, c0, c1);
 #pragma unroll
   for (int j = 0; j < kGatherRun; ++j) {
-    a0 |= f[j].x;
-    a1 |= f[j].y;
+    a0 |= c0[j];
+    a1 |= c1[j];
   }
 }
 
@@ -136,8 +191,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __res
                                                                const int4* __restrict__ longrows, int nbig, int nmid,
                                                                const int32_t* __restrict__ col_idx,
                                                                const uint64_t* __restrict__ frontier,
+                                                               const uint64_t* __restrict__ mfront,
                                                                const uint64_t* __restrict__ prev2,
+                                                               const uint64_t* __restrict__ mprev2,
                                                                ulonglong2* __restrict__ slot,
+                                                               uint64_t* __restrict__ mout,
                                                                int32_t* __restrict__ flags, int level, int base) {
   __shared__ ulonglong2 wor[kGatherWaves][kGatherLanes];
   if (flags[level - 1] == 0) return;  // the search of this sweep has ended
@@ -149,7 +207,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __res
     const int4 lr = longrows[blockIdx.x];  // (vertex, first CSR entry, degree, 0)
     uint64_t a0 = 0ull, a1 = 0ull;
     for (int e0 = wave * kWaveEntries; e0 < lr.z; e0 += kGatherWaves * kWaveEntries)
-      row_chunk_or(F, col_idx, lr.y, lr.z, e0, lane, grp, wl, level, base, a0, a1);
+      row_chunk_or(F, mfront, col_idx, lr.y, lr.z, e0, lane, grp, wl, level, base, a0, a1);
     groups_or(a0, a1);
     if (grp == 0) wor[wave][wl] = make_ulonglong2(a0, a1);
     __syncthreads();
@@ -160,7 +218,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __res
         a0 |= wor[w][wl].x;
         a1 |= wor[w][wl].y;
       }
-      bfs_settle(F, P2, slot, lr.x, wl, level, base, a0, a1, found);
+      bfs_settle(F, mfront, P2, mprev2, slot, mout, lr.x, wl, level, base, a0, a1, found);
     }
     raise_flag(found, flags, level);
     return;
@@ -171,10 +229,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __res
     const int4 lr = longrows[nbig + k];
     uint64_t a0 = 0ull, a1 = 0ull;
     for (int e0 = 0; e0 < lr.z; e0 += kWaveEntries)
-      row_chunk_or(F, col_idx, lr.y, lr.z, e0, lane, grp, wl, level, base, a0, a1);
+      row_chunk_or(F, mfront, col_idx, lr.y, lr.z, e0, lane, grp, wl, level, base, a0, a1);
     groups_or(a0, a1);
     bool found = false;
-    if (grp == 0) bfs_settle(F, P2, slot, lr.x, wl, level, base, a0, a1, found);
+    if (grp == 0) bfs_settle(F, mfront, P2, mprev2, slot, mout, lr.x, wl, level, base, a0, a1, found);
     raise_flag(found, flags, level);
     return;
   }
@@ -182,27 +240,24 @@ __global__ __launch_bounds__(kGatherThreads) void k_bfs_gather(const int2* __res
   // lane wl < kGatherRun of the group holds the run's entry wl: (neighbour, vertex), or (-1, -1)
   const int2 pr = r < nruns && wl < kGatherRun ? pairs[(size_t)r * kGatherRun + wl] : make_int2(-1, -1);
   const int vj = pr.y, uj = pr.x;
-  ulonglong2 f[kGatherRun];
-#pragma unroll
-  for (int j = 0; j < kGatherRun; ++j) {
-    const int u = __shfl(uj, kGatherLanes * grp + j, 64);  // -1 past the run
-    f[j] = frontier_chunk(F, u, wl, level, base);
-  }
+  // the entries' chunks (a row's entries are combined below)
+  uint64_t c0[kGatherRun], c1[kGatherRun];
+  frontier_or(F, uj, entry_mask(mfront, uj, level), kGatherLanes * grp, wl, level, base, c0, c1);
   int cur = -1;
   uint64_t a0 = 0ull, a1 = 0ull;
   bool found = false;
 #pragma unroll
   for (int j = 0; j < kGatherRun; ++j) {
-    const int v = __shfl(vj, kGatherLanes * grp + j, 64);
+    const int v = __builtin_amdgcn_readlane(vj, kGatherLanes * grp + j);
     if (v != cur) {
-      if (cur >= 0) bfs_settle(F, P2, slot, cur, wl, level, base, a0, a1, found);
+      if (cur >= 0) bfs_settle(F, mfront, P2, mprev2, slot, mout, cur, wl, level, base, a0, a1, found);
       cur = v;
       a0 = a1 = 0ull;
     }
-    a0 |= f[j].x;
-    a1 |= f[j].y;
+    a0 |= c0[j];
+    a1 |= c1[j];
   }
-  if (cur >= 0) bfs_settle(F, P2, slot, cur, wl, level, base, a0, a1, found);
+  if (cur >= 0) bfs_settle(F, mfront, P2, mprev2, slot, mout, cur, wl, level, base, a0, a1, found);
   raise_flag(found, flags, level);
 }
 
@@ -248,19 +303,31 @@ __global__ __launch_bounds__(256) void k_bfs_flags(int32_t* __restrict__ flags, 
 __device__ __forceinline__ uint32_t spread4(uint32_t nib) { return ((nib & 0xfu) * 0x00204081u) & 0x01010101u; }
 
 // Levels l0..l1 (one batch, l1 - l0 < 16) into d.  Workgroup: row block rb,
-// words 8 kq .. 8 kq + 7 of the sweep.
+// words 8 kq .. 8 kq + 7 of the sweep; the word blocks of one 128-byte line
+// are consecutive workgroups of one XCD (workgroups are handed to the XCDs in
+// turn), so the line is fetched into that XCD's L2 once.
 // Also the pairs' weights: each row's sum of d^-2 over the found pairs of its
 // 8 words (the sources at level l count popcount / l^2, levels from
 // count_from on) is added into wq[kq][v], one partial per word block, by one
 // thread in a fixed order, so W = sum over kq of wq is the same on every run.
 __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ slots, size_t slot_words,
+                                                   const uint64_t* __restrict__ masks,
                                                    const int32_t* __restrict__ flags, uint8_t* __restrict__ d,
                                                    double* __restrict__ wq, int n, int n_pad, int ng, int base,
                                                    int l0, int l1, int count_from) {
   if (l0 > 1 && flags[l0] == 0) return;  // nothing found in this batch; the first batch writes every byte
   __shared__ uint64_t planes[5][kRowBlock][kStoreWords + 1];
-  const int rb = blockIdx.x / (kBfsWords / kStoreWords), kq = blockIdx.x % (kBfsWords / kStoreWords);
+  // on XCD x: (rb, kq) = (0, 2 x), (0, 2 x + 1), (1, 2 x), ... for 16 word blocks
+  constexpr int kLinesPerXcd = kBfsWords / kStoreWords / kStoreBlocksPerLine / kXcds;
+  const int xi = (int)(blockIdx.x / kXcds), x = (int)(blockIdx.x % kXcds);
+  const int per_rb = kLinesPerXcd * kStoreBlocksPerLine;
+  const int rb = xi / per_rb,
+            kq = ((xi % per_rb) / kStoreBlocksPerLine * kXcds + x) * kStoreBlocksPerLine + xi % kStoreBlocksPerLine;
   const int t = threadIdx.x;
+  // the batch's levels l0 .. l0 + nl - 1 that found something (the levels after
+  // an empty one found nothing)
+  int nl = 0;
+  while (l0 + nl <= l1 && flags[l0 + nl] != 0) ++nl;
   // planes 0..3: bits of l - l0; plane 4: found in this batch
 #pragma unroll
   for (int r = 0; r < kRowBlock * kStoreWords / 256; ++r) {
@@ -268,18 +335,31 @@ __global__ __launch_bounds__(256) void k_bfs_store(const uint64_t* __restrict__ 
     const int row = p / kStoreWords, kk = p % kStoreWords;
     const int v = rb * kRowBlock + row;
     const size_t q = (size_t)v * kBfsWords + kq * kStoreWords + kk;
+    const int chunk = (kq * kStoreWords + kk) / 2;
     uint64_t P0 = 0, P1 = 0, P2 = 0, P3 = 0, Fd = 0;
     double ws = 0.0;
-    for (int l = l0; l <= l1; ++l) {
-      if (flags[l] == 0) break;  // levels after an empty one found nothing
-      const uint64_t nw = v < n ? slots[(size_t)(l % kBfsSlots) * slot_words + q] : 0ull;
-      const int off = l - l0;
+    // every mask first, then the words whose chunk bit is set: all loads in
+    // flight at once (a clear lane leaves its load register unwritten)
+    uint64_t mk[kBfsSlots], w[kBfsSlots];
+    bool on[kBfsSlots];
+#pragma unroll
+    for (int i = 0; i < kBfsSlots; ++i)
+      mk[i] = i < nl ? masks[(size_t)((l0 + i) % kBfsSlots) * n + (v < n ? v : n - 1)] : 0ull;
+#pragma unroll
+    for (int i = 0; i < kBfsSlots; ++i) {
+      on[i] = (v < n) & (((mk[i] >> chunk) & 1ull) != 0ull);
+      if (on[i]) w[i] = slots[(size_t)((l0 + i) % kBfsSlots) * slot_words + q];
+    }
+#pragma unroll
+    for (int i = 0; i < kBfsSlots; ++i) {
+      const uint64_t nw = on[i] ? w[i] : 0ull;
       Fd |= nw;
-      if (off & 1) P0 |= nw;
-      if (off & 2) P1 |= nw;
-      if (off & 4) P2 |= nw;
-      if (off & 8) P3 |= nw;
-      if (l >= count_from) ws += (double)__popcll(nw) / ((double)l * (double)l);
+      if (i & 1) P0 |= nw;
+      if (i & 2) P1 |= nw;
+      if (i & 4) P2 |= nw;
+      if (i & 8) P3 |= nw;
+      const int l = l0 + i;
+      if (i < nl && l >= count_from) ws += (double)__popcll(nw) / ((double)l * (double)l);
     }
     // the row's kStoreWords threads are consecutive lanes: add their sums in a fixed tree
 #pragma unroll
@@ -400,26 +480,29 @@ hipError_t launch_bfs_pairs(const int4* runs, int nruns, const int64_t* row_ptr,
 }
 
 hipError_t launch_bfs_level(const int2* pairs, int nruns, const int4* longrows, int nbig, int nmid,
-                            const int32_t* col_idx, const uint64_t* slots, int n, int base, int level,
-                            int32_t* flags, hipStream_t s) {
+                            const int32_t* col_idx, const uint64_t* slots, uint64_t* masks, int n, int base,
+                            int level, int32_t* flags, hipStream_t s) {
   if (n <= 0 || nruns + nbig + nmid == 0) return hipSuccess;
   const size_t words = (size_t)n * kBfsWords;
-  const uint64_t* frontier = slots + (size_t)((level - 1) % kBfsSlots) * words;
-  const uint64_t* prev2 = slots + (size_t)((level + kBfsSlots - 2) % kBfsSlots) * words;  // read from level 3 on
-  uint64_t* out = const_cast<uint64_t*>(slots) + (size_t)(level % kBfsSlots) * words;
+  const int s1 = (level - 1) % kBfsSlots, s2 = (level + kBfsSlots - 2) % kBfsSlots, s0 = level % kBfsSlots;
+  const uint64_t* frontier = slots + (size_t)s1 * words;
+  const uint64_t* prev2 = slots + (size_t)s2 * words;  // read from level 3 on
+  uint64_t* out = const_cast<uint64_t*>(slots) + (size_t)s0 * words;
   const int per_block = kGatherWaves * kGatherGroups;
   const unsigned blocks = (unsigned)(nbig + (nmid + kGatherWaves - 1) / kGatherWaves + (nruns + per_block - 1) / per_block);
-  k_bfs_gather<<<blocks, kGatherThreads, 0, s>>>(pairs, nruns, longrows, nbig, nmid, col_idx, frontier, prev2,
-                                                 reinterpret_cast<ulonglong2*>(out), flags, level, base);
+  k_bfs_gather<<<blocks, kGatherThreads, 0, s>>>(pairs, nruns, longrows, nbig, nmid, col_idx, frontier,
+                                                 masks + (size_t)s1 * n, prev2, masks + (size_t)s2 * n,
+                                                 reinterpret_cast<ulonglong2*>(out), masks + (size_t)s0 * n, flags,
+                                                 level, base);
   return hipGetLastError();
 }
 
-hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, double* wq, int n, int n_pad,
-                            int base, int l0, int l1, int count_from, hipStream_t s) {
+hipError_t launch_bfs_store(const uint64_t* slots, const uint64_t* masks, const int32_t* flags, uint8_t* d,
+                            double* wq, int n, int n_pad, int base, int l0, int l1, int count_from, hipStream_t s) {
   if (n <= 0 || l1 < l0) return hipSuccess;
   const int nrb = n_pad / kRowBlock;
   k_bfs_store<<<(unsigned)nrb * (kBfsWords / kStoreWords), 256, 0, s>>>(
-      slots, (size_t)n * kBfsWords, flags, d, wq, n, n_pad, n_pad / kColGroup, base, l0, l1, count_from);
+      slots, (size_t)n * kBfsWords, masks, flags, d, wq, n, n_pad, n_pad / kColGroup, base, l0, l1, count_from);
   return hipGetLastError();
 }
 

@@ -186,7 +186,11 @@ int bfs_words();              // 64-bit words per vertex in the BFS buffers
 int bfs_slots();              // level bitmaps kept (levels per batch)
 // slots: bfs_slots() buffers of n * bfs_words() words; slot l % bfs_slots()
 // holds the sources that first reach each vertex at level l >= 1 (the sources
-// themselves, level 0, are formed where needed).
+// themselves, level 0, are formed where needed).  masks: bfs_slots() buffers
+// of n words; bit c of mask l % bfs_slots() of v is set iff 16-byte chunk c
+// of v's level-l row is not zero, and only those chunks are written: a chunk
+// whose bit is clear holds stale bytes and is read as zero.  Level l writes
+// every vertex's mask; neither buffer needs clearing.
 // Runs of the gather: int4 (first CSR entry, count, row of that entry, 0),
 // count 1 .. bfs_run_entries(): whole rows of at most that many entries packed
 // together (a run never splits one).  Every other row is listed in longrows as
@@ -203,8 +207,8 @@ hipError_t launch_bfs_pairs(const int4* runs, int nruns, const int64_t* row_ptr,
 // flags[l] != 0 iff level l found a new vertex (flags[0]: the sources); a level
 // after an empty one does nothing.
 hipError_t launch_bfs_level(const int2* pairs, int nruns, const int4* longrows, int nbig, int nmid,
-                            const int32_t* col_idx, const uint64_t* slots, int n, int base, int level,
-                            int32_t* flags, hipStream_t s);
+                            const int32_t* col_idx, const uint64_t* slots, uint64_t* masks, int n, int base,
+                            int level, int32_t* flags, hipStream_t s);
 // `sweeps` flag rows of `stride` ints: [s][0] = 1, the rest 0.
 hipError_t launch_bfs_flags(int32_t* flags, int sweeps, int stride, hipStream_t s);
 // Weight partials of the stores: bfs_weight_partials() x n_pad doubles, zero
@@ -216,8 +220,8 @@ hipError_t launch_weights_from_partials(const double* wq, double* W, int n, int 
 // level 1 writes every byte of the sweep's columns (below n_pad) in all rows.
 // The weights d^-2 of the pairs found at levels >= count_from are added into
 // the partials wq.
-hipError_t launch_bfs_store(const uint64_t* slots, const int32_t* flags, uint8_t* d, double* wq, int n, int n_pad,
-                            int base, int l0, int l1, int count_from, hipStream_t s);
+hipError_t launch_bfs_store(const uint64_t* slots, const uint64_t* masks, const int32_t* flags, uint8_t* d,
+                            double* wq, int n, int n_pad, int base, int l0, int l1, int count_from, hipStream_t s);
 // W from d (or df); wpart: scratch of sp.slices * n_pad doubles.
 hipError_t launch_weights(const uint8_t* d, const float* df, double* W, double* wpart, const Split& sp, int n,
                           hipStream_t s);
