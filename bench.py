@@ -400,6 +400,7 @@ def bench_batch(omega, count=2048):
     pairs = float(np.sum(ns * (ns - 1) * its))
     return {"graphs": count, "vertices": int(ns.sum()), "pairs_per_pass": float(np.sum(ns * (ns - 1))),
             "seconds": round(wall, 4), "device_ms": round(tot["run_ms"], 3), "plan_s": round(plan_s, 3),
+            "plan_device_ms": round(tot["plan_ms"], 3),
             "tune_s": round(tune_s, 3),
             "pair_interactions_per_s": pairs / wall, "iterations_mean": float(its.mean()),
             "iterations_max": int(its.max()), "all_converged": bool(tot["converged"]),

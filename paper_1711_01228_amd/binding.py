@@ -429,17 +429,25 @@ class BatchArgs:
     """Concatenation of many graphs into one block-diagonal CSR (global ids)."""
 
     def __init__(self, graphs):
-        ns = [int(g.n) for g in graphs]
+        ns = np.fromiter((int(g.n) for g in graphs), dtype=np.int64, count=len(graphs))
         self.graph_ptr = np.zeros(len(graphs) + 1, dtype=np.int64)
         self.graph_ptr[1:] = np.cumsum(ns)
-        rps, cis = [np.zeros(1, dtype=np.int64)], []
-        off_e = 0
-        for g, v0 in zip(graphs, self.graph_ptr[:-1]):
-            rps.append(np.asarray(g.row_ptr[1:], dtype=np.int64) + off_e)
-            cis.append(np.asarray(g.col_idx, dtype=np.int64) + v0)
-            off_e += int(g.row_ptr[-1])
-        self.row_ptr = np.ascontiguousarray(np.concatenate(rps))
-        self.col_idx = np.ascontiguousarray(np.concatenate(cis).astype(np.int32) if cis else np.zeros(0, np.int32))
+        rps = [np.asarray(g.row_ptr, dtype=np.int64) for g in graphs]
+        nnz = np.fromiter((int(r[-1]) for r in rps), dtype=np.int64, count=len(graphs))
+        e_ptr = np.zeros(len(graphs) + 1, dtype=np.int64)
+        e_ptr[1:] = np.cumsum(nnz)
+        self.row_ptr = np.zeros(int(self.graph_ptr[-1]) + 1, dtype=np.int64)
+        if len(graphs):
+            # each graph's row_ptr[1:] shifted by the entries before it
+            np.concatenate([r[1:] for r in rps], out=self.row_ptr[1:])
+            self.row_ptr[1:] += np.repeat(e_ptr[:-1], ns)
+        if self.graph_ptr[-1] > np.iinfo(np.int32).max:
+            raise ValueError("more than 2^31 - 1 vertices in the batch")
+        # each graph's column indices shifted by the vertices before it (int32 ids)
+        self.col_idx = np.zeros(int(e_ptr[-1]), dtype=np.int32)
+        if int(e_ptr[-1]):
+            np.concatenate([np.asarray(g.col_idx, dtype=np.int32) for g in graphs], out=self.col_idx)
+            self.col_idx += np.repeat(self.graph_ptr[:-1].astype(np.int32), nnz)
         self.n_total = int(self.graph_ptr[-1])
         self.s = sl_batch(len(graphs), self.graph_ptr.ctypes.data, int(self.row_ptr[-1]), self.row_ptr.ctypes.data,
                           self.col_idx.ctypes.data if len(self.col_idx) else None)

@@ -19,8 +19,14 @@ namespace {
 // ---------------------------------------------------------------------------
 // Distances and weights, one graph per workgroup.  256 sources per sweep, one
 // bit each in 4 words per vertex, frontiers in LDS; a thread per vertex pulls
-// its neighbours' frontier words (the batch graphs have small degrees) and
-// writes new levels into its own row of the tile-major distance block.
+// its neighbours' frontier words (the batch graphs have small degrees: the
+// first kNbr neighbours of each of the thread's vertices stay in registers for
+// the whole graph, the others are read from a copy of the graph's column
+// indices in LDS when they fit, so that no level waits on global memory).  The
+// sweep's 256 distance bytes of each of the thread's rows are built in
+// registers and written once, as whole 16-byte chunks of the tile-major block,
+// when the sweep ends.  W_v = sum_j d_vj^-2 is summed as the levels are found:
+// a level l adds (new sources) / l^2, in the order sweep, level, word.
 // ---------------------------------------------------------------------------
 template <int T>
 __global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restrict__ graphs,
@@ -29,9 +35,13 @@ __global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restr
                                                        const int32_t* __restrict__ col_idx, uint8_t* __restrict__ d,
                                                        double* __restrict__ Wg, int32_t* __restrict__ status) {
   constexpr int kWords = 4;
+  constexpr int kPer = kBatchMaxN / T;  // vertices per thread: v = tid + r T
+  constexpr int kNbr = 8;               // neighbours per vertex held in registers
+  constexpr int kLdsEntries = 8192;     // CSR entries of a graph kept in LDS
   __shared__ uint64_t fa[kBatchMaxN * kWords], fb[kBatchMaxN * kWords], vis[kBatchMaxN * kWords];
+  __shared__ int32_t cols[kLdsEntries];
   __shared__ double wl[256];
-  __shared__ int sh_q, sh_any;
+  __shared__ int sh_q, sh_found[3];
   const int tid = threadIdx.x;
   for (int b = tid; b < 256; b += T) wl[b] = b ? 1.0 / ((double)b * (double)b) : 0.0;
   for (;;) {
@@ -45,7 +55,40 @@ __global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restr
     const int n = G.n, ng = G.n_pad / kColGroup;
     uint8_t* __restrict__ dg = d + G.d_off;
     int err = 0;
+    // the graph's column indices (local ids) in LDS when they fit
+    const int64_t ebase = row_ptr[G.v_off], nnz = row_ptr[G.v_off + n] - ebase;
+    const bool in_lds = nnz <= kLdsEntries;
+    if (in_lds)
+      for (int e = tid; e < (int)nnz; e += T) cols[e] = (int)(col_idx[ebase + e] - G.v_off);
+    // the thread's rows: degree, first CSR entry, first kNbr neighbours, W sum
+    int deg[kPer], nb[kPer][kNbr];
+    int64_t e0[kPer];
+    double ws[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int v = tid + r * T;
+      deg[r] = 0;
+      e0[r] = 0;
+      ws[r] = 0.0;
+      if (v < n) {
+        e0[r] = row_ptr[G.v_off + v];
+        deg[r] = (int)(row_ptr[G.v_off + v + 1] - e0[r]);
+      }
+#pragma unroll
+      for (int j = 0; j < kNbr; ++j) nb[r][j] = j < deg[r] ? (int)(col_idx[e0[r] + j] - G.v_off) : 0;
+    }
     for (int base = 0; base < n && !err; base += 64 * kWords) {
+      // byt[r][k][c][m]: bytes 4 m .. 4 m + 3 of the 16-byte chunk of sources
+      // base + 64 k + 16 c .. + 15 in row tid + r T
+      uint32_t byt[kPer][kWords][4][4];
+#pragma unroll
+      for (int r = 0; r < kPer; ++r)
+#pragma unroll
+        for (int k = 0; k < kWords; ++k)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) byt[r][k][c][m] = 0u;
       for (int v = tid; v < n; v += T) {
 #pragma unroll
         for (int k = 0; k < kWords; ++k) {
@@ -57,20 +100,42 @@ __global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restr
       }
       uint64_t* F = fa;
       uint64_t* N = fb;
+      if (tid < 3) sh_found[tid] = 0;
       __syncthreads();
+      // One barrier per level.  sh_found[l % 3] is set by every thread that
+      // finds a new pair at level l and read by all after the level's barrier.
+      // Level l + 1's flag was last read at level l - 2, by every thread before
+      // the barrier that ended level l - 1, and is set only after the barrier
+      // that ends level l: level l clears it.
       for (int level = 1;; ++level) {
-        __syncthreads();  // every wave has read the previous level's flag before it is cleared
-        if (tid == 0) sh_any = 0;
-        __syncthreads();
+        if (tid == 0) sh_found[(level + 1) % 3] = 0;
         bool any = false;
         const uint32_t lv = (uint32_t)level * 0x01010101u;
-        for (int v = tid; v < n; v += T) {
-          uint64_t acc[kWords] = {0, 0, 0, 0};
-          const int64_t e1 = row_ptr[G.v_off + v + 1];
-          for (int64_t e = row_ptr[G.v_off + v]; e < e1; ++e) {
-            const int u = (int)(col_idx[e] - G.v_off);
+        const double wlev = level <= 255 ? wl[level] : 0.0;
 #pragma unroll
-            for (int k = 0; k < kWords; ++k) acc[k] |= F[u * kWords + k];
+        for (int r = 0; r < kPer; ++r) {
+          const int v = tid + r * T;
+          if (v >= n) continue;
+          uint64_t acc[kWords] = {0, 0, 0, 0};
+#pragma unroll
+          for (int j = 0; j < kNbr; ++j)
+            if (j < deg[r]) {
+#pragma unroll
+              for (int k = 0; k < kWords; ++k) acc[k] |= F[nb[r][j] * kWords + k];
+            }
+          if (in_lds) {
+#pragma unroll 4
+            for (int e = (int)(e0[r] - ebase) + kNbr; e < (int)(e0[r] - ebase) + deg[r]; ++e) {
+              const int u = cols[e];
+#pragma unroll
+              for (int k = 0; k < kWords; ++k) acc[k] |= F[u * kWords + k];
+            }
+          } else {
+            for (int64_t e = e0[r] + kNbr; e < e0[r] + deg[r]; ++e) {
+              const int u = (int)(col_idx[e] - G.v_off);
+#pragma unroll
+              for (int k = 0; k < kWords; ++k) acc[k] |= F[u * kWords + k];
+            }
           }
 #pragma unroll
           for (int k = 0; k < kWords; ++k) {
@@ -81,25 +146,17 @@ __global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restr
             any = true;
             if (level > 255) continue;
             vis[v * kWords + k] = old | nw;
+            ws[r] += (double)__popcll(nw) * wlev;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const uint32_t bits = (uint32_t)(nw >> (16 * c)) & 0xffffu;
-              if (bits == 0) continue;
-              const int s0 = base + 64 * k + 16 * c;
-              uint4* chunk = reinterpret_cast<uint4*>(dg + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
-                                                      (size_t)(v % kRowBlock) * kColGroup);
-              uint4 w = *chunk;
-              w.x |= lv & byte_mask4(bits & 0xfu);
-              w.y |= lv & byte_mask4((bits >> 4) & 0xfu);
-              w.z |= lv & byte_mask4((bits >> 8) & 0xfu);
-              w.w |= lv & byte_mask4((bits >> 12) & 0xfu);
-              *chunk = w;
-            }
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+              for (int m = 0; m < 4; ++m)
+                byt[r][k][c][m] |= lv & byte_mask4((uint32_t)(nw >> (16 * c + 4 * m)) & 0xfu);
           }
         }
-        if (any) sh_any = 1;
+        if (any) sh_found[level % 3] = 1;
         __syncthreads();
-        const int a = sh_any;
+        const int a = sh_found[level % 3];
         if (!a) break;
         if (level > 255) {
           err = 1;
@@ -109,20 +166,29 @@ __global__ __launch_bounds__(T) void k_batch_distances(const BatchGraph* __restr
         F = N;
         N = tmp;
       }
+      // the sweep's bytes of the thread's rows (chunks past n_pad are not the graph's)
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        const int v = tid + r * T;
+        if (v >= n) continue;
+#pragma unroll
+        for (int k = 0; k < kWords; ++k)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int s0 = base + 64 * k + 16 * c;
+            if (s0 >= G.n_pad) continue;
+            *reinterpret_cast<uint4*>(dg + ((size_t)(v / kRowBlock) * ng + s0 / kColGroup) * kTileBytes +
+                                      (size_t)(v % kRowBlock) * kColGroup) =
+                make_uint4(byt[r][k][c][0], byt[r][k][c][1], byt[r][k][c][2], byt[r][k][c][3]);
+          }
+      }
       __syncthreads();
     }
     if (err && tid == 0) status[gid] = -4;
-    __syncthreads();
-    // W_i = sum_j d_ij^-2, columns in ascending order
-    for (int i = tid; i < G.n_pad; i += T) {
-      const uint4* row = reinterpret_cast<const uint4*>(dg + (size_t)(i / kRowBlock) * ng * kTileBytes) + (i % kRowBlock);
-      double s = 0.0;
-      for (int g = 0; g < ng; ++g) {
-        const uint4 qd = row[(size_t)g * 64];
 #pragma unroll
-        for (int k = 0; k < kColGroup; ++k) s += wl[byte_of(chunk_word(qd, k), k & 3)];
-      }
-      Wg[G.w_off + i] = (i < n) ? s : 0.0;
+    for (int r = 0; r < kPer; ++r) {
+      const int v = tid + r * T;
+      if (v < G.n_pad) Wg[G.w_off + v] = v < n ? ws[r] : 0.0;
     }
   }
 }
