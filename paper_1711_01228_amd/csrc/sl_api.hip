@@ -595,8 +595,10 @@ sl_status enqueue_fused_tail(sl_plan* p, const LoopParams& lp, const sl_options*
     // difference (and its select) only when they leave its sign open
     // (the exact variant instead after an iteration whose bounds left it open,
     // until they would have decided again: both launches are gated by the state)
+    // (one of the two runs in each iteration: one reduction after both)
     for (int exact = 0; exact < 2; ++exact)
-      HIP_TRY(launch_force_sym_sg(p->dim, lp, exact, 1, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+      HIP_TRY(launch_force_sym_sg(p->dim, lp, exact, 1, exact ? kSymReduceAny : kSymReduceNone, p->d, p->df, p->Xb,
+                                  p->stride, p->Eb, p->st, p->sym_items,
                                   p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
                                   p->n_pad, p->ps),
               "symmetric fused force and safeguard kernels");
@@ -1197,13 +1199,15 @@ sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega,
                   "symmetric force kernels");
           break;
         case 7:
-          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 0, 0, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 0, 0, kSymReducePass, p->d, p->df, p->Xb, p->stride, p->Eb, p->st,
+                                      p->sym_items,
                                       p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
                                       p->n_pad, p->ps),
                   "symmetric fused force and safeguard kernels");
           break;
         case 8:
-          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 1, 0, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->sym_items,
+          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 1, 0, kSymReducePass, p->d, p->df, p->Xb, p->stride, p->Eb, p->st,
+                                      p->sym_items,
                                       p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
                                       p->n_pad, p->ps),
                   "symmetric fused force and exact safeguard kernels");

@@ -154,8 +154,14 @@ hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df
 // reduction workgroup into edot (sym_reduce_blocks(n_pad) doubles).  With
 // `exact` the difference f(X~) - f(X^H) itself too, into sgpart[2 nitems + item].
 // With `gated` the launch does work only in the iterations the state gives to
-// it (DevState::exact_next: the exact variant, else the bounds alone).
-hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, int exact, int gated, const uint8_t* d, const float* df,
+// it (DevState::exact_next: the exact variant, else the bounds alone).  The
+// reduction into fpart and edot follows the pass (kSymReducePass), is left
+// out (kSymReduceNone), or runs in every iteration that is not done
+// (kSymReduceAny: after the second of the two gated variants, one of which
+// runs in each iteration).
+constexpr int kSymReducePass = 0, kSymReduceNone = 1, kSymReduceAny = 2;
+hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, int exact, int gated, int reduce, const uint8_t* d,
+                               const float* df,
                                const float* Xb, size_t stride, const float* Eb, const DevState* st, const int4* items,
                                int nitems, const int32_t* panel_items, float* Pi, float* Pj, double* sgpart,
                                double* fpart, double* edot, int n_pad, hipStream_t s);

@@ -588,14 +588,70 @@ __global__ __launch_bounds__(256) void k_apply_enum(const float* __restrict__ Eb
 __device__ __forceinline__ double strided_share(const double* __restrict__ x, int count, int step, int off) {
   double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < count; b += 256 * 8) {
+    // all 8 loads issued before any is used (a skipped one leaves its register
+    // unwritten and is masked out after)
+    double t[8];
+    bool on[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (b + q * 256 < count) u[q] += x[(size_t)(b + q * 256) * step + off];
+    for (int q = 0; q < 8; ++q) {
+      on[q] = b + q * 256 < count;
+      if (on[q]) t[q] = x[(size_t)(b + q * 256) * step + off];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] += on[q] ? t[q] : 0.0;
   }
   double t = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) t += u[q];
   return t;
+}
+
+// The bounds' sums over the pass's records: B and C from the (B, C) pairs of
+// the nsg items, P from the nedot records, and D from the items' differences
+// when dpart is given.  Each thread keeps 16 independent sums of each (items
+// t + 256 (16 r + u)), so 16 loads of each kind are in flight at once; the
+// partials are added in a fixed order.
+__device__ __forceinline__ void bounds_shares(const double* __restrict__ sgpart, int nsg,
+                                              const double* __restrict__ edot, int nedot,
+                                              const double* __restrict__ dpart, double& B, double& C, double& P,
+                                              double& D) {
+  constexpr int U = 16;
+  double b[U], c[U], q[U], e[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) b[u] = c[u] = q[u] = e[u] = 0.0;
+  const double2* __restrict__ bc = reinterpret_cast<const double2*>(sgpart);
+  const int count = nsg > nedot ? nsg : nedot;
+  for (int base = threadIdx.x; base < count; base += 256 * U) {
+    // every load of the round issued before any is used (a skipped one leaves
+    // its register unwritten and is masked out after)
+    double2 x[U];
+    double y[U], z[U];
+    bool on_s[U], on_e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = base + u * 256;
+      on_s[u] = k < nsg;
+      on_e[u] = k < nedot;
+      if (on_s[u]) x[u] = bc[k];
+      if (on_e[u]) y[u] = edot[k];
+      if (dpart && on_s[u]) z[u] = dpart[k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      b[u] += on_s[u] ? x[u].x : 0.0;
+      c[u] += on_s[u] ? x[u].y : 0.0;
+      q[u] += on_e[u] ? y[u] : 0.0;
+      if (dpart) e[u] += on_s[u] ? z[u] : 0.0;
+    }
+  }
+  B = C = P = D = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    B += b[u];
+    C += c[u];
+    P += q[u];
+    D += e[u];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __restrict__ red, int nred,
@@ -617,10 +673,9 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
   const bool sg = !p.enumerate && p.safeguard && (wp != 0.0 || p.omega_vertex);
   const bool bounds = sg && mode == kSelectBounds;
   if (bounds) {
-    v[7] = strided_share(sgpart, nsg, 2, 0);  // B
-    v[8] = strided_share(sgpart, nsg, 2, 1);  // C
-    v[9] = strided_share(edot, nedot, 1, 0);  // P
-    if (ran_exact) v[10] = strided_share(sgpart + 2 * (size_t)nsg, nsg, 1, 0);
+    // B, C, P, and the difference summed by the exact variant
+    bounds_shares(sgpart, nsg, edot, nedot, ran_exact ? sgpart + 2 * (size_t)nsg : nullptr, v[7], v[8], v[9],
+                  v[10]);
   } else if (sg) {
     v[7] = strided_share(sgpart, nsg, 1, 0);
   }
@@ -633,9 +688,15 @@ __global__ __launch_bounds__(256) void k_select(LoopParams p, const double* __re
     if (c < kEnumCandidates) {
       double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       for (int b = j; b < nsg; b += kPerCand * 8) {
+        double t[8];  // all 8 loads issued before any is used
+        bool on[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (b + q * kPerCand < nsg) u[q] += sgpart[(size_t)(b + q * kPerCand) * kEnumCandidates + c];
+        for (int q = 0; q < 8; ++q) {
+          on[q] = b + q * kPerCand < nsg;
+          if (on[q]) t[q] = sgpart[(size_t)(b + q * kPerCand) * kEnumCandidates + c];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) u[q] += on[q] ? t[q] : 0.0;
       }
       double t = 0.0;
 #pragma unroll

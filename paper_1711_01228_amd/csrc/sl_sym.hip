@@ -540,32 +540,35 @@ __global__ __launch_bounds__(256) void k_lw_sym_reduce(const double* __restrict_
 }
 
 template <int DIM, int SG, bool FD>
-void sym_launch(const LoopParams* lp, int gate, const uint8_t* d, const float* df, const float* Xb, size_t stride,
-                const float* Eb, const DevState* st, const int4* items, int nitems, const int32_t* panel_items,
-                float* Pi, float* Pj, double* sgpart, double* fpart, double* edot, int n_pad, hipStream_t s) {
+void sym_launch(const LoopParams* lp, int gate, int reduce, const uint8_t* d, const float* df, const float* Xb,
+                size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
+                const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart, double* edot,
+                int n_pad, hipStream_t s) {
   const int nb = n_pad / 64, ng = n_pad / kColGroup;
   k_force_sym<DIM, SG, FD><<<(nitems + kWaves - 1) / kWaves, kWaves * 64, 0, s>>>(
       d, df, Xb, stride, Eb, lp ? lp->omega_sched : nullptr, lp ? lp->omega_p : 0.0, lp && lp->omega_vertex ? 1 : 0,
       gate, st, items, nitems, Pi, Pj, sgpart, nb, ng, n_pad);
-  k_sym_reduce<DIM><<<sym_reduce_blocks(n_pad), 256, 0, s>>>(Pi, Pj, panel_items, gate, st, fpart,
+  if (reduce == kSymReduceNone) return;
+  k_sym_reduce<DIM><<<sym_reduce_blocks(n_pad), 256, 0, s>>>(Pi, Pj, panel_items,
+                                                             reduce == kSymReduceAny ? kGateNone : gate, st, fpart,
                                                              SG != 0 ? Eb : nullptr, edot, n_pad);
 }
 
 template <int SG>
-void sym_dispatch(int dim, const LoopParams* lp, int gate, const uint8_t* d, const float* df, const float* Xb,
-                  size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
+void sym_dispatch(int dim, const LoopParams* lp, int gate, int reduce, const uint8_t* d, const float* df,
+                  const float* Xb, size_t stride, const float* Eb, const DevState* st, const int4* items, int nitems,
                   const int32_t* panel_items, float* Pi, float* Pj, double* sgpart, double* fpart, double* edot,
                   int n_pad, hipStream_t s) {
   if (dim == 2) {
-    if (df) sym_launch<2, SG, true>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                    fpart, edot, n_pad, s);
-    else sym_launch<2, SG, false>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                  fpart, edot, n_pad, s);
+    if (df) sym_launch<2, SG, true>(lp, gate, reduce, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj,
+                                    sgpart, fpart, edot, n_pad, s);
+    else sym_launch<2, SG, false>(lp, gate, reduce, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj,
+                                  sgpart, fpart, edot, n_pad, s);
   } else {
-    if (df) sym_launch<3, SG, true>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                    fpart, edot, n_pad, s);
-    else sym_launch<3, SG, false>(lp, gate, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj, sgpart,
-                                  fpart, edot, n_pad, s);
+    if (df) sym_launch<3, SG, true>(lp, gate, reduce, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj,
+                                    sgpart, fpart, edot, n_pad, s);
+    else sym_launch<3, SG, false>(lp, gate, reduce, d, df, Xb, stride, Eb, st, items, nitems, panel_items, Pi, Pj,
+                                  sgpart, fpart, edot, n_pad, s);
   }
 }
 
@@ -600,8 +603,8 @@ SymSplit make_sym_split(int n_pad) {
 hipError_t launch_force_sym(int dim, int cond, const uint8_t* d, const float* df, const float* Xb, size_t stride,
                             const DevState* st, const int4* items, int nitems, const int32_t* panel_items, float* Pi,
                             float* Pj, double* fpart, int n_pad, hipStream_t s) {
-  sym_dispatch<0>(dim, nullptr, cond ? kGateForce : kGateNone, d, df, Xb, stride, nullptr, st, items, nitems,
-                  panel_items, Pi, Pj, nullptr, fpart, nullptr, n_pad, s);
+  sym_dispatch<0>(dim, nullptr, cond ? kGateForce : kGateNone, kSymReducePass, d, df, Xb, stride, nullptr, st, items,
+                  nitems, panel_items, Pi, Pj, nullptr, fpart, nullptr, n_pad, s);
   return hipGetLastError();
 }
 
@@ -623,16 +626,16 @@ hipError_t launch_lw_sym(int dim, const double* pd, const uint8_t* d, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, int exact, int gated, const uint8_t* d, const float* df,
-                               const float* Xb, size_t stride, const float* Eb, const DevState* st, const int4* items,
-                               int nitems, const int32_t* panel_items, float* Pi, float* Pj, double* sgpart,
-                               double* fpart, double* edot, int n_pad, hipStream_t s) {
+hipError_t launch_force_sym_sg(int dim, const LoopParams& lp, int exact, int gated, int reduce, const uint8_t* d,
+                               const float* df, const float* Xb, size_t stride, const float* Eb, const DevState* st,
+                               const int4* items, int nitems, const int32_t* panel_items, float* Pi, float* Pj,
+                               double* sgpart, double* fpart, double* edot, int n_pad, hipStream_t s) {
   if (exact)
-    sym_dispatch<2>(dim, &lp, gated ? kGateExact : kGateNone, d, df, Xb, stride, Eb, st, items, nitems, panel_items,
-                    Pi, Pj, sgpart, fpart, edot, n_pad, s);
+    sym_dispatch<2>(dim, &lp, gated ? kGateExact : kGateNone, reduce, d, df, Xb, stride, Eb, st, items, nitems,
+                    panel_items, Pi, Pj, sgpart, fpart, edot, n_pad, s);
   else
-    sym_dispatch<1>(dim, &lp, gated ? kGateBounds : kGateNone, d, df, Xb, stride, Eb, st, items, nitems, panel_items,
-                    Pi, Pj, sgpart, fpart, edot, n_pad, s);
+    sym_dispatch<1>(dim, &lp, gated ? kGateBounds : kGateNone, reduce, d, df, Xb, stride, Eb, st, items, nitems,
+                    panel_items, Pi, Pj, sgpart, fpart, edot, n_pad, s);
   return hipGetLastError();
 }
 
