@@ -120,6 +120,54 @@ def test_batch_fixed_iterations_match_oracle(omega, safeguard):
     assert checked >= 8
 
 
+def dense_and_hub_batch():
+    """Graphs that take the batched search's other paths: column indices that do
+    not fit in LDS (more than 8,192 CSR entries: a complete graph, a dense G(n, M),
+    and n = 1024 with the entries just above the limit), rows with more than 8
+    neighbours (a star joined to a path, a BA graph's hubs), and one just below the
+    limit (entries read from LDS)."""
+    star_path = inputs.to_csr(300, [(0, k) for k in range(1, 200)] + [(k, k + 1) for k in range(199, 299)])
+    gs = [
+        inputs.complete_graph(100),
+        inputs.largest_component(inputs.erdos_renyi(600, 7200, 21)),
+        inputs.largest_component(inputs.erdos_renyi(1024, 4200, 22)),
+        star_path,
+        inputs.barabasi_albert(700, 3, 23),
+        inputs.largest_component(inputs.erdos_renyi(1024, 4000, 24)),
+    ]
+    xs = [inputs.uniform_positions(g.n, 2, 300 + k) for k, g in enumerate(gs)]
+    return gs, xs
+
+
+def test_dense_and_hub_batch_takes_both_paths():
+    gs, _ = dense_and_hub_batch()
+    nnz = [int(g.row_ptr[-1]) for g in gs]
+    assert sum(e > 8192 for e in nnz) >= 3 and sum(e <= 8192 for e in nnz) >= 3
+    assert all(int(np.diff(g.row_ptr).max()) > 8 for g in gs)
+
+
+@pytest.mark.gpu
+def test_batch_dense_and_hub_graphs_match_oracle():
+    gs, xs = dense_and_hub_batch()
+    iters = 20
+    X = _dev(xs)
+    with b.BatchPlan(gs, 2) as plan:
+        tot, per = plan.run(X, omega=1.5, tol=0.0, max_iter=iters, safeguard=True)
+        out = _split(X, plan)
+    for k, (g, x0) in enumerate(zip(gs, xs)):
+        D = oracle.apsp(g.row_ptr, g.col_idx)
+        Xo, io = oracle.layout(D, x0, omega=1.5, tol=0.0, max_iter=iters, safeguard=True)
+        print("graph", k, g.n, int(g.row_ptr[-1]), per[k], io["iterations"], flush=True)
+        assert per[k]["iterations"] == io["iterations"]
+        tr = io["trace"]
+        if np.any((tr[:, 1] >= 0) & (np.abs(tr[:, 2]) <= AMBIG * tr[:, 3])):
+            continue
+        assert per[k]["rejected"] == io["rejected"], k
+        diam = float(np.linalg.norm(Xo.max(0) - Xo.min(0)))
+        err = np.abs(out[k] - Xo).max()
+        assert err <= 1e-4 * diam, (k, err, diam)
+
+
 @pytest.mark.gpu
 def test_batch_iterations_to_tol_and_tuning():
     gs, xs = small_batch()
