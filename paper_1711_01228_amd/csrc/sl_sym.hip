@@ -426,12 +426,18 @@ __global__ __launch_bounds__(256) void k_lw_sym(const uint8_t* __restrict__ d, c
         const uint4 qn = load_chunk<false>(d, nullptr, panel * kPanel + (r + 1 < rb ? r + 1 : r), ng, g, lane);
         const P pi = Pv[ilo + lane];
         double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+        // the strip's 16 weights first: a table read issued among the scalar
+        // loads of p_j waits for all of them (they share a counter and may
+        // complete out of order)
+        double wk[kColGroup];
+#pragma unroll
+        for (int k = 0; k < kColGroup; ++k) wk[k] = lut[byte_of(chunk_word(q, k), k & 3)];
 #pragma unroll
         for (int k = 0; k < kColGroup; ++k) {
           // 16 columns' FP64 p_j (lane-uniform, scalar registers) do not fit at
           // once: each half (quarter in 3-D) loads after the previous one's work
           if (k % (DIM == 3 ? kColGroup / 4 : kColGroup / 2) == 0) asm volatile("" ::: "memory");
-          double w = lut[byte_of(chunk_word(q, k), k & 3)];
+          double w = wk[k];
           if constexpr (MASK) {
             if (jlo + k <= ilo + lane) w = 0.0;  // the pairs j <= i of a diagonal group
           }
