@@ -184,9 +184,15 @@ __global__ __launch_bounds__(256) void k_lw(const uint8_t* __restrict__ d, const
         uint4 qn = make_uint4(0u, 0u, 0u, 0u);
         if (g + 1 < g1) qn = tile[(size_t)(g + 1) * 64];
         const P* __restrict__ pj = Pv + (size_t)g * kColGroup;
+        // the group's 16 weights first: a table read issued among the scalar
+        // loads of p_j waits for all of them (they share a counter and may
+        // complete out of order)
+        double wk[kColGroup];
+#pragma unroll
+        for (int k = 0; k < kColGroup; ++k) wk[k] = lut[byte_of(chunk_word(q, k), k & 3)];
 #pragma unroll
         for (int k = 0; k < kColGroup; ++k) {
-          const double w = lut[byte_of(chunk_word(q, k), k & 3)];
+          const double w = wk[k];
           const P pp = pj[k];
           Q0 = fma(w, pp.x, Q0);
           Q1 = fma(w, pp.y, Q1);
