@@ -201,7 +201,13 @@ def test_full_size_gradient_invariants():
     """ER n = 16,384, mean degree 8, 100 iterations at omega = 1.5, checkpoints
     every 10: gradients finite, translation- and rotation-invariant.  At this
     size an edge-length plan takes the unordered force pass; the unrolled
-    forward equals sl_plan_run bit for bit on it."""
+    forward equals sl_plan_run bit for bit on it.  Along a random direction v of
+    the start: over 20 iterations the unordered pass's adjoint equals the
+    ordered pass's (pinned against FP64 finite differences of the oracle at
+    n = 1,000), and over one iteration it equals the central difference of the
+    forward itself.  A central difference over 100 iterations is no check here:
+    the forward's FP32 rounding makes f noisy at ~1e-7 of its value, which
+    swamps h (g . v) at every usable h."""
     import torch
 
     from paper_1711_01228_amd import autograd as ag
@@ -224,8 +230,32 @@ def test_full_size_gradient_invariants():
         lay.plan.run(Xa, omega=1.5, tol=0.0, max_iter=20)
         lay.plan.unroll(Xb, omega=1.5, iters=20, ckpt_every=10)
         np.testing.assert_array_equal(Xa.cpu().numpy(), Xb.cpu().numpy())
+
+        v = np.random.default_rng(inputs.workload_seed(5) + 3).standard_normal(X0.shape)
+
+        def adjoint(iters, force):
+            x0 = dev(X0).requires_grad_(True)
+            ag.stress_loss(ag.unrolled_layout(x0, lt.detach(), lay, omega=1.5, iters=iters, ckpt_every=10,
+                                              force=force), lay).backward()
+            return float(np.sum(x0.grad.cpu().numpy().astype(np.float64) * v))
+
+        def forward(x0, iters):
+            X = dev(x0)
+            info = lay.plan.unroll(X, omega=1.5, iters=iters, ckpt_every=10)
+            return lay.hop_plan.stress(X), info["rejected"]
+
+        a_sym, a_ord = adjoint(20, "default"), adjoint(20, "ordered")
+        a1 = adjoint(1, "default")
+        h = 1e-2
+        (fp, rp), (fm, rm) = forward(X0 + h * v, 1), forward(X0 - h * v, 1)
+        fd1 = (fp - fm) / (2 * h)
+        print("directional derivative, 20 iterations: unordered %.6e, ordered %.6e; one iteration: adjoint %.6e, "
+              "central difference %.6e" % (a_sym, a_ord, a1, fd1), flush=True)
     finally:
         lay.close()
+    assert a_sym == pytest.approx(a_ord, rel=1e-3)
+    assert rp == rm
+    assert fd1 == pytest.approx(a1, rel=3e-2)
     assert np.all(np.isfinite(gX0)) and np.all(np.isfinite(glen))
     assert np.abs(glen).max() > 0
     assert np.abs(gX0.sum(0)).max() <= 1e-4 * np.abs(gX0).sum()
