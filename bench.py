@@ -600,7 +600,7 @@ def main():
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

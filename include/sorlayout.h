@@ -53,7 +53,7 @@ typedef enum {
   SL_EDEVICE = -3,   /* a HIP call failed                                      */
   SL_ERANGE = -4,    /* a finite graph distance exceeds 255 hops               */
   SL_ENUMERIC = -5,  /* a non-finite coordinate appeared during the iteration  */
-  SL_ENOTSUP = -6    /* valid input this build does not handle                 */
+  SL_ENOTSUP = -6    /* valid input the library does not handle               */
 } sl_status;
 
 /* Columns of one trace row (one row per iteration, doubles). */
