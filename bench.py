@@ -193,6 +193,17 @@ def host_cpu():
         m = re.search(r"@\s*([0-9.]+)\s*GHz", info["model"])
         if m:
             info["mhz"] = float(m.group(1)) * 1000.0
+    if info["mhz"] is None:  # the current clock the kernel reports for the first CPU
+        try:
+            with open("/proc/cpuinfo") as f:
+                for ln in f:
+                    k, _, v = ln.partition(":")
+                    if k.strip() == "cpu MHz":
+                        info["mhz"] = float(v.strip())
+                        info["mhz_source"] = "/proc/cpuinfo cpu MHz (current clock of CPU 0)"
+                        break
+        except (OSError, ValueError):
+            pass
     return info
 
 
