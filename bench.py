@@ -26,6 +26,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -69,8 +70,14 @@ def log(*a):
 
 
 def kernel_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of a source's code with its comments and blank lines removed, so a
+    counter record stays tied to the kernel it was taken on, not its prose."""
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = (" ".join(line.split()) for line in text.splitlines())
+    return hashlib.sha256("\n".join(l for l in lines if l).encode()).hexdigest()[:16]
 
 
 VALU = {True: (os.path.join(ROOT, "profiles", "force_safeguard_sym_ba65536_valu.json"),

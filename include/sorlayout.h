@@ -14,10 +14,10 @@
  *                             sweep of eq. 5 per iteration:
  *                             x_i^H = x_i + (1/W_i) sum_j w_ij (d_ij - r_ij) u_ij
  *                             SL_ORDER_EXACT solves eq. 5 (the paper's step,
- *                             Alg. 1/2 line 4) by preconditioned conjugate
+ *                             Alg. 1/2, step H) by preconditioned conjugate
  *                             gradients
  *   SOR (Alg. 2, eq. 11)      X~ = X^H + (omega - 1)(X^H - X); keep X~ only if
- *                             f(X~) <= f(X^H) (Alg. 2, lines 6-8)
+ *                             f(X~) <= f(X^H) (Alg. 2, the safeguard)
  *   termination               res_k = ||X^H - X^k||_F / ||X^H - mean(X^H)||_F
  *                             <= tol (the paper leaves the test open: Alg. 1/2)
  *
@@ -162,7 +162,7 @@ typedef struct {
   int32_t max_iter;         /* >= 0; 0 returns X unchanged                         */
   double omega;             /* relaxation factor, finite, in (0, 16]                */
   double tol;               /* >= 0, on res_k                                     */
-  int32_t safeguard;        /* 1: Alg. 2 lines 6-8; 0: always keep X~             */
+  int32_t safeguard;        /* 1: Alg. 2's safeguard; 0: always keep X~           */
   int32_t check_every;      /* iterations between host polls of the stop flag;
                                <= 0 selects a default from the graph size          */
   uint32_t flags;           /* SL_FLAG_*                                           */
@@ -235,7 +235,7 @@ sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan**
  *      SL_ORDER_EXACT the solution of eq. 5 by conjugate gradients started
  *      from X^k (whose residual is F); res_k
  *   3. X~ = X^H + (omega - 1)(X^H - X^k)          (eq. 11)
- *   4. keep X~ iff f(X~) - f(X^H) <= 0              (Alg. 2, lines 6-8)
+ *   4. keep X~ iff f(X~) - f(X^H) <= 0              (Alg. 2, the safeguard)
  *   5. stop when res_k <= tol or after max_iter steps
  * `out` may be NULL.  Not converging within max_iter is not an error.
  * Edge-length plans run the Jacobi step with a fixed, scheduled or per-vertex
@@ -305,7 +305,7 @@ sl_status sl_plan_profile(sl_plan* plan, const float* X, int32_t dim, double ome
  * The unrolled layout maps the initial placement X^0 and, for edge-length
  * plans, the edge lengths (through d_ij = shortest-path length) to X^K after
  * exactly K iterations of Algorithm 2 with the Jacobi step and a fixed omega.
- * Its derivative holds the safeguard decisions (Alg. 2, lines 6-8) at those
+ * Its derivative holds the safeguard decisions (Alg. 2, the safeguard) at those
  * the forward run took: they are piecewise constant in the inputs.
  * ------------------------------------------------------------------------- */
 

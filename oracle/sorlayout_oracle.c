@@ -205,7 +205,7 @@ double slo_stress(int32_t n, int32_t dim, const double* D, const double* X) {
 
 /* f(XA) - f(XB), summed pair by pair as sum_{i<j} [w(rA-d)^2 - w(rB-d)^2],
  * plus the scale sum_{i<j} |w(rA-d)^2 - w(rB-d)^2| of that sum: the
- * comparison of Algorithm 2 (line 6) and the size of the terms it rests on.
+ * safeguard comparison of Algorithm 2 and the size of the terms it rests on.
  * Row i's share (pairs j > i) from its distance row drow. */
 static void stress_delta_row(int32_t n, int32_t dim, const double* drow, int32_t i, const double* XA,
                              const double* XB, double* sd_out, double* ss_out) {
@@ -366,7 +366,7 @@ double slo_majorant(int32_t n, int32_t dim, const double* D, const double* X, co
 }
 
 /* ---------------------------------------------------------------------- */
-/* The majorization step H (Algorithm 1/2, line 4): X^H solves             */
+/* The majorization step H of Algorithm 1/2: X^H solves                   */
 /*   L^W X^H = L^X X          (eq. 5 with Y = X, one column per dimension) */
 /* ---------------------------------------------------------------------- */
 
@@ -615,7 +615,7 @@ int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega,
   /* a single vertex (or none) is already laid out: no step is taken */
   for (int32_t k = 0; k < max_iter && n > 1; ++k) {
     double f_k = trace_stress ? slo_stress(n, dim, D, X) : NAN;
-    /* line 4: X^{k+1} <- H(X^k) */
+    /* step H: X^{k+1} <- H(X^k) */
     if (ordering == SLO_JACOBI) slo_h_jacobi(n, dim, D, X, XH);
     else if (ordering == SLO_GAUSS_SEIDEL) slo_h_gauss_seidel(n, dim, D, X, XH);
     else status = slo_h_exact(ctx, dim, D, X, XH);
@@ -668,7 +668,7 @@ int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega,
       if (omega_p == 0.0 && !omega_vertex) {
         memcpy(X, XH, sizeof(double) * nd);
       } else {
-        /* line 5 (eq. 11): X~ = X^H + omega_p (X^H - X^k), per vertex if given */
+        /* extrapolation (eq. 11): X~ = X^H + omega_p (X^H - X^k), per vertex if given */
         for (int32_t i = 0; i < n; ++i) {
           const double wp = omega_vertex ? omega_vertex[i] - 1.0 : omega_p;
           for (int32_t c = 0; c < dim; ++c) {
@@ -678,7 +678,7 @@ int slo_layout(int32_t n, int32_t dim, const double* D, double* X, double omega,
         }
         int take = 1;
         if (safeguard) {
-          /* line 6: keep X~ only if f(X~) <= f(X^H) */
+          /* safeguard: keep X~ only if f(X~) <= f(X^H) */
           slo_stress_delta(n, dim, D, XT, XH, &df, &scale);
           take = (df <= 0.0);
         }

@@ -3,7 +3,7 @@
 // ordered largest first, keeps its iterates, weights and force partials in
 // LDS, and runs Algorithm 2 for that graph to its own termination test: the
 // same arithmetic as the single-graph kernels (force pass, Jacobi update and
-// extrapolation of eq. 11, safeguard of Alg. 2 lines 6-8 summed inside the pass
+// extrapolation of eq. 11, safeguard of Alg. 2 summed inside the pass
 // that takes the next force at X~, residual test), with workgroup barriers in
 // place of kernel boundaries.  Distances come from a
 // per-graph breadth-first search run the same way.

@@ -7,8 +7,8 @@
 //   k_update   Jacobi sweep of eq. 5, X^H = X^k + F / W, and the extrapolation
 //              X~ = X^H + (omega - 1)(X^H - X^k) of eq. 11, plus block sums for
 //              the termination test
-//   k_sgdelta  f(X~) - f(X^H) over unordered pairs (Alg. 2, line 6)
-//   k_select   the decision of Alg. 2 lines 6-8, the termination test and the
+//   k_sgdelta  f(X~) - f(X^H) over unordered pairs (Alg. 2, safeguard)
+//   k_select   the safeguard decision of Alg. 2, the termination test and the
 //              iteration counter, in one workgroup
 // The distances and W_i, built once per graph, are in sl_apsp.hip.
 //
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_sgdelta(const uint8_t* __restrict__ d, 
 
 // ---------------------------------------------------------------------------
 // The force pass at X~ with the safeguard of the same iteration folded in
-// (Alg. 2 line 6 and the next iteration's force pass need the same pair
+// (Alg. 2's safeguard and the next iteration's force pass need the same pair
 // geometry).  Every ordered pair takes its force term at X~ exactly as in
 // k_force (same order and precision), so that if X~ is accepted the next
 // iteration uses these sums as they are; otherwise k_force runs again at X^H.
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(256) void k_apply_enum(const float* __restrict__ Eb
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 2 lines 6-9 and the termination test, one workgroup.
+// Alg. 2's safeguard, the loop's end and the termination test, one workgroup.
 // mode kSelectPlain: sgpart holds partial sums of f(X~) - f(X^H).
 // mode kSelectBounds: sgpart holds (B, C) per item and edot partial sums of
 //   P = sum_i e_i . F_i(X~): U = -2P + B >= f(X~) - f(X^H) >= -2P - C = L.  U <= 0

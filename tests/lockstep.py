@@ -1,4 +1,4 @@
-"""Lockstep check of the safeguard (Alg. 2 lines 5-8) along a GPU run.
+"""Lockstep check of the safeguard (Alg. 2: extrapolation and safeguard) along a GPU run.
 
 For every iteration k of a run that recorded its trace and placements, the
 oracle takes the GPU's own X^k, forms X^H (the Jacobi step of eq. 5), X~

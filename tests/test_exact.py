@@ -1,4 +1,4 @@
-"""The exact step H (eq. 5 solved; the paper's Alg. 1/2 line 4) on the GPU:
+"""The exact step H (eq. 5 solved; the paper's Alg. 1/2, step H) on the GPU:
 host validation, and parity with the oracle's EXACT ordering (Cholesky of the
 reduced L^W in FP64, lowest vertex of each component held).
 

@@ -277,7 +277,7 @@ def test_extrapolation_is_eq10():
 
 @pytest.mark.parametrize("omega", [1.5, 3.0])
 def test_safeguard_keeps_the_better_placement(omega):
-    # Algorithm 2, lines 6-8: X~ replaces X^{k+1} only if f(X~) <= f(X^{k+1})
+    # Algorithm 2's safeguard: X~ replaces X^{k+1} only if f(X~) <= f(X^{k+1})
     D, X0 = _er_case(n=80, m=160, seed=33)
     X = X0.copy()
     decisions = []
