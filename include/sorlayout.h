@@ -50,7 +50,7 @@ typedef enum {
   SL_OK = 0,
   SL_EINVAL = -1,    /* malformed graph or option                               */
   SL_ENOMEM = -2,    /* device or host allocation failed                       */
-  SL_EDEVICE = -3,   /* a HIP call failed                                      */
+  SL_EDEVICE = -3,   /* a HIP call (or, rarely, the host runtime) failed       */
   SL_ERANGE = -4,    /* a finite graph distance exceeds 255 hops               */
   SL_ENUMERIC = -5,  /* a non-finite coordinate appeared during the iteration  */
   SL_ENOTSUP = -6    /* valid input the library does not handle               */

@@ -10,6 +10,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -40,6 +42,22 @@ sl_status fail(sl_status st, const char* fmt, ...) {
 sl_status hip_fail(hipError_t e, const char* what) {
   const sl_status st = (e == hipErrorOutOfMemory) ? SL_ENOMEM : SL_EDEVICE;
   return fail(st, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Every C entry point runs its body through this, so that no C++ exception
+// (a host container that cannot grow, say) crosses the C ABI: it becomes a
+// status and a message instead.
+template <class F>
+sl_status guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(SL_ENOMEM, "host allocation failed");
+  } catch (const std::exception& x) {
+    return fail(SL_EDEVICE, "host runtime error: %s", x.what());
+  } catch (...) {
+    return fail(SL_EDEVICE, "host runtime error");
+  }
 }
 
 #define HIP_TRY(expr, what)                       \
@@ -363,11 +381,19 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
       std::stable_partition(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
       nbig = (int)std::count_if(longrows.begin(), longrows.end(), [&](const int4& r) { return r.z > mid_max; });
     };
+    bool packed = true;  // false: a host container could not grow
+    auto pack_here = [&]() {
+      try {
+        pack();
+      } catch (...) {
+        packed = false;
+      }
+    };
     std::thread packer;
     try {
-      packer = std::thread(pack);
+      packer = std::thread(pack_here);
     } catch (...) {
-      pack();  // no thread to be had: pack here
+      pack_here();  // no thread to be had: pack on this one
     }
     auto join = [&]() {
       if (packer.joinable()) packer.join();
@@ -414,6 +440,10 @@ sl_status build_distances(sl_plan* p, const sl_graph* g) {
     e = hipMemcpyAsync(ci, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
     if (e == hipSuccess) e = hipMemcpyAsync(rp, g->row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, p->ps);
     join();
+    if (!packed) {
+      cleanup();
+      return fail(SL_ENOMEM, "host allocation failed (the search's runs)");
+    }
     const int nruns = (int)runs.size();
     const int nmid = (int)longrows.size() - nbig;
     if (e == hipSuccess && nruns > 0)
@@ -861,379 +891,391 @@ void sl_default_options(sl_options* o) {
 const char* sl_last_error(void) { return g_err.c_str(); }
 
 sl_status sl_validate(const sl_graph* g, const sl_options* opt) {
-  g_err.clear();
-  sl_status s = check_graph(g);
-  if (s != SL_OK) return s;
-  if (opt) return check_options(opt);
-  return SL_OK;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    sl_status s = check_graph(g);
+    if (s != SL_OK) return s;
+    if (opt) return check_options(opt);
+    return SL_OK;
+  });
 }
 
 sl_status sl_plan_create(const sl_graph* g, int32_t dim, void* stream, sl_plan** out) {
-  g_err.clear();
-  if (!out) return fail(SL_EINVAL, "out is NULL");
-  *out = nullptr;
-  sl_status s = check_graph(g);
-  if (s != SL_OK) return s;
-  if (dim != 2 && dim != 3) return fail(SL_EINVAL, "dim = %d, expected 2 or 3", dim);
-  sl_plan* p = new (std::nothrow) sl_plan();
-  if (!p) return fail(SL_ENOMEM, "host allocation failed");
-  p->n = g->n;
-  p->n_pad = std::max(64, round_up(g->n, 64));
-  p->dim = dim;
-  p->vec = dim == 2 ? 2 : 4;
-  p->sp = make_split(p->n_pad);
-  p->stride = (size_t)p->n_pad * p->vec;
-  p->nred = (p->n_pad + 255) / 256;
-  const std::vector<int4> items = triangle_items(p->sp);
-  p->nsg = (int)items.size();
-  hipStream_t user = (hipStream_t)stream;
-  auto bail = [&](sl_status st) {
-    free_plan_memory(p);
-    delete p;
-    return st;
-  };
-  hipError_t e = hipStreamCreateWithFlags(&p->ps, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreate(&p->ev_a);
-  if (e == hipSuccess) e = hipEventCreate(&p->ev_b);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_sync, hipEventDisableTiming);
-  if (g->edge_len) {
-    p->nnz = g->nnz;
-    if (e == hipSuccess) e = hipMalloc(&p->df, sizeof(float) * (size_t)p->n_pad * p->n_pad);
-    if (e == hipSuccess) e = hipMalloc(&p->pred, sizeof(int32_t) * std::max<size_t>(1, (size_t)p->n * p->n));
-    if (e == hipSuccess) e = hipMalloc(&p->g_row_ptr, sizeof(int64_t) * (p->n + 1));
-    if (e == hipSuccess) e = hipMalloc(&p->g_col_idx, sizeof(int32_t) * std::max<int64_t>(1, g->nnz));
-    if (e == hipSuccess) e = hipMalloc(&p->g_len, sizeof(float) * std::max<int64_t>(1, g->nnz));
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!out) return fail(SL_EINVAL, "out is NULL");
+    *out = nullptr;
+    sl_status s = check_graph(g);
+    if (s != SL_OK) return s;
+    if (dim != 2 && dim != 3) return fail(SL_EINVAL, "dim = %d, expected 2 or 3", dim);
+    sl_plan* p = new (std::nothrow) sl_plan();
+    if (!p) return fail(SL_ENOMEM, "host allocation failed");
+    p->n = g->n;
+    p->n_pad = std::max(64, round_up(g->n, 64));
+    p->dim = dim;
+    p->vec = dim == 2 ? 2 : 4;
+    p->sp = make_split(p->n_pad);
+    p->stride = (size_t)p->n_pad * p->vec;
+    p->nred = (p->n_pad + 255) / 256;
+    const std::vector<int4> items = triangle_items(p->sp);
+    p->nsg = (int)items.size();
+    hipStream_t user = (hipStream_t)stream;
+    auto bail = [&](sl_status st) {
+      free_plan_memory(p);
+      delete p;
+      return st;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&p->ps, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_a);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_b);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_sync, hipEventDisableTiming);
+    if (g->edge_len) {
+      p->nnz = g->nnz;
+      if (e == hipSuccess) e = hipMalloc(&p->df, sizeof(float) * (size_t)p->n_pad * p->n_pad);
+      if (e == hipSuccess) e = hipMalloc(&p->pred, sizeof(int32_t) * std::max<size_t>(1, (size_t)p->n * p->n));
+      if (e == hipSuccess) e = hipMalloc(&p->g_row_ptr, sizeof(int64_t) * (p->n + 1));
+      if (e == hipSuccess) e = hipMalloc(&p->g_col_idx, sizeof(int32_t) * std::max<int64_t>(1, g->nnz));
+      if (e == hipSuccess) e = hipMalloc(&p->g_len, sizeof(float) * std::max<int64_t>(1, g->nnz));
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(p->g_row_ptr, g->row_ptr, sizeof(int64_t) * (p->n + 1), hipMemcpyHostToDevice, p->ps);
+      if (e == hipSuccess && g->nnz > 0)
+        e = hipMemcpyAsync(p->g_col_idx, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
+      if (e == hipSuccess && g->nnz > 0)
+        e = hipMemcpyAsync(p->g_len, g->edge_len, sizeof(float) * g->nnz, hipMemcpyHostToDevice, p->ps);
+      std::vector<int32_t> erow((size_t)g->nnz);
+      for (int v = 0; v < g->n; ++v)
+        for (int64_t q = g->row_ptr[v]; q < g->row_ptr[v + 1]; ++q) erow[(size_t)q] = v;
+      if (e == hipSuccess) e = hipMalloc(&p->g_erow, sizeof(int32_t) * std::max<int64_t>(1, g->nnz));
+      if (e == hipSuccess && g->nnz > 0)
+        e = hipMemcpyAsync(p->g_erow, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
+      if (e == hipSuccess) e = hipStreamSynchronize(p->ps);  // erow is a host temporary
+    } else if (e == hipSuccess) {
+      e = hipMalloc(&p->d, (size_t)p->n_pad * p->n_pad);
+    }
+    if (e == hipSuccess) e = hipMalloc(&p->W, sizeof(double) * p->n_pad);
+    if (e == hipSuccess) e = hipMalloc(&p->Xb, sizeof(float) * 3 * p->stride);
+    if (e == hipSuccess) e = hipMalloc(&p->Eb, sizeof(float) * p->stride);
+    if (e == hipSuccess) e = hipMalloc(&p->items, sizeof(int4) * items.size());
+    if (e == hipSuccess) e = hipMalloc(&p->fpart, sizeof(double) * p->sp.slices * 3 * p->n_pad);
+    if (e == hipSuccess) e = hipMalloc(&p->spart, sizeof(double) * p->sp.slices * p->n_pad);
+    if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(double) * 8 * p->nred);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(p->g_row_ptr, g->row_ptr, sizeof(int64_t) * (p->n + 1), hipMemcpyHostToDevice, p->ps);
-    if (e == hipSuccess && g->nnz > 0)
-      e = hipMemcpyAsync(p->g_col_idx, g->col_idx, sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
-    if (e == hipSuccess && g->nnz > 0)
-      e = hipMemcpyAsync(p->g_len, g->edge_len, sizeof(float) * g->nnz, hipMemcpyHostToDevice, p->ps);
-    std::vector<int32_t> erow((size_t)g->nnz);
-    for (int v = 0; v < g->n; ++v)
-      for (int64_t q = g->row_ptr[v]; q < g->row_ptr[v + 1]; ++q) erow[(size_t)q] = v;
-    if (e == hipSuccess) e = hipMalloc(&p->g_erow, sizeof(int32_t) * std::max<int64_t>(1, g->nnz));
-    if (e == hipSuccess && g->nnz > 0)
-      e = hipMemcpyAsync(p->g_erow, erow.data(), sizeof(int32_t) * g->nnz, hipMemcpyHostToDevice, p->ps);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->ps);  // erow is a host temporary
-  } else if (e == hipSuccess) {
-    e = hipMalloc(&p->d, (size_t)p->n_pad * p->n_pad);
-  }
-  if (e == hipSuccess) e = hipMalloc(&p->W, sizeof(double) * p->n_pad);
-  if (e == hipSuccess) e = hipMalloc(&p->Xb, sizeof(float) * 3 * p->stride);
-  if (e == hipSuccess) e = hipMalloc(&p->Eb, sizeof(float) * p->stride);
-  if (e == hipSuccess) e = hipMalloc(&p->items, sizeof(int4) * items.size());
-  if (e == hipSuccess) e = hipMalloc(&p->fpart, sizeof(double) * p->sp.slices * 3 * p->n_pad);
-  if (e == hipSuccess) e = hipMalloc(&p->spart, sizeof(double) * p->sp.slices * p->n_pad);
-  if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(double) * 8 * p->nred);
-  if (e == hipSuccess)
-    e = hipMalloc(&p->sgpart, sizeof(double) * std::max<size_t>({(size_t)p->nsg * kEnumCandidates,
-                                                                 (size_t)p->sp.blocks_x * p->sp.slices,
-                                                                 3 * make_sym_split(p->n_pad).items.size()}));
-  if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
-  if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
-  if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
-  if (e == hipSuccess && !g->edge_len && g->n > 1 && g->nnz > 0) {
-    const size_t sweeps = ((size_t)g->n + bfs_sources_per_sweep() - 1) / bfs_sources_per_sweep();
-    e = hipHostMalloc(&p->host_flags, sizeof(int32_t) * (kBfsMaxLevel + 1) * sweeps, hipHostMallocDefault);
-  }
-  if (e != hipSuccess) return bail(hip_fail(e, "plan allocation"));
-  e = hipMemsetAsync(p->Xb, 0, sizeof(float) * 3 * p->stride, p->ps);
-  if (e == hipSuccess) e = hipMemsetAsync(p->Eb, 0, sizeof(float) * p->stride, p->ps);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->ps);
-  if (e != hipSuccess) return bail(hip_fail(e, "plan initialization"));
-  if ((s = join_from(p, user)) != SL_OK) return bail(s);
-  if ((e = hipEventRecord(p->ev_a, p->ps)) != hipSuccess) return bail(hip_fail(e, "hipEventRecord"));
-  if ((s = build_distances(p, g)) != SL_OK) return bail(s);
-  if ((e = hipEventRecord(p->ev_b, p->ps)) != hipSuccess) return bail(hip_fail(e, "hipEventRecord"));
-  if ((e = hipStreamSynchronize(p->ps)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
-  p->plan_ms = ms;
-  *out = p;
-  return SL_OK;
+      e = hipMalloc(&p->sgpart, sizeof(double) * std::max<size_t>({(size_t)p->nsg * kEnumCandidates,
+                                                                   (size_t)p->sp.blocks_x * p->sp.slices,
+                                                                   3 * make_sym_split(p->n_pad).items.size()}));
+    if (e == hipSuccess) e = hipMalloc(&p->st, sizeof(DevState));
+    if (e == hipSuccess) e = hipMalloc(&p->st_eval, sizeof(DevState));
+    if (e == hipSuccess) e = hipHostMalloc(&p->host_st, sizeof(DevState), hipHostMallocDefault);
+    if (e == hipSuccess && !g->edge_len && g->n > 1 && g->nnz > 0) {
+      const size_t sweeps = ((size_t)g->n + bfs_sources_per_sweep() - 1) / bfs_sources_per_sweep();
+      e = hipHostMalloc(&p->host_flags, sizeof(int32_t) * (kBfsMaxLevel + 1) * sweeps, hipHostMallocDefault);
+    }
+    if (e != hipSuccess) return bail(hip_fail(e, "plan allocation"));
+    e = hipMemsetAsync(p->Xb, 0, sizeof(float) * 3 * p->stride, p->ps);
+    if (e == hipSuccess) e = hipMemsetAsync(p->Eb, 0, sizeof(float) * p->stride, p->ps);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, p->ps);
+    if (e != hipSuccess) return bail(hip_fail(e, "plan initialization"));
+    if ((s = join_from(p, user)) != SL_OK) return bail(s);
+    if ((e = hipEventRecord(p->ev_a, p->ps)) != hipSuccess) return bail(hip_fail(e, "hipEventRecord"));
+    if ((s = build_distances(p, g)) != SL_OK) return bail(s);
+    if ((e = hipEventRecord(p->ev_b, p->ps)) != hipSuccess) return bail(hip_fail(e, "hipEventRecord"));
+    if ((e = hipStreamSynchronize(p->ps)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+    p->plan_ms = ms;
+    *out = p;
+    return SL_OK;
+  });
 }
 
 sl_status sl_plan_destroy(sl_plan* p) {
-  g_err.clear();
-  if (!p) return SL_OK;
-  (void)hipStreamSynchronize(p->ps);
-  free_plan_memory(p);
-  delete p;
-  return SL_OK;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return SL_OK;
+    (void)hipStreamSynchronize(p->ps);
+    free_plan_memory(p);
+    delete p;
+    return SL_OK;
+  });
 }
 
 sl_status sl_plan_run(sl_plan* p, float* X, const sl_options* o, void* stream, sl_result* out) {
-  g_err.clear();
-  if (!p) return fail(SL_EINVAL, "plan is NULL");
-  sl_status s = check_options(o);
-  if (s != SL_OK) return s;
-  if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
-  if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
-  if (p->df && (o->strategy == SL_OMEGA_ENUM || o->ordering == SL_ORDER_EXACT))
-    return fail(SL_ENOTSUP, "edge-length plans run the Jacobi step with a fixed, scheduled or per-vertex factor");
-  hipStream_t user = (hipStream_t)stream;
-  sl_result res{};
-  res.plan_ms = p->plan_ms;
-  LoopParams lp{};
-  lp.n = p->n;
-  lp.n_pad = p->n_pad;
-  lp.ng = p->sp.ng;
-  lp.nrb = p->sp.nrb;
-  lp.slices = p->sp.slices;
-  lp.groups_per_slice = p->sp.groups_per_slice;
-  lp.omega_p = o->omega - 1.0;
-  lp.tol = o->tol;
-  lp.safeguard = o->safeguard;
-  lp.stress = (o->flags & SL_FLAG_TRACE_STRESS) ? 1 : 0;
-  lp.enumerate = o->strategy == SL_OMEGA_ENUM ? 1 : 0;
-  lp.omega_vertex = o->omega_vertex;
-  lp.omega_sched = nullptr;
-  // the safeguard rides on the next force pass: a safeguard to evaluate, no
-  // enumeration or stress trace
-  lp.fuse = (lp.safeguard && !lp.enumerate && !lp.stress &&
-             !(o->flags & SL_FLAG_SEPARATE_SAFEGUARD) &&
-             (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->strategy == SL_OMEGA_AUTO ||
-              o->omega_vertex) &&
-             p->n > 1)
-                ? 1
-                : 0;
-  if ((o->flags & SL_FLAG_SYM_FORCE) && (o->flags & SL_FLAG_ORDERED_FORCE))
-    return fail(SL_EINVAL, "SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE exclude each other");
-  // with the exact step the flag chooses the L^W matvec (run_exact); the force pass stays ordered
-  lp.sym = (o->flags & SL_FLAG_SYM_FORCE) && o->ordering == SL_ORDER_JACOBI ? 1 : 0;
-  if ((o->flags & SL_FLAG_SYM_FORCE) && lp.stress) return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: no stress trace");
-  if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !lp.stress && o->ordering == SL_ORDER_JACOBI &&
-      sym_by_default(p, lp.fuse != 0))
-    lp.sym = 1;
-  if (lp.sym) {
-    if (p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
-    if (p->n <= 1) lp.sym = 0;
-    else lp.slices = 1;
-  }
-
-  if ((s = join_from(p, user)) != SL_OK) return s;
-  if (o->omega_vertex && p->n > 0) {
-    std::vector<float> wv(p->n);
-    HIP_TRY(hipMemcpyAsync(wv.data(), o->omega_vertex, sizeof(float) * p->n, hipMemcpyDeviceToHost, p->ps),
-            "omega_vertex copy");
-    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-    for (int i = 0; i < p->n; ++i)
-      if (!(std::isfinite(wv[i]) && wv[i] > 0.f && wv[i] <= 16.f))
-        return fail(SL_EINVAL, "omega_vertex[%d] = %g outside (0, 16]", i, (double)wv[i]);
-  }
-  if ((o->strategy == SL_OMEGA_SCHEDULE || o->strategy == SL_OMEGA_AUTO) && o->max_iter > 0) {
-    if ((s = upload_schedule(p, o)) != SL_OK) return s;
-    lp.omega_sched = p->sched;
-  }
-  if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
-  DevState* h = p->host_st;
-  std::memset(h, 0, sizeof(DevState));
-  h->max_iter = o->max_iter;
-  h->done = (o->max_iter == 0 || p->n <= 1) ? 1 : 0;
-  h->converged = p->n <= 1 ? 1 : 0;
-  HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
-
-  // iterations per captured graph between looks at the stop flag (those after
-  // the stop return at once)
-  // (not capped by max_iter: runs of any length replay the same captured graph,
-  // whose iterations after the stop return at once)
-  const int chunk = o->check_every > 0 ? o->check_every : (p->n <= 8192 ? 32 : 8);
-  const bool use_graph = !(o->flags & SL_FLAG_NO_GRAPH);
-  const bool exact = o->ordering == SL_ORDER_EXACT;
-  if (use_graph && !exact) {
-    std::vector<double> key = {(double)p->dim, lp.omega_p, lp.tol, (double)lp.safeguard, (double)lp.stress,
-                               (double)lp.sym, (double)lp.fuse,
-                               (double)chunk, (double)(uintptr_t)o->trace, (double)(uintptr_t)o->xtrace,
-                               (double)lp.enumerate, (double)(uintptr_t)lp.omega_sched,
-                               (double)(uintptr_t)lp.omega_vertex};
-    if (!p->gexec || key != p->gkey) {
-      if (p->gexec) {
-        (void)hipGraphExecDestroy(p->gexec);
-        p->gexec = nullptr;
-      }
-      hipGraph_t graph = nullptr;
-      HIP_TRY(hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-      sl_status cs = SL_OK;
-      for (int k = 0; k < chunk && cs == SL_OK; ++k) cs = enqueue_iteration(p, lp, o);
-      hipError_t ce = hipStreamEndCapture(p->ps, &graph);
-      if (cs != SL_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return cs;
-      }
-      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-      hipError_t ie = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) {
-        p->gexec = nullptr;
-        return hip_fail(ie, "hipGraphInstantiate");
-      }
-      p->gkey = key;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return fail(SL_EINVAL, "plan is NULL");
+    sl_status s = check_options(o);
+    if (s != SL_OK) return s;
+    if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
+    if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
+    if (p->df && (o->strategy == SL_OMEGA_ENUM || o->ordering == SL_ORDER_EXACT))
+      return fail(SL_ENOTSUP, "edge-length plans run the Jacobi step with a fixed, scheduled or per-vertex factor");
+    hipStream_t user = (hipStream_t)stream;
+    sl_result res{};
+    res.plan_ms = p->plan_ms;
+    LoopParams lp{};
+    lp.n = p->n;
+    lp.n_pad = p->n_pad;
+    lp.ng = p->sp.ng;
+    lp.nrb = p->sp.nrb;
+    lp.slices = p->sp.slices;
+    lp.groups_per_slice = p->sp.groups_per_slice;
+    lp.omega_p = o->omega - 1.0;
+    lp.tol = o->tol;
+    lp.safeguard = o->safeguard;
+    lp.stress = (o->flags & SL_FLAG_TRACE_STRESS) ? 1 : 0;
+    lp.enumerate = o->strategy == SL_OMEGA_ENUM ? 1 : 0;
+    lp.omega_vertex = o->omega_vertex;
+    lp.omega_sched = nullptr;
+    // the safeguard rides on the next force pass: a safeguard to evaluate, no
+    // enumeration or stress trace
+    lp.fuse = (lp.safeguard && !lp.enumerate && !lp.stress &&
+               !(o->flags & SL_FLAG_SEPARATE_SAFEGUARD) &&
+               (lp.omega_p != 0.0 || o->strategy == SL_OMEGA_SCHEDULE || o->strategy == SL_OMEGA_AUTO ||
+                o->omega_vertex) &&
+               p->n > 1)
+                  ? 1
+                  : 0;
+    if ((o->flags & SL_FLAG_SYM_FORCE) && (o->flags & SL_FLAG_ORDERED_FORCE))
+      return fail(SL_EINVAL, "SL_FLAG_SYM_FORCE and SL_FLAG_ORDERED_FORCE exclude each other");
+    // with the exact step the flag chooses the L^W matvec (run_exact); the force pass stays ordered
+    lp.sym = (o->flags & SL_FLAG_SYM_FORCE) && o->ordering == SL_ORDER_JACOBI ? 1 : 0;
+    if ((o->flags & SL_FLAG_SYM_FORCE) && lp.stress) return fail(SL_ENOTSUP, "SL_FLAG_SYM_FORCE: no stress trace");
+    if (!(o->flags & SL_FLAG_ORDERED_FORCE) && !lp.stress && o->ordering == SL_ORDER_JACOBI &&
+        sym_by_default(p, lp.fuse != 0))
+      lp.sym = 1;
+    if (lp.sym) {
+      if (p->n > 1 && (s = ensure_sym(p)) != SL_OK) return s;
+      if (p->n <= 1) lp.sym = 0;
+      else lp.slices = 1;
     }
-  }
-  HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
-  if (lp.fuse && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^0
-  if (exact) {
-    int inner = 0;
-    if ((s = run_exact(p, lp, o, use_graph, &inner)) != SL_OK) return s;
-    res.inner_iterations = inner;
-  }
-  const int max_launches = exact ? 0 : o->max_iter / chunk + 2;
-  for (int L = 0; L < max_launches; ++L) {
-    if (use_graph) {
-      HIP_TRY(hipGraphLaunch(p->gexec, p->ps), "hipGraphLaunch");
-    } else {
-      for (int k = 0; k < chunk; ++k)
-        if ((s = enqueue_iteration(p, lp, o)) != SL_OK) return s;
+
+    if ((s = join_from(p, user)) != SL_OK) return s;
+    if (o->omega_vertex && p->n > 0) {
+      std::vector<float> wv(p->n);
+      HIP_TRY(hipMemcpyAsync(wv.data(), o->omega_vertex, sizeof(float) * p->n, hipMemcpyDeviceToHost, p->ps),
+              "omega_vertex copy");
+      HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+      for (int i = 0; i < p->n; ++i)
+        if (!(std::isfinite(wv[i]) && wv[i] > 0.f && wv[i] <= 16.f))
+          return fail(SL_EINVAL, "omega_vertex[%d] = %g outside (0, 16]", i, (double)wv[i]);
     }
-    HIP_TRY(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->ps), "state download");
-    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-    if (h->done) break;
-  }
-  HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
-  HIP_TRY(hipEventSynchronize(p->ev_b), "hipEventSynchronize");
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
-  res.run_ms = ms;
-  const DevState fin = *h;
-  if (!fin.done) return fail(SL_EDEVICE, "iteration loop did not reach its stop flag");
-  if (p->n > 0) HIP_TRY(launch_pack_out(p->Xb, p->st, p->stride, X, p->n, p->dim, p->ps), "unpack kernel");
-  res.iterations = fin.iter;
-  res.converged = fin.converged;
-  res.rejected = fin.rejected;
-  res.residual = fin.residual;
-  if ((s = final_stress(p, fin, o->flags, &res)) != SL_OK) return s;
-  if ((s = join_to(p, user)) != SL_OK) return s;
-  if (out) *out = res;
-  if (fin.status != 0)
-    return fail(SL_ENUMERIC, "non-finite coordinate at iteration %d; X holds the last finite iterate", fin.iter + 1);
-  return SL_OK;
+    if ((o->strategy == SL_OMEGA_SCHEDULE || o->strategy == SL_OMEGA_AUTO) && o->max_iter > 0) {
+      if ((s = upload_schedule(p, o)) != SL_OK) return s;
+      lp.omega_sched = p->sched;
+    }
+    if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
+    DevState* h = p->host_st;
+    std::memset(h, 0, sizeof(DevState));
+    h->max_iter = o->max_iter;
+    h->done = (o->max_iter == 0 || p->n <= 1) ? 1 : 0;
+    h->converged = p->n <= 1 ? 1 : 0;
+    HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
+
+    // iterations per captured graph between looks at the stop flag (those after
+    // the stop return at once)
+    // (not capped by max_iter: runs of any length replay the same captured graph,
+    // whose iterations after the stop return at once)
+    const int chunk = o->check_every > 0 ? o->check_every : (p->n <= 8192 ? 32 : 8);
+    const bool use_graph = !(o->flags & SL_FLAG_NO_GRAPH);
+    const bool exact = o->ordering == SL_ORDER_EXACT;
+    if (use_graph && !exact) {
+      std::vector<double> key = {(double)p->dim, lp.omega_p, lp.tol, (double)lp.safeguard, (double)lp.stress,
+                                 (double)lp.sym, (double)lp.fuse,
+                                 (double)chunk, (double)(uintptr_t)o->trace, (double)(uintptr_t)o->xtrace,
+                                 (double)lp.enumerate, (double)(uintptr_t)lp.omega_sched,
+                                 (double)(uintptr_t)lp.omega_vertex};
+      if (!p->gexec || key != p->gkey) {
+        if (p->gexec) {
+          (void)hipGraphExecDestroy(p->gexec);
+          p->gexec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        sl_status cs = SL_OK;
+        for (int k = 0; k < chunk && cs == SL_OK; ++k) cs = enqueue_iteration(p, lp, o);
+        hipError_t ce = hipStreamEndCapture(p->ps, &graph);
+        if (cs != SL_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return cs;
+        }
+        if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+        hipError_t ie = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+          p->gexec = nullptr;
+          return hip_fail(ie, "hipGraphInstantiate");
+        }
+        p->gkey = key;
+      }
+    }
+    HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+    if (lp.fuse && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^0
+    if (exact) {
+      int inner = 0;
+      if ((s = run_exact(p, lp, o, use_graph, &inner)) != SL_OK) return s;
+      res.inner_iterations = inner;
+    }
+    const int max_launches = exact ? 0 : o->max_iter / chunk + 2;
+    for (int L = 0; L < max_launches; ++L) {
+      if (use_graph) {
+        HIP_TRY(hipGraphLaunch(p->gexec, p->ps), "hipGraphLaunch");
+      } else {
+        for (int k = 0; k < chunk; ++k)
+          if ((s = enqueue_iteration(p, lp, o)) != SL_OK) return s;
+      }
+      HIP_TRY(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->ps), "state download");
+      HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+      if (h->done) break;
+    }
+    HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+    HIP_TRY(hipEventSynchronize(p->ev_b), "hipEventSynchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+    res.run_ms = ms;
+    const DevState fin = *h;
+    if (!fin.done) return fail(SL_EDEVICE, "iteration loop did not reach its stop flag");
+    if (p->n > 0) HIP_TRY(launch_pack_out(p->Xb, p->st, p->stride, X, p->n, p->dim, p->ps), "unpack kernel");
+    res.iterations = fin.iter;
+    res.converged = fin.converged;
+    res.rejected = fin.rejected;
+    res.residual = fin.residual;
+    if ((s = final_stress(p, fin, o->flags, &res)) != SL_OK) return s;
+    if ((s = join_to(p, user)) != SL_OK) return s;
+    if (out) *out = res;
+    if (fin.status != 0)
+      return fail(SL_ENUMERIC, "non-finite coordinate at iteration %d; X holds the last finite iterate", fin.iter + 1);
+    return SL_OK;
+  });
 }
 
 sl_status sl_plan_stress(sl_plan* p, const float* X, int32_t dim, void* stream, double* f) {
-  g_err.clear();
-  if (!p || !f) return fail(SL_EINVAL, "plan or f is NULL");
-  if (dim != p->dim) return fail(SL_EINVAL, "dim %d differs from the plan's %d", dim, p->dim);
-  if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
-  sl_status s = join_from(p, (hipStream_t)stream);
-  if (s != SL_OK) return s;
-  if (p->n <= 1) {
-    *f = 0.0;
-    return SL_OK;
-  }
-  HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
-  if ((s = stress_pass(p, 0, f)) != SL_OK) return s;
-  return join_to(p, (hipStream_t)stream);
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p || !f) return fail(SL_EINVAL, "plan or f is NULL");
+    if (dim != p->dim) return fail(SL_EINVAL, "dim %d differs from the plan's %d", dim, p->dim);
+    if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
+    sl_status s = join_from(p, (hipStream_t)stream);
+    if (s != SL_OK) return s;
+    if (p->n <= 1) {
+      *f = 0.0;
+      return SL_OK;
+    }
+    HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
+    if ((s = stress_pass(p, 0, f)) != SL_OK) return s;
+    return join_to(p, (hipStream_t)stream);
+  });
 }
 
 sl_status sl_plan_profile(sl_plan* p, const float* X, int32_t dim, double omega, int32_t reps, void* stream,
                           double* ms) {
-  g_err.clear();
-  if (!p || !ms) return fail(SL_EINVAL, "plan or ms is NULL");
-  if (dim != p->dim) return fail(SL_EINVAL, "dim %d differs from the plan's %d", dim, p->dim);
-  if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
-  if (reps < 1) return fail(SL_EINVAL, "reps must be >= 1");
-  if (!(std::isfinite(omega) && omega > 0.0 && omega <= 16.0)) return fail(SL_EINVAL, "omega outside (0, 16]");
-  sl_status s = join_from(p, (hipStream_t)stream);
-  if (s != SL_OK) return s;
-  for (int k = 0; k < 9; ++k) ms[k] = 0.0;
-  if (p->n <= 1) return SL_OK;
-  if (!p->df && (s = ensure_exact(p)) != SL_OK) return s;  // the L^W matvec exists for hop-count plans
-  const bool lws = lw_sym_for(p, 0);  // the exact step's default matvec
-  if (lws && (s = ensure_lw_sym(p)) != SL_OK) return s;
-  LoopParams lp{};
-  lp.n = p->n;
-  lp.n_pad = p->n_pad;
-  lp.ng = p->sp.ng;
-  lp.nrb = p->sp.nrb;
-  lp.slices = p->sp.slices;
-  lp.groups_per_slice = p->sp.groups_per_slice;
-  lp.omega_p = omega - 1.0;
-  lp.tol = -1.0;  // never stop while timing
-  lp.safeguard = 1;
-  lp.stress = 0;
-  lp.sym = 0;  // the force pass sl_plan_run uses by default
-  if ((s = ensure_sym(p)) != SL_OK) return s;  // for ms[5] and ms[7]
-  HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
-  DevState* h = p->host_st;
-  std::memset(h, 0, sizeof(DevState));
-  h->max_iter = INT32_MAX;
-  HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
-  LoopParams lpf = lp;  // the fused pass, extrapolating with omega
-  lpf.fuse = 1;
-  lpf.safeguard = 1;
-  for (int which = 0; which < 9; ++which) {
-    if (which == 4 && p->df) continue;
-    if (which == 4) {  // a solver state from the current placement: r_0, z
-      HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
-                           p->ps), "force kernel");
-      HIP_TRY(launch_cg_init(p->dim, p->cg, p->fpart, p->sp.slices, p->W, p->comp, p->n, p->Xb, p->stride, p->st, p->cg_st,
-                             p->cg_part, p->ps),
-              "conjugate-gradient init kernel");
-    }
-    for (int r = -1; r < reps; ++r) {  // one untimed launch first
-      if (r == 0) HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
-      switch (which) {
-        case 4:
-          if (lws)
-            HIP_TRY(launch_lw_sym(p->dim, p->cg.pd, p->d, p->W, p->st, p->cg_st, p->lw_sym, p->fpart,
-                                  p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->n_pad, p->ps),
-                    "L^W kernels");
-          else
-            HIP_TRY(launch_lw(p->dim, p->cg, p->d, p->W, p->st, p->cg_st, p->fpart,
-                              p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->sp, p->ps),
-                    "L^W kernel");
-          break;
-        case 0:
-          if ((s = enqueue_force(p, lp)) != SL_OK) return s;
-          break;
-        case 6:
-          HIP_TRY(launch_force_sg(p->dim, lpf, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart,
-                                  p->sp, p->ps),
-                  "fused force and safeguard kernel");
-          break;
-        case 5:
-          HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->df, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
-                                   p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
-                  "symmetric force kernels");
-          break;
-        case 7:
-          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 0, 0, kSymReducePass, p->d, p->df, p->Xb, p->stride, p->Eb, p->st,
-                                      p->sym_items,
-                                      p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
-                                      p->n_pad, p->ps),
-                  "symmetric fused force and safeguard kernels");
-          break;
-        case 8:
-          HIP_TRY(launch_force_sym_sg(p->dim, lpf, 1, 0, kSymReducePass, p->d, p->df, p->Xb, p->stride, p->Eb, p->st,
-                                      p->sym_items,
-                                      p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
-                                      p->n_pad, p->ps),
-                  "symmetric fused force and exact safeguard kernels");
-          break;
-        case 1:
-          HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red,
-                                p->ps),
-                  "update kernel");
-          break;
-        case 2:
-          HIP_TRY(launch_sgdelta(p->dim, p->d, p->df, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart,
-                                 p->sp, p->ps),
-                  "safeguard kernel");
-          break;
-        default:
-          HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsg, p->st, nullptr, p->ps),
-                  "select kernel");
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p || !ms) return fail(SL_EINVAL, "plan or ms is NULL");
+    if (dim != p->dim) return fail(SL_EINVAL, "dim %d differs from the plan's %d", dim, p->dim);
+    if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
+    if (reps < 1) return fail(SL_EINVAL, "reps must be >= 1");
+    if (!(std::isfinite(omega) && omega > 0.0 && omega <= 16.0)) return fail(SL_EINVAL, "omega outside (0, 16]");
+    sl_status s = join_from(p, (hipStream_t)stream);
+    if (s != SL_OK) return s;
+    for (int k = 0; k < 9; ++k) ms[k] = 0.0;
+    if (p->n <= 1) return SL_OK;
+    if (!p->df && (s = ensure_exact(p)) != SL_OK) return s;  // the L^W matvec exists for hop-count plans
+    const bool lws = lw_sym_for(p, 0);  // the exact step's default matvec
+    if (lws && (s = ensure_lw_sym(p)) != SL_OK) return s;
+    LoopParams lp{};
+    lp.n = p->n;
+    lp.n_pad = p->n_pad;
+    lp.ng = p->sp.ng;
+    lp.nrb = p->sp.nrb;
+    lp.slices = p->sp.slices;
+    lp.groups_per_slice = p->sp.groups_per_slice;
+    lp.omega_p = omega - 1.0;
+    lp.tol = -1.0;  // never stop while timing
+    lp.safeguard = 1;
+    lp.stress = 0;
+    lp.sym = 0;  // the force pass sl_plan_run uses by default
+    if ((s = ensure_sym(p)) != SL_OK) return s;  // for ms[5] and ms[7]
+    HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
+    DevState* h = p->host_st;
+    std::memset(h, 0, sizeof(DevState));
+    h->max_iter = INT32_MAX;
+    HIP_TRY(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->ps), "state upload");
+    LoopParams lpf = lp;  // the fused pass, extrapolating with omega
+    lpf.fuse = 1;
+    lpf.safeguard = 1;
+    for (int which = 0; which < 9; ++which) {
+      if (which == 4 && p->df) continue;
+      if (which == 4) {  // a solver state from the current placement: r_0, z
+        HIP_TRY(launch_force(p->dim, false, p->d, p->df, p->Xb, p->stride, p->st, p->fpart, p->spart, p->sp, p->n_pad,
+                             p->ps), "force kernel");
+        HIP_TRY(launch_cg_init(p->dim, p->cg, p->fpart, p->sp.slices, p->W, p->comp, p->n, p->Xb, p->stride, p->st, p->cg_st,
+                               p->cg_part, p->ps),
+                "conjugate-gradient init kernel");
       }
+      for (int r = -1; r < reps; ++r) {  // one untimed launch first
+        if (r == 0) HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+        switch (which) {
+          case 4:
+            if (lws)
+              HIP_TRY(launch_lw_sym(p->dim, p->cg.pd, p->d, p->W, p->st, p->cg_st, p->lw_sym, p->fpart,
+                                    p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->n_pad, p->ps),
+                      "L^W kernels");
+            else
+              HIP_TRY(launch_lw(p->dim, p->cg, p->d, p->W, p->st, p->cg_st, p->fpart,
+                                p->cg_part + (size_t)kCgSlots * cg_blocks(p->n_pad) * 8, p->sp, p->ps),
+                      "L^W kernel");
+            break;
+          case 0:
+            if ((s = enqueue_force(p, lp)) != SL_OK) return s;
+            break;
+          case 6:
+            HIP_TRY(launch_force_sg(p->dim, lpf, p->d, p->df, p->Xb, p->stride, p->Eb, p->st, p->fpart, p->sgpart,
+                                    p->sp, p->ps),
+                    "fused force and safeguard kernel");
+            break;
+          case 5:
+            HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->df, p->Xb, p->stride, p->st, p->sym_items, p->nsym_items,
+                                     p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
+                    "symmetric force kernels");
+            break;
+          case 7:
+            HIP_TRY(launch_force_sym_sg(p->dim, lpf, 0, 0, kSymReducePass, p->d, p->df, p->Xb, p->stride, p->Eb, p->st,
+                                        p->sym_items,
+                                        p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
+                                        p->n_pad, p->ps),
+                    "symmetric fused force and safeguard kernels");
+            break;
+          case 8:
+            HIP_TRY(launch_force_sym_sg(p->dim, lpf, 1, 0, kSymReducePass, p->d, p->df, p->Xb, p->stride, p->Eb, p->st,
+                                        p->sym_items,
+                                        p->nsym_items, p->sym_panel_items, p->Pi, p->Pj, p->sgpart, p->fpart, p->edot,
+                                        p->n_pad, p->ps),
+                    "symmetric fused force and exact safeguard kernels");
+            break;
+          case 1:
+            HIP_TRY(launch_update(p->dim, lp, p->fpart, p->spart, p->W, p->Xb, p->stride, p->Eb, p->st, p->red,
+                                  p->ps),
+                    "update kernel");
+            break;
+          case 2:
+            HIP_TRY(launch_sgdelta(p->dim, p->d, p->df, p->Xb, p->stride, p->Eb, p->items, p->nsg, p->st, p->sgpart,
+                                   p->sp, p->ps),
+                    "safeguard kernel");
+            break;
+          default:
+            HIP_TRY(launch_select(p->dim, lp, p->red, p->nred, p->sgpart, p->nsg, p->st, nullptr, p->ps),
+                    "select kernel");
+        }
+      }
+      HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+      HIP_TRY(hipEventSynchronize(p->ev_b), "hipEventSynchronize");
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, p->ev_a, p->ev_b), "hipEventElapsedTime");
+      ms[which] = (double)t / reps;
     }
-    HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
-    HIP_TRY(hipEventSynchronize(p->ev_b), "hipEventSynchronize");
-    float t = 0.f;
-    HIP_TRY(hipEventElapsedTime(&t, p->ev_a, p->ev_b), "hipEventElapsedTime");
-    ms[which] = (double)t / reps;
-  }
-  return join_to(p, (hipStream_t)stream);
+    return join_to(p, (hipStream_t)stream);
+  });
 }
 
 namespace {
@@ -1269,79 +1311,89 @@ sl_status gather_rows(sl_plan* p, const int32_t* rows, int32_t nrows, hipStream_
 }  // namespace
 
 sl_status sl_plan_distance_rows(sl_plan* p, const int32_t* rows, int32_t nrows, void* stream, uint8_t* out) {
-  g_err.clear();
-  sl_status s = check_rows(p, rows, nrows, out);
-  if (s != SL_OK) return s;
-  if (p->df) return fail(SL_EINVAL, "the plan holds edge-length distances: use sl_plan_distance_rows_f32");
-  if (nrows == 0 || p->n == 0) return SL_OK;
-  std::vector<float> tmp((size_t)nrows * p->n);
-  if ((s = gather_rows(p, rows, nrows, (hipStream_t)stream, tmp.data())) != SL_OK) return s;
-  for (size_t q = 0; q < tmp.size(); ++q) out[q] = (uint8_t)tmp[q];
-  return SL_OK;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    sl_status s = check_rows(p, rows, nrows, out);
+    if (s != SL_OK) return s;
+    if (p->df) return fail(SL_EINVAL, "the plan holds edge-length distances: use sl_plan_distance_rows_f32");
+    if (nrows == 0 || p->n == 0) return SL_OK;
+    std::vector<float> tmp((size_t)nrows * p->n);
+    if ((s = gather_rows(p, rows, nrows, (hipStream_t)stream, tmp.data())) != SL_OK) return s;
+    for (size_t q = 0; q < tmp.size(); ++q) out[q] = (uint8_t)tmp[q];
+    return SL_OK;
+  });
 }
 
 sl_status sl_plan_distance_rows_f32(sl_plan* p, const int32_t* rows, int32_t nrows, void* stream, float* out) {
-  g_err.clear();
-  sl_status s = check_rows(p, rows, nrows, out);
-  if (s != SL_OK) return s;
-  if (nrows == 0 || p->n == 0) return SL_OK;
-  return gather_rows(p, rows, nrows, (hipStream_t)stream, out);
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    sl_status s = check_rows(p, rows, nrows, out);
+    if (s != SL_OK) return s;
+    if (nrows == 0 || p->n == 0) return SL_OK;
+    return gather_rows(p, rows, nrows, (hipStream_t)stream, out);
+  });
 }
 
 sl_status sl_plan_tree_rows(sl_plan* p, const int32_t* rows, int32_t nrows, void* stream, int32_t* out) {
-  g_err.clear();
-  sl_status s = check_rows(p, rows, nrows, out);
-  if (s != SL_OK) return s;
-  if (!p->pred) return fail(SL_EINVAL, "shortest-path trees are kept for edge-length plans only");
-  if (nrows == 0 || p->n == 0) return SL_OK;
-  if ((s = join_from(p, (hipStream_t)stream)) != SL_OK) return s;
-  for (int k = 0; k < nrows; ++k)
-    HIP_TRY(hipMemcpyAsync(out + (size_t)k * p->n, p->pred + (size_t)rows[k] * p->n, sizeof(int32_t) * p->n,
-                           hipMemcpyDeviceToHost, p->ps),
-            "tree rows copy");
-  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-  return SL_OK;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    sl_status s = check_rows(p, rows, nrows, out);
+    if (s != SL_OK) return s;
+    if (!p->pred) return fail(SL_EINVAL, "shortest-path trees are kept for edge-length plans only");
+    if (nrows == 0 || p->n == 0) return SL_OK;
+    if ((s = join_from(p, (hipStream_t)stream)) != SL_OK) return s;
+    for (int k = 0; k < nrows; ++k)
+      HIP_TRY(hipMemcpyAsync(out + (size_t)k * p->n, p->pred + (size_t)rows[k] * p->n, sizeof(int32_t) * p->n,
+                             hipMemcpyDeviceToHost, p->ps),
+              "tree rows copy");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    return SL_OK;
+  });
 }
 
 sl_status sl_plan_set_lengths(sl_plan* p, const float* edge_len, void* stream) {
-  g_err.clear();
-  if (!p) return fail(SL_EINVAL, "plan is NULL");
-  if (!p->df) return fail(SL_EINVAL, "the plan was created without edge lengths");
-  if (p->nnz > 0 && !edge_len) return fail(SL_EINVAL, "edge_len is NULL");
-  std::vector<int64_t> rp(p->n + 1);
-  std::vector<int32_t> ci((size_t)p->nnz);
-  sl_status s = join_from(p, (hipStream_t)stream);
-  if (s != SL_OK) return s;
-  HIP_TRY(hipMemcpyAsync(rp.data(), p->g_row_ptr, sizeof(int64_t) * (p->n + 1), hipMemcpyDeviceToHost, p->ps),
-          "graph copy");
-  if (p->nnz > 0)
-    HIP_TRY(hipMemcpyAsync(ci.data(), p->g_col_idx, sizeof(int32_t) * p->nnz, hipMemcpyDeviceToHost, p->ps),
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return fail(SL_EINVAL, "plan is NULL");
+    if (!p->df) return fail(SL_EINVAL, "the plan was created without edge lengths");
+    if (p->nnz > 0 && !edge_len) return fail(SL_EINVAL, "edge_len is NULL");
+    std::vector<int64_t> rp(p->n + 1);
+    std::vector<int32_t> ci((size_t)p->nnz);
+    sl_status s = join_from(p, (hipStream_t)stream);
+    if (s != SL_OK) return s;
+    HIP_TRY(hipMemcpyAsync(rp.data(), p->g_row_ptr, sizeof(int64_t) * (p->n + 1), hipMemcpyDeviceToHost, p->ps),
             "graph copy");
-  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-  sl_graph g{p->n, p->nnz, rp.data(), ci.data(), edge_len};
-  if ((s = check_lengths(&g, edge_len)) != SL_OK) return s;
-  if (p->nnz > 0)
-    HIP_TRY(hipMemcpyAsync(p->g_len, edge_len, sizeof(float) * p->nnz, hipMemcpyHostToDevice, p->ps),
-            "lengths upload");
-  HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
-  if ((s = build_weighted(p)) != SL_OK) return s;
-  HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
-  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
-  p->plan_ms = ms;
-  return join_to(p, (hipStream_t)stream);
+    if (p->nnz > 0)
+      HIP_TRY(hipMemcpyAsync(ci.data(), p->g_col_idx, sizeof(int32_t) * p->nnz, hipMemcpyDeviceToHost, p->ps),
+              "graph copy");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    sl_graph g{p->n, p->nnz, rp.data(), ci.data(), edge_len};
+    if ((s = check_lengths(&g, edge_len)) != SL_OK) return s;
+    if (p->nnz > 0)
+      HIP_TRY(hipMemcpyAsync(p->g_len, edge_len, sizeof(float) * p->nnz, hipMemcpyHostToDevice, p->ps),
+              "lengths upload");
+    HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+    if ((s = build_weighted(p)) != SL_OK) return s;
+    HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+    p->plan_ms = ms;
+    return join_to(p, (hipStream_t)stream);
+  });
 }
 
 sl_status sl_plan_weights(sl_plan* p, void* stream, double* W) {
-  g_err.clear();
-  if (!p || !W) return fail(SL_EINVAL, "plan or W is NULL");
-  if (p->n == 0) return SL_OK;
-  sl_status s = join_from(p, (hipStream_t)stream);
-  if (s != SL_OK) return s;
-  HIP_TRY(hipMemcpyAsync(W, p->W, sizeof(double) * p->n, hipMemcpyDeviceToHost, p->ps), "weights copy");
-  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-  return SL_OK;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p || !W) return fail(SL_EINVAL, "plan or W is NULL");
+    if (p->n == 0) return SL_OK;
+    sl_status s = join_from(p, (hipStream_t)stream);
+    if (s != SL_OK) return s;
+    HIP_TRY(hipMemcpyAsync(W, p->W, sizeof(double) * p->n, hipMemcpyDeviceToHost, p->ps), "weights copy");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    return SL_OK;
+  });
 }
 
 namespace {
@@ -1406,208 +1458,216 @@ sl_status set_state(sl_plan* p, DevState* dst, int iter, int max_iter) {
 }  // namespace
 
 sl_status sl_plan_stress_grad(sl_plan* p, const float* X, int32_t dim, void* stream, double* f, float* G) {
-  g_err.clear();
-  if (!p || !f) return fail(SL_EINVAL, "plan or f is NULL");
-  if (dim != p->dim) return fail(SL_EINVAL, "dim %d differs from the plan's %d", dim, p->dim);
-  if ((!X || !G) && p->n > 0) return fail(SL_EINVAL, "X or G is NULL");
-  sl_status s = join_from(p, (hipStream_t)stream);
-  if (s != SL_OK) return s;
-  *f = 0.0;
-  if (p->n == 0) return SL_OK;
-  if (p->n == 1) {
-    HIP_TRY(hipMemsetAsync(G, 0, sizeof(float) * dim, p->ps), "hipMemsetAsync");
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p || !f) return fail(SL_EINVAL, "plan or f is NULL");
+    if (dim != p->dim) return fail(SL_EINVAL, "dim %d differs from the plan's %d", dim, p->dim);
+    if ((!X || !G) && p->n > 0) return fail(SL_EINVAL, "X or G is NULL");
+    sl_status s = join_from(p, (hipStream_t)stream);
+    if (s != SL_OK) return s;
+    *f = 0.0;
+    if (p->n == 0) return SL_OK;
+    if (p->n == 1) {
+      HIP_TRY(hipMemsetAsync(G, 0, sizeof(float) * dim, p->ps), "hipMemsetAsync");
+      return join_to(p, (hipStream_t)stream);
+    }
+    HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
+    if ((s = stress_pass(p, 0, f)) != SL_OK) return s;
+    HIP_TRY(launch_stress_grad_out(p->fpart, p->sp.slices, p->n, p->n_pad, p->dim, G, p->ps), "gradient kernel");
     return join_to(p, (hipStream_t)stream);
-  }
-  HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
-  if ((s = stress_pass(p, 0, f)) != SL_OK) return s;
-  HIP_TRY(launch_stress_grad_out(p->fpart, p->sp.slices, p->n, p->n_pad, p->dim, G, p->ps), "gradient kernel");
-  return join_to(p, (hipStream_t)stream);
+  });
 }
 
 sl_status sl_plan_unroll(sl_plan* p, float* X, const sl_options* o, int32_t ckpt_every, void* stream,
                          sl_result* out) {
-  g_err.clear();
-  if (!p) return fail(SL_EINVAL, "plan is NULL");
-  sl_status s = check_options(o);
-  if (s != SL_OK) return s;
-  if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
-  if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
-  if (o->strategy != SL_OMEGA_FIXED || o->omega_vertex || o->ordering != SL_ORDER_JACOBI)
-    return fail(SL_ENOTSUP, "unrolled runs take the Jacobi step with a fixed omega");
-  if (o->trace || o->xtrace) return fail(SL_EINVAL, "unrolled runs keep their own trace");
-  if (ckpt_every < 1) return fail(SL_EINVAL, "ckpt_every = %d must be >= 1", ckpt_every);
-  const int K = o->max_iter, c = ckpt_every;
-  const int nseg = (K + c - 1) / c;
-  if ((s = join_from(p, (hipStream_t)stream)) != SL_OK) return s;
-  size_t cap = p->ckpt_cap;
-  if ((s = grow((void**)&p->ckpt, &cap, (size_t)std::max(nseg, 1) * p->stride, sizeof(float), "checkpoints")) != SL_OK)
-    return s;
-  p->ckpt_cap = cap;
-  size_t tcap = (size_t)p->tape_cap * SL_TRACE_COLS;
-  if ((s = grow((void**)&p->tape_trace, &tcap, (size_t)std::max(K, 1) * SL_TRACE_COLS, sizeof(double), "tape")) != SL_OK)
-    return s;
-  p->tape_cap = (int)(tcap / SL_TRACE_COLS);
-  p->tape_K = -1;
-  sl_options oo = *o;
-  oo.trace = p->tape_trace;
-  oo.xtrace = nullptr;
-  oo.flags &= ~SL_FLAG_TRACE_STRESS;
-  int sym = 0;
-  // the rule of sl_plan_run, so that the unrolled run equals it bit for bit
-  if ((s = unroll_sym(p, o->flags, o->safeguard && o->omega != 1.0 && p->n > 1, &sym)) != SL_OK) return s;
-  const LoopParams lp = unroll_params(p, o->omega, o->safeguard, sym);
-  sl_result res{};
-  res.plan_ms = p->plan_ms;
-  if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
-  if ((s = set_state(p, p->st, 0, K)) != SL_OK) return s;
-  HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
-  if (K > 0) HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->ckpt, p->ps), "checkpoint kernel");
-  if (lp.fuse && K > 0 && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^0
-  for (int k = 0; k < K && p->n > 1; ++k) {
-    if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
-    if ((k + 1) % c == 0 && k + 1 < K)
-      HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->ckpt + (size_t)((k + 1) / c) * p->stride, p->ps),
-              "checkpoint kernel");
-  }
-  HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
-  DevState* h = p->host_st;
-  HIP_TRY(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->ps), "state download");
-  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
-  res.run_ms = ms;
-  const DevState fin = *h;
-  if (p->n > 0) HIP_TRY(launch_pack_out(p->Xb, p->st, p->stride, X, p->n, p->dim, p->ps), "unpack kernel");
-  res.iterations = fin.iter;
-  res.converged = fin.converged;
-  res.rejected = fin.rejected;
-  res.residual = fin.residual;
-  if ((s = final_stress(p, fin, o->flags, &res)) != SL_OK) return s;
-  if ((s = join_to(p, (hipStream_t)stream)) != SL_OK) return s;
-  if (out) *out = res;
-  if (fin.status != 0)
-    return fail(SL_ENUMERIC, "non-finite coordinate at iteration %d; X holds the last finite iterate", fin.iter + 1);
-  p->tape_sym = sym;
-  p->tape_K = K;
-  p->tape_c = c;
-  p->tape_omega = o->omega;
-  p->tape_safeguard = o->safeguard;
-  return SL_OK;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return fail(SL_EINVAL, "plan is NULL");
+    sl_status s = check_options(o);
+    if (s != SL_OK) return s;
+    if (o->dim != p->dim) return fail(SL_EINVAL, "options dim %d differs from the plan's %d", o->dim, p->dim);
+    if (!X && p->n > 0) return fail(SL_EINVAL, "X is NULL");
+    if (o->strategy != SL_OMEGA_FIXED || o->omega_vertex || o->ordering != SL_ORDER_JACOBI)
+      return fail(SL_ENOTSUP, "unrolled runs take the Jacobi step with a fixed omega");
+    if (o->trace || o->xtrace) return fail(SL_EINVAL, "unrolled runs keep their own trace");
+    if (ckpt_every < 1) return fail(SL_EINVAL, "ckpt_every = %d must be >= 1", ckpt_every);
+    const int K = o->max_iter, c = ckpt_every;
+    const int nseg = (K + c - 1) / c;
+    if ((s = join_from(p, (hipStream_t)stream)) != SL_OK) return s;
+    size_t cap = p->ckpt_cap;
+    if ((s = grow((void**)&p->ckpt, &cap, (size_t)std::max(nseg, 1) * p->stride, sizeof(float), "checkpoints")) != SL_OK)
+      return s;
+    p->ckpt_cap = cap;
+    size_t tcap = (size_t)p->tape_cap * SL_TRACE_COLS;
+    if ((s = grow((void**)&p->tape_trace, &tcap, (size_t)std::max(K, 1) * SL_TRACE_COLS, sizeof(double), "tape")) != SL_OK)
+      return s;
+    p->tape_cap = (int)(tcap / SL_TRACE_COLS);
+    p->tape_K = -1;
+    sl_options oo = *o;
+    oo.trace = p->tape_trace;
+    oo.xtrace = nullptr;
+    oo.flags &= ~SL_FLAG_TRACE_STRESS;
+    int sym = 0;
+    // the rule of sl_plan_run, so that the unrolled run equals it bit for bit
+    if ((s = unroll_sym(p, o->flags, o->safeguard && o->omega != 1.0 && p->n > 1, &sym)) != SL_OK) return s;
+    const LoopParams lp = unroll_params(p, o->omega, o->safeguard, sym);
+    sl_result res{};
+    res.plan_ms = p->plan_ms;
+    if (p->n > 0) HIP_TRY(launch_pack_in(X, p->Xb, p->n, p->n_pad, p->dim, p->ps), "pack kernel");
+    if ((s = set_state(p, p->st, 0, K)) != SL_OK) return s;
+    HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+    if (K > 0) HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->ckpt, p->ps), "checkpoint kernel");
+    if (lp.fuse && K > 0 && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^0
+    for (int k = 0; k < K && p->n > 1; ++k) {
+      if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
+      if ((k + 1) % c == 0 && k + 1 < K)
+        HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->ckpt + (size_t)((k + 1) / c) * p->stride, p->ps),
+                "checkpoint kernel");
+    }
+    HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+    DevState* h = p->host_st;
+    HIP_TRY(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->ps), "state download");
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+    res.run_ms = ms;
+    const DevState fin = *h;
+    if (p->n > 0) HIP_TRY(launch_pack_out(p->Xb, p->st, p->stride, X, p->n, p->dim, p->ps), "unpack kernel");
+    res.iterations = fin.iter;
+    res.converged = fin.converged;
+    res.rejected = fin.rejected;
+    res.residual = fin.residual;
+    if ((s = final_stress(p, fin, o->flags, &res)) != SL_OK) return s;
+    if ((s = join_to(p, (hipStream_t)stream)) != SL_OK) return s;
+    if (out) *out = res;
+    if (fin.status != 0)
+      return fail(SL_ENUMERIC, "non-finite coordinate at iteration %d; X holds the last finite iterate", fin.iter + 1);
+    p->tape_sym = sym;
+    p->tape_K = K;
+    p->tape_c = c;
+    p->tape_omega = o->omega;
+    p->tape_safeguard = o->safeguard;
+    return SL_OK;
+  });
 }
 
 sl_status sl_plan_unroll_backward(sl_plan* p, const float* G, float* gX0, float* glen, void* stream) {
-  g_err.clear();
-  if (!p) return fail(SL_EINVAL, "plan is NULL");
-  if (p->tape_K < 0) return fail(SL_EINVAL, "no unrolled run to differentiate (call sl_plan_unroll first)");
-  if ((!G || !gX0) && p->n > 0) return fail(SL_EINVAL, "G or gX0 is NULL");
-  if (glen && !p->df) return fail(SL_EINVAL, "edge-length derivatives need a plan created with edge lengths");
-  const int K = p->tape_K, c = p->tape_c;
-  const int nseg = (K + c - 1) / c;
-  sl_status s = join_from(p, (hipStream_t)stream);
-  if (s != SL_OK) return s;
-  if (p->n == 0) return SL_OK;
-  const size_t col = (size_t)3 * p->n_pad;
-  size_t cap = p->gb ? col : 0;
-  if ((s = grow((void**)&p->gb, &cap, col, sizeof(double), "adjoint buffers")) != SL_OK) return s;
-  if ((s = grow((void**)&p->gvec, &p->gvec_cap, (size_t)std::max(c, 1) * p->stride, sizeof(float),
-                "adjoint buffers")) != SL_OK)
-    return s;
-  if ((s = grow((void**)&p->wbar, &p->wbar_cap, (size_t)std::max(c, 1) * p->n_pad, sizeof(float),
-                "adjoint buffers")) != SL_OK)
-    return s;
-  size_t scap = (size_t)p->seg_cap * p->stride;
-  if ((s = grow((void**)&p->segX, &scap, (size_t)std::max(c, 1) * p->stride, sizeof(float), "segment buffer")) != SL_OK)
-    return s;
-  p->seg_cap = (int)(scap / p->stride);
-  if (glen) {
-    cap = p->Dbar ? (size_t)p->n_pad * p->n_pad : 0;
-    if ((s = grow((void**)&p->Dbar, &cap, (size_t)p->n_pad * p->n_pad, sizeof(float), "distance adjoint")) != SL_OK)
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return fail(SL_EINVAL, "plan is NULL");
+    if (p->tape_K < 0) return fail(SL_EINVAL, "no unrolled run to differentiate (call sl_plan_unroll first)");
+    if ((!G || !gX0) && p->n > 0) return fail(SL_EINVAL, "G or gX0 is NULL");
+    if (glen && !p->df) return fail(SL_EINVAL, "edge-length derivatives need a plan created with edge lengths");
+    const int K = p->tape_K, c = p->tape_c;
+    const int nseg = (K + c - 1) / c;
+    sl_status s = join_from(p, (hipStream_t)stream);
+    if (s != SL_OK) return s;
+    if (p->n == 0) return SL_OK;
+    const size_t col = (size_t)3 * p->n_pad;
+    size_t cap = p->gb ? col : 0;
+    if ((s = grow((void**)&p->gb, &cap, col, sizeof(double), "adjoint buffers")) != SL_OK) return s;
+    if ((s = grow((void**)&p->gvec, &p->gvec_cap, (size_t)std::max(c, 1) * p->stride, sizeof(float),
+                  "adjoint buffers")) != SL_OK)
       return s;
-    cap = p->Sbuf ? (size_t)p->n * p->n : 0;
-    if ((s = grow((void**)&p->Sbuf, &cap, (size_t)p->n * p->n, sizeof(float), "distance adjoint")) != SL_OK) return s;
-    cap = p->Gedge ? (size_t)p->nnz : 0;
-    if ((s = grow((void**)&p->Gedge, &cap, (size_t)std::max<int64_t>(p->nnz, 1), sizeof(double), "edge adjoint")) !=
-        SL_OK)
+    if ((s = grow((void**)&p->wbar, &p->wbar_cap, (size_t)std::max(c, 1) * p->n_pad, sizeof(float),
+                  "adjoint buffers")) != SL_OK)
       return s;
-    HIP_TRY(hipMemsetAsync(p->Dbar, 0, sizeof(float) * (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync");
-  }
-  std::vector<double> tr((size_t)std::max(K, 1) * SL_TRACE_COLS);
-  if (K > 0)
-    HIP_TRY(hipMemcpyAsync(tr.data(), p->tape_trace, sizeof(double) * K * SL_TRACE_COLS, hipMemcpyDeviceToHost,
-                           p->ps),
-            "tape download");
-  HIP_TRY(launch_grad_in(G, p->gb, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
-  const LoopParams lp = unroll_params(p, p->tape_omega, p->tape_safeguard, p->tape_sym);
-  sl_options oo;
-  sl_default_options(&oo);
-  oo.dim = p->dim;
-  if ((s = set_state(p, p->st_eval, 0, 1)) != SL_OK) return s;  // cur = 0: force passes read the pointer given
-  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-  for (int m = nseg - 1; m >= 0 && p->n > 1; --m) {
-    const int k0 = m * c, k1 = std::min(k0 + c, K);
-    // recompute X^{k0} .. X^{k1-1} from the checkpoint
-    HIP_TRY(hipMemcpyAsync(p->segX, p->ckpt + (size_t)m * p->stride, sizeof(float) * p->stride,
-                           hipMemcpyDeviceToDevice, p->ps),
-            "checkpoint copy");
-    if (k1 - k0 > 1) {
-      HIP_TRY(hipMemcpyAsync(p->Xb, p->segX, sizeof(float) * p->stride, hipMemcpyDeviceToDevice, p->ps),
-              "checkpoint copy");
-      if ((s = set_state(p, p->st, k0, K)) != SL_OK) return s;
-      if (lp.fuse && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^{k0}
-      for (int q = 1; q < k1 - k0; ++q) {
-        if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
-        HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->segX + (size_t)q * p->stride, p->ps), "save kernel");
-      }
+    size_t scap = (size_t)p->seg_cap * p->stride;
+    if ((s = grow((void**)&p->segX, &scap, (size_t)std::max(c, 1) * p->stride, sizeof(float), "segment buffer")) != SL_OK)
+      return s;
+    p->seg_cap = (int)(scap / p->stride);
+    if (glen) {
+      cap = p->Dbar ? (size_t)p->n_pad * p->n_pad : 0;
+      if ((s = grow((void**)&p->Dbar, &cap, (size_t)p->n_pad * p->n_pad, sizeof(float), "distance adjoint")) != SL_OK)
+        return s;
+      cap = p->Sbuf ? (size_t)p->n * p->n : 0;
+      if ((s = grow((void**)&p->Sbuf, &cap, (size_t)p->n * p->n, sizeof(float), "distance adjoint")) != SL_OK) return s;
+      cap = p->Gedge ? (size_t)p->nnz : 0;
+      if ((s = grow((void**)&p->Gedge, &cap, (size_t)std::max<int64_t>(p->nnz, 1), sizeof(double), "edge adjoint")) !=
+          SL_OK)
+        return s;
+      HIP_TRY(hipMemsetAsync(p->Dbar, 0, sizeof(float) * (size_t)p->n_pad * p->n_pad, p->ps), "hipMemsetAsync");
     }
-    for (int k = k1 - 1; k >= k0; --k) {
-      const float* Xk = p->segX + (size_t)(k - k0) * p->stride;
-      // F at X^k by the pass the forward took (the unordered one leaves F in force slice 0)
-      int fslices = p->sp.slices;
-      if (lp.sym) {
-        HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->df, Xk, 0, p->st_eval, p->sym_items, p->nsym_items,
-                                 p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
-                "force kernel");
-        fslices = 1;
-      } else {
-        HIP_TRY(launch_force(p->dim, false, p->d, p->df, Xk, 0, p->st_eval, p->fpart, p->spart, p->sp, p->n_pad,
+    std::vector<double> tr((size_t)std::max(K, 1) * SL_TRACE_COLS);
+    if (K > 0)
+      HIP_TRY(hipMemcpyAsync(tr.data(), p->tape_trace, sizeof(double) * K * SL_TRACE_COLS, hipMemcpyDeviceToHost,
                              p->ps),
-                "force kernel");
+              "tape download");
+    HIP_TRY(launch_grad_in(G, p->gb, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
+    const LoopParams lp = unroll_params(p, p->tape_omega, p->tape_safeguard, p->tape_sym);
+    sl_options oo;
+    sl_default_options(&oo);
+    oo.dim = p->dim;
+    if ((s = set_state(p, p->st_eval, 0, 1)) != SL_OK) return s;  // cur = 0: force passes read the pointer given
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    for (int m = nseg - 1; m >= 0 && p->n > 1; --m) {
+      const int k0 = m * c, k1 = std::min(k0 + c, K);
+      // recompute X^{k0} .. X^{k1-1} from the checkpoint
+      HIP_TRY(hipMemcpyAsync(p->segX, p->ckpt + (size_t)m * p->stride, sizeof(float) * p->stride,
+                             hipMemcpyDeviceToDevice, p->ps),
+              "checkpoint copy");
+      if (k1 - k0 > 1) {
+        HIP_TRY(hipMemcpyAsync(p->Xb, p->segX, sizeof(float) * p->stride, hipMemcpyDeviceToDevice, p->ps),
+                "checkpoint copy");
+        if ((s = set_state(p, p->st, k0, K)) != SL_OK) return s;
+        if (lp.fuse && (s = enqueue_force(p, lp)) != SL_OK) return s;  // the force at X^{k0}
+        for (int q = 1; q < k1 - k0; ++q) {
+          if ((s = enqueue_iteration(p, lp, &oo)) != SL_OK) return s;
+          HIP_TRY(launch_save(p->Xb, p->stride, p->st, p->segX + (size_t)q * p->stride, p->ps), "save kernel");
+        }
       }
-      const double a = tr[(size_t)k * SL_TRACE_COLS + 1] == 1.0 ? p->tape_omega : 1.0;
-      HIP_TRY(launch_adjoint_step(p->dim, p->d, p->df, Xk, p->fpart, fslices, p->W, a, p->gb,
-                                  p->gvec + (size_t)(k - k0) * p->stride, p->wbar + (size_t)(k - k0) * p->n_pad,
-                                  p->fpart, p->sp, p->n_pad, p->ps),
-              "adjoint kernels");
+      for (int k = k1 - 1; k >= k0; --k) {
+        const float* Xk = p->segX + (size_t)(k - k0) * p->stride;
+        // F at X^k by the pass the forward took (the unordered one leaves F in force slice 0)
+        int fslices = p->sp.slices;
+        if (lp.sym) {
+          HIP_TRY(launch_force_sym(p->dim, 0, p->d, p->df, Xk, 0, p->st_eval, p->sym_items, p->nsym_items,
+                                   p->sym_panel_items, p->Pi, p->Pj, p->fpart, p->n_pad, p->ps),
+                  "force kernel");
+          fslices = 1;
+        } else {
+          HIP_TRY(launch_force(p->dim, false, p->d, p->df, Xk, 0, p->st_eval, p->fpart, p->spart, p->sp, p->n_pad,
+                               p->ps),
+                  "force kernel");
+        }
+        const double a = tr[(size_t)k * SL_TRACE_COLS + 1] == 1.0 ? p->tape_omega : 1.0;
+        HIP_TRY(launch_adjoint_step(p->dim, p->d, p->df, Xk, p->fpart, fslices, p->W, a, p->gb,
+                                    p->gvec + (size_t)(k - k0) * p->stride, p->wbar + (size_t)(k - k0) * p->n_pad,
+                                    p->fpart, p->sp, p->n_pad, p->ps),
+                "adjoint kernels");
+      }
+      // dL/dd of the segment's iterations, added once per pair
+      if (glen)
+        HIP_TRY(launch_dbar_segment(p->dim, p->d, p->df, p->segX, p->stride, p->gvec, p->wbar, k1 - k0, p->Dbar, p->sp,
+                                    p->n_pad, p->ps),
+                "distance adjoint kernel");
     }
-    // dL/dd of the segment's iterations, added once per pair
-    if (glen)
-      HIP_TRY(launch_dbar_segment(p->dim, p->d, p->df, p->segX, p->stride, p->gvec, p->wbar, k1 - k0, p->Dbar, p->sp,
-                                  p->n_pad, p->ps),
-              "distance adjoint kernel");
-  }
-  HIP_TRY(launch_grad_out(p->gb, gX0, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
-  if (glen) {
-    HIP_TRY(launch_edge_grad(p->Dbar, p->Sbuf, p->g_row_ptr, p->g_col_idx, p->g_erow, p->pred, p->Gedge, glen,
-                             p->n, p->nnz, p->n_pad, p->sp.ng, p->ps),
-            "edge-length gradient kernels");
-    if (p->n <= 1 || p->nnz == 0)
-      HIP_TRY(hipMemsetAsync(glen, 0, sizeof(float) * std::max<int64_t>(p->nnz, 0), p->ps), "hipMemsetAsync");
-  }
-  HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-  return join_to(p, (hipStream_t)stream);
+    HIP_TRY(launch_grad_out(p->gb, gX0, p->n, p->n_pad, p->dim, p->ps), "gradient kernel");
+    if (glen) {
+      HIP_TRY(launch_edge_grad(p->Dbar, p->Sbuf, p->g_row_ptr, p->g_col_idx, p->g_erow, p->pred, p->Gedge, glen,
+                               p->n, p->nnz, p->n_pad, p->sp.ng, p->ps),
+              "edge-length gradient kernels");
+      if (p->n <= 1 || p->nnz == 0)
+        HIP_TRY(hipMemsetAsync(glen, 0, sizeof(float) * std::max<int64_t>(p->nnz, 0), p->ps), "hipMemsetAsync");
+    }
+    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+    return join_to(p, (hipStream_t)stream);
+  });
 }
 
 sl_status sl_layout(const sl_graph* g, float* X, const sl_options* o, void* stream, sl_result* out) {
-  g_err.clear();
-  sl_status s = check_options(o);
-  if (s != SL_OK) return s;
-  sl_plan* p = nullptr;
-  if ((s = sl_plan_create(g, o->dim, stream, &p)) != SL_OK) return s;
-  s = sl_plan_run(p, X, o, stream, out);
-  const ErrorText keep = g_err;
-  sl_plan_destroy(p);
-  g_err = keep;
-  return s;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    sl_status s = check_options(o);
+    if (s != SL_OK) return s;
+    sl_plan* p = nullptr;
+    if ((s = sl_plan_create(g, o->dim, stream, &p)) != SL_OK) return s;
+    s = sl_plan_run(p, X, o, stream, out);
+    const ErrorText keep = g_err;
+    sl_plan_destroy(p);
+    g_err = keep;
+    return s;
+  });
 }
 
 }  // extern "C"
@@ -1743,278 +1803,286 @@ sl_status batch_time(sl_batch_plan* p, float* X, const int32_t* order, int count
 extern "C" {
 
 sl_status sl_batch_plan_create(const sl_batch* b, int32_t dim, void* stream, sl_batch_plan** out) {
-  g_err.clear();
-  if (!out) return fail(SL_EINVAL, "out is NULL");
-  *out = nullptr;
-  sl_status s = check_batch(b);
-  if (s != SL_OK) return s;
-  if (dim != 2 && dim != 3) return fail(SL_EINVAL, "dim = %d, expected 2 or 3", dim);
-  sl_batch_plan* p = new (std::nothrow) sl_batch_plan();
-  if (!p) return fail(SL_ENOMEM, "host allocation failed");
-  auto bail = [&](sl_status st) {
-    free_batch(p);
-    delete p;
-    return st;
-  };
-  p->ngraphs = b->num_graphs;
-  p->dim = dim;
-  p->n_total = b->num_graphs > 0 ? b->graph_ptr[b->num_graphs] : 0;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->ps, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreate(&p->ev_a);
-  if (e == hipSuccess) e = hipEventCreate(&p->ev_b);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_sync, hipEventDisableTiming);
-  if (e != hipSuccess) return bail(hip_fail(e, "batch plan setup"));
-  int64_t d_bytes = 0, w_total = 0;
-  p->hgraphs.resize(p->ngraphs);
-  for (int g = 0; g < p->ngraphs; ++g) {
-    BatchGraph& G = p->hgraphs[g];
-    G.n = (int32_t)(b->graph_ptr[g + 1] - b->graph_ptr[g]);
-    G.n_pad = std::max(kRowBlock, round_up(G.n, kRowBlock));
-    G.slices = default_slices(G.n_pad, p->threads);
-    G.pad = 0;
-    G.d_off = d_bytes;
-    G.v_off = b->graph_ptr[g];
-    G.w_off = w_total;
-    d_bytes += (int64_t)G.n_pad * G.n_pad;
-    w_total += G.n_pad;
-  }
-  p->horder.resize(p->ngraphs);
-  for (int g = 0; g < p->ngraphs; ++g) p->horder[g] = g;
-  std::stable_sort(p->horder.begin(), p->horder.end(),
-                   [&](int a, int c) { return p->hgraphs[a].n_pad > p->hgraphs[c].n_pad; });
-  p->hres.resize(p->ngraphs);
-  const size_t ng1 = std::max(1, p->ngraphs);
-  e = hipMalloc(&p->graphs, sizeof(BatchGraph) * ng1);
-  if (e == hipSuccess) e = hipMalloc(&p->order, sizeof(int32_t) * ng1);
-  if (e == hipSuccess) e = hipMalloc(&p->queue, sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&p->status, sizeof(int32_t) * ng1);
-  if (e == hipSuccess) e = hipMalloc(&p->d, std::max<int64_t>(d_bytes, 1));
-  if (e == hipSuccess) e = hipMalloc(&p->W, sizeof(double) * std::max<int64_t>(w_total, 1));
-  if (e == hipSuccess) e = hipMalloc(&p->res, sizeof(BatchResult) * ng1);
-  if (e != hipSuccess) return bail(hip_fail(e, "batch plan allocation"));
-  if (p->ngraphs == 0) {
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!out) return fail(SL_EINVAL, "out is NULL");
+    *out = nullptr;
+    sl_status s = check_batch(b);
+    if (s != SL_OK) return s;
+    if (dim != 2 && dim != 3) return fail(SL_EINVAL, "dim = %d, expected 2 or 3", dim);
+    sl_batch_plan* p = new (std::nothrow) sl_batch_plan();
+    if (!p) return fail(SL_ENOMEM, "host allocation failed");
+    auto bail = [&](sl_status st) {
+      free_batch(p);
+      delete p;
+      return st;
+    };
+    p->ngraphs = b->num_graphs;
+    p->dim = dim;
+    p->n_total = b->num_graphs > 0 ? b->graph_ptr[b->num_graphs] : 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->ps, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_a);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev_b);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_sync, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(hip_fail(e, "batch plan setup"));
+    int64_t d_bytes = 0, w_total = 0;
+    p->hgraphs.resize(p->ngraphs);
+    for (int g = 0; g < p->ngraphs; ++g) {
+      BatchGraph& G = p->hgraphs[g];
+      G.n = (int32_t)(b->graph_ptr[g + 1] - b->graph_ptr[g]);
+      G.n_pad = std::max(kRowBlock, round_up(G.n, kRowBlock));
+      G.slices = default_slices(G.n_pad, p->threads);
+      G.pad = 0;
+      G.d_off = d_bytes;
+      G.v_off = b->graph_ptr[g];
+      G.w_off = w_total;
+      d_bytes += (int64_t)G.n_pad * G.n_pad;
+      w_total += G.n_pad;
+    }
+    p->horder.resize(p->ngraphs);
+    for (int g = 0; g < p->ngraphs; ++g) p->horder[g] = g;
+    std::stable_sort(p->horder.begin(), p->horder.end(),
+                     [&](int a, int c) { return p->hgraphs[a].n_pad > p->hgraphs[c].n_pad; });
+    p->hres.resize(p->ngraphs);
+    const size_t ng1 = std::max(1, p->ngraphs);
+    e = hipMalloc(&p->graphs, sizeof(BatchGraph) * ng1);
+    if (e == hipSuccess) e = hipMalloc(&p->order, sizeof(int32_t) * ng1);
+    if (e == hipSuccess) e = hipMalloc(&p->queue, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&p->status, sizeof(int32_t) * ng1);
+    if (e == hipSuccess) e = hipMalloc(&p->d, std::max<int64_t>(d_bytes, 1));
+    if (e == hipSuccess) e = hipMalloc(&p->W, sizeof(double) * std::max<int64_t>(w_total, 1));
+    if (e == hipSuccess) e = hipMalloc(&p->res, sizeof(BatchResult) * ng1);
+    if (e != hipSuccess) return bail(hip_fail(e, "batch plan allocation"));
+    if (p->ngraphs == 0) {
+      *out = p;
+      return SL_OK;
+    }
+    int64_t* rp = nullptr;
+    int32_t* ci = nullptr;
+    e = hipMalloc(&rp, sizeof(int64_t) * (p->n_total + 1));
+    if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * std::max<int64_t>(b->nnz, 1));
+    if (e == hipSuccess) e = hipEventRecord(p->ev_sync, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->ps, p->ev_sync, 0);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_a, p->ps);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d, 0, d_bytes, p->ps);
+    if (e == hipSuccess) e = hipMemsetAsync(p->status, 0, sizeof(int32_t) * p->ngraphs, p->ps);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(rp, b->row_ptr, sizeof(int64_t) * (p->n_total + 1), hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess && b->nnz > 0)
+      e = hipMemcpyAsync(ci, b->col_idx, sizeof(int32_t) * b->nnz, hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->order, p->horder.data(), sizeof(int32_t) * p->ngraphs, hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->graphs, p->hgraphs.data(), sizeof(BatchGraph) * p->ngraphs, hipMemcpyHostToDevice, p->ps);
+    if (e == hipSuccess) e = launch_batch_reset(p->queue, p->ps);
+    if (e == hipSuccess)
+      e = launch_batch_distances(512, std::max(1, std::min(p->ngraphs, p->cus)), p->graphs, p->order, p->ngraphs,
+                                 p->queue, rp, ci, p->d, p->W, p->status, p->ps);
+    if (e == hipSuccess) e = hipEventRecord(p->ev_b, p->ps);
+    std::vector<int32_t> hstatus(p->ngraphs, 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hstatus.data(), p->status, sizeof(int32_t) * p->ngraphs, hipMemcpyDeviceToHost, p->ps);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
+    (void)hipFree(rp);
+    (void)hipFree(ci);
+    if (e != hipSuccess) return bail(hip_fail(e, "batch distances"));
+    for (int g = 0; g < p->ngraphs; ++g)
+      if (hstatus[g] != 0) return bail(fail(SL_ERANGE, "graph %d has a distance above 255 hops", g));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+    p->plan_ms = ms;
     *out = p;
     return SL_OK;
-  }
-  int64_t* rp = nullptr;
-  int32_t* ci = nullptr;
-  e = hipMalloc(&rp, sizeof(int64_t) * (p->n_total + 1));
-  if (e == hipSuccess) e = hipMalloc(&ci, sizeof(int32_t) * std::max<int64_t>(b->nnz, 1));
-  if (e == hipSuccess) e = hipEventRecord(p->ev_sync, (hipStream_t)stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(p->ps, p->ev_sync, 0);
-  if (e == hipSuccess) e = hipEventRecord(p->ev_a, p->ps);
-  if (e == hipSuccess) e = hipMemsetAsync(p->d, 0, d_bytes, p->ps);
-  if (e == hipSuccess) e = hipMemsetAsync(p->status, 0, sizeof(int32_t) * p->ngraphs, p->ps);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(rp, b->row_ptr, sizeof(int64_t) * (p->n_total + 1), hipMemcpyHostToDevice, p->ps);
-  if (e == hipSuccess && b->nnz > 0)
-    e = hipMemcpyAsync(ci, b->col_idx, sizeof(int32_t) * b->nnz, hipMemcpyHostToDevice, p->ps);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->order, p->horder.data(), sizeof(int32_t) * p->ngraphs, hipMemcpyHostToDevice, p->ps);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->graphs, p->hgraphs.data(), sizeof(BatchGraph) * p->ngraphs, hipMemcpyHostToDevice, p->ps);
-  if (e == hipSuccess) e = launch_batch_reset(p->queue, p->ps);
-  if (e == hipSuccess)
-    e = launch_batch_distances(512, std::max(1, std::min(p->ngraphs, p->cus)), p->graphs, p->order, p->ngraphs,
-                               p->queue, rp, ci, p->d, p->W, p->status, p->ps);
-  if (e == hipSuccess) e = hipEventRecord(p->ev_b, p->ps);
-  std::vector<int32_t> hstatus(p->ngraphs, 0);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hstatus.data(), p->status, sizeof(int32_t) * p->ngraphs, hipMemcpyDeviceToHost, p->ps);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->ps);
-  (void)hipFree(rp);
-  (void)hipFree(ci);
-  if (e != hipSuccess) return bail(hip_fail(e, "batch distances"));
-  for (int g = 0; g < p->ngraphs; ++g)
-    if (hstatus[g] != 0) return bail(fail(SL_ERANGE, "graph %d has a distance above 255 hops", g));
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
-  p->plan_ms = ms;
-  *out = p;
-  return SL_OK;
+  });
 }
 
 sl_status sl_batch_plan_destroy(sl_batch_plan* p) {
-  g_err.clear();
-  if (!p) return SL_OK;
-  (void)hipStreamSynchronize(p->ps);
-  free_batch(p);
-  delete p;
-  return SL_OK;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return SL_OK;
+    (void)hipStreamSynchronize(p->ps);
+    free_batch(p);
+    delete p;
+    return SL_OK;
+  });
 }
 
 sl_status sl_batch_plan_tune(sl_batch_plan* p, const float* X, const sl_options* o, void* stream, int32_t* config) {
-  g_err.clear();
-  if (!p) return fail(SL_EINVAL, "plan is NULL");
-  BatchParams bp{};
-  sl_status s = batch_params(p, o, &bp);
-  if (s != SL_OK) return s;
-  if (p->ngraphs == 0 || p->n_total == 0) return SL_OK;
-  if (!X) return fail(SL_EINVAL, "X is NULL");
-  // The workgroup size is timed on whole runs to the caller's tolerance: a
-  // launch lasts as long as its slowest graph, which short runs do not see
-  // (a graph that needs many iterations runs faster on a larger workgroup
-  // alone on its CU).  The slices per size class are timed on short runs.
-  const BatchParams bp_run = bp;
-  const bool whole = o->tol > 0.0;
-  bp.tol = 0.0;
-  bp.max_iter = std::max(1, std::min(o->max_iter, 8));
-  const size_t xbytes = sizeof(float) * (size_t)p->n_total * p->dim;
-  float* tmp = nullptr;
-  int32_t* sub = nullptr;
-  HIP_TRY(hipMalloc(&tmp, xbytes), "tuning buffer");
-  if (hipMalloc(&sub, sizeof(int32_t) * p->ngraphs) != hipSuccess) {
-    (void)hipFree(tmp);
-    return fail(SL_ENOMEM, "tuning buffer");
-  }
-  auto cleanup = [&]() {
-    (void)hipStreamSynchronize(p->ps);
-    (void)hipFree(tmp);
-    (void)hipFree(sub);
-  };
-  auto timed = [&](const int32_t* order, int count, const BatchParams& params, float* ms) -> sl_status {
-    HIP_TRY(hipMemcpyAsync(tmp, X, xbytes, hipMemcpyDeviceToDevice, p->ps), "tuning copy");
-    return batch_time(p, tmp, order, count, params, ms);
-  };
-  if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) {
-    cleanup();
-    return s;
-  }
-  // 1. workgroup size, with the default slices for each
-  int best_t = p->threads;
-  float best_ms = 1e30f;
-  for (int t : {256, 512, 1024}) {
-    p->threads = t;
-    for (auto& G : p->hgraphs) G.slices = default_slices(G.n_pad, t);
-    if ((s = batch_upload_graphs(p)) != SL_OK) break;
-    float ms = 0.f;
-    if ((s = timed(p->order, p->ngraphs, whole ? bp_run : bp, &ms)) != SL_OK) break;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best_t = t;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return fail(SL_EINVAL, "plan is NULL");
+    BatchParams bp{};
+    sl_status s = batch_params(p, o, &bp);
+    if (s != SL_OK) return s;
+    if (p->ngraphs == 0 || p->n_total == 0) return SL_OK;
+    if (!X) return fail(SL_EINVAL, "X is NULL");
+    // The workgroup size is timed on whole runs to the caller's tolerance: a
+    // launch lasts as long as its slowest graph, which short runs do not see
+    // (a graph that needs many iterations runs faster on a larger workgroup
+    // alone on its CU).  The slices per size class are timed on short runs.
+    const BatchParams bp_run = bp;
+    const bool whole = o->tol > 0.0;
+    bp.tol = 0.0;
+    bp.max_iter = std::max(1, std::min(o->max_iter, 8));
+    const size_t xbytes = sizeof(float) * (size_t)p->n_total * p->dim;
+    float* tmp = nullptr;
+    int32_t* sub = nullptr;
+    HIP_TRY(hipMalloc(&tmp, xbytes), "tuning buffer");
+    if (hipMalloc(&sub, sizeof(int32_t) * p->ngraphs) != hipSuccess) {
+      (void)hipFree(tmp);
+      return fail(SL_ENOMEM, "tuning buffer");
     }
-  }
-  if (s != SL_OK) {
-    cleanup();
-    return s;
-  }
-  p->threads = best_t;
-  for (auto& G : p->hgraphs) G.slices = default_slices(G.n_pad, best_t);
-  // 2. column slices per size class, timed on that class alone
-  int chosen[kBatchClasses] = {0};
-  for (int c = 0; c < kBatchClasses && s == SL_OK; ++c) {
-    const int n_pad = (c + 1) * kRowBlock;
-    std::vector<int32_t> members;
-    for (int g : p->horder)
-      if (p->hgraphs[g].n_pad == n_pad) members.push_back(g);
-    if (members.empty()) continue;
-    if ((s = hip_try_copy(sub, members.data(), sizeof(int32_t) * members.size(), p->ps)) != SL_OK) break;
-    int best_s = default_slices(n_pad, best_t);
-    float best = 1e30f;
-    for (int cand : {1, 2, 4, 8, 16}) {
-      if (!slices_ok(n_pad, cand)) continue;
-      for (int g : members) p->hgraphs[g].slices = cand;
+    auto cleanup = [&]() {
+      (void)hipStreamSynchronize(p->ps);
+      (void)hipFree(tmp);
+      (void)hipFree(sub);
+    };
+    auto timed = [&](const int32_t* order, int count, const BatchParams& params, float* ms) -> sl_status {
+      HIP_TRY(hipMemcpyAsync(tmp, X, xbytes, hipMemcpyDeviceToDevice, p->ps), "tuning copy");
+      return batch_time(p, tmp, order, count, params, ms);
+    };
+    if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) {
+      cleanup();
+      return s;
+    }
+    // 1. workgroup size, with the default slices for each
+    int best_t = p->threads;
+    float best_ms = 1e30f;
+    for (int t : {256, 512, 1024}) {
+      p->threads = t;
+      for (auto& G : p->hgraphs) G.slices = default_slices(G.n_pad, t);
       if ((s = batch_upload_graphs(p)) != SL_OK) break;
       float ms = 0.f;
-      if ((s = timed(sub, (int)members.size(), bp, &ms)) != SL_OK) break;
-      if (ms < best) {
-        best = ms;
-        best_s = cand;
+      if ((s = timed(p->order, p->ngraphs, whole ? bp_run : bp, &ms)) != SL_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_t = t;
       }
     }
-    for (int g : members) p->hgraphs[g].slices = best_s;
-    chosen[c] = best_s;
-  }
-  if (s == SL_OK) s = batch_upload_graphs(p);
-  cleanup();
-  if (s != SL_OK) return s;
-  if (config) {
-    config[0] = p->threads;
-    for (int c = 0; c < kBatchClasses; ++c) config[1 + c] = chosen[c];
-  }
-  return join_to_stream(p->ps, p->ev_sync, (hipStream_t)stream);
+    if (s != SL_OK) {
+      cleanup();
+      return s;
+    }
+    p->threads = best_t;
+    for (auto& G : p->hgraphs) G.slices = default_slices(G.n_pad, best_t);
+    // 2. column slices per size class, timed on that class alone
+    int chosen[kBatchClasses] = {0};
+    for (int c = 0; c < kBatchClasses && s == SL_OK; ++c) {
+      const int n_pad = (c + 1) * kRowBlock;
+      std::vector<int32_t> members;
+      for (int g : p->horder)
+        if (p->hgraphs[g].n_pad == n_pad) members.push_back(g);
+      if (members.empty()) continue;
+      if ((s = hip_try_copy(sub, members.data(), sizeof(int32_t) * members.size(), p->ps)) != SL_OK) break;
+      int best_s = default_slices(n_pad, best_t);
+      float best = 1e30f;
+      for (int cand : {1, 2, 4, 8, 16}) {
+        if (!slices_ok(n_pad, cand)) continue;
+        for (int g : members) p->hgraphs[g].slices = cand;
+        if ((s = batch_upload_graphs(p)) != SL_OK) break;
+        float ms = 0.f;
+        if ((s = timed(sub, (int)members.size(), bp, &ms)) != SL_OK) break;
+        if (ms < best) {
+          best = ms;
+          best_s = cand;
+        }
+      }
+      for (int g : members) p->hgraphs[g].slices = best_s;
+      chosen[c] = best_s;
+    }
+    if (s == SL_OK) s = batch_upload_graphs(p);
+    cleanup();
+    if (s != SL_OK) return s;
+    if (config) {
+      config[0] = p->threads;
+      for (int c = 0; c < kBatchClasses; ++c) config[1 + c] = chosen[c];
+    }
+    return join_to_stream(p->ps, p->ev_sync, (hipStream_t)stream);
+  });
 }
 
 sl_status sl_batch_plan_run(sl_batch_plan* p, float* X, const sl_options* o, void* stream, sl_result* per_graph,
                             sl_result* total) {
-  g_err.clear();
-  if (!p) return fail(SL_EINVAL, "plan is NULL");
-  BatchParams bp{};
-  sl_status s = batch_params(p, o, &bp);
-  if (s != SL_OK) return s;
-  sl_result tot{};
-  tot.plan_ms = p->plan_ms;
-  tot.converged = 1;
-  if (p->ngraphs > 0 && p->n_total == 0)  // graphs without vertices: converged, no iterations
-    for (BatchResult& r : p->hres) r = BatchResult{0, 1, 0, 0, 0.0, 0.0};
-  if (p->ngraphs > 0 && p->n_total > 0) {
-    if (!X) return fail(SL_EINVAL, "X is NULL");
-    if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) return s;
-    std::vector<double> key = {(double)p->threads, bp.omega_p, bp.tol, (double)bp.max_iter, (double)bp.safeguard,
-                               (double)(uintptr_t)X};
-    if (!p->gexec || key != p->gkey) {
-      if (p->gexec) {
-        (void)hipGraphExecDestroy(p->gexec);
-        p->gexec = nullptr;
+  return guarded([&]() -> sl_status {
+    g_err.clear();
+    if (!p) return fail(SL_EINVAL, "plan is NULL");
+    BatchParams bp{};
+    sl_status s = batch_params(p, o, &bp);
+    if (s != SL_OK) return s;
+    sl_result tot{};
+    tot.plan_ms = p->plan_ms;
+    tot.converged = 1;
+    if (p->ngraphs > 0 && p->n_total == 0)  // graphs without vertices: converged, no iterations
+      for (BatchResult& r : p->hres) r = BatchResult{0, 1, 0, 0, 0.0, 0.0};
+    if (p->ngraphs > 0 && p->n_total > 0) {
+      if (!X) return fail(SL_EINVAL, "X is NULL");
+      if ((s = join_from_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) return s;
+      std::vector<double> key = {(double)p->threads, bp.omega_p, bp.tol, (double)bp.max_iter, (double)bp.safeguard,
+                                 (double)(uintptr_t)X};
+      if (!p->gexec || key != p->gkey) {
+        if (p->gexec) {
+          (void)hipGraphExecDestroy(p->gexec);
+          p->gexec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipError_t le = launch_batch_reset(p->queue, p->ps);
+        if (le == hipSuccess)
+          le = launch_batch_layout(p->dim, p->threads, batch_blocks(p, p->ngraphs), p->graphs, p->order, p->ngraphs,
+                                   p->queue, p->d, p->W, X, p->res, bp, p->ps);
+        hipError_t ce = hipStreamEndCapture(p->ps, &graph);
+        if (le != hipSuccess || ce != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return hip_fail(le != hipSuccess ? le : ce, "batch graph capture");
+        }
+        hipError_t ie = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+          p->gexec = nullptr;
+          return hip_fail(ie, "hipGraphInstantiate");
+        }
+        p->gkey = key;
       }
-      hipGraph_t graph = nullptr;
-      HIP_TRY(hipStreamBeginCapture(p->ps, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-      hipError_t le = launch_batch_reset(p->queue, p->ps);
-      if (le == hipSuccess)
-        le = launch_batch_layout(p->dim, p->threads, batch_blocks(p, p->ngraphs), p->graphs, p->order, p->ngraphs,
-                                 p->queue, p->d, p->W, X, p->res, bp, p->ps);
-      hipError_t ce = hipStreamEndCapture(p->ps, &graph);
-      if (le != hipSuccess || ce != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return hip_fail(le != hipSuccess ? le : ce, "batch graph capture");
-      }
-      hipError_t ie = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) {
-        p->gexec = nullptr;
-        return hip_fail(ie, "hipGraphInstantiate");
-      }
-      p->gkey = key;
+      HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
+      HIP_TRY(hipGraphLaunch(p->gexec, p->ps), "hipGraphLaunch");
+      HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
+      HIP_TRY(hipMemcpyAsync(p->hres.data(), p->res, sizeof(BatchResult) * p->ngraphs, hipMemcpyDeviceToHost, p->ps),
+              "batch results");
+      HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
+      tot.run_ms = ms;
+      if ((s = join_to_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) return s;
     }
-    HIP_TRY(hipEventRecord(p->ev_a, p->ps), "hipEventRecord");
-    HIP_TRY(hipGraphLaunch(p->gexec, p->ps), "hipGraphLaunch");
-    HIP_TRY(hipEventRecord(p->ev_b, p->ps), "hipEventRecord");
-    HIP_TRY(hipMemcpyAsync(p->hres.data(), p->res, sizeof(BatchResult) * p->ngraphs, hipMemcpyDeviceToHost, p->ps),
-            "batch results");
-    HIP_TRY(hipStreamSynchronize(p->ps), "hipStreamSynchronize");
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, p->ev_a, p->ev_b);
-    tot.run_ms = ms;
-    if ((s = join_to_stream(p->ps, p->ev_sync, (hipStream_t)stream)) != SL_OK) return s;
-  }
-  int bad = -1;
-  for (int g = 0; g < p->ngraphs; ++g) {
-    const BatchResult& r = p->hres[g];
-    if (per_graph) {
-      sl_result& o2 = per_graph[g];
-      o2 = sl_result{};
-      o2.iterations = r.iterations;
-      o2.converged = r.converged;
-      o2.rejected = r.rejected;
-      o2.residual = r.residual;
-      o2.stress = r.stress;
-      o2.plan_ms = p->plan_ms;
-      o2.run_ms = tot.run_ms;
-      o2.rel_stress_drop = std::nan("");
+    int bad = -1;
+    for (int g = 0; g < p->ngraphs; ++g) {
+      const BatchResult& r = p->hres[g];
+      if (per_graph) {
+        sl_result& o2 = per_graph[g];
+        o2 = sl_result{};
+        o2.iterations = r.iterations;
+        o2.converged = r.converged;
+        o2.rejected = r.rejected;
+        o2.residual = r.residual;
+        o2.stress = r.stress;
+        o2.plan_ms = p->plan_ms;
+        o2.run_ms = tot.run_ms;
+        o2.rel_stress_drop = std::nan("");
+      }
+      tot.iterations = std::max(tot.iterations, r.iterations);
+      tot.converged = tot.converged && r.converged;
+      tot.rejected += r.rejected;
+      tot.residual = std::max(tot.residual, r.residual);
+      if (r.status != 0 && bad < 0) bad = g;
     }
-    tot.iterations = std::max(tot.iterations, r.iterations);
-    tot.converged = tot.converged && r.converged;
-    tot.rejected += r.rejected;
-    tot.residual = std::max(tot.residual, r.residual);
-    if (r.status != 0 && bad < 0) bad = g;
-  }
-  tot.rel_stress_drop = std::nan("");
-  if (total) *total = tot;
-  if (bad >= 0) return fail(SL_ENUMERIC, "graph %d: non-finite coordinate; its X holds the last finite iterate", bad);
-  return SL_OK;
+    tot.rel_stress_drop = std::nan("");
+    if (total) *total = tot;
+    if (bad >= 0) return fail(SL_ENUMERIC, "graph %d: non-finite coordinate; its X holds the last finite iterate", bad);
+    return SL_OK;
+  });
 }
 
 }  // extern "C"
