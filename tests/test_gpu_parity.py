@@ -318,6 +318,32 @@ def test_ba65536_one_step_sampled_rows(sl, dim):
     assert err <= 1e-5 * diam(X0), err
 
 
+def test_ba_above_full_size_ragged_sampled_rows(sl):
+    """A graph larger than the benchmark's, of a ragged size: BA n = 100,003,
+    m = 3 (n_pad = 100,032, so the last row block and column group are partial;
+    13 sweeps of the search, the last with 1,699 sources; 10 GB of distance
+    bytes).  Sampled distance rows bit-exact against the oracle's BFS, their
+    W to rounding, and the rows of one Jacobi step within the FP32 bound."""
+    g, X0 = inputs.ba65536(2, n=100003)
+    print("case ba100003", flush=True)
+    rng = np.random.default_rng(11)
+    edge = [0, 1, 63, 64, 8191, 8192, 98303, 98304, 99999, g.n - 1]
+    rows = np.unique(np.concatenate([rng.choice(g.n, 60, replace=False), edge]))
+    Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
+    XH_rows = oracle.h_jacobi_rows(Drows, rows, X0)
+    X = dev(X0)
+    with sl.Plan(g, 2) as plan:
+        np.testing.assert_array_equal(plan.distance_rows(rows), as_u8(Drows))
+        W = plan.weights()
+        info = plan.run(X, omega=1.0, tol=0.0, max_iter=1)
+    w = np.where((Drows > 0) & np.isfinite(Drows), 1.0 / np.where(Drows > 0, Drows, 1.0) ** 2, 0.0).sum(1)
+    np.testing.assert_allclose(W[rows], w, rtol=1e-12)
+    assert info["iterations"] == 1
+    got = X.cpu().numpy().astype(np.float64)[rows]
+    err = np.abs(got - XH_rows).max()
+    assert err <= 1e-5 * diam(X0), err
+
+
 # (dimension, iteration k from 0): both take the fused pass over unordered pairs
 # (the bounds of the safeguard, the exact difference when they leave its sign
 # open); each case costs the oracle two passes over all pairs with every distance
