@@ -318,21 +318,22 @@ def test_ba65536_one_step_sampled_rows(sl, dim):
     assert err <= 1e-5 * diam(X0), err
 
 
-def test_ba_above_full_size_ragged_sampled_rows(sl):
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ba_above_full_size_ragged_sampled_rows(sl, dim):
     """A graph larger than the benchmark's, of a ragged size: BA n = 100,003,
     m = 3 (n_pad = 100,032, so the last row block and column group are partial;
     13 sweeps of the search, the last with 1,699 sources; 10 GB of distance
-    bytes).  Sampled distance rows bit-exact against the oracle's BFS, their
-    W to rounding, and the rows of one Jacobi step within the FP32 bound."""
-    g, X0 = inputs.ba65536(2, n=100003)
-    print("case ba100003", flush=True)
+    bytes), in 2-D and 3-D.  Sampled distance rows bit-exact against the oracle's
+    BFS, their W to rounding, and the rows of one Jacobi step within the FP32 bound."""
+    g, X0 = inputs.ba65536(dim, n=100003)
+    print("case ba100003 dim", dim, flush=True)
     rng = np.random.default_rng(11)
     edge = [0, 1, 63, 64, 8191, 8192, 98303, 98304, 99999, g.n - 1]
     rows = np.unique(np.concatenate([rng.choice(g.n, 60, replace=False), edge]))
     Drows = oracle.sssp_rows(g.row_ptr, g.col_idx, rows)
     XH_rows = oracle.h_jacobi_rows(Drows, rows, X0)
     X = dev(X0)
-    with sl.Plan(g, 2) as plan:
+    with sl.Plan(g, dim) as plan:
         np.testing.assert_array_equal(plan.distance_rows(rows), as_u8(Drows))
         W = plan.weights()
         info = plan.run(X, omega=1.0, tol=0.0, max_iter=1)
