@@ -250,3 +250,13 @@ def test_noalloc_validates_like_the_plan():
     # after those errors the validation bitmap is clean: a valid batch gets as
     # far as the option check (dim 4 is refused after the batch checks)
     assert _noalloc_status([g, inputs.grid_graph(4, 4)], dim=4) == b.SL_EINVAL and "dim" in b.last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: asked for more (or started as one rank of
+    several) it exits with a message before any device work."""
+    for args, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        r = subprocess.run(["python3", os.path.join(ROOT, "bench.py")] + args, capture_output=True, text=True,
+                           timeout=120, env=dict(os.environ, **env))
+        assert r.returncode != 0 and r.stdout == ""
+        assert "one GPU only" in r.stderr
