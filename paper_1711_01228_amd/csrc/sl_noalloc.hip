@@ -56,6 +56,17 @@ uint64_t h_adj[kBatchMaxN * kAdjWords];  // one graph's adjacency bits, for vali
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// The entry point's body runs through this, so that no C++ exception (the
+// lock's, say) crosses the C ABI.
+template <class F>
+sl_status guarded_call(F&& body) noexcept {
+  try {
+    return body();
+  } catch (...) {
+    return api_error(SL_EDEVICE, "host runtime error");
+  }
+}
+
 sl_status errorf(sl_status st, const char* fmt, long long a, long long b = 0, long long c = 0) {
   char msg[256];
   snprintf(msg, sizeof msg, fmt, a, b, c);
@@ -156,120 +167,122 @@ extern "C" {
 
 sl_status sl_batch_layout_noalloc(const sl_batch* b, float* X, const sl_options* o, void* stream,
                                   sl_result* per_graph, sl_result* total) {
-  std::lock_guard<std::mutex> guard(g_lock);
-  api_clear_error();
-  sl_status s = check_batch_static(b);
-  if (s != SL_OK) return s;
-  if (!o) return api_error(SL_EINVAL, "options are NULL");
-  BatchParams bp{};
-  if ((s = api_batch_options(o->dim, o, &bp)) != SL_OK) return s;
-  const int ng = b->num_graphs;
-  const int dim = o->dim;
-  const int64_t n_total = ng > 0 ? b->graph_ptr[ng] : 0;
-  // descriptors as sl_batch_plan_create makes them: default slices of a
-  // 512-thread workgroup, largest graph first
-  constexpr int kThreads = 512;
-  int64_t d_bytes = 0, w_total = 0;
-  for (int g = 0; g < ng; ++g) {
-    BatchGraph& G = h_graphs[g];
-    G.n = (int32_t)(b->graph_ptr[g + 1] - b->graph_ptr[g]);
-    G.n_pad = std::max(kRowBlock, (G.n + kRowBlock - 1) / kRowBlock * kRowBlock);
-    G.slices = batch_default_slices(G.n_pad, kThreads);
-    G.pad = 0;
-    G.d_off = d_bytes;
-    G.v_off = b->graph_ptr[g];
-    G.w_off = w_total;
-    d_bytes += (int64_t)G.n_pad * G.n_pad;
-    w_total += G.n_pad;
-    h_order[g] = g;
-  }
-  // largest n_pad first, ties in graph order (a stable order without a buffer)
-  std::sort(h_order, h_order + ng, [](int a, int c) {
-    return h_graphs[a].n_pad != h_graphs[c].n_pad ? h_graphs[a].n_pad > h_graphs[c].n_pad : a < c;
-  });
-  // carve the scratch array
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = off;
-    off = align_up(off + std::max<size_t>(bytes, 1));
-    return at;
-  };
-  const size_t o_graphs = take(sizeof(BatchGraph) * ng), o_order = take(sizeof(int32_t) * ng),
-               o_queue = take(sizeof(int32_t)), o_status = take(sizeof(int32_t) * ng),
-               o_res = take(sizeof(BatchResult) * ng), o_W = take(sizeof(double) * (size_t)w_total),
-               o_rp = take(sizeof(int64_t) * (size_t)(n_total + 1)), o_ci = take(sizeof(int32_t) * (size_t)b->nnz),
-               o_d = take((size_t)d_bytes);
-  if (off > SL_NOALLOC_SCRATCH_BYTES)
-    return errorf(SL_EINVAL, "the batch needs %lld bytes of device scratch, more than SL_NOALLOC_SCRATCH_BYTES = %lld",
-                  (long long)off, (long long)SL_NOALLOC_SCRATCH_BYTES);
-  sl_result tot{};
-  tot.plan_ms = tot.run_ms = tot.rel_stress_drop = std::nan("");
-  tot.converged = 1;
-  if (ng > 0 && n_total > 0) {
-    if (!X) return api_error(SL_EINVAL, "X is NULL");
-    unsigned char* base = nullptr;
-    int cus = 0;
-    if ((s = device_scratch(&base, &cus)) != SL_OK) return s;
-    const hipStream_t st = (hipStream_t)stream;
-    BatchGraph* graphs = reinterpret_cast<BatchGraph*>(base + o_graphs);
-    int32_t* order = reinterpret_cast<int32_t*>(base + o_order);
-    int32_t* queue = reinterpret_cast<int32_t*>(base + o_queue);
-    int32_t* status = reinterpret_cast<int32_t*>(base + o_status);
-    BatchResult* res = reinterpret_cast<BatchResult*>(base + o_res);
-    double* W = reinterpret_cast<double*>(base + o_W);
-    int64_t* rp = reinterpret_cast<int64_t*>(base + o_rp);
-    int32_t* ci = reinterpret_cast<int32_t*>(base + o_ci);
-    uint8_t* d = base + o_d;
-    // distances and weights (the plan's part), on the caller's stream
-    hipError_t e = launch_fill_zero(d, (size_t)d_bytes, st);
-    if (e == hipSuccess) e = launch_fill_zero(status, sizeof(int32_t) * ng, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(rp, b->row_ptr, sizeof(int64_t) * (n_total + 1), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && b->nnz > 0)
-      e = hipMemcpyAsync(ci, b->col_idx, sizeof(int32_t) * b->nnz, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(order, h_order, sizeof(int32_t) * ng, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(graphs, h_graphs, sizeof(BatchGraph) * ng, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_batch_reset(queue, st);
-    if (e == hipSuccess)
-      e = launch_batch_distances(kThreads, std::max(1, std::min(ng, cus)), graphs, order, ng, queue, rp, ci, d, W,
-                                 status, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h_status, status, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return api_hip_error(e, "batch distances");
-    for (int g = 0; g < ng; ++g)
-      if (h_status[g] != 0) return errorf(SL_ERANGE, "graph %lld has a distance above 255 hops", g);
-    // the layout (the run's part)
-    e = launch_batch_reset(queue, st);
-    if (e == hipSuccess)
-      e = launch_batch_layout(dim, kThreads, batch_layout_blocks(dim, cus, ng), graphs, order, ng, queue, d, W, X, res,
-                              bp, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h_res, res, sizeof(BatchResult) * ng, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return api_hip_error(e, "batch layout");
-  }
-  int bad = -1;
-  for (int g = 0; g < ng; ++g) {
-    // graphs without vertices: converged, no iterations (as the kernel reports n <= 1)
-    const BatchResult r = n_total > 0 ? h_res[g] : BatchResult{0, 1, 0, 0, 0.0, 0.0};
-    if (per_graph) {
-      sl_result& o2 = per_graph[g];
-      o2 = sl_result{};
-      o2.iterations = r.iterations;
-      o2.converged = r.converged;
-      o2.rejected = r.rejected;
-      o2.residual = r.residual;
-      o2.stress = r.stress;
-      o2.plan_ms = o2.run_ms = o2.rel_stress_drop = std::nan("");
+  return guarded_call([&]() -> sl_status {
+    std::lock_guard<std::mutex> guard(g_lock);
+    api_clear_error();
+    sl_status s = check_batch_static(b);
+    if (s != SL_OK) return s;
+    if (!o) return api_error(SL_EINVAL, "options are NULL");
+    BatchParams bp{};
+    if ((s = api_batch_options(o->dim, o, &bp)) != SL_OK) return s;
+    const int ng = b->num_graphs;
+    const int dim = o->dim;
+    const int64_t n_total = ng > 0 ? b->graph_ptr[ng] : 0;
+    // descriptors as sl_batch_plan_create makes them: default slices of a
+    // 512-thread workgroup, largest graph first
+    constexpr int kThreads = 512;
+    int64_t d_bytes = 0, w_total = 0;
+    for (int g = 0; g < ng; ++g) {
+      BatchGraph& G = h_graphs[g];
+      G.n = (int32_t)(b->graph_ptr[g + 1] - b->graph_ptr[g]);
+      G.n_pad = std::max(kRowBlock, (G.n + kRowBlock - 1) / kRowBlock * kRowBlock);
+      G.slices = batch_default_slices(G.n_pad, kThreads);
+      G.pad = 0;
+      G.d_off = d_bytes;
+      G.v_off = b->graph_ptr[g];
+      G.w_off = w_total;
+      d_bytes += (int64_t)G.n_pad * G.n_pad;
+      w_total += G.n_pad;
+      h_order[g] = g;
     }
-    tot.iterations = std::max(tot.iterations, r.iterations);
-    tot.converged = tot.converged && r.converged;
-    tot.rejected += r.rejected;
-    tot.residual = std::max(tot.residual, r.residual);
-    if (r.status != 0 && bad < 0) bad = g;
-  }
-  if (total) *total = tot;
-  if (bad >= 0)
-    return errorf(SL_ENUMERIC, "graph %lld: non-finite coordinate; its X holds the last finite iterate", bad);
-  return SL_OK;
+    // largest n_pad first, ties in graph order (a stable order without a buffer)
+    std::sort(h_order, h_order + ng, [](int a, int c) {
+      return h_graphs[a].n_pad != h_graphs[c].n_pad ? h_graphs[a].n_pad > h_graphs[c].n_pad : a < c;
+    });
+    // carve the scratch array
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t at = off;
+      off = align_up(off + std::max<size_t>(bytes, 1));
+      return at;
+    };
+    const size_t o_graphs = take(sizeof(BatchGraph) * ng), o_order = take(sizeof(int32_t) * ng),
+                 o_queue = take(sizeof(int32_t)), o_status = take(sizeof(int32_t) * ng),
+                 o_res = take(sizeof(BatchResult) * ng), o_W = take(sizeof(double) * (size_t)w_total),
+                 o_rp = take(sizeof(int64_t) * (size_t)(n_total + 1)), o_ci = take(sizeof(int32_t) * (size_t)b->nnz),
+                 o_d = take((size_t)d_bytes);
+    if (off > SL_NOALLOC_SCRATCH_BYTES)
+      return errorf(SL_EINVAL, "the batch needs %lld bytes of device scratch, more than SL_NOALLOC_SCRATCH_BYTES = %lld",
+                    (long long)off, (long long)SL_NOALLOC_SCRATCH_BYTES);
+    sl_result tot{};
+    tot.plan_ms = tot.run_ms = tot.rel_stress_drop = std::nan("");
+    tot.converged = 1;
+    if (ng > 0 && n_total > 0) {
+      if (!X) return api_error(SL_EINVAL, "X is NULL");
+      unsigned char* base = nullptr;
+      int cus = 0;
+      if ((s = device_scratch(&base, &cus)) != SL_OK) return s;
+      const hipStream_t st = (hipStream_t)stream;
+      BatchGraph* graphs = reinterpret_cast<BatchGraph*>(base + o_graphs);
+      int32_t* order = reinterpret_cast<int32_t*>(base + o_order);
+      int32_t* queue = reinterpret_cast<int32_t*>(base + o_queue);
+      int32_t* status = reinterpret_cast<int32_t*>(base + o_status);
+      BatchResult* res = reinterpret_cast<BatchResult*>(base + o_res);
+      double* W = reinterpret_cast<double*>(base + o_W);
+      int64_t* rp = reinterpret_cast<int64_t*>(base + o_rp);
+      int32_t* ci = reinterpret_cast<int32_t*>(base + o_ci);
+      uint8_t* d = base + o_d;
+      // distances and weights (the plan's part), on the caller's stream
+      hipError_t e = launch_fill_zero(d, (size_t)d_bytes, st);
+      if (e == hipSuccess) e = launch_fill_zero(status, sizeof(int32_t) * ng, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(rp, b->row_ptr, sizeof(int64_t) * (n_total + 1), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess && b->nnz > 0)
+        e = hipMemcpyAsync(ci, b->col_idx, sizeof(int32_t) * b->nnz, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(order, h_order, sizeof(int32_t) * ng, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(graphs, h_graphs, sizeof(BatchGraph) * ng, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = launch_batch_reset(queue, st);
+      if (e == hipSuccess)
+        e = launch_batch_distances(kThreads, std::max(1, std::min(ng, cus)), graphs, order, ng, queue, rp, ci, d, W,
+                                   status, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(h_status, status, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return api_hip_error(e, "batch distances");
+      for (int g = 0; g < ng; ++g)
+        if (h_status[g] != 0) return errorf(SL_ERANGE, "graph %lld has a distance above 255 hops", g);
+      // the layout (the run's part)
+      e = launch_batch_reset(queue, st);
+      if (e == hipSuccess)
+        e = launch_batch_layout(dim, kThreads, batch_layout_blocks(dim, cus, ng), graphs, order, ng, queue, d, W, X, res,
+                                bp, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(h_res, res, sizeof(BatchResult) * ng, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return api_hip_error(e, "batch layout");
+    }
+    int bad = -1;
+    for (int g = 0; g < ng; ++g) {
+      // graphs without vertices: converged, no iterations (as the kernel reports n <= 1)
+      const BatchResult r = n_total > 0 ? h_res[g] : BatchResult{0, 1, 0, 0, 0.0, 0.0};
+      if (per_graph) {
+        sl_result& o2 = per_graph[g];
+        o2 = sl_result{};
+        o2.iterations = r.iterations;
+        o2.converged = r.converged;
+        o2.rejected = r.rejected;
+        o2.residual = r.residual;
+        o2.stress = r.stress;
+        o2.plan_ms = o2.run_ms = o2.rel_stress_drop = std::nan("");
+      }
+      tot.iterations = std::max(tot.iterations, r.iterations);
+      tot.converged = tot.converged && r.converged;
+      tot.rejected += r.rejected;
+      tot.residual = std::max(tot.residual, r.residual);
+      if (r.status != 0 && bad < 0) bad = g;
+    }
+    if (total) *total = tot;
+    if (bad >= 0)
+      return errorf(SL_ENUMERIC, "graph %lld: non-finite coordinate; its X holds the last finite iterate", bad);
+    return SL_OK;
+  });
 }
 
 }  // extern "C"
